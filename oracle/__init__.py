@@ -1,0 +1,290 @@
+"""Plain FP64 CPU oracle for one SPH hydro step (ctypes over sph_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product path. It shares no
+code with the HIP library; the only module both sides use is the seeded input
+generator (paper_1809_08013_amd.inputs), which holds none of the method's
+arithmetic.
+
+Every function works on particles in the order given (original-id order in
+the tests) and follows the generic SPH workflow of Algorithm 1 (Sec. 3):
+neighbours (step 2), density, EOS, momentum and energy (step 3), global
+time-step (step 5), kick-drift-kick update (step 6). The formulas are the
+textbook readings listed at the top of sph_oracle.c.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+from . import build as _build
+
+__all__ = [
+    "lib", "kernel_w", "kernel_dwdr", "neighbors", "neighbors_brute",
+    "smoothing_length", "density", "eos", "momentum_energy", "timestep",
+    "integrate", "diagnostics", "gravity_direct", "OracleRun", "num_threads",
+]
+
+_lock = threading.Lock()
+_lib = None
+
+_D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_I32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_I64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_DN = C.c_void_p  # nullable double*
+
+
+def lib():
+    """Load liboracle.so, compiling it with gcc first if missing or stale."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            path = _build.build(force=False)
+            L = C.CDLL(path)
+            L.orc_kernel_w.restype = C.c_double
+            L.orc_kernel_w.argtypes = [C.c_double, C.c_double]
+            L.orc_kernel_dwdr.restype = C.c_double
+            L.orc_kernel_dwdr.argtypes = [C.c_double, C.c_double]
+            nb_args = [C.c_int64, _D, _D, _D, _D, _D, _D, _I32, C.c_int64, _I64, _I32]
+            L.orc_neighbors_brute.restype = C.c_int64
+            L.orc_neighbors_brute.argtypes = nb_args
+            L.orc_neighbors_grid.restype = C.c_int64
+            L.orc_neighbors_grid.argtypes = nb_args
+            L.orc_smoothing_length.restype = C.c_int32
+            L.orc_smoothing_length.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _I32,
+                                               C.c_double, C.c_int32, C.c_int32,
+                                               C.c_int32, _I32]
+            L.orc_density.restype = None
+            L.orc_density.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _D, _I32,
+                                      _I64, _I32, _D]
+            L.orc_eos.restype = None
+            L.orc_eos.argtypes = [C.c_int64, C.c_int32, C.c_double, C.c_double,
+                                  C.c_double, C.c_double, _D, _D, _D, _D, _D, _D, _D]
+            L.orc_momentum_energy.restype = None
+            L.orc_momentum_energy.argtypes = (
+                [C.c_int64] + [_D] * 11 + [_D, _D, _I32, _I64, _I32]
+                + [C.c_double] * 3 + [_D] * 5 + [_DN, _DN])
+            L.orc_timestep.restype = C.c_double
+            L.orc_timestep.argtypes = ([C.c_int64] + [_D] * 6 + [_DN] * 3
+                                       + [C.c_double] * 4)
+            L.orc_integrate.restype = None
+            L.orc_integrate.argtypes = ([C.c_int64, C.c_int32, C.c_double] + [_D] * 7
+                                        + [_D] * 4 + [_DN] * 3 + [_D, _D, _I32])
+            L.orc_diagnostics.restype = None
+            L.orc_diagnostics.argtypes = [C.c_int64] + [_D] * 8 + [_D]
+            L.orc_gravity_direct.restype = None
+            L.orc_gravity_direct.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_double,
+                                             _D, _D, _D]
+            L.orc_num_threads.restype = C.c_int32
+            L.orc_num_threads.argtypes = []
+            L.orc_set_num_threads.restype = None
+            L.orc_set_num_threads.argtypes = [C.c_int32]
+            _lib = L
+    return _lib
+
+
+def num_threads(set_to: int | None = None) -> int:
+    if set_to is not None:
+        lib().orc_set_num_threads(int(set_to))
+    return int(lib().orc_num_threads())
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _box(lo, hi, periodic):
+    return (_d(lo), _d(hi), np.ascontiguousarray(periodic, dtype=np.int32))
+
+
+def _dn(a):
+    return None if a is None else _d(a).ctypes.data
+
+
+def kernel_w(r: float, h: float) -> float:
+    return lib().orc_kernel_w(float(r), float(h))
+
+
+def kernel_dwdr(r: float, h: float) -> float:
+    return lib().orc_kernel_dwdr(float(r), float(h))
+
+
+def _neighbors(fn, x, y, z, h, lo, hi, periodic):
+    n = len(x)
+    x, y, z, h = _d(x), _d(y), _d(z), _d(h)
+    blo, bhi, bper = _box(lo, hi, periodic)
+    off = np.zeros(n + 1, dtype=np.int64)
+    cap = max(1, 128 * n)
+    ids = np.zeros(cap, dtype=np.int32)
+    tot = fn(n, x, y, z, h, blo, bhi, bper, cap, off, ids)
+    if tot < 0:
+        raise RuntimeError("oracle neighbour set too large")
+    if tot > cap:
+        cap = int(tot)
+        ids = np.zeros(cap, dtype=np.int32)
+        tot = fn(n, x, y, z, h, blo, bhi, bper, cap, off, ids)
+    return off, ids[:tot].copy()
+
+
+def neighbors(x, y, z, h, lo, hi, periodic):
+    """Neighbour sets (CSR, each set ascending) by a plain uniform grid."""
+    return _neighbors(lib().orc_neighbors_grid, x, y, z, h, lo, hi, periodic)
+
+
+def neighbors_brute(x, y, z, h, lo, hi, periodic):
+    """Neighbour sets (CSR, each set ascending) by the O(N^2) definition."""
+    return _neighbors(lib().orc_neighbors_brute, x, y, z, h, lo, hi, periodic)
+
+
+def smoothing_length(x, y, z, h, lo, hi, periodic, n_target=100.0,
+                     lo_count=95, hi_count=105, max_iter=10):
+    """Count-based h iteration; returns (h, gather counts, sweeps)."""
+    n = len(x)
+    hh = _d(h).copy()
+    cnt = np.zeros(n, dtype=np.int32)
+    blo, bhi, bper = _box(lo, hi, periodic)
+    it = lib().orc_smoothing_length(n, _d(x), _d(y), _d(z), hh, blo, bhi, bper,
+                                    float(n_target), int(lo_count), int(hi_count),
+                                    int(max_iter), cnt)
+    return hh, cnt, int(it)
+
+
+def density(x, y, z, h, m, lo, hi, periodic, off, ids):
+    n = len(x)
+    rho = np.zeros(n)
+    blo, bhi, bper = _box(lo, hi, periodic)
+    lib().orc_density(n, _d(x), _d(y), _d(z), _d(h), _d(m), blo, bhi, bper,
+                      np.ascontiguousarray(off, dtype=np.int64),
+                      np.ascontiguousarray(ids, dtype=np.int32), rho)
+    return rho
+
+
+def eos(params, rho, u, rho_ref, p_bg):
+    n = len(rho)
+    p, c, pr2 = np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_eos(n, int(params.eos), float(params.rho0), float(params.c0),
+                  float(params.gamma_tait), float(params.gamma_gas), _d(rho), _d(u),
+                  _d(rho_ref), _d(p_bg), p, c, pr2)
+    return p, c, pr2
+
+
+def momentum_energy(x, y, z, vx, vy, vz, h, m, rho, c, pr2, lo, hi, periodic,
+                    off, ids, params, scales=False):
+    """Returns dict ax, ay, az, dudt, mumax (and sa, su if scales)."""
+    n = len(x)
+    out = {k: np.zeros(n) for k in ("ax", "ay", "az", "dudt", "mumax")}
+    sa = np.zeros(n) if scales else None
+    su = np.zeros(n) if scales else None
+    blo, bhi, bper = _box(lo, hi, periodic)
+    lib().orc_momentum_energy(
+        n, _d(x), _d(y), _d(z), _d(vx), _d(vy), _d(vz), _d(h), _d(m), _d(rho),
+        _d(c), _d(pr2), blo, bhi, bper, np.ascontiguousarray(off, dtype=np.int64),
+        np.ascontiguousarray(ids, dtype=np.int32), float(params.alpha),
+        float(params.beta), float(params.eta2), out["ax"], out["ay"], out["az"],
+        out["dudt"], out["mumax"], None if sa is None else sa.ctypes.data,
+        None if su is None else su.ctypes.data)
+    if scales:
+        out["sa"], out["su"] = sa, su
+    return out
+
+
+def timestep(h, c, mumax, ax, ay, az, params, g=None):
+    n = len(h)
+    gx = gy = gz = None
+    if g is not None:
+        gx, gy, gz = (_d(a) for a in g)
+    return float(lib().orc_timestep(
+        n, _d(h), _d(c), _d(mumax), _d(ax), _d(ay), _d(az), _dn(gx), _dn(gy),
+        _dn(gz), float(params.alpha), float(params.beta), float(params.c_cfl),
+        float(params.c_force)))
+
+
+def integrate(state: dict, stage: int, dt: float, acc: dict, lo, hi, periodic,
+              g=None):
+    """In place on state's float64 arrays x..vz, u (stage 0 kick+drift, 1 kick)."""
+    n = len(state["x"])
+    gx = gy = gz = None
+    if g is not None:
+        gx, gy, gz = (_d(a) for a in g)
+    blo, bhi, bper = _box(lo, hi, periodic)
+    lib().orc_integrate(n, int(stage), float(dt), state["x"], state["y"], state["z"],
+                        state["vx"], state["vy"], state["vz"], state["u"],
+                        _d(acc["ax"]), _d(acc["ay"]), _d(acc["az"]), _d(acc["dudt"]),
+                        _dn(gx), _dn(gy), _dn(gz), blo, bhi, bper)
+
+
+def diagnostics(x, y, z, vx, vy, vz, u, m):
+    out = np.zeros(8)
+    lib().orc_diagnostics(len(x), _d(x), _d(y), _d(z), _d(vx), _d(vy), _d(vz),
+                          _d(u), _d(m), out)
+    return out
+
+
+def gravity_direct(x, y, z, m, eps=0.01):
+    n = len(x)
+    gx, gy, gz = np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_gravity_direct(n, _d(x), _d(y), _d(z), _d(m), float(eps), gx, gy, gz)
+    return gx, gy, gz
+
+
+class OracleRun:
+    """A whole run on the oracle: t = 0 force evaluation, then KDK steps.
+
+    rho_ref: the per-particle Tait reference density. None means
+    rho_ref := rho(t = 0), this run's own summation density (the reading used
+    for the square patch); an array is used as given.
+    """
+
+    def __init__(self, ic, rho_ref=None, g=None):
+        self.ic = ic
+        self.params = ic.params
+        self.box = (ic.lo, ic.hi, ic.periodic)
+        self.s = {k: _d(getattr(ic, k)).copy() for k in
+                  ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m", "p_bg")}
+        self.g = g
+        self.rho_ref = None if rho_ref is None else _d(rho_ref).copy()
+        self.dt = None
+        self.t = 0.0
+        self.steps = 0
+        self.n_pairs = 0
+
+    def forces(self):
+        s, (lo, hi, per) = self.s, self.box
+        off, ids = neighbors(s["x"], s["y"], s["z"], s["h"], lo, hi, per)
+        self.off, self.ids = off, ids
+        self.n_pairs = int(off[-1])
+        rho = density(s["x"], s["y"], s["z"], s["h"], s["m"], lo, hi, per, off, ids)
+        if self.rho_ref is None:
+            self.rho_ref = rho.copy()
+        p, c, pr2 = eos(self.params, rho, s["u"], self.rho_ref, s["p_bg"])
+        acc = momentum_energy(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"],
+                              s["h"], s["m"], rho, c, pr2, lo, hi, per, off, ids,
+                              self.params)
+        self.rho, self.p, self.c, self.pr2, self.acc = rho, p, c, pr2, acc
+        return acc
+
+    def init(self):
+        self.forces()
+        self.dt = timestep(self.s["h"], self.c, self.acc["mumax"], self.acc["ax"],
+                           self.acc["ay"], self.acc["az"], self.params, self.g)
+        return self
+
+    def step(self):
+        lo, hi, per = self.box
+        dt = self.dt
+        integrate(self.s, 0, dt, self.acc, lo, hi, per, self.g)
+        self.forces()
+        integrate(self.s, 1, dt, self.acc, lo, hi, per, self.g)
+        self.t += dt
+        self.steps += 1
+        self.dt = timestep(self.s["h"], self.c, self.acc["mumax"], self.acc["ax"],
+                           self.acc["ay"], self.acc["az"], self.params, self.g)
+        return dt
+
+    def diagnostics(self):
+        s = self.s
+        return diagnostics(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"],
+                           s["u"], s["m"])

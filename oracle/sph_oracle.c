@@ -1,0 +1,667 @@
+/*
+ * Plain FP64 CPU oracle for one SPH hydro step.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may call, link or
+ * load this file or the library built from it; only the tests, the smoke
+ * check and the CPU-baseline leg of the benchmark do. It shares no code,
+ * header, table or constant generator with the HIP path.
+ *
+ * It follows the generic SPH workflow of Algorithm 1 (Sec. 3): find the
+ * neighbours of every particle (step 2), evaluate density, pressure,
+ * acceleration and rate of change of internal energy (step 3, as listed in
+ * the prose after Algorithm 1), compute a new global time-step (step 5) and
+ * update velocity and position (step 6). The paper names the ingredients but
+ * not their formulas; the readings used (each a textbook choice) are:
+ *
+ *   kernel    M4 cubic spline (Table 1, ChaNGa), W = w(r/h) / (pi h^3)
+ *   gradient  kernel derivatives, standard volume elements m/rho (Table 1)
+ *   density   summation, self term included, gather with h_i
+ *   variable h  neighbour iff r^2 < (2 max(h_i, h_j))^2; gradient is the
+ *             mean of grad W(r, h_i) and grad W(r, h_j)
+ *   momentum  a_i = -sum_j m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi_ij) gradW_ij
+ *   energy    du_i = 1/2 sum_j m_j (...) v_ij . gradW_ij
+ *   AV        Monaghan: mu = hbar v.r / (r^2 + eta^2 hbar^2) if v.r < 0,
+ *             Pi = (-alpha cbar mu + beta mu^2) / rhobar
+ *   EOS       Tait (square patch) or ideal gas gamma = 5/3 (Evrard, Sec. 5.1)
+ *   dt        global min over particles of the Courant and force limits
+ *   update    kick-drift-kick leapfrog with a global dt
+ *
+ * Every sum over neighbours runs in ascending neighbour-index order. Built
+ * with -O2 -ffp-contract=off so that no multiply-add is fused unless written
+ * as fma() below.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ---------------------------------------------------------------- kernel */
+
+/* M4 cubic spline shape, q = r/h (Monaghan & Lattanzio 1985). */
+static double m4_w(double q)
+{
+    if (q < 1.0) return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+    if (q < 2.0) { double t = 2.0 - q; return 0.25 * t * t * t; }
+    return 0.0;
+}
+
+/* dw/dq of the M4 shape. */
+static double m4_dw(double q)
+{
+    if (q < 1.0) return -3.0 * q + 2.25 * q * q;
+    if (q < 2.0) { double t = 2.0 - q; return -0.75 * t * t; }
+    return 0.0;
+}
+
+/* W(r, h) in 3D, sigma = 1/pi. */
+double orc_kernel_w(double r, double h)
+{
+    return m4_w(r / h) / (ORC_PI * h * h * h);
+}
+
+/* dW/dr (r, h) in 3D. */
+double orc_kernel_dwdr(double r, double h)
+{
+    return m4_dw(r / h) / (ORC_PI * h * h * h * h);
+}
+
+/* ------------------------------------------------------------ geometry */
+
+typedef struct {
+    double lo[3], hi[3];
+    int32_t periodic[3];
+} orc_box;
+
+/* Minimum image along one periodic axis of length len. */
+static double min_image(double d, double len)
+{
+    double half = 0.5 * len;
+    if (d > half) return d - len;
+    if (d < -half) return d + len;
+    return d;
+}
+
+/* Separation x_i - x_j with the minimum image on periodic axes. */
+static void separation(const double *x, const double *y, const double *z,
+                       int64_t i, int64_t j, const orc_box *b,
+                       double *dx, double *dy, double *dz)
+{
+    double ex = x[i] - x[j], ey = y[i] - y[j], ez = z[i] - z[j];
+    if (b->periodic[0]) ex = min_image(ex, b->hi[0] - b->lo[0]);
+    if (b->periodic[1]) ey = min_image(ey, b->hi[1] - b->lo[1]);
+    if (b->periodic[2]) ez = min_image(ez, b->hi[2] - b->lo[2]);
+    *dx = ex; *dy = ey; *dz = ez;
+}
+
+/* Squared distance, evaluated in one fixed order:
+ * r^2 = fma(dz, dz, fma(dy, dy, dx*dx)). */
+static double dist2(double dx, double dy, double dz)
+{
+    return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
+/* The neighbour relation: j != i and r^2 < (2 max(h_i, h_j))^2, strict. */
+static int is_neighbor(const double *x, const double *y, const double *z,
+                       const double *h, int64_t i, int64_t j, const orc_box *b)
+{
+    double dx, dy, dz;
+    if (i == j) return 0;
+    separation(x, y, z, i, j, b, &dx, &dy, &dz);
+    double s = 2.0 * fmax(h[i], h[j]);
+    return dist2(dx, dy, dz) < s * s;
+}
+
+/* Gather-only relation used for smoothing-length counting: r^2 < 4 h_i^2. */
+static int in_gather_sphere(const double *x, const double *y, const double *z,
+                            const double *h, int64_t i, int64_t j,
+                            const orc_box *b)
+{
+    double dx, dy, dz;
+    if (i == j) return 0;
+    separation(x, y, z, i, j, b, &dx, &dy, &dz);
+    double s = 2.0 * h[i];
+    return dist2(dx, dy, dz) < s * s;
+}
+
+static orc_box make_box(const double *lo, const double *hi, const int32_t *per)
+{
+    orc_box b;
+    for (int a = 0; a < 3; ++a) {
+        b.lo[a] = lo[a]; b.hi[a] = hi[a]; b.periodic[a] = per[a];
+    }
+    return b;
+}
+
+/* ------------------------------------------------- brute-force neighbours */
+
+/*
+ * O(N^2) neighbour sets, the definition written out. offsets has n+1
+ * entries. If the total exceeds cap, ids is left partially written and the
+ * needed total is returned; otherwise the total is returned.
+ */
+int64_t orc_neighbors_brute(int64_t n, const double *x, const double *y,
+                            const double *z, const double *h,
+                            const double *lo, const double *hi,
+                            const int32_t *per, int64_t cap,
+                            int64_t *offsets, int32_t *ids)
+{
+    orc_box b = make_box(lo, hi, per);
+    int64_t *cnt = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; ++j) c += is_neighbor(x, y, z, h, i, j, &b);
+        cnt[i] = c;
+    }
+    offsets[0] = 0;
+    for (int64_t i = 0; i < n; ++i) offsets[i + 1] = offsets[i] + cnt[i];
+    int64_t total = offsets[n];
+    free(cnt);
+    if (total > cap) return total;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t o = offsets[i];
+        for (int64_t j = 0; j < n; ++j)
+            if (is_neighbor(x, y, z, h, i, j, &b)) ids[o++] = (int32_t)j;
+    }
+    return total;
+}
+
+/* ------------------------------------------------- uniform-grid neighbours */
+
+typedef struct {
+    int64_t nc[3];        /* cells per axis */
+    double inv_s[3];      /* 1 / cell side */
+    int64_t *start;       /* first sorted slot of each linear cell */
+    int64_t *order;       /* particle index of each sorted slot */
+    int64_t ncell;
+} orc_grid;
+
+typedef struct { int64_t cell, idx; } cell_rec;
+
+static int cmp_cell_rec(const void *a, const void *b)
+{
+    const cell_rec *p = (const cell_rec *)a, *q = (const cell_rec *)b;
+    if (p->cell != q->cell) return p->cell < q->cell ? -1 : 1;
+    return p->idx < q->idx ? -1 : (p->idx > q->idx);
+}
+
+static int64_t cell_coord(double v, double lo, double inv_s, int64_t nc)
+{
+    double f = floor((v - lo) * inv_s);
+    if (f < 0.0) return 0;
+    if (f > (double)(nc - 1)) return nc - 1;
+    return (int64_t)f;
+}
+
+/* Cells of side >= reach * (1 + 1e-9); particles outside the box are
+ * clamped into the border cells, which keeps every pair within reach in
+ * adjacent cells. */
+static void grid_build(orc_grid *g, int64_t n, const double *x, const double *y,
+                       const double *z, const orc_box *b, double reach)
+{
+    const double *p[3] = {x, y, z};
+    g->ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        double len = b->hi[a] - b->lo[a];
+        double want = reach * (1.0 + 1e-9);
+        int64_t nc = (int64_t)floor(len / want);
+        if (nc < 1) nc = 1;
+        if (nc > 1024) nc = 1024;
+        g->nc[a] = nc;
+        g->inv_s[a] = (double)nc / len;
+        g->ncell *= nc;
+    }
+    cell_rec *rec = (cell_rec *)malloc(sizeof(cell_rec) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a)
+            c[a] = cell_coord(p[a][i], b->lo[a], g->inv_s[a], g->nc[a]);
+        rec[i].cell = (c[2] * g->nc[1] + c[1]) * g->nc[0] + c[0];
+        rec[i].idx = i;
+    }
+    qsort(rec, (size_t)n, sizeof(cell_rec), cmp_cell_rec);
+    g->start = (int64_t *)calloc((size_t)(g->ncell + 1), sizeof(int64_t));
+    g->order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t s = 0; s < n; ++s) {
+        g->order[s] = rec[s].idx;
+        g->start[rec[s].cell + 1]++;
+    }
+    for (int64_t c = 0; c < g->ncell; ++c) g->start[c + 1] += g->start[c];
+    free(rec);
+}
+
+static void grid_free(orc_grid *g)
+{
+    free(g->start);
+    free(g->order);
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t p = *(const int32_t *)a, q = *(const int32_t *)b;
+    return (p > q) - (p < q);
+}
+
+/* Distinct neighbouring cell coordinates of c along one axis. */
+static int axis_cells(int64_t c, int64_t nc, int periodic, int64_t out[3])
+{
+    int k = 0;
+    for (int64_t d = -1; d <= 1; ++d) {
+        int64_t v = c + d;
+        if (periodic) {
+            v = ((v % nc) + nc) % nc;
+        } else if (v < 0 || v >= nc) {
+            continue;
+        }
+        int dup = 0;
+        for (int t = 0; t < k; ++t) dup |= (out[t] == v);
+        if (!dup) out[k++] = v;
+    }
+    return k;
+}
+
+/* All candidates j of particle i whose relation rel(i, j) holds, sorted
+ * ascending; returns the count (writes at most cap entries to buf). */
+typedef int (*relation_fn)(const double *, const double *, const double *,
+                           const double *, int64_t, int64_t, const orc_box *);
+
+static int64_t grid_query(const orc_grid *g, int64_t i, const double *x,
+                          const double *y, const double *z, const double *h,
+                          const orc_box *b, relation_fn rel, int32_t *buf,
+                          int64_t cap)
+{
+    const double *p[3] = {x, y, z};
+    int64_t c[3], nb[3][3];
+    int k[3];
+    for (int a = 0; a < 3; ++a) {
+        c[a] = cell_coord(p[a][i], b->lo[a], g->inv_s[a], g->nc[a]);
+        k[a] = axis_cells(c[a], g->nc[a], b->periodic[a], nb[a]);
+    }
+    int64_t cnt = 0;
+    for (int iz = 0; iz < k[2]; ++iz)
+        for (int iy = 0; iy < k[1]; ++iy)
+            for (int ix = 0; ix < k[0]; ++ix) {
+                int64_t cell = (nb[2][iz] * g->nc[1] + nb[1][iy]) * g->nc[0] + nb[0][ix];
+                for (int64_t s = g->start[cell]; s < g->start[cell + 1]; ++s) {
+                    int64_t j = g->order[s];
+                    if (rel(x, y, z, h, i, j, b)) {
+                        if (cnt < cap) buf[cnt] = (int32_t)j;
+                        ++cnt;
+                    }
+                }
+            }
+    if (cnt <= cap) qsort(buf, (size_t)cnt, sizeof(int32_t), cmp_i32);
+    return cnt;
+}
+
+static double max_of(const double *v, int64_t n)
+{
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i) m = fmax(m, v[i]);
+    return m;
+}
+
+/*
+ * Neighbour sets by a plain uniform grid (cells of side >= 2 h_max, sorted
+ * by linear cell index). Same contract as orc_neighbors_brute; each set is
+ * sorted ascending. Returns -1 if one set exceeds 2^22 entries.
+ */
+int64_t orc_neighbors_grid(int64_t n, const double *x, const double *y,
+                           const double *z, const double *h,
+                           const double *lo, const double *hi,
+                           const int32_t *per, int64_t cap,
+                           int64_t *offsets, int32_t *ids)
+{
+    orc_box b = make_box(lo, hi, per);
+    orc_grid g;
+    offsets[0] = 0;
+    if (n == 0) return 0;
+    grid_build(&g, n, x, y, z, &b, 2.0 * max_of(h, n));
+    int64_t *cnt = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    int64_t bufcap = n < ((int64_t)1 << 22) ? n : ((int64_t)1 << 22);
+    #pragma omp parallel
+    {
+        int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)bufcap);
+        #pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i)
+            cnt[i] = grid_query(&g, i, x, y, z, h, &b, is_neighbor, buf, 0);
+        free(buf);
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (cnt[i] > bufcap) { free(cnt); grid_free(&g); return -1; }
+        offsets[i + 1] = offsets[i] + cnt[i];
+    }
+    int64_t total = offsets[n];
+    free(cnt);
+    if (total <= cap) {
+        #pragma omp parallel
+        {
+            int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)bufcap);
+            #pragma omp for schedule(dynamic, 256)
+            for (int64_t i = 0; i < n; ++i) {
+                int64_t c = grid_query(&g, i, x, y, z, h, &b, is_neighbor, buf, bufcap);
+                memcpy(ids + offsets[i], buf, sizeof(int32_t) * (size_t)c);
+            }
+            free(buf);
+        }
+    }
+    grid_free(&g);
+    return total;
+}
+
+/*
+ * Smoothing-length iteration toward a target neighbour count (Algorithm 1
+ * step 2 and its footnote: the code aims at a given number of neighbours and
+ * h follows from it). Gather count N_i = |{j != i : r^2 < 4 h_i^2}|; every
+ * particle outside [lo_count, hi_count] is updated with
+ * h <- h * (1 + (n_target / N_i)^(1/3)) / 2 (h doubles when N_i = 0); at most
+ * max_iter sweeps. Returns the number of sweeps done.
+ */
+int32_t orc_smoothing_length(int64_t n, const double *x, const double *y,
+                             const double *z, double *h,
+                             const double *lo, const double *hi,
+                             const int32_t *per, double n_target,
+                             int32_t lo_count, int32_t hi_count,
+                             int32_t max_iter, int32_t *count_out)
+{
+    orc_box b = make_box(lo, hi, per);
+    int32_t it;
+    int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (it = 0; it <= max_iter; ++it) {
+        orc_grid g;
+        grid_build(&g, n, x, y, z, &b, 2.0 * max_of(h, n));
+        #pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i)
+            cnt[i] = (int32_t)grid_query(&g, i, x, y, z, h, &b, in_gather_sphere, NULL, 0);
+        grid_free(&g);
+        int64_t bad = 0;
+        for (int64_t i = 0; i < n; ++i) bad += (cnt[i] < lo_count || cnt[i] > hi_count);
+        if (bad == 0 || it == max_iter) break;
+        #pragma omp parallel for
+        for (int64_t i = 0; i < n; ++i) {
+            if (cnt[i] >= lo_count && cnt[i] <= hi_count) continue;
+            if (cnt[i] == 0) h[i] = 2.0 * h[i];
+            else h[i] = h[i] * 0.5 * (1.0 + cbrt(n_target / (double)cnt[i]));
+        }
+    }
+    if (count_out) memcpy(count_out, cnt, sizeof(int32_t) * (size_t)n);
+    free(cnt);
+    return it;
+}
+
+/* ------------------------------------------------------------- density */
+
+/* rho_i = m_i W(0, h_i) + sum_{j in N_i} m_j W(r_ij, h_i). */
+void orc_density(int64_t n, const double *x, const double *y, const double *z,
+                 const double *h, const double *m,
+                 const double *lo, const double *hi, const int32_t *per,
+                 const int64_t *offsets, const int32_t *ids, double *rho)
+{
+    orc_box b = make_box(lo, hi, per);
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        double s = m[i] * orc_kernel_w(0.0, h[i]);
+        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            int64_t j = ids[k];
+            double dx, dy, dz;
+            separation(x, y, z, i, j, &b, &dx, &dy, &dz);
+            double r = sqrt(dist2(dx, dy, dz));
+            s += m[j] * orc_kernel_w(r, h[i]);
+        }
+        rho[i] = s;
+    }
+}
+
+/* ------------------------------------------------------------------ EOS */
+
+/*
+ * eos = 0, Tait: x = rho/rho_ref, P = p_bg + B (x^7 - 1), c = c0 x^3 with
+ *       B = rho0 c0^2 / gamma_tait (gamma_tait = 7 assumed by the powers).
+ * eos = 1, ideal gas: P = (gamma - 1) rho u, c = sqrt(gamma (gamma - 1) u).
+ * Also pr2 = P / rho^2.
+ */
+void orc_eos(int64_t n, int32_t eos, double rho0, double c0, double gamma_tait,
+             double gamma_gas, const double *rho, const double *u,
+             const double *rho_ref, const double *p_bg,
+             double *p, double *c, double *pr2)
+{
+    #pragma omp parallel for
+    for (int64_t i = 0; i < n; ++i) {
+        double P, C;
+        if (eos == 0) {
+            double B = rho0 * c0 * c0 / gamma_tait;
+            double xr = rho[i] / rho_ref[i];
+            double x2 = xr * xr, x4 = x2 * x2, x6 = x4 * x2, x7 = x6 * xr;
+            double x3 = x2 * xr;
+            P = p_bg[i] + B * (x7 - 1.0);
+            C = c0 * x3;
+        } else {
+            P = (gamma_gas - 1.0) * rho[i] * u[i];
+            C = sqrt(gamma_gas * (gamma_gas - 1.0) * u[i]);
+        }
+        p[i] = P;
+        c[i] = C;
+        pr2[i] = P / (rho[i] * rho[i]);
+    }
+}
+
+/* ------------------------------------------------- momentum and energy */
+
+/*
+ * For each j in N_i (ascending):
+ *   gradW = 1/2 [dW/dr(r, h_i) + dW/dr(r, h_j)] r_ij / r  (zero when r = 0)
+ *   mu    = hbar (v_ij . r_ij) / (r^2 + eta2 hbar^2) if v_ij . r_ij < 0 else 0
+ *   Pi    = (-alpha cbar mu + beta mu^2) / rhobar
+ *   G     = pr2_i + pr2_j + Pi
+ *   a_i  -= m_j G gradW ;  du_i += 1/2 m_j G v_ij . gradW ; mumax_i = max |mu|
+ * Also the error scales S^a_i = sum m_j |G| |gradW| and
+ * S^u_i = 1/2 sum m_j |G| |v_ij| |gradW| (either output may be NULL).
+ */
+void orc_momentum_energy(int64_t n, const double *x, const double *y,
+                         const double *z, const double *vx, const double *vy,
+                         const double *vz, const double *h, const double *m,
+                         const double *rho, const double *c, const double *pr2,
+                         const double *lo, const double *hi, const int32_t *per,
+                         const int64_t *offsets, const int32_t *ids,
+                         double alpha, double beta, double eta2,
+                         double *ax, double *ay, double *az, double *dudt,
+                         double *mumax, double *sa, double *su)
+{
+    orc_box b = make_box(lo, hi, per);
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, mum = 0.0;
+        double sai = 0.0, sui = 0.0;
+        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            int64_t j = ids[k];
+            double dx, dy, dz;
+            separation(x, y, z, i, j, &b, &dx, &dy, &dz);
+            double r2 = dist2(dx, dy, dz);
+            double r = sqrt(r2);
+            double gx = 0.0, gy = 0.0, gz = 0.0;
+            if (r > 0.0) {
+                double dwbar = 0.5 * (orc_kernel_dwdr(r, h[i]) + orc_kernel_dwdr(r, h[j]));
+                gx = dwbar * dx / r;
+                gy = dwbar * dy / r;
+                gz = dwbar * dz / r;
+            }
+            double wx = vx[i] - vx[j], wy = vy[i] - vy[j], wz = vz[i] - vz[j];
+            double vdotr = wx * dx + wy * dy + wz * dz;
+            double hbar = 0.5 * (h[i] + h[j]);
+            double cbar = 0.5 * (c[i] + c[j]);
+            double rhobar = 0.5 * (rho[i] + rho[j]);
+            double mu = 0.0;
+            if (vdotr < 0.0) mu = hbar * vdotr / (r2 + eta2 * hbar * hbar);
+            double Pi = (-alpha * cbar * mu + beta * mu * mu) / rhobar;
+            double G = pr2[i] + pr2[j] + Pi;
+            axi -= m[j] * G * gx;
+            ayi -= m[j] * G * gy;
+            azi -= m[j] * G * gz;
+            dui += 0.5 * m[j] * G * (wx * gx + wy * gy + wz * gz);
+            if (fabs(mu) > mum) mum = fabs(mu);
+            double gn = sqrt(gx * gx + gy * gy + gz * gz);
+            sai += m[j] * fabs(G) * gn;
+            sui += 0.5 * m[j] * fabs(G) * sqrt(wx * wx + wy * wy + wz * wz) * gn;
+        }
+        ax[i] = axi; ay[i] = ayi; az[i] = azi; dudt[i] = dui;
+        if (mumax) mumax[i] = mum;
+        if (sa) sa[i] = sai;
+        if (su) su[i] = sui;
+    }
+}
+
+/* ------------------------------------------------------------ time-step */
+
+/*
+ * Global dt = min_i min( c_cfl h_i / (c_i + 1.2 (alpha c_i + beta mumax_i)),
+ *                        c_force sqrt(h_i / |a_i + g_i|) ),
+ * the force limit skipped where |a + g| = 0 (Monaghan 1989). g may be NULL.
+ */
+double orc_timestep(int64_t n, const double *h, const double *c,
+                    const double *mumax, const double *ax, const double *ay,
+                    const double *az, const double *gx, const double *gy,
+                    const double *gz, double alpha, double beta, double c_cfl,
+                    double c_force)
+{
+    double dt = INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        double d = c_cfl * h[i] / (c[i] + 1.2 * (alpha * c[i] + beta * mumax[i]));
+        double tx = ax[i], ty = ay[i], tz = az[i];
+        if (gx) { tx += gx[i]; ty += gy[i]; tz += gz[i]; }
+        double amag = sqrt(tx * tx + ty * ty + tz * tz);
+        if (amag > 0.0) d = fmin(d, c_force * sqrt(h[i] / amag));
+        dt = fmin(dt, d);
+    }
+    return dt;
+}
+
+/* ---------------------------------------------------------- integration */
+
+/*
+ * Kick-drift-kick leapfrog with a global dt.
+ * stage 0 (kick + drift): v += dt/2 (a + g); u += dt/2 du; x += dt v; each
+ *         periodic coordinate is wrapped back into [lo, hi).
+ * stage 1 (kick):         v += dt/2 (a + g); u += dt/2 du.
+ * g may be NULL.
+ */
+void orc_integrate(int64_t n, int32_t stage, double dt, double *x, double *y,
+                   double *z, double *vx, double *vy, double *vz, double *u,
+                   const double *ax, const double *ay, const double *az,
+                   const double *dudt, const double *gx, const double *gy,
+                   const double *gz, const double *lo, const double *hi,
+                   const int32_t *per)
+{
+    double half = 0.5 * dt;
+    double *p[3] = {x, y, z};
+    #pragma omp parallel for
+    for (int64_t i = 0; i < n; ++i) {
+        double tx = ax[i], ty = ay[i], tz = az[i];
+        if (gx) { tx += gx[i]; ty += gy[i]; tz += gz[i]; }
+        vx[i] += half * tx;
+        vy[i] += half * ty;
+        vz[i] += half * tz;
+        u[i] += half * dudt[i];
+        if (stage == 0) {
+            x[i] += dt * vx[i];
+            y[i] += dt * vy[i];
+            z[i] += dt * vz[i];
+            for (int a = 0; a < 3; ++a) {
+                if (!per[a]) continue;
+                double len = hi[a] - lo[a];
+                if (p[a][i] >= hi[a]) p[a][i] -= len;
+                else if (p[a][i] < lo[a]) p[a][i] += len;
+            }
+        }
+    }
+}
+
+/* ---------------------------------------------------------- diagnostics */
+
+/* Neumaier-compensated running sum. */
+typedef struct { double s, c; } nsum;
+
+static void nsum_add(nsum *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+/*
+ * out[8] = M, Px, Py, Pz, Lx, Ly, Lz, E with P = sum m v, L = sum m x cross v,
+ * E = sum m (v^2/2 + u).
+ */
+void orc_diagnostics(int64_t n, const double *x, const double *y,
+                     const double *z, const double *vx, const double *vy,
+                     const double *vz, const double *u, const double *m,
+                     double *out)
+{
+    nsum acc[8];
+    memset(acc, 0, sizeof(acc));
+    for (int64_t i = 0; i < n; ++i) {
+        double mi = m[i];
+        nsum_add(&acc[0], mi);
+        nsum_add(&acc[1], mi * vx[i]);
+        nsum_add(&acc[2], mi * vy[i]);
+        nsum_add(&acc[3], mi * vz[i]);
+        nsum_add(&acc[4], mi * (y[i] * vz[i] - z[i] * vy[i]));
+        nsum_add(&acc[5], mi * (z[i] * vx[i] - x[i] * vz[i]));
+        nsum_add(&acc[6], mi * (x[i] * vy[i] - y[i] * vx[i]));
+        nsum_add(&acc[7], mi * (0.5 * (vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i]) + u[i]));
+    }
+    for (int k = 0; k < 8; ++k) out[k] = acc[k].s + acc[k].c;
+}
+
+/* -------------------------------------------------------- self-gravity */
+
+/* Plummer-softened direct sum, G = 1: g_i = -sum_{j != i} m_j r_ij /
+ * (r^2 + eps^2)^{3/2}. Supplies the fixed external field of the Evrard
+ * inputs; it is not part of the hydro step. */
+void orc_gravity_direct(int64_t n, const double *x, const double *y,
+                        const double *z, const double *m, double eps,
+                        double *gx, double *gy, double *gz)
+{
+    double e2 = eps * eps;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            double d2 = dx * dx + dy * dy + dz * dz + e2;
+            double inv = 1.0 / (d2 * sqrt(d2));
+            sx -= m[j] * dx * inv;
+            sy -= m[j] * dy * inv;
+            sz -= m[j] * dz * inv;
+        }
+        gx[i] = sx; gy[i] = sy; gz[i] = sz;
+    }
+}
+
+/* ----------------------------------------------------------- threading */
+
+int32_t orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_num_threads(int32_t t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
