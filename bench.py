@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark: SPH hydro steps of the 1,000,000-particle rotating square patch
+on one MI355X, through the C ABI of libsph.
+
+One step = kick-drift, cell build (Morton radix sort + reorder), neighbour
+search, density, EOS, momentum/energy with artificial viscosity, kick, and
+the global time-step with the FP64 conserved totals, all on the GPU. Inputs
+are resident in HBM before the timed region; the t = 0 force evaluation is
+untimed. Prints ONE JSON line.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+
+value = pair-interactions/s of the plain FP64 form (directed neighbour pairs
+per step / wall time per step). The FP32-pair form (FP32 pair arithmetic,
+FP64 state, integration and reductions) is timed on the same GPU and
+reported beside it. The CPU baseline is the FP64 oracle on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+CALLS = ("integrate_kd", "build_cells", "find_neighbors", "density", "eos",
+         "momentum_energy", "integrate_k", "timestep")
+
+
+def kernel_model(n: int, pairs: float, precision: int) -> dict:
+    """Algorithmic HBM bytes and flops per launch of each C-ABI call.
+
+    Bytes: compulsory traffic, each particle's own arrays read/written once,
+    neighbour-list entries 4 B each, neighbour (j) data assumed served from
+    cache. Flops: FP operations per directed pair (pair kernels) or per
+    particle (others) of the arithmetic as written.
+    """
+    nb = pairs / max(n, 1)
+    f32 = precision == 1
+    own_pair = 88 if not f32 else 68        # x y z v h m rho c pr2 (FP32 copies)
+    per_particle_bytes = {
+        "integrate_kd": 136,
+        "build_cells": 40 + 3 * 20 + 2 * 2 * 100 + 8,
+        "find_neighbors": 40 + 4 + 4 * nb,
+        "density": 52 + 4 * nb if not f32 else 44 + 4 * nb,
+        "eos": 60,
+        "momentum_energy": own_pair + 44 + 4 * nb,
+        "integrate_k": 120,
+        "timestep": 112,
+    }
+    flops_per_pair = {"find_neighbors": 12.0 * 729 / max(nb, 1), "density": 20.0,
+                      "momentum_energy": 75.0}
+    out = {}
+    for k in CALLS:
+        b = per_particle_bytes[k] * n
+        fl = flops_per_pair.get(k, 0.0) * pairs
+        out[k] = (b, fl)
+    return out
+
+
+def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128) -> dict:
+    import numpy as np
+    import torch
+
+    from paper_1809_08013_amd import sph as S
+
+    ctx = S.Context(ic.n, max_nb)
+    st = S.SphState(ic, max_nb)
+    prm = S.make_params(ic.params, precision)
+    S.sph_init_forces(ctx, st, prm, set_rho_ref=True)
+    S.sph_ctx_check(ctx)
+
+    calls = [
+        lambda: S.sph_integrate(ctx, st, S.SPH_KICK_DRIFT),
+        lambda: S.sph_build_cells(ctx, st),
+        lambda: S.sph_find_neighbors(ctx, st),
+        lambda: S.sph_density(ctx, st, prm),
+        lambda: S.sph_eos(ctx, st, prm),
+        lambda: S.sph_momentum_energy(ctx, st, prm),
+        lambda: S.sph_integrate(ctx, st, S.SPH_KICK),
+        lambda: S.sph_timestep(ctx, st, prm),
+    ]
+    stream = ctx.stream
+
+    def step(evs=None):
+        for k, c in enumerate(calls):
+            if evs is not None:
+                evs[k].record(stream)
+            c()
+        if evs is not None:
+            evs[len(calls)].record(stream)
+
+    for _ in range(warmup):
+        step()
+    S.sph_ctx_check(ctx)
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
+              for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        step(events[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    S.sph_ctx_check(ctx)
+    per_call = {k: 0.0 for k in CALLS}
+    for evs in events:
+        for k, name in enumerate(CALLS):
+            per_call[name] += evs[k].elapsed_time(evs[k + 1])
+    per_call = {k: v / steps for k, v in per_call.items()}  # ms per launch
+    pairs = float(st.t["count"][: ic.n].sum().item())
+    diag = st.diag
+    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, per_call_ms=per_call,
+                pairs_per_step=pairs, dt=st.dt, diag=diag.tolist(),
+                max_count=int(st.t["count"][: ic.n].max().item()),
+                scratch_bytes=ctx.scratch_bytes)
+
+
+def roofline(n: int, r: dict, precision: int) -> dict:
+    model = kernel_model(n, r["pairs_per_step"], precision)
+    dom = max(CALLS, key=lambda k: r["per_call_ms"][k])
+    b, fl = model[dom]
+    t = r["per_call_ms"][dom] * 1e-3
+    gbs = b / t / 1e9
+    tfl = fl / t / 1e12
+    peak_fl = FP64_VECTOR_PEAK_TFLOPS if precision == 0 else FP32_VECTOR_PEAK_TFLOPS
+    hbm_frac = gbs / HBM_PEAK_GBS
+    alu_frac = tfl / peak_fl
+    if alu_frac > hbm_frac:
+        return dict(bound="alu", kernel=dom, achieved=round(tfl, 3), peak=peak_fl,
+                    unit="TFLOP/s", frac=round(alu_frac, 4), traffic=None,
+                    hbm_gbs=round(gbs, 1), hbm_frac=round(hbm_frac, 4),
+                    ms_per_launch=round(r["per_call_ms"][dom], 4))
+    return dict(bound="hbm", kernel=dom, achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(hbm_frac, 4), traffic=None,
+                alu_tflops=round(tfl, 3), alu_frac=round(alu_frac, 4),
+                ms_per_launch=round(r["per_call_ms"][dom], 4))
+
+
+def cpu_baseline(ic, steps: int) -> dict:
+    import oracle as O
+    run = O.OracleRun(ic).init()
+    t0 = time.perf_counter()
+    pairs = 0
+    for _ in range(steps):
+        run.step()
+        pairs += run.n_pairs
+    t = time.perf_counter() - t0
+    return dict(value=pairs / t, unit="pair-interactions/s", cores=O.num_threads(),
+                kind="oracle", ms_per_step=t * 1e3 / steps,
+                sample=f"{steps} full KDK steps of the same 1,000,000-particle input "
+                       f"(after an untimed t=0 force evaluation), FP64 oracle, OpenMP")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n-side", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1809_08013_amd import inputs as I
+    from paper_1809_08013_amd import sph as S
+    if not os.path.exists(S.LIB_PATH):
+        from paper_1809_08013_amd import build
+        build.build()
+    torch.cuda.set_device(0)
+    ic = I.square_patch(args.n_side, seed=0)
+    n = ic.n
+    r64 = run_gpu(ic, S.SPH_FP64, args.steps, args.warmup)
+    r32 = None if args.no_fp32 else run_gpu(ic, S.SPH_FP32_PAIR, args.steps, args.warmup)
+    value = r64["pairs_per_step"] / (r64["ms_per_step"] * 1e-3)
+    line = {
+        "metric": "SPH pair-interactions/s & step time @1M; p50/p99 ensemble-request latency",
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"rotating square patch, {args.n_side}^3 = {n:,} particles, "
+                        "periodic z, h = 1.5 spacing, cubic spline, Tait EOS, Monaghan AV "
+                        "alpha=1 beta=2, KDK with global Courant dt, FP64",
+            "n_particles": n,
+            "pairs_per_step": r64["pairs_per_step"],
+            "mean_neighbours": r64["pairs_per_step"] / n,
+            "max_neighbours": r64["max_count"],
+        },
+        "per_call_ms": {k: round(v, 4) for k, v in r64["per_call_ms"].items()},
+        "roofline": roofline(n, r64, 0),
+    }
+    if r32 is not None:
+        v32 = r32["pairs_per_step"] / (r32["ms_per_step"] * 1e-3)
+        line["fp32_pair"] = {
+            "value": v32, "ms_per_step": r32["ms_per_step"],
+            "speedup_vs_fp64": r64["ms_per_step"] / r32["ms_per_step"],
+            "per_call_ms": {k: round(v, 4) for k, v in r32["per_call_ms"].items()},
+            "roofline": roofline(n, r32, 1),
+        }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(ic, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

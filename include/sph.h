@@ -1,0 +1,240 @@
+/*
+ * sph.h -- C ABI of libsph: one SPH hydro step on one MI355X (gfx950).
+ *
+ * The step is one pass of the generic SPH loop, Algorithm 1 of the paper
+ * (Sec. 3): build the spatial structure (step 1), find the neighbours
+ * (step 2), evaluate density, pressure, acceleration and the rate of change
+ * of internal energy (step 3, as listed in the prose after Algorithm 1),
+ * compute the new global time-step (step 5) and update velocity and position
+ * (step 6). Self-gravity (step 4) is not computed here; a fixed external
+ * acceleration may be supplied instead.
+ *
+ * The paper names these steps but not their formulas. The library uses:
+ *   - M4 cubic-spline kernel (Table 1), W(r,h) = w(r/h)/(pi h^3), kernel
+ *     derivatives for gradients and standard volume elements m/rho (Table 1);
+ *   - neighbour relation j != i and r^2 < (2 max(h_i,h_j))^2 (strict), with
+ *     r^2 = fma(dz,dz,fma(dy,dy,dx*dx)) in FP64 and the minimum image on
+ *     periodic axes (d > L/2: d -= L; d < -L/2: d += L);
+ *   - density by summation including the self term, gathered with h_i;
+ *   - Tait EOS P = p_bg + B((rho/rho_ref)^7 - 1), c = c0 (rho/rho_ref)^3,
+ *     B = rho0 c0^2/7, or ideal gas P = (gamma-1) rho u (Sec. 5.1, Evrard);
+ *   - momentum a_i = -sum_j m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi_ij) gradW_ij
+ *     with gradW_ij the mean of the gradients at h_i and h_j; energy
+ *     du_i = 1/2 sum_j m_j (...) v_ij . gradW_ij; Monaghan viscosity
+ *     mu = hbar v.r/(r^2 + eta2 hbar^2) if v.r < 0, Pi = (-alpha cbar mu +
+ *     beta mu^2)/rhobar;
+ *   - global dt = min_i min(c_cfl h_i/(c_i + 1.2(alpha c_i + beta mumax_i)),
+ *     c_force sqrt(h_i/|a_i + g_i|));
+ *   - kick-drift-kick leapfrog with that global dt.
+ *
+ * Conventions
+ *   - Every call returns sph_status. No exceptions cross this boundary.
+ *   - Every pointer inside the structs below is a DEVICE pointer owned by the
+ *     caller (e.g. a torch tensor's storage), unless stated otherwise. Arrays
+ *     are structure-of-arrays, FP64 (int32 for id, count and idx), one entry
+ *     per particle.
+ *   - The library owns only the opaque context and its scratch (sort buffers,
+ *     cell table, reduction partials, FP32 copies, status word), allocated
+ *     once by sph_ctx_create for n_max particles. Step calls never allocate.
+ *   - Calls are asynchronous and ordered on the context's stream (borrowed,
+ *     never destroyed by the library). Host-side argument errors return at
+ *     once. Device-side conditions (neighbour overflow, h above the h_max the
+ *     caller promised, non-finite state) set a status word on the device;
+ *     sph_ctx_check synchronises the stream, returns and clears it.
+ *   - sph_build_cells reorders every particle array in place, in lockstep,
+ *     into cell (Morton) order; id[] carries the original ids. Neighbour
+ *     indices always refer to the current order.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sph_status;
+enum {
+    SPH_OK = 0,
+    SPH_E_INVALID = 1,   /* bad argument (null pointer, size, enum) */
+    SPH_E_CAPACITY = 2,  /* a neighbour list exceeded max_nb (truncated) */
+    SPH_E_HIP = 3,       /* a HIP runtime call failed */
+    SPH_E_DOMAIN = 4,    /* h_i > h_max, or a periodic axis shorter than 4 h_max */
+    SPH_E_NOMEM = 5,     /* device allocation failed */
+    SPH_E_AGAIN = 6,     /* result not ready yet (serving) */
+    SPH_E_NONFINITE = 7  /* NaN or Inf in the state */
+};
+
+enum { SPH_FP64 = 0, SPH_FP32_PAIR = 1 };        /* sph_params.precision */
+enum { SPH_EOS_TAIT = 0, SPH_EOS_IDEAL = 1 };    /* sph_params.eos */
+enum { SPH_KICK_DRIFT = 0, SPH_KICK = 1 };       /* sph_integrate stage */
+
+typedef struct sph_ctx_s *sph_ctx;
+typedef void *sph_stream; /* a hipStream_t; NULL = the null stream */
+
+/* Particle state. gx, gy, gz: optional fixed external acceleration (NULL
+ * when absent); they are permuted with the rest. rho_ref and p_bg are the
+ * per-particle Tait reference density and background pressure (read only by
+ * the Tait EOS; may be NULL for the ideal gas). */
+typedef struct {
+    int64_t n;
+    double *x, *y, *z, *vx, *vy, *vz, *u, *h, *m, *rho_ref, *p_bg;
+    double *gx, *gy, *gz;
+    int32_t *id;
+} sph_particles;
+
+/* Axis-aligned box. On a periodic axis positions live in [lo, hi) and the
+ * minimum image applies; on an open axis the box only sizes the cell grid
+ * (particles outside it are clamped into the border cells, which keeps the
+ * search exact). Host memory. */
+typedef struct {
+    double lo[3], hi[3];
+    int32_t periodic[3];
+} sph_box;
+
+/* Neighbour lists, ELL layout, column-major: the k-th neighbour of particle
+ * i is idx[k * n + i], k < min(count[i], max_nb). count[i] is the true count,
+ * which may exceed max_nb only after SPH_E_CAPACITY was raised. */
+typedef struct {
+    int32_t max_nb;
+    int32_t *count;  /* [n] */
+    int32_t *idx;    /* [max_nb * n] */
+} sph_nbrs;
+
+/* Per-particle fields from sph_density / sph_eos. pr2 = P / rho^2. */
+typedef struct {
+    double *rho, *p, *c, *pr2;
+} sph_fields;
+
+/* Outputs of sph_momentum_energy: hydrodynamic acceleration (external g not
+ * included), du/dt, and the largest |mu| over each particle's pairs. */
+typedef struct {
+    double *ax, *ay, *az, *dudt, *mumax;
+} sph_accel;
+
+/* Scalar physics constants (host memory). precision selects the pair
+ * arithmetic of sph_density and sph_momentum_energy: SPH_FP64, or
+ * SPH_FP32_PAIR (separations formed in FP64 and rounded to FP32, FP32 copies
+ * of h, m, rho, P/rho^2 and c, FP32 accumulation, results widened to FP64;
+ * the neighbour relation, the state, the integration and all reductions stay
+ * FP64). */
+typedef struct {
+    int32_t precision;
+    int32_t eos;
+    double rho0, c0, gamma_tait, gamma_gas;
+    double alpha, beta, eta2;
+    double c_cfl, c_force;
+} sph_params;
+
+/* Text for a status code (static storage). */
+const char *sph_status_string(sph_status s);
+
+/* Detail of the last error seen on ctx (valid until the next call). */
+const char *sph_last_error(sph_ctx ctx);
+
+/* Library and device description, e.g. "libsph 1 gfx950 256 CUs" (static). */
+const char *sph_version(void);
+
+/* Create a context for up to n_max particles (n_max >= 1) and neighbour
+ * lists of width max_nb (1..4096) on the current HIP device; all scratch is
+ * allocated here. Returns SPH_E_NOMEM if the device memory is not there. */
+sph_status sph_ctx_create(sph_ctx *out, int64_t n_max, int32_t max_nb,
+                          sph_stream stream);
+
+/* Release the context and its scratch (synchronises its stream first). */
+sph_status sph_ctx_destroy(sph_ctx ctx);
+
+/* Synchronise the stream and return (and clear) the device status word:
+ * SPH_OK or the first error raised since the last check. */
+sph_status sph_ctx_check(sph_ctx ctx);
+
+/* Bytes of device scratch held by ctx (host value). */
+int64_t sph_ctx_scratch_bytes(sph_ctx ctx);
+
+/* Algorithm 1, step 1. Assign every particle to a cell of side
+ * >= 2 h_max (1 + 1e-9), sort the particles by the cell's Morton key (stable
+ * LSD radix sort, so equal keys keep their previous order), reorder all
+ * particle arrays of p in place and build the cell table. h_max is the
+ * caller's bound on h (no device-to-host copy); a particle with h > h_max
+ * raises SPH_E_DOMAIN. A periodic axis must be longer than 4 h_max. */
+sph_status sph_build_cells(sph_ctx ctx, const sph_particles *p,
+                           const sph_box *box, double h_max);
+
+/* Algorithm 1, step 2. Neighbour sets by the relation stated at the top of
+ * this file, searched over the 27 cells around each particle's cell. Needs a
+ * preceding sph_build_cells on the same particles. Raises SPH_E_CAPACITY on
+ * overflow (lists truncated at max_nb, count still exact). */
+sph_status sph_find_neighbors(sph_ctx ctx, const sph_particles *p,
+                              const sph_box *box, const sph_nbrs *nb);
+
+/* Algorithm 1, step 3: summation density
+ * rho_i = m_i W(0,h_i) + sum_{j in N_i} m_j W(r_ij, h_i). */
+sph_status sph_density(sph_ctx ctx, const sph_particles *p,
+                       const sph_box *box, const sph_nbrs *nb,
+                       const sph_params *prm, double *rho);
+
+/* Algorithm 1, step 3: EOS. Reads f->rho and p->u (ideal) or p->rho_ref,
+ * p->p_bg (Tait); writes f->p, f->c, f->pr2 (and the FP32 copies used by the
+ * FP32-pair form). */
+sph_status sph_eos(sph_ctx ctx, const sph_particles *p, const sph_params *prm,
+                   const sph_fields *f);
+
+/* Algorithm 1, step 3: acceleration, du/dt and per-particle max |mu|. */
+sph_status sph_momentum_energy(sph_ctx ctx, const sph_particles *p,
+                               const sph_box *box, const sph_nbrs *nb,
+                               const sph_params *prm, const sph_fields *f,
+                               const sph_accel *a);
+
+/* Algorithm 1, step 6, one half of a kick-drift-kick step with the global
+ * dt read from device memory dt_dev[0]:
+ *   SPH_KICK_DRIFT: v += dt/2 (a + g); u += dt/2 du; x += dt v; wrap
+ *                   periodic coordinates into [lo, hi);
+ *   SPH_KICK:       v += dt/2 (a + g); u += dt/2 du; raises SPH_E_NONFINITE
+ *                   if the new state holds a NaN or Inf. */
+sph_status sph_integrate(sph_ctx ctx, const sph_particles *p,
+                         const sph_box *box, int32_t stage,
+                         const double *dt_dev, const sph_accel *a);
+
+/* Algorithm 1, step 5: dt_dev[0] = global minimum of the Courant and force
+ * limits (two-level min reduction, exact). If diag_dev is not NULL it
+ * receives 8 FP64 totals: M, Px, Py, Pz, Lx, Ly, Lz, E with P = sum m v,
+ * L = sum m x cross v, E = sum m (v^2/2 + u), summed in a fixed tree order
+ * (deterministic). */
+sph_status sph_timestep(sph_ctx ctx, const sph_particles *p,
+                        const sph_params *prm, const sph_fields *f,
+                        const sph_accel *a, double *dt_dev, double *diag_dev);
+
+/* Forces at the current state: build cells, neighbours, density, EOS (if
+ * set_rho_ref, rho_ref := rho first, so that P = p_bg), momentum and energy,
+ * then dt. The t = 0 evaluation that precedes the first step. */
+sph_status sph_init_forces(sph_ctx ctx, const sph_particles *p,
+                           const sph_box *box, double h_max,
+                           const sph_nbrs *nb, const sph_params *prm,
+                           const sph_fields *f, const sph_accel *a,
+                           int32_t set_rho_ref, double *dt_dev,
+                           double *diag_dev);
+
+/* One whole hydro step: sph_integrate(KICK_DRIFT), sph_build_cells,
+ * sph_find_neighbors, sph_density, sph_eos, sph_momentum_energy,
+ * sph_integrate(KICK), sph_timestep, in that order on ctx's stream. */
+sph_status sph_step(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                    double h_max, const sph_nbrs *nb, const sph_params *prm,
+                    const sph_fields *f, const sph_accel *a, double *dt_dev,
+                    double *diag_dev);
+
+/* Test helper (synchronising): neighbour sets in ORIGINAL-id terms.
+ * offsets_host[n+1] (int64) and ids_host[cap] (int32) are HOST buffers;
+ * the set of original id k is ids_host[offsets_host[k] .. offsets_host[k+1]),
+ * sorted ascending. Requires the ids to be a permutation of 0..n-1.
+ * *total receives the number of entries (SPH_E_CAPACITY if > cap). */
+sph_status sph_export_neighbors(sph_ctx ctx, const sph_particles *p,
+                                const sph_nbrs *nb, int64_t *offsets_host,
+                                int32_t *ids_host, int64_t cap,
+                                int64_t *total);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

@@ -1,0 +1,483 @@
+// Host side of the C ABI declared in include/sph.h: argument checks, the
+// context and its scratch, grid set-up and the order of launches.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sph_internal.h"
+
+using namespace sph;
+
+namespace {
+
+thread_local std::string g_no_ctx_error;
+
+sph_status fail(sph_ctx ctx, sph_status s, const char *fmt, ...)
+    __attribute__((format(printf, 3, 4)));
+
+sph_status fail(sph_ctx ctx, sph_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->last_error = buf;
+    else g_no_ctx_error = buf;
+    return s;
+}
+
+sph_status hip_fail(sph_ctx ctx, hipError_t e, const char *where)
+{
+    return fail(ctx, SPH_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define SPH_HIP(ctx, call)                                          \
+    do {                                                            \
+        hipError_t e_ = (call);                                     \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);    \
+    } while (0)
+
+sph_status check_particles(sph_ctx ctx, const sph_particles *p, bool need_v)
+{
+    if (!p) return fail(ctx, SPH_E_INVALID, "particles is NULL");
+    if (p->n < 0 || p->n > ctx->n_max)
+        return fail(ctx, SPH_E_INVALID, "n = %lld outside [0, n_max = %lld]",
+                    (long long)p->n, (long long)ctx->n_max);
+    if (p->n > 0) {
+        if (!p->x || !p->y || !p->z || !p->h || !p->m || !p->id)
+            return fail(ctx, SPH_E_INVALID, "x, y, z, h, m and id are required");
+        if (need_v && (!p->vx || !p->vy || !p->vz || !p->u))
+            return fail(ctx, SPH_E_INVALID, "vx, vy, vz and u are required");
+        const bool any_g = p->gx || p->gy || p->gz, all_g = p->gx && p->gy && p->gz;
+        if (any_g && !all_g) return fail(ctx, SPH_E_INVALID, "gx, gy, gz: all or none");
+    }
+    return SPH_OK;
+}
+
+sph_status check_box(sph_ctx ctx, const sph_box *b)
+{
+    if (!b) return fail(ctx, SPH_E_INVALID, "box is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (!(std::isfinite(b->lo[a]) && std::isfinite(b->hi[a]) && b->hi[a] > b->lo[a]))
+            return fail(ctx, SPH_E_INVALID, "box axis %d: need finite lo < hi", a);
+        if (b->periodic[a] != 0 && b->periodic[a] != 1)
+            return fail(ctx, SPH_E_INVALID, "box axis %d: periodic must be 0 or 1", a);
+    }
+    return SPH_OK;
+}
+
+sph_status check_nbrs(sph_ctx ctx, const sph_nbrs *nb, int64_t n)
+{
+    if (!nb) return fail(ctx, SPH_E_INVALID, "nbrs is NULL");
+    if (nb->max_nb < 1 || nb->max_nb > ctx->max_nb)
+        return fail(ctx, SPH_E_INVALID, "max_nb = %d outside [1, %d]", nb->max_nb, ctx->max_nb);
+    if (n > 0 && (!nb->count || !nb->idx))
+        return fail(ctx, SPH_E_INVALID, "count and idx are required");
+    return SPH_OK;
+}
+
+sph_status check_params(sph_ctx ctx, const sph_params *prm)
+{
+    if (!prm) return fail(ctx, SPH_E_INVALID, "params is NULL");
+    if (prm->precision != SPH_FP64 && prm->precision != SPH_FP32_PAIR)
+        return fail(ctx, SPH_E_INVALID, "unknown precision %d", prm->precision);
+    if (prm->eos != SPH_EOS_TAIT && prm->eos != SPH_EOS_IDEAL)
+        return fail(ctx, SPH_E_INVALID, "unknown eos %d", prm->eos);
+    return SPH_OK;
+}
+
+// Grid of cells of side >= 2 h_max (1 + 1e-9) on every axis, at most
+// kMaxAxisCells per axis and ctx->cell_cap in total.
+Grid make_grid(const sph_box &b, double h_max, int64_t cell_cap)
+{
+    Grid g{};
+    const double want = 2.0 * h_max * (1.0 + 1e-9);
+    for (int a = 0; a < 3; ++a) {
+        g.periodic[a] = b.periodic[a];
+        g.lo[a] = b.lo[a];
+        g.hi[a] = b.hi[a];
+        g.len[a] = b.hi[a] - b.lo[a];
+        g.half[a] = 0.5 * g.len[a];
+        double nc = std::floor(g.len[a] / want);
+        nc = std::min(std::max(nc, 1.0), (double)kMaxAxisCells);
+        g.nc[a] = (int)nc;
+    }
+    while ((int64_t)g.nc[0] * g.nc[1] * g.nc[2] > cell_cap) {
+        int a = 0;
+        for (int k = 1; k < 3; ++k)
+            if (g.nc[k] > g.nc[a]) a = k;
+        g.nc[a] = std::max(1, g.nc[a] / 2);
+    }
+    int maxc = std::max(g.nc[0], std::max(g.nc[1], g.nc[2]));
+    g.bits = 0;
+    while ((1 << g.bits) < maxc) ++g.bits;
+    for (int a = 0; a < 3; ++a) g.inv_s[a] = (double)g.nc[a] / g.len[a];
+    return g;
+}
+
+Grid box_grid(const sph_box &b)
+{
+    Grid g{};
+    for (int a = 0; a < 3; ++a) {
+        g.periodic[a] = b.periodic[a];
+        g.lo[a] = b.lo[a];
+        g.hi[a] = b.hi[a];
+        g.len[a] = b.hi[a] - b.lo[a];
+        g.half[a] = 0.5 * g.len[a];
+        g.nc[a] = 1;
+    }
+    return g;
+}
+
+bool same_box(const Grid &g, const sph_box &b)
+{
+    for (int a = 0; a < 3; ++a)
+        if (g.lo[a] != b.lo[a] || g.hi[a] != b.hi[a] || g.periodic[a] != b.periodic[a])
+            return false;
+    return true;
+}
+
+template <typename T>
+sph_status dev_alloc(sph_ctx ctx, T **p, int64_t count)
+{
+    const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    if (hipMalloc((void **)p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, SPH_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    ctx->scratch_bytes += (int64_t)bytes;
+    return SPH_OK;
+}
+
+void free_ctx(sph_ctx ctx)
+{
+    void *ptrs[] = {ctx->keys[0], ctx->keys[1], ctx->vals[0], ctx->vals[1], ctx->hist,
+                    ctx->scan_part, ctx->cell_start, ctx->cell_end, ctx->perm_tmp,
+                    ctx->perm_tmp_id, ctx->hf, ctx->mf, ctx->rhof, ctx->pr2f, ctx->cf,
+                    ctx->red_part, ctx->status_dev};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete ctx;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sph_status_string(sph_status s)
+{
+    switch (s) {
+    case SPH_OK: return "ok";
+    case SPH_E_INVALID: return "invalid argument";
+    case SPH_E_CAPACITY: return "neighbour list capacity exceeded";
+    case SPH_E_HIP: return "HIP runtime error";
+    case SPH_E_DOMAIN: return "domain error (h above h_max or periodic axis too short)";
+    case SPH_E_NOMEM: return "out of device memory";
+    case SPH_E_AGAIN: return "not ready";
+    case SPH_E_NONFINITE: return "non-finite state";
+    default: return "unknown status";
+    }
+}
+
+const char *sph_last_error(sph_ctx ctx)
+{
+    return ctx ? ctx->last_error.c_str() : g_no_ctx_error.c_str();
+}
+
+const char *sph_version(void)
+{
+    static char buf[128];
+    hipDeviceProp_t prop;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        snprintf(buf, sizeof buf, "libsph 1 %s %d CUs", prop.gcnArchName,
+                 prop.multiProcessorCount);
+    else
+        snprintf(buf, sizeof buf, "libsph 1 (no device)");
+    return buf;
+}
+
+sph_status sph_ctx_create(sph_ctx *out, int64_t n_max, int32_t max_nb, sph_stream stream)
+{
+    if (!out) return fail(nullptr, SPH_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_max < 1 || n_max > ((int64_t)1 << 31) - kSortTile)
+        return fail(nullptr, SPH_E_INVALID, "n_max = %lld out of range", (long long)n_max);
+    if (max_nb < 1 || max_nb > 4096)
+        return fail(nullptr, SPH_E_INVALID, "max_nb = %d out of range [1, 4096]", max_nb);
+    if ((int64_t)max_nb * n_max >= ((int64_t)1 << 40))
+        return fail(nullptr, SPH_E_INVALID, "max_nb * n_max too large");
+    sph_ctx ctx = new (std::nothrow) sph_ctx_s();
+    if (!ctx) return fail(nullptr, SPH_E_NOMEM, "host allocation failed");
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, SPH_E_HIP, "no HIP device");
+    }
+    ctx->stream = (hipStream_t)stream;
+    ctx->n_max = n_max;
+    ctx->max_nb = max_nb;
+    ctx->tiles_max = (n_max + kSortTile - 1) / kSortTile;
+    ctx->scan_len_max = ctx->tiles_max * kRadixBins;
+    ctx->cell_cap = std::max<int64_t>(2 * n_max + 64, 32768);
+    sph_status s = SPH_OK;
+#define ALLOC(ptr, count)                                   \
+    if (s == SPH_OK) s = dev_alloc(ctx, &(ptr), (count));
+    ALLOC(ctx->keys[0], n_max);
+    ALLOC(ctx->keys[1], n_max);
+    ALLOC(ctx->vals[0], n_max);
+    ALLOC(ctx->vals[1], n_max);
+    ALLOC(ctx->hist, ctx->scan_len_max);
+    ALLOC(ctx->scan_part, (ctx->scan_len_max + kScanChunk - 1) / kScanChunk + 1);
+    ALLOC(ctx->cell_start, ctx->cell_cap);
+    ALLOC(ctx->cell_end, ctx->cell_cap);
+    ALLOC(ctx->perm_tmp, (int64_t)kPermFields * n_max);
+    ALLOC(ctx->perm_tmp_id, n_max);
+    ALLOC(ctx->hf, n_max);
+    ALLOC(ctx->mf, n_max);
+    ALLOC(ctx->rhof, n_max);
+    ALLOC(ctx->pr2f, n_max);
+    ALLOC(ctx->cf, n_max);
+    ALLOC(ctx->red_part, (int64_t)kRedFields * kRedMaxBlocks);
+    ALLOC(ctx->status_dev, 1);
+#undef ALLOC
+    if (s != SPH_OK) {
+        g_no_ctx_error = ctx->last_error;
+        free_ctx(ctx);
+        return s;
+    }
+    if (hipMemsetAsync(ctx->status_dev, 0, sizeof(uint32_t), ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        free_ctx(ctx);
+        return fail(nullptr, SPH_E_HIP, "status word initialisation failed");
+    }
+    *out = ctx;
+    return SPH_OK;
+}
+
+sph_status sph_ctx_destroy(sph_ctx ctx)
+{
+    if (!ctx) return SPH_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_ctx(ctx);
+    return SPH_OK;
+}
+
+int64_t sph_ctx_scratch_bytes(sph_ctx ctx) { return ctx ? ctx->scratch_bytes : 0; }
+
+sph_status sph_ctx_check(sph_ctx ctx)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    SPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    uint32_t st = 0;
+    SPH_HIP(ctx, hipMemcpy(&st, ctx->status_dev, sizeof st, hipMemcpyDeviceToHost));
+    if (st) SPH_HIP(ctx, hipMemset(ctx->status_dev, 0, sizeof st));
+    if (st & ST_DOMAIN) return fail(ctx, SPH_E_DOMAIN, "a particle has h > h_max");
+    if (st & ST_CAPACITY) return fail(ctx, SPH_E_CAPACITY, "a neighbour list exceeded max_nb");
+    if (st & ST_NONFINITE) return fail(ctx, SPH_E_NONFINITE, "NaN or Inf in the state");
+    return SPH_OK;
+}
+
+sph_status sph_build_cells(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                           double h_max)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, false)) != SPH_OK) return s;
+    if ((s = check_box(ctx, box)) != SPH_OK) return s;
+    if (!(h_max > 0.0) || !std::isfinite(h_max))
+        return fail(ctx, SPH_E_INVALID, "h_max must be finite and > 0");
+    for (int a = 0; a < 3; ++a)
+        if (box->periodic[a] && !(box->hi[a] - box->lo[a] > 4.0 * h_max))
+            return fail(ctx, SPH_E_DOMAIN, "periodic axis %d is not longer than 4 h_max", a);
+    ctx->grid = make_grid(*box, h_max, ctx->cell_cap);
+    ctx->n_built = p->n;
+    if (p->n == 0) return SPH_OK;
+    SPH_HIP(ctx, launch_build_cells(ctx, *p, ctx->grid, h_max));
+    return SPH_OK;
+}
+
+sph_status sph_find_neighbors(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                              const sph_nbrs *nb)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, false)) != SPH_OK) return s;
+    if ((s = check_box(ctx, box)) != SPH_OK) return s;
+    if ((s = check_nbrs(ctx, nb, p->n)) != SPH_OK) return s;
+    if (ctx->n_built != p->n || !same_box(ctx->grid, *box))
+        return fail(ctx, SPH_E_INVALID, "sph_build_cells was not called for these particles/box");
+    if (p->n == 0) return SPH_OK;
+    SPH_HIP(ctx, launch_find_neighbors(ctx, *p, *nb));
+    return SPH_OK;
+}
+
+sph_status sph_density(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                       const sph_nbrs *nb, const sph_params *prm, double *rho)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, false)) != SPH_OK) return s;
+    if ((s = check_box(ctx, box)) != SPH_OK) return s;
+    if ((s = check_nbrs(ctx, nb, p->n)) != SPH_OK) return s;
+    if ((s = check_params(ctx, prm)) != SPH_OK) return s;
+    if (p->n > 0 && !rho) return fail(ctx, SPH_E_INVALID, "rho is NULL");
+    if (ctx->n_built != p->n || !same_box(ctx->grid, *box))
+        return fail(ctx, SPH_E_INVALID, "sph_build_cells was not called for these particles/box");
+    if (p->n == 0) return SPH_OK;
+    SPH_HIP(ctx, launch_density(ctx, *p, *nb, prm->precision, rho));
+    return SPH_OK;
+}
+
+sph_status sph_eos(sph_ctx ctx, const sph_particles *p, const sph_params *prm,
+                   const sph_fields *f)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, false)) != SPH_OK) return s;
+    if ((s = check_params(ctx, prm)) != SPH_OK) return s;
+    if (!f) return fail(ctx, SPH_E_INVALID, "fields is NULL");
+    if (p->n == 0) return SPH_OK;
+    if (!f->rho || !f->p || !f->c || !f->pr2)
+        return fail(ctx, SPH_E_INVALID, "rho, p, c and pr2 are required");
+    if (prm->eos == SPH_EOS_TAIT && (!p->rho_ref || !p->p_bg))
+        return fail(ctx, SPH_E_INVALID, "the Tait EOS needs rho_ref and p_bg");
+    if (prm->eos == SPH_EOS_IDEAL && !p->u)
+        return fail(ctx, SPH_E_INVALID, "the ideal-gas EOS needs u");
+    SPH_HIP(ctx, launch_eos(ctx, *p, *prm, *f));
+    return SPH_OK;
+}
+
+sph_status sph_momentum_energy(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                               const sph_nbrs *nb, const sph_params *prm,
+                               const sph_fields *f, const sph_accel *a)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, true)) != SPH_OK) return s;
+    if ((s = check_box(ctx, box)) != SPH_OK) return s;
+    if ((s = check_nbrs(ctx, nb, p->n)) != SPH_OK) return s;
+    if ((s = check_params(ctx, prm)) != SPH_OK) return s;
+    if (!f || !a) return fail(ctx, SPH_E_INVALID, "fields and accel are required");
+    if (ctx->n_built != p->n || !same_box(ctx->grid, *box))
+        return fail(ctx, SPH_E_INVALID, "sph_build_cells was not called for these particles/box");
+    if (p->n == 0) return SPH_OK;
+    if (!f->rho || !f->c || !f->pr2 || !a->ax || !a->ay || !a->az || !a->dudt || !a->mumax)
+        return fail(ctx, SPH_E_INVALID, "rho, c, pr2, ax, ay, az, dudt, mumax are required");
+    SPH_HIP(ctx, launch_momentum(ctx, *p, *nb, *prm, *f, *a));
+    return SPH_OK;
+}
+
+sph_status sph_integrate(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                         int32_t stage, const double *dt_dev, const sph_accel *a)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, true)) != SPH_OK) return s;
+    if ((s = check_box(ctx, box)) != SPH_OK) return s;
+    if (stage != SPH_KICK_DRIFT && stage != SPH_KICK)
+        return fail(ctx, SPH_E_INVALID, "unknown stage %d", stage);
+    if (!dt_dev || !a) return fail(ctx, SPH_E_INVALID, "dt_dev and accel are required");
+    if (p->n == 0) return SPH_OK;
+    if (!a->ax || !a->ay || !a->az || !a->dudt)
+        return fail(ctx, SPH_E_INVALID, "ax, ay, az, dudt are required");
+    SPH_HIP(ctx, launch_integrate(ctx, *p, box_grid(*box), stage, dt_dev, *a));
+    return SPH_OK;
+}
+
+sph_status sph_timestep(sph_ctx ctx, const sph_particles *p, const sph_params *prm,
+                        const sph_fields *f, const sph_accel *a, double *dt_dev,
+                        double *diag_dev)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, true)) != SPH_OK) return s;
+    if ((s = check_params(ctx, prm)) != SPH_OK) return s;
+    if (!f || !a || !dt_dev) return fail(ctx, SPH_E_INVALID, "fields, accel, dt_dev required");
+    if (p->n > 0 && (!f->c || !a->ax || !a->ay || !a->az || !a->mumax))
+        return fail(ctx, SPH_E_INVALID, "c, ax, ay, az, mumax are required");
+    SPH_HIP(ctx, launch_timestep(ctx, *p, *prm, *f, *a, dt_dev, diag_dev));
+    return SPH_OK;
+}
+
+sph_status sph_init_forces(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                           double h_max, const sph_nbrs *nb, const sph_params *prm,
+                           const sph_fields *f, const sph_accel *a, int32_t set_rho_ref,
+                           double *dt_dev, double *diag_dev)
+{
+    sph_status s;
+    if ((s = sph_build_cells(ctx, p, box, h_max)) != SPH_OK) return s;
+    if ((s = sph_find_neighbors(ctx, p, box, nb)) != SPH_OK) return s;
+    if (!f) return fail(ctx, SPH_E_INVALID, "fields is NULL");
+    if ((s = sph_density(ctx, p, box, nb, prm, f->rho)) != SPH_OK) return s;
+    if (set_rho_ref && p->n > 0) {
+        if (!p->rho_ref) return fail(ctx, SPH_E_INVALID, "set_rho_ref needs rho_ref");
+        SPH_HIP(ctx, launch_copy(ctx, p->rho_ref, f->rho, p->n));
+    }
+    if ((s = sph_eos(ctx, p, prm, f)) != SPH_OK) return s;
+    if ((s = sph_momentum_energy(ctx, p, box, nb, prm, f, a)) != SPH_OK) return s;
+    return sph_timestep(ctx, p, prm, f, a, dt_dev, diag_dev);
+}
+
+sph_status sph_step(sph_ctx ctx, const sph_particles *p, const sph_box *box, double h_max,
+                    const sph_nbrs *nb, const sph_params *prm, const sph_fields *f,
+                    const sph_accel *a, double *dt_dev, double *diag_dev)
+{
+    sph_status s;
+    if ((s = sph_integrate(ctx, p, box, SPH_KICK_DRIFT, dt_dev, a)) != SPH_OK) return s;
+    if ((s = sph_build_cells(ctx, p, box, h_max)) != SPH_OK) return s;
+    if ((s = sph_find_neighbors(ctx, p, box, nb)) != SPH_OK) return s;
+    if (!f) return fail(ctx, SPH_E_INVALID, "fields is NULL");
+    if ((s = sph_density(ctx, p, box, nb, prm, f->rho)) != SPH_OK) return s;
+    if ((s = sph_eos(ctx, p, prm, f)) != SPH_OK) return s;
+    if ((s = sph_momentum_energy(ctx, p, box, nb, prm, f, a)) != SPH_OK) return s;
+    if ((s = sph_integrate(ctx, p, box, SPH_KICK, dt_dev, a)) != SPH_OK) return s;
+    return sph_timestep(ctx, p, prm, f, a, dt_dev, diag_dev);
+}
+
+sph_status sph_export_neighbors(sph_ctx ctx, const sph_particles *p, const sph_nbrs *nb,
+                                int64_t *offsets_host, int32_t *ids_host, int64_t cap,
+                                int64_t *total)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, false)) != SPH_OK) return s;
+    if ((s = check_nbrs(ctx, nb, p->n)) != SPH_OK) return s;
+    if (!offsets_host || !total || (cap > 0 && !ids_host))
+        return fail(ctx, SPH_E_INVALID, "offsets_host, ids_host and total are required");
+    const int64_t n = p->n;
+    offsets_host[0] = 0;
+    *total = 0;
+    if (n == 0) return SPH_OK;
+    SPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<int32_t> count(n), id(n), idx((size_t)nb->max_nb * n);
+    SPH_HIP(ctx, hipMemcpy(count.data(), nb->count, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    SPH_HIP(ctx, hipMemcpy(id.data(), p->id, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    SPH_HIP(ctx, hipMemcpy(idx.data(), nb->idx, sizeof(int32_t) * idx.size(),
+                           hipMemcpyDeviceToHost));
+    std::vector<int64_t> slot_of(n, -1);
+    for (int64_t i = 0; i < n; ++i) {
+        if (id[i] < 0 || id[i] >= n || slot_of[id[i]] >= 0)
+            return fail(ctx, SPH_E_INVALID, "ids are not a permutation of 0..n-1");
+        slot_of[id[i]] = i;
+    }
+    for (int64_t k = 0; k < n; ++k)
+        offsets_host[k + 1] = offsets_host[k] + std::min(count[slot_of[k]], nb->max_nb);
+    *total = offsets_host[n];
+    if (*total > cap) return fail(ctx, SPH_E_CAPACITY, "export needs %lld entries", (long long)*total);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t i = slot_of[k];
+        const int c = std::min(count[i], nb->max_nb);
+        int32_t *dst = ids_host + offsets_host[k];
+        for (int t = 0; t < c; ++t) dst[t] = id[idx[(size_t)t * n + i]];
+        std::sort(dst, dst + c);
+    }
+    return SPH_OK;
+}
+
+}  // extern "C"

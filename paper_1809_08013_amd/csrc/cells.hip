@@ -1,0 +1,330 @@
+// Algorithm 1, step 1 on the GPU: cell assignment, Morton keys, stable LSD
+// radix sort, in-place reorder of the particle arrays and the cell table.
+//
+// The paper's parent codes build an octree here (Sec. 5.2.5, phase A). A
+// uniform grid of cells of side >= 2 h_max sorted along a Morton curve gives
+// the same exact candidate set for a fixed-radius search and keeps the
+// particles of a cell, and of neighbouring cells, contiguous in memory.
+#include "sph_internal.h"
+
+namespace sph {
+namespace {
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030C30C3u;
+    v = (v | (v >> 4)) & 0x0300F00Fu;
+    v = (v | (v >> 8)) & 0x030000FFu;
+    v = (v | (v >> 16)) & 0x000003FFu;
+    return v;
+}
+
+__device__ __forceinline__ int cell_of(double v, double lo, double inv_s, int nc)
+{
+    double f = floor((v - lo) * inv_s);
+    f = fmin(fmax(f, 0.0), (double)(nc - 1));
+    return (int)f;
+}
+
+// Morton key of each particle's cell; vals = current index. Flags h > h_max.
+__global__ void __launch_bounds__(256)
+keys_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+            const double *__restrict__ z, const double *__restrict__ h, Grid g,
+            double h_max, uint32_t *__restrict__ keys, int32_t *__restrict__ vals,
+            uint32_t *status)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t cx = (uint32_t)cell_of(x[i], g.lo[0], g.inv_s[0], g.nc[0]);
+    uint32_t cy = (uint32_t)cell_of(y[i], g.lo[1], g.inv_s[1], g.nc[1]);
+    uint32_t cz = (uint32_t)cell_of(z[i], g.lo[2], g.inv_s[2], g.nc[2]);
+    keys[i] = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+    vals[i] = (int32_t)i;
+    if (!(h[i] <= h_max)) atomicOr(status, ST_DOMAIN);
+}
+
+// Per-tile digit histogram, digit-major layout hist[d * ntiles + tile].
+__global__ void __launch_bounds__(kSortThreads)
+radix_hist_kernel(const uint32_t *__restrict__ keys, int64_t n, int shift,
+                  uint32_t *__restrict__ hist, int64_t ntiles)
+{
+    __shared__ uint32_t cnt[kRadixBins];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        int64_t i = base + it * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads, wave64).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total,
+                                                         uint32_t *lds /*[4]*/)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) lds[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        uint32_t s = lds[w];
+        if (w < wave) before += s;
+        all += s;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+// Scan phase 1: per-chunk sums.
+__global__ void __launch_bounds__(kScanThreads)
+scan_reduce_kernel(const uint32_t *__restrict__ a, int64_t len,
+                   uint32_t *__restrict__ part)
+{
+    __shared__ uint32_t lds[4];
+    int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < len) s += a[base + k];
+    uint32_t total;
+    block_exclusive_scan(s, &total, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// Scan phase 2: exclusive scan of the chunk sums in one block.
+__global__ void __launch_bounds__(kScanThreads)
+scan_partials_kernel(uint32_t *__restrict__ part, int64_t nparts)
+{
+    __shared__ uint32_t lds[4];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nparts; base += kScanThreads) {
+        int64_t i = base + threadIdx.x;
+        uint32_t v = i < nparts ? part[i] : 0u;
+        uint32_t total;
+        uint32_t ex = block_exclusive_scan(v, &total, lds);
+        if (i < nparts) part[i] = carry + ex;
+        carry += total;
+    }
+}
+
+// Scan phase 3: exclusive scan inside each chunk plus the chunk offset.
+__global__ void __launch_bounds__(kScanThreads)
+scan_down_kernel(uint32_t *__restrict__ a, int64_t len,
+                 const uint32_t *__restrict__ part)
+{
+    __shared__ uint32_t lds[4];
+    int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < len) ? a[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, &total, lds) + part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < len) a[base + k] = run;
+        run += v[k];
+    }
+}
+
+// Stable scatter of one radix pass. Elements of a tile are ranked in index
+// order: sub-tile by sub-tile, wave by wave, lane by lane. Lanes holding the
+// same digit are matched with one ballot per digit bit.
+__global__ void __launch_bounds__(kSortThreads)
+radix_scatter_kernel(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin,
+                     int64_t n, int shift, const uint32_t *__restrict__ hist,
+                     int64_t ntiles, uint32_t *__restrict__ kout,
+                     int32_t *__restrict__ vout)
+{
+    constexpr int kWaves = kSortThreads / 64;
+    __shared__ uint32_t base_of[kRadixBins];
+    __shared__ uint32_t run[kRadixBins];
+    __shared__ uint32_t wcnt[kWaves][kRadixBins];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    base_of[tid] = hist[(int64_t)tid * ntiles + blockIdx.x];
+    run[tid] = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = tile0 + it * kSortThreads + tid;
+        const bool valid = i < n;
+        const uint32_t k = valid ? kin[i] : 0u;
+        const int32_t v = valid ? vin[i] : 0;
+        const uint32_t d = (k >> shift) & (kRadixBins - 1);
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t ones = __ballot(bit);
+            same &= bit ? ones : ~ones;
+        }
+        const uint32_t rank = __popcll(same & lt_mask);
+        if (valid && rank == 0) wcnt[wave][d] = __popcll(same);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = run[d];
+            for (int w = 0; w < wave; ++w) off += wcnt[w][d];
+            const uint32_t pos = base_of[d] + off + rank;
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            tot += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        run[tid] += tot;
+        __syncthreads();
+    }
+}
+
+// Gather every particle array into scratch in sorted order.
+__global__ void __launch_bounds__(256)
+permute_gather_kernel(int64_t n, int64_t stride, const int32_t *__restrict__ perm,
+                      PermFields f, double *__restrict__ tmp,
+                      int32_t *__restrict__ tmp_id)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = perm[i];
+    for (int k = 0; k < f.nf; ++k) tmp[k * stride + i] = f.f[k][j];
+    tmp_id[i] = f.id[j];
+}
+
+// Copy the sorted arrays back into the caller's storage; refresh the FP32
+// copies of h and m.
+__global__ void __launch_bounds__(256)
+permute_store_kernel(int64_t n, int64_t stride, PermFields f,
+                     const double *__restrict__ tmp, const int32_t *__restrict__ tmp_id,
+                     int h_field, int m_field, float *__restrict__ hf,
+                     float *__restrict__ mf)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < f.nf; ++k) f.f[k][i] = tmp[k * stride + i];
+    f.id[i] = tmp_id[i];
+    hf[i] = (float)tmp[h_field * stride + i];
+    mf[i] = (float)tmp[m_field * stride + i];
+}
+
+// Cell table by binary search of each cell's key in the sorted keys: every
+// entry is rewritten on every build, empty cells get start == end.
+__global__ void __launch_bounds__(256)
+cell_table_kernel(int64_t ncell, Grid g, const uint32_t *__restrict__ keys, int64_t n,
+                  int32_t *__restrict__ cstart, int32_t *__restrict__ cend)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const uint32_t cx = (uint32_t)(c % g.nc[0]);
+    const uint32_t cy = (uint32_t)((c / g.nc[0]) % g.nc[1]);
+    const uint32_t cz = (uint32_t)(c / ((int64_t)g.nc[0] * g.nc[1]));
+    const uint32_t key = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {   // first index with keys[i] >= key
+        int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    const int64_t s = lo;
+    hi = n;
+    while (lo < hi) {   // first index with keys[i] > key
+        int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] <= key) lo = mid + 1; else hi = mid;
+    }
+    cstart[c] = (int32_t)s;
+    cend[c] = (int32_t)lo;
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t exclusive_scan(sph_ctx ctx, uint32_t *a, int64_t len)
+{
+    const int64_t nparts = (len + kScanChunk - 1) / kScanChunk;
+    scan_reduce_kernel<<<(unsigned)nparts, kScanThreads, 0, ctx->stream>>>(a, len, ctx->scan_part);
+    scan_partials_kernel<<<1, kScanThreads, 0, ctx->stream>>>(ctx->scan_part, nparts);
+    scan_down_kernel<<<(unsigned)nparts, kScanThreads, 0, ctx->stream>>>(a, len, ctx->scan_part);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g,
+                              double h_max)
+{
+    const int64_t n = p.n;
+    hipStream_t s = ctx->stream;
+    const int64_t ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+    keys_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, p.x, p.y, p.z, p.h, g, h_max,
+                                                   ctx->keys[0], ctx->vals[0],
+                                                   ctx->status_dev);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int key_bits = 3 * g.bits;
+    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    int cur = 0;
+    for (int shift = 0; shift < key_bits; shift += kRadixBits) {
+        radix_hist_kernel<<<(unsigned)ntiles, kSortThreads, 0, s>>>(
+            ctx->keys[cur], n, shift, ctx->hist, ntiles);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = exclusive_scan(ctx, ctx->hist, ntiles * kRadixBins)) != hipSuccess) return e;
+        radix_scatter_kernel<<<(unsigned)ntiles, kSortThreads, 0, s>>>(
+            ctx->keys[cur], ctx->vals[cur], n, shift, ctx->hist, ntiles,
+            ctx->keys[cur ^ 1], ctx->vals[cur ^ 1]);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        cur ^= 1;
+    }
+    ctx->sorted_keys = ctx->keys[cur];
+
+    PermFields f{};
+    double *fields[kPermFields] = {p.x, p.y, p.z, p.vx, p.vy, p.vz, p.u, p.h, p.m,
+                                   p.rho_ref, p.p_bg, p.gx, p.gy, p.gz};
+    int h_field = -1, m_field = -1;
+    for (int k = 0; k < kPermFields; ++k) {
+        if (!fields[k]) continue;
+        if (k == 7) h_field = f.nf;
+        if (k == 8) m_field = f.nf;
+        f.f[f.nf++] = fields[k];
+    }
+    f.id = p.id;
+    permute_gather_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, ctx->n_max, ctx->vals[cur], f,
+                                                             ctx->perm_tmp, ctx->perm_tmp_id);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    permute_store_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, ctx->n_max, f, ctx->perm_tmp,
+                                                            ctx->perm_tmp_id, h_field, m_field,
+                                                            ctx->hf, ctx->mf);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    cell_table_kernel<<<blocks_for(ncell, 256), 256, 0, s>>>(ncell, g, ctx->sorted_keys, n,
+                                                             ctx->cell_start, ctx->cell_end);
+    return hipGetLastError();
+}
+
+}  // namespace sph

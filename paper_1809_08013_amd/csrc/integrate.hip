@@ -1,0 +1,214 @@
+// Algorithm 1, steps 5 and 6 on the GPU: kick-drift-kick update with a
+// global dt held in device memory, and the global dt itself as a two-level
+// min reduction (wavefront shuffles, then LDS, then one block over the block
+// partials). The same pass sums the conserved totals in FP64 in a fixed tree
+// order, so they are identical from run to run.
+#include "sph_internal.h"
+
+namespace sph {
+namespace {
+
+__global__ void __launch_bounds__(256)
+integrate_kernel(int64_t n, int stage, const double *__restrict__ dt_dev, Grid g,
+                 double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
+                 double *__restrict__ vx, double *__restrict__ vy, double *__restrict__ vz,
+                 double *__restrict__ u, const double *__restrict__ ax,
+                 const double *__restrict__ ay, const double *__restrict__ az,
+                 const double *__restrict__ dudt, const double *__restrict__ gx,
+                 const double *__restrict__ gy, const double *__restrict__ gz,
+                 uint32_t *status)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double dt = dt_dev[0];
+    const double half = 0.5 * dt;
+    double tx = ax[i], ty = ay[i], tz = az[i];
+    if (gx) {
+        tx += gx[i];
+        ty += gy[i];
+        tz += gz[i];
+    }
+    const double nvx = vx[i] + half * tx;
+    const double nvy = vy[i] + half * ty;
+    const double nvz = vz[i] + half * tz;
+    const double nu = u[i] + half * dudt[i];
+    vx[i] = nvx;
+    vy[i] = nvy;
+    vz[i] = nvz;
+    u[i] = nu;
+    if (stage == SPH_KICK_DRIFT) {
+        double p[3] = {x[i] + dt * nvx, y[i] + dt * nvy, z[i] + dt * nvz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (!g.periodic[a]) continue;
+            if (p[a] >= g.hi[a]) p[a] -= g.len[a];
+            else if (p[a] < g.lo[a]) p[a] += g.len[a];
+        }
+        x[i] = p[0];
+        y[i] = p[1];
+        z[i] = p[2];
+    } else {
+        const double s = x[i] + y[i] + z[i] + nvx + nvy + nvz + nu;
+        if (!isfinite(s)) atomicOr(status, ST_NONFINITE);
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
+    return v;
+}
+
+// Block-level combine of kRedFields values (field 0 by min, the others by
+// sum), fixed order; result valid in thread 0.
+__device__ __forceinline__ void block_combine(double v[kRedFields],
+                                              double (*lds)[kRedThreads / 64])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v[0] = wave_min(v[0]);
+#pragma unroll
+    for (int k = 1; k < kRedFields; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kRedFields; ++k) lds[k][wave] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r0 = lds[0][0];
+        for (int w = 1; w < kRedThreads / 64; ++w) r0 = fmin(r0, lds[0][w]);
+        v[0] = r0;
+#pragma unroll
+        for (int k = 1; k < kRedFields; ++k) {
+            double s = lds[k][0];
+            for (int w = 1; w < kRedThreads / 64; ++w) s += lds[k][w];
+            v[k] = s;
+        }
+    }
+}
+
+// Per-block partials: dt candidate min and the 8 conserved totals.
+__global__ void __launch_bounds__(kRedThreads)
+timestep_partial_kernel(int64_t n, const double *__restrict__ h, const double *__restrict__ c,
+                        const double *__restrict__ mumax, const double *__restrict__ ax,
+                        const double *__restrict__ ay, const double *__restrict__ az,
+                        const double *__restrict__ gx, const double *__restrict__ gy,
+                        const double *__restrict__ gz, const double *__restrict__ x,
+                        const double *__restrict__ y, const double *__restrict__ z,
+                        const double *__restrict__ vx, const double *__restrict__ vy,
+                        const double *__restrict__ vz, const double *__restrict__ u,
+                        const double *__restrict__ m, double alpha, double beta,
+                        double c_cfl, double c_force, double *__restrict__ part)
+{
+    __shared__ double lds[kRedFields][kRedThreads / 64];
+    double v[kRedFields];
+    v[0] = INFINITY;
+#pragma unroll
+    for (int k = 1; k < kRedFields; ++k) v[k] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double hi = h[i], ci = c[i];
+        double d = c_cfl * hi / (ci + 1.2 * (alpha * ci + beta * mumax[i]));
+        double tx = ax[i], ty = ay[i], tz = az[i];
+        if (gx) {
+            tx += gx[i];
+            ty += gy[i];
+            tz += gz[i];
+        }
+        const double amag = sqrt(tx * tx + ty * ty + tz * tz);
+        if (amag > 0.0) d = fmin(d, c_force * sqrt(hi / amag));
+        v[0] = fmin(v[0], d);
+        const double mi = m[i], px = x[i], py = y[i], pz = z[i];
+        const double qx = vx[i], qy = vy[i], qz = vz[i];
+        v[1] += mi;
+        v[2] += mi * qx;
+        v[3] += mi * qy;
+        v[4] += mi * qz;
+        v[5] += mi * (py * qz - pz * qy);
+        v[6] += mi * (pz * qx - px * qz);
+        v[7] += mi * (px * qy - py * qx);
+        v[8] += mi * (0.5 * (qx * qx + qy * qy + qz * qz) + u[i]);
+    }
+    block_combine(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kRedFields; ++k) part[(int64_t)k * kRedMaxBlocks + blockIdx.x] = v[k];
+    }
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+timestep_final_kernel(int nblocks, const double *__restrict__ part,
+                      double *__restrict__ dt_dev, double *__restrict__ diag)
+{
+    __shared__ double lds[kRedFields][kRedThreads / 64];
+    double v[kRedFields];
+    v[0] = INFINITY;
+#pragma unroll
+    for (int k = 1; k < kRedFields; ++k) v[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kRedThreads) {
+        v[0] = fmin(v[0], part[b]);
+#pragma unroll
+        for (int k = 1; k < kRedFields; ++k) v[k] += part[(int64_t)k * kRedMaxBlocks + b];
+    }
+    block_combine(v, lds);
+    if (threadIdx.x == 0) {
+        dt_dev[0] = v[0];
+        if (diag) {
+#pragma unroll
+            for (int k = 1; k < kRedFields; ++k) diag[k - 1] = v[k];
+        }
+    }
+}
+
+__global__ void copy_kernel(int64_t n, double *__restrict__ dst, const double *__restrict__ src)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_integrate(sph_ctx ctx, const sph_particles &p, const Grid &g, int stage,
+                            const double *dt_dev, const sph_accel &a)
+{
+    integrate_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
+        p.n, stage, dt_dev, g, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.u, a.ax, a.ay, a.az, a.dudt,
+        p.gx, p.gy, p.gz, ctx->status_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_timestep(sph_ctx ctx, const sph_particles &p, const sph_params &prm,
+                           const sph_fields &f, const sph_accel &a, double *dt_dev,
+                           double *diag_dev)
+{
+    int64_t nb = (p.n + kRedThreads - 1) / kRedThreads;
+    if (nb > kRedMaxBlocks) nb = kRedMaxBlocks;
+    if (nb > 0) {
+        timestep_partial_kernel<<<(unsigned)nb, kRedThreads, 0, ctx->stream>>>(
+            p.n, p.h, f.c, a.mumax, a.ax, a.ay, a.az, p.gx, p.gy, p.gz, p.x, p.y, p.z, p.vx,
+            p.vy, p.vz, p.u, p.m, prm.alpha, prm.beta, prm.c_cfl, prm.c_force, ctx->red_part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    timestep_final_kernel<<<1, kRedThreads, 0, ctx->stream>>>((int)nb, ctx->red_part, dt_dev,
+                                                              diag_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(sph_ctx ctx, double *dst, const double *src, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    copy_kernel<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, dst, src);
+    return hipGetLastError();
+}
+
+}  // namespace sph

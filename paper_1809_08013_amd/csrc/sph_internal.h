@@ -1,0 +1,116 @@
+// Internal declarations of libsph shared by its translation units.
+// Not installed, not part of the C ABI (include/sph.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "sph.h"
+
+namespace sph {
+
+// Status bits raised on the device; sph_ctx_check maps them to sph_status.
+enum : uint32_t {
+    ST_CAPACITY = 1u << 0,
+    ST_DOMAIN = 1u << 1,
+    ST_NONFINITE = 1u << 2,
+};
+
+constexpr int kMaxAxisCells = 1024;   // 10 Morton bits per axis
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;   // keys per tile
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kScanThreads * kScanItems;  // elements per block
+constexpr int kRedThreads = 256;
+constexpr int kRedMaxBlocks = 2048;
+constexpr int kRedFields = 9;   // dt candidate min + 8 totals
+constexpr int kPermFields = 14; // x y z vx vy vz u h m rho_ref p_bg gx gy gz
+
+// Uniform cell grid of one build (host values, passed to kernels by value).
+struct Grid {
+    int nc[3];          // cells per axis
+    int bits;           // Morton bits per axis
+    int periodic[3];
+    double lo[3];
+    double hi[3];
+    double len[3];      // hi - lo
+    double half[3];     // 0.5 * len (minimum image threshold)
+    double inv_s[3];    // cells per unit length
+};
+
+struct PermFields {
+    double *f[kPermFields];
+    int nf;
+    int32_t *id;
+};
+
+}  // namespace sph
+
+struct sph_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t n_max = 0;
+    int32_t max_nb = 0;
+
+    // radix sort
+    uint32_t *keys[2] = {nullptr, nullptr};
+    int32_t *vals[2] = {nullptr, nullptr};
+    uint32_t *hist = nullptr;        // kRadixBins * tiles_max
+    uint32_t *scan_part = nullptr;   // block partials of the scan
+    int64_t tiles_max = 0;
+    int64_t scan_len_max = 0;
+    const uint32_t *sorted_keys = nullptr;  // key of each particle after the build
+
+    // cell table, indexed by linear cell id (cz * ny + cy) * nx + cx
+    int32_t *cell_start = nullptr;
+    int32_t *cell_end = nullptr;
+    int64_t cell_cap = 0;
+    sph::Grid grid{};
+    int64_t n_built = -1;
+
+    // permutation scratch
+    double *perm_tmp = nullptr;      // kPermFields * n_max
+    int32_t *perm_tmp_id = nullptr;  // n_max
+
+    // FP32 copies for the FP32-pair form (h, m written by the build; rho,
+    // pr2, c by the EOS)
+    float *hf = nullptr, *mf = nullptr, *rhof = nullptr, *pr2f = nullptr,
+          *cf = nullptr;
+
+    // reductions
+    double *red_part = nullptr;      // kRedFields * kRedMaxBlocks
+
+    uint32_t *status_dev = nullptr;
+    std::string last_error;
+    int64_t scratch_bytes = 0;
+};
+
+namespace sph {
+
+// Launchers (defined in the .hip files); each returns hipSuccess or the
+// launch error.
+hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g,
+                              double h_max);
+hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p,
+                                 const sph_nbrs &nb);
+hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
+                          int precision, double *rho);
+hipError_t launch_eos(sph_ctx ctx, const sph_particles &p, const sph_params &prm,
+                      const sph_fields &f);
+hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
+                           const sph_params &prm, const sph_fields &f,
+                           const sph_accel &a);
+hipError_t launch_integrate(sph_ctx ctx, const sph_particles &p, const Grid &g,
+                            int stage, const double *dt_dev, const sph_accel &a);
+hipError_t launch_timestep(sph_ctx ctx, const sph_particles &p,
+                           const sph_params &prm, const sph_fields &f,
+                           const sph_accel &a, double *dt_dev, double *diag_dev);
+hipError_t launch_copy(sph_ctx ctx, double *dst, const double *src, int64_t n);
+
+}  // namespace sph

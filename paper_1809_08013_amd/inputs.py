@@ -114,7 +114,7 @@ def square_patch_pressure(x: np.ndarray, y: np.ndarray, L: float = 1.0,
     coef = -32.0 * omega * omega / (mm * nn * np.pi ** 2 *
                                     ((mm * np.pi / L) ** 2 + (nn * np.pi / L) ** 2))
     # P_i = sum_mn sx[i,m] coef[m,n] sy[i,n]
-    return rho * np.einsum("im,mn,in->i", sx, coef, sy)
+    return rho * np.sum((sx @ coef) * sy, axis=1)
 
 
 def square_patch(n_side: int = 20, nz: int | None = None, L: float = 1.0,
