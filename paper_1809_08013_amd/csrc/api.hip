@@ -159,8 +159,8 @@ void free_ctx(sph_ctx ctx)
 {
     void *ptrs[] = {ctx->keys[0], ctx->keys[1], ctx->vals[0], ctx->vals[1], ctx->hist,
                     ctx->scan_part, ctx->cell_start, ctx->cell_end, ctx->perm_tmp,
-                    ctx->perm_tmp_id, ctx->hf, ctx->mf, ctx->rhof, ctx->pr2f, ctx->cf,
-                    ctx->red_part, ctx->status_dev};
+                    ctx->perm_tmp_id, ctx->red_part, ctx->status_dev, ctx->nb_ranges, ctx->nb_nranges, ctx->nb_mask, ctx->hflag_dev,
+                    ctx->srec, ctx->drec, ctx->prec};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete ctx;
@@ -224,7 +224,7 @@ sph_status sph_ctx_create(sph_ctx *out, int64_t n_max, int32_t max_nb, sph_strea
     ctx->max_nb = max_nb;
     ctx->tiles_max = (n_max + kSortTile - 1) / kSortTile;
     ctx->scan_len_max = ctx->tiles_max * kRadixBins;
-    ctx->cell_cap = std::max<int64_t>(2 * n_max + 64, 32768);
+    ctx->cell_cap = std::max<int64_t>(n_max / 8 + 64, 65536);
     sph_status s = SPH_OK;
 #define ALLOC(ptr, count)                                   \
     if (s == SPH_OK) s = dev_alloc(ctx, &(ptr), (count));
@@ -236,15 +236,17 @@ sph_status sph_ctx_create(sph_ctx *out, int64_t n_max, int32_t max_nb, sph_strea
     ALLOC(ctx->scan_part, (ctx->scan_len_max + kScanChunk - 1) / kScanChunk + 1);
     ALLOC(ctx->cell_start, ctx->cell_cap);
     ALLOC(ctx->cell_end, ctx->cell_cap);
+    ALLOC(ctx->nb_ranges, (int64_t)kStencil * ctx->cell_cap);
+    ALLOC(ctx->nb_nranges, ctx->cell_cap);
+    ALLOC(ctx->nb_mask, (int64_t)kSearchMaskWords * ((n_max + 63) / 64) * 64);
+    ALLOC(ctx->srec, n_max);
+    ALLOC(ctx->drec, n_max);
+    ALLOC(ctx->prec, n_max);
     ALLOC(ctx->perm_tmp, (int64_t)kPermFields * n_max);
     ALLOC(ctx->perm_tmp_id, n_max);
-    ALLOC(ctx->hf, n_max);
-    ALLOC(ctx->mf, n_max);
-    ALLOC(ctx->rhof, n_max);
-    ALLOC(ctx->pr2f, n_max);
-    ALLOC(ctx->cf, n_max);
     ALLOC(ctx->red_part, (int64_t)kRedFields * kRedMaxBlocks);
     ALLOC(ctx->status_dev, 1);
+    ALLOC(ctx->hflag_dev, 1);
 #undef ALLOC
     if (s != SPH_OK) {
         g_no_ctx_error = ctx->last_error;

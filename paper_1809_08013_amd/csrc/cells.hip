@@ -37,15 +37,41 @@ __device__ __forceinline__ int cell_of(double v, double lo, double inv_s, int nc
     return (int)f;
 }
 
-// Morton key of each particle's cell; vals = current index. Flags h > h_max.
+// Distinct cells around c along one axis (periodic axes wrap; with fewer
+// than three cells on a periodic axis every cell is listed once).
+__device__ __forceinline__ int axis_cells(int c, int nc, int periodic, int out[3])
+{
+    int k = 0;
+    if (periodic) {
+        if (nc >= 3) {
+            out[0] = c == 0 ? nc - 1 : c - 1;
+            out[1] = c;
+            out[2] = c == nc - 1 ? 0 : c + 1;
+            k = 3;
+        } else {
+            for (int v = 0; v < nc; ++v) out[k++] = v;
+        }
+    } else {
+        if (c > 0) out[k++] = c - 1;
+        out[k++] = c;
+        if (c < nc - 1) out[k++] = c + 1;
+    }
+    return k;
+}
+
+__global__ void clear_word_kernel(uint32_t *w) { *w = 0u; }
+
+// Morton key of each particle's cell; vals = current index. Flags h > h_max,
+// and sets *hflag when some h differs from h[0].
 __global__ void __launch_bounds__(256)
 keys_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
             const double *__restrict__ z, const double *__restrict__ h, Grid g,
             double h_max, uint32_t *__restrict__ keys, int32_t *__restrict__ vals,
-            uint32_t *status)
+            uint32_t *hflag, uint32_t *status)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (h[i] != h[0]) atomicOr(hflag, 1u);
     uint32_t cx = (uint32_t)cell_of(x[i], g.lo[0], g.inv_s[0], g.nc[0]);
     uint32_t cy = (uint32_t)cell_of(y[i], g.lo[1], g.inv_s[1], g.nc[1]);
     uint32_t cz = (uint32_t)cell_of(z[i], g.lo[2], g.inv_s[2], g.nc[2]);
@@ -221,20 +247,64 @@ permute_gather_kernel(int64_t n, int64_t stride, const int32_t *__restrict__ per
     tmp_id[i] = f.id[j];
 }
 
-// Copy the sorted arrays back into the caller's storage; refresh the FP32
-// copies of h and m.
+// Copy the sorted arrays back into the caller's storage and write the
+// search records (position and (2h)^2). Fields 0..2 are x, y, z (always
+// present).
 __global__ void __launch_bounds__(256)
 permute_store_kernel(int64_t n, int64_t stride, PermFields f,
                      const double *__restrict__ tmp, const int32_t *__restrict__ tmp_id,
-                     int h_field, int m_field, float *__restrict__ hf,
-                     float *__restrict__ mf)
+                     int h_field, SearchRec *__restrict__ srec)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     for (int k = 0; k < f.nf; ++k) f.f[k][i] = tmp[k * stride + i];
     f.id[i] = tmp_id[i];
-    hf[i] = (float)tmp[h_field * stride + i];
-    mf[i] = (float)tmp[m_field * stride + i];
+    const double x = tmp[i], y = tmp[stride + i], z = tmp[2 * stride + i];
+    const double s = 2.0 * tmp[h_field * stride + i];
+    srec[i] = SearchRec{x, y, z, s * s};
+}
+
+// For every cell, the particle ranges of its neighbouring cells (the cell
+// itself included), non-empty ones only, sorted by start and merged where
+// one ends where the next begins. Walking them in this order visits a
+// particle's candidates in ascending index order, so neighbour lists come
+// out sorted.
+__global__ void __launch_bounds__(256)
+nb_ranges_kernel(int64_t ncell, Grid g, const int32_t *__restrict__ cstart,
+                 const int32_t *__restrict__ cend, int2 *__restrict__ ranges,
+                 int32_t *__restrict__ nranges)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int cx = (int)(c % g.nc[0]);
+    const int cy = (int)((c / g.nc[0]) % g.nc[1]);
+    const int cz = (int)(c / ((int64_t)g.nc[0] * g.nc[1]));
+    int xs[3], ys[3], zs[3];
+    const int kx = axis_cells(cx, g.nc[0], g.periodic[0], xs);
+    const int ky = axis_cells(cy, g.nc[1], g.periodic[1], ys);
+    const int kz = axis_cells(cz, g.nc[2], g.periodic[2], zs);
+    int2 *out = ranges + c * kStencil;
+    int k = 0;
+    for (int a = 0; a < kz; ++a)
+        for (int b = 0; b < ky; ++b)
+            for (int d = 0; d < kx; ++d) {
+                const int64_t cell = ((int64_t)zs[a] * g.nc[1] + ys[b]) * g.nc[0] + xs[d];
+                const int2 r = make_int2(cstart[cell], cend[cell]);
+                if (r.x >= r.y) continue;
+                int t = k++;  // insertion by start
+                while (t > 0 && out[t - 1].x > r.x) {
+                    out[t] = out[t - 1];
+                    --t;
+                }
+                out[t] = r;
+            }
+    int m = 0;
+    for (int t = 0; t < k; ++t) {
+        const int2 r = out[t];
+        if (m > 0 && out[m - 1].y == r.x) out[m - 1].y = r.y;
+        else out[m++] = r;
+    }
+    nranges[c] = m;
 }
 
 // Cell table by binary search of each cell's key in the sorted keys: every
@@ -283,8 +353,9 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
     const int64_t n = p.n;
     hipStream_t s = ctx->stream;
     const int64_t ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+    clear_word_kernel<<<1, 1, 0, s>>>(ctx->hflag_dev);
     keys_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, p.x, p.y, p.z, p.h, g, h_max,
-                                                   ctx->keys[0], ctx->vals[0],
+                                                   ctx->keys[0], ctx->vals[0], ctx->hflag_dev,
                                                    ctx->status_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -307,11 +378,10 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
     PermFields f{};
     double *fields[kPermFields] = {p.x, p.y, p.z, p.vx, p.vy, p.vz, p.u, p.h, p.m,
                                    p.rho_ref, p.p_bg, p.gx, p.gy, p.gz};
-    int h_field = -1, m_field = -1;
+    int h_field = -1;
     for (int k = 0; k < kPermFields; ++k) {
         if (!fields[k]) continue;
         if (k == 7) h_field = f.nf;
-        if (k == 8) m_field = f.nf;
         f.f[f.nf++] = fields[k];
     }
     f.id = p.id;
@@ -319,11 +389,15 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
                                                              ctx->perm_tmp, ctx->perm_tmp_id);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     permute_store_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, ctx->n_max, f, ctx->perm_tmp,
-                                                            ctx->perm_tmp_id, h_field, m_field,
-                                                            ctx->hf, ctx->mf);
+                                                            ctx->perm_tmp_id, h_field,
+                                                            ctx->srec);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cell_table_kernel<<<blocks_for(ncell, 256), 256, 0, s>>>(ncell, g, ctx->sorted_keys, n,
                                                              ctx->cell_start, ctx->cell_end);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    nb_ranges_kernel<<<blocks_for(ncell, 256), 256, 0, s>>>(ncell, g, ctx->cell_start,
+                                                            ctx->cell_end, ctx->nb_ranges,
+                                                            ctx->nb_nranges);
     return hipGetLastError();
 }
 

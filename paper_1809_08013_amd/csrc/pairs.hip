@@ -1,61 +1,45 @@
-// Algorithm 1, steps 2 and 3 on the GPU: neighbour search over the cell
-// grid, summation density, EOS, momentum and energy with artificial
-// viscosity. Gather form throughout: each particle owns its outputs and sums
-// its own pairs, so there are no atomics on floating-point values and every
-// result is the same from run to run.
+// Algorithm 1, step 3 on the GPU: summation density, EOS, and momentum and
+// energy with artificial viscosity.
 //
-// The pair arithmetic comes in two forms (template parameter Real):
-//   double: everything FP64;
-//   float:  separations and velocity differences formed in FP64 and rounded
-//           to FP32, FP32 copies of h, m, rho, P/rho^2 and c, FP32 sums,
-//           outputs widened to FP64.
+// Gather form throughout: each particle owns its outputs and sums its own
+// pairs in the order of its neighbour list, so there are no atomics on
+// floating-point values and every result is the same from run to run.
+//
+// One lane per particle; at step k every lane needs the record of its own
+// k-th neighbour. Loaded lane by lane, each load instruction touches 64
+// different cache lines, and the L1 resolves about one line per clock. So
+// the records are packed (one aligned record per particle) and fetched
+// cooperatively: a group of lanes loads the 16-byte chunks of ONE record, so
+// an instruction touches one line per group, and the chunks are then passed
+// to their owner lanes through a small per-wave LDS buffer whose padded
+// stride keeps both the writes and the reads free of bank conflicts.
+//
+// The density and momentum pair arithmetic comes in two forms:
+//   FP64:      everything FP64;
+//   FP32-pair: separations and velocity differences formed in FP64 and
+//              rounded to FP32, FP32 copies of h, m, rho, P/rho^2 and c, FP32
+//              sums, outputs widened to FP64.
+#include <type_traits>
+
 #include "sph_internal.h"
 
 namespace sph {
 namespace {
 
 constexpr double kInvPi = 0.318309886183790671537767526745;
-
-__device__ __forceinline__ uint32_t compact3(uint32_t v)
-{
-    v &= 0x09249249u;
-    v = (v | (v >> 2)) & 0x030C30C3u;
-    v = (v | (v >> 4)) & 0x0300F00Fu;
-    v = (v | (v >> 8)) & 0x030000FFu;
-    v = (v | (v >> 16)) & 0x000003FFu;
-    return v;
-}
-
-// Distinct cells around c along one axis (periodic axes wrap; with fewer
-// than three cells on a periodic axis every cell is listed once).
-__device__ __forceinline__ int axis_cells(int c, int nc, int periodic, int out[3])
-{
-    int k = 0;
-    if (periodic) {
-        if (nc >= 3) {
-            out[0] = c == 0 ? nc - 1 : c - 1;
-            out[1] = c;
-            out[2] = c == nc - 1 ? 0 : c + 1;
-            k = 3;
-        } else {
-            for (int v = 0; v < nc; ++v) out[k++] = v;
-        }
-    } else {
-        if (c > 0) out[k++] = c - 1;
-        out[k++] = c;
-        if (c < nc - 1) out[k++] = c + 1;
-    }
-    return k;
-}
+constexpr int kThreads = 256;
 
 __device__ __forceinline__ double min_image(double d, int periodic, double len, double half)
 {
     if (periodic) {
-        if (d > half) d -= len;
-        else if (d < -half) d += len;
+        d = d > half ? d - len : d;
+        d = d < -half ? d + len : d;
     }
     return d;
 }
+
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // M4 spline shape w(q) and slope w'(q).
 template <typename R>
@@ -79,109 +63,92 @@ __device__ __forceinline__ R m4_dw(R q)
 }
 
 // ---------------------------------------------------------------------------
-// Neighbour search: one lane per particle, the 27 cells around its cell,
-// exact FP64 relation, ELL column-major output.
-__global__ void __launch_bounds__(256)
-find_neighbors_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                      const double *__restrict__ z, const double *__restrict__ h,
-                      const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
-                      const int32_t *__restrict__ cend, Grid g, int max_nb,
-                      int32_t *__restrict__ count, int32_t *__restrict__ idx,
-                      uint32_t *status)
+// Order the compiler's LDS accesses around the cooperative loads (LDS
+// operations of one wave complete in order).
+__device__ __forceinline__ void wave_lds_fence()
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double xi = x[i], yi = y[i], zi = z[i], hi = h[i];
-    const uint32_t key = keys[i];
-    int cxs[3], cys[3], czs[3];
-    const int kx = axis_cells((int)compact3(key), g.nc[0], g.periodic[0], cxs);
-    const int ky = axis_cells((int)compact3(key >> 1), g.nc[1], g.periodic[1], cys);
-    const int kz = axis_cells((int)compact3(key >> 2), g.nc[2], g.periodic[2], czs);
-    int cnt = 0;
-    for (int a = 0; a < kz; ++a) {
-        for (int b = 0; b < ky; ++b) {
-            const int64_t row = ((int64_t)czs[a] * g.nc[1] + cys[b]) * g.nc[0];
-            for (int c = 0; c < kx; ++c) {
-                const int64_t cell = row + cxs[c];
-                const int32_t s = cstart[cell], e = cend[cell];
-                for (int32_t j = s; j < e; ++j) {
-                    if (j == i) continue;
-                    const double dx = min_image(xi - x[j], g.periodic[0], g.len[0], g.half[0]);
-                    const double dy = min_image(yi - y[j], g.periodic[1], g.len[1], g.half[1]);
-                    const double dz = min_image(zi - z[j], g.periodic[2], g.len[2], g.half[2]);
-                    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                    const double sr = 2.0 * fmax(hi, h[j]);
-                    if (r2 < sr * sr) {
-                        if (cnt < max_nb) idx[(int64_t)cnt * n + i] = j;
-                        ++cnt;
-                    }
-                }
-            }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double4 lds_load4(const char *p)
+{
+    return *reinterpret_cast<const double4 *>(p);
+}
+
+// ---------------------------------------------------------------------------
+// Summation density: rho_i = (m_i + sum_j m_j w(r_ij / h_i)) / (pi h_i^3).
+// Records: DensRec {x, y, z, m}, 32 B; two lanes fetch one record.
+constexpr int kDensStride = 48;  // LDS bytes per record: 32 + 16 padding
+
+template <bool F32>
+__global__ void __launch_bounds__(kThreads)
+density_kernel(int64_t n, const DensRec *__restrict__ drec, const double *__restrict__ h,
+               const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
+               Grid g, double *__restrict__ rho)
+{
+    using R = typename std::conditional<F32, float, double>::type;
+    __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kDensStride];
+    const int lane = threadIdx.x & 63;
+    char *buf = lds[threadIdx.x >> 6];
+    const int64_t i = xcd_block() * kThreads + threadIdx.x;
+    const bool active = i < n;
+    const int64_t ii = active ? i : 0;
+    const DensRec me = drec[ii];
+    const R inv_h = R(1) / (R)h[ii];
+    R sum = (R)me.m;  // w(0) = 1
+    const int cnt = active ? min(count[ii], max_nb) : 0;
+    int maxc = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, 64));
+    const int s = lane & 1;
+    const char *src_base = reinterpret_cast<const char *>(drec) + 16 * s;
+    char *dst_own = buf + lane * kDensStride;
+    char *dst_a = buf + (lane & ~1) * kDensStride + 16 * s;
+    int jn = cnt > 0 ? idx[ii] : (int)ii;
+    for (int k = 0; k < maxc; ++k) {
+        const int jk = jn;
+        jn = k + 1 < cnt ? idx[(int64_t)(k + 1) * n + ii] : (int)ii;
+        const int jp = __shfl_xor(jk, 1, 64);
+        // lanes 2g and 2g+1 fetch chunk s of the records of lanes 2g and 2g+1
+        const int j0 = s == 0 ? jk : jp, j1 = s == 0 ? jp : jk;
+        const double2 c0 = *reinterpret_cast<const double2 *>(src_base + (int64_t)j0 * sizeof(DensRec));
+        const double2 c1 = *reinterpret_cast<const double2 *>(src_base + (int64_t)j1 * sizeof(DensRec));
+        wave_lds_fence();
+        *reinterpret_cast<double2 *>(dst_a) = c0;
+        *reinterpret_cast<double2 *>(dst_a + kDensStride) = c1;
+        wave_lds_fence();
+        const double2 lo = *reinterpret_cast<const double2 *>(dst_own);
+        const double2 hi = *reinterpret_cast<const double2 *>(dst_own + 16);
+        if (k < cnt) {
+            const R dx = (R)min_image(me.x - lo.x, g.periodic[0], g.len[0], g.half[0]);
+            const R dy = (R)min_image(me.y - lo.y, g.periodic[1], g.len[1], g.half[1]);
+            const R dz = (R)min_image(me.z - hi.x, g.periodic[2], g.len[2], g.half[2]);
+            const R r = sqrt(fma_r(dz, dz, fma_r(dy, dy, dx * dx)));
+            sum = fma_r((R)hi.y, m4_w(r * inv_h), sum);
         }
     }
-    count[i] = cnt;
-    if (cnt > max_nb) atomicOr(status, ST_CAPACITY);
+    if (active) rho[i] = (double)(sum * ((R)kInvPi * inv_h * inv_h * inv_h));
+}
+
+// Density records {x, y, z, m}.
+__global__ void __launch_bounds__(256)
+pack_dens_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                 const double *__restrict__ z, const double *__restrict__ m,
+                 DensRec *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = DensRec{x[i], y[i], z[i], m[i]};
 }
 
 // ---------------------------------------------------------------------------
-// Summation density, FP64 pair arithmetic.
-__global__ void __launch_bounds__(256)
-density_fp64_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                    const double *__restrict__ z, const double *__restrict__ h,
-                    const double *__restrict__ m, const int32_t *__restrict__ count,
-                    const int32_t *__restrict__ idx, int max_nb, Grid g,
-                    double *__restrict__ rho)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double xi = x[i], yi = y[i], zi = z[i], hi = h[i];
-    const double inv_h = 1.0 / hi;
-    double sum = m[i];  // w(0) = 1
-    const int cnt = min(count[i], max_nb);
-    for (int k = 0; k < cnt; ++k) {
-        const int32_t j = idx[(int64_t)k * n + i];
-        const double dx = min_image(xi - x[j], g.periodic[0], g.len[0], g.half[0]);
-        const double dy = min_image(yi - y[j], g.periodic[1], g.len[1], g.half[1]);
-        const double dz = min_image(zi - z[j], g.periodic[2], g.len[2], g.half[2]);
-        const double r = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
-        sum += m[j] * m4_w(r * inv_h);
-    }
-    rho[i] = sum * (kInvPi * inv_h * inv_h * inv_h);
-}
-
-// Summation density, FP32 pair arithmetic.
-__global__ void __launch_bounds__(256)
-density_fp32_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                    const double *__restrict__ z, const float *__restrict__ hf,
-                    const float *__restrict__ mf, const int32_t *__restrict__ count,
-                    const int32_t *__restrict__ idx, int max_nb, Grid g,
-                    double *__restrict__ rho)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double xi = x[i], yi = y[i], zi = z[i];
-    const float inv_h = 1.0f / hf[i];
-    float sum = mf[i];
-    const int cnt = min(count[i], max_nb);
-    for (int k = 0; k < cnt; ++k) {
-        const int32_t j = idx[(int64_t)k * n + i];
-        const float dx = (float)min_image(xi - x[j], g.periodic[0], g.len[0], g.half[0]);
-        const float dy = (float)min_image(yi - y[j], g.periodic[1], g.len[1], g.half[1]);
-        const float dz = (float)min_image(zi - z[j], g.periodic[2], g.len[2], g.half[2]);
-        const float r = sqrtf(__builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx)));
-        sum = __builtin_fmaf(mf[j], m4_w(r * inv_h), sum);
-    }
-    rho[i] = (double)(sum * ((float)kInvPi * inv_h * inv_h * inv_h));
-}
-
-// ---------------------------------------------------------------------------
-// EOS; also the FP32 copies of rho, P/rho^2 and c.
+// EOS.
 __global__ void __launch_bounds__(256)
 eos_kernel(int64_t n, int eos, double rho0, double c0, double gamma_tait,
            double gamma_gas, const double *__restrict__ rho, const double *__restrict__ u,
            const double *__restrict__ rho_ref, const double *__restrict__ p_bg,
-           double *__restrict__ p, double *__restrict__ c, double *__restrict__ pr2,
-           float *__restrict__ rhof, float *__restrict__ pr2f, float *__restrict__ cf)
+           double *__restrict__ p, double *__restrict__ c, double *__restrict__ pr2)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -198,151 +165,163 @@ eos_kernel(int64_t n, int eos, double rho0, double c0, double gamma_tait,
         P = (gamma_gas - 1.0) * r * u[i];
         C = sqrt(gamma_gas * (gamma_gas - 1.0) * u[i]);
     }
-    const double q = P / (r * r);
     p[i] = P;
     c[i] = C;
-    pr2[i] = q;
-    rhof[i] = (float)r;
-    pr2f[i] = (float)q;
-    cf[i] = (float)C;
+    pr2[i] = P / (r * r);
 }
 
 // ---------------------------------------------------------------------------
-// Momentum and energy with Monaghan artificial viscosity, FP64.
-__global__ void __launch_bounds__(256)
-momentum_fp64_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                     const double *__restrict__ z, const double *__restrict__ vx,
-                     const double *__restrict__ vy, const double *__restrict__ vz,
-                     const double *__restrict__ h, const double *__restrict__ m,
-                     const double *__restrict__ rho, const double *__restrict__ cs,
-                     const double *__restrict__ pr2, const int32_t *__restrict__ count,
-                     const int32_t *__restrict__ idx, int max_nb, Grid g, double alpha,
-                     double beta, double eta2, double *__restrict__ ax,
-                     double *__restrict__ ay, double *__restrict__ az,
-                     double *__restrict__ dudt, double *__restrict__ mumax)
+// Momentum and energy with Monaghan artificial viscosity.
+// Records: PairRec (96 B used of 128); a group of 8 lanes fetches one record
+// (lanes 0..5 of the group one 16-byte chunk each), 8 records per load.
+constexpr int kMomStride = 112;  // LDS bytes per record: 96 + 16 padding
+
+struct MomParams {
+    double alpha, beta, eta2;
+};
+
+template <bool F32>
+__global__ void __launch_bounds__(kThreads)
+momentum_kernel(int64_t n, const PairRec *__restrict__ rec, const int32_t *__restrict__ count,
+                const int32_t *__restrict__ idx, int max_nb, Grid g, MomParams prm,
+                double *__restrict__ ax, double *__restrict__ ay, double *__restrict__ az,
+                double *__restrict__ dudt, double *__restrict__ mumax)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double xi = x[i], yi = y[i], zi = z[i];
-    const double vxi = vx[i], vyi = vy[i], vzi = vz[i];
-    const double hi = h[i], rhoi = rho[i], ci = cs[i], pi = pr2[i];
-    const double inv_hi = 1.0 / hi;
-    const double fi = kInvPi * (inv_hi * inv_hi) * (inv_hi * inv_hi);
-    double sx = 0.0, sy = 0.0, sz = 0.0, su = 0.0, mum = 0.0;
-    const int cnt = min(count[i], max_nb);
-    for (int k = 0; k < cnt; ++k) {
-        const int32_t j = idx[(int64_t)k * n + i];
-        const double dx = min_image(xi - x[j], g.periodic[0], g.len[0], g.half[0]);
-        const double dy = min_image(yi - y[j], g.periodic[1], g.len[1], g.half[1]);
-        const double dz = min_image(zi - z[j], g.periodic[2], g.len[2], g.half[2]);
-        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        const double r = sqrt(r2);
-        const double hj = h[j];
-        const double inv_hj = 1.0 / hj;
-        const double fj = kInvPi * (inv_hj * inv_hj) * (inv_hj * inv_hj);
-        const double dwbar = 0.5 * (fi * m4_dw(r * inv_hi) + fj * m4_dw(r * inv_hj));
-        const double F = r > 0.0 ? dwbar / r : 0.0;
-        const double wx = vxi - vx[j], wy = vyi - vy[j], wz = vzi - vz[j];
-        const double vdotr = __builtin_fma(wz, dz, __builtin_fma(wy, dy, wx * dx));
-        const double hbar = 0.5 * (hi + hj);
-        double mu = 0.0;
-        if (vdotr < 0.0) mu = hbar * vdotr / __builtin_fma(eta2 * hbar, hbar, r2);
-        const double cbar = 0.5 * (ci + cs[j]);
-        const double rhobar = 0.5 * (rhoi + rho[j]);
-        const double Pi = mu * (beta * mu - alpha * cbar) / rhobar;
-        const double mG = m[j] * (pi + pr2[j] + Pi) * F;
-        sx = __builtin_fma(-mG, dx, sx);
-        sy = __builtin_fma(-mG, dy, sy);
-        sz = __builtin_fma(-mG, dz, sz);
-        su = __builtin_fma(mG, vdotr, su);
-        mum = fmax(mum, fabs(mu));
+    using R = typename std::conditional<F32, float, double>::type;
+    __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kMomStride];
+    const int lane = threadIdx.x & 63;
+    char *buf = lds[threadIdx.x >> 6];
+    const int64_t i = xcd_block() * kThreads + threadIdx.x;
+    const bool active = i < n;
+    const int64_t ii = active ? i : 0;
+    const PairRec *mp = rec + ii;
+    const double mex = mp->x, mey = mp->y, mez = mp->z;
+    const double mevx = mp->vx, mevy = mp->vy, mevz = mp->vz;
+    const R hi = (R)mp->h, inv_hi = (R)mp->inv_h, rhoi = (R)mp->rho, ci = (R)mp->c,
+            pi = (R)mp->pr2;
+    const R fi = (R)kInvPi * (inv_hi * inv_hi) * (inv_hi * inv_hi);
+    const R alpha = (R)prm.alpha, beta = (R)prm.beta, eta2 = (R)prm.eta2;
+    R sx = 0, sy = 0, sz = 0, su = 0, mum = 0;
+    const int cnt = active ? min(count[ii], max_nb) : 0;
+    int maxc = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, 64));
+    const int grp = lane & ~7, s = lane & 7;
+    const bool loader = s < 6;
+    const char *src_base = reinterpret_cast<const char *>(rec) + 16 * (loader ? s : 0);
+    const char *own = buf + lane * kMomStride;
+    char *dst = buf + grp * kMomStride + 16 * s;
+    // Software pipelined: the chunks of step k + 1 are loaded into registers
+    // (c0..c7) while step k is computed from LDS.
+#define SPH_FETCH(t, jk)                                                                   \
+    c##t = *reinterpret_cast<const double2 *>(                                             \
+        src_base + (int64_t)__shfl((jk), grp + (t), 64) * (int64_t)sizeof(PairRec))
+#define SPH_FETCH_ALL(jk)                                                                  \
+    SPH_FETCH(0, jk); SPH_FETCH(1, jk); SPH_FETCH(2, jk); SPH_FETCH(3, jk);                \
+    SPH_FETCH(4, jk); SPH_FETCH(5, jk); SPH_FETCH(6, jk); SPH_FETCH(7, jk)
+    double2 c0, c1, c2, c3, c4, c5, c6, c7;
+    int jn = cnt > 1 ? idx[n + ii] : (int)ii;
+    {
+        const int j0 = cnt > 0 ? idx[ii] : (int)ii;
+        SPH_FETCH_ALL(j0);
     }
-    ax[i] = sx;
-    ay[i] = sy;
-    az[i] = sz;
-    dudt[i] = 0.5 * su;
-    mumax[i] = mum;
+    for (int k = 0; k < maxc; ++k) {
+        wave_lds_fence();
+        if (loader) {
+            *reinterpret_cast<double2 *>(dst + 0 * kMomStride) = c0;
+            *reinterpret_cast<double2 *>(dst + 1 * kMomStride) = c1;
+            *reinterpret_cast<double2 *>(dst + 2 * kMomStride) = c2;
+            *reinterpret_cast<double2 *>(dst + 3 * kMomStride) = c3;
+            *reinterpret_cast<double2 *>(dst + 4 * kMomStride) = c4;
+            *reinterpret_cast<double2 *>(dst + 5 * kMomStride) = c5;
+            *reinterpret_cast<double2 *>(dst + 6 * kMomStride) = c6;
+            *reinterpret_cast<double2 *>(dst + 7 * kMomStride) = c7;
+        }
+        wave_lds_fence();
+        if (k + 1 < maxc) {
+            SPH_FETCH_ALL(jn);
+            jn = k + 2 < cnt ? idx[(int64_t)(k + 2) * n + ii] : (int)ii;
+        }
+#undef SPH_FETCH_ALL
+#undef SPH_FETCH
+        const double2 q0 = *reinterpret_cast<const double2 *>(own);       // x y
+        const double2 q1 = *reinterpret_cast<const double2 *>(own + 16);  // z vx
+        const double2 q2 = *reinterpret_cast<const double2 *>(own + 32);  // vy vz
+        const double2 q3 = *reinterpret_cast<const double2 *>(own + 48);  // h inv_h
+        const double2 q4 = *reinterpret_cast<const double2 *>(own + 64);  // m rho
+        const double2 q5 = *reinterpret_cast<const double2 *>(own + 80);  // c pr2
+        if (k < cnt) {
+            const R dx = (R)min_image(mex - q0.x, g.periodic[0], g.len[0], g.half[0]);
+            const R dy = (R)min_image(mey - q0.y, g.periodic[1], g.len[1], g.half[1]);
+            const R dz = (R)min_image(mez - q1.x, g.periodic[2], g.len[2], g.half[2]);
+            const R r2 = fma_r(dz, dz, fma_r(dy, dy, dx * dx));
+            const R r = sqrt(r2);
+            const R hj = (R)q3.x, inv_hj = (R)q3.y;
+            const R fj = (R)kInvPi * (inv_hj * inv_hj) * (inv_hj * inv_hj);
+            const R dwbar = R(0.5) * (fi * m4_dw(r * inv_hi) + fj * m4_dw(r * inv_hj));
+            const R F = r > R(0) ? dwbar / r : R(0);
+            const R wx = (R)(mevx - q1.y), wy = (R)(mevy - q2.x), wz = (R)(mevz - q2.y);
+            const R vdotr = fma_r(wz, dz, fma_r(wy, dy, wx * dx));
+            const R hbar = R(0.5) * (hi + hj);
+            R mu = R(0);
+            if (vdotr < R(0)) mu = hbar * vdotr / fma_r(eta2 * hbar, hbar, r2);
+            const R cbar = R(0.5) * (ci + (R)q5.x);
+            const R rhobar = R(0.5) * (rhoi + (R)q4.y);
+            const R Pi = mu * (beta * mu - alpha * cbar) / rhobar;
+            const R mG = (R)q4.x * (pi + (R)q5.y + Pi) * F;
+            sx = fma_r(-mG, dx, sx);
+            sy = fma_r(-mG, dy, sy);
+            sz = fma_r(-mG, dz, sz);
+            su = fma_r(mG, vdotr, su);
+            mum = fmax(mum, fabs(mu));
+        }
+    }
+    if (active) {
+        ax[i] = (double)sx;
+        ay[i] = (double)sy;
+        az[i] = (double)sz;
+        dudt[i] = 0.5 * (double)su;
+        mumax[i] = (double)mum;
+    }
 }
 
-// Momentum and energy, FP32 pair arithmetic.
+// Pair records {x, y, z, vx, vy, vz, h, 1/h, m, rho, c, P/rho^2}.
 __global__ void __launch_bounds__(256)
-momentum_fp32_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                     const double *__restrict__ z, const double *__restrict__ vx,
-                     const double *__restrict__ vy, const double *__restrict__ vz,
-                     const float *__restrict__ h, const float *__restrict__ m,
-                     const float *__restrict__ rho, const float *__restrict__ cs,
-                     const float *__restrict__ pr2, const int32_t *__restrict__ count,
-                     const int32_t *__restrict__ idx, int max_nb, Grid g, float alpha,
-                     float beta, float eta2, double *__restrict__ ax,
-                     double *__restrict__ ay, double *__restrict__ az,
-                     double *__restrict__ dudt, double *__restrict__ mumax)
+pack_pair_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                 const double *__restrict__ z, const double *__restrict__ vx,
+                 const double *__restrict__ vy, const double *__restrict__ vz,
+                 const double *__restrict__ h, const double *__restrict__ m,
+                 const double *__restrict__ rho, const double *__restrict__ c,
+                 const double *__restrict__ pr2, PairRec *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double xi = x[i], yi = y[i], zi = z[i];
-    const double vxi = vx[i], vyi = vy[i], vzi = vz[i];
-    const float hi = h[i], rhoi = rho[i], ci = cs[i], pi = pr2[i];
-    const float inv_hi = 1.0f / hi;
-    const float fi = (float)kInvPi * (inv_hi * inv_hi) * (inv_hi * inv_hi);
-    float sx = 0.f, sy = 0.f, sz = 0.f, su = 0.f, mum = 0.f;
-    const int cnt = min(count[i], max_nb);
-    for (int k = 0; k < cnt; ++k) {
-        const int32_t j = idx[(int64_t)k * n + i];
-        const float dx = (float)min_image(xi - x[j], g.periodic[0], g.len[0], g.half[0]);
-        const float dy = (float)min_image(yi - y[j], g.periodic[1], g.len[1], g.half[1]);
-        const float dz = (float)min_image(zi - z[j], g.periodic[2], g.len[2], g.half[2]);
-        const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-        const float r = sqrtf(r2);
-        const float hj = h[j];
-        const float inv_hj = 1.0f / hj;
-        const float fj = (float)kInvPi * (inv_hj * inv_hj) * (inv_hj * inv_hj);
-        const float dwbar = 0.5f * (fi * m4_dw(r * inv_hi) + fj * m4_dw(r * inv_hj));
-        const float F = r > 0.f ? dwbar / r : 0.f;
-        const float wx = (float)(vxi - vx[j]), wy = (float)(vyi - vy[j]),
-                    wz = (float)(vzi - vz[j]);
-        const float vdotr = __builtin_fmaf(wz, dz, __builtin_fmaf(wy, dy, wx * dx));
-        const float hbar = 0.5f * (hi + hj);
-        float mu = 0.f;
-        if (vdotr < 0.f) mu = hbar * vdotr / __builtin_fmaf(eta2 * hbar, hbar, r2);
-        const float cbar = 0.5f * (ci + cs[j]);
-        const float rhobar = 0.5f * (rhoi + rho[j]);
-        const float Pi = mu * (beta * mu - alpha * cbar) / rhobar;
-        const float mG = m[j] * (pi + pr2[j] + Pi) * F;
-        sx = __builtin_fmaf(-mG, dx, sx);
-        sy = __builtin_fmaf(-mG, dy, sy);
-        sz = __builtin_fmaf(-mG, dz, sz);
-        su = __builtin_fmaf(mG, vdotr, su);
-        mum = fmaxf(mum, fabsf(mu));
-    }
-    ax[i] = (double)sx;
-    ay[i] = (double)sy;
-    az[i] = (double)sz;
-    dudt[i] = 0.5 * (double)su;
-    mumax[i] = (double)mum;
+    const double hi = h[i];
+    PairRec r;
+    r.x = x[i]; r.y = y[i]; r.z = z[i];
+    r.vx = vx[i]; r.vy = vy[i]; r.vz = vz[i];
+    r.h = hi; r.inv_h = 1.0 / hi; r.m = m[i];
+    r.rho = rho[i]; r.c = c[i]; r.pr2 = pr2[i];
+    r.pad[0] = r.pad[1] = r.pad[2] = r.pad[3] = 0.0;
+    out[i] = r;
 }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
-hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb)
-{
-    find_neighbors_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
-        p.n, p.x, p.y, p.z, p.h, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
-        nb.max_nb, nb.count, nb.idx, ctx->status_dev);
-    return hipGetLastError();
-}
-
 hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
                           int precision, double *rho)
 {
-    if (precision == SPH_FP32_PAIR) {
-        density_fp32_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
-            p.n, p.x, p.y, p.z, ctx->hf, ctx->mf, nb.count, nb.idx, nb.max_nb, ctx->grid, rho);
-    } else {
-        density_fp64_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
-            p.n, p.x, p.y, p.z, p.h, p.m, nb.count, nb.idx, nb.max_nb, ctx->grid, rho);
-    }
+    const unsigned nblk = blocks_for(p.n, kThreads);
+    pack_dens_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, p.x, p.y, p.z, p.m,
+                                                                    ctx->drec);
+    if (precision == SPH_FP32_PAIR)
+        density_kernel<true><<<nblk, kThreads, 0, ctx->stream>>>(
+            p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho);
+    else
+        density_kernel<false><<<nblk, kThreads, 0, ctx->stream>>>(
+            p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho);
     return hipGetLastError();
 }
 
@@ -351,24 +330,25 @@ hipError_t launch_eos(sph_ctx ctx, const sph_particles &p, const sph_params &prm
 {
     eos_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
         p.n, prm.eos, prm.rho0, prm.c0, prm.gamma_tait, prm.gamma_gas, f.rho, p.u, p.rho_ref,
-        p.p_bg, f.p, f.c, f.pr2, ctx->rhof, ctx->pr2f, ctx->cf);
+        p.p_bg, f.p, f.c, f.pr2);
     return hipGetLastError();
 }
 
 hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
                            const sph_params &prm, const sph_fields &f, const sph_accel &a)
 {
-    if (prm.precision == SPH_FP32_PAIR) {
-        momentum_fp32_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
-            p.n, p.x, p.y, p.z, p.vx, p.vy, p.vz, ctx->hf, ctx->mf, ctx->rhof, ctx->cf,
-            ctx->pr2f, nb.count, nb.idx, nb.max_nb, ctx->grid, (float)prm.alpha,
-            (float)prm.beta, (float)prm.eta2, a.ax, a.ay, a.az, a.dudt, a.mumax);
-    } else {
-        momentum_fp64_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
-            p.n, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2, nb.count,
-            nb.idx, nb.max_nb, ctx->grid, prm.alpha, prm.beta, prm.eta2, a.ax, a.ay, a.az,
+    const unsigned nblk = blocks_for(p.n, kThreads);
+    const MomParams mp{prm.alpha, prm.beta, prm.eta2};
+    pack_pair_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
+        p.n, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2, ctx->prec);
+    if (prm.precision == SPH_FP32_PAIR)
+        momentum_kernel<true><<<nblk, kThreads, 0, ctx->stream>>>(
+            p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp, a.ax, a.ay, a.az,
             a.dudt, a.mumax);
-    }
+    else
+        momentum_kernel<false><<<nblk, kThreads, 0, ctx->stream>>>(
+            p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp, a.ax, a.ay, a.az,
+            a.dudt, a.mumax);
     return hipGetLastError();
 }
 

@@ -1,0 +1,372 @@
+// Algorithm 1, step 2 on the GPU: the neighbour search.
+//
+// One wavefront per block of 64 consecutive particles (cell order). The
+// wave first builds, in LDS, the union of the 27-cell stencils of the cells
+// its particles live in: the non-empty cells, sorted by their first particle
+// and without duplicates, so walking them visits candidates in ascending
+// index order. It then streams that union wave-uniformly: each candidate's
+// record is one scalar load into SGPRs, every lane tests it against its own
+// particle with the exact FP64 relation, and the outcome goes into a per-lane
+// bit mask (one bit per union position, kept in a global scratch region so
+// that the wave's LDS footprint stays small and occupancy high; each 32-bit
+// word of 64 lanes is one 256-byte store). A second phase expands the
+// masks row by row, so that all lanes write row k of the ELL list together
+// (one contiguous 256-byte store per row) instead of scattering 4-byte
+// writes.
+//
+// A wave whose union does not fit (many distinct cells, or more candidates
+// than the mask holds) takes the per-lane path instead: each lane walks its
+// own cell's precomputed neighbour ranges and writes its entries directly.
+// Both paths produce the same set in the same (ascending) order.
+#include <climits>
+
+#include "sph_internal.h"
+
+namespace sph {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kMaxEntries = 128;        // 27 * distinct cells, before dedup
+constexpr int kMaxCandidates = kSearchMaskWords * 32;
+constexpr int kMaxWords = kSearchMaskWords;
+
+__device__ __forceinline__ uint32_t compact3(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030C30C3u;
+    v = (v | (v >> 4)) & 0x0300F00Fu;
+    v = (v | (v >> 8)) & 0x030000FFu;
+    v = (v | (v >> 16)) & 0x000003FFu;
+    return v;
+}
+
+// Minimum image as a select chain: identical results to
+// "if (d > half) d -= len; else if (d < -half) d += len;".
+__device__ __forceinline__ double min_image_sel(double d, double len, double half)
+{
+    d = d > half ? d - len : d;
+    return d < -half ? d + len : d;
+}
+
+__device__ __forceinline__ int wrap_or_clip(int c, int nc, int periodic, bool &ok)
+{
+    if (periodic) {
+        ok = true;
+        return c < 0 ? c + nc : (c >= nc ? c - nc : c);
+    }
+    ok = c >= 0 && c < nc;
+    return c;
+}
+
+// Mode of the relation test. Any: r2 < (2h_i)^2 or r2 < (2h_j)^2, i.e.
+// r2 < (2 max(h_i, h_j))^2. Uniform: every particle has the same h, so the
+// test is one compare against the lane's own (2h)^2.
+template <bool Wrap, bool UniformH>
+__device__ __forceinline__ bool related(const SearchRec &me, const SearchRec &o, const Grid &g)
+{
+    double dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
+    if (Wrap) {
+        if (g.periodic[0]) dx = min_image_sel(dx, g.len[0], g.half[0]);
+        if (g.periodic[1]) dy = min_image_sel(dy, g.len[1], g.half[1]);
+        if (g.periodic[2]) dz = min_image_sel(dz, g.len[2], g.half[2]);
+    }
+    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+    if (UniformH) return r2 < me.s2;
+    return (r2 < me.s2) | (r2 < o.s2);
+}
+
+// Stream the union (cells[0..nu)) and record, for each candidate u, whether
+// it is related to the lane's particle. Masks are 32-bit words bm[word][lane]
+// (word = u / 32) filled from the top: candidate u sits at bit 31 - u % 32.
+// Within a cell the next four records are loaded while the current four are
+// tested, so the scalar-load latency is overlapped with work.
+template <bool Wrap, bool UniformH>
+__device__ __forceinline__ void stream_union(const SearchRec &me, const SearchRec *__restrict__ srec,
+                                             const int2 *cells, int nu, const Grid &g,
+                                             uint32_t *__restrict__ bm, int lane, int &cnt,
+                                             uint64_t &occ)
+{
+    uint32_t acc = 0;
+    int u = 0;
+    auto flush = [&](int w, uint32_t word) {
+        bm[w * kWave + lane] = word;
+        cnt += __popc(word);
+        occ |= word ? (1ull << w) : 0ull;
+    };
+    auto step = [&](const SearchRec &o) {
+        acc = (acc << 1) | (related<Wrap, UniformH>(me, o, g) ? 1u : 0u);
+        ++u;
+        if ((u & 31) == 0) {
+            flush((u >> 5) - 1, acc);
+            acc = 0;
+        }
+    };
+    for (int c = 0; c < nu; ++c) {
+        const int s = __builtin_amdgcn_readfirstlane(cells[c].x);
+        const int e = __builtin_amdgcn_readfirstlane(cells[c].y);
+        int j = s;
+        if (e - j >= 4) {
+            SearchRec a0 = srec[j], a1 = srec[j + 1], a2 = srec[j + 2], a3 = srec[j + 3];
+            j += 4;
+            while (e - j >= 4) {
+                const SearchRec b0 = srec[j], b1 = srec[j + 1], b2 = srec[j + 2],
+                                b3 = srec[j + 3];
+                step(a0);
+                step(a1);
+                step(a2);
+                step(a3);
+                // keep the wait for b0..b3 (scalar loads complete out of order,
+                // so it is a full wait) after the work on a0..a3
+                __builtin_amdgcn_sched_barrier(0);
+                a0 = b0;
+                a1 = b1;
+                a2 = b2;
+                a3 = b3;
+                j += 4;
+            }
+            step(a0);
+            step(a1);
+            step(a2);
+            step(a3);
+        }
+        for (; j < e; ++j) step(srec[j]);
+    }
+    if (u & 31) flush(u >> 5, acc << (32 - (u & 31)));
+}
+
+__global__ void __launch_bounds__(kWave)
+find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
+                      const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
+                      const int32_t *__restrict__ cend, const int2 *__restrict__ ranges,
+                      const int32_t *__restrict__ nranges, Grid g, int max_nb,
+                      int32_t *__restrict__ count, int32_t *__restrict__ idx,
+                      uint32_t *__restrict__ mask_scratch, const uint32_t *__restrict__ hflag,
+                      uint32_t *status)
+{
+    __shared__ uint32_t dkeys[kWave];
+    __shared__ int2 ent[kMaxEntries];
+    __shared__ int2 cells[kMaxEntries];
+    __shared__ int u0[kMaxEntries + 1];
+
+    const int lane = threadIdx.x;
+    const int64_t tile = xcd_block();
+    const int64_t t0 = tile * kWave;
+    uint32_t *bm = mask_scratch + tile * (kMaxWords * kWave);
+    const int64_t i = t0 + lane;
+    const bool active = i < n;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+
+    const uint32_t key = active ? keys[i] : 0xFFFFFFFFu;
+    const SearchRec me = active ? srec[i] : SearchRec{0.0, 0.0, 0.0, 0.0};
+    const uint32_t prev = __shfl_up(key, 1, kWave);
+    const bool first = active && (lane == 0 || key != prev);
+    const uint64_t fm = __ballot(first);
+    const int ndist = __popcll(fm);
+    if (first) dkeys[__popcll(fm & lt)] = key;
+
+    // The minimum image can be skipped for the whole wave when, on every
+    // periodic axis, the union of the stencils spans less than half the box:
+    // then |d| < L/2 for every candidate and the image test is a no-op.
+    const int cx = (int)compact3(key), cy = (int)compact3(key >> 1), cz = (int)compact3(key >> 2);
+    bool wrap = false;
+    {
+        const int cc[3] = {cx, cy, cz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (!g.periodic[a]) continue;
+            int mn = active ? cc[a] : INT_MAX, mx = active ? cc[a] : INT_MIN;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                mn = min(mn, __shfl_xor(mn, o, kWave));
+                mx = max(mx, __shfl_xor(mx, o, kWave));
+            }
+            // candidates lie in cells [mn - 1, mx + 1]: |d| < (mx - mn + 3) cells
+            if (mn < 1 || mx > g.nc[a] - 2 || 2 * (mx - mn + 3) >= g.nc[a]) wrap = true;
+        }
+    }
+
+    const int nent = ndist * kStencil;
+    bool use_union = nent <= kMaxEntries;
+    int nu = 0, total = 0;
+    __syncthreads();
+    if (use_union) {
+        // stencil cells of every distinct cell; empty ones become sentinels
+        for (int e = lane; e < kMaxEntries; e += kWave) {
+            int2 v = make_int2(INT_MAX, INT_MAX);
+            if (e < nent) {
+                const uint32_t k = dkeys[e / kStencil];
+                const int s = e % kStencil;
+                bool okx, oky, okz;
+                const int x = wrap_or_clip((int)compact3(k) + s % 3 - 1, g.nc[0], g.periodic[0], okx);
+                const int y = wrap_or_clip((int)compact3(k >> 1) + (s / 3) % 3 - 1, g.nc[1],
+                                           g.periodic[1], oky);
+                const int z = wrap_or_clip((int)compact3(k >> 2) + s / 9 - 1, g.nc[2],
+                                           g.periodic[2], okz);
+                if (okx && oky && okz) {
+                    const int64_t cell = ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
+                    const int a = cstart[cell], b = cend[cell];
+                    if (a < b) v = make_int2(a, b);
+                }
+            }
+            ent[e] = v;
+        }
+        __syncthreads();
+        // bitonic sort of the 128 entries by start, one pair per lane per step
+        for (int k = 2; k <= kMaxEntries; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int lo_i = ((lane & ~(j - 1)) << 1) | (lane & (j - 1));
+                const int hi_i = lo_i | j;
+                const int2 a = ent[lo_i], b = ent[hi_i];
+                const bool up = (lo_i & k) == 0;
+                if ((a.x > b.x) == up) {
+                    ent[lo_i] = b;
+                    ent[hi_i] = a;
+                }
+                __syncthreads();
+            }
+        }
+        // drop sentinels and duplicates (a cell listed by several stencils)
+        int2 v0 = ent[lane], v1 = ent[lane + kWave];
+        const int p0 = lane == 0 ? INT_MIN : ent[lane - 1].x;
+        const int p1 = ent[lane + kWave - 1].x;
+        const bool k0 = v0.x != INT_MAX && v0.x != p0;
+        const bool k1 = v1.x != INT_MAX && v1.x != p1;
+        const uint64_t m0 = __ballot(k0), m1 = __ballot(k1);
+        const int n0 = __popcll(m0);
+        nu = n0 + __popcll(m1);
+        int pos0 = __popcll(m0 & lt), pos1 = n0 + __popcll(m1 & lt);
+        if (k0) cells[pos0] = v0;
+        if (k1) cells[pos1] = v1;
+        __syncthreads();
+        // u0[c]: exclusive prefix of the cell lengths; lane holds c = lane and
+        // c = lane + 64
+        const int l0 = lane < nu ? cells[lane].y - cells[lane].x : 0;
+        const int l1 = lane + kWave < nu ? cells[lane + kWave].y - cells[lane + kWave].x : 0;
+        int s0 = l0, s1 = l1;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int t0s = __shfl_up(s0, o, kWave), t1s = __shfl_up(s1, o, kWave);
+            if (lane >= o) {
+                s0 += t0s;
+                s1 += t1s;
+            }
+        }
+        const int tot0 = __shfl(s0, kWave - 1, kWave);
+        total = tot0 + __shfl(s1, kWave - 1, kWave);
+        if (lane < nu) u0[lane] = s0 - l0;
+        if (lane + kWave < nu) u0[lane + kWave] = tot0 + s1 - l1;
+        if (lane == 0) u0[nu] = total;
+        use_union = total <= kMaxCandidates;
+        __syncthreads();
+    }
+
+    if (use_union) {
+        const bool uniform_h = hflag[0] == 0;
+        int cnt = 0;
+        uint64_t occ = 0;  // bit w: mask word w has at least one bit for this lane
+        if (wrap) {
+            if (uniform_h) stream_union<true, true>(me, srec, cells, nu, g, bm, lane, cnt, occ);
+            else stream_union<true, false>(me, srec, cells, nu, g, bm, lane, cnt, occ);
+        } else {
+            if (uniform_h) stream_union<false, true>(me, srec, cells, nu, g, bm, lane, cnt, occ);
+            else stream_union<false, false>(me, srec, cells, nu, g, bm, lane, cnt, occ);
+        }
+        // the lane's own particle is in the union: drop its bit
+        if (active) {
+            int lo = 0, hi = nu - 1;
+            while (lo < hi) {  // last cell with start <= i
+                const int mid = (lo + hi + 1) >> 1;
+                if (cells[mid].x <= i) lo = mid; else hi = mid - 1;
+            }
+            const int u_self = u0[lo] + (int)(i - cells[lo].x);
+            const int ws = u_self >> 5;
+            const uint32_t bit = 0x80000000u >> (u_self & 31);
+            const uint32_t word = bm[ws * kWave + lane];
+            if (word & bit) {
+                bm[ws * kWave + lane] = word & ~bit;
+                --cnt;
+                if ((word & ~bit) == 0) occ &= ~(1ull << ws);
+            }
+        } else {
+            cnt = 0;
+        }
+        int maxc = cnt;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, kWave));
+        const int rows = min(maxc, max_nb);
+        // Expand row by row: row k of every lane is written by one store. Each
+        // lane walks its non-empty words (occ) with the next word already in
+        // flight, and keeps the current cell's bounds in registers.
+        auto pop_word = [&]() -> int {
+            if (occ == 0) return -1;
+            const int w = __builtin_ctzll(occ);
+            occ &= occ - 1;
+            return w;
+        };
+        int w_cur = pop_word();
+        uint32_t cur = w_cur >= 0 ? bm[w_cur * kWave + lane] : 0u;
+        int w_nxt = pop_word();
+        uint32_t nxt = w_nxt >= 0 ? bm[w_nxt * kWave + lane] : 0u;
+        int cp = 0;
+        int c_start = cells[0].x, c_u0 = 0, c_end_u = u0[1];
+        for (int k = 0; k < rows; ++k) {
+            if (k < cnt) {
+                if (cur == 0) {
+                    cur = nxt;
+                    w_cur = w_nxt;
+                    w_nxt = pop_word();
+                    nxt = w_nxt >= 0 ? bm[w_nxt * kWave + lane] : 0u;
+                }
+                const int t = __builtin_clz(cur);
+                const int uu = w_cur * 32 + t;
+                cur &= ~(0x80000000u >> t);
+                while (uu >= c_end_u) {
+                    ++cp;
+                    c_start = cells[cp].x;
+                    c_u0 = c_end_u;
+                    c_end_u = u0[cp + 1];
+                }
+                idx[(int64_t)k * n + i] = c_start + (uu - c_u0);
+            }
+        }
+        if (active) {
+            count[i] = cnt;
+            if (cnt > max_nb) atomicOr(status, ST_CAPACITY);
+        }
+        return;
+    }
+
+    // per-lane path: the lane's own cell's merged neighbour ranges
+    if (!active) return;
+    const int64_t cell = ((int64_t)cz * g.nc[1] + cy) * g.nc[0] + cx;
+    const int nr = nranges[cell];
+    const int2 *rr = ranges + cell * kStencil;
+    int cnt = 0;
+    const int32_t ii = (int32_t)i;
+    for (int t = 0; t < nr; ++t) {
+        const int2 r = rr[t];
+        for (int32_t j = r.x; j < r.y; ++j) {
+            const SearchRec o = srec[j];
+            if (related<true, false>(me, o, g) && j != ii) {
+                if (cnt < max_nb) idx[(int64_t)cnt * n + i] = j;
+                ++cnt;
+            }
+        }
+    }
+    count[i] = cnt;
+    if (cnt > max_nb) atomicOr(status, ST_CAPACITY);
+}
+
+}  // namespace
+
+hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb)
+{
+    const unsigned blocks = (unsigned)((p.n + kWave - 1) / kWave);
+    find_neighbors_kernel<<<blocks, kWave, 0, ctx->stream>>>(
+        p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->nb_ranges,
+        ctx->nb_nranges, ctx->grid, nb.max_nb, nb.count, nb.idx, ctx->nb_mask, ctx->hflag_dev,
+        ctx->status_dev);
+    return hipGetLastError();
+}
+
+}  // namespace sph

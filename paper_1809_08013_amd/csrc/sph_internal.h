@@ -50,6 +50,35 @@ struct PermFields {
     int32_t *id;
 };
 
+constexpr int kStencil = 27;
+constexpr int kSearchMaskWords = 64;  // per lane of a search wave: 2048 candidates
+
+// Neighbour-side records, one per particle in cell order, so that a
+// neighbour's data is one aligned block instead of one cache line per array.
+//   SearchRec: position and (2h)^2 (the relation test), 32 B;
+//   DensRec:   position and mass (density), 32 B;
+//   PairRec:   position, velocity, h, 1/h, m, rho, c, P/rho^2 (momentum and
+//              energy), 96 B padded to one 128-byte line.
+struct __attribute__((aligned(32))) SearchRec { double x, y, z, s2; };
+struct __attribute__((aligned(32))) DensRec { double x, y, z, m; };
+struct __attribute__((aligned(128))) PairRec {
+    double x, y, z, vx, vy, vz, h, inv_h, m, rho, c, pr2;
+    double pad[4];
+};
+static_assert(sizeof(PairRec) == 128, "PairRec is one cache line");
+
+// Block index remapped so that each XCD runs one contiguous range of blocks.
+// Blocks are dispatched to the 8 XCDs round-robin (block b to XCD b % 8);
+// giving XCD x the x-th contiguous slice keeps a Morton-contiguous region of
+// particles, and most of its neighbours, in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block()
+{
+    const uint32_t B = gridDim.x, b = blockIdx.x;
+    const uint32_t q = B / 8, r = B % 8, x = b % 8, pos = b / 8;
+    return x < r ? (int64_t)x * (q + 1) + pos
+                 : (int64_t)r * (q + 1) + (int64_t)(x - r) * q + pos;
+}
+
 }  // namespace sph
 
 struct sph_ctx_s {
@@ -71,6 +100,15 @@ struct sph_ctx_s {
     int32_t *cell_start = nullptr;
     int32_t *cell_end = nullptr;
     int64_t cell_cap = 0;
+    // per cell: the particle ranges of its (up to 27) neighbouring cells,
+    // non-empty, sorted by start and merged where contiguous
+    int2 *nb_ranges = nullptr;       // kStencil * cell_cap
+    uint32_t *nb_mask = nullptr;     // search bit masks: kSearchMaskWords words per particle slot
+    int32_t *nb_nranges = nullptr;   // cell_cap
+
+    sph::SearchRec *srec = nullptr;  // search records, cell order
+    sph::DensRec *drec = nullptr;    // density records (written by sph_density)
+    sph::PairRec *prec = nullptr;    // pair records (written by sph_momentum_energy)
     sph::Grid grid{};
     int64_t n_built = -1;
 
@@ -78,15 +116,11 @@ struct sph_ctx_s {
     double *perm_tmp = nullptr;      // kPermFields * n_max
     int32_t *perm_tmp_id = nullptr;  // n_max
 
-    // FP32 copies for the FP32-pair form (h, m written by the build; rho,
-    // pr2, c by the EOS)
-    float *hf = nullptr, *mf = nullptr, *rhof = nullptr, *pr2f = nullptr,
-          *cf = nullptr;
-
     // reductions
     double *red_part = nullptr;      // kRedFields * kRedMaxBlocks
 
     uint32_t *status_dev = nullptr;
+    uint32_t *hflag_dev = nullptr;   // 0 after a build iff every particle has the same h
     std::string last_error;
     int64_t scratch_bytes = 0;
 };
