@@ -66,16 +66,16 @@ def kernel_model(n: int, pairs: float, precision: int) -> dict:
     return out
 
 
-def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128) -> dict:
+def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=None) -> dict:
     import numpy as np
     import torch
 
     from paper_1809_08013_amd import sph as S
 
     ctx = S.Context(ic.n, max_nb)
-    st = S.SphState(ic, max_nb)
+    st = S.SphState(ic, max_nb, g=g)
     prm = S.make_params(ic.params, precision)
-    S.sph_init_forces(ctx, st, prm, set_rho_ref=True)
+    S.sph_init_forces(ctx, st, prm, set_rho_ref=ic.params.eos == S.SPH_EOS_TAIT)
     S.sph_ctx_check(ctx)
 
     calls = [
@@ -144,6 +144,33 @@ def roofline(n: int, r: dict, precision: int) -> dict:
                 ms_per_launch=round(r["per_call_ms"][dom], 4))
 
 
+def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
+    """Evrard-like sphere, hydro step only, FP64 and FP32-pair.
+
+    h is the analytic estimate for ~100 gather neighbours under the 1/r
+    profile; the fixed external acceleration is the continuum field of that
+    profile, g = -M(<r)/r^2 r_hat = -r_hat (G = M = R = 1), standing in for
+    the direct-sum self-gravity, which is outside the timed path.
+    """
+    import numpy as np
+
+    from paper_1809_08013_amd import inputs as I
+    from paper_1809_08013_amd import sph as S
+    ic = I.evrard(n, seed=0)
+    r = np.sqrt(ic.x ** 2 + ic.y ** 2 + ic.z ** 2)
+    g = tuple(-c / np.maximum(r, 1e-12) for c in (ic.x, ic.y, ic.z))
+    out = {"workload": f"Evrard-like sphere, {n:,} particles, rho ~ 1/r, ideal gas gamma=5/3, "
+                       "analytic h (~100 neighbours), fixed external g"}
+    for name, prec in (("fp64", S.SPH_FP64), ("fp32_pair", S.SPH_FP32_PAIR)):
+        res = run_gpu(ic, prec, steps, warmup, max_nb=512, g=g)
+        out[name] = {"value": res["pairs_per_step"] / (res["ms_per_step"] * 1e-3),
+                     "ms_per_step": res["ms_per_step"],
+                     "per_call_ms": {k: round(v, 4) for k, v in res["per_call_ms"].items()},
+                     "mean_neighbours": res["pairs_per_step"] / n,
+                     "max_neighbours": res["max_count"]}
+    return out
+
+
 def cpu_baseline(ic, steps: int) -> dict:
     import oracle as O
     run = O.OracleRun(ic).init()
@@ -168,6 +195,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--evrard", action="store_true",
+                    help="also time the 1,000,000-particle Evrard-like hydro step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -220,6 +249,8 @@ def main():
             "per_call_ms": {k: round(v, 4) for k, v in r32["per_call_ms"].items()},
             "roofline": roofline(n, r32, 1),
         }
+    if args.evrard:
+        line["evrard"] = run_evrard(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ic, args.cpu_steps)
     print(json.dumps(line), flush=True)

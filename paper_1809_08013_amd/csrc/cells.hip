@@ -37,28 +37,6 @@ __device__ __forceinline__ int cell_of(double v, double lo, double inv_s, int nc
     return (int)f;
 }
 
-// Distinct cells around c along one axis (periodic axes wrap; with fewer
-// than three cells on a periodic axis every cell is listed once).
-__device__ __forceinline__ int axis_cells(int c, int nc, int periodic, int out[3])
-{
-    int k = 0;
-    if (periodic) {
-        if (nc >= 3) {
-            out[0] = c == 0 ? nc - 1 : c - 1;
-            out[1] = c;
-            out[2] = c == nc - 1 ? 0 : c + 1;
-            k = 3;
-        } else {
-            for (int v = 0; v < nc; ++v) out[k++] = v;
-        }
-    } else {
-        if (c > 0) out[k++] = c - 1;
-        out[k++] = c;
-        if (c < nc - 1) out[k++] = c + 1;
-    }
-    return k;
-}
-
 __global__ void clear_word_kernel(uint32_t *w) { *w = 0u; }
 
 // Morton key of each particle's cell; vals = current index. Flags h > h_max,
@@ -264,49 +242,6 @@ permute_store_kernel(int64_t n, int64_t stride, PermFields f,
     srec[i] = SearchRec{x, y, z, s * s};
 }
 
-// For every cell, the particle ranges of its neighbouring cells (the cell
-// itself included), non-empty ones only, sorted by start and merged where
-// one ends where the next begins. Walking them in this order visits a
-// particle's candidates in ascending index order, so neighbour lists come
-// out sorted.
-__global__ void __launch_bounds__(256)
-nb_ranges_kernel(int64_t ncell, Grid g, const int32_t *__restrict__ cstart,
-                 const int32_t *__restrict__ cend, int2 *__restrict__ ranges,
-                 int32_t *__restrict__ nranges)
-{
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    const int cx = (int)(c % g.nc[0]);
-    const int cy = (int)((c / g.nc[0]) % g.nc[1]);
-    const int cz = (int)(c / ((int64_t)g.nc[0] * g.nc[1]));
-    int xs[3], ys[3], zs[3];
-    const int kx = axis_cells(cx, g.nc[0], g.periodic[0], xs);
-    const int ky = axis_cells(cy, g.nc[1], g.periodic[1], ys);
-    const int kz = axis_cells(cz, g.nc[2], g.periodic[2], zs);
-    int2 *out = ranges + c * kStencil;
-    int k = 0;
-    for (int a = 0; a < kz; ++a)
-        for (int b = 0; b < ky; ++b)
-            for (int d = 0; d < kx; ++d) {
-                const int64_t cell = ((int64_t)zs[a] * g.nc[1] + ys[b]) * g.nc[0] + xs[d];
-                const int2 r = make_int2(cstart[cell], cend[cell]);
-                if (r.x >= r.y) continue;
-                int t = k++;  // insertion by start
-                while (t > 0 && out[t - 1].x > r.x) {
-                    out[t] = out[t - 1];
-                    --t;
-                }
-                out[t] = r;
-            }
-    int m = 0;
-    for (int t = 0; t < k; ++t) {
-        const int2 r = out[t];
-        if (m > 0 && out[m - 1].y == r.x) out[m - 1].y = r.y;
-        else out[m++] = r;
-    }
-    nranges[c] = m;
-}
-
 // Cell table by binary search of each cell's key in the sorted keys: every
 // entry is rewritten on every build, empty cells get start == end.
 __global__ void __launch_bounds__(256)
@@ -394,10 +329,6 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cell_table_kernel<<<blocks_for(ncell, 256), 256, 0, s>>>(ncell, g, ctx->sorted_keys, n,
                                                              ctx->cell_start, ctx->cell_end);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    nb_ranges_kernel<<<blocks_for(ncell, 256), 256, 0, s>>>(ncell, g, ctx->cell_start,
-                                                            ctx->cell_end, ctx->nb_ranges,
-                                                            ctx->nb_nranges);
     return hipGetLastError();
 }
 

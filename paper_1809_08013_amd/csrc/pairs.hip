@@ -106,19 +106,26 @@ density_kernel(int64_t n, const DensRec *__restrict__ drec, const double *__rest
     const char *src_base = reinterpret_cast<const char *>(drec) + 16 * s;
     char *dst_own = buf + lane * kDensStride;
     char *dst_a = buf + (lane & ~1) * kDensStride + 16 * s;
-    int jn = cnt > 0 ? idx[ii] : (int)ii;
-    for (int k = 0; k < maxc; ++k) {
-        const int jk = jn;
-        jn = k + 1 < cnt ? idx[(int64_t)(k + 1) * n + ii] : (int)ii;
+    // Software pipelined: the chunks of step k + 1 are loaded while step k is
+    // computed. Lanes 2g and 2g+1 fetch chunk s of the records of both.
+    auto fetch = [&](int jk, double2 &a, double2 &b) {
         const int jp = __shfl_xor(jk, 1, 64);
-        // lanes 2g and 2g+1 fetch chunk s of the records of lanes 2g and 2g+1
         const int j0 = s == 0 ? jk : jp, j1 = s == 0 ? jp : jk;
-        const double2 c0 = *reinterpret_cast<const double2 *>(src_base + (int64_t)j0 * sizeof(DensRec));
-        const double2 c1 = *reinterpret_cast<const double2 *>(src_base + (int64_t)j1 * sizeof(DensRec));
+        a = *reinterpret_cast<const double2 *>(src_base + (int64_t)j0 * sizeof(DensRec));
+        b = *reinterpret_cast<const double2 *>(src_base + (int64_t)j1 * sizeof(DensRec));
+    };
+    double2 c0, c1;
+    int jn = cnt > 1 ? idx[n + ii] : (int)ii;
+    fetch(cnt > 0 ? idx[ii] : (int)ii, c0, c1);
+    for (int k = 0; k < maxc; ++k) {
         wave_lds_fence();
         *reinterpret_cast<double2 *>(dst_a) = c0;
         *reinterpret_cast<double2 *>(dst_a + kDensStride) = c1;
         wave_lds_fence();
+        if (k + 1 < maxc) {
+            fetch(jn, c0, c1);
+            jn = k + 2 < cnt ? idx[(int64_t)(k + 2) * n + ii] : (int)ii;
+        }
         const double2 lo = *reinterpret_cast<const double2 *>(dst_own);
         const double2 hi = *reinterpret_cast<const double2 *>(dst_own + 16);
         if (k < cnt) {

@@ -16,8 +16,9 @@
 //
 // A wave whose union does not fit (many distinct cells, or more candidates
 // than the mask holds) takes the per-lane path instead: each lane walks its
-// own cell's precomputed neighbour ranges and writes its entries directly.
-// Both paths produce the same set in the same (ascending) order.
+// own stencil and writes its entries directly. Both paths produce the same
+// set in the same (ascending) order, so the sums over a list do not depend on
+// the path or on where the wave boundaries fall.
 #include <climits>
 
 #include "sph_internal.h"
@@ -137,8 +138,7 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const SearchRe
 __global__ void __launch_bounds__(kWave)
 find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
                       const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
-                      const int32_t *__restrict__ cend, const int2 *__restrict__ ranges,
-                      const int32_t *__restrict__ nranges, Grid g, int max_nb,
+                      const int32_t *__restrict__ cend, Grid g, int max_nb,
                       int32_t *__restrict__ count, int32_t *__restrict__ idx,
                       uint32_t *__restrict__ mask_scratch, const uint32_t *__restrict__ hflag,
                       uint32_t *status)
@@ -336,22 +336,37 @@ find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
         return;
     }
 
-    // per-lane path: the lane's own cell's merged neighbour ranges
+    // Per-lane path: the lane visits its own stencil's non-empty cells in
+    // ascending order of their first particle (selecting the next one each
+    // time), so its list is ascending too.
     if (!active) return;
-    const int64_t cell = ((int64_t)cz * g.nc[1] + cy) * g.nc[0] + cx;
-    const int nr = nranges[cell];
-    const int2 *rr = ranges + cell * kStencil;
     int cnt = 0;
     const int32_t ii = (int32_t)i;
-    for (int t = 0; t < nr; ++t) {
-        const int2 r = rr[t];
-        for (int32_t j = r.x; j < r.y; ++j) {
+    int last = -1;
+    for (;;) {
+        int best_s = INT_MAX, best_e = 0;
+        for (int s = 0; s < kStencil; ++s) {
+            bool okx, oky, okz;
+            const int x = wrap_or_clip(cx + s % 3 - 1, g.nc[0], g.periodic[0], okx);
+            const int y = wrap_or_clip(cy + (s / 3) % 3 - 1, g.nc[1], g.periodic[1], oky);
+            const int z = wrap_or_clip(cz + s / 9 - 1, g.nc[2], g.periodic[2], okz);
+            if (!(okx && oky && okz)) continue;
+            const int64_t cell = ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
+            const int a = cstart[cell], b = cend[cell];
+            if (a < b && a > last && a < best_s) {
+                best_s = a;
+                best_e = b;
+            }
+        }
+        if (best_s == INT_MAX) break;
+        for (int32_t j = best_s; j < best_e; ++j) {
             const SearchRec o = srec[j];
             if (related<true, false>(me, o, g) && j != ii) {
                 if (cnt < max_nb) idx[(int64_t)cnt * n + i] = j;
                 ++cnt;
             }
         }
+        last = best_s;
     }
     count[i] = cnt;
     if (cnt > max_nb) atomicOr(status, ST_CAPACITY);
@@ -363,8 +378,7 @@ hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_
 {
     const unsigned blocks = (unsigned)((p.n + kWave - 1) / kWave);
     find_neighbors_kernel<<<blocks, kWave, 0, ctx->stream>>>(
-        p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->nb_ranges,
-        ctx->nb_nranges, ctx->grid, nb.max_nb, nb.count, nb.idx, ctx->nb_mask, ctx->hflag_dev,
+        p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid, nb.max_nb, nb.count, nb.idx, ctx->nb_mask, ctx->hflag_dev,
         ctx->status_dev);
     return hipGetLastError();
 }

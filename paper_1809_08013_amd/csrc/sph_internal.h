@@ -100,11 +100,7 @@ struct sph_ctx_s {
     int32_t *cell_start = nullptr;
     int32_t *cell_end = nullptr;
     int64_t cell_cap = 0;
-    // per cell: the particle ranges of its (up to 27) neighbouring cells,
-    // non-empty, sorted by start and merged where contiguous
-    int2 *nb_ranges = nullptr;       // kStencil * cell_cap
     uint32_t *nb_mask = nullptr;     // search bit masks: kSearchMaskWords words per particle slot
-    int32_t *nb_nranges = nullptr;   // cell_cap
 
     sph::SearchRec *srec = nullptr;  // search records, cell order
     sph::DensRec *drec = nullptr;    // density records (written by sph_density)
