@@ -35,6 +35,11 @@ CALLS = ("integrate_kd", "build_cells", "find_neighbors", "density", "eos",
          "momentum_energy", "integrate_k", "timestep")
 
 
+def log(msg: str) -> None:
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_model(n: int, pairs: float, precision: int) -> dict:
     """Algorithmic HBM bytes and flops per launch of each C-ABI call.
 
@@ -72,11 +77,13 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
 
     from paper_1809_08013_amd import sph as S
 
+    log(f"run n={ic.n} precision={precision} steps={steps} warmup={warmup}")
     ctx = S.Context(ic.n, max_nb)
     st = S.SphState(ic, max_nb, g=g)
     prm = S.make_params(ic.params, precision)
     S.sph_init_forces(ctx, st, prm, set_rho_ref=ic.params.eos == S.SPH_EOS_TAIT)
     S.sph_ctx_check(ctx)
+    diag0 = st.diag.tolist()
 
     calls = [
         lambda: S.sph_integrate(ctx, st, S.SPH_KICK_DRIFT),
@@ -118,7 +125,7 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
     pairs = float(st.t["count"][: ic.n].sum().item())
     diag = st.diag
     return dict(ms_per_step=(t1 - t0) * 1e3 / steps, per_call_ms=per_call,
-                pairs_per_step=pairs, dt=st.dt, diag=diag.tolist(),
+                pairs_per_step=pairs, dt=st.dt, diag=diag.tolist(), diag0=diag0,
                 max_count=int(st.t["count"][: ic.n].max().item()),
                 scratch_bytes=ctx.scratch_bytes)
 
@@ -156,6 +163,7 @@ def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
 
     from paper_1809_08013_amd import inputs as I
     from paper_1809_08013_amd import sph as S
+    log(f"generating Evrard sphere n={n}")
     ic = I.evrard(n, seed=0)
     r = np.sqrt(ic.x ** 2 + ic.y ** 2 + ic.z ** 2)
     g = tuple(-c / np.maximum(r, 1e-12) for c in (ic.x, ic.y, ic.z))
@@ -171,8 +179,144 @@ def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
     return out
 
 
+def drift(r: dict) -> dict:
+    """Relative change of total energy and of L_z (|L| for an open box) over
+    all steps taken (warm-up included), from the FP64 on-device totals."""
+    d0, d1 = r["diag0"], r["diag"]
+    de = abs(d1[7] - d0[7]) / max(abs(d0[7]), 1e-300)
+    dl = abs(d1[6] - d0[6]) / max(abs(d0[6]), 1e-300)
+    return {"energy": de, "angular_momentum_z": dl}
+
+
+def run_large(n_side: int, steps: int, warmup: int) -> dict:
+    """Large rotating square patch (n_side^3 particles), FP32-pair and FP64."""
+    from paper_1809_08013_amd import inputs as I
+    from paper_1809_08013_amd import sph as S
+    log(f"generating square patch {n_side}^3")
+    ic = I.square_patch(n_side, seed=0)
+    n = ic.n
+    out = {"workload": f"rotating square patch, {n_side}^3 = {n:,} particles, same physics "
+                       "as the 1M case", "steps": steps, "warmup": warmup}
+    for name, prec in (("fp32_pair", S.SPH_FP32_PAIR), ("fp64", S.SPH_FP64)):
+        res = run_gpu(ic, prec, steps, warmup)
+        out[name] = {"value": res["pairs_per_step"] / (res["ms_per_step"] * 1e-3),
+                     "ms_per_step": res["ms_per_step"],
+                     "per_call_ms": {k: round(v, 4) for k, v in res["per_call_ms"].items()},
+                     "roofline": roofline(n, res, prec),
+                     "drift": drift(res),
+                     "mean_neighbours": res["pairs_per_step"] / n,
+                     "scratch_bytes": res["scratch_bytes"]}
+    return out
+
+
+def serving_workload(runs: int, seed: int = 0):
+    """Ensemble requests: n log-uniform in [4096, 262144] rounded to a cube
+    n_side^3 (n_side in [16, 64]), omega ~ U[2, 8], 50 steps each; each run
+    is a seeded rotating square patch. ICs are made before the clock starts
+    (a client prepares them before it submits)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1809_08013_amd import inputs as I
+    rng = np.random.default_rng(seed)
+    n = np.exp(rng.uniform(np.log(4096), np.log(262144), runs))
+    sides = np.clip(np.rint(np.cbrt(n)), 16, 64).astype(int)
+    omegas = rng.uniform(2.0, 8.0, runs)
+    gaps = rng.exponential(1.0, runs)  # unit-rate Poisson gaps, scaled per rate
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        ics = list(ex.map(lambda k: I.square_patch(int(sides[k]), omega=float(omegas[k]),
+                                                    seed=1000 + k), range(runs)))
+    return ics, gaps
+
+
+def serve(ics, gaps, steps: int, budget: int, max_slots: int, rate: float | None) -> dict:
+    """Submit every run (all at once, or at Poisson arrival times of the
+    given rate from a client thread), wait for all; latency = done - submit."""
+    import threading
+
+    import numpy as np
+
+    from paper_1809_08013_amd import sph as S
+    ens = S.Ensemble(budget, max_slots=max_slots, max_n_per_run=max(ic.n for ic in ics))
+    tickets = [None] * len(ics)
+    try:
+        t0 = S.ens_clock()
+        if rate is None:
+            for k, ic in enumerate(ics):
+                tickets[k] = ens.submit(ic, steps)
+        else:
+            arrive = t0 + np.cumsum(gaps) / rate
+
+            def client():
+                for k, ic in enumerate(ics):
+                    d = arrive[k] - S.ens_clock()
+                    if d > 0:
+                        time.sleep(d)
+                    tickets[k] = ens.submit(ic, steps)
+            th = threading.Thread(target=client)
+            th.start()
+        res = []
+        for k, ic in enumerate(ics):
+            while tickets[k] is None:
+                time.sleep(0.0005)
+            r = ens.wait(tickets[k], ic.n, arrays=False)
+            if r["status"] != S.SPH_OK:
+                raise RuntimeError(f"run {k} ended with status {r['status']}")
+            res.append(r)
+        if rate is not None:
+            th.join()
+        st = ens.stats()
+    finally:
+        ens.close()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+    svc = np.array([r["t_done"] - r["t_admit"] for r in res])
+    t_first = min(r["t_submit"] for r in res)
+    span = max(r["t_done"] for r in res) - t_first
+    pst = float(sum(ic.n for ic in ics)) * steps
+    return {"runs_per_s": len(ics) / span, "particle_steps_per_s": pst / span,
+            "makespan_s": span, "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "p50_service_s": float(np.percentile(svc, 50)),
+            "p99_service_s": float(np.percentile(svc, 99)),
+            "peak_runs": st["peak_runs"], "peak_particles": st["peak_particles"],
+            "batched_steps": st["steps"], "capacity_particles": st["capacity_particles"],
+            "bytes_per_particle": st["bytes_per_particle"]}
+
+
+def run_serving(runs: int, steps: int = 50, budget_gib: float = 8.0) -> dict:
+    budget = int(budget_gib * (1 << 30))
+    log(f"serving: generating {runs} runs")
+    ics, gaps = serving_workload(runs)
+    tot = sum(ic.n for ic in ics)
+    out = {"workload": f"{runs} rotating square patch runs, n = n_side^3 log-uniform in "
+                       f"[4096, 262144] (n_side in [16, 64]), omega ~ U[2, 8], {steps} steps "
+                       f"each, HBM budget {budget_gib:g} GiB, FP64, Poisson arrivals",
+           "total_particles": tot, "steps_per_run": steps}
+    log("serving: saturated (all submitted at once)")
+    sat = serve(ics, gaps, steps, budget, 511, None)
+    out["saturated"] = sat
+    mu = sat["runs_per_s"]
+    out["poisson"] = []
+    for f in (0.5, 0.8):
+        log(f"serving: Poisson arrivals at {f} x saturated rate")
+        r = serve(ics, gaps, steps, budget, 511, f * mu)
+        r["load_fraction"] = f
+        r["arrival_rate_runs_per_s"] = f * mu
+        out["poisson"].append(r)
+    # the baseline engine holds one run: its budget (and so its launch grids)
+    # is sized for the largest run, not for the batch
+    one_budget = (16 << 20) + int(sat["bytes_per_particle"]) * max(ic.n for ic in ics) * 11 // 10
+    log("serving: one run at a time (same engine and kernels, one slot)")
+    one = serve(ics, gaps, steps, one_budget, 1, None)
+    one["budget_bytes"] = one_budget
+    out["one_at_a_time"] = one
+    out["throughput_speedup_vs_one_at_a_time"] = sat["runs_per_s"] / one["runs_per_s"]
+    return out
+
+
 def cpu_baseline(ic, steps: int) -> dict:
     import oracle as O
+    log(f"CPU oracle baseline, {steps} steps")
     run = O.OracleRun(ic).init()
     t0 = time.perf_counter()
     pairs = 0
@@ -197,6 +341,11 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--evrard", action="store_true",
                     help="also time the 1,000,000-particle Evrard-like hydro step")
+    ap.add_argument("--serve-runs", type=int, default=512,
+                    help="ensemble serving requests (0 skips the serving leg)")
+    ap.add_argument("--large", type=int, default=0, metavar="N_SIDE",
+                    help="also time a large square patch of N_SIDE^3 particles "
+                         "(400 gives 64,000,000), 20 steps after 2 warm-up steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -240,6 +389,7 @@ def main():
         },
         "per_call_ms": {k: round(v, 4) for k, v in r64["per_call_ms"].items()},
         "roofline": roofline(n, r64, 0),
+        "drift": drift(r64),
     }
     if r32 is not None:
         v32 = r32["pairs_per_step"] / (r32["ms_per_step"] * 1e-3)
@@ -249,8 +399,12 @@ def main():
             "per_call_ms": {k: round(v, 4) for k, v in r32["per_call_ms"].items()},
             "roofline": roofline(n, r32, 1),
         }
+    if args.serve_runs > 0:
+        line["serving"] = run_serving(args.serve_runs)
     if args.evrard:
         line["evrard"] = run_evrard(args.steps, args.warmup)
+    if args.large:
+        line["large"] = run_large(args.large, 20, 2)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ic, args.cpu_steps)
     print(json.dumps(line), flush=True)

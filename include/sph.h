@@ -233,6 +233,111 @@ sph_status sph_export_neighbors(sph_ctx ctx, const sph_particles *p,
                                 int32_t *ids_host, int64_t cap,
                                 int64_t *total);
 
+/* ------------------------------------------------------------------------
+ * Ensemble serving: many independent runs of the step above (for instance
+ * rotating patches of uneven sizes), advanced together.
+ *
+ * Not part of the paper, which runs one simulation at a time: this is a
+ * serving layer over the same step. Every resident run's state stays in
+ * device memory; all resident runs advance together through one captured
+ * HIP graph of fused launches per step (each launch covers every resident
+ * particle). A persistent host thread admits queued runs in arrival order as
+ * soon as a run slot is free and the run's particles and cells fit in the
+ * memory budget, and retires runs after their last step. Each run takes its
+ * own global dt (Sec. 3, Algorithm 1, step 5, per run) and its own
+ * conserved totals, and its results are bitwise those of the same run
+ * advanced alone (and of the single-run calls above at the same precision).
+ *
+ * A run: the t = 0 evaluation (cells, neighbours, density, optionally
+ * rho_ref := rho, EOS, momentum and energy, dt), then n_steps kick-drift-kick
+ * steps, exactly as sph_init_forces followed by n_steps calls of sph_step.
+ * No external acceleration. Cells: side >= 2 h_max, at most 32 per axis.
+ *
+ * Threads: submit, poll, wait and stats may be called from any thread.
+ * Times are seconds on the steady clock that sph_ens_clock reads.
+ * ------------------------------------------------------------------------ */
+typedef struct sph_ens_s *sph_ens;
+
+typedef struct {
+    int32_t device;            /* HIP device ordinal */
+    int32_t precision;         /* SPH_FP64 or SPH_FP32_PAIR, for every run */
+    int32_t max_nb;            /* neighbour-list capacity per particle, >= 1 */
+    int32_t max_slots;         /* runs resident at once, 1..511 */
+    int64_t hbm_budget_bytes;  /* device memory for the arena and its scratch */
+    int64_t max_n_per_run;     /* largest run accepted, >= 1 */
+} sph_ens_config;
+
+typedef struct {
+    int64_t n;                 /* particles, >= 1, <= max_n_per_run */
+    int32_t n_steps;           /* KDK steps after the t = 0 evaluation, >= 0 */
+    int32_t set_rho_ref;       /* Tait: rho_ref := rho at t = 0 */
+    sph_params params;         /* params.precision is ignored (engine's) */
+    sph_box box;
+    double h_max;              /* >= every h (h stays fixed); sets the cells */
+    /* HOST arrays of n entries in any order, copied by sph_ens_submit
+     * (the caller may free them when it returns) */
+    const double *x, *y, *z, *vx, *vy, *vz, *u, *h, *m, *p_bg;
+    const double *rho_ref;     /* Tait without set_rho_ref; else may be NULL */
+    const int32_t *id;         /* a permutation of 0..n-1 */
+} sph_run_request;
+
+typedef struct {
+    /* HOST buffers of n entries owned by the caller, each may be NULL;
+     * filled in id order (entry k belongs to the particle with id k) */
+    double *x, *y, *z, *vx, *vy, *vz, *u, *rho;
+    /* filled by the library */
+    double diag[8];            /* M, Px, Py, Pz, Lx, Ly, Lz, E after the run */
+    double dt;                 /* dt from the run's last force evaluation */
+    double t_submit, t_admit, t_done;
+    int32_t steps_done;
+    sph_status status;         /* the run's own outcome (SPH_OK, SPH_E_CAPACITY,
+                                  SPH_E_DOMAIN, SPH_E_NONFINITE, SPH_E_HIP) */
+} sph_run_result;
+
+typedef struct {
+    int64_t submitted, completed, queued, running;
+    int64_t steps;               /* batched steps launched */
+    int64_t particle_steps;      /* sum over launched steps of resident live particles */
+    int64_t capacity_particles;  /* particles the budget holds */
+    int64_t capacity_cells;
+    int64_t bytes_per_particle;  /* device bytes per resident particle */
+    int64_t bytes_allocated;     /* device bytes held by the engine */
+    int64_t peak_particles;      /* most live particles in one step */
+    int32_t peak_runs;           /* most live runs in one step */
+    int32_t max_slots;
+    double busy_seconds;         /* time from the first admission to the last completion */
+} sph_ens_counters;
+
+/* Allocate the arena (SPH_E_NOMEM if the budget cannot be allocated,
+ * SPH_E_INVALID if it holds no run of max_n_per_run particles), capture the
+ * step graph and start the engine thread. */
+sph_status sph_ens_create(sph_ens *out, const sph_ens_config *cfg);
+
+/* Queue a run (non-blocking; copies the arrays). *ticket identifies it.
+ * SPH_E_INVALID for bad arguments, SPH_E_DOMAIN if some h > h_max or a
+ * periodic axis is not longer than 4 h_max, SPH_E_CAPACITY if the run could
+ * never fit (particles or cells above what the budget holds). */
+sph_status sph_ens_submit(sph_ens e, const sph_run_request *req, uint64_t *ticket);
+
+/* Non-blocking: SPH_E_AGAIN while the run is queued or running. When it is
+ * finished, fills *res, forgets the ticket and returns SPH_OK (the run's own
+ * outcome is res->status). SPH_E_INVALID for an unknown ticket. */
+sph_status sph_ens_poll(sph_ens e, uint64_t ticket, sph_run_result *res);
+
+/* As sph_ens_poll, but blocks until the run is finished. */
+sph_status sph_ens_wait(sph_ens e, uint64_t ticket, sph_run_result *res);
+
+sph_status sph_ens_stats(sph_ens e, sph_ens_counters *out);
+
+/* Finish every queued and running run, stop the thread, free everything.
+ * Results not yet polled are discarded. */
+sph_status sph_ens_destroy(sph_ens e);
+
+const char *sph_ens_last_error(sph_ens e);
+
+/* The clock of t_submit, t_admit and t_done (seconds, steady). */
+double sph_ens_clock(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,40 @@
 
 using namespace sph;
 
+namespace sph {
+
+// Grid of cells of side >= 2 h_max (1 + 1e-9) on every axis, at most
+// max_axis cells per axis and cell_cap in total (coarser cells only add
+// candidates: the relation test is exact).
+Grid make_grid(const sph_box &b, double h_max, int64_t cell_cap, int max_axis)
+{
+    Grid g{};
+    const double want = 2.0 * h_max * (1.0 + 1e-9);
+    for (int a = 0; a < 3; ++a) {
+        g.periodic[a] = b.periodic[a];
+        g.lo[a] = b.lo[a];
+        g.hi[a] = b.hi[a];
+        g.len[a] = b.hi[a] - b.lo[a];
+        g.half[a] = 0.5 * g.len[a];
+        double nc = std::floor(g.len[a] / want);
+        nc = std::min(std::max(nc, 1.0), (double)max_axis);
+        g.nc[a] = (int)nc;
+    }
+    while ((int64_t)g.nc[0] * g.nc[1] * g.nc[2] > cell_cap) {
+        int a = 0;
+        for (int k = 1; k < 3; ++k)
+            if (g.nc[k] > g.nc[a]) a = k;
+        g.nc[a] = std::max(1, g.nc[a] / 2);
+    }
+    int maxc = std::max(g.nc[0], std::max(g.nc[1], g.nc[2]));
+    g.bits = 0;
+    while ((1 << g.bits) < maxc) ++g.bits;
+    for (int a = 0; a < 3; ++a) g.inv_s[a] = (double)g.nc[a] / g.len[a];
+    return g;
+}
+
+}  // namespace sph
+
 namespace {
 
 thread_local std::string g_no_ctx_error;
@@ -89,35 +123,6 @@ sph_status check_params(sph_ctx ctx, const sph_params *prm)
     if (prm->eos != SPH_EOS_TAIT && prm->eos != SPH_EOS_IDEAL)
         return fail(ctx, SPH_E_INVALID, "unknown eos %d", prm->eos);
     return SPH_OK;
-}
-
-// Grid of cells of side >= 2 h_max (1 + 1e-9) on every axis, at most
-// kMaxAxisCells per axis and ctx->cell_cap in total.
-Grid make_grid(const sph_box &b, double h_max, int64_t cell_cap)
-{
-    Grid g{};
-    const double want = 2.0 * h_max * (1.0 + 1e-9);
-    for (int a = 0; a < 3; ++a) {
-        g.periodic[a] = b.periodic[a];
-        g.lo[a] = b.lo[a];
-        g.hi[a] = b.hi[a];
-        g.len[a] = b.hi[a] - b.lo[a];
-        g.half[a] = 0.5 * g.len[a];
-        double nc = std::floor(g.len[a] / want);
-        nc = std::min(std::max(nc, 1.0), (double)kMaxAxisCells);
-        g.nc[a] = (int)nc;
-    }
-    while ((int64_t)g.nc[0] * g.nc[1] * g.nc[2] > cell_cap) {
-        int a = 0;
-        for (int k = 1; k < 3; ++k)
-            if (g.nc[k] > g.nc[a]) a = k;
-        g.nc[a] = std::max(1, g.nc[a] / 2);
-    }
-    int maxc = std::max(g.nc[0], std::max(g.nc[1], g.nc[2]));
-    g.bits = 0;
-    while ((1 << g.bits) < maxc) ++g.bits;
-    for (int a = 0; a < 3; ++a) g.inv_s[a] = (double)g.nc[a] / g.len[a];
-    return g;
 }
 
 Grid box_grid(const sph_box &b)
@@ -295,7 +300,7 @@ sph_status sph_build_cells(sph_ctx ctx, const sph_particles *p, const sph_box *b
     for (int a = 0; a < 3; ++a)
         if (box->periodic[a] && !(box->hi[a] - box->lo[a] > 4.0 * h_max))
             return fail(ctx, SPH_E_DOMAIN, "periodic axis %d is not longer than 4 h_max", a);
-    ctx->grid = make_grid(*box, h_max, ctx->cell_cap);
+    ctx->grid = make_grid(*box, h_max, ctx->cell_cap, kMaxAxisCells);
     ctx->n_built = p->n;
     if (p->n == 0) return SPH_OK;
     SPH_HIP(ctx, launch_build_cells(ctx, *p, ctx->grid, h_max));

@@ -5,6 +5,8 @@
 // uniform grid of cells of side >= 2 h_max sorted along a Morton curve gives
 // the same exact candidate set for a fixed-radius search and keeps the
 // particles of a cell, and of neighbouring cells, contiguous in memory.
+#include <algorithm>
+
 #include "sph_internal.h"
 
 namespace sph {
@@ -60,10 +62,11 @@ keys_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ 
 
 // Per-tile digit histogram, digit-major layout hist[d * ntiles + tile].
 __global__ void __launch_bounds__(kSortThreads)
-radix_hist_kernel(const uint32_t *__restrict__ keys, int64_t n, int shift,
+radix_hist_kernel(const uint32_t *__restrict__ keys, int64_t n, const int64_t *n_dev, int shift,
                   uint32_t *__restrict__ hist, int64_t ntiles)
 {
     __shared__ uint32_t cnt[kRadixBins];
+    if (n_dev) n = *n_dev;
     cnt[threadIdx.x] = 0;
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -161,10 +164,12 @@ scan_down_kernel(uint32_t *__restrict__ a, int64_t len,
 // same digit are matched with one ballot per digit bit.
 __global__ void __launch_bounds__(kSortThreads)
 radix_scatter_kernel(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin,
-                     int64_t n, int shift, const uint32_t *__restrict__ hist,
-                     int64_t ntiles, uint32_t *__restrict__ kout,
-                     int32_t *__restrict__ vout)
+                     int64_t n, const int64_t *n_dev, int shift,
+                     const uint32_t *__restrict__ hist, int64_t ntiles,
+                     uint32_t *__restrict__ kout, int32_t *__restrict__ vout)
 {
+    if (n_dev) n = *n_dev;
+    if ((int64_t)blockIdx.x * kSortTile >= n) return;
     constexpr int kWaves = kSortThreads / 64;
     __shared__ uint32_t base_of[kRadixBins];
     __shared__ uint32_t run[kRadixBins];
@@ -214,32 +219,40 @@ radix_scatter_kernel(const uint32_t *__restrict__ kin, const int32_t *__restrict
 
 // Gather every particle array into scratch in sorted order.
 __global__ void __launch_bounds__(256)
-permute_gather_kernel(int64_t n, int64_t stride, const int32_t *__restrict__ perm,
-                      PermFields f, double *__restrict__ tmp,
-                      int32_t *__restrict__ tmp_id)
+permute_gather_kernel(int64_t n, const int64_t *n_dev, int64_t stride,
+                      const int32_t *__restrict__ perm, PermFields f,
+                      double *__restrict__ tmp, int32_t *__restrict__ tmp_id,
+                      int32_t *__restrict__ tmp_slot)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t j = perm[i];
-    for (int k = 0; k < f.nf; ++k) tmp[k * stride + i] = f.f[k][j];
-    tmp_id[i] = f.id[j];
+    if (n_dev) n = *n_dev;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        const int64_t j = perm[i];
+        for (int k = 0; k < f.nf; ++k) tmp[k * stride + i] = f.f[k][j];
+        tmp_id[i] = f.id[j];
+        if (f.slot) tmp_slot[i] = f.slot[j];
+    }
 }
 
 // Copy the sorted arrays back into the caller's storage and write the
 // search records (position and (2h)^2). Fields 0..2 are x, y, z (always
 // present).
 __global__ void __launch_bounds__(256)
-permute_store_kernel(int64_t n, int64_t stride, PermFields f,
+permute_store_kernel(int64_t n, const int64_t *n_dev, int64_t stride, PermFields f,
                      const double *__restrict__ tmp, const int32_t *__restrict__ tmp_id,
-                     int h_field, SearchRec *__restrict__ srec)
+                     const int32_t *__restrict__ tmp_slot, int h_field,
+                     SearchRec *__restrict__ srec)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int k = 0; k < f.nf; ++k) f.f[k][i] = tmp[k * stride + i];
-    f.id[i] = tmp_id[i];
-    const double x = tmp[i], y = tmp[stride + i], z = tmp[2 * stride + i];
-    const double s = 2.0 * tmp[h_field * stride + i];
-    srec[i] = SearchRec{x, y, z, s * s};
+    if (n_dev) n = *n_dev;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        for (int k = 0; k < f.nf; ++k) f.f[k][i] = tmp[k * stride + i];
+        f.id[i] = tmp_id[i];
+        if (f.slot) f.slot[i] = tmp_slot[i];
+        const double x = tmp[i], y = tmp[stride + i], z = tmp[2 * stride + i];
+        const double s = 2.0 * tmp[h_field * stride + i];
+        srec[i] = SearchRec{x, y, z, s * s};
+    }
 }
 
 // Cell table by binary search of each cell's key in the sorted keys: every
@@ -267,6 +280,94 @@ cell_table_kernel(int64_t ncell, Grid g, const uint32_t *__restrict__ keys, int6
     }
     cstart[c] = (int32_t)s;
     cend[c] = (int32_t)lo;
+}
+
+// ---------------------------------------------------------------------------
+// Ensemble kernels: the same cell assignment and table per run, with the
+// run's slot in the high key bits. Counts come from the step header, so one
+// captured launch sequence serves every batch composition.
+
+// Runs admitted before this step: tag their particles with the slot and
+// clear the slot's status word.
+__global__ void __launch_bounds__(256)
+admit_kernel(BatchDev b)
+{
+    const BatchHdr *hd = b.hdr;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int r = 0; r < hd->nnew; ++r) {
+        const int s = hd->new_slot[r];
+        const int64_t off = hd->new_off[r], nr = hd->new_n[r];
+        for (int64_t i = t0; i < nr; i += step) b.slot[off + i] = s;
+        if (t0 == 0) b.status[s] = 0u;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+keys_batch_kernel(BatchDev b, const double *__restrict__ x, const double *__restrict__ y,
+                  const double *__restrict__ z, const double *__restrict__ h,
+                  uint32_t *__restrict__ keys, int32_t *__restrict__ vals)
+{
+    const int64_t n = b.hdr->n_in;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        const int s = b.slot[i];
+        const RunDev &r = b.runs[s];
+        uint32_t key = kEnsDropKey;
+        if (r.phase == RUN_INIT || r.phase == RUN_STEP) {
+            const Grid &g = r.grid;
+            const uint32_t cx = (uint32_t)cell_of(x[i], g.lo[0], g.inv_s[0], g.nc[0]);
+            const uint32_t cy = (uint32_t)cell_of(y[i], g.lo[1], g.inv_s[1], g.nc[1]);
+            const uint32_t cz = (uint32_t)cell_of(z[i], g.lo[2], g.inv_s[2], g.nc[2]);
+            key = ((uint32_t)s << (3 * kEnsAxisBits)) | spread3(cx) | (spread3(cy) << 1) |
+                  (spread3(cz) << 2);
+            if (!(h[i] <= r.h_max)) atomicOr(&b.status[s], ST_DOMAIN);
+        }
+        keys[i] = key;
+        vals[i] = (int32_t)i;
+    }
+}
+
+// Cell table of every live run: global cell c belongs to the live run whose
+// cell range holds it; its particles are found by binary search inside the
+// run's sorted range.
+__global__ void __launch_bounds__(256)
+cell_table_batch_kernel(BatchDev b, const uint32_t *__restrict__ keys,
+                        int32_t *__restrict__ cstart, int32_t *__restrict__ cend)
+{
+    const BatchHdr *hd = b.hdr;
+    const int64_t ncell = hd->ncell;
+    const int nlive = hd->nlive;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += step) {
+        int lo = 0, hi = nlive - 1;
+        while (lo < hi) {  // last live run with cell_base <= c
+            const int mid = (lo + hi + 1) >> 1;
+            if (hd->live_cell_base[mid] <= c) lo = mid; else hi = mid - 1;
+        }
+        const int s = hd->live_slot[lo];
+        const RunDev &r = b.runs[s];
+        const Grid &g = r.grid;
+        const int64_t lc = c - r.cell_base;
+        const uint32_t cx = (uint32_t)(lc % g.nc[0]);
+        const uint32_t cy = (uint32_t)((lc / g.nc[0]) % g.nc[1]);
+        const uint32_t cz = (uint32_t)(lc / ((int64_t)g.nc[0] * g.nc[1]));
+        const uint32_t key = ((uint32_t)s << (3 * kEnsAxisBits)) | spread3(cx) |
+                             (spread3(cy) << 1) | (spread3(cz) << 2);
+        int64_t a = r.start, e = (int64_t)r.start + r.n;
+        while (a < e) {
+            const int64_t mid = (a + e) >> 1;
+            if (keys[mid] < key) a = mid + 1; else e = mid;
+        }
+        const int64_t first = a;
+        e = (int64_t)r.start + r.n;
+        while (a < e) {
+            const int64_t mid = (a + e) >> 1;
+            if (keys[mid] <= key) a = mid + 1; else e = mid;
+        }
+        cstart[c] = (int32_t)first;
+        cend[c] = (int32_t)a;
+    }
 }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -299,11 +400,11 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
     int cur = 0;
     for (int shift = 0; shift < key_bits; shift += kRadixBits) {
         radix_hist_kernel<<<(unsigned)ntiles, kSortThreads, 0, s>>>(
-            ctx->keys[cur], n, shift, ctx->hist, ntiles);
+            ctx->keys[cur], n, nullptr, shift, ctx->hist, ntiles);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = exclusive_scan(ctx, ctx->hist, ntiles * kRadixBins)) != hipSuccess) return e;
         radix_scatter_kernel<<<(unsigned)ntiles, kSortThreads, 0, s>>>(
-            ctx->keys[cur], ctx->vals[cur], n, shift, ctx->hist, ntiles,
+            ctx->keys[cur], ctx->vals[cur], n, nullptr, shift, ctx->hist, ntiles,
             ctx->keys[cur ^ 1], ctx->vals[cur ^ 1]);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         cur ^= 1;
@@ -320,15 +421,63 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
         f.f[f.nf++] = fields[k];
     }
     f.id = p.id;
-    permute_gather_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, ctx->n_max, ctx->vals[cur], f,
-                                                             ctx->perm_tmp, ctx->perm_tmp_id);
+    permute_gather_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, nullptr, ctx->n_max,
+                                                             ctx->vals[cur], f, ctx->perm_tmp,
+                                                             ctx->perm_tmp_id, nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    permute_store_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, ctx->n_max, f, ctx->perm_tmp,
-                                                            ctx->perm_tmp_id, h_field,
-                                                            ctx->srec);
+    permute_store_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, nullptr, ctx->n_max, f,
+                                                            ctx->perm_tmp, ctx->perm_tmp_id,
+                                                            nullptr, h_field, ctx->srec);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cell_table_kernel<<<blocks_for(ncell, 256), 256, 0, s>>>(ncell, g, ctx->sorted_keys, n,
                                                              ctx->cell_start, ctx->cell_end);
+    return hipGetLastError();
+}
+
+hipError_t launch_admit_batch(sph_ctx ctx, const BatchDev &b)
+{
+    admit_kernel<<<256, 256, 0, ctx->stream>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_cells_batch(sph_ctx ctx, const BatchDev &b, double *F, int32_t *id,
+                                    int32_t *slot_tmp)
+{
+    hipStream_t s = ctx->stream;
+    const int64_t cap = b.cap;
+    const unsigned grid = std::min<unsigned>(blocks_for(cap, 256), 4096u);
+    const int64_t *n_in = &b.hdr->n_in;
+    keys_batch_kernel<<<grid, 256, 0, s>>>(b, F + 0 * cap, F + 1 * cap, F + 2 * cap,
+                                           F + 7 * cap, ctx->keys[0], ctx->vals[0]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t ntiles = (cap + kSortTile - 1) / kSortTile;
+    int cur = 0;
+    for (int shift = 0; shift < kEnsKeyBits; shift += kRadixBits) {
+        radix_hist_kernel<<<(unsigned)ntiles, kSortThreads, 0, s>>>(
+            ctx->keys[cur], cap, n_in, shift, ctx->hist, ntiles);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = exclusive_scan(ctx, ctx->hist, ntiles * kRadixBins)) != hipSuccess) return e;
+        radix_scatter_kernel<<<(unsigned)ntiles, kSortThreads, 0, s>>>(
+            ctx->keys[cur], ctx->vals[cur], cap, n_in, shift, ctx->hist, ntiles,
+            ctx->keys[cur ^ 1], ctx->vals[cur ^ 1]);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        cur ^= 1;
+    }
+    ctx->sorted_keys = ctx->keys[cur];
+    PermFields f{};
+    for (int k = 0; k < kEnsFields; ++k) f.f[f.nf++] = F + k * cap;
+    f.id = id;
+    f.slot = b.slot;
+    permute_gather_kernel<<<grid, 256, 0, s>>>(cap, n_in, ctx->n_max, ctx->vals[cur], f,
+                                               ctx->perm_tmp, ctx->perm_tmp_id, slot_tmp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    permute_store_kernel<<<grid, 256, 0, s>>>(cap, n_in, ctx->n_max, f, ctx->perm_tmp,
+                                              ctx->perm_tmp_id, slot_tmp, 7, ctx->srec);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const unsigned cgrid = std::min<unsigned>(blocks_for(b.cell_cap, 256), 4096u);
+    cell_table_batch_kernel<<<cgrid, 256, 0, s>>>(b, ctx->sorted_keys, ctx->cell_start,
+                                                  ctx->cell_end);
     return hipGetLastError();
 }
 

@@ -3,6 +3,8 @@
 // min reduction (wavefront shuffles, then LDS, then one block over the block
 // partials). The same pass sums the conserved totals in FP64 in a fixed tree
 // order, so they are identical from run to run.
+#include <algorithm>
+
 #include "sph_internal.h"
 
 namespace sph {
@@ -167,6 +169,142 @@ timestep_final_kernel(int nblocks, const double *__restrict__ part,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Ensemble: the same update and reductions per run. A particle is advanced
+// only when its run is stepping (not at its t = 0 evaluation, not when it is
+// being dropped), with its run's dt and box.
+__global__ void __launch_bounds__(256)
+integrate_batch_kernel(BatchDev b, int stage, double *__restrict__ F,
+                       const double *__restrict__ ax, const double *__restrict__ ay,
+                       const double *__restrict__ az, const double *__restrict__ dudt)
+{
+    const int64_t cap = b.cap;
+    const int64_t n = stage == SPH_KICK_DRIFT ? b.hdr->n_in : b.hdr->n_out;
+    double *x = F, *y = F + cap, *z = F + 2 * cap;
+    double *vx = F + 3 * cap, *vy = F + 4 * cap, *vz = F + 5 * cap, *u = F + 6 * cap;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        const int s = b.slot[i];
+        const RunDev &r = b.runs[s];
+        if (r.phase != RUN_STEP) continue;
+        const Grid &g = r.grid;
+        const double dt = b.dt[s];
+        const double half = 0.5 * dt;
+        const double tx = ax[i], ty = ay[i], tz = az[i];
+        const double nvx = vx[i] + half * tx;
+        const double nvy = vy[i] + half * ty;
+        const double nvz = vz[i] + half * tz;
+        const double nu = u[i] + half * dudt[i];
+        vx[i] = nvx;
+        vy[i] = nvy;
+        vz[i] = nvz;
+        u[i] = nu;
+        if (stage == SPH_KICK_DRIFT) {
+            double p[3] = {x[i] + dt * nvx, y[i] + dt * nvy, z[i] + dt * nvz};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (!g.periodic[a]) continue;
+                if (p[a] >= g.hi[a]) p[a] -= g.len[a];
+                else if (p[a] < g.lo[a]) p[a] += g.len[a];
+            }
+            x[i] = p[0];
+            y[i] = p[1];
+            z[i] = p[2];
+        } else {
+            const double sm = x[i] + y[i] + z[i] + nvx + nvy + nvz + nu;
+            if (!isfinite(sm)) atomicOr(&b.status[s], ST_NONFINITE);
+        }
+    }
+}
+
+// Partials per run: reduction block q of a run covers its particles
+// [256 q, 256 q + 256), the same blocks and the same tree as the single-run
+// reduction of that run (which covers 256 consecutive particles per block
+// whenever the run has at most kRedMaxBlocks * 256 particles).
+__global__ void __launch_bounds__(kRedThreads)
+timestep_partial_batch_kernel(BatchDev b, const double *__restrict__ F,
+                              const double *__restrict__ c, const double *__restrict__ mumax,
+                              const double *__restrict__ ax, const double *__restrict__ ay,
+                              const double *__restrict__ az, double *__restrict__ part)
+{
+    __shared__ double lds[kRedFields][kRedThreads / 64];
+    const BatchHdr *hd = b.hdr;
+    const int64_t cap = b.cap;
+    const double *x = F, *y = F + cap, *z = F + 2 * cap;
+    const double *vx = F + 3 * cap, *vy = F + 4 * cap, *vz = F + 5 * cap, *u = F + 6 * cap;
+    const double *h = F + 7 * cap, *m = F + 8 * cap;
+    const int64_t nred = hd->nred;
+    const int nlive = hd->nlive;
+    for (int64_t vb = blockIdx.x; vb < nred; vb += gridDim.x) {
+        int lo = 0, hi = nlive - 1;
+        while (lo < hi) {  // last live run with red_base <= vb
+            const int mid = (lo + hi + 1) >> 1;
+            if (hd->live_red_base[mid] <= vb) lo = mid; else hi = mid - 1;
+        }
+        const RunDev &r = b.runs[hd->live_slot[lo]];
+        const int64_t q = vb - r.red_base;
+        const int64_t i = (int64_t)r.start + q * kRedThreads + threadIdx.x;
+        const int64_t end = (int64_t)r.start + r.n;
+        double v[kRedFields];
+        v[0] = INFINITY;
+#pragma unroll
+        for (int k = 1; k < kRedFields; ++k) v[k] = 0.0;
+        if (i < end) {
+            const double hi_ = h[i], ci = c[i];
+            double d = r.c_cfl * hi_ / (ci + 1.2 * (r.alpha * ci + r.beta * mumax[i]));
+            const double tx = ax[i], ty = ay[i], tz = az[i];
+            const double amag = sqrt(tx * tx + ty * ty + tz * tz);
+            if (amag > 0.0) d = fmin(d, r.c_force * sqrt(hi_ / amag));
+            v[0] = fmin(v[0], d);
+            const double mi = m[i], px = x[i], py = y[i], pz = z[i];
+            const double qx = vx[i], qy = vy[i], qz = vz[i];
+            v[1] += mi;
+            v[2] += mi * qx;
+            v[3] += mi * qy;
+            v[4] += mi * qz;
+            v[5] += mi * (py * qz - pz * qy);
+            v[6] += mi * (pz * qx - px * qz);
+            v[7] += mi * (px * qy - py * qx);
+            v[8] += mi * (0.5 * (qx * qx + qy * qy + qz * qz) + u[i]);
+        }
+        block_combine(v, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < kRedFields; ++k) part[(int64_t)k * b.nred_cap + vb] = v[k];
+        }
+        __syncthreads();
+    }
+}
+
+// One block per live run: its partials in the single-run final order.
+__global__ void __launch_bounds__(kRedThreads)
+timestep_final_batch_kernel(BatchDev b, const double *__restrict__ part)
+{
+    __shared__ double lds[kRedFields][kRedThreads / 64];
+    const BatchHdr *hd = b.hdr;
+    for (int k = blockIdx.x; k < hd->nlive; k += gridDim.x) {
+        const int s = hd->live_slot[k];
+        const int64_t base = hd->live_red_base[k];
+        const int nb = hd->live_red_base[k + 1] - hd->live_red_base[k];
+        double v[kRedFields];
+        v[0] = INFINITY;
+#pragma unroll
+        for (int f = 1; f < kRedFields; ++f) v[f] = 0.0;
+        for (int q = threadIdx.x; q < nb; q += kRedThreads) {
+            v[0] = fmin(v[0], part[base + q]);
+#pragma unroll
+            for (int f = 1; f < kRedFields; ++f) v[f] += part[(int64_t)f * b.nred_cap + base + q];
+        }
+        block_combine(v, lds);
+        if (threadIdx.x == 0) {
+            b.dt[s] = v[0];
+#pragma unroll
+            for (int f = 1; f < kRedFields; ++f) b.diag[(int64_t)s * 8 + f - 1] = v[f];
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void copy_kernel(int64_t n, double *__restrict__ dst, const double *__restrict__ src)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -208,6 +346,28 @@ hipError_t launch_copy(sph_ctx ctx, double *dst, const double *src, int64_t n)
 {
     if (n <= 0) return hipSuccess;
     copy_kernel<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate_batch(sph_ctx ctx, const BatchDev &b, int stage, double *F,
+                                  const double *ax, const double *ay, const double *az,
+                                  const double *dudt)
+{
+    const unsigned g = std::min<unsigned>(blocks_for(b.cap, 256), 4096u);
+    integrate_batch_kernel<<<g, 256, 0, ctx->stream>>>(b, stage, F, ax, ay, az, dudt);
+    return hipGetLastError();
+}
+
+hipError_t launch_timestep_batch(sph_ctx ctx, const BatchDev &b, const double *F,
+                                 const double *c, const double *mumax, const double *ax,
+                                 const double *ay, const double *az, double *part)
+{
+    const unsigned g = (unsigned)std::min<int64_t>(b.nred_cap, 2048);
+    timestep_partial_batch_kernel<<<g, kRedThreads, 0, ctx->stream>>>(b, F, c, mumax, ax, ay,
+                                                                       az, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    timestep_final_batch_kernel<<<kEnsMaxSlots, kRedThreads, 0, ctx->stream>>>(b, part);
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@
 //   FP32-pair: separations and velocity differences formed in FP64 and
 //              rounded to FP32, FP32 copies of h, m, rho, P/rho^2 and c, FP32
 //              sums, outputs widened to FP64.
+#include <algorithm>
 #include <type_traits>
 
 #include "sph_internal.h"
@@ -82,19 +83,60 @@ __device__ __forceinline__ double4 lds_load4(const char *p)
 // Records: DensRec {x, y, z, m}, 32 B; two lanes fetch one record.
 constexpr int kDensStride = 48;  // LDS bytes per record: 32 + 16 padding
 
-template <bool F32>
-__global__ void __launch_bounds__(kThreads)
-density_kernel(int64_t n, const DensRec *__restrict__ drec, const double *__restrict__ h,
-               const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
-               Grid g, double *__restrict__ rho)
+// Minimum-image parameters of the lane's run. Single run: the kernel's grid
+// (wave-uniform). Ensemble: the run of the lane's particle; an axis is
+// treated as periodic for the wave when any lane's run is periodic on it, and
+// a lane whose run is not gets half = +inf, for which the select chain leaves
+// the difference unchanged.
+struct Img {
+    bool per[3];
+    double len[3], half[3];
+};
+
+template <bool Multi>
+__device__ __forceinline__ Img lane_img(const Grid &g, const BatchDev &b, int64_t ii)
+{
+    Img m;
+    if constexpr (Multi) {
+        const Grid &rg = b.runs[b.slot[ii]].grid;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const bool p = rg.periodic[a] != 0;
+            m.per[a] = __ballot(p) != 0ull;
+            m.len[a] = rg.len[a];
+            m.half[a] = p ? rg.half[a] : INFINITY;
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            m.per[a] = g.periodic[a] != 0;
+            m.len[a] = g.len[a];
+            m.half[a] = g.half[a];
+        }
+    }
+    return m;
+}
+
+__device__ __forceinline__ double img(double d, const Img &m, int a)
+{
+    return min_image(d, m.per[a], m.len[a], m.half[a]);
+}
+
+template <bool F32, bool Multi>
+__device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld,
+                                             const DensRec *__restrict__ drec,
+                                             const double *__restrict__ h,
+                                             const int32_t *__restrict__ count,
+                                             const int32_t *__restrict__ idx, int max_nb,
+                                             const Grid &g, double *__restrict__ rho,
+                                             const BatchDev &b, char *buf)
 {
     using R = typename std::conditional<F32, float, double>::type;
-    __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kDensStride];
     const int lane = threadIdx.x & 63;
-    char *buf = lds[threadIdx.x >> 6];
-    const int64_t i = xcd_block() * kThreads + threadIdx.x;
+    const int64_t i = tile * kThreads + threadIdx.x;
     const bool active = i < n;
     const int64_t ii = active ? i : 0;
+    const Img im = lane_img<Multi>(g, b, ii);
     const DensRec me = drec[ii];
     const R inv_h = R(1) / (R)h[ii];
     R sum = (R)me.m;  // w(0) = 1
@@ -115,7 +157,7 @@ density_kernel(int64_t n, const DensRec *__restrict__ drec, const double *__rest
         b = *reinterpret_cast<const double2 *>(src_base + (int64_t)j1 * sizeof(DensRec));
     };
     double2 c0, c1;
-    int jn = cnt > 1 ? idx[n + ii] : (int)ii;
+    int jn = cnt > 1 ? idx[ld + ii] : (int)ii;
     fetch(cnt > 0 ? idx[ii] : (int)ii, c0, c1);
     for (int k = 0; k < maxc; ++k) {
         wave_lds_fence();
@@ -124,14 +166,14 @@ density_kernel(int64_t n, const DensRec *__restrict__ drec, const double *__rest
         wave_lds_fence();
         if (k + 1 < maxc) {
             fetch(jn, c0, c1);
-            jn = k + 2 < cnt ? idx[(int64_t)(k + 2) * n + ii] : (int)ii;
+            jn = k + 2 < cnt ? idx[(int64_t)(k + 2) * ld + ii] : (int)ii;
         }
         const double2 lo = *reinterpret_cast<const double2 *>(dst_own);
         const double2 hi = *reinterpret_cast<const double2 *>(dst_own + 16);
         if (k < cnt) {
-            const R dx = (R)min_image(me.x - lo.x, g.periodic[0], g.len[0], g.half[0]);
-            const R dy = (R)min_image(me.y - lo.y, g.periodic[1], g.len[1], g.half[1]);
-            const R dz = (R)min_image(me.z - hi.x, g.periodic[2], g.len[2], g.half[2]);
+            const R dx = (R)img(me.x - lo.x, im, 0);
+            const R dy = (R)img(me.y - lo.y, im, 1);
+            const R dz = (R)img(me.z - hi.x, im, 2);
             const R r = sqrt(fma_r(dz, dz, fma_r(dy, dy, dx * dx)));
             sum = fma_r((R)hi.y, m4_w(r * inv_h), sum);
         }
@@ -139,14 +181,36 @@ density_kernel(int64_t n, const DensRec *__restrict__ drec, const double *__rest
     if (active) rho[i] = (double)(sum * ((R)kInvPi * inv_h * inv_h * inv_h));
 }
 
+template <bool F32, bool Multi>
+__global__ void __launch_bounds__(kThreads)
+density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
+               const double *__restrict__ h, const int32_t *__restrict__ count,
+               const int32_t *__restrict__ idx, int max_nb, Grid g, double *__restrict__ rho,
+               BatchDev b)
+{
+    __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kDensStride];
+    char *buf = lds[threadIdx.x >> 6];
+    if constexpr (Multi) {
+        const int64_t nn = b.hdr->n_out;
+        const int64_t ntile = (nn + kThreads - 1) / kThreads;
+        for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
+            density_tile<F32, true>(t, nn, ld, drec, h, count, idx, max_nb, g, rho, b, buf);
+    } else {
+        density_tile<F32, false>(xcd_block(), n, ld, drec, h, count, idx, max_nb, g, rho, b,
+                                 buf);
+    }
+}
+
 // Density records {x, y, z, m}.
 __global__ void __launch_bounds__(256)
-pack_dens_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                 const double *__restrict__ z, const double *__restrict__ m,
-                 DensRec *__restrict__ out)
+pack_dens_kernel(int64_t n, const int64_t *n_dev, const double *__restrict__ x,
+                 const double *__restrict__ y, const double *__restrict__ z,
+                 const double *__restrict__ m, DensRec *__restrict__ out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = DensRec{x[i], y[i], z[i], m[i]};
+    if (n_dev) n = *n_dev;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step)
+        out[i] = DensRec{x[i], y[i], z[i], m[i]};
 }
 
 // ---------------------------------------------------------------------------
@@ -187,20 +251,25 @@ struct MomParams {
     double alpha, beta, eta2;
 };
 
-template <bool F32>
-__global__ void __launch_bounds__(kThreads)
-momentum_kernel(int64_t n, const PairRec *__restrict__ rec, const int32_t *__restrict__ count,
-                const int32_t *__restrict__ idx, int max_nb, Grid g, MomParams prm,
-                double *__restrict__ ax, double *__restrict__ ay, double *__restrict__ az,
-                double *__restrict__ dudt, double *__restrict__ mumax)
+template <bool F32, bool Multi>
+__device__ __forceinline__ void momentum_tile(
+    int64_t tile, int64_t n, int64_t ld, const PairRec *__restrict__ rec,
+    const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
+    const Grid &g, const MomParams &prm0, double *__restrict__ ax, double *__restrict__ ay,
+    double *__restrict__ az, double *__restrict__ dudt, double *__restrict__ mumax,
+    const BatchDev &b, char *buf)
 {
     using R = typename std::conditional<F32, float, double>::type;
-    __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kMomStride];
     const int lane = threadIdx.x & 63;
-    char *buf = lds[threadIdx.x >> 6];
-    const int64_t i = xcd_block() * kThreads + threadIdx.x;
+    const int64_t i = tile * kThreads + threadIdx.x;
     const bool active = i < n;
     const int64_t ii = active ? i : 0;
+    const Img im = lane_img<Multi>(g, b, ii);
+    MomParams prm = prm0;
+    if constexpr (Multi) {
+        const RunDev &r = b.runs[b.slot[ii]];
+        prm = MomParams{r.alpha, r.beta, r.eta2};
+    }
     const PairRec *mp = rec + ii;
     const double mex = mp->x, mey = mp->y, mez = mp->z;
     const double mevx = mp->vx, mevy = mp->vy, mevz = mp->vz;
@@ -227,7 +296,7 @@ momentum_kernel(int64_t n, const PairRec *__restrict__ rec, const int32_t *__res
     SPH_FETCH(0, jk); SPH_FETCH(1, jk); SPH_FETCH(2, jk); SPH_FETCH(3, jk);                \
     SPH_FETCH(4, jk); SPH_FETCH(5, jk); SPH_FETCH(6, jk); SPH_FETCH(7, jk)
     double2 c0, c1, c2, c3, c4, c5, c6, c7;
-    int jn = cnt > 1 ? idx[n + ii] : (int)ii;
+    int jn = cnt > 1 ? idx[ld + ii] : (int)ii;
     {
         const int j0 = cnt > 0 ? idx[ii] : (int)ii;
         SPH_FETCH_ALL(j0);
@@ -247,7 +316,7 @@ momentum_kernel(int64_t n, const PairRec *__restrict__ rec, const int32_t *__res
         wave_lds_fence();
         if (k + 1 < maxc) {
             SPH_FETCH_ALL(jn);
-            jn = k + 2 < cnt ? idx[(int64_t)(k + 2) * n + ii] : (int)ii;
+            jn = k + 2 < cnt ? idx[(int64_t)(k + 2) * ld + ii] : (int)ii;
         }
 #undef SPH_FETCH_ALL
 #undef SPH_FETCH
@@ -258,9 +327,9 @@ momentum_kernel(int64_t n, const PairRec *__restrict__ rec, const int32_t *__res
         const double2 q4 = *reinterpret_cast<const double2 *>(own + 64);  // m rho
         const double2 q5 = *reinterpret_cast<const double2 *>(own + 80);  // c pr2
         if (k < cnt) {
-            const R dx = (R)min_image(mex - q0.x, g.periodic[0], g.len[0], g.half[0]);
-            const R dy = (R)min_image(mey - q0.y, g.periodic[1], g.len[1], g.half[1]);
-            const R dz = (R)min_image(mez - q1.x, g.periodic[2], g.len[2], g.half[2]);
+            const R dx = (R)img(mex - q0.x, im, 0);
+            const R dy = (R)img(mey - q0.y, im, 1);
+            const R dz = (R)img(mez - q1.x, im, 2);
             const R r2 = fma_r(dz, dz, fma_r(dy, dy, dx * dx));
             const R r = sqrt(r2);
             const R hj = (R)q3.x, inv_hj = (R)q3.y;
@@ -292,28 +361,86 @@ momentum_kernel(int64_t n, const PairRec *__restrict__ rec, const int32_t *__res
     }
 }
 
+template <bool F32, bool Multi>
+__global__ void __launch_bounds__(kThreads)
+momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
+                const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
+                Grid g, MomParams prm, double *__restrict__ ax, double *__restrict__ ay,
+                double *__restrict__ az, double *__restrict__ dudt, double *__restrict__ mumax,
+                BatchDev b)
+{
+    __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kMomStride];
+    char *buf = lds[threadIdx.x >> 6];
+    if constexpr (Multi) {
+        const int64_t nn = b.hdr->n_out;
+        const int64_t ntile = (nn + kThreads - 1) / kThreads;
+        for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
+            momentum_tile<F32, true>(t, nn, ld, rec, count, idx, max_nb, g, prm, ax, ay, az,
+                                     dudt, mumax, b, buf);
+    } else {
+        momentum_tile<F32, false>(xcd_block(), n, ld, rec, count, idx, max_nb, g, prm, ax, ay,
+                                  az, dudt, mumax, b, buf);
+    }
+}
+
 // Pair records {x, y, z, vx, vy, vz, h, 1/h, m, rho, c, P/rho^2}.
 __global__ void __launch_bounds__(256)
-pack_pair_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                 const double *__restrict__ z, const double *__restrict__ vx,
-                 const double *__restrict__ vy, const double *__restrict__ vz,
-                 const double *__restrict__ h, const double *__restrict__ m,
-                 const double *__restrict__ rho, const double *__restrict__ c,
-                 const double *__restrict__ pr2, PairRec *__restrict__ out)
+pack_pair_kernel(int64_t n, const int64_t *n_dev, const double *__restrict__ x,
+                 const double *__restrict__ y, const double *__restrict__ z,
+                 const double *__restrict__ vx, const double *__restrict__ vy,
+                 const double *__restrict__ vz, const double *__restrict__ h,
+                 const double *__restrict__ m, const double *__restrict__ rho,
+                 const double *__restrict__ c, const double *__restrict__ pr2,
+                 PairRec *__restrict__ out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double hi = h[i];
-    PairRec r;
-    r.x = x[i]; r.y = y[i]; r.z = z[i];
-    r.vx = vx[i]; r.vy = vy[i]; r.vz = vz[i];
-    r.h = hi; r.inv_h = 1.0 / hi; r.m = m[i];
-    r.rho = rho[i]; r.c = c[i]; r.pr2 = pr2[i];
-    r.pad[0] = r.pad[1] = r.pad[2] = r.pad[3] = 0.0;
-    out[i] = r;
+    if (n_dev) n = *n_dev;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        const double hi = h[i];
+        PairRec r;
+        r.x = x[i]; r.y = y[i]; r.z = z[i];
+        r.vx = vx[i]; r.vy = vy[i]; r.vz = vz[i];
+        r.h = hi; r.inv_h = 1.0 / hi; r.m = m[i];
+        r.rho = rho[i]; r.c = c[i]; r.pr2 = pr2[i];
+        r.pad[0] = r.pad[1] = r.pad[2] = r.pad[3] = 0.0;
+        out[i] = r;
+    }
 }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// Ensemble EOS: each particle with its run's constants. At a run's t = 0
+// evaluation with a density reference, rho_ref := rho first (then the Tait
+// ratio is exactly one, as in the single-run initial evaluation).
+__global__ void __launch_bounds__(256)
+eos_batch_kernel(BatchDev b, const double *__restrict__ rho, const double *__restrict__ u,
+                 double *__restrict__ rho_ref, const double *__restrict__ p_bg,
+                 double *__restrict__ p, double *__restrict__ c, double *__restrict__ pr2)
+{
+    const int64_t n = b.hdr->n_out;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        const RunDev &rd = b.runs[b.slot[i]];
+        const double r = rho[i];
+        if (rd.phase == RUN_INIT && rd.set_rho_ref) rho_ref[i] = r;
+        double P, C;
+        if (rd.eos == SPH_EOS_TAIT) {
+            const double B = rd.rho0 * rd.c0 * rd.c0 / rd.gamma_tait;
+            const double xr = r / rho_ref[i];
+            const double x2 = xr * xr, x4 = x2 * x2, x6 = x4 * x2, x7 = x6 * xr;
+            const double x3 = x2 * xr;
+            P = p_bg[i] + B * (x7 - 1.0);
+            C = rd.c0 * x3;
+        } else {
+            const double g = rd.gamma_gas;
+            P = (g - 1.0) * r * u[i];
+            C = sqrt(g * (g - 1.0) * u[i]);
+        }
+        p[i] = P;
+        c[i] = C;
+        pr2[i] = P / (r * r);
+    }
+}
 
 }  // namespace
 
@@ -321,14 +448,14 @@ hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &n
                           int precision, double *rho)
 {
     const unsigned nblk = blocks_for(p.n, kThreads);
-    pack_dens_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, p.x, p.y, p.z, p.m,
-                                                                    ctx->drec);
+    pack_dens_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, nullptr, p.x, p.y,
+                                                                    p.z, p.m, ctx->drec);
     if (precision == SPH_FP32_PAIR)
-        density_kernel<true><<<nblk, kThreads, 0, ctx->stream>>>(
-            p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho);
+        density_kernel<true, false><<<nblk, kThreads, 0, ctx->stream>>>(
+            p.n, p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho, BatchDev{});
     else
-        density_kernel<false><<<nblk, kThreads, 0, ctx->stream>>>(
-            p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho);
+        density_kernel<false, false><<<nblk, kThreads, 0, ctx->stream>>>(
+            p.n, p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho, BatchDev{});
     return hipGetLastError();
 }
 
@@ -347,15 +474,71 @@ hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &
     const unsigned nblk = blocks_for(p.n, kThreads);
     const MomParams mp{prm.alpha, prm.beta, prm.eta2};
     pack_pair_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
-        p.n, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2, ctx->prec);
+        p.n, nullptr, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2, ctx->prec);
     if (prm.precision == SPH_FP32_PAIR)
-        momentum_kernel<true><<<nblk, kThreads, 0, ctx->stream>>>(
-            p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp, a.ax, a.ay, a.az,
-            a.dudt, a.mumax);
+        momentum_kernel<true, false><<<nblk, kThreads, 0, ctx->stream>>>(
+            p.n, p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp, a.ax, a.ay, a.az,
+            a.dudt, a.mumax, BatchDev{});
     else
-        momentum_kernel<false><<<nblk, kThreads, 0, ctx->stream>>>(
-            p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp, a.ax, a.ay, a.az,
-            a.dudt, a.mumax);
+        momentum_kernel<false, false><<<nblk, kThreads, 0, ctx->stream>>>(
+            p.n, p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp, a.ax, a.ay, a.az,
+            a.dudt, a.mumax, BatchDev{});
+    return hipGetLastError();
+}
+
+// Ensemble launches: fixed grids sized for the capacity (loops over the
+// header's count), so that the same captured sequence serves every step.
+hipError_t launch_density_batch(sph_ctx ctx, const BatchDev &b, int precision, const double *F,
+                                const int32_t *count, const int32_t *idx, int max_nb,
+                                double *rho)
+{
+    const int64_t cap = b.cap;
+    const int64_t *n_out = &b.hdr->n_out;
+    const unsigned g1 = std::min<unsigned>(blocks_for(cap, 256), 4096u);
+    const unsigned g2 = std::min<unsigned>(blocks_for(cap, kThreads), 4096u);
+    pack_dens_kernel<<<g1, 256, 0, ctx->stream>>>(0, n_out, F + 0 * cap, F + 1 * cap,
+                                                  F + 2 * cap, F + 8 * cap, ctx->drec);
+    if (precision == SPH_FP32_PAIR)
+        density_kernel<true, true><<<g2, kThreads, 0, ctx->stream>>>(
+            0, cap, ctx->drec, F + 7 * cap, count, idx, max_nb, Grid{}, rho, b);
+    else
+        density_kernel<false, true><<<g2, kThreads, 0, ctx->stream>>>(
+            0, cap, ctx->drec, F + 7 * cap, count, idx, max_nb, Grid{}, rho, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_eos_batch(sph_ctx ctx, const BatchDev &b, double *F, const double *rho,
+                            double *p, double *c, double *pr2)
+{
+    const int64_t cap = b.cap;
+    const unsigned g1 = std::min<unsigned>(blocks_for(cap, 256), 4096u);
+    eos_batch_kernel<<<g1, 256, 0, ctx->stream>>>(b, rho, F + 6 * cap, F + 10 * cap,
+                                                  F + 9 * cap, p, c, pr2);
+    return hipGetLastError();
+}
+
+hipError_t launch_momentum_batch(sph_ctx ctx, const BatchDev &b, int precision,
+                                 const double *F, const int32_t *count, const int32_t *idx,
+                                 int max_nb, const double *rho, const double *c,
+                                 const double *pr2, double *ax, double *ay, double *az,
+                                 double *dudt, double *mumax)
+{
+    const int64_t cap = b.cap;
+    const int64_t *n_out = &b.hdr->n_out;
+    const unsigned g1 = std::min<unsigned>(blocks_for(cap, 256), 4096u);
+    const unsigned g2 = std::min<unsigned>(blocks_for(cap, kThreads), 4096u);
+    pack_pair_kernel<<<g1, 256, 0, ctx->stream>>>(0, n_out, F + 0 * cap, F + 1 * cap,
+                                                  F + 2 * cap, F + 3 * cap, F + 4 * cap,
+                                                  F + 5 * cap, F + 7 * cap, F + 8 * cap, rho, c,
+                                                  pr2, ctx->prec);
+    if (precision == SPH_FP32_PAIR)
+        momentum_kernel<true, true><<<g2, kThreads, 0, ctx->stream>>>(
+            0, cap, ctx->prec, count, idx, max_nb, Grid{}, MomParams{}, ax, ay, az, dudt, mumax,
+            b);
+    else
+        momentum_kernel<false, true><<<g2, kThreads, 0, ctx->stream>>>(
+            0, cap, ctx->prec, count, idx, max_nb, Grid{}, MomParams{}, ax, ay, az, dudt, mumax,
+            b);
     return hipGetLastError();
 }
 

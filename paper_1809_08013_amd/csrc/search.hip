@@ -19,6 +19,7 @@
 // own stencil and writes its entries directly. Both paths produce the same
 // set in the same (ascending) order, so the sums over a list do not depend on
 // the path or on where the wave boundaries fall.
+#include <algorithm>
 #include <climits>
 
 #include "sph_internal.h"
@@ -135,21 +136,31 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const SearchRe
     if (u & 31) flush(u >> 5, acc << (32 - (u & 31)));
 }
 
-__global__ void __launch_bounds__(kWave)
-find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
-                      const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
-                      const int32_t *__restrict__ cend, Grid g, int max_nb,
-                      int32_t *__restrict__ count, int32_t *__restrict__ idx,
-                      uint32_t *__restrict__ mask_scratch, const uint32_t *__restrict__ hflag,
-                      uint32_t *status)
+struct SearchLds {
+    uint32_t dkeys[kWave];
+    int2 ent[kMaxEntries];
+    int2 cells[kMaxEntries];
+    int u0[kMaxEntries + 1];
+};
+
+// One tile of 64 particles. Multi: the particles belong to runs of an
+// ensemble (slot in the high key bits); a tile whose particles are all of one
+// run uses that run's grid and cell range, a tile spanning two runs takes the
+// per-lane path with each lane's own run.
+template <bool Multi>
+__device__ __forceinline__ void search_tile(
+    int64_t tile, int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
+    const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
+    const int32_t *__restrict__ cend, const Grid &g0, int max_nb, int32_t *__restrict__ count,
+    int32_t *__restrict__ idx, uint32_t *__restrict__ mask_scratch,
+    const uint32_t *__restrict__ hflag, uint32_t *status0, const BatchDev &b, SearchLds &L)
 {
-    __shared__ uint32_t dkeys[kWave];
-    __shared__ int2 ent[kMaxEntries];
-    __shared__ int2 cells[kMaxEntries];
-    __shared__ int u0[kMaxEntries + 1];
+    uint32_t *dkeys = L.dkeys;
+    int2 *ent = L.ent;
+    int2 *cells = L.cells;
+    int *u0 = L.u0;
 
     const int lane = threadIdx.x;
-    const int64_t tile = xcd_block();
     const int64_t t0 = tile * kWave;
     uint32_t *bm = mask_scratch + tile * (kMaxWords * kWave);
     const int64_t i = t0 + lane;
@@ -158,16 +169,28 @@ find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
 
     const uint32_t key = active ? keys[i] : 0xFFFFFFFFu;
     const SearchRec me = active ? srec[i] : SearchRec{0.0, 0.0, 0.0, 0.0};
+    // run of the tile (lane 0 is always active) and whether all lanes share it
+    int my_slot = 0, slot0 = 0;
+    bool mixed = false;
+    if constexpr (Multi) {
+        my_slot = active ? (int)(key >> (3 * kEnsAxisBits)) : 0;
+        slot0 = __builtin_amdgcn_readfirstlane(my_slot);
+        mixed = __ballot(active && my_slot != slot0) != 0ull;
+    }
+    const Grid &g = Multi ? b.runs[slot0].grid : g0;
+    const int64_t cbase = Multi ? (int64_t)b.runs[slot0].cell_base : 0;
+    const uint32_t mkey = Multi ? (key & kEnsMortonMask) : key;
     const uint32_t prev = __shfl_up(key, 1, kWave);
     const bool first = active && (lane == 0 || key != prev);
     const uint64_t fm = __ballot(first);
     const int ndist = __popcll(fm);
-    if (first) dkeys[__popcll(fm & lt)] = key;
+    if (first) dkeys[__popcll(fm & lt)] = mkey;
 
     // The minimum image can be skipped for the whole wave when, on every
     // periodic axis, the union of the stencils spans less than half the box:
     // then |d| < L/2 for every candidate and the image test is a no-op.
-    const int cx = (int)compact3(key), cy = (int)compact3(key >> 1), cz = (int)compact3(key >> 2);
+    const int cx = (int)compact3(mkey), cy = (int)compact3(mkey >> 1),
+              cz = (int)compact3(mkey >> 2);
     bool wrap = false;
     {
         const int cc[3] = {cx, cy, cz};
@@ -186,7 +209,7 @@ find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
     }
 
     const int nent = ndist * kStencil;
-    bool use_union = nent <= kMaxEntries;
+    bool use_union = nent <= kMaxEntries && !mixed;
     int nu = 0, total = 0;
     __syncthreads();
     if (use_union) {
@@ -203,9 +226,9 @@ find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
                 const int z = wrap_or_clip((int)compact3(k >> 2) + s / 9 - 1, g.nc[2],
                                            g.periodic[2], okz);
                 if (okx && oky && okz) {
-                    const int64_t cell = ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
-                    const int a = cstart[cell], b = cend[cell];
-                    if (a < b) v = make_int2(a, b);
+                    const int64_t cell = cbase + ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
+                    const int a = cstart[cell], e2 = cend[cell];
+                    if (a < e2) v = make_int2(a, e2);
                 }
             }
             ent[e] = v;
@@ -216,11 +239,11 @@ find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
             for (int j = k >> 1; j > 0; j >>= 1) {
                 const int lo_i = ((lane & ~(j - 1)) << 1) | (lane & (j - 1));
                 const int hi_i = lo_i | j;
-                const int2 a = ent[lo_i], b = ent[hi_i];
+                const int2 ea = ent[lo_i], eb = ent[hi_i];
                 const bool up = (lo_i & k) == 0;
-                if ((a.x > b.x) == up) {
-                    ent[lo_i] = b;
-                    ent[hi_i] = a;
+                if ((ea.x > eb.x) == up) {
+                    ent[lo_i] = eb;
+                    ent[hi_i] = ea;
                 }
                 __syncthreads();
             }
@@ -261,7 +284,7 @@ find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
     }
 
     if (use_union) {
-        const bool uniform_h = hflag[0] == 0;
+        const bool uniform_h = Multi ? b.runs[slot0].uniform_h != 0 : hflag[0] == 0;
         int cnt = 0;
         uint64_t occ = 0;  // bit w: mask word w has at least one bit for this lane
         if (wrap) {
@@ -326,12 +349,12 @@ find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
                     c_u0 = c_end_u;
                     c_end_u = u0[cp + 1];
                 }
-                idx[(int64_t)k * n + i] = c_start + (uu - c_u0);
+                idx[(int64_t)k * ld + i] = c_start + (uu - c_u0);
             }
         }
         if (active) {
             count[i] = cnt;
-            if (cnt > max_nb) atomicOr(status, ST_CAPACITY);
+            if (cnt > max_nb) atomicOr(Multi ? &b.status[slot0] : status0, ST_CAPACITY);
         }
         return;
     }
@@ -340,6 +363,8 @@ find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
     // ascending order of their first particle (selecting the next one each
     // time), so its list is ascending too.
     if (!active) return;
+    const Grid &gl = Multi ? b.runs[my_slot].grid : g0;
+    const int64_t cbl = Multi ? (int64_t)b.runs[my_slot].cell_base : 0;
     int cnt = 0;
     const int32_t ii = (int32_t)i;
     int last = -1;
@@ -347,11 +372,11 @@ find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
         int best_s = INT_MAX, best_e = 0;
         for (int s = 0; s < kStencil; ++s) {
             bool okx, oky, okz;
-            const int x = wrap_or_clip(cx + s % 3 - 1, g.nc[0], g.periodic[0], okx);
-            const int y = wrap_or_clip(cy + (s / 3) % 3 - 1, g.nc[1], g.periodic[1], oky);
-            const int z = wrap_or_clip(cz + s / 9 - 1, g.nc[2], g.periodic[2], okz);
+            const int x = wrap_or_clip(cx + s % 3 - 1, gl.nc[0], gl.periodic[0], okx);
+            const int y = wrap_or_clip(cy + (s / 3) % 3 - 1, gl.nc[1], gl.periodic[1], oky);
+            const int z = wrap_or_clip(cz + s / 9 - 1, gl.nc[2], gl.periodic[2], okz);
             if (!(okx && oky && okz)) continue;
-            const int64_t cell = ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
+            const int64_t cell = cbl + ((int64_t)z * gl.nc[1] + y) * gl.nc[0] + x;
             const int a = cstart[cell], b = cend[cell];
             if (a < b && a > last && a < best_s) {
                 best_s = a;
@@ -361,15 +386,41 @@ find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
         if (best_s == INT_MAX) break;
         for (int32_t j = best_s; j < best_e; ++j) {
             const SearchRec o = srec[j];
-            if (related<true, false>(me, o, g) && j != ii) {
-                if (cnt < max_nb) idx[(int64_t)cnt * n + i] = j;
+            if (related<true, false>(me, o, gl) && j != ii) {
+                if (cnt < max_nb) idx[(int64_t)cnt * ld + i] = j;
                 ++cnt;
             }
         }
         last = best_s;
     }
     count[i] = cnt;
-    if (cnt > max_nb) atomicOr(status, ST_CAPACITY);
+    if (cnt > max_nb) atomicOr(Multi ? &b.status[my_slot] : status0, ST_CAPACITY);
+}
+
+template <bool Multi>
+__global__ void __launch_bounds__(kWave)
+find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
+                      const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
+                      const int32_t *__restrict__ cend, Grid g, int max_nb,
+                      int32_t *__restrict__ count, int32_t *__restrict__ idx,
+                      uint32_t *__restrict__ mask_scratch, const uint32_t *__restrict__ hflag,
+                      uint32_t *status, BatchDev b)
+{
+    __shared__ SearchLds L;
+    if constexpr (Multi) {
+        const int64_t nn = b.hdr->n_out;
+        const int64_t ntile = (nn + kWave - 1) / kWave;
+        // the loop bound is wave-uniform, and each pass ends with the LDS
+        // reuse ordered by the block barriers inside the tile
+        for (int64_t tile = xcd_block(); tile < ntile; tile += gridDim.x) {
+            search_tile<true>(tile, nn, ld, srec, keys, cstart, cend, g, max_nb, count, idx,
+                              mask_scratch, hflag, status, b, L);
+            __syncthreads();
+        }
+    } else {
+        search_tile<false>(xcd_block(), n, ld, srec, keys, cstart, cend, g, max_nb, count, idx,
+                           mask_scratch, hflag, status, b, L);
+    }
 }
 
 }  // namespace
@@ -377,9 +428,21 @@ find_neighbors_kernel(int64_t n, const SearchRec *__restrict__ srec,
 hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb)
 {
     const unsigned blocks = (unsigned)((p.n + kWave - 1) / kWave);
-    find_neighbors_kernel<<<blocks, kWave, 0, ctx->stream>>>(
-        p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid, nb.max_nb, nb.count, nb.idx, ctx->nb_mask, ctx->hflag_dev,
-        ctx->status_dev);
+    find_neighbors_kernel<false><<<blocks, kWave, 0, ctx->stream>>>(
+        p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
+        nb.max_nb, nb.count, nb.idx, ctx->nb_mask, ctx->hflag_dev, ctx->status_dev, BatchDev{});
+    return hipGetLastError();
+}
+
+hipError_t launch_find_neighbors_batch(sph_ctx ctx, const BatchDev &b, int max_nb,
+                                       int32_t *count, int32_t *idx)
+{
+    // the mask scratch holds one region per tile of the capacity
+    const unsigned blocks =
+        (unsigned)std::min<int64_t>((b.cap + kWave - 1) / kWave, 16384);
+    find_neighbors_kernel<true><<<blocks, kWave, 0, ctx->stream>>>(
+        0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,
+        count, idx, ctx->nb_mask, nullptr, nullptr, b);
     return hipGetLastError();
 }
 

@@ -48,6 +48,71 @@ struct PermFields {
     double *f[kPermFields];
     int nf;
     int32_t *id;
+    int32_t *slot;      // ensemble only: run slot of each particle (else null)
+};
+
+// ---------------------------------------------------------------------------
+// Ensemble (many independent runs in one arena).
+//
+// Key of a particle of run slot s: (s << 3 kEnsAxisBits) | Morton(cell), so
+// one stable radix sort over kEnsKeyBits bits groups the particles by run and,
+// inside a run, by cell, exactly as the single-run sort does. A run being
+// dropped gets the all-ones key and sorts behind every live particle.
+constexpr int kEnsAxisBits = 5;                     // <= 32 cells per axis per run
+constexpr int kEnsSlotBits = 9;
+constexpr int kEnsMaxSlots = (1 << kEnsSlotBits) - 1;  // slot 511 is the drop key
+constexpr int kEnsKeyBits = kEnsSlotBits + 3 * kEnsAxisBits;
+constexpr uint32_t kEnsMortonMask = (1u << (3 * kEnsAxisBits)) - 1u;
+constexpr uint32_t kEnsDropKey = 0xFFFFFFFFu;
+constexpr int kEnsFields = 11;  // x y z vx vy vz u h m p_bg rho_ref (rows of one block)
+
+enum : int32_t { RUN_FREE = 0, RUN_INIT = 1, RUN_STEP = 2, RUN_DROP = 3 };
+
+// Per-slot description of a run for the current step (host-written).
+struct RunDev {
+    Grid grid;
+    double h_max;
+    double rho0, c0, gamma_tait, gamma_gas, alpha, beta, eta2, c_cfl, c_force;
+    int32_t eos;
+    int32_t phase;        // RUN_*
+    int32_t set_rho_ref;  // rho_ref := rho at the t = 0 evaluation
+    int32_t uniform_h;    // every particle of the run has the same h
+    int32_t cell_base;    // first entry of the run in the cell table
+    int32_t ncell;
+    int32_t start;        // first particle after this step's sort
+    int32_t n;
+    int32_t red_base;     // first reduction block of the run
+    int32_t pad;
+};
+
+// Per-step header (host-written): counts, live runs in slot order, and the
+// runs admitted before this step with the arena range they were copied to.
+struct BatchHdr {
+    int64_t n_in;    // particles before the sort (live + dropped + admitted)
+    int64_t n_out;   // particles of live runs, after the sort
+    int64_t ncell;   // cells of live runs
+    int64_t nred;    // reduction blocks of live runs
+    int32_t nlive;
+    int32_t nnew;
+    int32_t live_slot[kEnsMaxSlots];
+    int32_t live_cell_base[kEnsMaxSlots + 1];
+    int32_t live_red_base[kEnsMaxSlots + 1];
+    int32_t new_slot[kEnsMaxSlots];
+    int32_t new_off[kEnsMaxSlots];
+    int32_t new_n[kEnsMaxSlots];
+};
+
+// Device pointers an ensemble step reads besides the particle arrays.
+struct BatchDev {
+    const BatchHdr *hdr;
+    const RunDev *runs;
+    int32_t *slot;       // per particle
+    double *dt;          // per slot
+    double *diag;        // 8 per slot
+    uint32_t *status;    // per slot
+    int64_t cap;         // particle capacity (ELL leading dimension)
+    int64_t cell_cap;
+    int64_t nred_cap;
 };
 
 constexpr int kStencil = 27;
@@ -142,5 +207,32 @@ hipError_t launch_timestep(sph_ctx ctx, const sph_particles &p,
                            const sph_params &prm, const sph_fields &f,
                            const sph_accel &a, double *dt_dev, double *diag_dev);
 hipError_t launch_copy(sph_ctx ctx, double *dst, const double *src, int64_t n);
+
+Grid make_grid(const sph_box &b, double h_max, int64_t cell_cap, int max_axis);
+
+// Ensemble launchers: fixed grids sized for b.cap; counts are read from the
+// step header on the device. F is the block of kEnsFields state rows
+// (x y z vx vy vz u h m p_bg rho_ref), each b.cap long.
+hipError_t launch_admit_batch(sph_ctx ctx, const BatchDev &b);
+hipError_t launch_build_cells_batch(sph_ctx ctx, const BatchDev &b, double *F, int32_t *id,
+                                    int32_t *slot_tmp);
+hipError_t launch_find_neighbors_batch(sph_ctx ctx, const BatchDev &b, int max_nb,
+                                       int32_t *count, int32_t *idx);
+hipError_t launch_density_batch(sph_ctx ctx, const BatchDev &b, int precision, const double *F,
+                                const int32_t *count, const int32_t *idx, int max_nb,
+                                double *rho);
+hipError_t launch_eos_batch(sph_ctx ctx, const BatchDev &b, double *F, const double *rho,
+                            double *p, double *c, double *pr2);
+hipError_t launch_momentum_batch(sph_ctx ctx, const BatchDev &b, int precision,
+                                 const double *F, const int32_t *count, const int32_t *idx,
+                                 int max_nb, const double *rho, const double *c,
+                                 const double *pr2, double *ax, double *ay, double *az,
+                                 double *dudt, double *mumax);
+hipError_t launch_integrate_batch(sph_ctx ctx, const BatchDev &b, int stage, double *F,
+                                  const double *ax, const double *ay, const double *az,
+                                  const double *dudt);
+hipError_t launch_timestep_batch(sph_ctx ctx, const BatchDev &b, const double *F,
+                                 const double *c, const double *mumax, const double *ax,
+                                 const double *ay, const double *az, double *part);
 
 }  // namespace sph

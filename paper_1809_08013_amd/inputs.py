@@ -106,15 +106,32 @@ def square_patch_pressure(x: np.ndarray, y: np.ndarray, L: float = 1.0,
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     ks = np.arange(1, kmax + 1, 2, dtype=np.float64)  # odd 1..kmax
-    xs = (x + 0.5 * L) / L
-    ys = (y + 0.5 * L) / L
-    sx = np.sin(np.pi * np.outer(xs, ks))  # (N, K)
-    sy = np.sin(np.pi * np.outer(ys, ks))
     mm, nn = np.meshgrid(ks, ks, indexing="ij")
     coef = -32.0 * omega * omega / (mm * nn * np.pi ** 2 *
                                     ((mm * np.pi / L) ** 2 + (nn * np.pi / L) ** 2))
-    # P_i = sum_mn sx[i,m] coef[m,n] sy[i,n]
-    return rho * np.sum((sx @ coef) * sy, axis=1)
+    out = np.empty(x.shape[0])
+
+    def rows(a: int, b: int) -> None:
+        xs = (x[a:b] + 0.5 * L) / L
+        ys = (y[a:b] + 0.5 * L) / L
+        sx = np.sin(np.pi * np.outer(xs, ks))  # (rows, K)
+        sy = np.sin(np.pi * np.outer(ys, ks))
+        # P_i = sum_mn sx[i,m] coef[m,n] sy[i,n]
+        out[a:b] = rho * np.sum((sx @ coef) * sy, axis=1)
+
+    # Fixed row chunks bound the (N, K) temporaries; chunks are independent,
+    # so the result does not depend on how many threads evaluate them.
+    chunk = 1 << 20
+    spans = [(a, min(a + chunk, x.shape[0])) for a in range(0, x.shape[0], chunk)]
+    if len(spans) <= 1:
+        for a, b in spans:
+            rows(a, b)
+    else:
+        import os
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            list(ex.map(lambda ab: rows(*ab), spans))
+    return out
 
 
 def square_patch(n_side: int = 20, nz: int | None = None, L: float = 1.0,

@@ -9,7 +9,9 @@ raises.
 The functions carry the C names (sph_build_cells, sph_find_neighbors,
 sph_density, sph_eos, sph_momentum_energy, sph_integrate, sph_timestep,
 sph_init_forces, sph_step, sph_ctx_check, sph_export_neighbors). `SphState`
-holds one run's device arrays.
+holds one run's device arrays. `Ensemble` wraps the serving engine
+(sph_ens_create, sph_ens_submit, sph_ens_poll, sph_ens_wait, sph_ens_stats,
+sph_ens_destroy).
 """
 from __future__ import annotations
 
@@ -66,6 +68,37 @@ class Params(C.Structure):
                                   "beta", "eta2", "c_cfl", "c_force")]
 
 
+class EnsConfig(C.Structure):
+    _fields_ = [("device", C.c_int32), ("precision", C.c_int32), ("max_nb", C.c_int32),
+                ("max_slots", C.c_int32), ("hbm_budget_bytes", C.c_int64),
+                ("max_n_per_run", C.c_int64)]
+
+
+_REQ_ARRAYS = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m", "p_bg", "rho_ref", "id")
+_RES_ARRAYS = ("x", "y", "z", "vx", "vy", "vz", "u", "rho")
+
+
+class RunRequest(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_steps", C.c_int32), ("set_rho_ref", C.c_int32),
+                ("params", Params), ("box", Box), ("h_max", C.c_double)] + [
+        (k, _VP) for k in _REQ_ARRAYS]
+
+
+class RunResult(C.Structure):
+    _fields_ = [(k, _VP) for k in _RES_ARRAYS] + [
+        ("diag", C.c_double * 8), ("dt", C.c_double), ("t_submit", C.c_double),
+        ("t_admit", C.c_double), ("t_done", C.c_double), ("steps_done", C.c_int32),
+        ("status", C.c_int32)]
+
+
+class EnsCounters(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "submitted", "completed", "queued", "running", "steps", "particle_steps",
+        "capacity_particles", "capacity_cells", "bytes_per_particle", "bytes_allocated",
+        "peak_particles")] + [("peak_runs", C.c_int32), ("max_slots", C.c_int32),
+                              ("busy_seconds", C.c_double)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -103,6 +136,15 @@ def load():
             "sph_step": (C.c_int32, [_VP, P, B, C.c_double, N, M, F, A, _VP, _VP]),
             "sph_export_neighbors": (C.c_int32, [_VP, P, N, _VP, _VP, C.c_int64,
                                                  C.POINTER(C.c_int64)]),
+            "sph_ens_create": (C.c_int32, [C.POINTER(_VP), C.POINTER(EnsConfig)]),
+            "sph_ens_submit": (C.c_int32, [_VP, C.POINTER(RunRequest),
+                                           C.POINTER(C.c_uint64)]),
+            "sph_ens_poll": (C.c_int32, [_VP, C.c_uint64, C.POINTER(RunResult)]),
+            "sph_ens_wait": (C.c_int32, [_VP, C.c_uint64, C.POINTER(RunResult)]),
+            "sph_ens_stats": (C.c_int32, [_VP, C.POINTER(EnsCounters)]),
+            "sph_ens_destroy": (C.c_int32, [_VP]),
+            "sph_ens_last_error": (C.c_char_p, [_VP]),
+            "sph_ens_clock": (C.c_double, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -316,3 +358,93 @@ def sph_export_neighbors(ctx: Context, st: SphState):
 
 def version() -> str:
     return load().sph_version().decode()
+
+
+# ---------------------------------------------------------------- serving --
+
+class Ensemble:
+    """The serving engine (include/sph.h, sph_ens_*): runs are submitted as
+    host arrays, advanced together on the GPU, and collected by ticket."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64, max_n_per_run: int = 262144,
+                 precision: int = SPH_FP64, max_nb: int = 128, device: int | None = None):
+        import torch
+        self.lib = load()
+        if device is None:
+            device = torch.cuda.current_device()
+        cfg = EnsConfig(int(device), int(precision), int(max_nb), int(max_slots),
+                        int(budget_bytes), int(max_n_per_run))
+        h = _VP()
+        s = self.lib.sph_ens_create(C.byref(h), C.byref(cfg))
+        if s != SPH_OK:
+            raise SphError(s, self.lib.sph_ens_last_error(None).decode())
+        self.h = h
+
+    def _raise(self, s: int):
+        if s != SPH_OK:
+            raise SphError(s, self.lib.sph_ens_last_error(self.h).decode())
+
+    def submit(self, ic, n_steps: int, set_rho_ref: bool = True, h_max: float | None = None,
+               rho_ref=None) -> int:
+        """Queue a run of the initial state `ic` (inputs.SphIC); returns the ticket."""
+        arrs = ic.arrays()
+        keep = {}
+        for k in _REQ_ARRAYS:
+            if k == "rho_ref":
+                src = rho_ref
+            else:
+                src = arrs[k]
+            if src is None:
+                keep[k] = None
+                continue
+            dt = np.int32 if k == "id" else np.float64
+            keep[k] = np.ascontiguousarray(src, dtype=dt)
+        req = RunRequest(int(ic.n), int(n_steps), int(bool(set_rho_ref)),
+                         make_params(ic.params, SPH_FP64), make_box(ic.lo, ic.hi, ic.periodic),
+                         float(h_max if h_max is not None else np.max(ic.h)),
+                         *[None if keep[k] is None else _VP(keep[k].ctypes.data)
+                           for k in _REQ_ARRAYS])
+        t = C.c_uint64(0)
+        self._raise(self.lib.sph_ens_submit(self.h, C.byref(req), C.byref(t)))
+        return int(t.value)
+
+    def _result(self, fn, ticket: int, n: int, arrays: bool = True):
+        out = {k: np.empty(n) for k in _RES_ARRAYS} if arrays else {}
+        res = RunResult(*[_VP(out[k].ctypes.data) if arrays else None for k in _RES_ARRAYS])
+        s = fn(self.h, C.c_uint64(ticket), C.byref(res))
+        if s == SPH_E_AGAIN:
+            return None
+        self._raise(s)
+        out.update(diag=np.array(res.diag[:]), dt=res.dt, t_submit=res.t_submit,
+                   t_admit=res.t_admit, t_done=res.t_done, steps_done=res.steps_done,
+                   status=res.status)
+        return out
+
+    def poll(self, ticket: int, n: int, arrays: bool = True):
+        """Result dict (arrays in id order unless arrays=False), or None while
+        the run is not done."""
+        return self._result(self.lib.sph_ens_poll, ticket, n, arrays)
+
+    def wait(self, ticket: int, n: int, arrays: bool = True):
+        return self._result(self.lib.sph_ens_wait, ticket, n, arrays)
+
+    def stats(self) -> dict:
+        c = EnsCounters()
+        self._raise(self.lib.sph_ens_stats(self.h, C.byref(c)))
+        return {k: getattr(c, k) for k, _ in EnsCounters._fields_}
+
+    def close(self):
+        if self.h:
+            s = self.lib.sph_ens_destroy(self.h)
+            self.h = _VP()
+            self._raise(s)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ens_clock() -> float:
+    return float(load().sph_ens_clock())

@@ -60,3 +60,55 @@ def test_status_strings_and_null_checks():
         if fn == "sph_integrate":
             args[3] = 0
         assert f(*args) == S.SPH_E_INVALID, fn
+
+
+def test_ensemble_host_checks():
+    """sph_ens_*: configuration and request checks run on the host before any
+    device work."""
+    L = _lib()
+    h = C.c_void_p()
+    assert L.sph_ens_create(None, None) == S.SPH_E_INVALID
+    for cfg in (S.EnsConfig(0, 7, 128, 4, 1 << 30, 1000),     # precision
+                S.EnsConfig(0, 0, 0, 4, 1 << 30, 1000),       # max_nb
+                S.EnsConfig(0, 0, 128, 0, 1 << 30, 1000),     # max_slots
+                S.EnsConfig(0, 0, 128, 512, 1 << 30, 1000),
+                S.EnsConfig(0, 0, 128, 4, 1 << 30, 0),        # max_n_per_run
+                S.EnsConfig(0, 0, 128, 4, 1 << 20, 1000)):    # budget below one run
+        assert L.sph_ens_create(C.byref(h), C.byref(cfg)) == S.SPH_E_INVALID
+    assert b"budget" in L.sph_ens_last_error(None)
+    t = C.c_uint64()
+    assert L.sph_ens_submit(None, None, C.byref(t)) == S.SPH_E_INVALID
+    assert L.sph_ens_poll(None, 1, None) == S.SPH_E_INVALID
+    assert L.sph_ens_wait(None, 1, None) == S.SPH_E_INVALID
+    assert L.sph_ens_stats(None, None) == S.SPH_E_INVALID
+    assert L.sph_ens_destroy(None) == S.SPH_E_INVALID
+    a = L.sph_ens_clock()
+    b = L.sph_ens_clock()
+    assert 0 < a <= b
+
+
+def test_ensemble_structs_match_header():
+    """ctypes mirrors of the ensemble structs have the C sizes and offsets."""
+    import subprocess
+    import tempfile
+    src = r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "sph.h"
+int main(void) {
+    printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(sph_ens_config), sizeof(sph_run_request),
+           sizeof(sph_run_result), sizeof(sph_ens_counters), offsetof(sph_run_request, rho_ref),
+           offsetof(sph_run_result, status), offsetof(sph_ens_counters, busy_seconds));
+    return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        got = [int(v) for v in subprocess.check_output([exe]).split()]
+    want = [C.sizeof(S.EnsConfig), C.sizeof(S.RunRequest), C.sizeof(S.RunResult),
+            C.sizeof(S.EnsCounters), S.RunRequest.rho_ref.offset, S.RunResult.status.offset,
+            S.EnsCounters.busy_seconds.offset]
+    assert got == want
