@@ -40,35 +40,92 @@ def log(msg: str) -> None:
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_model(n: int, pairs: float, precision: int) -> dict:
-    """Algorithmic HBM bytes and flops per launch of each C-ABI call.
+def stencil_candidates(ic) -> float:
+    """Candidates a cell-list search tests: for every particle, the particles
+    of the 27 cells around its own (cells of side >= 2 h_max, the grid the
+    library builds for this box, at most 1024 per axis), summed exactly from
+    the cell occupancy."""
+    import numpy as np
+    lo, hi, per = np.array(ic.lo), np.array(ic.hi), ic.periodic
+    want = 2.0 * float(np.max(ic.h)) * (1.0 + 1e-9)
+    nc = np.clip(np.floor((hi - lo) / want), 1, 1024).astype(int)
+    idx = []
+    for a, v in enumerate((ic.x, ic.y, ic.z)):
+        c = np.floor((v - lo[a]) * (nc[a] / (hi[a] - lo[a])))
+        idx.append(np.clip(c, 0, nc[a] - 1).astype(int))
+    cnt = np.zeros(nc, dtype=np.int64)
+    np.add.at(cnt, tuple(idx), 1)
+    tot = np.zeros_like(cnt)
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                sh = cnt
+                for a, d in enumerate((dx, dy, dz)):
+                    if d == 0:
+                        continue
+                    if per[a]:
+                        sh = np.roll(sh, -d, axis=a)
+                    else:
+                        sh = np.roll(sh, -d, axis=a)
+                        sl = [slice(None)] * 3
+                        sl[a] = slice(nc[a] - 1, nc[a]) if d > 0 else slice(0, 1)
+                        sh = sh.copy()
+                        sh[tuple(sl)] = 0
+                tot += sh
+    return float(np.sum(cnt * tot))
 
-    Bytes: compulsory traffic, each particle's own arrays read/written once,
-    neighbour-list entries 4 B each, neighbour (j) data assumed served from
-    cache. Flops: FP operations per directed pair (pair kernels) or per
-    particle (others) of the arithmetic as written.
+
+def kernel_model(n: int, pairs: float, candidates: float, precision: int) -> dict:
+    """Algorithmic HBM bytes and FP64-equivalent flops per launch of each call.
+
+    Bytes: compulsory traffic with each particle's own arrays read or written
+    once, neighbour-list entries 4 B each, neighbour (j) data served from
+    cache, the reorder counted in place (read + write of every field once).
+    Flops (FMA = 2): the search tests every stencil candidate (3 differences,
+    r^2 with one multiply and two FMAs: 8); density ~20 and momentum ~75 per
+    directed pair.
     """
     nb = pairs / max(n, 1)
-    f32 = precision == 1
-    own_pair = 88 if not f32 else 68        # x y z v h m rho c pr2 (FP32 copies)
+    own_pair = 88 if precision == 0 else 68
     per_particle_bytes = {
-        "integrate_kd": 136,
-        "build_cells": 40 + 3 * 20 + 2 * 2 * 100 + 8,
-        "find_neighbors": 40 + 4 + 4 * nb,
-        "density": 52 + 4 * nb if not f32 else 44 + 4 * nb,
-        "eos": 60,
+        "integrate_kd": 144,
+        "build_cells": 40 + 3 * 16 + 2 * 92 + 32,
+        "find_neighbors": 40 + 4 * nb,
+        "density": 52 + 4 * nb,
+        "eos": 48,
         "momentum_energy": own_pair + 44 + 4 * nb,
         "integrate_k": 120,
         "timestep": 112,
     }
-    flops_per_pair = {"find_neighbors": 12.0 * 729 / max(nb, 1), "density": 20.0,
-                      "momentum_energy": 75.0}
-    out = {}
-    for k in CALLS:
-        b = per_particle_bytes[k] * n
-        fl = flops_per_pair.get(k, 0.0) * pairs
-        out[k] = (b, fl)
-    return out
+    flops = {"find_neighbors": 8.0 * candidates, "density": 20.0 * pairs,
+             "momentum_energy": 75.0 * pairs}
+    return {k: (per_particle_bytes[k] * n, flops.get(k, 0.0)) for k in CALLS}
+
+
+KERNEL_OF_CALL = {"find_neighbors": "find_neighbors_kernel", "density": "density_kernel",
+                  "momentum_energy": "momentum_kernel"}
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_<workload>_counters.md), or None when there is none or
+    the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    h = re.search(r"source_sha256:\s*([0-9a-f]{64})\s+(\S+)", txt)
+    if not m or not h:
+        return None
+    src = os.path.join(ROOT, h.group(2))
+    if not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return float(m.group(1))
 
 
 def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=None) -> dict:
@@ -125,30 +182,46 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
     pairs = float(st.t["count"][: ic.n].sum().item())
     diag = st.diag
     return dict(ms_per_step=(t1 - t0) * 1e3 / steps, per_call_ms=per_call,
+                candidates=stencil_candidates(ic),
                 pairs_per_step=pairs, dt=st.dt, diag=diag.tolist(), diag0=diag0,
                 max_count=int(st.t["count"][: ic.n].max().item()),
                 scratch_bytes=ctx.scratch_bytes)
 
 
-def roofline(n: int, r: dict, precision: int) -> dict:
-    model = kernel_model(n, r["pairs_per_step"], precision)
+def roofline(n: int, r: dict, precision: int, workload: str | None = None) -> dict:
+    """Roofline of the dominant call's kernel (the call with the longest time
+    per launch): achieved = algorithmic bytes or flops per launch / measured
+    time per launch; bound = whichever of the two takes longer at peak."""
+    model = kernel_model(n, r["pairs_per_step"], r["candidates"], precision)
     dom = max(CALLS, key=lambda k: r["per_call_ms"][k])
     b, fl = model[dom]
     t = r["per_call_ms"][dom] * 1e-3
     gbs = b / t / 1e9
     tfl = fl / t / 1e12
     peak_fl = FP64_VECTOR_PEAK_TFLOPS if precision == 0 else FP32_VECTOR_PEAK_TFLOPS
-    hbm_frac = gbs / HBM_PEAK_GBS
-    alu_frac = tfl / peak_fl
-    if alu_frac > hbm_frac:
-        return dict(bound="alu", kernel=dom, achieved=round(tfl, 3), peak=peak_fl,
-                    unit="TFLOP/s", frac=round(alu_frac, 4), traffic=None,
-                    hbm_gbs=round(gbs, 1), hbm_frac=round(hbm_frac, 4),
-                    ms_per_launch=round(r["per_call_ms"][dom], 4))
-    return dict(bound="hbm", kernel=dom, achieved=round(gbs, 1), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(hbm_frac, 4), traffic=None,
-                alu_tflops=round(tfl, 3), alu_frac=round(alu_frac, 4),
-                ms_per_launch=round(r["per_call_ms"][dom], 4))
+    alu_bound = fl / (peak_fl * 1e12) > b / (HBM_PEAK_GBS * 1e9)
+    kern = KERNEL_OF_CALL.get(dom, dom)
+    traffic = recorded_traffic(kern, workload) if (workload and precision == 0) else None
+    out = dict(kernel=kern, call=dom, ms_per_launch=round(r["per_call_ms"][dom], 4),
+               algorithmic_bytes=b, algorithmic_flops=fl,
+               hbm_gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+               alu_tflops=round(tfl, 3), alu_frac=round(tfl / peak_fl, 4), traffic=traffic)
+    if alu_bound:
+        out.update(bound="alu", achieved=round(tfl, 3), peak=peak_fl, unit="TFLOP/s",
+                   frac=round(tfl / peak_fl, 4))
+    else:
+        out.update(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                   frac=round(gbs / HBM_PEAK_GBS, 4))
+    return out
+
+
+def step_hbm(n: int, r: dict, precision: int) -> dict:
+    """Whole-step algorithmic bytes against HBM peak."""
+    model = kernel_model(n, r["pairs_per_step"], r["candidates"], precision)
+    b = sum(v[0] for v in model.values())
+    gbs = b / (r["ms_per_step"] * 1e-3) / 1e9
+    return {"bytes_per_step": b, "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "ms_at_peak": b / (HBM_PEAK_GBS * 1e9) * 1e3}
 
 
 def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
@@ -203,6 +276,7 @@ def run_large(n_side: int, steps: int, warmup: int) -> dict:
                      "ms_per_step": res["ms_per_step"],
                      "per_call_ms": {k: round(v, 4) for k, v in res["per_call_ms"].items()},
                      "roofline": roofline(n, res, prec),
+                     "step_hbm": step_hbm(n, res, prec),
                      "drift": drift(res),
                      "mean_neighbours": res["pairs_per_step"] / n,
                      "scratch_bytes": res["scratch_bytes"]}
@@ -341,6 +415,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--evrard", action="store_true",
                     help="also time the 1,000,000-particle Evrard-like hydro step")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (a known-size "
+                         "reference for hardware byte counters)")
     ap.add_argument("--serve-runs", type=int, default=512,
                     help="ensemble serving requests (0 skips the serving leg)")
     ap.add_argument("--large", type=int, default=0, metavar="N_SIDE",
@@ -360,6 +437,12 @@ def main():
         from paper_1809_08013_amd import build
         build.build()
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ic = I.square_patch(args.n_side, seed=0)
     n = ic.n
     r64 = run_gpu(ic, S.SPH_FP64, args.steps, args.warmup)
@@ -388,7 +471,8 @@ def main():
             "max_neighbours": r64["max_count"],
         },
         "per_call_ms": {k: round(v, 4) for k, v in r64["per_call_ms"].items()},
-        "roofline": roofline(n, r64, 0),
+        "roofline": roofline(n, r64, 0, f"square_patch_{args.n_side}"),
+        "step_hbm": step_hbm(n, r64, 0),
         "drift": drift(r64),
     }
     if r32 is not None:
@@ -398,6 +482,7 @@ def main():
             "speedup_vs_fp64": r64["ms_per_step"] / r32["ms_per_step"],
             "per_call_ms": {k: round(v, 4) for k, v in r32["per_call_ms"].items()},
             "roofline": roofline(n, r32, 1),
+            "step_hbm": step_hbm(n, r32, 1),
         }
     if args.serve_runs > 0:
         line["serving"] = run_serving(args.serve_runs)

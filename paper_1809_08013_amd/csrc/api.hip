@@ -165,6 +165,7 @@ void free_ctx(sph_ctx ctx)
     void *ptrs[] = {ctx->keys[0], ctx->keys[1], ctx->vals[0], ctx->vals[1], ctx->hist,
                     ctx->scan_part, ctx->cell_start, ctx->cell_end, ctx->perm_tmp,
                     ctx->perm_tmp_id, ctx->red_part, ctx->status_dev, ctx->nb_mask, ctx->hflag_dev,
+                    ctx->fb_tiles, ctx->fb_count,
                     ctx->srec, ctx->drec, ctx->prec};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -242,6 +243,8 @@ sph_status sph_ctx_create(sph_ctx *out, int64_t n_max, int32_t max_nb, sph_strea
     ALLOC(ctx->cell_start, ctx->cell_cap);
     ALLOC(ctx->cell_end, ctx->cell_cap);
     ALLOC(ctx->nb_mask, (int64_t)kSearchMaskWords * ((n_max + 63) / 64) * 64);
+    ALLOC(ctx->fb_tiles, (n_max + 63) / 64);
+    ALLOC(ctx->fb_count, 1);
     ALLOC(ctx->srec, n_max);
     ALLOC(ctx->drec, n_max);
     ALLOC(ctx->prec, n_max);

@@ -1,24 +1,38 @@
 // Algorithm 1, step 2 on the GPU: the neighbour search.
 //
-// One wavefront per block of 64 consecutive particles (cell order). The
-// wave first builds, in LDS, the union of the 27-cell stencils of the cells
-// its particles live in: the non-empty cells, sorted by their first particle
-// and without duplicates, so walking them visits candidates in ascending
-// index order. It then streams that union wave-uniformly: each candidate's
-// record is one scalar load into SGPRs, every lane tests it against its own
-// particle with the exact FP64 relation, and the outcome goes into a per-lane
-// bit mask (one bit per union position, kept in a global scratch region so
-// that the wave's LDS footprint stays small and occupancy high; each 32-bit
-// word of 64 lanes is one 256-byte store). A second phase expands the
-// masks row by row, so that all lanes write row k of the ELL list together
-// (one contiguous 256-byte store per row) instead of scattering 4-byte
-// writes.
+// One wavefront per tile of 64 consecutive particles (cell order), four
+// independent wavefronts per block. The wave first builds, in its own LDS
+// region, the union of the 27-cell stencils of the cells its particles live
+// in: the non-empty cells, sorted by their first particle and without
+// duplicates, so walking them visits candidates in ascending index order. It
+// then streams that union wave-uniformly: each candidate's record is one
+// scalar load into SGPRs, every lane tests it against its own particle with
+// the exact FP64 relation, and the outcome goes into a per-lane bit mask (one
+// bit per union position, kept in a global scratch region so that the LDS
+// footprint stays small and occupancy high; each 32-bit word of 64 lanes is
+// one 256-byte store). A second phase expands the masks row by row, so that
+// all lanes write row k of the ELL list together (one contiguous 256-byte
+// store per row) instead of scattering 4-byte writes; a per-wave table maps
+// each union position to its cell, so a set bit becomes an index with two
+// LDS reads.
+//
+// Periodic axes: when no stencil of the tile reaches across a periodic
+// boundary the image test is skipped. Otherwise, when every periodic axis has
+// at least 5 cells, the image is chosen once per (union cell, lane) from the
+// cell indices: a true neighbour lies in an adjacent cell, and for adjacent
+// cells the wrapped ones are exactly those whose raw difference exceeds half
+// the box, so adding -L, 0 or +L to the raw difference reproduces the
+// minimum-image arithmetic (d -= L or d += L) for every true neighbour; for
+// any other candidate a wrong image only makes the distance larger than half
+// the box, i.e. larger than 2 h_max, and it is rejected either way. With
+// fewer cells the image is chosen per candidate.
 //
 // A wave whose union does not fit (many distinct cells, or more candidates
-// than the mask holds) takes the per-lane path instead: each lane walks its
-// own stencil and writes its entries directly. Both paths produce the same
-// set in the same (ascending) order, so the sums over a list do not depend on
-// the path or on where the wave boundaries fall.
+// than the mask holds), or whose particles belong to two runs of an
+// ensemble, takes the per-lane path instead: each lane walks its own stencil
+// (sorted by Morton key) and writes its entries directly. Both paths produce the same set in the
+// same (ascending) order, so the sums over a list do not depend on the path
+// or on where the tile boundaries fall.
 #include <algorithm>
 #include <climits>
 
@@ -28,9 +42,23 @@ namespace sph {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kMaxEntries = 128;        // 27 * distinct cells, before dedup
 constexpr int kMaxCandidates = kSearchMaskWords * 32;
 constexpr int kMaxWords = kSearchMaskWords;
+
+enum WrapMode { WRAP_NONE = 0, WRAP_CELL = 1, WRAP_PAIR = 2 };
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
 
 __device__ __forceinline__ uint32_t compact3(uint32_t v)
 {
@@ -40,6 +68,15 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v)
     v = (v | (v >> 8)) & 0x030000FFu;
     v = (v | (v >> 16)) & 0x000003FFu;
     return v;
+}
+
+// LDS operations of one wave complete in order; this only keeps the
+// compiler from moving them across the point (the wave's regions are its own).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Minimum image as a select chain: identical results to
@@ -60,14 +97,19 @@ __device__ __forceinline__ int wrap_or_clip(int c, int nc, int periodic, bool &o
     return c;
 }
 
-// Mode of the relation test. Any: r2 < (2h_i)^2 or r2 < (2h_j)^2, i.e.
-// r2 < (2 max(h_i, h_j))^2. Uniform: every particle has the same h, so the
-// test is one compare against the lane's own (2h)^2.
-template <bool Wrap, bool UniformH>
-__device__ __forceinline__ bool related(const SearchRec &me, const SearchRec &o, const Grid &g)
+// Relation test: r2 < (2h_i)^2 or r2 < (2h_j)^2, i.e. r2 < (2 max(h_i,h_j))^2.
+// UniformH: every particle has the same h, one compare against the lane's
+// own (2h)^2. sh: the per-cell image shift (WRAP_CELL).
+template <int Mode, bool UniformH>
+__device__ __forceinline__ bool related(const SearchRec &me, const SearchRec &o, const Grid &g,
+                                        const double (&sh)[3])
 {
     double dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
-    if (Wrap) {
+    if (Mode == WRAP_CELL) {
+        dx += sh[0];
+        dy += sh[1];
+        dz += sh[2];
+    } else if (Mode == WRAP_PAIR) {
         if (g.periodic[0]) dx = min_image_sel(dx, g.len[0], g.half[0]);
         if (g.periodic[1]) dy = min_image_sel(dy, g.len[1], g.half[1]);
         if (g.periodic[2]) dz = min_image_sel(dz, g.len[2], g.half[2]);
@@ -77,26 +119,48 @@ __device__ __forceinline__ bool related(const SearchRec &me, const SearchRec &o,
     return (r2 < me.s2) | (r2 < o.s2);
 }
 
+// Per-wave LDS. The position -> cell table is filled after the stream and
+// the self-bit removal, when the union-build arrays are no longer read, and
+// overlays them.
+struct SearchLds {
+    union {
+        struct {
+            uint32_t dkeys[kWave];
+            int2 ent[kMaxEntries];        // stencil entries {first particle, entry index}
+            int2 cells[kMaxEntries];      // union cells {first, end}, ascending
+            uint32_t cxyz[kMaxEntries];   // packed cell coordinates x | y << 10 | z << 20
+        };
+        uint8_t cellof[kMaxCandidates];   // union position -> union cell
+    };
+    int base[kMaxEntries];        // first particle minus first union position
+    int u0[kMaxEntries + 1];      // first union position of each cell
+};
+static_assert(kMaxCandidates <= 4 * kWave + 8 * kMaxEntries * 2 + 4 * kMaxEntries,
+              "the cell table overlays the union-build arrays");
+
 // Stream the union (cells[0..nu)) and record, for each candidate u, whether
 // it is related to the lane's particle. Masks are 32-bit words bm[word][lane]
 // (word = u / 32) filled from the top: candidate u sits at bit 31 - u % 32.
 // Within a cell the next four records are loaded while the current four are
 // tested, so the scalar-load latency is overlapped with work.
-template <bool Wrap, bool UniformH>
-__device__ __forceinline__ void stream_union(const SearchRec &me, const SearchRec *__restrict__ srec,
-                                             const int2 *cells, int nu, const Grid &g,
+template <int Mode, bool UniformH>
+__device__ __forceinline__ void stream_union(const SearchRec &me, const int (&myc)[3],
+                                             const SearchRec *__restrict__ srec,
+                                             const SearchLds &L, int nu, const Grid &g,
                                              uint32_t *__restrict__ bm, int lane, int &cnt,
-                                             uint64_t &occ)
+                                             uint64_t &occ0, uint32_t &occ1)
 {
     uint32_t acc = 0;
     int u = 0;
+    double sh[3] = {0.0, 0.0, 0.0};
     auto flush = [&](int w, uint32_t word) {
         bm[w * kWave + lane] = word;
         cnt += __popc(word);
-        occ |= word ? (1ull << w) : 0ull;
+        if (w < 64) occ0 |= word ? (1ull << w) : 0ull;
+        else occ1 |= word ? (1u << (w - 64)) : 0u;
     };
     auto step = [&](const SearchRec &o) {
-        acc = (acc << 1) | (related<Wrap, UniformH>(me, o, g) ? 1u : 0u);
+        acc = (acc << 1) | (related<Mode, UniformH>(me, o, g, sh) ? 1u : 0u);
         ++u;
         if ((u & 31) == 0) {
             flush((u >> 5) - 1, acc);
@@ -104,8 +168,17 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const SearchRe
         }
     };
     for (int c = 0; c < nu; ++c) {
-        const int s = __builtin_amdgcn_readfirstlane(cells[c].x);
-        const int e = __builtin_amdgcn_readfirstlane(cells[c].y);
+        const int s = __builtin_amdgcn_readfirstlane(L.cells[c].x);
+        const int e = __builtin_amdgcn_readfirstlane(L.cells[c].y);
+        if (Mode == WRAP_CELL) {
+            const uint32_t p = __builtin_amdgcn_readfirstlane(L.cxyz[c]);
+            const int cc[3] = {(int)(p & 1023u), (int)((p >> 10) & 1023u), (int)(p >> 20)};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int d = cc[a] - myc[a];
+                sh[a] = !g.periodic[a] ? 0.0 : (d >= 2 ? g.len[a] : (d <= -2 ? -g.len[a] : 0.0));
+            }
+        }
         int j = s;
         if (e - j >= 4) {
             SearchRec a0 = srec[j], a1 = srec[j + 1], a2 = srec[j + 2], a3 = srec[j + 3];
@@ -136,13 +209,6 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const SearchRe
     if (u & 31) flush(u >> 5, acc << (32 - (u & 31)));
 }
 
-struct SearchLds {
-    uint32_t dkeys[kWave];
-    int2 ent[kMaxEntries];
-    int2 cells[kMaxEntries];
-    int u0[kMaxEntries + 1];
-};
-
 // One tile of 64 particles. Multi: the particles belong to runs of an
 // ensemble (slot in the high key bits); a tile whose particles are all of one
 // run uses that run's grid and cell range, a tile spanning two runs takes the
@@ -153,14 +219,10 @@ __device__ __forceinline__ void search_tile(
     const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
     const int32_t *__restrict__ cend, const Grid &g0, int max_nb, int32_t *__restrict__ count,
     int32_t *__restrict__ idx, uint32_t *__restrict__ mask_scratch,
-    const uint32_t *__restrict__ hflag, uint32_t *status0, const BatchDev &b, SearchLds &L)
+    const uint32_t *__restrict__ hflag, uint32_t *status0, const BatchDev &b, SearchLds &L,
+    int32_t *__restrict__ fb_tiles, uint32_t *fb_count)
 {
-    uint32_t *dkeys = L.dkeys;
-    int2 *ent = L.ent;
-    int2 *cells = L.cells;
-    int *u0 = L.u0;
-
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
     const int64_t t0 = tile * kWave;
     uint32_t *bm = mask_scratch + tile * (kMaxWords * kWave);
     const int64_t i = t0 + lane;
@@ -184,40 +246,38 @@ __device__ __forceinline__ void search_tile(
     const bool first = active && (lane == 0 || key != prev);
     const uint64_t fm = __ballot(first);
     const int ndist = __popcll(fm);
-    if (first) dkeys[__popcll(fm & lt)] = mkey;
+    if (first) L.dkeys[__popcll(fm & lt)] = mkey;
 
-    // The minimum image can be skipped for the whole wave when, on every
+    // The image test can be skipped for the whole wave when, on every
     // periodic axis, the union of the stencils spans less than half the box:
-    // then |d| < L/2 for every candidate and the image test is a no-op.
-    const int cx = (int)compact3(mkey), cy = (int)compact3(mkey >> 1),
-              cz = (int)compact3(mkey >> 2);
-    bool wrap = false;
-    {
-        const int cc[3] = {cx, cy, cz};
+    // then |d| < L/2 for every candidate. Per-cell images need >= 5 cells.
+    const int myc[3] = {(int)compact3(mkey), (int)compact3(mkey >> 1),
+                        (int)compact3(mkey >> 2)};
+    bool wrap = false, few_cells = false;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (!g.periodic[a]) continue;
-            int mn = active ? cc[a] : INT_MAX, mx = active ? cc[a] : INT_MIN;
+    for (int a = 0; a < 3; ++a) {
+        if (!g.periodic[a]) continue;
+        int mn = active ? myc[a] : INT_MAX, mx = active ? myc[a] : INT_MIN;
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                mn = min(mn, __shfl_xor(mn, o, kWave));
-                mx = max(mx, __shfl_xor(mx, o, kWave));
-            }
-            // candidates lie in cells [mn - 1, mx + 1]: |d| < (mx - mn + 3) cells
-            if (mn < 1 || mx > g.nc[a] - 2 || 2 * (mx - mn + 3) >= g.nc[a]) wrap = true;
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = min(mn, __shfl_xor(mn, o, kWave));
+            mx = max(mx, __shfl_xor(mx, o, kWave));
         }
+        // candidates lie in cells [mn - 1, mx + 1]: |d| < (mx - mn + 3) cells
+        if (mn < 1 || mx > g.nc[a] - 2 || 2 * (mx - mn + 3) >= g.nc[a]) wrap = true;
+        if (g.nc[a] < 5) few_cells = true;
     }
 
     const int nent = ndist * kStencil;
     bool use_union = nent <= kMaxEntries && !mixed;
     int nu = 0, total = 0;
-    __syncthreads();
+    wave_sync();
     if (use_union) {
         // stencil cells of every distinct cell; empty ones become sentinels
         for (int e = lane; e < kMaxEntries; e += kWave) {
-            int2 v = make_int2(INT_MAX, INT_MAX);
+            int2 v = make_int2(INT_MAX, e);
             if (e < nent) {
-                const uint32_t k = dkeys[e / kStencil];
+                const uint32_t k = L.dkeys[e / kStencil];
                 const int s = e % kStencil;
                 bool okx, oky, okz;
                 const int x = wrap_or_clip((int)compact3(k) + s % 3 - 1, g.nc[0], g.periodic[0], okx);
@@ -228,43 +288,57 @@ __device__ __forceinline__ void search_tile(
                 if (okx && oky && okz) {
                     const int64_t cell = cbase + ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
                     const int a = cstart[cell], e2 = cend[cell];
-                    if (a < e2) v = make_int2(a, e2);
+                    if (a < e2) v = make_int2(a, e);
                 }
             }
-            ent[e] = v;
+            L.ent[e] = v;
         }
-        __syncthreads();
-        // bitonic sort of the 128 entries by start, one pair per lane per step
+        wave_sync();
+        // bitonic sort of the 128 entries by first particle, one pair per
+        // lane per step
         for (int k = 2; k <= kMaxEntries; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
                 const int lo_i = ((lane & ~(j - 1)) << 1) | (lane & (j - 1));
                 const int hi_i = lo_i | j;
-                const int2 ea = ent[lo_i], eb = ent[hi_i];
+                const int2 ea = L.ent[lo_i], eb = L.ent[hi_i];
                 const bool up = (lo_i & k) == 0;
                 if ((ea.x > eb.x) == up) {
-                    ent[lo_i] = eb;
-                    ent[hi_i] = ea;
+                    L.ent[lo_i] = eb;
+                    L.ent[hi_i] = ea;
                 }
-                __syncthreads();
+                wave_sync();
             }
         }
-        // drop sentinels and duplicates (a cell listed by several stencils)
-        int2 v0 = ent[lane], v1 = ent[lane + kWave];
-        const int p0 = lane == 0 ? INT_MIN : ent[lane - 1].x;
-        const int p1 = ent[lane + kWave - 1].x;
+        // drop sentinels and duplicates (a cell listed by several stencils);
+        // a kept entry's cell is recomputed from its entry index
+        const int2 v0 = L.ent[lane], v1 = L.ent[lane + kWave];
+        const int p0 = lane == 0 ? INT_MIN : L.ent[lane - 1].x;
+        const int p1 = L.ent[lane + kWave - 1].x;
         const bool k0 = v0.x != INT_MAX && v0.x != p0;
         const bool k1 = v1.x != INT_MAX && v1.x != p1;
         const uint64_t m0 = __ballot(k0), m1 = __ballot(k1);
         const int n0 = __popcll(m0);
         nu = n0 + __popcll(m1);
-        int pos0 = __popcll(m0 & lt), pos1 = n0 + __popcll(m1 & lt);
-        if (k0) cells[pos0] = v0;
-        if (k1) cells[pos1] = v1;
-        __syncthreads();
+        auto keep = [&](const int2 v, int pos) {
+            const uint32_t k = L.dkeys[v.y / kStencil];
+            const int s = v.y % kStencil;
+            bool ok;
+            const int x = wrap_or_clip((int)compact3(k) + s % 3 - 1, g.nc[0], g.periodic[0], ok);
+            const int y = wrap_or_clip((int)compact3(k >> 1) + (s / 3) % 3 - 1, g.nc[1],
+                                       g.periodic[1], ok);
+            const int z = wrap_or_clip((int)compact3(k >> 2) + s / 9 - 1, g.nc[2],
+                                       g.periodic[2], ok);
+            const int64_t cell = cbase + ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
+            L.cells[pos] = make_int2(v.x, cend[cell]);
+            L.cxyz[pos] = (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
+        };
+        if (k0) keep(v0, __popcll(m0 & lt));
+        if (k1) keep(v1, n0 + __popcll(m1 & lt));
+        wave_sync();
         // u0[c]: exclusive prefix of the cell lengths; lane holds c = lane and
         // c = lane + 64
-        const int l0 = lane < nu ? cells[lane].y - cells[lane].x : 0;
-        const int l1 = lane + kWave < nu ? cells[lane + kWave].y - cells[lane + kWave].x : 0;
+        const int l0 = lane < nu ? L.cells[lane].y - L.cells[lane].x : 0;
+        const int l1 = lane + kWave < nu ? L.cells[lane + kWave].y - L.cells[lane + kWave].x : 0;
         int s0 = l0, s1 = l1;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
@@ -276,81 +350,115 @@ __device__ __forceinline__ void search_tile(
         }
         const int tot0 = __shfl(s0, kWave - 1, kWave);
         total = tot0 + __shfl(s1, kWave - 1, kWave);
-        if (lane < nu) u0[lane] = s0 - l0;
-        if (lane + kWave < nu) u0[lane + kWave] = tot0 + s1 - l1;
-        if (lane == 0) u0[nu] = total;
+        if (lane < nu) {
+            L.u0[lane] = s0 - l0;
+            L.base[lane] = L.cells[lane].x - (s0 - l0);
+        }
+        if (lane + kWave < nu) {
+            L.u0[lane + kWave] = tot0 + s1 - l1;
+            L.base[lane + kWave] = L.cells[lane + kWave].x - (tot0 + s1 - l1);
+        }
+        if (lane == 0) L.u0[nu] = total;
         use_union = total <= kMaxCandidates;
-        __syncthreads();
+        wave_sync();
     }
 
     if (use_union) {
         const bool uniform_h = Multi ? b.runs[slot0].uniform_h != 0 : hflag[0] == 0;
+        const int mode = !wrap ? WRAP_NONE : (few_cells ? WRAP_PAIR : WRAP_CELL);
         int cnt = 0;
-        uint64_t occ = 0;  // bit w: mask word w has at least one bit for this lane
-        if (wrap) {
-            if (uniform_h) stream_union<true, true>(me, srec, cells, nu, g, bm, lane, cnt, occ);
-            else stream_union<true, false>(me, srec, cells, nu, g, bm, lane, cnt, occ);
+        uint64_t occ0 = 0;  // bit w: mask word w has at least one bit for this lane
+        uint32_t occ1 = 0;  // the same for words 64..
+#define SPH_STREAM(M, U) \
+    stream_union<M, U>(me, myc, srec, L, nu, g, bm, lane, cnt, occ0, occ1)
+        if (mode == WRAP_NONE) {
+            if (uniform_h) SPH_STREAM(WRAP_NONE, true); else SPH_STREAM(WRAP_NONE, false);
+        } else if (mode == WRAP_CELL) {
+            if (uniform_h) SPH_STREAM(WRAP_CELL, true); else SPH_STREAM(WRAP_CELL, false);
         } else {
-            if (uniform_h) stream_union<false, true>(me, srec, cells, nu, g, bm, lane, cnt, occ);
-            else stream_union<false, false>(me, srec, cells, nu, g, bm, lane, cnt, occ);
+            if (uniform_h) SPH_STREAM(WRAP_PAIR, true); else SPH_STREAM(WRAP_PAIR, false);
         }
+#undef SPH_STREAM
         // the lane's own particle is in the union: drop its bit
         if (active) {
             int lo = 0, hi = nu - 1;
             while (lo < hi) {  // last cell with start <= i
                 const int mid = (lo + hi + 1) >> 1;
-                if (cells[mid].x <= i) lo = mid; else hi = mid - 1;
+                if (L.cells[mid].x <= i) lo = mid; else hi = mid - 1;
             }
-            const int u_self = u0[lo] + (int)(i - cells[lo].x);
+            const int u_self = L.u0[lo] + (int)(i - L.cells[lo].x);
             const int ws = u_self >> 5;
             const uint32_t bit = 0x80000000u >> (u_self & 31);
             const uint32_t word = bm[ws * kWave + lane];
             if (word & bit) {
                 bm[ws * kWave + lane] = word & ~bit;
                 --cnt;
-                if ((word & ~bit) == 0) occ &= ~(1ull << ws);
+                if ((word & ~bit) == 0) {
+                    if (ws < 64) occ0 &= ~(1ull << ws);
+                    else occ1 &= ~(1u << (ws - 64));
+                }
             }
         } else {
             cnt = 0;
         }
+        wave_sync();
+        // union position -> union cell, for the expansion (overlays the
+        // union-build arrays, which are not read after this point)
+        for (int c = 0; c < nu; ++c) {
+            const int a = L.u0[c], e = L.u0[c + 1];
+            for (int uu = a + lane; uu < e; uu += kWave) L.cellof[uu] = (uint8_t)c;
+        }
+        wave_sync();
         int maxc = cnt;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, kWave));
         const int rows = min(maxc, max_nb);
         // Expand row by row: row k of every lane is written by one store. Each
         // lane walks its non-empty words (occ) with the next word already in
-        // flight, and keeps the current cell's bounds in registers.
+        // flight. Rows go out in chunks: the chunk's entries are formed in
+        // registers first, then stored together, so that a wait for a mask
+        // word (stores share its counter) waits for the previous chunk's
+        // stores once per chunk, not once per row.
         auto pop_word = [&]() -> int {
-            if (occ == 0) return -1;
-            const int w = __builtin_ctzll(occ);
-            occ &= occ - 1;
+            if (occ0 != 0) {
+                const int w = __builtin_ctzll(occ0);
+                occ0 &= occ0 - 1;
+                return w;
+            }
+            if (occ1 == 0) return -1;
+            const int w = 64 + __builtin_ctz(occ1);
+            occ1 &= occ1 - 1;
             return w;
         };
         int w_cur = pop_word();
         uint32_t cur = w_cur >= 0 ? bm[w_cur * kWave + lane] : 0u;
         int w_nxt = pop_word();
         uint32_t nxt = w_nxt >= 0 ? bm[w_nxt * kWave + lane] : 0u;
-        int cp = 0;
-        int c_start = cells[0].x, c_u0 = 0, c_end_u = u0[1];
-        for (int k = 0; k < rows; ++k) {
-            if (k < cnt) {
-                if (cur == 0) {
-                    cur = nxt;
-                    w_cur = w_nxt;
-                    w_nxt = pop_word();
-                    nxt = w_nxt >= 0 ? bm[w_nxt * kWave + lane] : 0u;
+        constexpr int kChunk = 16;
+        const int mine = min(cnt, max_nb);
+        for (int k0 = 0; k0 < rows; k0 += kChunk) {
+            int val[kChunk];
+#pragma unroll
+            for (int r = 0; r < kChunk; ++r) {
+                val[r] = 0;
+                if (k0 + r < mine) {
+                    if (cur == 0) {
+                        cur = nxt;
+                        w_cur = w_nxt;
+                        w_nxt = pop_word();
+                        nxt = w_nxt >= 0 ? bm[w_nxt * kWave + lane] : 0u;
+                    }
+                    const int t = __builtin_clz(cur);
+                    val[r] = w_cur * 32 + t;
+                    cur &= ~(0x80000000u >> t);
                 }
-                const int t = __builtin_clz(cur);
-                const int uu = w_cur * 32 + t;
-                cur &= ~(0x80000000u >> t);
-                while (uu >= c_end_u) {
-                    ++cp;
-                    c_start = cells[cp].x;
-                    c_u0 = c_end_u;
-                    c_end_u = u0[cp + 1];
-                }
-                idx[(int64_t)k * ld + i] = c_start + (uu - c_u0);
             }
+#pragma unroll
+            for (int r = 0; r < kChunk; ++r)
+                if (k0 + r < mine) val[r] += L.base[L.cellof[val[r]]];
+#pragma unroll
+            for (int r = 0; r < kChunk; ++r)
+                if (k0 + r < mine) idx[(int64_t)(k0 + r) * ld + i] = val[r];
         }
         if (active) {
             count[i] = cnt;
@@ -359,67 +467,123 @@ __device__ __forceinline__ void search_tile(
         return;
     }
 
-    // Per-lane path: the lane visits its own stencil's non-empty cells in
-    // ascending order of their first particle (selecting the next one each
-    // time), so its list is ascending too.
-    if (!active) return;
+    // The tile takes the per-lane path, in a kernel of its own (its
+    // registers would otherwise lower the occupancy of this one).
+    if (lane == 0) fb_tiles[atomicAdd(fb_count, 1u)] = (int32_t)tile;
+}
+
+// Per-lane path, one wave per listed tile: each lane visits its own
+// stencil's cells in ascending Morton order (= ascending order of their
+// particles): the 27 keys are sorted in registers, then each cell is walked
+// once with the next record already in flight, so the lane's list is
+// ascending too.
+template <bool Multi>
+__global__ void __launch_bounds__(kWave)
+fallback_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
+                const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
+                const int32_t *__restrict__ cend, Grid g0, int max_nb,
+                int32_t *__restrict__ count, int32_t *__restrict__ idx, uint32_t *status0,
+                BatchDev b, const int32_t *__restrict__ fb_tiles, const uint32_t *fb_count)
+{
+    const int lane = threadIdx.x;
+    if (Multi) n = b.hdr->n_out;
+    const uint32_t nfb = *fb_count;
+    for (uint32_t q = blockIdx.x; q < nfb; q += gridDim.x) {
+    const int64_t i = (int64_t)fb_tiles[q] * kWave + lane;
+    if (i >= n) continue;
+    const uint32_t key = keys[i];
+    const SearchRec me = srec[i];
+    const int my_slot = Multi ? (int)(key >> (3 * kEnsAxisBits)) : 0;
+    const uint32_t mkey = Multi ? (key & kEnsMortonMask) : key;
+    const int myc[3] = {(int)compact3(mkey), (int)compact3(mkey >> 1),
+                        (int)compact3(mkey >> 2)};
     const Grid &gl = Multi ? b.runs[my_slot].grid : g0;
     const int64_t cbl = Multi ? (int64_t)b.runs[my_slot].cell_base : 0;
-    int cnt = 0;
-    const int32_t ii = (int32_t)i;
-    int last = -1;
-    for (;;) {
-        int best_s = INT_MAX, best_e = 0;
-        for (int s = 0; s < kStencil; ++s) {
+    const double no_shift[3] = {0.0, 0.0, 0.0};
+    uint32_t ks[32];
+#pragma unroll
+    for (int s = 0; s < 32; ++s) {
+        ks[s] = 0xFFFFFFFFu;
+        if (s < kStencil) {
             bool okx, oky, okz;
-            const int x = wrap_or_clip(cx + s % 3 - 1, gl.nc[0], gl.periodic[0], okx);
-            const int y = wrap_or_clip(cy + (s / 3) % 3 - 1, gl.nc[1], gl.periodic[1], oky);
-            const int z = wrap_or_clip(cz + s / 9 - 1, gl.nc[2], gl.periodic[2], okz);
-            if (!(okx && oky && okz)) continue;
-            const int64_t cell = cbl + ((int64_t)z * gl.nc[1] + y) * gl.nc[0] + x;
-            const int a = cstart[cell], b = cend[cell];
-            if (a < b && a > last && a < best_s) {
-                best_s = a;
-                best_e = b;
+            const int x = wrap_or_clip(myc[0] + s % 3 - 1, gl.nc[0], gl.periodic[0], okx);
+            const int y = wrap_or_clip(myc[1] + (s / 3) % 3 - 1, gl.nc[1], gl.periodic[1], oky);
+            const int z = wrap_or_clip(myc[2] + s / 9 - 1, gl.nc[2], gl.periodic[2], okz);
+            if (okx && oky && okz)
+                ks[s] = spread3((uint32_t)x) | (spread3((uint32_t)y) << 1) |
+                        (spread3((uint32_t)z) << 2);
+        }
+    }
+    // bitonic sorting network over the 32 registers (indices are constants)
+#pragma unroll
+    for (int k = 2; k <= 32; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int t = 0; t < 32; ++t) {
+                const int p = t ^ j;
+                if (p > t) {
+                    const uint32_t lo = min(ks[t], ks[p]), hi = max(ks[t], ks[p]);
+                    const bool up = (t & k) == 0;
+                    ks[t] = up ? lo : hi;
+                    ks[p] = up ? hi : lo;
+                }
             }
         }
-        if (best_s == INT_MAX) break;
-        for (int32_t j = best_s; j < best_e; ++j) {
-            const SearchRec o = srec[j];
-            if (related<true, false>(me, o, gl) && j != ii) {
+    }
+    int cnt = 0;
+    const int32_t ii = (int32_t)i;
+    uint32_t prev_key = 0xFFFFFFFFu;
+#pragma unroll 1
+    for (int s = 0; s < kStencil; ++s) {
+        const uint32_t kc = ks[s];
+        if (kc == 0xFFFFFFFFu) break;
+        if (kc == prev_key) continue;  // a short periodic axis lists a cell twice
+        prev_key = kc;
+        const int x = (int)compact3(kc), y = (int)compact3(kc >> 1), z = (int)compact3(kc >> 2);
+        const int64_t cell = cbl + ((int64_t)z * gl.nc[1] + y) * gl.nc[0] + x;
+        const int a = cstart[cell], e = cend[cell];
+        if (a >= e) continue;
+        SearchRec nx = srec[a];
+        for (int32_t j = a; j < e; ++j) {
+            const SearchRec o = nx;
+            if (j + 1 < e) nx = srec[j + 1];
+            if (related<WRAP_PAIR, false>(me, o, gl, no_shift) && j != ii) {
                 if (cnt < max_nb) idx[(int64_t)cnt * ld + i] = j;
                 ++cnt;
             }
         }
-        last = best_s;
     }
     count[i] = cnt;
     if (cnt > max_nb) atomicOr(Multi ? &b.status[my_slot] : status0, ST_CAPACITY);
+    }
 }
 
+__global__ void clear_count_kernel(uint32_t *c) { *c = 0u; }
+
+
 template <bool Multi>
-__global__ void __launch_bounds__(kWave)
+__global__ void __launch_bounds__(kBlock)
 find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
                       const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
                       const int32_t *__restrict__ cend, Grid g, int max_nb,
                       int32_t *__restrict__ count, int32_t *__restrict__ idx,
                       uint32_t *__restrict__ mask_scratch, const uint32_t *__restrict__ hflag,
-                      uint32_t *status, BatchDev b)
+                      uint32_t *status, BatchDev b, int32_t *__restrict__ fb_tiles,
+                      uint32_t *fb_count)
 {
-    __shared__ SearchLds L;
-    if constexpr (Multi) {
-        const int64_t nn = b.hdr->n_out;
-        const int64_t ntile = (nn + kWave - 1) / kWave;
-        // the loop bound is wave-uniform, and each pass ends with the LDS
-        // reuse ordered by the block barriers inside the tile
-        for (int64_t tile = xcd_block(); tile < ntile; tile += gridDim.x) {
-            search_tile<true>(tile, nn, ld, srec, keys, cstart, cend, g, max_nb, count, idx,
-                              mask_scratch, hflag, status, b, L);
-            __syncthreads();
-        }
-    } else {
-        search_tile<false>(xcd_block(), n, ld, srec, keys, cstart, cend, g, max_nb, count, idx,
-                           mask_scratch, hflag, status, b, L);
+    __shared__ SearchLds lds[kWavesPerBlock];
+    const int w = threadIdx.x / kWave;
+    SearchLds &L = lds[w];
+    const int64_t nn = Multi ? b.hdr->n_out : n;
+    const int64_t ntile = (nn + kWave - 1) / kWave;
+    // the four waves of a block work on consecutive tiles, independently
+    for (int64_t tile = xcd_block() * kWavesPerBlock + w; tile < ntile;
+         tile += (int64_t)gridDim.x * kWavesPerBlock) {
+        search_tile<Multi>(tile, nn, ld, srec, keys, cstart, cend, g, max_nb, count, idx,
+                           mask_scratch, hflag, status, b, L, fb_tiles, fb_count);
+        wave_sync();
+        if (!Multi) break;
     }
 }
 
@@ -427,10 +591,17 @@ find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
 
 hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb)
 {
-    const unsigned blocks = (unsigned)((p.n + kWave - 1) / kWave);
-    find_neighbors_kernel<false><<<blocks, kWave, 0, ctx->stream>>>(
+    const int64_t tiles = (p.n + kWave - 1) / kWave;
+    const unsigned blocks = (unsigned)((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
+    clear_count_kernel<<<1, 1, 0, ctx->stream>>>(ctx->fb_count);
+    find_neighbors_kernel<false><<<blocks, kBlock, 0, ctx->stream>>>(
         p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
-        nb.max_nb, nb.count, nb.idx, ctx->nb_mask, ctx->hflag_dev, ctx->status_dev, BatchDev{});
+        nb.max_nb, nb.count, nb.idx, ctx->nb_mask, ctx->hflag_dev, ctx->status_dev, BatchDev{},
+        ctx->fb_tiles, ctx->fb_count);
+    const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, 2048);
+    fallback_kernel<false><<<fblocks, kWave, 0, ctx->stream>>>(
+        p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
+        nb.max_nb, nb.count, nb.idx, ctx->status_dev, BatchDev{}, ctx->fb_tiles, ctx->fb_count);
     return hipGetLastError();
 }
 
@@ -438,11 +609,17 @@ hipError_t launch_find_neighbors_batch(sph_ctx ctx, const BatchDev &b, int max_n
                                        int32_t *count, int32_t *idx)
 {
     // the mask scratch holds one region per tile of the capacity
-    const unsigned blocks =
-        (unsigned)std::min<int64_t>((b.cap + kWave - 1) / kWave, 16384);
-    find_neighbors_kernel<true><<<blocks, kWave, 0, ctx->stream>>>(
+    const int64_t tiles = (b.cap + kWave - 1) / kWave;
+    const unsigned blocks = (unsigned)std::min<int64_t>(
+        (tiles + kWavesPerBlock - 1) / kWavesPerBlock, 4096);
+    clear_count_kernel<<<1, 1, 0, ctx->stream>>>(ctx->fb_count);
+    find_neighbors_kernel<true><<<blocks, kBlock, 0, ctx->stream>>>(
         0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,
-        count, idx, ctx->nb_mask, nullptr, nullptr, b);
+        count, idx, ctx->nb_mask, nullptr, nullptr, b, ctx->fb_tiles, ctx->fb_count);
+    const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, 2048);
+    fallback_kernel<true><<<fblocks, kWave, 0, ctx->stream>>>(
+        0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,
+        count, idx, nullptr, b, ctx->fb_tiles, ctx->fb_count);
     return hipGetLastError();
 }
 

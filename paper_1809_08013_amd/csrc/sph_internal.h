@@ -116,7 +116,7 @@ struct BatchDev {
 };
 
 constexpr int kStencil = 27;
-constexpr int kSearchMaskWords = 64;  // per lane of a search wave: 2048 candidates
+constexpr int kSearchMaskWords = 88;  // per lane of a search wave: 2816 candidates
 
 // Neighbour-side records, one per particle in cell order, so that a
 // neighbour's data is one aligned block instead of one cache line per array.
@@ -166,6 +166,8 @@ struct sph_ctx_s {
     int32_t *cell_end = nullptr;
     int64_t cell_cap = 0;
     uint32_t *nb_mask = nullptr;     // search bit masks: kSearchMaskWords words per particle slot
+    int32_t *fb_tiles = nullptr;     // search tiles left to the per-lane path
+    uint32_t *fb_count = nullptr;
 
     sph::SearchRec *srec = nullptr;  // search records, cell order
     sph::DensRec *drec = nullptr;    // density records (written by sph_density)
