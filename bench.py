@@ -388,6 +388,54 @@ def run_serving(runs: int, steps: int = 50, budget_gib: float = 8.0) -> dict:
     return out
 
 
+def run_trajectory(n_side: int, steps: int) -> dict:
+    """Per-field error of the GPU runs (FP64 and FP32-pair) against the FP64
+    oracle after `steps` KDK steps from the same state (each path with its own
+    rho_ref = rho(t = 0)). Fields: positions, velocities, u, rho; max and RMS
+    absolute errors, scaled by the field's RMS; totals drift from the FP64
+    on-device reductions."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1809_08013_amd import inputs as I
+    from paper_1809_08013_amd import sph as S
+    ic = I.square_patch(n_side, seed=0)
+    log(f"trajectory: oracle {steps} steps, n={ic.n}")
+    t0 = time.perf_counter()
+    ref = O.OracleRun(ic).init()
+    for _ in range(steps):
+        ref.step()
+    t_cpu = time.perf_counter() - t0
+    refs = dict(ref.s)
+    refs["rho"] = ref.rho
+    out = {"workload": f"rotating square patch {n_side}^3, {steps} steps", "steps": steps,
+           "oracle_seconds": t_cpu}
+    for name, prec in (("fp64", S.SPH_FP64), ("fp32_pair", S.SPH_FP32_PAIR)):
+        log(f"trajectory: GPU {name}")
+        ctx = S.Context(ic.n, 128)
+        st = S.SphState(ic, 128)
+        prm = S.make_params(ic.params, prec)
+        S.sph_init_forces(ctx, st, prm, set_rho_ref=True)
+        d0 = st.diag.copy()
+        for _ in range(steps):
+            S.sph_step(ctx, st, prm)
+        S.sph_ctx_check(ctx)
+        got = st.host(["x", "y", "z", "vx", "vy", "vz", "u", "rho"])
+        d1 = st.diag
+        err = {}
+        for k in ("x", "y", "z", "vx", "vy", "vz", "u", "rho"):
+            d = got[k] - refs[k]
+            scale = float(np.sqrt(np.mean(refs[k] ** 2))) or 1.0
+            err[k] = {"max_abs": float(np.max(np.abs(d))), "rms_abs": float(np.sqrt(np.mean(d * d))),
+                      "max_rel_to_rms": float(np.max(np.abs(d))) / scale}
+        out[name] = {"errors": err, "dt_rel": abs(st.dt - ref.dt) / ref.dt,
+                     "energy_drift": abs(d1[7] - d0[7]) / abs(d0[7]),
+                     "lz_drift": abs(d1[6] - d0[6]) / abs(d0[6]),
+                     "px_drift_abs": abs(d1[1] - d0[1]), "py_drift_abs": abs(d1[2] - d0[2])}
+        del ctx, st
+    return out
+
+
 def cpu_baseline(ic, steps: int) -> dict:
     import oracle as O
     log(f"CPU oracle baseline, {steps} steps")
@@ -418,6 +466,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a known-size "
                          "reference for hardware byte counters)")
+    ap.add_argument("--trajectory", type=int, default=0, metavar="STEPS",
+                    help="also compare FP64 and FP32-pair GPU runs with the oracle after "
+                         "STEPS steps on the same patch")
     ap.add_argument("--serve-runs", type=int, default=512,
                     help="ensemble serving requests (0 skips the serving leg)")
     ap.add_argument("--large", type=int, default=0, metavar="N_SIDE",
@@ -484,6 +535,8 @@ def main():
             "roofline": roofline(n, r32, 1),
             "step_hbm": step_hbm(n, r32, 1),
         }
+    if args.trajectory > 0:
+        line["trajectory"] = run_trajectory(args.n_side, args.trajectory)
     if args.serve_runs > 0:
         line["serving"] = run_serving(args.serve_runs)
     if args.evrard:

@@ -335,3 +335,46 @@ def test_trajectory_conserves_momentum_and_energy():
     assert abs(d1[1] - d0[1]) < 1e-15 and abs(d1[2] - d0[2]) < 1e-15
     assert abs(d1[6] - d0[6]) < 1e-13
     assert abs(d1[7] - d0[7]) / d0[7] < 1e-4
+
+
+# ------------------------------------------------------- gravity (Evrard) --
+def test_gravity_direct_closed_forms():
+    """Plummer-softened direct sum used for the Evrard external field:
+    two bodies against the closed form (sign and magnitude), pairwise
+    antisymmetry (sum m g = 0), the far field of a compact cluster against
+    the monopole -M r / r^3, and the shell theorem inside a thin shell."""
+    eps = 0.01
+    # two bodies
+    x, y, z = np.array([0.1, -0.2]), np.array([0.3, 0.0]), np.array([0.0, 0.4])
+    m = np.array([2.0, 3.0])
+    gx, gy, gz = O.gravity_direct(x, y, z, m, eps=eps)
+    d = np.array([x[0] - x[1], y[0] - y[1], z[0] - z[1]])
+    f = -m[1] * d / (d @ d + eps * eps) ** 1.5
+    assert np.allclose([gx[0], gy[0], gz[0]], f, rtol=1e-14, atol=0)
+    assert np.allclose([gx[1], gy[1], gz[1]], -f * m[0] / m[1], rtol=1e-14, atol=0)
+    # antisymmetry over a random cloud
+    rng = np.random.default_rng(7)
+    P = rng.normal(size=(300, 3))
+    mm = rng.uniform(0.5, 1.5, 300)
+    gx, gy, gz = O.gravity_direct(P[:, 0], P[:, 1], P[:, 2], mm, eps=eps)
+    tot = np.array([np.sum(mm * gx), np.sum(mm * gy), np.sum(mm * gz)])
+    scale = np.sum(mm * np.sqrt(gx * gx + gy * gy + gz * gz))
+    assert np.max(np.abs(tot)) < 1e-13 * scale
+    # far field of a compact cluster plus one distant probe of negligible mass
+    C = rng.uniform(-0.05, 0.05, size=(200, 3))
+    mc = np.full(200, 1.0 / 200)
+    probe = np.array([[3.0, -1.0, 2.0]])
+    Q = np.vstack([C, probe])
+    mq = np.concatenate([mc, [1e-30]])
+    gx, gy, gz = O.gravity_direct(Q[:, 0], Q[:, 1], Q[:, 2], mq, eps=eps)
+    com = (mc[:, None] * C).sum(0)
+    r = probe[0] - com
+    mono = -1.0 * r / np.linalg.norm(r) ** 3
+    assert np.allclose([gx[-1], gy[-1], gz[-1]], mono, rtol=2e-3)
+    # shell theorem: inside a thin uniform shell the field nearly vanishes
+    u = rng.normal(size=(20000, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    S = np.vstack([u, [[0.2, 0.1, -0.1]]])
+    ms = np.concatenate([np.full(20000, 1.0 / 20000), [1e-30]])
+    gx, gy, gz = O.gravity_direct(S[:, 0], S[:, 1], S[:, 2], ms, eps=eps)
+    assert math.sqrt(gx[-1] ** 2 + gy[-1] ** 2 + gz[-1] ** 2) < 0.02
