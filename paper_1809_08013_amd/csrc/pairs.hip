@@ -75,24 +75,38 @@ __device__ __forceinline__ R fast_sqrt(R x)
 }
 
 // M4 spline shape w(q) and slope w'(q).
+// (2 - q) is clamped at 0, so the outer piece is zero beyond the support and
+// one select suffices.
 template <typename R>
 __device__ __forceinline__ R m4_w(R q)
 {
-    const R one = R(1), two = R(2);
-    R t = two - q;
-    R inner = one + q * q * (R(-1.5) + R(0.75) * q);
-    R outer = R(0.25) * t * t * t;
-    return q < one ? inner : (q < two ? outer : R(0));
+    const R one = R(1);
+    const R t = fmax(R(2) - q, R(0));
+    const R inner = one + q * q * (R(-1.5) + R(0.75) * q);
+    const R outer = R(0.25) * t * t * t;
+    return q < one ? inner : outer;
 }
 
 template <typename R>
 __device__ __forceinline__ R m4_dw(R q)
 {
-    const R one = R(1), two = R(2);
-    R t = two - q;
-    R inner = q * (R(-3) + R(2.25) * q);
-    R outer = R(-0.75) * t * t;
-    return q < one ? inner : (q < two ? outer : R(0));
+    const R one = R(1);
+    const R t = fmax(R(2) - q, R(0));
+    const R inner = q * (R(-3) + R(2.25) * q);
+    const R outer = R(-0.75) * t * t;
+    return q < one ? inner : outer;
+}
+
+// 16 bytes at byte c of record j of an array of Size-byte records. Arrays
+// below 4 GiB use a 32-bit offset from the uniform base (the load then takes
+// the base from SGPRs and needs no 64-bit address arithmetic).
+template <bool Big, int Size>
+__device__ __forceinline__ double2 rec_chunk(const char *__restrict__ base, int j, uint32_t c)
+{
+    if constexpr (Big)
+        return *reinterpret_cast<const double2 *>(base + (int64_t)j * Size + c);
+    else
+        return *reinterpret_cast<const double2 *>(base + ((uint32_t)j * (uint32_t)Size + c));
 }
 
 // ---------------------------------------------------------------------------
@@ -154,7 +168,7 @@ __device__ __forceinline__ double img(double d, const Img &m, int a)
     return min_image(d, m.per[a], m.len[a], m.half[a]);
 }
 
-template <bool F32, bool Multi>
+template <bool F32, bool Multi, bool Big>
 __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld,
                                              const DensRec *__restrict__ drec,
                                              const double *__restrict__ h,
@@ -177,7 +191,8 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, 64));
     const int s = lane & 1;
-    const char *src_base = reinterpret_cast<const char *>(drec) + 16 * s;
+    const char *src_base = reinterpret_cast<const char *>(drec);
+    const uint32_t chunk = 16u * (uint32_t)s;
     char *dst_own = buf + lane * kDensStride;
     char *dst_a = buf + (lane & ~1) * kDensStride + 16 * s;
     // Software pipelined: the chunks of step k + 1 are loaded while step k is
@@ -185,8 +200,8 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
     auto fetch = [&](int jk, double2 &a, double2 &b) {
         const int jp = __shfl_xor(jk, 1, 64);
         const int j0 = s == 0 ? jk : jp, j1 = s == 0 ? jp : jk;
-        a = *reinterpret_cast<const double2 *>(src_base + (int64_t)j0 * sizeof(DensRec));
-        b = *reinterpret_cast<const double2 *>(src_base + (int64_t)j1 * sizeof(DensRec));
+        a = rec_chunk<Big, (int)sizeof(DensRec)>(src_base, j0, chunk);
+        b = rec_chunk<Big, (int)sizeof(DensRec)>(src_base, j1, chunk);
     };
     double2 c0, c1;
     int jn = cnt > 1 ? idx[ld + ii] : (int)ii;
@@ -213,7 +228,7 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
     if (active) rho[i] = (double)(sum * ((R)kInvPi * inv_h * inv_h * inv_h));
 }
 
-template <bool F32, bool Multi>
+template <bool F32, bool Multi, bool Big>
 __global__ void __launch_bounds__(kThreads)
 density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
                const double *__restrict__ h, const int32_t *__restrict__ count,
@@ -226,10 +241,10 @@ density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
         const int64_t nn = b.hdr->n_out;
         const int64_t ntile = (nn + kThreads - 1) / kThreads;
         for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
-            density_tile<F32, true>(t, nn, ld, drec, h, count, idx, max_nb, g, rho, b, buf);
+            density_tile<F32, true, Big>(t, nn, ld, drec, h, count, idx, max_nb, g, rho, b, buf);
     } else {
-        density_tile<F32, false>(xcd_block(), n, ld, drec, h, count, idx, max_nb, g, rho, b,
-                                 buf);
+        density_tile<F32, false, Big>(xcd_block(), n, ld, drec, h, count, idx, max_nb, g, rho,
+                                      b, buf);
     }
 }
 
@@ -283,7 +298,7 @@ struct MomParams {
     double alpha, beta, eta2;
 };
 
-template <bool F32, bool Multi>
+template <bool F32, bool Multi, bool Big>
 __device__ __forceinline__ void momentum_tile(
     int64_t tile, int64_t n, int64_t ld, const PairRec *__restrict__ rec,
     const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
@@ -316,14 +331,14 @@ __device__ __forceinline__ void momentum_tile(
     for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, 64));
     const int grp = lane & ~7, s = lane & 7;
     const bool loader = s < 6;
-    const char *src_base = reinterpret_cast<const char *>(rec) + 16 * (loader ? s : 0);
+    const char *src_base = reinterpret_cast<const char *>(rec);
+    const uint32_t chunk = 16u * (uint32_t)(loader ? s : 0);
     const char *own = buf + lane * kMomStride;
     char *dst = buf + grp * kMomStride + 16 * s;
     // Software pipelined: the chunks of step k + 1 are loaded into registers
     // (c0..c7) while step k is computed from LDS.
 #define SPH_FETCH(t, jk)                                                                   \
-    c##t = *reinterpret_cast<const double2 *>(                                             \
-        src_base + (int64_t)__shfl((jk), grp + (t), 64) * (int64_t)sizeof(PairRec))
+    c##t = rec_chunk<Big, (int)sizeof(PairRec)>(src_base, __shfl((jk), grp + (t), 64), chunk)
 #define SPH_FETCH_ALL(jk)                                                                  \
     SPH_FETCH(0, jk); SPH_FETCH(1, jk); SPH_FETCH(2, jk); SPH_FETCH(3, jk);                \
     SPH_FETCH(4, jk); SPH_FETCH(5, jk); SPH_FETCH(6, jk); SPH_FETCH(7, jk)
@@ -397,7 +412,7 @@ __device__ __forceinline__ void momentum_tile(
     }
 }
 
-template <bool F32, bool Multi>
+template <bool F32, bool Multi, bool Big>
 __global__ void __launch_bounds__(kThreads)
 momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
                 const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
@@ -411,11 +426,11 @@ momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
         const int64_t nn = b.hdr->n_out;
         const int64_t ntile = (nn + kThreads - 1) / kThreads;
         for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
-            momentum_tile<F32, true>(t, nn, ld, rec, count, idx, max_nb, g, prm, ax, ay, az,
-                                     dudt, mumax, b, buf);
+            momentum_tile<F32, true, Big>(t, nn, ld, rec, count, idx, max_nb, g, prm, ax, ay,
+                                          az, dudt, mumax, b, buf);
     } else {
-        momentum_tile<F32, false>(xcd_block(), n, ld, rec, count, idx, max_nb, g, prm, ax, ay,
-                                  az, dudt, mumax, b, buf);
+        momentum_tile<F32, false, Big>(xcd_block(), n, ld, rec, count, idx, max_nb, g, prm, ax,
+                                       ay, az, dudt, mumax, b, buf);
     }
 }
 
@@ -478,6 +493,43 @@ eos_batch_kernel(BatchDev b, const double *__restrict__ rho, const double *__res
     }
 }
 
+// Record arrays of 4 GiB or more need 64-bit element offsets.
+inline bool big_records(int64_t n, size_t rec) { return (uint64_t)n * rec >= (1ull << 32); }
+
+template <bool Multi>
+void density_launch(hipStream_t st, unsigned blocks, int precision, bool big, int64_t n,
+                    int64_t ld, const DensRec *drec, const double *h, const int32_t *count,
+                    const int32_t *idx, int max_nb, const Grid &g, double *rho, const BatchDev &b)
+{
+#define SPH_DENS(F, B)                                                                     \
+    density_kernel<F, Multi, B><<<blocks, kThreads, 0, st>>>(n, ld, drec, h, count, idx,  \
+                                                             max_nb, g, rho, b)
+    if (precision == SPH_FP32_PAIR) {
+        if (big) SPH_DENS(true, true); else SPH_DENS(true, false);
+    } else {
+        if (big) SPH_DENS(false, true); else SPH_DENS(false, false);
+    }
+#undef SPH_DENS
+}
+
+template <bool Multi>
+void momentum_launch(hipStream_t st, unsigned blocks, int precision, bool big, int64_t n,
+                     int64_t ld, const PairRec *rec, const int32_t *count, const int32_t *idx,
+                     int max_nb, const Grid &g, const MomParams &mp, double *ax, double *ay,
+                     double *az, double *dudt, double *mumax, const BatchDev &b)
+{
+#define SPH_MOM(F, B)                                                                      \
+    momentum_kernel<F, Multi, B><<<blocks, kThreads, 0, st>>>(n, ld, rec, count, idx,     \
+                                                              max_nb, g, mp, ax, ay, az,   \
+                                                              dudt, mumax, b)
+    if (precision == SPH_FP32_PAIR) {
+        if (big) SPH_MOM(true, true); else SPH_MOM(true, false);
+    } else {
+        if (big) SPH_MOM(false, true); else SPH_MOM(false, false);
+    }
+#undef SPH_MOM
+}
+
 }  // namespace
 
 hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
@@ -486,12 +538,9 @@ hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &n
     const unsigned nblk = blocks_for(p.n, kThreads);
     pack_dens_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, nullptr, p.x, p.y,
                                                                     p.z, p.m, ctx->drec);
-    if (precision == SPH_FP32_PAIR)
-        density_kernel<true, false><<<nblk, kThreads, 0, ctx->stream>>>(
-            p.n, p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho, BatchDev{});
-    else
-        density_kernel<false, false><<<nblk, kThreads, 0, ctx->stream>>>(
-            p.n, p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho, BatchDev{});
+    density_launch<false>(ctx->stream, nblk, precision, big_records(p.n, sizeof(DensRec)), p.n,
+                          p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho,
+                          BatchDev{});
     return hipGetLastError();
 }
 
@@ -511,14 +560,9 @@ hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &
     const MomParams mp{prm.alpha, prm.beta, prm.eta2};
     pack_pair_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
         p.n, nullptr, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2, ctx->prec);
-    if (prm.precision == SPH_FP32_PAIR)
-        momentum_kernel<true, false><<<nblk, kThreads, 0, ctx->stream>>>(
-            p.n, p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp, a.ax, a.ay, a.az,
-            a.dudt, a.mumax, BatchDev{});
-    else
-        momentum_kernel<false, false><<<nblk, kThreads, 0, ctx->stream>>>(
-            p.n, p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp, a.ax, a.ay, a.az,
-            a.dudt, a.mumax, BatchDev{});
+    momentum_launch<false>(ctx->stream, nblk, prm.precision, big_records(p.n, sizeof(PairRec)),
+                           p.n, p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp,
+                           a.ax, a.ay, a.az, a.dudt, a.mumax, BatchDev{});
     return hipGetLastError();
 }
 
@@ -534,12 +578,8 @@ hipError_t launch_density_batch(sph_ctx ctx, const BatchDev &b, int precision, c
     const unsigned g2 = std::min<unsigned>(blocks_for(cap, kThreads), 4096u);
     pack_dens_kernel<<<g1, 256, 0, ctx->stream>>>(0, n_out, F + 0 * cap, F + 1 * cap,
                                                   F + 2 * cap, F + 8 * cap, ctx->drec);
-    if (precision == SPH_FP32_PAIR)
-        density_kernel<true, true><<<g2, kThreads, 0, ctx->stream>>>(
-            0, cap, ctx->drec, F + 7 * cap, count, idx, max_nb, Grid{}, rho, b);
-    else
-        density_kernel<false, true><<<g2, kThreads, 0, ctx->stream>>>(
-            0, cap, ctx->drec, F + 7 * cap, count, idx, max_nb, Grid{}, rho, b);
+    density_launch<true>(ctx->stream, g2, precision, big_records(cap, sizeof(DensRec)), 0, cap,
+                         ctx->drec, F + 7 * cap, count, idx, max_nb, Grid{}, rho, b);
     return hipGetLastError();
 }
 
@@ -567,14 +607,9 @@ hipError_t launch_momentum_batch(sph_ctx ctx, const BatchDev &b, int precision,
                                                   F + 2 * cap, F + 3 * cap, F + 4 * cap,
                                                   F + 5 * cap, F + 7 * cap, F + 8 * cap, rho, c,
                                                   pr2, ctx->prec);
-    if (precision == SPH_FP32_PAIR)
-        momentum_kernel<true, true><<<g2, kThreads, 0, ctx->stream>>>(
-            0, cap, ctx->prec, count, idx, max_nb, Grid{}, MomParams{}, ax, ay, az, dudt, mumax,
-            b);
-    else
-        momentum_kernel<false, true><<<g2, kThreads, 0, ctx->stream>>>(
-            0, cap, ctx->prec, count, idx, max_nb, Grid{}, MomParams{}, ax, ay, az, dudt, mumax,
-            b);
+    momentum_launch<true>(ctx->stream, g2, precision, big_records(cap, sizeof(PairRec)), 0, cap,
+                          ctx->prec, count, idx, max_nb, Grid{}, MomParams{}, ax, ay, az, dudt,
+                          mumax, b);
     return hipGetLastError();
 }
 
