@@ -27,10 +27,11 @@
 // the box, i.e. larger than 2 h_max, and it is rejected either way. With
 // fewer cells the image is chosen per candidate.
 //
-// A wave whose union does not fit (many distinct cells, or more candidates
-// than the mask holds), or whose particles belong to two runs of an
-// ensemble, takes the per-lane path instead: each lane walks its own stencil
-// (sorted by Morton key) and writes its entries directly. Both paths produce the same set in the
+// A wave whose union has more candidates than the masks hold (dense cells)
+// streams the same union but lets each lane append its accepted candidates
+// directly. A wave with too many distinct cells, or whose particles belong to
+// two runs of an ensemble, takes the per-lane path instead: each lane walks
+// its own stencil (sorted by Morton key) and writes its entries directly. Both paths produce the same set in the
 // same (ascending) order, so the sums over a list do not depend on the path
 // or on where the tile boundaries fall.
 #include <algorithm>
@@ -209,6 +210,66 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const int (&my
     if (u & 31) flush(u >> 5, acc << (32 - (u & 31)));
 }
 
+// Stream a union too large for the masks (dense cells): the same
+// wave-uniform walk, each lane appending its accepted candidates to its own
+// list as it goes (few candidates pass, so the scattered stores are rare).
+template <int Mode, bool UniformH>
+__device__ __forceinline__ int stream_direct(const SearchRec &me, const int (&myc)[3],
+                                             const SearchRec *__restrict__ srec,
+                                             const int2 *__restrict__ cells,
+                                             const uint32_t *__restrict__ cxyz, int nu,
+                                             const Grid &g, bool active, int64_t i, int64_t ld,
+                                             int max_nb, int32_t *__restrict__ idx)
+{
+    int cnt = 0;
+    double sh[3] = {0.0, 0.0, 0.0};
+    const int32_t ii = active ? (int32_t)i : -1;
+    auto step = [&](const SearchRec &o, int32_t j) {
+        if (related<Mode, UniformH>(me, o, g, sh) && j != ii && active) {
+            if (cnt < max_nb) idx[(int64_t)cnt * ld + i] = j;
+            ++cnt;
+        }
+    };
+    for (int c = 0; c < nu; ++c) {
+        const int s = __builtin_amdgcn_readfirstlane(cells[c].x);
+        const int e = __builtin_amdgcn_readfirstlane(cells[c].y);
+        if (Mode == WRAP_CELL) {
+            const uint32_t p = __builtin_amdgcn_readfirstlane(cxyz[c]);
+            const int cc[3] = {(int)(p & 1023u), (int)((p >> 10) & 1023u), (int)(p >> 20)};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int d = cc[a] - myc[a];
+                sh[a] = !g.periodic[a] ? 0.0 : (d >= 2 ? g.len[a] : (d <= -2 ? -g.len[a] : 0.0));
+            }
+        }
+        int j = s;
+        if (e - j >= 4) {
+            SearchRec a0 = srec[j], a1 = srec[j + 1], a2 = srec[j + 2], a3 = srec[j + 3];
+            j += 4;
+            while (e - j >= 4) {
+                const SearchRec b0 = srec[j], b1 = srec[j + 1], b2 = srec[j + 2],
+                                b3 = srec[j + 3];
+                step(a0, j - 4);
+                step(a1, j - 3);
+                step(a2, j - 2);
+                step(a3, j - 1);
+                __builtin_amdgcn_sched_barrier(0);
+                a0 = b0;
+                a1 = b1;
+                a2 = b2;
+                a3 = b3;
+                j += 4;
+            }
+            step(a0, j - 4);
+            step(a1, j - 3);
+            step(a2, j - 2);
+            step(a3, j - 1);
+        }
+        for (; j < e; ++j) step(srec[j], j);
+    }
+    return cnt;
+}
+
 // One tile of 64 particles. Multi: the particles belong to runs of an
 // ensemble (slot in the high key bits); a tile whose particles are all of one
 // run uses that run's grid and cell range, a tile spanning two runs takes the
@@ -359,8 +420,23 @@ __device__ __forceinline__ void search_tile(
             L.base[lane + kWave] = L.cells[lane + kWave].x - (tot0 + s1 - l1);
         }
         if (lane == 0) L.u0[nu] = total;
-        use_union = total <= kMaxCandidates;
         wave_sync();
+        if (total > kMaxCandidates) {
+            // Too large for the masks: the second kernel walks the same union,
+            // read from this tile's scratch region (cells, then coordinates,
+            // then the count), with each lane appending directly.
+            int2 *gc = reinterpret_cast<int2 *>(bm);
+            uint32_t *gx = bm + 2 * kMaxEntries;
+            for (int c = lane; c < nu; c += kWave) {
+                gc[c] = L.cells[c];
+                gx[c] = L.cxyz[c];
+            }
+            if (lane == 0) {
+                bm[3 * kMaxEntries] = (uint32_t)nu;
+                fb_tiles[atomicAdd(fb_count, 1u)] = (int32_t)(0x80000000u | (uint32_t)tile);
+            }
+            return;
+        }
     }
 
     if (use_union) {
@@ -483,20 +559,60 @@ fallback_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
                 const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
                 const int32_t *__restrict__ cend, Grid g0, int max_nb,
                 int32_t *__restrict__ count, int32_t *__restrict__ idx, uint32_t *status0,
-                BatchDev b, const int32_t *__restrict__ fb_tiles, const uint32_t *fb_count)
+                BatchDev b, const int32_t *__restrict__ fb_tiles, const uint32_t *fb_count,
+                const uint32_t *__restrict__ mask_scratch, const uint32_t *__restrict__ hflag)
 {
     const int lane = threadIdx.x;
     if (Multi) n = b.hdr->n_out;
     const uint32_t nfb = *fb_count;
     for (uint32_t q = blockIdx.x; q < nfb; q += gridDim.x) {
-    const int64_t i = (int64_t)fb_tiles[q] * kWave + lane;
-    if (i >= n) continue;
-    const uint32_t key = keys[i];
-    const SearchRec me = srec[i];
-    const int my_slot = Multi ? (int)(key >> (3 * kEnsAxisBits)) : 0;
+    const uint32_t entry = (uint32_t)fb_tiles[q];
+    const int64_t tile = (int64_t)(entry & 0x7FFFFFFFu);
+    const int64_t i = tile * kWave + lane;
+    const bool active = i < n;
+    const uint32_t key = active ? keys[i] : 0xFFFFFFFFu;
+    const SearchRec me = active ? srec[i] : SearchRec{0.0, 0.0, 0.0, 0.0};
+    const int my_slot = Multi && active ? (int)(key >> (3 * kEnsAxisBits)) : 0;
     const uint32_t mkey = Multi ? (key & kEnsMortonMask) : key;
     const int myc[3] = {(int)compact3(mkey), (int)compact3(mkey >> 1),
                         (int)compact3(mkey >> 2)};
+    if (entry & 0x80000000u) {
+        // a union too large for the masks (its particles are of one run)
+        const uint32_t *bm = mask_scratch + tile * (kMaxWords * kWave);
+        const int nu = (int)__builtin_amdgcn_readfirstlane(bm[3 * kMaxEntries]);
+        const int slot0 = __builtin_amdgcn_readfirstlane(my_slot);
+        const Grid &g = Multi ? b.runs[slot0].grid : g0;
+        bool wrap = false, few_cells = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (!g.periodic[a]) continue;
+            int mn = active ? myc[a] : INT_MAX, mx = active ? myc[a] : INT_MIN;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                mn = min(mn, __shfl_xor(mn, o, kWave));
+                mx = max(mx, __shfl_xor(mx, o, kWave));
+            }
+            if (mn < 1 || mx > g.nc[a] - 2 || 2 * (mx - mn + 3) >= g.nc[a]) wrap = true;
+            if (g.nc[a] < 5) few_cells = true;
+        }
+        const bool uniform_h = Multi ? b.runs[slot0].uniform_h != 0 : hflag[0] == 0;
+        const int mode = !wrap ? WRAP_NONE : (few_cells ? WRAP_PAIR : WRAP_CELL);
+        const int2 *gc = reinterpret_cast<const int2 *>(bm);
+        const uint32_t *gx = bm + 2 * kMaxEntries;
+        int cnt;
+#define SPH_DIRECT(M, U) \
+    stream_direct<M, U>(me, myc, srec, gc, gx, nu, g, active, i, ld, max_nb, idx)
+        if (mode == WRAP_NONE) cnt = uniform_h ? SPH_DIRECT(WRAP_NONE, true) : SPH_DIRECT(WRAP_NONE, false);
+        else if (mode == WRAP_CELL) cnt = uniform_h ? SPH_DIRECT(WRAP_CELL, true) : SPH_DIRECT(WRAP_CELL, false);
+        else cnt = uniform_h ? SPH_DIRECT(WRAP_PAIR, true) : SPH_DIRECT(WRAP_PAIR, false);
+#undef SPH_DIRECT
+        if (active) {
+            count[i] = cnt;
+            if (cnt > max_nb) atomicOr(Multi ? &b.status[slot0] : status0, ST_CAPACITY);
+        }
+        continue;
+    }
+    if (!active) continue;
     const Grid &gl = Multi ? b.runs[my_slot].grid : g0;
     const int64_t cbl = Multi ? (int64_t)b.runs[my_slot].cell_base : 0;
     const double no_shift[3] = {0.0, 0.0, 0.0};
@@ -601,7 +717,8 @@ hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_
     const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, 2048);
     fallback_kernel<false><<<fblocks, kWave, 0, ctx->stream>>>(
         p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
-        nb.max_nb, nb.count, nb.idx, ctx->status_dev, BatchDev{}, ctx->fb_tiles, ctx->fb_count);
+        nb.max_nb, nb.count, nb.idx, ctx->status_dev, BatchDev{}, ctx->fb_tiles, ctx->fb_count,
+        ctx->nb_mask, ctx->hflag_dev);
     return hipGetLastError();
 }
 
@@ -619,7 +736,7 @@ hipError_t launch_find_neighbors_batch(sph_ctx ctx, const BatchDev &b, int max_n
     const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, 2048);
     fallback_kernel<true><<<fblocks, kWave, 0, ctx->stream>>>(
         0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,
-        count, idx, nullptr, b, ctx->fb_tiles, ctx->fb_count);
+        count, idx, nullptr, b, ctx->fb_tiles, ctx->fb_count, ctx->nb_mask, nullptr);
     return hipGetLastError();
 }
 
