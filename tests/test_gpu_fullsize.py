@@ -1,0 +1,97 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (the single-run calls, one context sized for the run).
+
+* Rotating square patch 100^3 (1,000,000 particles): every particle's
+  neighbour set bit-exact, and rho, a, du/dt against the FP64 oracle within
+  the FP64 and FP32-pair tolerances.
+* Evrard-like sphere, 1,000,000 particles (analytic h, dense centre): the
+  same, covering the dense-cell and per-lane search paths at full size.
+* Rotating square patch 400^3 (64,000,000 particles): too large for the
+  oracle, so properties that hold at any size: linear momentum of the
+  pairwise forces to round-off, neighbour counts within the lattice bounds,
+  and L_z and total energy after steps.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1809_08013_amd import inputs as I  # noqa: E402
+from paper_1809_08013_amd import sph as S  # noqa: E402
+from gpu_helpers import field_errors, gpu_forces, oracle_forces  # noqa: E402
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    S.load()
+    torch.cuda.set_device(0)
+
+
+def _check(ic, ref, max_nb, label):
+    got, _, ctx = gpu_forces(ic, ref["rho_ref"], S.SPH_FP64, max_nb=max_nb, rho_in=ref["rho"])
+    assert np.array_equal(got["off"], ref["off"]), label
+    assert np.array_equal(got["ids"], ref["ids"]), label
+    e = field_errors(ref, got)
+    print(label, "fp64", e, flush=True)
+    assert e["rho"] <= FP64_TOL and e["a"] <= FP64_TOL and e["du"] <= FP64_TOL
+    assert e["dt"] <= 1e-14
+    got32, _, _ = gpu_forces(ic, ref["rho_ref"], S.SPH_FP32_PAIR, max_nb=max_nb,
+                             rho_in=ref["rho"], export=False, ctx=ctx)
+    e32 = field_errors(ref, got32)
+    print(label, "fp32-pair", e32, flush=True)
+    assert e32["rho"] <= FP32_TOL and e32["a"] <= FP32_TOL and e32["du"] <= FP32_TOL
+    assert e32["dt"] <= FP32_TOL
+
+
+def test_square_patch_1M_every_particle():
+    ic = I.square_patch(100, seed=0)
+    print("case square patch 100^3", flush=True)
+    ref = oracle_forces(ic)
+    _check(ic, ref, 128, "patch 1M")
+
+
+def test_evrard_1M_every_particle():
+    ic = I.evrard(1_000_000, seed=0)
+    print("case Evrard 1M", flush=True)
+    ref = oracle_forces(ic, rho_ref=np.ones(ic.n))
+    max_nb = int(np.diff(ref["off"]).max()) + 8
+    _check(ic, ref, max_nb, "evrard 1M")
+
+
+def test_square_patch_64M_invariants():
+    ic = I.square_patch(400, seed=0)
+    n = ic.n
+    print("case square patch 400^3", flush=True)
+    ctx = S.Context(n, 128)
+    st = S.SphState(ic, 128)
+    prm = S.make_params(ic.params)
+    S.sph_init_forces(ctx, st, prm, set_rho_ref=True)
+    S.sph_ctx_check(ctx)
+    t = st.t
+    cnt = t["count"][:n]
+    # interior lattice particles have 92..122 neighbours, none more than 128
+    assert int(cnt.max().item()) <= 128 and int(cnt.min().item()) >= 20
+    # pairwise antisymmetric forces: sum m a = 0 to round-off (periodic z only
+    # adds exact images, so this holds in every component)
+    m = t["m"][:n]
+    tot = [float(torch.sum(m * t[k][:n]).item()) for k in ("ax", "ay", "az")]
+    scale = float(torch.sum(m * torch.sqrt(t["ax"][:n] ** 2 + t["ay"][:n] ** 2
+                                           + t["az"][:n] ** 2)).item())
+    print("sum m a", tot, "scale", scale, flush=True)
+    assert max(abs(v) for v in tot) < 1e-10 * scale
+    d0 = st.diag.copy()
+    for _ in range(3):
+        S.sph_step(ctx, st, prm)
+    S.sph_ctx_check(ctx)
+    d1 = st.diag
+    print("totals before", d0, "after", d1, flush=True)
+    assert abs(d1[6] - d0[6]) <= 1e-12 * abs(d0[6])     # L_z
+    assert abs(d1[7] - d0[7]) <= 1e-6 * abs(d0[7])      # energy over 3 steps
+    assert abs(d1[1] - d0[1]) < 1e-12 and abs(d1[2] - d0[2]) < 1e-12  # P_x, P_y
