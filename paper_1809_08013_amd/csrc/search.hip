@@ -160,13 +160,32 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const int (&my
         if (w < 64) occ0 |= word ? (1ull << w) : 0ull;
         else occ1 |= word ? (1u << (w - 64)) : 0u;
     };
+    auto bit = [&](const SearchRec &o) -> uint32_t {
+        return related<Mode, UniformH>(me, o, g, sh) ? 1u : 0u;
+    };
     auto step = [&](const SearchRec &o) {
-        acc = (acc << 1) | (related<Mode, UniformH>(me, o, g, sh) ? 1u : 0u);
+        acc = (acc << 1) | bit(o);
         ++u;
         if ((u & 31) == 0) {
             flush((u >> 5) - 1, acc);
             acc = 0;
         }
+    };
+    auto step4 = [&](const SearchRec &o0, const SearchRec &o1, const SearchRec &o2,
+                     const SearchRec &o3) {
+        const uint32_t b4 = (bit(o0) << 3) | (bit(o1) << 2) | (bit(o2) << 1) | bit(o3);
+        const int room = 32 - (u & 31);
+        const int w = u >> 5;
+        if (room > 4) {
+            acc = (acc << 4) | b4;
+        } else if (room == 4) {
+            flush(w, (acc << 4) | b4);
+            acc = 0;
+        } else {
+            flush(w, (acc << room) | (b4 >> (4 - room)));
+            acc = b4 & ((1u << (4 - room)) - 1u);
+        }
+        u += 4;
     };
     for (int c = 0; c < nu; ++c) {
         const int s = __builtin_amdgcn_readfirstlane(L.cells[c].x);
@@ -187,10 +206,7 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const int (&my
             while (e - j >= 4) {
                 const SearchRec b0 = srec[j], b1 = srec[j + 1], b2 = srec[j + 2],
                                 b3 = srec[j + 3];
-                step(a0);
-                step(a1);
-                step(a2);
-                step(a3);
+                step4(a0, a1, a2, a3);
                 // keep the wait for b0..b3 (scalar loads complete out of order,
                 // so it is a full wait) after the work on a0..a3
                 __builtin_amdgcn_sched_barrier(0);
@@ -200,10 +216,7 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const int (&my
                 a3 = b3;
                 j += 4;
             }
-            step(a0);
-            step(a1);
-            step(a2);
-            step(a3);
+            step4(a0, a1, a2, a3);
         }
         for (; j < e; ++j) step(srec[j]);
     }
