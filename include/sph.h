@@ -223,6 +223,24 @@ sph_status sph_step(sph_ctx ctx, const sph_particles *p, const sph_box *box,
                     const sph_fields *f, const sph_accel *a, double *dt_dev,
                     double *diag_dev);
 
+/* Algorithm 1, step 2 ("find the neighbours and the smoothing length"); the
+ * target neighbour count of Sec. 3. Iterates, for it = 0, 1, ..., max_iter:
+ * build the cells for the current largest h (this reorders p as
+ * sph_build_cells does), count for every particle the gather neighbours
+ * N_i = #{j != i : r^2 < (2 h_i)^2} (exact FP64 test, minimum image on
+ * periodic axes) into count[] (DEVICE, n int32, current order); stop when
+ * every N_i is in [lo_count, hi_count] or it == max_iter; otherwise, for the
+ * particles outside the band, h_i <- 2 h_i if N_i = 0, else
+ * h_i <- (h_i / 2) (1 + (n_target / N_i)^(1/3)), the cube root evaluated
+ * on the host per distinct count. *iterations (HOST) receives the last it.
+ * On return the cells are built for the final h (sph_find_neighbors may
+ * follow directly). Synchronising; may allocate a small table.
+ * SPH_E_DOMAIN if a periodic axis becomes shorter than 4 h_max,
+ * SPH_E_NONFINITE if h stops being finite and positive. */
+sph_status sph_smoothing_length(sph_ctx ctx, sph_particles *p, const sph_box *box,
+                                double n_target, int32_t lo_count, int32_t hi_count,
+                                int32_t max_iter, int32_t *count, int32_t *iterations);
+
 /* Test helper (synchronising): neighbour sets in ORIGINAL-id terms.
  * offsets_host[n+1] (int64) and ids_host[cap] (int32) are HOST buffers;
  * the set of original id k is ids_host[offsets_host[k] .. offsets_host[k+1]),

@@ -165,7 +165,7 @@ void free_ctx(sph_ctx ctx)
     void *ptrs[] = {ctx->keys[0], ctx->keys[1], ctx->vals[0], ctx->vals[1], ctx->hist,
                     ctx->scan_part, ctx->cell_start, ctx->cell_end, ctx->perm_tmp,
                     ctx->perm_tmp_id, ctx->red_part, ctx->status_dev, ctx->nb_mask, ctx->hflag_dev,
-                    ctx->fb_tiles, ctx->fb_count,
+                    ctx->fb_tiles, ctx->fb_count, ctx->it_words, ctx->it_hmax,
                     ctx->srec, ctx->drec, ctx->prec};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -245,6 +245,8 @@ sph_status sph_ctx_create(sph_ctx *out, int64_t n_max, int32_t max_nb, sph_strea
     ALLOC(ctx->nb_mask, (int64_t)kSearchMaskWords * ((n_max + 63) / 64) * 64);
     ALLOC(ctx->fb_tiles, (n_max + 63) / 64);
     ALLOC(ctx->fb_count, 1);
+    ALLOC(ctx->it_words, 2);
+    ALLOC(ctx->it_hmax, 1);
     ALLOC(ctx->srec, n_max);
     ALLOC(ctx->drec, n_max);
     ALLOC(ctx->prec, n_max);
@@ -446,6 +448,82 @@ sph_status sph_step(sph_ctx ctx, const sph_particles *p, const sph_box *box, dou
     if ((s = sph_momentum_energy(ctx, p, box, nb, prm, f, a)) != SPH_OK) return s;
     if ((s = sph_integrate(ctx, p, box, SPH_KICK, dt_dev, a)) != SPH_OK) return s;
     return sph_timestep(ctx, p, prm, f, a, dt_dev, diag_dev);
+}
+
+sph_status sph_smoothing_length(sph_ctx ctx, sph_particles *p, const sph_box *box,
+                                double n_target, int32_t lo_count, int32_t hi_count,
+                                int32_t max_iter, int32_t *count, int32_t *iterations)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, false)) != SPH_OK) return s;
+    if ((s = check_box(ctx, box)) != SPH_OK) return s;
+    if (!(n_target > 0.0) || !std::isfinite(n_target))
+        return fail(ctx, SPH_E_INVALID, "n_target must be finite and > 0");
+    if (lo_count < 0 || hi_count < lo_count || max_iter < 0)
+        return fail(ctx, SPH_E_INVALID, "need 0 <= lo_count <= hi_count and max_iter >= 0");
+    if (!iterations || (p->n > 0 && !count))
+        return fail(ctx, SPH_E_INVALID, "count and iterations are required");
+    *iterations = 0;
+    if (p->n == 0) return SPH_OK;
+    double *factor = nullptr;
+    int64_t factor_len = 0;
+    auto done = [&](sph_status st) {
+        if (factor) (void)hipFree(factor);
+        return st;
+    };
+    int32_t it = 0;
+    for (it = 0; it <= max_iter; ++it) {
+        unsigned long long hbits = 0;
+        hipError_t e = launch_max_h(ctx, *p, ctx->it_hmax);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&hbits, ctx->it_hmax, sizeof hbits, hipMemcpyDeviceToHost,
+                               ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return done(hip_fail(ctx, e, "largest h"));
+        double h_max;
+        std::memcpy(&h_max, &hbits, sizeof h_max);
+        if (!(h_max > 0.0) || !std::isfinite(h_max))
+            return done(fail(ctx, SPH_E_NONFINITE, "h is not finite and positive"));
+        for (int a = 0; a < 3; ++a)
+            if (box->periodic[a] && !(box->hi[a] - box->lo[a] > 4.0 * h_max))
+                return done(fail(ctx, SPH_E_DOMAIN,
+                                 "periodic axis %d is not longer than 4 h_max", a));
+        ctx->grid = make_grid(*box, h_max, ctx->cell_cap, kMaxAxisCells);
+        ctx->n_built = p->n;
+        uint32_t words[2] = {0, 0};
+        e = launch_build_cells(ctx, *p, ctx->grid, h_max);
+        if (e == hipSuccess) e = launch_gather_count(ctx, *p, count, lo_count, hi_count,
+                                                     ctx->it_words);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(words, ctx->it_words, sizeof words, hipMemcpyDeviceToHost,
+                               ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return done(hip_fail(ctx, e, "gather counts"));
+        if (words[0] == 0 || it == max_iter) break;
+        // factor[k] = 1 + (n_target / k)^(1/3), evaluated here once per count
+        const int64_t need = (int64_t)words[1] + 1;
+        if (need > factor_len) {
+            if (factor) (void)hipFree(factor);
+            factor = nullptr;
+            factor_len = std::max<int64_t>(need, 1024);
+            if (hipMalloc((void **)&factor, sizeof(double) * factor_len) != hipSuccess) {
+                (void)hipGetLastError();
+                factor = nullptr;
+                return done(fail(ctx, SPH_E_NOMEM, "factor table allocation failed"));
+            }
+        }
+        std::vector<double> host((size_t)need);
+        host[0] = 0.0;
+        for (int64_t k = 1; k < need; ++k) host[k] = 1.0 + std::cbrt(n_target / (double)k);
+        e = hipMemcpyAsync(factor, host.data(), sizeof(double) * need, hipMemcpyHostToDevice,
+                           ctx->stream);
+        if (e == hipSuccess) e = launch_update_h(ctx, *p, count, lo_count, hi_count, factor);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return done(hip_fail(ctx, e, "h update"));
+    }
+    *iterations = it;
+    return done(SPH_OK);
 }
 
 sph_status sph_export_neighbors(sph_ctx ctx, const sph_particles *p, const sph_nbrs *nb,

@@ -716,6 +716,102 @@ find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Smoothing-length iteration (Algorithm 1, step 2, "neighbours and smoothing
+// length"; Sec. 3, target neighbour count): gather counts
+// N_i = #{j != i : r^2 < (2 h_i)^2}, the number of particles outside the
+// accepted band, and the update of h from a table of factors indexed by the
+// integer count (filled by the host, so that the factor is the same number
+// as in any other implementation that evaluates the same expression).
+
+// Offsets -1, 0, +1 on one axis, without repeating a cell when a periodic
+// axis has fewer than 3 cells.
+__device__ __forceinline__ int axis_offsets(int nc, int periodic, int (&off)[3])
+{
+    if (periodic && nc == 1) { off[0] = 0; return 1; }
+    if (periodic && nc == 2) { off[0] = 0; off[1] = 1; return 2; }
+    off[0] = -1; off[1] = 0; off[2] = 1;
+    return 3;
+}
+
+__global__ void __launch_bounds__(256)
+gather_count_kernel(int64_t n, const SearchRec *__restrict__ srec,
+                    const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
+                    const int32_t *__restrict__ cend, Grid g, int32_t *__restrict__ count,
+                    int32_t lo_count, int32_t hi_count, uint32_t *bad, uint32_t *max_count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const SearchRec me = srec[i];
+    const uint32_t key = keys[i];
+    const int myc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
+    int ox[3], oy[3], oz[3];
+    const int nx = axis_offsets(g.nc[0], g.periodic[0], ox);
+    const int ny = axis_offsets(g.nc[1], g.periodic[1], oy);
+    const int nz = axis_offsets(g.nc[2], g.periodic[2], oz);
+    const double no_shift[3] = {0.0, 0.0, 0.0};
+    int cnt = 0;
+    for (int c = 0; c < nz; ++c) {
+        bool okz;
+        const int z = wrap_or_clip(myc[2] + oz[c], g.nc[2], g.periodic[2], okz);
+        if (!okz) continue;
+        for (int b = 0; b < ny; ++b) {
+            bool oky;
+            const int y = wrap_or_clip(myc[1] + oy[b], g.nc[1], g.periodic[1], oky);
+            if (!oky) continue;
+            for (int a = 0; a < nx; ++a) {
+                bool okx;
+                const int x = wrap_or_clip(myc[0] + ox[a], g.nc[0], g.periodic[0], okx);
+                if (!okx) continue;
+                const int64_t cell = ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
+                const int e = cend[cell];
+                for (int j = cstart[cell]; j < e; ++j)
+                    if (j != (int)i && related<WRAP_PAIR, true>(me, srec[j], g, no_shift)) ++cnt;
+            }
+        }
+    }
+    count[i] = cnt;
+    if (cnt < lo_count || cnt > hi_count) atomicAdd(bad, 1u);
+    atomicMax(max_count, (uint32_t)cnt);
+}
+
+// h <- 2 h for an empty sphere, else (h / 2) (1 + (n_target / N)^(1/3)),
+// with the second factor read from the table at N.
+__global__ void __launch_bounds__(256)
+update_h_kernel(int64_t n, const int32_t *__restrict__ count, double *__restrict__ h,
+                int32_t lo_count, int32_t hi_count, const double *__restrict__ factor)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = count[i];
+    if (c >= lo_count && c <= hi_count) return;
+    h[i] = c == 0 ? 2.0 * h[i] : (h[i] * 0.5) * factor[c];
+}
+
+// Largest h, as the ordered bit patterns of positive doubles.
+__global__ void __launch_bounds__(256)
+max_h_kernel(int64_t n, const double *__restrict__ h, unsigned long long *out)
+{
+    unsigned long long m = 0;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        const unsigned long long v = (unsigned long long)__double_as_longlong(h[i]);
+        m = v > m ? v : m;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(m, o, 64);
+        m = t > m ? t : m;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+__global__ void clear_words_kernel(uint32_t *a, int k)
+{
+    if ((int)threadIdx.x < k) a[threadIdx.x] = 0u;
+}
+
 }  // namespace
 
 hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb)
@@ -750,6 +846,32 @@ hipError_t launch_find_neighbors_batch(sph_ctx ctx, const BatchDev &b, int max_n
     fallback_kernel<true><<<fblocks, kWave, 0, ctx->stream>>>(
         0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,
         count, idx, nullptr, b, ctx->fb_tiles, ctx->fb_count, ctx->nb_mask, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_h(sph_ctx ctx, const sph_particles &p, unsigned long long *out)
+{
+    clear_words_kernel<<<1, 64, 0, ctx->stream>>>(reinterpret_cast<uint32_t *>(out), 2);
+    const unsigned blocks = (unsigned)std::min<int64_t>((p.n + 255) / 256, 1024);
+    max_h_kernel<<<blocks, 256, 0, ctx->stream>>>(p.n, p.h, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_count(sph_ctx ctx, const sph_particles &p, int32_t *count,
+                               int32_t lo_count, int32_t hi_count, uint32_t *words)
+{
+    clear_words_kernel<<<1, 64, 0, ctx->stream>>>(words, 2);
+    gather_count_kernel<<<(unsigned)((p.n + 255) / 256), 256, 0, ctx->stream>>>(
+        p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid, count,
+        lo_count, hi_count, words, words + 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_h(sph_ctx ctx, const sph_particles &p, const int32_t *count,
+                           int32_t lo_count, int32_t hi_count, const double *factor)
+{
+    update_h_kernel<<<(unsigned)((p.n + 255) / 256), 256, 0, ctx->stream>>>(
+        p.n, count, p.h, lo_count, hi_count, factor);
     return hipGetLastError();
 }
 

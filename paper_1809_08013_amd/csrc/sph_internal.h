@@ -168,6 +168,8 @@ struct sph_ctx_s {
     uint32_t *nb_mask = nullptr;     // search bit masks: kSearchMaskWords words per particle slot
     int32_t *fb_tiles = nullptr;     // search tiles left to the per-lane path
     uint32_t *fb_count = nullptr;
+    uint32_t *it_words = nullptr;    // h iteration: out-of-band count, largest count
+    unsigned long long *it_hmax = nullptr;  // h iteration: largest h (bit pattern)
 
     sph::SearchRec *srec = nullptr;  // search records, cell order
     sph::DensRec *drec = nullptr;    // density records (written by sph_density)
@@ -211,6 +213,13 @@ hipError_t launch_timestep(sph_ctx ctx, const sph_particles &p,
 hipError_t launch_copy(sph_ctx ctx, double *dst, const double *src, int64_t n);
 
 Grid make_grid(const sph_box &b, double h_max, int64_t cell_cap, int max_axis);
+
+// Smoothing-length iteration.
+hipError_t launch_max_h(sph_ctx ctx, const sph_particles &p, unsigned long long *out);
+hipError_t launch_gather_count(sph_ctx ctx, const sph_particles &p, int32_t *count,
+                               int32_t lo_count, int32_t hi_count, uint32_t *words);
+hipError_t launch_update_h(sph_ctx ctx, const sph_particles &p, const int32_t *count,
+                           int32_t lo_count, int32_t hi_count, const double *factor);
 
 // Ensemble launchers: fixed grids sized for b.cap; counts are read from the
 // step header on the device. F is the block of kEnsFields state rows

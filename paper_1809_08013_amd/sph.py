@@ -136,6 +136,8 @@ def load():
             "sph_step": (C.c_int32, [_VP, P, B, C.c_double, N, M, F, A, _VP, _VP]),
             "sph_export_neighbors": (C.c_int32, [_VP, P, N, _VP, _VP, C.c_int64,
                                                  C.POINTER(C.c_int64)]),
+            "sph_smoothing_length": (C.c_int32, [_VP, P, B, C.c_double, C.c_int32, C.c_int32,
+                                                 C.c_int32, _VP, C.POINTER(C.c_int32)]),
             "sph_ens_create": (C.c_int32, [C.POINTER(_VP), C.POINTER(EnsConfig)]),
             "sph_ens_submit": (C.c_int32, [_VP, C.POINTER(RunRequest),
                                            C.POINTER(C.c_uint64)]),
@@ -341,6 +343,18 @@ def sph_step(ctx: Context, st: SphState, prm: Params, h_max: float | None = None
         float(h_max if h_max is not None else st.h_max), C.byref(st.nbrs), C.byref(prm),
         C.byref(st.fields), C.byref(st.accel), _ptr(st.t["dt"]),
         _ptr(st.t["diag"]) if diag else None))
+
+
+def sph_smoothing_length(ctx: Context, st: SphState, n_target: float = 100.0,
+                         lo_count: int = 95, hi_count: int = 105, max_iter: int = 10) -> int:
+    """Count-based h iteration on the GPU; gather counts land in st.t["count"]
+    (current order) and st.h_max is updated. Returns the last iteration."""
+    it = C.c_int32(0)
+    ctx.raise_on(ctx.lib.sph_smoothing_length(
+        ctx.h, C.byref(st.particles), C.byref(st.box), float(n_target), int(lo_count),
+        int(hi_count), int(max_iter), _ptr(st.t["count"]), C.byref(it)))
+    st.h_max = float(st.t["h"][: st.n].max().item()) if st.n else st.h_max
+    return int(it.value)
 
 
 def sph_export_neighbors(ctx: Context, st: SphState):

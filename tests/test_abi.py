@@ -112,3 +112,10 @@ int main(void) {
             C.sizeof(S.EnsCounters), S.RunRequest.rho_ref.offset, S.RunResult.status.offset,
             S.EnsCounters.busy_seconds.offset]
     assert got == want
+
+
+def test_smoothing_length_host_checks():
+    L = _lib()
+    it = C.c_int32(0)
+    assert L.sph_smoothing_length(None, None, None, 100.0, 95, 105, 10, None,
+                                  C.byref(it)) == S.SPH_E_INVALID

@@ -65,6 +65,23 @@ def test_evrard_1M_every_particle():
     _check(ic, ref, max_nb, "evrard 1M")
 
 
+def test_evrard_1M_smoothing_length_bitwise():
+    """The GPU h iteration at full size equals the oracle's bit for bit."""
+    import oracle as O
+    ic = I.evrard(1_000_000, seed=0)
+    print("case Evrard 1M h iteration", flush=True)
+    h_ref, cnt_ref, it_ref = O.smoothing_length(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi,
+                                                ic.periodic)
+    ctx = S.Context(ic.n, 64)
+    st = S.SphState(ic, 64)
+    it = S.sph_smoothing_length(ctx, st)
+    got = st.host(["h", "count"])
+    print("iterations", it, it_ref, flush=True)
+    assert it == it_ref
+    assert np.array_equal(got["count"], cnt_ref)
+    assert np.array_equal(got["h"], h_ref)
+
+
 def test_square_patch_64M_invariants():
     ic = I.square_patch(400, seed=0)
     n = ic.n

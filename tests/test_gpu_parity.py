@@ -234,3 +234,24 @@ def test_evrard_variable_h():
     e32 = field_errors(ref, got32)
     print("evrard fp32-pair", e32)
     assert e32["a"] <= FP32_TOL and e32["du"] <= FP32_TOL
+
+
+@pytest.mark.parametrize("case", ["evrard_20k", "cloud_periodic"])
+def test_smoothing_length_iteration_bitwise(case):
+    """sph_smoothing_length reproduces the oracle's count-based h iteration
+    bit for bit: same iterations, same final gather counts, same h."""
+    if case == "evrard_20k":
+        ic = I.evrard(20000, seed=3)
+    else:
+        ic = I.random_cloud(5000, seed=4, h_min=0.02, h_max=0.08, periodic=(1, 1, 1))
+    print("case", case, flush=True)
+    h_ref, cnt_ref, it_ref = O.smoothing_length(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi,
+                                                ic.periodic)
+    ctx = S.Context(ic.n, 64)
+    st = S.SphState(ic, 64)
+    it = S.sph_smoothing_length(ctx, st)
+    got = st.host(["h", "count"])
+    print(case, "iterations", it, it_ref, "count range", cnt_ref.min(), cnt_ref.max(), flush=True)
+    assert it == it_ref
+    assert np.array_equal(got["count"], cnt_ref)
+    assert np.array_equal(got["h"], h_ref)
