@@ -40,6 +40,8 @@ Grid make_grid(const sph_box &b, double h_max, int64_t cell_cap, int max_axis)
     int maxc = std::max(g.nc[0], std::max(g.nc[1], g.nc[2]));
     g.bits = 0;
     while ((1 << g.bits) < maxc) ++g.bits;
+    // z slices inside a cell, in the key bits the Morton code leaves free
+    g.zbits = std::min(kSliceBits, 32 - 3 * g.bits);
     for (int a = 0; a < 3; ++a) g.inv_s[a] = (double)g.nc[a] / g.len[a];
     return g;
 }
@@ -165,7 +167,7 @@ void free_ctx(sph_ctx ctx)
     void *ptrs[] = {ctx->keys[0], ctx->keys[1], ctx->vals[0], ctx->vals[1], ctx->hist,
                     ctx->scan_part, ctx->cell_start, ctx->cell_end, ctx->perm_tmp,
                     ctx->perm_tmp_id, ctx->red_part, ctx->status_dev, ctx->nb_mask, ctx->hflag_dev,
-                    ctx->fb_tiles, ctx->fb_count, ctx->it_words, ctx->it_hmax,
+                    ctx->fb_tiles, ctx->fb_count, ctx->it_words, ctx->it_hmax, ctx->cell_s2max,
                     ctx->srec, ctx->drec, ctx->prec};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -242,6 +244,7 @@ sph_status sph_ctx_create(sph_ctx *out, int64_t n_max, int32_t max_nb, sph_strea
     ALLOC(ctx->scan_part, (ctx->scan_len_max + kScanChunk - 1) / kScanChunk + 1);
     ALLOC(ctx->cell_start, ctx->cell_cap);
     ALLOC(ctx->cell_end, ctx->cell_cap);
+    ALLOC(ctx->cell_s2max, ctx->cell_cap);
     ALLOC(ctx->nb_mask, (int64_t)kSearchMaskWords * ((n_max + 63) / 64) * 64);
     ALLOC(ctx->fb_tiles, (n_max + 63) / 64);
     ALLOC(ctx->fb_count, 1);

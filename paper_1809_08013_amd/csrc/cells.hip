@@ -39,10 +39,22 @@ __device__ __forceinline__ int cell_of(double v, double lo, double inv_s, int nc
     return (int)f;
 }
 
+// z slice of a point in its cell (zbits bits): the fractional part of its
+// cell coordinate, scaled by 2^zbits, with points outside the box clamped
+// to the first or last slice.
+__device__ __forceinline__ uint32_t slice_of(double v, double lo, double inv_s, int cz, int zbits)
+{
+    const double f = (v - lo) * inv_s;
+    double q = floor((f - (double)cz) * (double)(1 << zbits));
+    q = fmin(fmax(q, 0.0), (double)((1 << zbits) - 1));
+    return (uint32_t)q;
+}
+
 __global__ void clear_word_kernel(uint32_t *w) { *w = 0u; }
 
-// Morton key of each particle's cell; vals = current index. Flags h > h_max,
-// and sets *hflag when some h differs from h[0].
+// Sort key of each particle: the Morton key of its cell, then its z slice in
+// the cell; vals = current index. Flags h > h_max, and sets *hflag when some
+// h differs from h[0].
 __global__ void __launch_bounds__(256)
 keys_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
             const double *__restrict__ z, const double *__restrict__ h, Grid g,
@@ -55,7 +67,8 @@ keys_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ 
     uint32_t cx = (uint32_t)cell_of(x[i], g.lo[0], g.inv_s[0], g.nc[0]);
     uint32_t cy = (uint32_t)cell_of(y[i], g.lo[1], g.inv_s[1], g.nc[1]);
     uint32_t cz = (uint32_t)cell_of(z[i], g.lo[2], g.inv_s[2], g.nc[2]);
-    keys[i] = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+    const uint32_t zq = slice_of(z[i], g.lo[2], g.inv_s[2], (int)cz, g.zbits);
+    keys[i] = ((spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2)) << g.zbits) | zq;
     vals[i] = (int32_t)i;
     if (!(h[i] <= h_max)) atomicOr(status, ST_DOMAIN);
 }
@@ -255,18 +268,21 @@ permute_store_kernel(int64_t n, const int64_t *n_dev, int64_t stride, PermFields
     }
 }
 
-// Cell table by binary search of each cell's key in the sorted keys: every
-// entry is rewritten on every build, empty cells get start == end.
+// Cell table by binary search of each cell's key range (all its slices) in
+// the sorted keys: every entry is rewritten on every build, empty cells get
+// start == end. Also clears the cell's largest (2h)^2.
 __global__ void __launch_bounds__(256)
 cell_table_kernel(int64_t ncell, Grid g, const uint32_t *__restrict__ keys, int64_t n,
-                  int32_t *__restrict__ cstart, int32_t *__restrict__ cend)
+                  int32_t *__restrict__ cstart, int32_t *__restrict__ cend,
+                  unsigned long long *__restrict__ s2max)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     const uint32_t cx = (uint32_t)(c % g.nc[0]);
     const uint32_t cy = (uint32_t)((c / g.nc[0]) % g.nc[1]);
     const uint32_t cz = (uint32_t)(c / ((int64_t)g.nc[0] * g.nc[1]));
-    const uint32_t key = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+    const uint32_t key = (spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2)) << g.zbits;
+    const uint32_t last = key | ((1u << g.zbits) - 1u);
     int64_t lo = 0, hi = n;
     while (lo < hi) {   // first index with keys[i] >= key
         int64_t mid = (lo + hi) >> 1;
@@ -274,12 +290,39 @@ cell_table_kernel(int64_t ncell, Grid g, const uint32_t *__restrict__ keys, int6
     }
     const int64_t s = lo;
     hi = n;
-    while (lo < hi) {   // first index with keys[i] > key
+    while (lo < hi) {   // first index with keys[i] > last
         int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] <= key) lo = mid + 1; else hi = mid;
+        if (keys[mid] <= last) lo = mid + 1; else hi = mid;
     }
     cstart[c] = (int32_t)s;
     cend[c] = (int32_t)lo;
+    s2max[c] = 0ull;
+}
+
+// Largest (2h)^2 of each cell, as the ordered bit pattern of a positive
+// double: a segmented maximum over the wave's lanes (a cell's particles are
+// consecutive), then one atomic per cell and wave.
+__global__ void __launch_bounds__(256)
+cell_s2max_kernel(int64_t n, Grid g, const uint32_t *__restrict__ keys,
+                  const SearchRec *__restrict__ srec, unsigned long long *__restrict__ s2max)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool active = i < n;
+    const uint32_t ck = active ? keys[i] >> g.zbits : 0xFFFFFFFFu;
+    unsigned long long v = active ? (unsigned long long)__double_as_longlong(srec[i].s2) : 0ull;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long t = __shfl_down(v, o, 64);
+        const uint32_t tk = __shfl_down(ck, o, 64);
+        if (lane + o < 64 && tk == ck) v = t > v ? t : v;
+    }
+    const uint32_t pk = __shfl_up(ck, 1, 64);
+    if (active && (lane == 0 || pk != ck)) {
+        const int64_t cell = ((int64_t)compact3(ck >> 2) * g.nc[1] + compact3(ck >> 1)) * g.nc[0] +
+                             compact3(ck);
+        atomicMax(&s2max[cell], v);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -319,8 +362,10 @@ keys_batch_kernel(BatchDev b, const double *__restrict__ x, const double *__rest
             const uint32_t cx = (uint32_t)cell_of(x[i], g.lo[0], g.inv_s[0], g.nc[0]);
             const uint32_t cy = (uint32_t)cell_of(y[i], g.lo[1], g.inv_s[1], g.nc[1]);
             const uint32_t cz = (uint32_t)cell_of(z[i], g.lo[2], g.inv_s[2], g.nc[2]);
-            key = ((uint32_t)s << (3 * kEnsAxisBits)) | spread3(cx) | (spread3(cy) << 1) |
-                  (spread3(cz) << 2);
+            const uint32_t zq = slice_of(z[i], g.lo[2], g.inv_s[2], (int)cz, g.zbits);
+            key = ((uint32_t)s << kEnsSlotShift) |
+                  ((spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2)) << kSliceBits) |
+                  (zq << (kSliceBits - g.zbits));
             if (!(h[i] <= r.h_max)) atomicOr(&b.status[s], ST_DOMAIN);
         }
         keys[i] = key;
@@ -352,8 +397,9 @@ cell_table_batch_kernel(BatchDev b, const uint32_t *__restrict__ keys,
         const uint32_t cx = (uint32_t)(lc % g.nc[0]);
         const uint32_t cy = (uint32_t)((lc / g.nc[0]) % g.nc[1]);
         const uint32_t cz = (uint32_t)(lc / ((int64_t)g.nc[0] * g.nc[1]));
-        const uint32_t key = ((uint32_t)s << (3 * kEnsAxisBits)) | spread3(cx) |
-                             (spread3(cy) << 1) | (spread3(cz) << 2);
+        const uint32_t key = ((uint32_t)s << kEnsSlotShift) |
+                             ((spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2)) << kSliceBits);
+        const uint32_t last = key | ((1u << kSliceBits) - 1u);
         int64_t a = r.start, e = (int64_t)r.start + r.n;
         while (a < e) {
             const int64_t mid = (a + e) >> 1;
@@ -363,7 +409,7 @@ cell_table_batch_kernel(BatchDev b, const uint32_t *__restrict__ keys,
         e = (int64_t)r.start + r.n;
         while (a < e) {
             const int64_t mid = (a + e) >> 1;
-            if (keys[mid] <= key) a = mid + 1; else e = mid;
+            if (keys[mid] <= last) a = mid + 1; else e = mid;
         }
         cstart[c] = (int32_t)first;
         cend[c] = (int32_t)a;
@@ -395,7 +441,7 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
                                                    ctx->status_dev);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int key_bits = 3 * g.bits;
+    const int key_bits = 3 * g.bits + g.zbits;
     const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
     int cur = 0;
     for (int shift = 0; shift < key_bits; shift += kRadixBits) {
@@ -429,8 +475,11 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
                                                             ctx->perm_tmp, ctx->perm_tmp_id,
                                                             nullptr, h_field, ctx->srec);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    unsigned long long *s2max = reinterpret_cast<unsigned long long *>(ctx->cell_s2max);
     cell_table_kernel<<<blocks_for(ncell, 256), 256, 0, s>>>(ncell, g, ctx->sorted_keys, n,
-                                                             ctx->cell_start, ctx->cell_end);
+                                                             ctx->cell_start, ctx->cell_end, s2max);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    cell_s2max_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, g, ctx->sorted_keys, ctx->srec, s2max);
     return hipGetLastError();
 }
 

@@ -29,7 +29,9 @@
 //
 // A wave whose union has more candidates than the masks hold (dense cells)
 // streams the same union but lets each lane append its accepted candidates
-// directly. A wave with too many distinct cells, or whose particles belong to
+// directly; when no image is in play it walks, in each cell, only the z
+// slices (the lowest key bits order a cell's particles by z) within reach of
+// the tile's z extent. A wave with too many distinct cells, or whose particles belong to
 // two runs of an ensemble, takes the per-lane path instead: each lane walks
 // its own stencil (sorted by Morton key) and writes its entries directly. Both paths produce the same set in the
 // same (ascending) order, so the sums over a list do not depend on the path
@@ -226,11 +228,12 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const int (&my
 // Stream a union too large for the masks (dense cells): the same
 // wave-uniform walk, each lane appending its accepted candidates to its own
 // list as it goes (few candidates pass, so the scattered stores are rare).
+// The union is held across the lanes: lane l has cell l in r0/p0 (range,
+// packed coordinates) and cell l + 64 in r1/p1.
 template <int Mode, bool UniformH>
 __device__ __forceinline__ int stream_direct(const SearchRec &me, const int (&myc)[3],
-                                             const SearchRec *__restrict__ srec,
-                                             const int2 *__restrict__ cells,
-                                             const uint32_t *__restrict__ cxyz, int nu,
+                                             const SearchRec *__restrict__ srec, int2 r0,
+                                             int2 r1, uint32_t p0, uint32_t p1, int nu,
                                              const Grid &g, bool active, int64_t i, int64_t ld,
                                              int max_nb, int32_t *__restrict__ idx)
 {
@@ -244,10 +247,12 @@ __device__ __forceinline__ int stream_direct(const SearchRec &me, const int (&my
         }
     };
     for (int c = 0; c < nu; ++c) {
-        const int s = __builtin_amdgcn_readfirstlane(cells[c].x);
-        const int e = __builtin_amdgcn_readfirstlane(cells[c].y);
+        const bool hi_half = c >= kWave;
+        const int cl = c & (kWave - 1);
+        const int s = __builtin_amdgcn_readlane(hi_half ? r1.x : r0.x, cl);
+        const int e = __builtin_amdgcn_readlane(hi_half ? r1.y : r0.y, cl);
         if (Mode == WRAP_CELL) {
-            const uint32_t p = __builtin_amdgcn_readfirstlane(cxyz[c]);
+            const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)(hi_half ? p1 : p0), cl);
             const int cc[3] = {(int)(p & 1023u), (int)((p >> 10) & 1023u), (int)(p >> 20)};
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -283,6 +288,47 @@ __device__ __forceinline__ int stream_direct(const SearchRec &me, const int (&my
     return cnt;
 }
 
+// z window of a union cell for a dense tile (no periodic image in play):
+// the sub-range of the cell's particles whose z slices can hold a candidate
+// related to a particle of the tile. A particle in a slice outside the window
+// lies more than R + (one slice) beyond the tile's z extent [zlo, zhi], where
+// R^2 = the larger of the tile's and the cell's largest (2h)^2, so its
+// distance to every particle of the tile exceeds both smoothing diameters;
+// the one-slice margin dwarfs the rounding of the window's arithmetic. A
+// cell's keys are ordered by slice, so the window is found by binary search.
+__device__ __forceinline__ int2 z_window(int2 cr, uint32_t p, const Grid &g, double zlo,
+                                         double zhi, double s2t,
+                                         const unsigned long long *__restrict__ s2max,
+                                         const uint32_t *__restrict__ keys)
+{
+    if (cr.x >= cr.y) return cr;
+    const int x = (int)(p & 1023u), y = (int)((p >> 10) & 1023u), z = (int)(p >> 20);
+    const int64_t cell = ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
+    const double s2c = __longlong_as_double((long long)s2max[cell]);
+    const double r = sqrt(fmax(s2t, s2c));
+    const double ns = (double)(1 << g.zbits);
+    const double fl = ((zlo - r) - g.lo[2]) * g.inv_s[2] - (double)z;
+    const double fh = ((zhi + r) - g.lo[2]) * g.inv_s[2] - (double)z;
+    const double ql = fmax(floor(fl * ns) - 1.0, 0.0);
+    const double qh = fmin(floor(fh * ns) + 1.0, ns - 1.0);
+    if (ql > qh) return make_int2(cr.x, cr.x);
+    if (ql == 0.0 && qh == ns - 1.0) return cr;
+    const uint32_t base = keys[cr.x] & ~((1u << g.zbits) - 1u);
+    const uint32_t klo = base | (uint32_t)ql, khi = base | (uint32_t)qh;
+    int a = cr.x, e = cr.y;
+    while (a < e) {  // first key >= klo
+        const int mid = (a + e) >> 1;
+        if (keys[mid] < klo) a = mid + 1; else e = mid;
+    }
+    const int first = a;
+    e = cr.y;
+    while (a < e) {  // first key > khi
+        const int mid = (a + e) >> 1;
+        if (keys[mid] <= khi) a = mid + 1; else e = mid;
+    }
+    return make_int2(first, a);
+}
+
 // One tile of 64 particles. Multi: the particles belong to runs of an
 // ensemble (slot in the high key bits); a tile whose particles are all of one
 // run uses that run's grid and cell range, a tile spanning two runs takes the
@@ -309,15 +355,17 @@ __device__ __forceinline__ void search_tile(
     int my_slot = 0, slot0 = 0;
     bool mixed = false;
     if constexpr (Multi) {
-        my_slot = active ? (int)(key >> (3 * kEnsAxisBits)) : 0;
+        my_slot = active ? (int)(key >> kEnsSlotShift) : 0;
         slot0 = __builtin_amdgcn_readfirstlane(my_slot);
         mixed = __ballot(active && my_slot != slot0) != 0ull;
     }
     const Grid &g = Multi ? b.runs[slot0].grid : g0;
     const int64_t cbase = Multi ? (int64_t)b.runs[slot0].cell_base : 0;
-    const uint32_t mkey = Multi ? (key & kEnsMortonMask) : key;
-    const uint32_t prev = __shfl_up(key, 1, kWave);
-    const bool first = active && (lane == 0 || key != prev);
+    // cell part of the key (run and Morton code, without the z slice)
+    const uint32_t ckey = key >> (Multi ? kSliceBits : g0.zbits);
+    const uint32_t mkey = Multi ? (ckey & kEnsMortonMask) : ckey;
+    const uint32_t prev = __shfl_up(ckey, 1, kWave);
+    const bool first = active && (lane == 0 || ckey != prev);
     const uint64_t fm = __ballot(first);
     const int ndist = __popcll(fm);
     if (first) L.dkeys[__popcll(fm & lt)] = mkey;
@@ -573,7 +621,8 @@ fallback_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
                 const int32_t *__restrict__ cend, Grid g0, int max_nb,
                 int32_t *__restrict__ count, int32_t *__restrict__ idx, uint32_t *status0,
                 BatchDev b, const int32_t *__restrict__ fb_tiles, const uint32_t *fb_count,
-                const uint32_t *__restrict__ mask_scratch, const uint32_t *__restrict__ hflag)
+                const uint32_t *__restrict__ mask_scratch, const uint32_t *__restrict__ hflag,
+                const unsigned long long *__restrict__ s2max)
 {
     const int lane = threadIdx.x;
     if (Multi) n = b.hdr->n_out;
@@ -585,8 +634,8 @@ fallback_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
     const bool active = i < n;
     const uint32_t key = active ? keys[i] : 0xFFFFFFFFu;
     const SearchRec me = active ? srec[i] : SearchRec{0.0, 0.0, 0.0, 0.0};
-    const int my_slot = Multi && active ? (int)(key >> (3 * kEnsAxisBits)) : 0;
-    const uint32_t mkey = Multi ? (key & kEnsMortonMask) : key;
+    const int my_slot = Multi && active ? (int)(key >> kEnsSlotShift) : 0;
+    const uint32_t mkey = Multi ? ((key >> kSliceBits) & kEnsMortonMask) : (key >> g0.zbits);
     const int myc[3] = {(int)compact3(mkey), (int)compact3(mkey >> 1),
                         (int)compact3(mkey >> 2)};
     if (entry & 0x80000000u) {
@@ -612,9 +661,33 @@ fallback_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
         const int mode = !wrap ? WRAP_NONE : (few_cells ? WRAP_PAIR : WRAP_CELL);
         const int2 *gc = reinterpret_cast<const int2 *>(bm);
         const uint32_t *gx = bm + 2 * kMaxEntries;
+        int2 r0 = make_int2(0, 0), r1 = make_int2(0, 0);
+        uint32_t p0 = 0u, p1 = 0u;
+        if (lane < nu) {
+            r0 = gc[lane];
+            p0 = gx[lane];
+        }
+        if (lane + kWave < nu) {
+            r1 = gc[lane + kWave];
+            p1 = gx[lane + kWave];
+        }
+        if (!Multi && mode == WRAP_NONE && g.zbits > 0) {
+            // walk only each cell's z window (single run: the cell table
+            // carries the cells' largest (2h)^2)
+            double zlo = active ? me.z : INFINITY, zhi = active ? me.z : -INFINITY;
+            double s2t = active ? me.s2 : 0.0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                zlo = fmin(zlo, __shfl_xor(zlo, o, kWave));
+                zhi = fmax(zhi, __shfl_xor(zhi, o, kWave));
+                s2t = fmax(s2t, __shfl_xor(s2t, o, kWave));
+            }
+            if (lane < nu) r0 = z_window(r0, p0, g, zlo, zhi, s2t, s2max, keys);
+            if (lane + kWave < nu) r1 = z_window(r1, p1, g, zlo, zhi, s2t, s2max, keys);
+        }
         int cnt;
 #define SPH_DIRECT(M, U) \
-    stream_direct<M, U>(me, myc, srec, gc, gx, nu, g, active, i, ld, max_nb, idx)
+    stream_direct<M, U>(me, myc, srec, r0, r1, p0, p1, nu, g, active, i, ld, max_nb, idx)
         if (mode == WRAP_NONE) cnt = uniform_h ? SPH_DIRECT(WRAP_NONE, true) : SPH_DIRECT(WRAP_NONE, false);
         else if (mode == WRAP_CELL) cnt = uniform_h ? SPH_DIRECT(WRAP_CELL, true) : SPH_DIRECT(WRAP_CELL, false);
         else cnt = uniform_h ? SPH_DIRECT(WRAP_PAIR, true) : SPH_DIRECT(WRAP_PAIR, false);
@@ -744,7 +817,7 @@ gather_count_kernel(int64_t n, const SearchRec *__restrict__ srec,
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const SearchRec me = srec[i];
-    const uint32_t key = keys[i];
+    const uint32_t key = keys[i] >> g.zbits;
     const int myc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
     int ox[3], oy[3], oz[3];
     const int nx = axis_offsets(g.nc[0], g.periodic[0], ox);
@@ -827,7 +900,8 @@ hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_
     fallback_kernel<false><<<fblocks, kWave, 0, ctx->stream>>>(
         p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
         nb.max_nb, nb.count, nb.idx, ctx->status_dev, BatchDev{}, ctx->fb_tiles, ctx->fb_count,
-        ctx->nb_mask, ctx->hflag_dev);
+        ctx->nb_mask, ctx->hflag_dev,
+        reinterpret_cast<const unsigned long long *>(ctx->cell_s2max));
     return hipGetLastError();
 }
 
@@ -845,7 +919,7 @@ hipError_t launch_find_neighbors_batch(sph_ctx ctx, const BatchDev &b, int max_n
     const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, 2048);
     fallback_kernel<true><<<fblocks, kWave, 0, ctx->stream>>>(
         0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,
-        count, idx, nullptr, b, ctx->fb_tiles, ctx->fb_count, ctx->nb_mask, nullptr);
+        count, idx, nullptr, b, ctx->fb_tiles, ctx->fb_count, ctx->nb_mask, nullptr, nullptr);
     return hipGetLastError();
 }
 

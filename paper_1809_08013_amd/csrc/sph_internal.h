@@ -36,6 +36,7 @@ constexpr int kPermFields = 14; // x y z vx vy vz u h m rho_ref p_bg gx gy gz
 struct Grid {
     int nc[3];          // cells per axis
     int bits;           // Morton bits per axis
+    int zbits;          // key bits below the cell's Morton code: the z slice in the cell
     int periodic[3];
     double lo[3];
     double hi[3];
@@ -51,17 +52,25 @@ struct PermFields {
     int32_t *slot;      // ensemble only: run slot of each particle (else null)
 };
 
+// Below a cell's Morton code the sort key holds the particle's z slice in the
+// cell (at most kSliceBits bits), so that each cell's particles are ordered by
+// z and a search can skip the slices out of reach.
+constexpr int kSliceBits = 6;
+
 // ---------------------------------------------------------------------------
 // Ensemble (many independent runs in one arena).
 //
-// Key of a particle of run slot s: (s << 3 kEnsAxisBits) | Morton(cell), so
-// one stable radix sort over kEnsKeyBits bits groups the particles by run and,
-// inside a run, by cell, exactly as the single-run sort does. A run being
-// dropped gets the all-ones key and sorts behind every live particle.
+// Key of a particle of run slot s:
+//   (s << (3 kEnsAxisBits + kSliceBits)) | (Morton(cell) << kSliceBits) | slice,
+// so one stable radix sort over kEnsKeyBits bits groups the particles by run
+// and, inside a run, by cell and by z slice, exactly as the single-run sort
+// does for the same run. A run being dropped gets the all-ones key and sorts
+// behind every live particle.
 constexpr int kEnsAxisBits = 5;                     // <= 32 cells per axis per run
 constexpr int kEnsSlotBits = 9;
 constexpr int kEnsMaxSlots = (1 << kEnsSlotBits) - 1;  // slot 511 is the drop key
-constexpr int kEnsKeyBits = kEnsSlotBits + 3 * kEnsAxisBits;
+constexpr int kEnsSlotShift = 3 * kEnsAxisBits + kSliceBits;
+constexpr int kEnsKeyBits = kEnsSlotBits + kEnsSlotShift;
 constexpr uint32_t kEnsMortonMask = (1u << (3 * kEnsAxisBits)) - 1u;
 constexpr uint32_t kEnsDropKey = 0xFFFFFFFFu;
 constexpr int kEnsFields = 11;  // x y z vx vy vz u h m p_bg rho_ref (rows of one block)
@@ -166,6 +175,7 @@ struct sph_ctx_s {
     int32_t *cell_end = nullptr;
     int64_t cell_cap = 0;
     uint32_t *nb_mask = nullptr;     // search bit masks: kSearchMaskWords words per particle slot
+    double *cell_s2max = nullptr;    // per cell: largest (2h)^2 of its particles
     int32_t *fb_tiles = nullptr;     // search tiles left to the per-lane path
     uint32_t *fb_count = nullptr;
     uint32_t *it_words = nullptr;    // h iteration: out-of-band count, largest count
