@@ -153,7 +153,8 @@ sph_status sph_ctx_check(sph_ctx ctx);
 int64_t sph_ctx_scratch_bytes(sph_ctx ctx);
 
 /* Algorithm 1, step 1. Assign every particle to a cell of side
- * >= 2 h_max (1 + 1e-9), sort the particles by the cell's Morton key (stable
+ * >= 2 h_max (1 + 1e-9), sort the particles by the cell's Morton key and,
+ * inside a cell, by the particle's z slice (up to 64 slices per cell; stable
  * LSD radix sort, so equal keys keep their previous order), reorder all
  * particle arrays of p in place and build the cell table. h_max is the
  * caller's bound on h (no device-to-host copy); a particle with h > h_max
@@ -180,7 +181,9 @@ sph_status sph_density(sph_ctx ctx, const sph_particles *p,
 sph_status sph_eos(sph_ctx ctx, const sph_particles *p, const sph_params *prm,
                    const sph_fields *f);
 
-/* Algorithm 1, step 3: acceleration, du/dt and per-particle max |mu|. */
+/* Algorithm 1, step 3: acceleration, du/dt and per-particle max |mu|.
+ * Like sph_find_neighbors, it takes h as of the last sph_build_cells (h must
+ * not change between the build and the pair calls of a step). */
 sph_status sph_momentum_energy(sph_ctx ctx, const sph_particles *p,
                                const sph_box *box, const sph_nbrs *nb,
                                const sph_params *prm, const sph_fields *f,

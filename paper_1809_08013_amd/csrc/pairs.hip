@@ -163,12 +163,27 @@ __device__ __forceinline__ Img lane_img(const Grid &g, const BatchDev &b, int64_
     return m;
 }
 
+// Per >= 0: the periodic axes are known at compile time (bit a set for a
+// periodic axis a), so the other axes carry no image code; Per = -1: decided
+// at run time from m.
+template <int Per>
 __device__ __forceinline__ double img(double d, const Img &m, int a)
 {
-    return min_image(d, m.per[a], m.len[a], m.half[a]);
+    if constexpr (Per >= 0)
+        return ((Per >> a) & 1) ? min_image(d, 1, m.len[a], m.half[a]) : d;
+    else
+        return min_image(d, m.per[a], m.len[a], m.half[a]);
 }
 
-template <bool F32, bool Multi, bool Big>
+// Compile-time periodic mask for a single run's grid: the common cases get
+// their own kernels, any other mix is decided at run time.
+inline int per_mask(const Grid &g)
+{
+    const int m = (g.periodic[0] ? 1 : 0) | (g.periodic[1] ? 2 : 0) | (g.periodic[2] ? 4 : 0);
+    return (m == 0 || m == 4 || m == 7) ? m : -1;
+}
+
+template <bool F32, bool Multi, bool Big, int Per>
 __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld,
                                              const DensRec *__restrict__ drec,
                                              const double *__restrict__ h,
@@ -218,9 +233,9 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
         const double2 lo = *reinterpret_cast<const double2 *>(dst_own);
         const double2 hi = *reinterpret_cast<const double2 *>(dst_own + 16);
         if (k < cnt) {
-            const R dx = (R)img(me.x - lo.x, im, 0);
-            const R dy = (R)img(me.y - lo.y, im, 1);
-            const R dz = (R)img(me.z - hi.x, im, 2);
+            const R dx = (R)img<Per>(me.x - lo.x, im, 0);
+            const R dy = (R)img<Per>(me.y - lo.y, im, 1);
+            const R dz = (R)img<Per>(me.z - hi.x, im, 2);
             const R r = fast_sqrt(fma_r(dz, dz, fma_r(dy, dy, dx * dx)));
             sum = fma_r((R)hi.y, m4_w(r * inv_h), sum);
         }
@@ -228,7 +243,7 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
     if (active) rho[i] = (double)(sum * ((R)kInvPi * inv_h * inv_h * inv_h));
 }
 
-template <bool F32, bool Multi, bool Big>
+template <bool F32, bool Multi, bool Big, int Per>
 __global__ void __launch_bounds__(kThreads)
 density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
                const double *__restrict__ h, const int32_t *__restrict__ count,
@@ -241,10 +256,11 @@ density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
         const int64_t nn = b.hdr->n_out;
         const int64_t ntile = (nn + kThreads - 1) / kThreads;
         for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
-            density_tile<F32, true, Big>(t, nn, ld, drec, h, count, idx, max_nb, g, rho, b, buf);
+            density_tile<F32, true, Big, -1>(t, nn, ld, drec, h, count, idx, max_nb, g, rho, b,
+                                             buf);
     } else {
-        density_tile<F32, false, Big>(xcd_block(), n, ld, drec, h, count, idx, max_nb, g, rho,
-                                      b, buf);
+        density_tile<F32, false, Big, Per>(xcd_cu_block(), n, ld, drec, h, count, idx, max_nb, g,
+                                           rho, b, buf);
     }
 }
 
@@ -298,7 +314,10 @@ struct MomParams {
     double alpha, beta, eta2;
 };
 
-template <bool F32, bool Multi, bool Big>
+// UH: every particle has the same h. Then h_i = h_j bit for bit, the two
+// kernel slopes of the mean gradient are the same number t, and
+// 0.5 (t + t) = t exactly, so one evaluation gives the general form's result.
+template <bool F32, bool Multi, bool Big, int Per, bool UH>
 __device__ __forceinline__ void momentum_tile(
     int64_t tile, int64_t n, int64_t ld, const PairRec *__restrict__ rec,
     const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
@@ -374,20 +393,26 @@ __device__ __forceinline__ void momentum_tile(
         const double2 q4 = *reinterpret_cast<const double2 *>(own + 64);  // m rho
         const double2 q5 = *reinterpret_cast<const double2 *>(own + 80);  // c pr2
         if (k < cnt) {
-            const R dx = (R)img(mex - q0.x, im, 0);
-            const R dy = (R)img(mey - q0.y, im, 1);
-            const R dz = (R)img(mez - q1.x, im, 2);
+            const R dx = (R)img<Per>(mex - q0.x, im, 0);
+            const R dy = (R)img<Per>(mey - q0.y, im, 1);
+            const R dz = (R)img<Per>(mez - q1.x, im, 2);
             const R r2 = fma_r(dz, dz, fma_r(dy, dy, dx * dx));
             // 1/r (0 for coincident particles, whose gradient term vanishes)
             const R rinv = r2 > R(0) ? fast_rsq(r2) : R(0);
             const R r = r2 * rinv;
-            const R hj = (R)q3.x, inv_hj = (R)q3.y;
-            const R fj = (R)kInvPi * (inv_hj * inv_hj) * (inv_hj * inv_hj);
-            const R dwbar = R(0.5) * (fi * m4_dw(r * inv_hi) + fj * m4_dw(r * inv_hj));
+            R dwbar, hbar;
+            if constexpr (UH) {
+                dwbar = fi * m4_dw(r * inv_hi);
+                hbar = hi;
+            } else {
+                const R hj = (R)q3.x, inv_hj = (R)q3.y;
+                const R fj = (R)kInvPi * (inv_hj * inv_hj) * (inv_hj * inv_hj);
+                dwbar = R(0.5) * (fi * m4_dw(r * inv_hi) + fj * m4_dw(r * inv_hj));
+                hbar = R(0.5) * (hi + hj);
+            }
             const R F = dwbar * rinv;
             const R wx = (R)(mevx - q1.y), wy = (R)(mevy - q2.x), wz = (R)(mevz - q2.y);
             const R vdotr = fma_r(wz, dz, fma_r(wy, dy, wx * dx));
-            const R hbar = R(0.5) * (hi + hj);
             const R cbar = R(0.5) * (ci + (R)q5.x);
             const R rhobar = R(0.5) * (rhoi + (R)q4.y);
             // one reciprocal for both denominators: inv = 1 / (den rhobar)
@@ -412,13 +437,13 @@ __device__ __forceinline__ void momentum_tile(
     }
 }
 
-template <bool F32, bool Multi, bool Big>
+template <bool F32, bool Multi, bool Big, int Per>
 __global__ void __launch_bounds__(kThreads)
 momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
                 const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
                 Grid g, MomParams prm, double *__restrict__ ax, double *__restrict__ ay,
                 double *__restrict__ az, double *__restrict__ dudt, double *__restrict__ mumax,
-                BatchDev b)
+                BatchDev b, const uint32_t *__restrict__ hflag)
 {
     __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kMomStride];
     char *buf = lds[threadIdx.x >> 6];
@@ -426,11 +451,15 @@ momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
         const int64_t nn = b.hdr->n_out;
         const int64_t ntile = (nn + kThreads - 1) / kThreads;
         for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
-            momentum_tile<F32, true, Big>(t, nn, ld, rec, count, idx, max_nb, g, prm, ax, ay,
-                                          az, dudt, mumax, b, buf);
+            momentum_tile<F32, true, Big, -1, false>(t, nn, ld, rec, count, idx, max_nb, g, prm,
+                                                     ax, ay, az, dudt, mumax, b, buf);
+    } else if (hflag[0] == 0u) {
+        // uniform h (flag of the last cell build)
+        momentum_tile<F32, false, Big, Per, true>(xcd_block(), n, ld, rec, count, idx, max_nb,
+                                                  g, prm, ax, ay, az, dudt, mumax, b, buf);
     } else {
-        momentum_tile<F32, false, Big>(xcd_block(), n, ld, rec, count, idx, max_nb, g, prm, ax,
-                                       ay, az, dudt, mumax, b, buf);
+        momentum_tile<F32, false, Big, Per, false>(xcd_block(), n, ld, rec, count, idx, max_nb,
+                                                   g, prm, ax, ay, az, dudt, mumax, b, buf);
     }
 }
 
@@ -501,33 +530,54 @@ void density_launch(hipStream_t st, unsigned blocks, int precision, bool big, in
                     int64_t ld, const DensRec *drec, const double *h, const int32_t *count,
                     const int32_t *idx, int max_nb, const Grid &g, double *rho, const BatchDev &b)
 {
+#define SPH_DENS_P(F, B, P)                                                                \
+    density_kernel<F, Multi, B, P><<<blocks, kThreads, 0, st>>>(n, ld, drec, h, count, idx, \
+                                                                max_nb, g, rho, b)
 #define SPH_DENS(F, B)                                                                     \
-    density_kernel<F, Multi, B><<<blocks, kThreads, 0, st>>>(n, ld, drec, h, count, idx,  \
-                                                             max_nb, g, rho, b)
+    do {                                                                                   \
+        const int pm = Multi ? -1 : per_mask(g);                                           \
+        if constexpr (Multi) SPH_DENS_P(F, B, -1);                                         \
+        else if (pm == 0) SPH_DENS_P(F, B, 0);                                             \
+        else if (pm == 4) SPH_DENS_P(F, B, 4);                                             \
+        else if (pm == 7) SPH_DENS_P(F, B, 7);                                             \
+        else SPH_DENS_P(F, B, -1);                                                         \
+    } while (0)
     if (precision == SPH_FP32_PAIR) {
         if (big) SPH_DENS(true, true); else SPH_DENS(true, false);
     } else {
         if (big) SPH_DENS(false, true); else SPH_DENS(false, false);
     }
 #undef SPH_DENS
+#undef SPH_DENS_P
 }
 
 template <bool Multi>
 void momentum_launch(hipStream_t st, unsigned blocks, int precision, bool big, int64_t n,
                      int64_t ld, const PairRec *rec, const int32_t *count, const int32_t *idx,
                      int max_nb, const Grid &g, const MomParams &mp, double *ax, double *ay,
-                     double *az, double *dudt, double *mumax, const BatchDev &b)
+                     double *az, double *dudt, double *mumax, const BatchDev &b,
+                     const uint32_t *hflag)
 {
+#define SPH_MOM_P(F, B, P)                                                                 \
+    momentum_kernel<F, Multi, B, P><<<blocks, kThreads, 0, st>>>(n, ld, rec, count, idx,  \
+                                                                 max_nb, g, mp, ax, ay, az, \
+                                                                 dudt, mumax, b, hflag)
 #define SPH_MOM(F, B)                                                                      \
-    momentum_kernel<F, Multi, B><<<blocks, kThreads, 0, st>>>(n, ld, rec, count, idx,     \
-                                                              max_nb, g, mp, ax, ay, az,   \
-                                                              dudt, mumax, b)
+    do {                                                                                   \
+        const int pm = Multi ? -1 : per_mask(g);                                           \
+        if constexpr (Multi) SPH_MOM_P(F, B, -1);                                         \
+        else if (pm == 0) SPH_MOM_P(F, B, 0);                                              \
+        else if (pm == 4) SPH_MOM_P(F, B, 4);                                              \
+        else if (pm == 7) SPH_MOM_P(F, B, 7);                                              \
+        else SPH_MOM_P(F, B, -1);                                                          \
+    } while (0)
     if (precision == SPH_FP32_PAIR) {
         if (big) SPH_MOM(true, true); else SPH_MOM(true, false);
     } else {
         if (big) SPH_MOM(false, true); else SPH_MOM(false, false);
     }
 #undef SPH_MOM
+#undef SPH_MOM_P
 }
 
 }  // namespace
@@ -562,7 +612,7 @@ hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &
         p.n, nullptr, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2, ctx->prec);
     momentum_launch<false>(ctx->stream, nblk, prm.precision, big_records(p.n, sizeof(PairRec)),
                            p.n, p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp,
-                           a.ax, a.ay, a.az, a.dudt, a.mumax, BatchDev{});
+                           a.ax, a.ay, a.az, a.dudt, a.mumax, BatchDev{}, ctx->hflag_dev);
     return hipGetLastError();
 }
 
@@ -609,7 +659,7 @@ hipError_t launch_momentum_batch(sph_ctx ctx, const BatchDev &b, int precision,
                                                   pr2, ctx->prec);
     momentum_launch<true>(ctx->stream, g2, precision, big_records(cap, sizeof(PairRec)), 0, cap,
                           ctx->prec, count, idx, max_nb, Grid{}, MomParams{}, ax, ay, az, dudt,
-                          mumax, b);
+                          mumax, b, nullptr);
     return hipGetLastError();
 }
 

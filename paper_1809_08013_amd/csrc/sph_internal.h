@@ -153,6 +153,21 @@ __device__ __forceinline__ int64_t xcd_block()
                  : (int64_t)r * (q + 1) + (int64_t)(x - r) * q + pos;
 }
 
+// xcd_block, refined per CU: the blocks an XCD receives are handed out to
+// its 32 CUs in turn, so block pos of the XCD is mapped to the pos / 32-th
+// entry of CU pos % 32's own contiguous range. Blocks resident on one CU then
+// work on neighbouring tiles and share their neighbours' records in its L1.
+__device__ __forceinline__ int64_t xcd_cu_block()
+{
+    const uint32_t B = gridDim.x, b = blockIdx.x;
+    const uint32_t q = B / 8, r = B % 8, x = b % 8, pos = b / 8;
+    const uint32_t nb = q + (x < r ? 1u : 0u);  // blocks of this XCD
+    const int64_t base = x < r ? (int64_t)x * (q + 1) : (int64_t)r * (q + 1) + (int64_t)(x - r) * q;
+    constexpr uint32_t kCus = 32;
+    const uint32_t qc = nb / kCus, rc = nb % kCus, c = pos % kCus, round = pos / kCus;
+    return base + (int64_t)(c * qc + (c < rc ? c : rc)) + round;
+}
+
 }  // namespace sph
 
 struct sph_ctx_s {
