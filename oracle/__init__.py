@@ -23,7 +23,7 @@ import numpy as np
 from . import build as _build
 
 __all__ = [
-    "lib", "kernel_w", "kernel_dwdr", "neighbors", "neighbors_brute",
+    "lib", "set_kernel", "kernel_sigma", "kernel_w", "kernel_dwdr", "neighbors", "neighbors_brute",
     "smoothing_length", "density", "eos", "momentum_energy", "timestep",
     "integrate", "diagnostics", "gravity_direct", "OracleRun", "num_threads",
 ]
@@ -48,6 +48,10 @@ def lib():
             L.orc_kernel_w.argtypes = [C.c_double, C.c_double]
             L.orc_kernel_dwdr.restype = C.c_double
             L.orc_kernel_dwdr.argtypes = [C.c_double, C.c_double]
+            L.orc_set_kernel.restype = C.c_int32
+            L.orc_set_kernel.argtypes = [C.c_int32, C.c_int32]
+            L.orc_kernel_sigma.restype = C.c_double
+            L.orc_kernel_sigma.argtypes = []
             nb_args = [C.c_int64, _D, _D, _D, _D, _D, _D, _I32, C.c_int64, _I64, _I32]
             L.orc_neighbors_brute.restype = C.c_int64
             L.orc_neighbors_brute.argtypes = nb_args
@@ -102,6 +106,21 @@ def _box(lo, hi, periodic):
 
 def _dn(a):
     return None if a is None else _d(a).ctypes.data
+
+
+KERNEL_M4, KERNEL_WENDLAND_C2, KERNEL_SINC = 0, 1, 2
+
+
+def set_kernel(family: int, n: int = 5) -> None:
+    """Select the kernel used by kernel_w/dwdr, density and momentum_energy
+    (0 M4, 1 Wendland C2, 2 sinc of exponent n); see sph_oracle.c."""
+    if lib().orc_set_kernel(int(family), int(n)) != 0:
+        raise ValueError(f"unknown kernel {family} (n = {n})")
+
+
+def kernel_sigma() -> float:
+    """W(0, h) h^3 of the current kernel."""
+    return lib().orc_kernel_sigma()
 
 
 def kernel_w(r: float, h: float) -> float:

@@ -13,7 +13,9 @@
  * update velocity and position (step 6). The paper names the ingredients but
  * not their formulas; the readings used (each a textbook choice) are:
  *
- *   kernel    M4 cubic spline (Table 1, ChaNGa), W = w(r/h) / (pi h^3)
+ *   kernel    M4 cubic spline (Table 1, ChaNGa), W = w(r/h) / (pi h^3); the
+ *             mini-app's other interchangeable kernels (Sec. 4, Table 2)
+ *             are selectable: Wendland C2 and the sinc family (orc_set_kernel)
  *   gradient  kernel derivatives, standard volume elements m/rho (Table 1)
  *   density   summation, self term included, gather with h_i
  *   variable h  neighbour iff r^2 < (2 max(h_i, h_j))^2; gradient is the
@@ -59,16 +61,110 @@ static double m4_dw(double q)
     return 0.0;
 }
 
-/* W(r, h) in 3D, sigma = 1/pi. */
+/*
+ * The other kernels of the mini-app's interchangeable set (Sec. 4, Table 2;
+ * Table 1 names Wendland for ChaNGa and SPH-flow and the sinc family for
+ * SPHYNX). All have support 2h, so the neighbour relation is unchanged.
+ *
+ * Wendland C2 in 3D (Wendland 1995), written for support H = 2h:
+ *   W = 21 / (2 pi H^3) (1 - r/H)^4 (1 + 4 r/H)
+ * which with q = r/h is 21 / (16 pi h^3) (1 - q/2)^4 (1 + 2q).
+ *
+ * Sinc family (Cabezon, Garcia-Senz & Relano 2008): with S(x) = sin(x)/x,
+ *   W = B_n / h^3 S(pi q / 2)^n for q < 2,
+ * B_n from the normalisation 4 pi int_0^2 q^2 S(pi q/2)^n dq = 1.
+ */
+static int32_t g_kernel = 0;     /* 0 M4, 1 Wendland C2, 2 sinc */
+static int32_t g_sinc_n = 5;
+static double g_sinc_b = 0.0;    /* B_n of the current exponent */
+
+static double sinc_s(double x)
+{
+    if (x == 0.0) return 1.0;
+    return sin(x) / x;
+}
+
+/* dS/dx = (x cos x - sin x) / x^2, with its series near 0 */
+static double sinc_ds(double x)
+{
+    if (fabs(x) < 1e-4) return -x / 3.0 + x * x * x / 30.0;
+    return (x * cos(x) - sin(x)) / (x * x);
+}
+
+static double sinc_shape(double q)
+{
+    if (q >= 2.0) return 0.0;
+    return pow(sinc_s(0.5 * ORC_PI * q), (double)g_sinc_n);
+}
+
+/* B_n by composite Simpson's rule on [0, 2] */
+static double sinc_norm(void)
+{
+    const int k = 20000;
+    const double dq = 2.0 / k;
+    double acc = 0.0;
+    for (int i = 0; i <= k; ++i) {
+        double q = i * dq;
+        double f = q * q * sinc_shape(q);
+        double wgt = (i == 0 || i == k) ? 1.0 : ((i & 1) ? 4.0 : 2.0);
+        acc += wgt * f;
+    }
+    return 1.0 / (4.0 * ORC_PI * acc * dq / 3.0);
+}
+
+/* Select the kernel of orc_kernel_w/dwdr, orc_density and
+ * orc_momentum_energy: 0 M4 (default), 1 Wendland C2, 2 sinc of exponent n
+ * (3 <= n <= 12). Returns 0, or -1 for an unknown choice. Not thread-safe:
+ * call it between evaluations. */
+int32_t orc_set_kernel(int32_t family, int32_t n)
+{
+    if (family < 0 || family > 2) return -1;
+    if (family == 2 && (n < 3 || n > 12)) return -1;
+    g_kernel = family;
+    if (family == 2) {
+        g_sinc_n = n;
+        g_sinc_b = sinc_norm();
+    }
+    return 0;
+}
+
+/* The normalisation constant of the current kernel: W(0, h) h^3. */
+double orc_kernel_sigma(void)
+{
+    if (g_kernel == 1) return 21.0 / (16.0 * ORC_PI);
+    if (g_kernel == 2) return g_sinc_b;
+    return 1.0 / ORC_PI;
+}
+
+/* W(r, h) in 3D. */
 double orc_kernel_w(double r, double h)
 {
-    return m4_w(r / h) / (ORC_PI * h * h * h);
+    double q = r / h;
+    if (g_kernel == 1) {
+        if (q >= 2.0) return 0.0;
+        double t = 1.0 - 0.5 * q;
+        return 21.0 / (16.0 * ORC_PI * h * h * h) * t * t * t * t * (1.0 + 2.0 * q);
+    }
+    if (g_kernel == 2) return g_sinc_b / (h * h * h) * sinc_shape(q);
+    return m4_w(q) / (ORC_PI * h * h * h);
 }
 
 /* dW/dr (r, h) in 3D. */
 double orc_kernel_dwdr(double r, double h)
 {
-    return m4_dw(r / h) / (ORC_PI * h * h * h * h);
+    double q = r / h;
+    if (g_kernel == 1) {
+        if (q >= 2.0) return 0.0;
+        double t = 1.0 - 0.5 * q;
+        return -105.0 / (16.0 * ORC_PI * h * h * h * h) * q * t * t * t;
+    }
+    if (g_kernel == 2) {
+        if (q >= 2.0) return 0.0;
+        double x = 0.5 * ORC_PI * q;
+        return g_sinc_b / (h * h * h * h) * (double)g_sinc_n *
+               pow(sinc_s(x), (double)(g_sinc_n - 1)) * sinc_ds(x) * 0.5 * ORC_PI;
+    }
+    return m4_dw(q) / (ORC_PI * h * h * h * h);
 }
 
 /* ------------------------------------------------------------ geometry */

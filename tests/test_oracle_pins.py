@@ -109,6 +109,81 @@ def test_T3_kernel_normalisation_and_shape():
         assert O.kernel_dwdr(r, h) == pytest.approx(fd, rel=1e-7, abs=1e-9)
 
 
+KERNEL_CASES = [(O.KERNEL_WENDLAND_C2, 5), (O.KERNEL_SINC, 3), (O.KERNEL_SINC, 5),
+                (O.KERNEL_SINC, 9)]
+
+
+@pytest.fixture
+def kernel_choice(request):
+    family, n = request.param
+    O.set_kernel(family, n)
+    yield family, n
+    O.set_kernel(O.KERNEL_M4, 5)
+
+
+def _sinc_shape(q, n):
+    x = 0.5 * math.pi * q
+    return (math.sin(x) / x if x else 1.0) ** n if q < 2 else 0.0
+
+
+@pytest.mark.parametrize("kernel_choice", KERNEL_CASES, indirect=True)
+def test_T3_other_kernels(kernel_choice):
+    """Wendland C2 and the sinc family (the mini-app's interchangeable kernels,
+    Sec. 4, Table 2): unit integral (adaptive quadrature, independent of the
+    oracle's Simpson rule for B_n), closed-form values at q = 0 and q = 1,
+    compact support 2h, and dW/dr the derivative of W."""
+    family, n = kernel_choice
+    h = 0.37
+    val, _ = sint.quad(lambda r: 4 * math.pi * r * r * O.kernel_w(r, h), 0, 2 * h,
+                       epsabs=1e-14, epsrel=1e-13, limit=200)
+    assert abs(val - 1.0) < 1e-12
+    if family == O.KERNEL_WENDLAND_C2:
+        sigma = 21 / (16 * math.pi)
+        w1 = sigma * 0.5 ** 4 * 3
+    else:
+        integral, _ = sint.quad(lambda q: q * q * _sinc_shape(q, n), 0, 2,
+                                epsabs=1e-15, epsrel=1e-14, limit=200)
+        sigma = 1 / (4 * math.pi * integral)
+        w1 = sigma * (2 / math.pi) ** n
+    assert O.kernel_sigma() == pytest.approx(sigma, rel=1e-12)
+    assert O.kernel_w(0.0, h) == pytest.approx(sigma / h ** 3, rel=1e-12)
+    assert O.kernel_w(h, h) == pytest.approx(w1 / h ** 3, rel=1e-12)
+    assert O.kernel_dwdr(0.0, h) == 0.0
+    assert O.kernel_w(2 * h, h) == 0.0 and O.kernel_dwdr(2 * h, h) == 0.0
+    assert O.kernel_w(2 * h * (1 - 1e-6), h) < 1e-12 * O.kernel_w(0.0, h)
+    for q in (1e-3, 0.1, 0.5, 0.9, 1.2, 1.7, 1.95):
+        r, d = q * h, 1e-6 * h
+        fd = (O.kernel_w(r + d, h) - O.kernel_w(r - d, h)) / (2 * d)
+        assert O.kernel_dwdr(r, h) == pytest.approx(fd, rel=1e-7, abs=1e-9)
+
+
+@pytest.mark.parametrize("kernel_choice", KERNEL_CASES[:2], indirect=True)
+def test_T5_T7_other_kernels(kernel_choice):
+    """The symmetry invariants hold for any radial kernel: no force in a
+    uniform periodic lattice, sum m a = 0 and power balance on a cloud."""
+    lat = I.lattice_periodic(12, spacing=2.0 ** -4)
+    lat.p_bg[:] = 3.0
+    r = _run_forces(lat)
+    acc = O.momentum_energy(*(r.s[k] for k in ("x", "y", "z", "vx", "vy", "vz", "h", "m")),
+                            r.rho, r.c, r.pr2, lat.lo, lat.hi, lat.periodic, r.off,
+                            r.ids, lat.params, scales=True)
+    amag = np.sqrt(acc["ax"] ** 2 + acc["ay"] ** 2 + acc["az"] ** 2)
+    assert (acc["sa"] > 0).all() and (amag <= 1e-14 * acc["sa"]).all()
+    ic = I.random_cloud(2000, seed=12, h_min=0.04, h_max=0.07, velocity=2.0)
+    r = _run_forces(ic, rho_ref=np.full(ic.n, 1.0))
+    s = r.s
+    acc = O.momentum_energy(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["h"],
+                            s["m"], r.rho, r.c, r.pr2, ic.lo, ic.hi, ic.periodic,
+                            r.off, r.ids, ic.params, scales=True)
+    m = s["m"]
+    F = np.array([np.sum(m * acc[k]) for k in ("ax", "ay", "az")])
+    assert np.linalg.norm(F) <= 1e-13 * np.sum(m * acc["sa"])
+    vmag = np.sqrt(s["vx"] ** 2 + s["vy"] ** 2 + s["vz"] ** 2)
+    power = np.sum(m * (s["vx"] * acc["ax"] + s["vy"] * acc["ay"] + s["vz"] * acc["az"]
+                        + acc["dudt"]))
+    assert abs(power) <= 1e-13 * np.sum(m * (vmag * acc["sa"] + acc["su"]))
+
+
 # ---------------------------------------------------------------- T4 -------
 def test_T4_lattice_normalisation():
     """Periodic lattice, h = 1.5 d: rho/rho0 is the exact finite lattice sum
