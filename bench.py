@@ -403,6 +403,51 @@ def run_serving(runs: int, steps: int = 50, budget_gib: float = 8.0) -> dict:
     return out
 
 
+def run_kernels(ic, steps: int, warmup: int) -> dict:
+    """The interchangeable kernels (M4, Wendland C2, sinc n = 5) on the same
+    neighbour lists: time per sph_density and per sph_momentum_energy call,
+    FP64, and the pair rate of the two together."""
+    import dataclasses
+
+    import torch
+
+    from paper_1809_08013_amd import sph as S
+
+    log("kernel families")
+    ctx = S.Context(ic.n, 128)
+    st = S.SphState(ic, 128)
+    S.sph_init_forces(ctx, st, S.make_params(ic.params), set_rho_ref=True)
+    S.sph_ctx_check(ctx)
+    pairs = float(st.t["count"][: ic.n].sum().item())
+    out = {"workload": "rotating square patch 100^3, the same lists; density and "
+                       "momentum/energy calls only", "pairs": pairs}
+    stream = ctx.stream
+    for name, fam, n in (("m4", S.SPH_KERNEL_M4, 5), ("wendland_c2", S.SPH_KERNEL_WENDLAND_C2, 5),
+                         ("sinc_5", S.SPH_KERNEL_SINC, 5)):
+        prm = S.make_params(dataclasses.replace(ic.params, kernel=fam, sinc_n=n))
+        for _ in range(warmup):
+            S.sph_density(ctx, st, prm)
+            S.sph_eos(ctx, st, prm)
+            S.sph_momentum_energy(ctx, st, prm)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        dens = mom = 0.0
+        for _ in range(steps):
+            ev[0].record(stream)
+            S.sph_density(ctx, st, prm)
+            ev[1].record(stream)
+            S.sph_eos(ctx, st, prm)
+            S.sph_momentum_energy(ctx, st, prm)
+            ev[2].record(stream)
+            torch.cuda.synchronize()
+            dens += ev[0].elapsed_time(ev[1])
+            mom += ev[1].elapsed_time(ev[2])
+        S.sph_ctx_check(ctx)
+        d, m = dens / steps, mom / steps
+        out[name] = {"density_ms": round(d, 4), "eos_plus_momentum_ms": round(m, 4),
+                     "pair_rate_both": 2 * pairs / ((d + m) * 1e-3)}
+    return out
+
+
 def run_trajectory(n_side: int, steps: int) -> dict:
     """Per-field error of the GPU runs (FP64 and FP32-pair) against the FP64
     oracle after `steps` KDK steps from the same state (each path with its own
@@ -486,6 +531,8 @@ def main():
                          "STEPS steps on the same patch")
     ap.add_argument("--serve-runs", type=int, default=512,
                     help="ensemble serving requests (0 skips the serving leg)")
+    ap.add_argument("--no-kernels", action="store_true",
+                    help="skip the timing of the Wendland C2 and sinc kernels")
     ap.add_argument("--large", type=int, default=0, metavar="N_SIDE",
                     help="also time a large square patch of N_SIDE^3 particles "
                          "(400 gives 64,000,000), 20 steps after 2 warm-up steps")
@@ -550,6 +597,8 @@ def main():
             "roofline": roofline(n, r32, 1),
             "step_hbm": step_hbm(n, r32, 1),
         }
+    if not args.no_kernels:
+        line["kernels"] = run_kernels(ic, min(args.steps, 20), 2)
     if args.trajectory > 0:
         line["trajectory"] = run_trajectory(args.n_side, args.trajectory)
     if args.serve_runs > 0:

@@ -113,18 +113,31 @@ typedef struct {
     double *ax, *ay, *az, *dudt, *mumax;
 } sph_accel;
 
+/* Interpolation kernels: the interchangeable set of the mini-app (Sec. 4,
+ * Table 2; Table 1 lists which parent code uses which). All have support 2h,
+ * so the neighbour relation does not depend on the choice; q = r/h:
+ *   SPH_KERNEL_M4           W = w(q) / (pi h^3), the M4 cubic spline
+ *   SPH_KERNEL_WENDLAND_C2  W = 21 / (16 pi h^3) (1 - q/2)^4 (1 + 2q)
+ *   SPH_KERNEL_SINC         W = B_n / h^3 (sin(x)/x)^n, x = pi q / 2, with
+ *                           B_n normalising W to unit integral, 3 <= n <= 12 */
+enum { SPH_KERNEL_M4 = 0, SPH_KERNEL_WENDLAND_C2 = 1, SPH_KERNEL_SINC = 2 };
+
 /* Scalar physics constants (host memory). precision selects the pair
  * arithmetic of sph_density and sph_momentum_energy: SPH_FP64, or
  * SPH_FP32_PAIR (separations formed in FP64 and rounded to FP32, FP32 copies
  * of h, m, rho, P/rho^2 and c, FP32 accumulation, results widened to FP64;
  * the neighbour relation, the state, the integration and all reductions stay
- * FP64). */
+ * FP64). kernel selects W and its gradient in both pair calls (zero, the
+ * default of a zeroed struct, is M4); sinc_n is the sinc exponent, read only
+ * for SPH_KERNEL_SINC. */
 typedef struct {
     int32_t precision;
     int32_t eos;
     double rho0, c0, gamma_tait, gamma_gas;
     double alpha, beta, eta2;
     double c_cfl, c_force;
+    int32_t kernel;
+    int32_t sinc_n;
 } sph_params;
 
 /* Text for a status code (static storage). */
@@ -292,7 +305,8 @@ typedef struct {
     int64_t n;                 /* particles, >= 1, <= max_n_per_run */
     int32_t n_steps;           /* KDK steps after the t = 0 evaluation, >= 0 */
     int32_t set_rho_ref;       /* Tait: rho_ref := rho at t = 0 */
-    sph_params params;         /* params.precision is ignored (engine's) */
+    sph_params params;         /* params.precision is ignored (engine's);
+                                  params.kernel must be SPH_KERNEL_M4 */
     sph_box box;
     double h_max;              /* >= every h (h stays fixed); sets the cells */
     /* HOST arrays of n entries in any order, copied by sph_ens_submit

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/sph.h: argument checks, the
 // context and its scratch, grid set-up and the order of launches.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -17,6 +18,45 @@ namespace sph {
 // Grid of cells of side >= 2 h_max (1 + 1e-9) on every axis, at most
 // max_axis cells per axis and cell_cap in total (coarser cells only add
 // candidates: the relation test is exact).
+// Normalisation of the sinc kernel of exponent n: B_n = 1 / (4 pi I_n) with
+// I_n = int_0^2 q^2 (sin(x)/x)^n dq, x = pi q / 2, by the 5-point
+// Gauss-Legendre rule on 400 panels (the integrand is analytic; the rule is
+// exact to rounding here). One table for n = 3..12, filled once.
+static double sinc_norm(int n)
+{
+    static const double node[5] = {-0.9061798459386640, -0.5384693101056831, 0.0,
+                                   0.5384693101056831, 0.9061798459386640};
+    static const double wgt[5] = {0.2369268850561891, 0.4786286704993665,
+                                  0.5688888888888889, 0.4786286704993665,
+                                  0.2369268850561891};
+    const int panels = 400;
+    const double half = 1.0 / panels;  // half width of a panel of [0, 2]
+    double acc = 0.0;
+    for (int k = 0; k < panels; ++k) {
+        const double mid = (2 * k + 1) * half;
+        for (int t = 0; t < 5; ++t) {
+            const double q = mid + half * node[t];
+            const double x = 0.5 * M_PI * q;
+            const double sx = std::sin(x) / x;
+            acc += wgt[t] * q * q * std::pow(sx, n);
+        }
+    }
+    return 1.0 / (4.0 * M_PI * acc * half);
+}
+
+KernelSel kernel_sel(const sph_params &prm)
+{
+    static const std::array<double, 13> sinc_b = [] {
+        std::array<double, 13> t{};
+        for (int n = 3; n <= 12; ++n) t[n] = sinc_norm(n);
+        return t;
+    }();
+    KernelSel k{prm.kernel, prm.sinc_n, 1.0 / M_PI};
+    if (prm.kernel == SPH_KERNEL_WENDLAND_C2) k.sigma = 21.0 / (16.0 * M_PI);
+    if (prm.kernel == SPH_KERNEL_SINC) k.sigma = sinc_b[prm.sinc_n];
+    return k;
+}
+
 Grid make_grid(const sph_box &b, double h_max, int64_t cell_cap, int max_axis)
 {
     Grid g{};
@@ -124,6 +164,11 @@ sph_status check_params(sph_ctx ctx, const sph_params *prm)
         return fail(ctx, SPH_E_INVALID, "unknown precision %d", prm->precision);
     if (prm->eos != SPH_EOS_TAIT && prm->eos != SPH_EOS_IDEAL)
         return fail(ctx, SPH_E_INVALID, "unknown eos %d", prm->eos);
+    if (prm->kernel != SPH_KERNEL_M4 && prm->kernel != SPH_KERNEL_WENDLAND_C2 &&
+        prm->kernel != SPH_KERNEL_SINC)
+        return fail(ctx, SPH_E_INVALID, "unknown kernel %d", prm->kernel);
+    if (prm->kernel == SPH_KERNEL_SINC && (prm->sinc_n < 3 || prm->sinc_n > 12))
+        return fail(ctx, SPH_E_INVALID, "sinc exponent %d outside [3, 12]", prm->sinc_n);
     return SPH_OK;
 }
 
@@ -343,7 +388,7 @@ sph_status sph_density(sph_ctx ctx, const sph_particles *p, const sph_box *box,
     if (ctx->n_built != p->n || !same_box(ctx->grid, *box))
         return fail(ctx, SPH_E_INVALID, "sph_build_cells was not called for these particles/box");
     if (p->n == 0) return SPH_OK;
-    SPH_HIP(ctx, launch_density(ctx, *p, *nb, prm->precision, rho));
+    SPH_HIP(ctx, launch_density(ctx, *p, *nb, prm->precision, kernel_sel(*prm), rho));
     return SPH_OK;
 }
 

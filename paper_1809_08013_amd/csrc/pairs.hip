@@ -97,6 +97,71 @@ __device__ __forceinline__ R m4_dw(R q)
     return q < one ? inner : outer;
 }
 
+// The other kernels of the interchangeable set, as shapes w(q) and dw/dq
+// with W = sigma w(q) / h^3 (sigma passed in): Wendland C2,
+// w = (1 - q/2)^4 (1 + 2q), and the sinc family, w = S(pi q / 2)^n with
+// S(x) = sin(x)/x. Both vanish for q >= 2 and have w(0) = 1, like M4.
+enum { KF_M4 = 0, KF_WENDLAND = 1, KF_SINC = 2 };
+
+__device__ __forceinline__ void sin_cos(double x, double *s, double *c) { sincos(x, s, c); }
+__device__ __forceinline__ void sin_cos(float x, float *s, float *c) { sincosf(x, s, c); }
+
+template <int KF, typename R>
+__device__ __forceinline__ R shape_w(R q, int n)
+{
+    if constexpr (KF == KF_M4) {
+        return m4_w(q);
+    } else if constexpr (KF == KF_WENDLAND) {
+        const R t = fmax(R(1) - R(0.5) * q, R(0));
+        const R t2 = t * t;
+        return t2 * t2 * fma_r(R(2), q, R(1));
+    } else {
+        if (!(q < R(2))) return R(0);
+        const R x = R(1.5707963267948966) * q;
+        R sx;
+        if (x < R(1e-4)) {
+            sx = R(1) - x * x * R(1.0 / 6.0);
+        } else {
+            sx = sin(x) / x;
+        }
+        R pw = sx;
+        for (int k = 1; k < n; ++k) pw *= sx;
+        return pw;
+    }
+}
+
+template <int KF, typename R>
+__device__ __forceinline__ R shape_dw(R q, int n)
+{
+    if constexpr (KF == KF_M4) {
+        return m4_dw(q);
+    } else if constexpr (KF == KF_WENDLAND) {
+        const R t = fmax(R(1) - R(0.5) * q, R(0));
+        return R(-5) * q * (t * t * t);
+    } else {
+        if (!(q < R(2))) return R(0);
+        const R x = R(1.5707963267948966) * q;
+        R sx, dsx;
+        // (x cos x - sin x) / x^2 cancels for small x: FP32 takes its series
+        // up to x^7 below x = 0.6 (truncation below 1e-8 relative there)
+        const R small = sizeof(R) == 4 ? R(0.6) : R(1e-4);
+        if (x < small) {
+            const R x2 = x * x;
+            sx = R(1) - x2 * (R(1.0 / 6.0) - x2 * (R(1.0 / 120.0) - x2 * R(1.0 / 5040.0)));
+            dsx = -x * (R(1.0 / 3.0) - x2 * (R(1.0 / 30.0) - x2 * (R(1.0 / 840.0) -
+                                                                    x2 * R(1.0 / 45360.0))));
+        } else {
+            R sn, cs;
+            sin_cos(x, &sn, &cs);
+            sx = sn / x;
+            dsx = (x * cs - sn) / (x * x);
+        }
+        R pw = R(1);
+        for (int k = 1; k < n; ++k) pw *= sx;  // S^(n-1)
+        return R(n) * pw * dsx * R(1.5707963267948966);
+    }
+}
+
 // 16 bytes at byte c of record j of an array of Size-byte records. Arrays
 // below 4 GiB use a 32-bit offset from the uniform base (the load then takes
 // the base from SGPRs and needs no 64-bit address arithmetic).
@@ -183,14 +248,15 @@ inline int per_mask(const Grid &g)
     return (m == 0 || m == 4 || m == 7) ? m : -1;
 }
 
-template <bool F32, bool Multi, bool Big, int Per>
+template <bool F32, bool Multi, bool Big, int Per, int KF>
 __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld,
                                              const DensRec *__restrict__ drec,
                                              const double *__restrict__ h,
                                              const int32_t *__restrict__ count,
                                              const int32_t *__restrict__ idx, int max_nb,
                                              const Grid &g, double *__restrict__ rho,
-                                             const BatchDev &b, char *buf)
+                                             const BatchDev &b, char *buf, double sigma,
+                                             int sinc_n)
 {
     using R = typename std::conditional<F32, float, double>::type;
     const int lane = threadIdx.x & 63;
@@ -237,18 +303,19 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
             const R dy = (R)img<Per>(me.y - lo.y, im, 1);
             const R dz = (R)img<Per>(me.z - hi.x, im, 2);
             const R r = fast_sqrt(fma_r(dz, dz, fma_r(dy, dy, dx * dx)));
-            sum = fma_r((R)hi.y, m4_w(r * inv_h), sum);
+            sum = fma_r((R)hi.y, shape_w<KF>(r * inv_h, sinc_n), sum);
         }
     }
-    if (active) rho[i] = (double)(sum * ((R)kInvPi * inv_h * inv_h * inv_h));
+    const R sg = KF == KF_M4 ? (R)kInvPi : (R)sigma;
+    if (active) rho[i] = (double)(sum * (sg * inv_h * inv_h * inv_h));
 }
 
-template <bool F32, bool Multi, bool Big, int Per>
+template <bool F32, bool Multi, bool Big, int Per, int KF>
 __global__ void __launch_bounds__(kThreads)
 density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
                const double *__restrict__ h, const int32_t *__restrict__ count,
                const int32_t *__restrict__ idx, int max_nb, Grid g, double *__restrict__ rho,
-               BatchDev b)
+               BatchDev b, double sigma, int sinc_n)
 {
     __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kDensStride];
     char *buf = lds[threadIdx.x >> 6];
@@ -256,11 +323,11 @@ density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
         const int64_t nn = b.hdr->n_out;
         const int64_t ntile = (nn + kThreads - 1) / kThreads;
         for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
-            density_tile<F32, true, Big, -1>(t, nn, ld, drec, h, count, idx, max_nb, g, rho, b,
-                                             buf);
+            density_tile<F32, true, Big, -1, KF>(t, nn, ld, drec, h, count, idx, max_nb, g, rho,
+                                                 b, buf, sigma, sinc_n);
     } else {
-        density_tile<F32, false, Big, Per>(xcd_cu_block(), n, ld, drec, h, count, idx, max_nb, g,
-                                           rho, b, buf);
+        density_tile<F32, false, Big, Per, KF>(xcd_cu_block(), n, ld, drec, h, count, idx,
+                                               max_nb, g, rho, b, buf, sigma, sinc_n);
     }
 }
 
@@ -312,12 +379,14 @@ constexpr int kMomStride = 112;  // LDS bytes per record: 96 + 16 padding
 
 struct MomParams {
     double alpha, beta, eta2;
+    double sigma;  // W(0, h) h^3 of the kernel (KF != KF_M4)
+    int sinc_n;
 };
 
 // UH: every particle has the same h. Then h_i = h_j bit for bit, the two
 // kernel slopes of the mean gradient are the same number t, and
 // 0.5 (t + t) = t exactly, so one evaluation gives the general form's result.
-template <bool F32, bool Multi, bool Big, int Per, bool UH>
+template <bool F32, bool Multi, bool Big, int Per, bool UH, int KF>
 __device__ __forceinline__ void momentum_tile(
     int64_t tile, int64_t n, int64_t ld, const PairRec *__restrict__ rec,
     const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
@@ -334,14 +403,16 @@ __device__ __forceinline__ void momentum_tile(
     MomParams prm = prm0;
     if constexpr (Multi) {
         const RunDev &r = b.runs[b.slot[ii]];
-        prm = MomParams{r.alpha, r.beta, r.eta2};
+        prm = MomParams{r.alpha, r.beta, r.eta2, 0.0, 0};
     }
     const PairRec *mp = rec + ii;
     const double mex = mp->x, mey = mp->y, mez = mp->z;
     const double mevx = mp->vx, mevy = mp->vy, mevz = mp->vz;
     const R hi = (R)mp->h, inv_hi = (R)mp->inv_h, rhoi = (R)mp->rho, ci = (R)mp->c,
             pi = (R)mp->pr2;
-    const R fi = (R)kInvPi * (inv_hi * inv_hi) * (inv_hi * inv_hi);
+    const R sg = KF == KF_M4 ? (R)kInvPi : (R)prm.sigma;
+    const int sn = prm.sinc_n;
+    const R fi = sg * (inv_hi * inv_hi) * (inv_hi * inv_hi);
     const R alpha = (R)prm.alpha, beta = (R)prm.beta, eta2 = (R)prm.eta2;
     R sx = 0, sy = 0, sz = 0, su = 0, mum = 0;
     const int cnt = active ? min(count[ii], max_nb) : 0;
@@ -402,12 +473,13 @@ __device__ __forceinline__ void momentum_tile(
             const R r = r2 * rinv;
             R dwbar, hbar;
             if constexpr (UH) {
-                dwbar = fi * m4_dw(r * inv_hi);
+                dwbar = fi * shape_dw<KF>(r * inv_hi, sn);
                 hbar = hi;
             } else {
                 const R hj = (R)q3.x, inv_hj = (R)q3.y;
-                const R fj = (R)kInvPi * (inv_hj * inv_hj) * (inv_hj * inv_hj);
-                dwbar = R(0.5) * (fi * m4_dw(r * inv_hi) + fj * m4_dw(r * inv_hj));
+                const R fj = sg * (inv_hj * inv_hj) * (inv_hj * inv_hj);
+                dwbar = R(0.5) * (fi * shape_dw<KF>(r * inv_hi, sn) +
+                                  fj * shape_dw<KF>(r * inv_hj, sn));
                 hbar = R(0.5) * (hi + hj);
             }
             const R F = dwbar * rinv;
@@ -437,7 +509,7 @@ __device__ __forceinline__ void momentum_tile(
     }
 }
 
-template <bool F32, bool Multi, bool Big, int Per>
+template <bool F32, bool Multi, bool Big, int Per, int KF>
 __global__ void __launch_bounds__(kThreads)
 momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
                 const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
@@ -451,15 +523,17 @@ momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
         const int64_t nn = b.hdr->n_out;
         const int64_t ntile = (nn + kThreads - 1) / kThreads;
         for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
-            momentum_tile<F32, true, Big, -1, false>(t, nn, ld, rec, count, idx, max_nb, g, prm,
-                                                     ax, ay, az, dudt, mumax, b, buf);
+            momentum_tile<F32, true, Big, -1, false, KF>(t, nn, ld, rec, count, idx, max_nb, g,
+                                                         prm, ax, ay, az, dudt, mumax, b, buf);
     } else if (hflag[0] == 0u) {
         // uniform h (flag of the last cell build)
-        momentum_tile<F32, false, Big, Per, true>(xcd_block(), n, ld, rec, count, idx, max_nb,
-                                                  g, prm, ax, ay, az, dudt, mumax, b, buf);
+        momentum_tile<F32, false, Big, Per, true, KF>(xcd_block(), n, ld, rec, count, idx,
+                                                      max_nb, g, prm, ax, ay, az, dudt, mumax,
+                                                      b, buf);
     } else {
-        momentum_tile<F32, false, Big, Per, false>(xcd_block(), n, ld, rec, count, idx, max_nb,
-                                                   g, prm, ax, ay, az, dudt, mumax, b, buf);
+        momentum_tile<F32, false, Big, Per, false, KF>(xcd_block(), n, ld, rec, count, idx,
+                                                       max_nb, g, prm, ax, ay, az, dudt, mumax,
+                                                       b, buf);
     }
 }
 
@@ -528,19 +602,22 @@ inline bool big_records(int64_t n, size_t rec) { return (uint64_t)n * rec >= (1u
 template <bool Multi>
 void density_launch(hipStream_t st, unsigned blocks, int precision, bool big, int64_t n,
                     int64_t ld, const DensRec *drec, const double *h, const int32_t *count,
-                    const int32_t *idx, int max_nb, const Grid &g, double *rho, const BatchDev &b)
+                    const int32_t *idx, int max_nb, const Grid &g, double *rho, const BatchDev &b,
+                    const KernelSel &ks)
 {
-#define SPH_DENS_P(F, B, P)                                                                \
-    density_kernel<F, Multi, B, P><<<blocks, kThreads, 0, st>>>(n, ld, drec, h, count, idx, \
-                                                                max_nb, g, rho, b)
+#define SPH_DENS_P(F, B, P, K)                                                             \
+    density_kernel<F, Multi, B, P, K><<<blocks, kThreads, 0, st>>>(                        \
+        n, ld, drec, h, count, idx, max_nb, g, rho, b, ks.sigma, ks.sinc_n)
 #define SPH_DENS(F, B)                                                                     \
     do {                                                                                   \
         const int pm = Multi ? -1 : per_mask(g);                                           \
-        if constexpr (Multi) SPH_DENS_P(F, B, -1);                                         \
-        else if (pm == 0) SPH_DENS_P(F, B, 0);                                             \
-        else if (pm == 4) SPH_DENS_P(F, B, 4);                                             \
-        else if (pm == 7) SPH_DENS_P(F, B, 7);                                             \
-        else SPH_DENS_P(F, B, -1);                                                         \
+        if constexpr (Multi) SPH_DENS_P(F, B, -1, KF_M4);                                  \
+        else if (ks.family == SPH_KERNEL_WENDLAND_C2) SPH_DENS_P(F, B, -1, KF_WENDLAND);    \
+        else if (ks.family == SPH_KERNEL_SINC) SPH_DENS_P(F, B, -1, KF_SINC);              \
+        else if (pm == 0) SPH_DENS_P(F, B, 0, KF_M4);                                      \
+        else if (pm == 4) SPH_DENS_P(F, B, 4, KF_M4);                                      \
+        else if (pm == 7) SPH_DENS_P(F, B, 7, KF_M4);                                      \
+        else SPH_DENS_P(F, B, -1, KF_M4);                                                  \
     } while (0)
     if (precision == SPH_FP32_PAIR) {
         if (big) SPH_DENS(true, true); else SPH_DENS(true, false);
@@ -556,20 +633,21 @@ void momentum_launch(hipStream_t st, unsigned blocks, int precision, bool big, i
                      int64_t ld, const PairRec *rec, const int32_t *count, const int32_t *idx,
                      int max_nb, const Grid &g, const MomParams &mp, double *ax, double *ay,
                      double *az, double *dudt, double *mumax, const BatchDev &b,
-                     const uint32_t *hflag)
+                     const uint32_t *hflag, int family)
 {
-#define SPH_MOM_P(F, B, P)                                                                 \
-    momentum_kernel<F, Multi, B, P><<<blocks, kThreads, 0, st>>>(n, ld, rec, count, idx,  \
-                                                                 max_nb, g, mp, ax, ay, az, \
-                                                                 dudt, mumax, b, hflag)
+#define SPH_MOM_P(F, B, P, K)                                                              \
+    momentum_kernel<F, Multi, B, P, K><<<blocks, kThreads, 0, st>>>(                       \
+        n, ld, rec, count, idx, max_nb, g, mp, ax, ay, az, dudt, mumax, b, hflag)
 #define SPH_MOM(F, B)                                                                      \
     do {                                                                                   \
         const int pm = Multi ? -1 : per_mask(g);                                           \
-        if constexpr (Multi) SPH_MOM_P(F, B, -1);                                         \
-        else if (pm == 0) SPH_MOM_P(F, B, 0);                                              \
-        else if (pm == 4) SPH_MOM_P(F, B, 4);                                              \
-        else if (pm == 7) SPH_MOM_P(F, B, 7);                                              \
-        else SPH_MOM_P(F, B, -1);                                                          \
+        if constexpr (Multi) SPH_MOM_P(F, B, -1, KF_M4);                                   \
+        else if (family == SPH_KERNEL_WENDLAND_C2) SPH_MOM_P(F, B, -1, KF_WENDLAND);        \
+        else if (family == SPH_KERNEL_SINC) SPH_MOM_P(F, B, -1, KF_SINC);                  \
+        else if (pm == 0) SPH_MOM_P(F, B, 0, KF_M4);                                       \
+        else if (pm == 4) SPH_MOM_P(F, B, 4, KF_M4);                                       \
+        else if (pm == 7) SPH_MOM_P(F, B, 7, KF_M4);                                       \
+        else SPH_MOM_P(F, B, -1, KF_M4);                                                   \
     } while (0)
     if (precision == SPH_FP32_PAIR) {
         if (big) SPH_MOM(true, true); else SPH_MOM(true, false);
@@ -583,14 +661,14 @@ void momentum_launch(hipStream_t st, unsigned blocks, int precision, bool big, i
 }  // namespace
 
 hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
-                          int precision, double *rho)
+                          int precision, const KernelSel &ks, double *rho)
 {
     const unsigned nblk = blocks_for(p.n, kThreads);
     pack_dens_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, nullptr, p.x, p.y,
                                                                     p.z, p.m, ctx->drec);
     density_launch<false>(ctx->stream, nblk, precision, big_records(p.n, sizeof(DensRec)), p.n,
                           p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho,
-                          BatchDev{});
+                          BatchDev{}, ks);
     return hipGetLastError();
 }
 
@@ -607,12 +685,14 @@ hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &
                            const sph_params &prm, const sph_fields &f, const sph_accel &a)
 {
     const unsigned nblk = blocks_for(p.n, kThreads);
-    const MomParams mp{prm.alpha, prm.beta, prm.eta2};
+    const KernelSel ks = kernel_sel(prm);
+    const MomParams mp{prm.alpha, prm.beta, prm.eta2, ks.sigma, ks.sinc_n};
     pack_pair_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
         p.n, nullptr, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2, ctx->prec);
     momentum_launch<false>(ctx->stream, nblk, prm.precision, big_records(p.n, sizeof(PairRec)),
                            p.n, p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp,
-                           a.ax, a.ay, a.az, a.dudt, a.mumax, BatchDev{}, ctx->hflag_dev);
+                           a.ax, a.ay, a.az, a.dudt, a.mumax, BatchDev{}, ctx->hflag_dev,
+                           ks.family);
     return hipGetLastError();
 }
 
@@ -629,7 +709,8 @@ hipError_t launch_density_batch(sph_ctx ctx, const BatchDev &b, int precision, c
     pack_dens_kernel<<<g1, 256, 0, ctx->stream>>>(0, n_out, F + 0 * cap, F + 1 * cap,
                                                   F + 2 * cap, F + 8 * cap, ctx->drec);
     density_launch<true>(ctx->stream, g2, precision, big_records(cap, sizeof(DensRec)), 0, cap,
-                         ctx->drec, F + 7 * cap, count, idx, max_nb, Grid{}, rho, b);
+                         ctx->drec, F + 7 * cap, count, idx, max_nb, Grid{}, rho, b,
+                         KernelSel{SPH_KERNEL_M4, 0, 0.0});
     return hipGetLastError();
 }
 
@@ -659,7 +740,7 @@ hipError_t launch_momentum_batch(sph_ctx ctx, const BatchDev &b, int precision,
                                                   pr2, ctx->prec);
     momentum_launch<true>(ctx->stream, g2, precision, big_records(cap, sizeof(PairRec)), 0, cap,
                           ctx->prec, count, idx, max_nb, Grid{}, MomParams{}, ax, ay, az, dudt,
-                          mumax, b, nullptr);
+                          mumax, b, nullptr, SPH_KERNEL_M4);
     return hipGetLastError();
 }
 

@@ -223,8 +223,17 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
                               double h_max);
 hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p,
                                  const sph_nbrs &nb);
+// The interpolation kernel of a pair call: family (SPH_KERNEL_*), sinc
+// exponent, and sigma = W(0, h) h^3.
+struct KernelSel {
+    int family;
+    int sinc_n;
+    double sigma;
+};
+KernelSel kernel_sel(const sph_params &prm);
+
 hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
-                          int precision, double *rho);
+                          int precision, const KernelSel &ks, double *rho);
 hipError_t launch_eos(sph_ctx ctx, const sph_particles &p, const sph_params &prm,
                       const sph_fields &f);
 hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,

@@ -39,6 +39,7 @@ class SphParams:
     """Scalar physics constants shared by both paths.
 
     eos: 0 = weakly compressible Tait, 1 = ideal gas.
+    kernel: 0 = M4 spline, 1 = Wendland C2, 2 = sinc of exponent sinc_n.
     The Tait exponent, eta^2, the Courant and force factors are the usual
     Monaghan (1992, 1994) choices; the paper leaves them open.
     """
@@ -53,6 +54,8 @@ class SphParams:
     eta2: float = 0.01
     c_cfl: float = 0.3
     c_force: float = 0.25
+    kernel: int = 0
+    sinc_n: int = 5
 
 
 @dataclass

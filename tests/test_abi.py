@@ -88,7 +88,8 @@ def test_ensemble_host_checks():
 
 
 def test_ensemble_structs_match_header():
-    """ctypes mirrors of the ensemble structs have the C sizes and offsets."""
+    """ctypes mirrors of the ensemble structs and of sph_params have the C
+    sizes and offsets."""
     import subprocess
     import tempfile
     src = r'''
@@ -96,9 +97,11 @@ def test_ensemble_structs_match_header():
 #include <stdio.h>
 #include "sph.h"
 int main(void) {
-    printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(sph_ens_config), sizeof(sph_run_request),
-           sizeof(sph_run_result), sizeof(sph_ens_counters), offsetof(sph_run_request, rho_ref),
-           offsetof(sph_run_result, status), offsetof(sph_ens_counters, busy_seconds));
+    printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sph_ens_config),
+           sizeof(sph_run_request), sizeof(sph_run_result), sizeof(sph_ens_counters),
+           offsetof(sph_run_request, rho_ref), offsetof(sph_run_result, status),
+           offsetof(sph_ens_counters, busy_seconds), sizeof(sph_params),
+           offsetof(sph_params, kernel), offsetof(sph_params, sinc_n));
     return 0;
 }
 '''
@@ -110,7 +113,8 @@ int main(void) {
         got = [int(v) for v in subprocess.check_output([exe]).split()]
     want = [C.sizeof(S.EnsConfig), C.sizeof(S.RunRequest), C.sizeof(S.RunResult),
             C.sizeof(S.EnsCounters), S.RunRequest.rho_ref.offset, S.RunResult.status.offset,
-            S.EnsCounters.busy_seconds.offset]
+            S.EnsCounters.busy_seconds.offset, C.sizeof(S.Params), S.Params.kernel.offset,
+            S.Params.sinc_n.offset]
     assert got == want
 
 

@@ -153,6 +153,12 @@ def test_poll_and_rejections():
         with pytest.raises(S.SphError) as e:
             ens.submit(big, 1)
         assert e.value.status == S.SPH_E_INVALID
+        import dataclasses
+        wend = _ic(10, 5.0, 1)
+        wend.params = dataclasses.replace(wend.params, kernel=S.SPH_KERNEL_WENDLAND_C2)
+        with pytest.raises(S.SphError) as e:
+            ens.submit(wend, 1)  # the engine runs M4 only
+        assert e.value.status == S.SPH_E_INVALID
         bad = _ic(10, 5.0, 1)
         bad.id = bad.id.copy()
         bad.id[0] = bad.id[1]

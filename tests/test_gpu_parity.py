@@ -255,3 +255,50 @@ def test_smoothing_length_iteration_bitwise(case):
     assert it == it_ref
     assert np.array_equal(got["count"], cnt_ref)
     assert np.array_equal(got["h"], h_ref)
+
+
+KERNEL_CASES = [(S.SPH_KERNEL_WENDLAND_C2, 5), (S.SPH_KERNEL_SINC, 5), (S.SPH_KERNEL_SINC, 3)]
+
+
+@pytest.mark.parametrize("family,n", KERNEL_CASES)
+@pytest.mark.parametrize("name", ["square_patch_c0", "cloud_open", "cloud_pxyz"])
+def test_other_kernels(family, n, name):
+    """The mini-app's interchangeable kernels (Wendland C2, sinc): density and
+    momentum/energy against the oracle with the same kernel, uniform h (the
+    square patch) and variable h with all image cases."""
+    import dataclasses
+    make, max_nb = _cases()[name]
+    ic = make()
+    ic.params = dataclasses.replace(ic.params, kernel=family, sinc_n=n)
+    print(f"case {name} kernel {family} n {n}", flush=True)
+    O.set_kernel(family, n)
+    try:
+        ref = oracle_forces(ic)
+    finally:
+        O.set_kernel(O.KERNEL_M4)
+    got, _, ctx = gpu_forces(ic, ref["rho_ref"], S.SPH_FP64, max_nb=max_nb, rho_in=ref["rho"])
+    assert np.array_equal(got["off"], ref["off"]) and np.array_equal(got["ids"], ref["ids"])
+    e = field_errors(ref, got)
+    print(name, "fp64", e, flush=True)
+    assert e["rho"] <= FP64_TOL and e["a"] <= FP64_TOL and e["du"] <= FP64_TOL
+    assert e["dt"] <= 1e-13
+    got32, _, _ = gpu_forces(ic, ref["rho_ref"], S.SPH_FP32_PAIR, max_nb=max_nb,
+                             rho_in=ref["rho"], export=False, ctx=ctx)
+    e32 = field_errors(ref, got32)
+    print(name, "fp32-pair", e32, flush=True)
+    assert e32["rho"] <= FP32_TOL and e32["a"] <= FP32_TOL and e32["du"] <= FP32_TOL
+
+
+def test_kernel_choice_rejected():
+    import dataclasses
+    ic = I.square_patch(10)
+    ctx = S.Context(ic.n, 128)
+    st = S.SphState(ic, 128)
+    S.sph_build_cells(ctx, st)
+    S.sph_find_neighbors(ctx, st)
+    for kernel, n in ((7, 5), (S.SPH_KERNEL_SINC, 2), (S.SPH_KERNEL_SINC, 13)):
+        prm = S.make_params(dataclasses.replace(ic.params, kernel=kernel, sinc_n=n))
+        with pytest.raises(S.SphError) as e:
+            S.sph_density(ctx, st, prm)
+        assert e.value.status == S.SPH_E_INVALID
+    S.sph_ctx_check(ctx)
