@@ -202,6 +202,18 @@ sph_status sph_momentum_energy(sph_ctx ctx, const sph_particles *p,
                                const sph_params *prm, const sph_fields *f,
                                const sph_accel *a);
 
+/* Algorithm 1, step 4 (self-gravity; Sec. 5.2.5 phase I) by direct
+ * summation in FP64, G = 1, Plummer softening eps >= 0:
+ *   g_i = - sum_{j != i} m_j (x_i - x_j) / (|x_i - x_j|^2 + eps^2)^{3/2},
+ * no periodic images. Reads p->x, y, z, m (device, n, current order; h and
+ * id are checked but not read) and writes gx, gy, gz (device, n doubles
+ * each, caller-owned, same order); uses the context's density records as
+ * scratch. O(n^2) work: the reference the parent codes' tree multipoles
+ * approximate, not a fast solver. Asynchronous on ctx's stream;
+ * SPH_E_INVALID for NULL arrays or a negative or non-finite eps. */
+sph_status sph_gravity_direct(sph_ctx ctx, const sph_particles *p, double eps,
+                              double *gx, double *gy, double *gz);
+
 /* Algorithm 1, step 6, one half of a kick-drift-kick step with the global
  * dt read from device memory dt_dev[0]:
  *   SPH_KICK_DRIFT: v += dt/2 (a + g); u += dt/2 du; x += dt v; wrap

@@ -25,7 +25,7 @@ from . import build as _build
 __all__ = [
     "lib", "set_kernel", "kernel_sigma", "kernel_w", "kernel_dwdr", "neighbors", "neighbors_brute",
     "smoothing_length", "density", "eos", "momentum_energy", "timestep",
-    "integrate", "diagnostics", "gravity_direct", "OracleRun", "num_threads",
+    "integrate", "diagnostics", "gravity_direct", "gravity_direct_subset", "OracleRun", "num_threads",
 ]
 
 _lock = threading.Lock()
@@ -82,6 +82,9 @@ def lib():
             L.orc_gravity_direct.restype = None
             L.orc_gravity_direct.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_double,
                                              _D, _D, _D]
+            L.orc_gravity_direct_subset.restype = None
+            L.orc_gravity_direct_subset.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_double,
+                                                    C.c_int64, _I64, _D, _D, _D, _D]
             L.orc_num_threads.restype = C.c_int32
             L.orc_num_threads.argtypes = []
             L.orc_set_num_threads.restype = None
@@ -247,6 +250,18 @@ def gravity_direct(x, y, z, m, eps=0.01):
     gx, gy, gz = np.zeros(n), np.zeros(n), np.zeros(n)
     lib().orc_gravity_direct(n, _d(x), _d(y), _d(z), _d(m), float(eps), gx, gy, gz)
     return gx, gy, gz
+
+
+def gravity_direct_subset(x, y, z, m, sel, eps=0.01):
+    """g (and its error scale sum_j m_j r_ij / (r^2 + eps^2)^{3/2}) for the
+    particles in sel only."""
+    n = len(x)
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    k = len(sel)
+    gx, gy, gz, sg = np.zeros(k), np.zeros(k), np.zeros(k), np.zeros(k)
+    lib().orc_gravity_direct_subset(n, _d(x), _d(y), _d(z), _d(m), float(eps), k, sel,
+                                    gx, gy, gz, sg)
+    return gx, gy, gz, sg
 
 
 class OracleRun:

@@ -742,6 +742,36 @@ void orc_gravity_direct(int64_t n, const double *x, const double *y,
     }
 }
 
+/*
+ * The same direct sum for the particles listed in sel only (nsel of them),
+ * plus its error scale sg_k = sum_{j != i} m_j |x_i - x_j| / (r^2 + eps^2)^{3/2}
+ * (sg may be NULL). Every j in index order, as orc_gravity_direct.
+ */
+void orc_gravity_direct_subset(int64_t n, const double *x, const double *y,
+                               const double *z, const double *m, double eps,
+                               int64_t nsel, const int64_t *sel, double *gx,
+                               double *gy, double *gz, double *sg)
+{
+    double e2 = eps * eps;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < nsel; ++k) {
+        int64_t i = sel[k];
+        double sx = 0.0, sy = 0.0, sz = 0.0, ss = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+            double d2 = dx * dx + dy * dy + dz * dz + e2;
+            double inv = 1.0 / (d2 * sqrt(d2));
+            sx -= m[j] * dx * inv;
+            sy -= m[j] * dy * inv;
+            sz -= m[j] * dz * inv;
+            ss += m[j] * sqrt(dx * dx + dy * dy + dz * dz) * inv;
+        }
+        gx[k] = sx; gy[k] = sy; gz[k] = sz;
+        if (sg) sg[k] = ss;
+    }
+}
+
 /* ----------------------------------------------------------- threading */
 
 int32_t orc_num_threads(void)

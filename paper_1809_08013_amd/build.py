@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libsph.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["cells.hip", "search.hip", "pairs.hip", "integrate.hip", "api.hip", "ensemble.hip"]
+SOURCES = ["cells.hip", "search.hip", "pairs.hip", "integrate.hip", "gravity.hip", "api.hip",
+           "ensemble.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -392,6 +392,20 @@ sph_status sph_density(sph_ctx ctx, const sph_particles *p, const sph_box *box,
     return SPH_OK;
 }
 
+sph_status sph_gravity_direct(sph_ctx ctx, const sph_particles *p, double eps, double *gx,
+                              double *gy, double *gz)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, false)) != SPH_OK) return s;
+    if (!(eps >= 0.0) || !std::isfinite(eps))
+        return fail(ctx, SPH_E_INVALID, "eps must be finite and >= 0");
+    if (p->n == 0) return SPH_OK;
+    if (!gx || !gy || !gz) return fail(ctx, SPH_E_INVALID, "gx, gy and gz are required");
+    SPH_HIP(ctx, launch_gravity_direct(ctx, *p, eps, gx, gy, gz));
+    return SPH_OK;
+}
+
 sph_status sph_eos(sph_ctx ctx, const sph_particles *p, const sph_params *prm,
                    const sph_fields *f)
 {

@@ -234,6 +234,8 @@ KernelSel kernel_sel(const sph_params &prm);
 
 hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
                           int precision, const KernelSel &ks, double *rho);
+hipError_t launch_gravity_direct(sph_ctx ctx, const sph_particles &p, double eps, double *gx,
+                                 double *gy, double *gz);
 hipError_t launch_eos(sph_ctx ctx, const sph_particles &p, const sph_params &prm,
                       const sph_fields &f);
 hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,

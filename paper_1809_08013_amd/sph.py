@@ -130,6 +130,7 @@ def load():
             "sph_find_neighbors": (C.c_int32, [_VP, P, B, N]),
             "sph_density": (C.c_int32, [_VP, P, B, N, M, _VP]),
             "sph_eos": (C.c_int32, [_VP, P, M, F]),
+            "sph_gravity_direct": (C.c_int32, [_VP, P, C.c_double, _VP, _VP, _VP]),
             "sph_momentum_energy": (C.c_int32, [_VP, P, B, N, M, F, A]),
             "sph_integrate": (C.c_int32, [_VP, P, B, C.c_int32, _VP, A]),
             "sph_timestep": (C.c_int32, [_VP, P, M, F, A, _VP, _VP]),
@@ -306,6 +307,20 @@ def sph_find_neighbors(ctx: Context, st: SphState):
 def sph_density(ctx: Context, st: SphState, prm: Params):
     ctx.raise_on(ctx.lib.sph_density(ctx.h, C.byref(st.particles), C.byref(st.box),
                                      C.byref(st.nbrs), C.byref(prm), _ptr(st.t["rho"])))
+
+
+def sph_gravity_direct(ctx: Context, st: SphState, eps: float = 0.01):
+    """Direct-sum self-gravity into st.t["gx"/"gy"/"gz"] (current order). The
+    arrays are created if the state has none; from then on the integration
+    adds them as the external acceleration."""
+    import torch
+    if "gx" not in st.t:
+        for k in ("gx", "gy", "gz"):
+            st.t[k] = torch.zeros(max(st.n, 1), dtype=torch.float64, device=st.device)
+        st._refresh()
+    ctx.raise_on(ctx.lib.sph_gravity_direct(ctx.h, C.byref(st.particles), float(eps),
+                                            _ptr(st.t["gx"]), _ptr(st.t["gy"]),
+                                            _ptr(st.t["gz"])))
 
 
 def sph_eos(ctx: Context, st: SphState, prm: Params):

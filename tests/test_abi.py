@@ -51,7 +51,8 @@ def test_status_strings_and_null_checks():
     assert L.sph_ctx_create(C.byref(h), 10, 5000, None) == S.SPH_E_INVALID
     assert b"max_nb" in L.sph_last_error(None)
     for fn in ("sph_ctx_check", "sph_build_cells", "sph_find_neighbors", "sph_density",
-               "sph_eos", "sph_momentum_energy", "sph_integrate", "sph_timestep"):
+               "sph_eos", "sph_momentum_energy", "sph_integrate", "sph_timestep",
+               "sph_gravity_direct"):
         f = getattr(L, fn)
         nargs = len(f.argtypes)
         args = [None] * nargs
@@ -59,6 +60,8 @@ def test_status_strings_and_null_checks():
             args[3] = 1.0
         if fn == "sph_integrate":
             args[3] = 0
+        if fn == "sph_gravity_direct":
+            args[2] = 0.01
         assert f(*args) == S.SPH_E_INVALID, fn
 
 

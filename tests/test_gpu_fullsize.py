@@ -112,3 +112,24 @@ def test_square_patch_64M_invariants():
     assert abs(d1[6] - d0[6]) <= 1e-12 * abs(d0[6])     # L_z
     assert abs(d1[7] - d0[7]) <= 1e-6 * abs(d0[7])      # energy over 3 steps
     assert abs(d1[1] - d0[1]) < 1e-12 and abs(d1[2] - d0[2]) < 1e-12  # P_x, P_y
+
+
+def test_evrard_1M_gravity_sampled():
+    """Direct-sum self-gravity on the 1M Evrard sphere: 2,000 sampled
+    particles against the oracle's sum over all 10^6 (errors in units of the
+    sum of the absolute pair terms)."""
+    import oracle as O
+    ic = I.evrard(1_000_000, seed=0)
+    print("case Evrard 1M gravity", flush=True)
+    ctx = S.Context(ic.n, 64)
+    st = S.SphState(ic, 64)
+    S.sph_gravity_direct(ctx, st, 0.01)
+    S.sph_ctx_check(ctx)
+    got = st.host(["gx", "gy", "gz"])
+    sel = np.random.default_rng(7).choice(ic.n, 2000, replace=False)
+    gx, gy, gz, sg = O.gravity_direct_subset(ic.x, ic.y, ic.z, ic.m, sel, eps=0.01)
+    d = np.sqrt((got["gx"][sel] - gx) ** 2 + (got["gy"][sel] - gy) ** 2
+                + (got["gz"][sel] - gz) ** 2)
+    e = float(np.max(d / sg))
+    print("gravity 1M sampled error", e, flush=True)
+    assert e <= 1e-12

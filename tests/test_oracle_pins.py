@@ -453,3 +453,20 @@ def test_gravity_direct_closed_forms():
     ms = np.concatenate([np.full(20000, 1.0 / 20000), [1e-30]])
     gx, gy, gz = O.gravity_direct(S[:, 0], S[:, 1], S[:, 2], ms, eps=eps)
     assert math.sqrt(gx[-1] ** 2 + gy[-1] ** 2 + gz[-1] ** 2) < 0.02
+
+
+def test_gravity_direct_subset_matches_full_sum():
+    """The sampled direct sum is the full one restricted to the sample, bit
+    for bit (same j order), and its error scale bounds |g| (triangle
+    inequality)."""
+    rng = np.random.default_rng(5)
+    n = 700
+    x, y, z = rng.normal(size=(3, n))
+    m = rng.uniform(0.5, 1.5, n)
+    for eps in (0.0, 0.05):
+        g = O.gravity_direct(x, y, z, m, eps=eps)
+        sel = np.array([0, 1, 350, 699])
+        gx, gy, gz, sg = O.gravity_direct_subset(x, y, z, m, sel, eps=eps)
+        for a, b in zip(g, (gx, gy, gz)):
+            assert np.array_equal(a[sel], b)
+        assert (np.sqrt(gx ** 2 + gy ** 2 + gz ** 2) <= sg * (1 + 1e-14)).all()
