@@ -23,7 +23,7 @@ import numpy as np
 from . import build as _build
 
 __all__ = [
-    "lib", "set_kernel", "kernel_sigma", "kernel_w", "kernel_dwdr", "neighbors", "neighbors_brute",
+    "lib", "set_kernel", "kernel_sigma", "set_gradient", "iad_matrices", "kernel_w", "kernel_dwdr", "neighbors", "neighbors_brute",
     "smoothing_length", "density", "eos", "momentum_energy", "timestep",
     "integrate", "diagnostics", "gravity_direct", "gravity_direct_subset", "OracleRun", "num_threads",
 ]
@@ -50,6 +50,11 @@ def lib():
             L.orc_kernel_dwdr.argtypes = [C.c_double, C.c_double]
             L.orc_set_kernel.restype = C.c_int32
             L.orc_set_kernel.argtypes = [C.c_int32, C.c_int32]
+            L.orc_set_gradient.restype = C.c_int32
+            L.orc_set_gradient.argtypes = [C.c_int32]
+            L.orc_iad_matrices.restype = None
+            L.orc_iad_matrices.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _D, _D, _I32,
+                                           _I64, _I32, _D]
             L.orc_kernel_sigma.restype = C.c_double
             L.orc_kernel_sigma.argtypes = []
             nb_args = [C.c_int64, _D, _D, _D, _D, _D, _D, _I32, C.c_int64, _I64, _I32]
@@ -119,6 +124,27 @@ def set_kernel(family: int, n: int = 5) -> None:
     (0 M4, 1 Wendland C2, 2 sinc of exponent n); see sph_oracle.c."""
     if lib().orc_set_kernel(int(family), int(n)) != 0:
         raise ValueError(f"unknown kernel {family} (n = {n})")
+
+
+GRADIENT_KERNEL, GRADIENT_IAD = 0, 1
+
+
+def set_gradient(mode: int) -> None:
+    """Select the gradient of momentum_energy: 0 kernel derivatives (default),
+    1 integral approach to derivatives (IAD); see sph_oracle.c."""
+    if lib().orc_set_gradient(int(mode)) != 0:
+        raise ValueError(f"unknown gradient mode {mode}")
+
+
+def iad_matrices(x, y, z, h, m, rho, lo, hi, periodic, off, ids):
+    """The IAD matrices c_i (n x 6: xx, xy, xz, yy, yz, zz)."""
+    n = len(x)
+    c6 = np.zeros(6 * n)
+    blo, bhi, bper = _box(lo, hi, periodic)
+    lib().orc_iad_matrices(n, _d(x), _d(y), _d(z), _d(h), _d(m), _d(rho), blo, bhi, bper,
+                           np.ascontiguousarray(off, dtype=np.int64),
+                           np.ascontiguousarray(ids, dtype=np.int32), c6)
+    return c6.reshape(n, 6)
 
 
 def kernel_sigma() -> float:

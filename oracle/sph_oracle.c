@@ -16,7 +16,9 @@
  *   kernel    M4 cubic spline (Table 1, ChaNGa), W = w(r/h) / (pi h^3); the
  *             mini-app's other interchangeable kernels (Sec. 4, Table 2)
  *             are selectable: Wendland C2 and the sinc family (orc_set_kernel)
- *   gradient  kernel derivatives, standard volume elements m/rho (Table 1)
+ *   gradient  kernel derivatives, standard volume elements m/rho (Table 1);
+ *             or the integral approach to derivatives (IAD, Table 1 for
+ *             SPHYNX; orc_set_gradient), with the same volume elements
  *   density   summation, self term included, gather with h_i
  *   variable h  neighbour iff r^2 < (2 max(h_i, h_j))^2; gradient is the
  *             mean of grad W(r, h_i) and grad W(r, h_j)
@@ -548,6 +550,66 @@ void orc_eos(int64_t n, int32_t eos, double rho0, double c0, double gamma_tait,
     }
 }
 
+/* ------------------------------------------------------------------ IAD */
+
+/*
+ * Integral approach to derivatives (Garcia-Senz, Cabezon & Escartin 2012),
+ * with standard volume elements V_j = m_j / rho_j:
+ *   tau_i = sum_{j in N_i} V_j (x_j - x_i)(x_j - x_i)^T W(r_ij, h_i),
+ *   c_i   = tau_i^{-1}  (zero when tau_i is singular),
+ *   A_ij  = c_i (x_j - x_i) W(r_ij, h_i),
+ * so that sum_j V_j (f_j - f_i) A_ij is exact for linear f. A_ij takes the
+ * place of grad_i W_ij; the pair forces use the antisymmetric mean
+ * Abar_ij = (A_ij - A_ji) / 2 = -(W(r, h_i) c_i + W(r, h_j) c_j) r_ij / 2.
+ * c6 holds c_i as xx, xy, xz, yy, yz, zz (6 doubles per particle).
+ */
+static int32_t g_gradient = 0;   /* 0 kernel derivatives, 1 IAD */
+
+int32_t orc_set_gradient(int32_t mode)
+{
+    if (mode != 0 && mode != 1) return -1;
+    g_gradient = mode;
+    return 0;
+}
+
+void orc_iad_matrices(int64_t n, const double *x, const double *y, const double *z,
+                      const double *h, const double *m, const double *rho,
+                      const double *lo, const double *hi, const int32_t *per,
+                      const int64_t *offsets, const int32_t *ids, double *c6)
+{
+    orc_box b = make_box(lo, hi, per);
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        double a = 0.0, bb = 0.0, c = 0.0, d = 0.0, e = 0.0, f = 0.0;
+        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
+            int64_t j = ids[k];
+            double dx, dy, dz;
+            separation(x, y, z, i, j, &b, &dx, &dy, &dz);  /* x_i - x_j */
+            double r = sqrt(dist2(dx, dy, dz));
+            double vw = m[j] / rho[j] * orc_kernel_w(r, h[i]);
+            a += vw * dx * dx;
+            bb += vw * dx * dy;
+            c += vw * dx * dz;
+            d += vw * dy * dy;
+            e += vw * dy * dz;
+            f += vw * dz * dz;
+        }
+        double cof_a = d * f - e * e, cof_b = c * e - bb * f, cof_c = bb * e - c * d;
+        double det = a * cof_a + bb * cof_b + c * cof_c;
+        double *o = c6 + 6 * i;
+        if (!(det != 0.0) || !isfinite(det)) {
+            for (int t = 0; t < 6; ++t) o[t] = 0.0;
+            continue;
+        }
+        o[0] = cof_a / det;
+        o[1] = cof_b / det;
+        o[2] = cof_c / det;
+        o[3] = (a * f - c * c) / det;
+        o[4] = (bb * c - a * e) / det;
+        o[5] = (a * d - bb * bb) / det;
+    }
+}
+
 /* ------------------------------------------------- momentum and energy */
 
 /*
@@ -571,6 +633,11 @@ void orc_momentum_energy(int64_t n, const double *x, const double *y,
                          double *mumax, double *sa, double *su)
 {
     orc_box b = make_box(lo, hi, per);
+    double *c6 = NULL;
+    if (g_gradient == 1) {
+        c6 = (double *)malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1));
+        orc_iad_matrices(n, x, y, z, h, m, rho, lo, hi, per, offsets, ids, c6);
+    }
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, mum = 0.0;
@@ -582,7 +649,16 @@ void orc_momentum_energy(int64_t n, const double *x, const double *y,
             double r2 = dist2(dx, dy, dz);
             double r = sqrt(r2);
             double gx = 0.0, gy = 0.0, gz = 0.0;
-            if (r > 0.0) {
+            if (c6) {
+                const double *ci = c6 + 6 * i, *cj = c6 + 6 * j;
+                double wi = orc_kernel_w(r, h[i]), wj = orc_kernel_w(r, h[j]);
+                gx = -0.5 * (wi * (ci[0] * dx + ci[1] * dy + ci[2] * dz) +
+                             wj * (cj[0] * dx + cj[1] * dy + cj[2] * dz));
+                gy = -0.5 * (wi * (ci[1] * dx + ci[3] * dy + ci[4] * dz) +
+                             wj * (cj[1] * dx + cj[3] * dy + cj[4] * dz));
+                gz = -0.5 * (wi * (ci[2] * dx + ci[4] * dy + ci[5] * dz) +
+                             wj * (cj[2] * dx + cj[4] * dy + cj[5] * dz));
+            } else if (r > 0.0) {
                 double dwbar = 0.5 * (orc_kernel_dwdr(r, h[i]) + orc_kernel_dwdr(r, h[j]));
                 gx = dwbar * dx / r;
                 gy = dwbar * dy / r;
@@ -611,6 +687,7 @@ void orc_momentum_energy(int64_t n, const double *x, const double *y,
         if (sa) sa[i] = sai;
         if (su) su[i] = sui;
     }
+    free(c6);
 }
 
 /* ------------------------------------------------------------ time-step */

@@ -470,3 +470,65 @@ def test_gravity_direct_subset_matches_full_sum():
         for a, b in zip(g, (gx, gy, gz)):
             assert np.array_equal(a[sel], b)
         assert (np.sqrt(gx ** 2 + gy ** 2 + gz ** 2) <= sg * (1 + 1e-14)).all()
+
+
+@pytest.fixture
+def iad_gradient():
+    O.set_gradient(O.GRADIENT_IAD)
+    yield
+    O.set_gradient(O.GRADIENT_KERNEL)
+
+
+def test_iad_matrices_invert_tau(iad_gradient):
+    """IAD (Table 1, SPHYNX): c_i is the inverse of
+    tau_i = sum_j V_j (x_j - x_i)(x_j - x_i)^T W(r_ij, h_i), assembled here
+    independently with numpy; then sum_j V_j (f_j - f_i) A_ij is exact for
+    linear f (checked for f = a . x with a random a)."""
+    ic = I.random_cloud(1500, seed=21, h_min=0.05, h_max=0.08, periodic=(0, 0, 1))
+    off, ids = O.neighbors(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi, ic.periodic)
+    rho = O.density(ic.x, ic.y, ic.z, ic.h, ic.m, ic.lo, ic.hi, ic.periodic, off, ids)
+    c6 = O.iad_matrices(ic.x, ic.y, ic.z, ic.h, ic.m, rho, ic.lo, ic.hi, ic.periodic, off, ids)
+    L = np.asarray(ic.hi) - np.asarray(ic.lo)
+    P = np.stack([ic.x, ic.y, ic.z], 1)
+    avec = np.array([0.3, -1.2, 0.7])
+    for i in range(0, ic.n, 37):
+        js = ids[off[i]:off[i + 1]]
+        d = P[js] - P[i]
+        d[:, 2] -= L[2] * np.round(d[:, 2] / L[2])  # periodic z
+        r = np.linalg.norm(d, axis=1)
+        w = np.array([O.kernel_w(rr, ic.h[i]) for rr in r])
+        v = ic.m[js] / rho[js]
+        tau = (v * w)[:, None, None] * d[:, :, None] * d[:, None, :]
+        tau = tau.sum(0)
+        c = np.array([[c6[i, 0], c6[i, 1], c6[i, 2]], [c6[i, 1], c6[i, 3], c6[i, 4]],
+                      [c6[i, 2], c6[i, 4], c6[i, 5]]])
+        assert np.abs(c @ tau - np.eye(3)).max() < 1e-9
+        A = (c @ (d * w[:, None]).T).T          # A_ij = c_i (x_j - x_i) W_ij
+        grad = ((v * (d @ avec))[:, None] * A).sum(0)
+        assert np.abs(grad - avec).max() < 1e-9
+
+
+def test_iad_symmetry_invariants(iad_gradient):
+    """With IAD the pair force uses the antisymmetric mean of A_ij and A_ji:
+    no force in a uniform periodic lattice, sum m a = 0 and power balance."""
+    lat = I.lattice_periodic(12, spacing=2.0 ** -4)
+    lat.p_bg[:] = 3.0
+    r = _run_forces(lat)
+    acc = O.momentum_energy(*(r.s[k] for k in ("x", "y", "z", "vx", "vy", "vz", "h", "m")),
+                            r.rho, r.c, r.pr2, lat.lo, lat.hi, lat.periodic, r.off,
+                            r.ids, lat.params, scales=True)
+    amag = np.sqrt(acc["ax"] ** 2 + acc["ay"] ** 2 + acc["az"] ** 2)
+    assert (acc["sa"] > 0).all() and (amag <= 1e-13 * acc["sa"]).all()
+    ic = I.random_cloud(2000, seed=13, h_min=0.04, h_max=0.07, velocity=2.0)
+    r = _run_forces(ic, rho_ref=np.full(ic.n, 1.0))
+    s = r.s
+    acc = O.momentum_energy(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["h"],
+                            s["m"], r.rho, r.c, r.pr2, ic.lo, ic.hi, ic.periodic,
+                            r.off, r.ids, ic.params, scales=True)
+    m = s["m"]
+    F = np.array([np.sum(m * acc[k]) for k in ("ax", "ay", "az")])
+    assert np.linalg.norm(F) <= 1e-13 * np.sum(m * acc["sa"])
+    vmag = np.sqrt(s["vx"] ** 2 + s["vy"] ** 2 + s["vz"] ** 2)
+    power = np.sum(m * (s["vx"] * acc["ax"] + s["vy"] * acc["ay"] + s["vz"] * acc["az"]
+                        + acc["dudt"]))
+    assert abs(power) <= 1e-13 * np.sum(m * (vmag * acc["sa"] + acc["su"]))
