@@ -122,6 +122,17 @@ typedef struct {
  *                           B_n normalising W to unit integral, 3 <= n <= 12 */
 enum { SPH_KERNEL_M4 = 0, SPH_KERNEL_WENDLAND_C2 = 1, SPH_KERNEL_SINC = 2 };
 
+/* Gradient estimates of sph_momentum_energy (Table 1: kernel derivatives for
+ * ChaNGa and SPH-flow, IAD for SPHYNX; the mini-app keeps both, Table 2):
+ *   SPH_GRAD_KERNEL  grad W, the mean of grad W(r, h_i) and grad W(r, h_j)
+ *   SPH_GRAD_IAD     the integral approach to derivatives with standard
+ *                    volume elements V_j = m_j / rho_j:
+ *                    tau_i = sum_j V_j (x_j - x_i)(x_j - x_i)^T W(r_ij, h_i),
+ *                    c_i = tau_i^{-1} (zero if singular),
+ *                    A_ij = c_i (x_j - x_i) W(r_ij, h_i), and the pair terms
+ *                    use (A_ij - A_ji) / 2 in place of the kernel gradient. */
+enum { SPH_GRAD_KERNEL = 0, SPH_GRAD_IAD = 1 };
+
 /* Scalar physics constants (host memory). precision selects the pair
  * arithmetic of sph_density and sph_momentum_energy: SPH_FP64, or
  * SPH_FP32_PAIR (separations formed in FP64 and rounded to FP32, FP32 copies
@@ -129,7 +140,9 @@ enum { SPH_KERNEL_M4 = 0, SPH_KERNEL_WENDLAND_C2 = 1, SPH_KERNEL_SINC = 2 };
  * the neighbour relation, the state, the integration and all reductions stay
  * FP64). kernel selects W and its gradient in both pair calls (zero, the
  * default of a zeroed struct, is M4); sinc_n is the sinc exponent, read only
- * for SPH_KERNEL_SINC. */
+ * for SPH_KERNEL_SINC; gradient selects SPH_GRAD_KERNEL (zero) or
+ * SPH_GRAD_IAD for sph_momentum_energy (IAD matrices are formed inside that
+ * call, in FP64 for both precisions). */
 typedef struct {
     int32_t precision;
     int32_t eos;
@@ -138,6 +151,7 @@ typedef struct {
     double c_cfl, c_force;
     int32_t kernel;
     int32_t sinc_n;
+    int32_t gradient;
 } sph_params;
 
 /* Text for a status code (static storage). */
@@ -318,7 +332,8 @@ typedef struct {
     int32_t n_steps;           /* KDK steps after the t = 0 evaluation, >= 0 */
     int32_t set_rho_ref;       /* Tait: rho_ref := rho at t = 0 */
     sph_params params;         /* params.precision is ignored (engine's);
-                                  params.kernel must be SPH_KERNEL_M4 */
+                                  params.kernel must be SPH_KERNEL_M4 and
+                                  params.gradient SPH_GRAD_KERNEL */
     sph_box box;
     double h_max;              /* >= every h (h stays fixed); sets the cells */
     /* HOST arrays of n entries in any order, copied by sph_ens_submit

@@ -169,6 +169,8 @@ sph_status check_params(sph_ctx ctx, const sph_params *prm)
         return fail(ctx, SPH_E_INVALID, "unknown kernel %d", prm->kernel);
     if (prm->kernel == SPH_KERNEL_SINC && (prm->sinc_n < 3 || prm->sinc_n > 12))
         return fail(ctx, SPH_E_INVALID, "sinc exponent %d outside [3, 12]", prm->sinc_n);
+    if (prm->gradient != SPH_GRAD_KERNEL && prm->gradient != SPH_GRAD_IAD)
+        return fail(ctx, SPH_E_INVALID, "unknown gradient %d", prm->gradient);
     return SPH_OK;
 }
 
@@ -213,6 +215,7 @@ void free_ctx(sph_ctx ctx)
                     ctx->scan_part, ctx->cell_start, ctx->cell_end, ctx->perm_tmp,
                     ctx->perm_tmp_id, ctx->red_part, ctx->status_dev, ctx->nb_mask, ctx->hflag_dev,
                     ctx->fb_tiles, ctx->fb_count, ctx->it_words, ctx->it_hmax, ctx->cell_s2max,
+                    ctx->iad_c,
                     ctx->srec, ctx->drec, ctx->prec};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -290,6 +293,7 @@ sph_status sph_ctx_create(sph_ctx *out, int64_t n_max, int32_t max_nb, sph_strea
     ALLOC(ctx->cell_start, ctx->cell_cap);
     ALLOC(ctx->cell_end, ctx->cell_cap);
     ALLOC(ctx->cell_s2max, ctx->cell_cap);
+    ALLOC(ctx->iad_c, 6 * n_max);
     ALLOC(ctx->nb_mask, (int64_t)kSearchMaskWords * ((n_max + 63) / 64) * 64);
     ALLOC(ctx->fb_tiles, (n_max + 63) / 64);
     ALLOC(ctx->fb_count, 1);

@@ -381,12 +381,105 @@ struct MomParams {
     double alpha, beta, eta2;
     double sigma;  // W(0, h) h^3 of the kernel (KF != KF_M4)
     int sinc_n;
+    const double *iad_c;  // IAD matrices (IAD instances), 6 per particle
 };
+
+// IAD matrices (integral approach to derivatives, standard volume elements):
+// tau_i = sum_j V_j d d^T W(r, h_i) over the lane's list, d = x_i - x_j
+// (the sign cancels), c_i = tau_i^{-1} as xx xy xz yy yz zz, zero when tau_i
+// is singular. Records {x, y, z, V = m / rho}, one lane per particle, FP64.
+// Near free surfaces tau_i can be close to singular, and its inverse then
+// magnifies last-bit differences. So the matrix is formed with correctly
+// rounded operations only (sqrt, division, no fused multiply-add), in the
+// plain textbook order: r = sqrt(r^2), q = r / h, W = w(q) / (pi h h h),
+// tau += (V W d_a) d_b. For the polynomial kernels (M4, Wendland C2) the
+// result is then the same number as in any implementation that evaluates
+// these expressions in this order.
+template <int KF>
+__device__ __forceinline__ double kernel_w_plain(double r, double hh, double sigma, int n)
+{
+    const double q = r / hh;
+    if constexpr (KF == KF_M4) {
+        double w = 0.0;
+        if (q < 1.0) {
+            w = 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+        } else if (q < 2.0) {
+            const double t = 2.0 - q;
+            w = 0.25 * t * t * t;
+        }
+        return w / (M_PI * hh * hh * hh);
+    } else if constexpr (KF == KF_WENDLAND) {
+        if (q >= 2.0) return 0.0;
+        const double t = 1.0 - 0.5 * q;
+        return 21.0 / (16.0 * M_PI * hh * hh * hh) * t * t * t * t * (1.0 + 2.0 * q);
+    } else {
+        if (q >= 2.0) return 0.0;
+        const double x = 0.5 * M_PI * q;
+        const double sx = x == 0.0 ? 1.0 : sin(x) / x;
+        return sigma / (hh * hh * hh) * pow(sx, (double)n);
+    }
+}
+
+template <int KF>
+__global__ void __launch_bounds__(256)
+iad_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ vrec,
+           const double *__restrict__ h, const int32_t *__restrict__ count,
+           const int32_t *__restrict__ idx, int max_nb, Grid g, double sigma, int sinc_n,
+           double *__restrict__ c6)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Img im = lane_img<false>(g, BatchDev{}, i);
+    const DensRec me = vrec[i];
+    const double hh = h[i];
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0, e = 0.0, f = 0.0;
+    const int cnt = min(count[i], max_nb);
+    for (int k = 0; k < cnt; ++k) {
+        const DensRec o = vrec[idx[(int64_t)k * ld + i]];
+        const double dx = img<-1>(me.x - o.x, im, 0);
+        const double dy = img<-1>(me.y - o.y, im, 1);
+        const double dz = img<-1>(me.z - o.z, im, 2);
+        const double r = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
+        const double vw = o.m * kernel_w_plain<KF>(r, hh, sigma, sinc_n);
+        a += vw * dx * dx;
+        b += vw * dx * dy;
+        c += vw * dx * dz;
+        d += vw * dy * dy;
+        e += vw * dy * dz;
+        f += vw * dz * dz;
+    }
+    const double ca = d * f - e * e, cb = c * e - b * f, cc = b * e - c * d;
+    const double det = a * ca + b * cb + c * cc;
+    double *o6 = c6 + 6 * i;
+    if (!(det != 0.0) || !isfinite(det)) {
+        for (int t = 0; t < 6; ++t) o6[t] = 0.0;
+        return;
+    }
+    o6[0] = ca / det;
+    o6[1] = cb / det;
+    o6[2] = cc / det;
+    o6[3] = (a * f - c * c) / det;
+    o6[4] = (b * c - a * e) / det;
+    o6[5] = (a * d - b * b) / det;
+}
+
+// Volume records {x, y, z, m / rho} for the IAD pass.
+__global__ void __launch_bounds__(256)
+pack_vol_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                const double *__restrict__ z, const double *__restrict__ m,
+                const double *__restrict__ rho, DensRec *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = DensRec{x[i], y[i], z[i], m[i] / rho[i]};
+}
 
 // UH: every particle has the same h. Then h_i = h_j bit for bit, the two
 // kernel slopes of the mean gradient are the same number t, and
 // 0.5 (t + t) = t exactly, so one evaluation gives the general form's result.
-template <bool F32, bool Multi, bool Big, int Per, bool UH, int KF>
+// IAD: the pair terms use Abar_ij = -(W(r, h_i) c_i + W(r, h_j) c_j) r_ij / 2
+// in place of the mean kernel gradient; c_j of the next step is loaded with
+// the records.
+template <bool F32, bool Multi, bool Big, int Per, bool UH, int KF, bool IAD = false>
 __device__ __forceinline__ void momentum_tile(
     int64_t tile, int64_t n, int64_t ld, const PairRec *__restrict__ rec,
     const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
@@ -403,7 +496,7 @@ __device__ __forceinline__ void momentum_tile(
     MomParams prm = prm0;
     if constexpr (Multi) {
         const RunDev &r = b.runs[b.slot[ii]];
-        prm = MomParams{r.alpha, r.beta, r.eta2, 0.0, 0};
+        prm = MomParams{r.alpha, r.beta, r.eta2, 0.0, 0, nullptr};
     }
     const PairRec *mp = rec + ii;
     const double mex = mp->x, mey = mp->y, mez = mp->z;
@@ -415,6 +508,20 @@ __device__ __forceinline__ void momentum_tile(
     const R fi = sg * (inv_hi * inv_hi) * (inv_hi * inv_hi);
     const R alpha = (R)prm.alpha, beta = (R)prm.beta, eta2 = (R)prm.eta2;
     R sx = 0, sy = 0, sz = 0, su = 0, mum = 0;
+    // IAD: the lane's own matrix, and the next neighbour's
+    R cix = 0, ciy = 0, ciz = 0, ciyy = 0, ciyz = 0, cizz = 0;
+    double2 e0 = make_double2(0.0, 0.0), e1 = e0, e2 = e0;
+    auto load_c = [&](int jj) {
+        const double2 *cp = reinterpret_cast<const double2 *>(prm.iad_c + 6 * (int64_t)jj);
+        e0 = cp[0];
+        e1 = cp[1];
+        e2 = cp[2];
+    };
+    if constexpr (IAD) {
+        const double *cp = prm.iad_c + 6 * ii;
+        cix = (R)cp[0]; ciy = (R)cp[1]; ciz = (R)cp[2];
+        ciyy = (R)cp[3]; ciyz = (R)cp[4]; cizz = (R)cp[5];
+    }
     const int cnt = active ? min(count[ii], max_nb) : 0;
     int maxc = cnt;
 #pragma unroll
@@ -437,8 +544,10 @@ __device__ __forceinline__ void momentum_tile(
     {
         const int j0 = cnt > 0 ? idx[ii] : (int)ii;
         SPH_FETCH_ALL(j0);
+        if constexpr (IAD) load_c(j0);
     }
     for (int k = 0; k < maxc; ++k) {
+        const double2 f0 = e0, f1 = e1, f2 = e2;  // IAD: c_j of this step
         wave_lds_fence();
         if (loader) {
             *reinterpret_cast<double2 *>(dst + 0 * kMomStride) = c0;
@@ -453,6 +562,7 @@ __device__ __forceinline__ void momentum_tile(
         wave_lds_fence();
         if (k + 1 < maxc) {
             SPH_FETCH_ALL(jn);
+            if constexpr (IAD) load_c(jn);
             jn = k + 2 < cnt ? idx[(int64_t)(k + 2) * ld + ii] : (int)ii;
         }
 #undef SPH_FETCH_ALL
@@ -472,7 +582,25 @@ __device__ __forceinline__ void momentum_tile(
             const R rinv = r2 > R(0) ? fast_rsq(r2) : R(0);
             const R r = r2 * rinv;
             R dwbar, hbar;
-            if constexpr (UH) {
+            R gx = 0, gy = 0, gz = 0;  // IAD: Abar_ij
+            if constexpr (IAD) {
+                const R hj = (R)q3.x, inv_hj = (R)q3.y;
+                const R wi = sg * (inv_hi * inv_hi * inv_hi) * shape_w<KF>(r * inv_hi, sn);
+                const R wj = sg * (inv_hj * inv_hj * inv_hj) * shape_w<KF>(r * inv_hj, sn);
+                const R cjx = (R)f0.x, cjy = (R)f0.y, cjz = (R)f1.x, cjyy = (R)f1.y,
+                        cjyz = (R)f2.x, cjzz = (R)f2.y;
+                const R tix = fma_r(ciz, dz, fma_r(ciy, dy, cix * dx));
+                const R tiy = fma_r(ciyz, dz, fma_r(ciyy, dy, ciy * dx));
+                const R tiz = fma_r(cizz, dz, fma_r(ciyz, dy, ciz * dx));
+                const R tjx = fma_r(cjz, dz, fma_r(cjy, dy, cjx * dx));
+                const R tjy = fma_r(cjyz, dz, fma_r(cjyy, dy, cjy * dx));
+                const R tjz = fma_r(cjzz, dz, fma_r(cjyz, dy, cjz * dx));
+                gx = R(-0.5) * fma_r(wj, tjx, wi * tix);
+                gy = R(-0.5) * fma_r(wj, tjy, wi * tiy);
+                gz = R(-0.5) * fma_r(wj, tjz, wi * tiz);
+                dwbar = R(0);
+                hbar = R(0.5) * (hi + hj);
+            } else if constexpr (UH) {
                 dwbar = fi * shape_dw<KF>(r * inv_hi, sn);
                 hbar = hi;
             } else {
@@ -492,11 +620,19 @@ __device__ __forceinline__ void momentum_tile(
             const R inv = fast_rcp(den * rhobar);
             const R mu = vdotr < R(0) ? hbar * vdotr * (rhobar * inv) : R(0);
             const R Pi = mu * (beta * mu - alpha * cbar) * (den * inv);
-            const R mG = (R)q4.x * (pi + (R)q5.y + Pi) * F;
-            sx = fma_r(-mG, dx, sx);
-            sy = fma_r(-mG, dy, sy);
-            sz = fma_r(-mG, dz, sz);
-            su = fma_r(mG, vdotr, su);
+            if constexpr (IAD) {
+                const R mGs = (R)q4.x * (pi + (R)q5.y + Pi);
+                sx = fma_r(-mGs, gx, sx);
+                sy = fma_r(-mGs, gy, sy);
+                sz = fma_r(-mGs, gz, sz);
+                su = fma_r(mGs, fma_r(wz, gz, fma_r(wy, gy, wx * gx)), su);
+            } else {
+                const R mG = (R)q4.x * (pi + (R)q5.y + Pi) * F;
+                sx = fma_r(-mG, dx, sx);
+                sy = fma_r(-mG, dy, sy);
+                sz = fma_r(-mG, dz, sz);
+                su = fma_r(mG, vdotr, su);
+            }
             mum = fmax(mum, fabs(mu));
         }
     }
@@ -509,7 +645,7 @@ __device__ __forceinline__ void momentum_tile(
     }
 }
 
-template <bool F32, bool Multi, bool Big, int Per, int KF>
+template <bool F32, bool Multi, bool Big, int Per, int KF, bool IAD = false>
 __global__ void __launch_bounds__(kThreads)
 momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
                 const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
@@ -525,6 +661,10 @@ momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
         for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
             momentum_tile<F32, true, Big, -1, false, KF>(t, nn, ld, rec, count, idx, max_nb, g,
                                                          prm, ax, ay, az, dudt, mumax, b, buf);
+    } else if constexpr (IAD) {
+        momentum_tile<F32, false, Big, Per, false, KF, true>(xcd_block(), n, ld, rec, count,
+                                                             idx, max_nb, g, prm, ax, ay, az,
+                                                             dudt, mumax, b, buf);
     } else if (hflag[0] == 0u) {
         // uniform h (flag of the last cell build)
         momentum_tile<F32, false, Big, Per, true, KF>(xcd_block(), n, ld, rec, count, idx,
@@ -633,15 +773,21 @@ void momentum_launch(hipStream_t st, unsigned blocks, int precision, bool big, i
                      int64_t ld, const PairRec *rec, const int32_t *count, const int32_t *idx,
                      int max_nb, const Grid &g, const MomParams &mp, double *ax, double *ay,
                      double *az, double *dudt, double *mumax, const BatchDev &b,
-                     const uint32_t *hflag, int family)
+                     const uint32_t *hflag, int family, bool iad)
 {
 #define SPH_MOM_P(F, B, P, K)                                                              \
     momentum_kernel<F, Multi, B, P, K><<<blocks, kThreads, 0, st>>>(                       \
+        n, ld, rec, count, idx, max_nb, g, mp, ax, ay, az, dudt, mumax, b, hflag)
+#define SPH_MOM_IAD(F, B, K)                                                               \
+    momentum_kernel<F, false, B, -1, K, true><<<blocks, kThreads, 0, st>>>(                \
         n, ld, rec, count, idx, max_nb, g, mp, ax, ay, az, dudt, mumax, b, hflag)
 #define SPH_MOM(F, B)                                                                      \
     do {                                                                                   \
         const int pm = Multi ? -1 : per_mask(g);                                           \
         if constexpr (Multi) SPH_MOM_P(F, B, -1, KF_M4);                                   \
+        else if (iad && family == SPH_KERNEL_WENDLAND_C2) SPH_MOM_IAD(F, B, KF_WENDLAND);  \
+        else if (iad && family == SPH_KERNEL_SINC) SPH_MOM_IAD(F, B, KF_SINC);             \
+        else if (iad) SPH_MOM_IAD(F, B, KF_M4);                                            \
         else if (family == SPH_KERNEL_WENDLAND_C2) SPH_MOM_P(F, B, -1, KF_WENDLAND);        \
         else if (family == SPH_KERNEL_SINC) SPH_MOM_P(F, B, -1, KF_SINC);                  \
         else if (pm == 0) SPH_MOM_P(F, B, 0, KF_M4);                                       \
@@ -655,6 +801,7 @@ void momentum_launch(hipStream_t st, unsigned blocks, int precision, bool big, i
         if (big) SPH_MOM(false, true); else SPH_MOM(false, false);
     }
 #undef SPH_MOM
+#undef SPH_MOM_IAD
 #undef SPH_MOM_P
 }
 
@@ -686,13 +833,26 @@ hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &
 {
     const unsigned nblk = blocks_for(p.n, kThreads);
     const KernelSel ks = kernel_sel(prm);
-    const MomParams mp{prm.alpha, prm.beta, prm.eta2, ks.sigma, ks.sinc_n};
+    const bool iad = prm.gradient == SPH_GRAD_IAD;
+    const MomParams mp{prm.alpha, prm.beta, prm.eta2, ks.sigma, ks.sinc_n, ctx->iad_c};
+    if (iad) {
+        pack_vol_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, p.x, p.y, p.z, p.m,
+                                                                       f.rho, ctx->drec);
+#define SPH_IAD(K)                                                                         \
+    iad_kernel<K><<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(                          \
+        p.n, p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, ks.sigma,        \
+        ks.sinc_n, ctx->iad_c)
+        if (ks.family == SPH_KERNEL_WENDLAND_C2) SPH_IAD(KF_WENDLAND);
+        else if (ks.family == SPH_KERNEL_SINC) SPH_IAD(KF_SINC);
+        else SPH_IAD(KF_M4);
+#undef SPH_IAD
+    }
     pack_pair_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
         p.n, nullptr, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2, ctx->prec);
     momentum_launch<false>(ctx->stream, nblk, prm.precision, big_records(p.n, sizeof(PairRec)),
                            p.n, p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp,
                            a.ax, a.ay, a.az, a.dudt, a.mumax, BatchDev{}, ctx->hflag_dev,
-                           ks.family);
+                           ks.family, iad);
     return hipGetLastError();
 }
 
@@ -740,7 +900,7 @@ hipError_t launch_momentum_batch(sph_ctx ctx, const BatchDev &b, int precision,
                                                   pr2, ctx->prec);
     momentum_launch<true>(ctx->stream, g2, precision, big_records(cap, sizeof(PairRec)), 0, cap,
                           ctx->prec, count, idx, max_nb, Grid{}, MomParams{}, ax, ay, az, dudt,
-                          mumax, b, nullptr, SPH_KERNEL_M4);
+                          mumax, b, nullptr, SPH_KERNEL_M4, false);
     return hipGetLastError();
 }
 

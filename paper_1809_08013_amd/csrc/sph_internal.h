@@ -191,6 +191,7 @@ struct sph_ctx_s {
     int64_t cell_cap = 0;
     uint32_t *nb_mask = nullptr;     // search bit masks: kSearchMaskWords words per particle slot
     double *cell_s2max = nullptr;    // per cell: largest (2h)^2 of its particles
+    double *iad_c = nullptr;         // IAD matrices, 6 per particle (xx xy xz yy yz zz)
     int32_t *fb_tiles = nullptr;     // search tiles left to the per-lane path
     uint32_t *fb_count = nullptr;
     uint32_t *it_words = nullptr;    // h iteration: out-of-band count, largest count

@@ -40,6 +40,7 @@ class SphParams:
 
     eos: 0 = weakly compressible Tait, 1 = ideal gas.
     kernel: 0 = M4 spline, 1 = Wendland C2, 2 = sinc of exponent sinc_n.
+    gradient: 0 = kernel derivatives, 1 = integral approach (IAD).
     The Tait exponent, eta^2, the Courant and force factors are the usual
     Monaghan (1992, 1994) choices; the paper leaves them open.
     """
@@ -56,6 +57,7 @@ class SphParams:
     c_force: float = 0.25
     kernel: int = 0
     sinc_n: int = 5
+    gradient: int = 0
 
 
 @dataclass

@@ -30,6 +30,7 @@ SPH_FP64, SPH_FP32_PAIR = 0, 1
 SPH_EOS_TAIT, SPH_EOS_IDEAL = 0, 1
 SPH_KICK_DRIFT, SPH_KICK = 0, 1
 SPH_KERNEL_M4, SPH_KERNEL_WENDLAND_C2, SPH_KERNEL_SINC = 0, 1, 2
+SPH_GRAD_KERNEL, SPH_GRAD_IAD = 0, 1
 
 _VP = C.c_void_p
 
@@ -67,7 +68,7 @@ class Params(C.Structure):
     _fields_ = [("precision", C.c_int32), ("eos", C.c_int32)] + [
         (k, C.c_double) for k in ("rho0", "c0", "gamma_tait", "gamma_gas", "alpha",
                                   "beta", "eta2", "c_cfl", "c_force")] + [
-        ("kernel", C.c_int32), ("sinc_n", C.c_int32)]
+        ("kernel", C.c_int32), ("sinc_n", C.c_int32), ("gradient", C.c_int32)]
 
 
 class EnsConfig(C.Structure):
@@ -205,7 +206,8 @@ def make_params(p, precision: int = SPH_FP64) -> Params:
     return Params(int(precision), int(p.eos), float(p.rho0), float(p.c0),
                   float(p.gamma_tait), float(p.gamma_gas), float(p.alpha),
                   float(p.beta), float(p.eta2), float(p.c_cfl), float(p.c_force),
-                  int(getattr(p, "kernel", SPH_KERNEL_M4)), int(getattr(p, "sinc_n", 5)))
+                  int(getattr(p, "kernel", SPH_KERNEL_M4)), int(getattr(p, "sinc_n", 5)),
+                  int(getattr(p, "gradient", SPH_GRAD_KERNEL)))
 
 
 def make_box(lo, hi, periodic) -> Box:

@@ -159,6 +159,11 @@ def test_poll_and_rejections():
         with pytest.raises(S.SphError) as e:
             ens.submit(wend, 1)  # the engine runs M4 only
         assert e.value.status == S.SPH_E_INVALID
+        iad = _ic(10, 5.0, 1)
+        iad.params = dataclasses.replace(iad.params, gradient=S.SPH_GRAD_IAD)
+        with pytest.raises(S.SphError) as e:
+            ens.submit(iad, 1)  # and kernel derivatives only
+        assert e.value.status == S.SPH_E_INVALID
         bad = _ic(10, 5.0, 1)
         bad.id = bad.id.copy()
         bad.id[0] = bad.id[1]
