@@ -4,6 +4,7 @@ Each test names what it pins: brute force, a closed form, an invariant of the
 symmetric SPH forms, a worked example computed by hand, or the paper's
 initial-condition formulas (Sec. 5.1). Runs on CPU only.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -532,3 +533,50 @@ def test_iad_symmetry_invariants(iad_gradient):
     power = np.sum(m * (s["vx"] * acc["ax"] + s["vy"] * acc["ay"] + s["vz"] * acc["az"]
                         + acc["dudt"]))
     assert abs(power) <= 1e-13 * np.sum(m * (vmag * acc["sa"] + acc["su"]))
+
+
+@pytest.mark.parametrize("family,n", [(O.KERNEL_M4, 5)] + KERNEL_CASES[:2])
+def test_iad_exact_linear_fields(family, n):
+    """IAD reproduces linear fields exactly, so on a uniform lattice with AV
+    off the pair forces give the continuum values to round-off: with
+    P/rho^2 = q0 + g.x the acceleration is -rho g, and with v = G x and
+    uniform P/rho^2 = q the heating is -rho q tr(G). Kernel derivatives miss
+    both by the lattice error of the kernel sum, which the second half checks
+    (so the first half cannot pass by accident)."""
+    lat = I.lattice_periodic(12, spacing=2.0 ** -4)
+    prm = dataclasses.replace(lat.params, alpha=0.0, beta=0.0)
+    rng = np.random.default_rng(31)
+    G = rng.uniform(-1.0, 1.0, (3, 3))
+    g = np.array([0.3, -0.5, 0.2])
+    P = np.stack([lat.x, lat.y, lat.z], 1)
+    v = P @ G.T
+    idx = np.rint(P / 2.0 ** -4 - 0.5).astype(int)
+    # Neighbours lie within two lattice steps: particles 2..9 along every
+    # axis see no periodic wrap of the linear fields.
+    inner = ((idx >= 2) & (idx <= 9)).all(1)
+    O.set_kernel(family, n)
+    try:
+        off, ids = O.neighbors(lat.x, lat.y, lat.z, lat.h, lat.lo, lat.hi, lat.periodic)
+        rho = O.density(lat.x, lat.y, lat.z, lat.h, lat.m, lat.lo, lat.hi, lat.periodic,
+                        off, ids)
+        c = np.full(lat.n, 10.0)
+        errs = {}
+        for mode in (O.GRADIENT_IAD, O.GRADIENT_KERNEL):
+            O.set_gradient(mode)
+            acc = O.momentum_energy(lat.x, lat.y, lat.z, lat.vx, lat.vy, lat.vz, lat.h,
+                                    lat.m, rho, c, 1.0 + P @ g, lat.lo, lat.hi,
+                                    lat.periodic, off, ids, prm, scales=True)
+            a = np.stack([acc["ax"], acc["ay"], acc["az"]], 1)
+            ea = np.linalg.norm(a + rho[:, None] * g, axis=1)[inner] / acc["sa"][inner]
+            q = 0.7
+            acc = O.momentum_energy(lat.x, lat.y, lat.z, v[:, 0], v[:, 1], v[:, 2],
+                                    lat.h, lat.m, rho, c, np.full(lat.n, q), lat.lo,
+                                    lat.hi, lat.periodic, off, ids, prm, scales=True)
+            eu = np.abs(acc["dudt"] + rho * q * np.trace(G))[inner] / acc["su"][inner]
+            errs[mode] = (ea.max(), eu.max())
+    finally:
+        O.set_gradient(O.GRADIENT_KERNEL)
+        O.set_kernel(O.KERNEL_M4, 5)
+    assert inner.sum() == 8 ** 3
+    assert errs[O.GRADIENT_IAD][0] < 1e-13 and errs[O.GRADIENT_IAD][1] < 1e-13
+    assert errs[O.GRADIENT_KERNEL][0] > 1e-6 and errs[O.GRADIENT_KERNEL][1] > 1e-6
