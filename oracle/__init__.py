@@ -69,6 +69,15 @@ def lib():
             L.orc_density.restype = None
             L.orc_density.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _D, _I32,
                                       _I64, _I32, _D]
+            L.orc_volume_weights.restype = None
+            L.orc_volume_weights.argtypes = [C.c_int64, _D, _D, C.c_double, _D]
+            L.orc_density_weighted.restype = None
+            L.orc_density_weighted.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _D, _D,
+                                               _I32, _I64, _I32, _D]
+            L.orc_momentum_energy_weighted.restype = None
+            L.orc_momentum_energy_weighted.argtypes = (
+                [C.c_int64] + [_D] * 12 + [_D, _D, _I32, _I64, _I32]
+                + [C.c_double] * 3 + [_D] * 5 + [_DN, _DN])
             L.orc_eos.restype = None
             L.orc_eos.argtypes = [C.c_int64, C.c_int32, C.c_double, C.c_double,
                                   C.c_double, C.c_double, _D, _D, _D, _D, _D, _D, _D]
@@ -200,13 +209,27 @@ def smoothing_length(x, y, z, h, lo, hi, periodic, n_target=100.0,
     return hh, cnt, int(it)
 
 
-def density(x, y, z, h, m, lo, hi, periodic, off, ids):
+def volume_weights(m, rho_prev, p):
+    """Generalised volume-element weights X = (m / rho_prev)^p."""
+    X = np.zeros(len(m))
+    lib().orc_volume_weights(len(m), _d(m), _d(rho_prev), float(p), X)
+    return X
+
+
+def density(x, y, z, h, m, lo, hi, periodic, off, ids, X=None):
+    """Summation density; with weights X the generalised volume elements
+    (rho = k m / X, k = sum X W)."""
     n = len(x)
     rho = np.zeros(n)
     blo, bhi, bper = _box(lo, hi, periodic)
-    lib().orc_density(n, _d(x), _d(y), _d(z), _d(h), _d(m), blo, bhi, bper,
-                      np.ascontiguousarray(off, dtype=np.int64),
-                      np.ascontiguousarray(ids, dtype=np.int32), rho)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    ids = np.ascontiguousarray(ids, dtype=np.int32)
+    if X is None:
+        lib().orc_density(n, _d(x), _d(y), _d(z), _d(h), _d(m), blo, bhi, bper, off, ids,
+                          rho)
+    else:
+        lib().orc_density_weighted(n, _d(x), _d(y), _d(z), _d(h), _d(m), _d(X), blo, bhi,
+                                   bper, off, ids, rho)
     return rho
 
 
@@ -220,20 +243,25 @@ def eos(params, rho, u, rho_ref, p_bg):
 
 
 def momentum_energy(x, y, z, vx, vy, vz, h, m, rho, c, pr2, lo, hi, periodic,
-                    off, ids, params, scales=False):
-    """Returns dict ax, ay, az, dudt, mumax (and sa, su if scales)."""
+                    off, ids, params, scales=False, X=None):
+    """Returns dict ax, ay, az, dudt, mumax (and sa, su if scales); with
+    weights X the generalised volume elements."""
     n = len(x)
     out = {k: np.zeros(n) for k in ("ax", "ay", "az", "dudt", "mumax")}
     sa = np.zeros(n) if scales else None
     su = np.zeros(n) if scales else None
     blo, bhi, bper = _box(lo, hi, periodic)
-    lib().orc_momentum_energy(
-        n, _d(x), _d(y), _d(z), _d(vx), _d(vy), _d(vz), _d(h), _d(m), _d(rho),
-        _d(c), _d(pr2), blo, bhi, bper, np.ascontiguousarray(off, dtype=np.int64),
-        np.ascontiguousarray(ids, dtype=np.int32), float(params.alpha),
-        float(params.beta), float(params.eta2), out["ax"], out["ay"], out["az"],
-        out["dudt"], out["mumax"], None if sa is None else sa.ctypes.data,
-        None if su is None else su.ctypes.data)
+    head = [n, _d(x), _d(y), _d(z), _d(vx), _d(vy), _d(vz), _d(h), _d(m)]
+    tail = [_d(rho), _d(c), _d(pr2), blo, bhi, bper,
+            np.ascontiguousarray(off, dtype=np.int64),
+            np.ascontiguousarray(ids, dtype=np.int32), float(params.alpha),
+            float(params.beta), float(params.eta2), out["ax"], out["ay"], out["az"],
+            out["dudt"], out["mumax"], None if sa is None else sa.ctypes.data,
+            None if su is None else su.ctypes.data]
+    if X is None:
+        lib().orc_momentum_energy(*head, *tail)
+    else:
+        lib().orc_momentum_energy_weighted(*head, _d(X), *tail)
     if scales:
         out["sa"], out["su"] = sa, su
     return out
@@ -296,6 +324,11 @@ class OracleRun:
     rho_ref: the per-particle Tait reference density. None means
     rho_ref := rho(t = 0), this run's own summation density (the reading used
     for the square patch); an array is used as given.
+
+    With params.volume == 1 (generalised volume elements) each force
+    evaluation takes the weights X = (m / rho~)^p from the previous density
+    rho~ (at t = 0 from the standard summation density) and uses them in the
+    density and in the momentum and energy equations.
     """
 
     def __init__(self, ic, rho_ref=None, g=None):
@@ -316,13 +349,20 @@ class OracleRun:
         off, ids = neighbors(s["x"], s["y"], s["z"], s["h"], lo, hi, per)
         self.off, self.ids = off, ids
         self.n_pairs = int(off[-1])
-        rho = density(s["x"], s["y"], s["z"], s["h"], s["m"], lo, hi, per, off, ids)
+        X = None
+        if getattr(self.params, "volume", 0) == 1:
+            prev = getattr(self, "rho", None)
+            if prev is None:
+                prev = density(s["x"], s["y"], s["z"], s["h"], s["m"], lo, hi, per, off, ids)
+            X = volume_weights(s["m"], prev, self.params.volume_p)
+        rho = density(s["x"], s["y"], s["z"], s["h"], s["m"], lo, hi, per, off, ids, X=X)
         if self.rho_ref is None:
             self.rho_ref = rho.copy()
         p, c, pr2 = eos(self.params, rho, s["u"], self.rho_ref, s["p_bg"])
         acc = momentum_energy(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"],
                               s["h"], s["m"], rho, c, pr2, lo, hi, per, off, ids,
-                              self.params)
+                              self.params, X=X)
+        self.X = X
         self.rho, self.p, self.c, self.pr2, self.acc = rho, p, c, pr2, acc
         return acc
 

@@ -19,6 +19,9 @@
  *   gradient  kernel derivatives, standard volume elements m/rho (Table 1);
  *             or the integral approach to derivatives (IAD, Table 1 for
  *             SPHYNX; orc_set_gradient), with the same volume elements
+ *   volumes   standard (X = m), or SPHYNX's generalised volume elements
+ *             (Table 1) with weights X (orc_density_weighted and
+ *             orc_momentum_energy_weighted)
  *   density   summation, self term included, gather with h_i
  *   variable h  neighbour iff r^2 < (2 max(h_i, h_j))^2; gradient is the
  *             mean of grad W(r, h_i) and grad W(r, h_j)
@@ -517,6 +520,42 @@ void orc_density(int64_t n, const double *x, const double *y, const double *z,
     }
 }
 
+/* ------------------------------------------ generalised volume elements */
+
+/*
+ * Generalised volume elements (Table 1, SPHYNX; Cabezon, Garcia-Senz &
+ * Figueira 2017, in the general form of Hopkins 2013). With weights X_j:
+ *   k_i   = X_i W(0, h_i) + sum_{j in N_i} X_j W(r_ij, h_i),
+ *   V_i   = X_i / k_i,   rho_i = m_i / V_i = k_i (m_i / X_i),
+ * and X_i = (m_i / rho~_i)^p from a previous density estimate rho~. X = m
+ * gives the standard elements (m_i / X_i = 1 exactly).
+ */
+void orc_volume_weights(int64_t n, const double *m, const double *rho_prev, double p,
+                        double *X)
+{
+    for (int64_t i = 0; i < n; ++i) X[i] = pow(m[i] / rho_prev[i], p);
+}
+
+void orc_density_weighted(int64_t n, const double *x, const double *y, const double *z,
+                          const double *h, const double *m, const double *X,
+                          const double *lo, const double *hi, const int32_t *per,
+                          const int64_t *offsets, const int32_t *ids, double *rho)
+{
+    orc_box b = make_box(lo, hi, per);
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        double k = X[i] * orc_kernel_w(0.0, h[i]);
+        for (int64_t q = offsets[i]; q < offsets[i + 1]; ++q) {
+            int64_t j = ids[q];
+            double dx, dy, dz;
+            separation(x, y, z, i, j, &b, &dx, &dy, &dz);
+            double r = sqrt(dist2(dx, dy, dz));
+            k += X[j] * orc_kernel_w(r, h[i]);
+        }
+        rho[i] = k * (m[i] / X[i]);
+    }
+}
+
 /* ------------------------------------------------------------------ EOS */
 
 /*
@@ -613,7 +652,7 @@ void orc_iad_matrices(int64_t n, const double *x, const double *y, const double 
 /* ------------------------------------------------- momentum and energy */
 
 /*
- * For each j in N_i (ascending):
+ * Without weights (standard volume elements), for each j in N_i (ascending):
  *   gradW = 1/2 [dW/dr(r, h_i) + dW/dr(r, h_j)] r_ij / r  (zero when r = 0)
  *   mu    = hbar (v_ij . r_ij) / (r^2 + eta2 hbar^2) if v_ij . r_ij < 0 else 0
  *   Pi    = (-alpha cbar mu + beta mu^2) / rhobar
@@ -621,16 +660,23 @@ void orc_iad_matrices(int64_t n, const double *x, const double *y, const double 
  *   a_i  -= m_j G gradW ;  du_i += 1/2 m_j G v_ij . gradW ; mumax_i = max |mu|
  * Also the error scales S^a_i = sum m_j |G| |gradW| and
  * S^u_i = 1/2 sum m_j |G| |v_ij| |gradW| (either output may be NULL).
+ *
+ * With generalised volume elements of weights X, the pair weight m_j G
+ * becomes (the same form with X = m)
+ *   F_ij = (X_j Q_i + X_i Q_j) / m_i + m_j Pi_ij,  Q_i = m_i^2 pr2_i / X_i,
+ * from m_i a_i = -sum_j X_i X_j (P_i / k_i^2 + P_j / k_j^2) gradW_ij with
+ * k = rho X / m; F_ij m_i is symmetric in i and j, so momentum and energy
+ * stay conserved. IAD keeps V_j = m_j / rho_j, which equals X_j / k_j.
  */
-void orc_momentum_energy(int64_t n, const double *x, const double *y,
-                         const double *z, const double *vx, const double *vy,
-                         const double *vz, const double *h, const double *m,
-                         const double *rho, const double *c, const double *pr2,
-                         const double *lo, const double *hi, const int32_t *per,
-                         const int64_t *offsets, const int32_t *ids,
-                         double alpha, double beta, double eta2,
-                         double *ax, double *ay, double *az, double *dudt,
-                         double *mumax, double *sa, double *su)
+static void momentum_energy_impl(int64_t n, const double *x, const double *y,
+                                 const double *z, const double *vx, const double *vy,
+                                 const double *vz, const double *h, const double *m,
+                                 const double *X, const double *rho, const double *c,
+                                 const double *pr2, const double *lo, const double *hi,
+                                 const int32_t *per, const int64_t *offsets,
+                                 const int32_t *ids, double alpha, double beta, double eta2,
+                                 double *ax, double *ay, double *az, double *dudt,
+                                 double *mumax, double *sa, double *su)
 {
     orc_box b = make_box(lo, hi, per);
     double *c6 = NULL;
@@ -673,14 +719,19 @@ void orc_momentum_energy(int64_t n, const double *x, const double *y,
             if (vdotr < 0.0) mu = hbar * vdotr / (r2 + eta2 * hbar * hbar);
             double Pi = (-alpha * cbar * mu + beta * mu * mu) / rhobar;
             double G = pr2[i] + pr2[j] + Pi;
-            axi -= m[j] * G * gx;
-            ayi -= m[j] * G * gy;
-            azi -= m[j] * G * gz;
-            dui += 0.5 * m[j] * G * (wx * gx + wy * gy + wz * gz);
+            double F = m[j] * G;
+            if (X) {
+                double Qi = m[i] * m[i] * pr2[i] / X[i], Qj = m[j] * m[j] * pr2[j] / X[j];
+                F = (X[j] * Qi + X[i] * Qj) / m[i] + m[j] * Pi;
+            }
+            axi -= F * gx;
+            ayi -= F * gy;
+            azi -= F * gz;
+            dui += 0.5 * F * (wx * gx + wy * gy + wz * gz);
             if (fabs(mu) > mum) mum = fabs(mu);
             double gn = sqrt(gx * gx + gy * gy + gz * gz);
-            sai += m[j] * fabs(G) * gn;
-            sui += 0.5 * m[j] * fabs(G) * sqrt(wx * wx + wy * wy + wz * wz) * gn;
+            sai += fabs(F) * gn;
+            sui += 0.5 * fabs(F) * sqrt(wx * wx + wy * wy + wz * wz) * gn;
         }
         ax[i] = axi; ay[i] = ayi; az[i] = azi; dudt[i] = dui;
         if (mumax) mumax[i] = mum;
@@ -688,6 +739,34 @@ void orc_momentum_energy(int64_t n, const double *x, const double *y,
         if (su) su[i] = sui;
     }
     free(c6);
+}
+
+void orc_momentum_energy(int64_t n, const double *x, const double *y,
+                         const double *z, const double *vx, const double *vy,
+                         const double *vz, const double *h, const double *m,
+                         const double *rho, const double *c, const double *pr2,
+                         const double *lo, const double *hi, const int32_t *per,
+                         const int64_t *offsets, const int32_t *ids,
+                         double alpha, double beta, double eta2,
+                         double *ax, double *ay, double *az, double *dudt,
+                         double *mumax, double *sa, double *su)
+{
+    momentum_energy_impl(n, x, y, z, vx, vy, vz, h, m, NULL, rho, c, pr2, lo, hi, per,
+                         offsets, ids, alpha, beta, eta2, ax, ay, az, dudt, mumax, sa, su);
+}
+
+void orc_momentum_energy_weighted(int64_t n, const double *x, const double *y,
+                                  const double *z, const double *vx, const double *vy,
+                                  const double *vz, const double *h, const double *m,
+                                  const double *X, const double *rho, const double *c,
+                                  const double *pr2, const double *lo, const double *hi,
+                                  const int32_t *per, const int64_t *offsets,
+                                  const int32_t *ids, double alpha, double beta,
+                                  double eta2, double *ax, double *ay, double *az,
+                                  double *dudt, double *mumax, double *sa, double *su)
+{
+    momentum_energy_impl(n, x, y, z, vx, vy, vz, h, m, X, rho, c, pr2, lo, hi, per, offsets,
+                         ids, alpha, beta, eta2, ax, ay, az, dudt, mumax, sa, su);
 }
 
 /* ------------------------------------------------------------ time-step */

@@ -41,6 +41,8 @@ class SphParams:
     eos: 0 = weakly compressible Tait, 1 = ideal gas.
     kernel: 0 = M4 spline, 1 = Wendland C2, 2 = sinc of exponent sinc_n.
     gradient: 0 = kernel derivatives, 1 = integral approach (IAD).
+    volume: 0 = standard volume elements m/rho, 1 = generalised volume
+    elements with weights X = (m / rho_previous)^volume_p.
     The Tait exponent, eta^2, the Courant and force factors are the usual
     Monaghan (1992, 1994) choices; the paper leaves them open.
     """
@@ -58,6 +60,8 @@ class SphParams:
     kernel: int = 0
     sinc_n: int = 5
     gradient: int = 0
+    volume: int = 0
+    volume_p: float = 0.7
 
 
 @dataclass

@@ -580,3 +580,106 @@ def test_iad_exact_linear_fields(family, n):
     assert inner.sum() == 8 ** 3
     assert errs[O.GRADIENT_IAD][0] < 1e-13 and errs[O.GRADIENT_IAD][1] < 1e-13
     assert errs[O.GRADIENT_KERNEL][0] > 1e-6 and errs[O.GRADIENT_KERNEL][1] > 1e-6
+
+
+def _forces_inputs(ic, seed=5):
+    """Neighbours, standard density and a non-uniform pressure field."""
+    off, ids = O.neighbors(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi, ic.periodic)
+    rho = O.density(ic.x, ic.y, ic.z, ic.h, ic.m, ic.lo, ic.hi, ic.periodic, off, ids)
+    rng = np.random.default_rng(seed)
+    pr2 = 1.0 + 0.5 * rng.random(ic.n)
+    c = 5.0 + rng.random(ic.n)
+    return off, ids, rho, pr2, c
+
+
+def test_gve_mass_weights_reduce_to_standard():
+    """Generalised volume elements (Table 1, SPHYNX) with X = m are the
+    standard elements: the density bit for bit (m/X = 1 exactly), the forces
+    to round-off."""
+    ic = I.random_cloud(2000, seed=41, h_min=0.04, h_max=0.07, velocity=2.0,
+                        periodic=(0, 0, 1))
+    off, ids, rho, pr2, c = _forces_inputs(ic)
+    rho_x = O.density(ic.x, ic.y, ic.z, ic.h, ic.m, ic.lo, ic.hi, ic.periodic, off, ids,
+                      X=ic.m)
+    assert np.array_equal(rho_x, rho)
+    args = (ic.x, ic.y, ic.z, ic.vx, ic.vy, ic.vz, ic.h, ic.m, rho, c, pr2, ic.lo, ic.hi,
+            ic.periodic, off, ids, ic.params)
+    a = O.momentum_energy(*args, scales=True)
+    b = O.momentum_energy(*args, scales=True, X=ic.m)
+    for k in ("ax", "ay", "az"):
+        assert (np.abs(a[k] - b[k]) <= 1e-14 * a["sa"]).all()
+    assert (np.abs(a["dudt"] - b["dudt"]) <= 1e-14 * a["su"]).all()
+
+
+def test_gve_unit_weights_are_number_density_sph():
+    """X = 1 is number-density SPH (Hopkins 2013): n_i = sum_j W(r_ij, h_i)
+    including the self term, rho_i = m_i n_i, and without viscosity
+    m_i a_i = -sum_j (P_i/n_i^2 + P_j/n_j^2) gradW_ij,
+    m_i du_i/dt = 1/2 sum_j (P_i/n_i^2 + P_j/n_j^2) v_ij . gradW_ij,
+    evaluated here independently in those variables."""
+    ic = I.random_cloud(600, seed=43, h_min=0.06, h_max=0.09, velocity=1.5,
+                        periodic=(0, 0, 0))
+    ic.m[:] = np.random.default_rng(2).uniform(0.5, 1.5, ic.n) * ic.m
+    off, ids, _, pr2, c = _forces_inputs(ic, seed=7)
+    one = np.ones(ic.n)
+    rho = O.density(ic.x, ic.y, ic.z, ic.h, ic.m, ic.lo, ic.hi, ic.periodic, off, ids, X=one)
+    P = np.stack([ic.x, ic.y, ic.z], 1)
+    V = np.stack([ic.vx, ic.vy, ic.vz], 1)
+    nd = np.array([O.kernel_w(0.0, ic.h[i]) + sum(
+        O.kernel_w(float(np.linalg.norm(P[i] - P[j])), ic.h[i])
+        for j in ids[off[i]:off[i + 1]]) for i in range(ic.n)])
+    assert np.allclose(rho, ic.m * nd, rtol=1e-14, atol=0)
+    prm = dataclasses.replace(ic.params, alpha=0.0, beta=0.0)
+    acc = O.momentum_energy(ic.x, ic.y, ic.z, ic.vx, ic.vy, ic.vz, ic.h, ic.m, rho, c, pr2,
+                            ic.lo, ic.hi, ic.periodic, off, ids, prm, scales=True, X=one)
+    Pn2 = pr2 * rho ** 2 / nd ** 2       # P / n^2
+    for i in range(0, ic.n, 7):
+        f = np.zeros(3)
+        du = 0.0
+        for j in ids[off[i]:off[i + 1]]:
+            d = P[i] - P[j]
+            r = np.linalg.norm(d)
+            gw = 0.5 * (O.kernel_dwdr(r, ic.h[i]) + O.kernel_dwdr(r, ic.h[j])) * d / r
+            f -= (Pn2[i] + Pn2[j]) * gw
+            du += 0.5 * (Pn2[i] + Pn2[j]) * np.dot(V[i] - V[j], gw)
+        a = np.array([acc["ax"][i], acc["ay"][i], acc["az"][i]])
+        assert np.linalg.norm(a - f / ic.m[i]) <= 1e-12 * acc["sa"][i]
+        assert abs(acc["dudt"][i] - du / ic.m[i]) <= 1e-12 * acc["su"][i]
+
+
+@pytest.mark.parametrize("gradient", [O.GRADIENT_KERNEL, O.GRADIENT_IAD])
+def test_gve_conservation(gradient):
+    """With weights X = (m / rho)^0.7 the pair force X_j Q_i + X_i Q_j is
+    symmetric, so sum m a = 0 and the power balance hold to round-off (also
+    with IAD); a uniform periodic lattice feels no force."""
+    O.set_gradient(gradient)
+    try:
+        ic = I.random_cloud(2000, seed=13, h_min=0.04, h_max=0.07, velocity=2.0)
+        ic.m[:] = np.random.default_rng(3).uniform(0.5, 1.5, ic.n) * ic.m
+        off, ids, rho0, pr2, c = _forces_inputs(ic)
+        X = O.volume_weights(ic.m, rho0, 0.7)
+        assert np.allclose(X, (ic.m / rho0) ** 0.7, rtol=1e-15)
+        rho = O.density(ic.x, ic.y, ic.z, ic.h, ic.m, ic.lo, ic.hi, ic.periodic, off, ids, X=X)
+        acc = O.momentum_energy(ic.x, ic.y, ic.z, ic.vx, ic.vy, ic.vz, ic.h, ic.m, rho, c,
+                                pr2, ic.lo, ic.hi, ic.periodic, off, ids, ic.params,
+                                scales=True, X=X)
+        m = ic.m
+        F = np.array([np.sum(m * acc[k]) for k in ("ax", "ay", "az")])
+        assert np.linalg.norm(F) <= 1e-13 * np.sum(m * acc["sa"])
+        vmag = np.sqrt(ic.vx ** 2 + ic.vy ** 2 + ic.vz ** 2)
+        power = np.sum(m * (ic.vx * acc["ax"] + ic.vy * acc["ay"] + ic.vz * acc["az"]
+                            + acc["dudt"]))
+        assert abs(power) <= 1e-13 * np.sum(m * (vmag * acc["sa"] + acc["su"]))
+        lat = I.lattice_periodic(12, spacing=2.0 ** -4)
+        off, ids, rho0, _, _ = _forces_inputs(lat)
+        X = O.volume_weights(lat.m, rho0, 0.7)
+        rho = O.density(lat.x, lat.y, lat.z, lat.h, lat.m, lat.lo, lat.hi, lat.periodic,
+                        off, ids, X=X)
+        assert np.allclose(rho, rho0, rtol=1e-14)
+        acc = O.momentum_energy(lat.x, lat.y, lat.z, lat.vx, lat.vy, lat.vz, lat.h, lat.m,
+                                rho, np.full(lat.n, 5.0), np.full(lat.n, 3.0), lat.lo, lat.hi,
+                                lat.periodic, off, ids, lat.params, scales=True, X=X)
+        amag = np.sqrt(acc["ax"] ** 2 + acc["ay"] ** 2 + acc["az"] ** 2)
+        assert (amag <= 1e-13 * acc["sa"]).all()
+    finally:
+        O.set_gradient(O.GRADIENT_KERNEL)
