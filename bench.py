@@ -418,10 +418,11 @@ def run_serving(runs: int, steps: int = 50, budget_gib: float = 8.0) -> dict:
 
 
 def run_kernels(ic, steps: int, warmup: int) -> dict:
-    """The interchangeable kernels (M4, Wendland C2, sinc n = 5) and the IAD
-    gradients (with M4) on the same neighbour lists: time per sph_density and
-    per sph_momentum_energy call (IAD: including its matrix pass), FP64, and
-    the pair rate of the two together."""
+    """The interchangeable kernels (M4, Wendland C2, sinc n = 5), the IAD
+    gradients and the generalised volume elements (both with M4) on the same
+    neighbour lists: time per sph_density and per sph_momentum_energy call
+    (IAD: including its matrix pass), FP64, and the pair rate of the two
+    together."""
     import dataclasses
 
     import torch
@@ -437,11 +438,16 @@ def run_kernels(ic, steps: int, warmup: int) -> dict:
     out = {"workload": "rotating square patch 100^3, the same lists; density and "
                        "momentum/energy calls only", "pairs": pairs}
     stream = ctx.stream
-    for name, fam, n, grad in (("m4", S.SPH_KERNEL_M4, 5, S.SPH_GRAD_KERNEL),
-                               ("wendland_c2", S.SPH_KERNEL_WENDLAND_C2, 5, S.SPH_GRAD_KERNEL),
-                               ("sinc_5", S.SPH_KERNEL_SINC, 5, S.SPH_GRAD_KERNEL),
-                               ("m4_iad", S.SPH_KERNEL_M4, 5, S.SPH_GRAD_IAD)):
-        prm = S.make_params(dataclasses.replace(ic.params, kernel=fam, sinc_n=n, gradient=grad))
+    G0, VS, VG = S.SPH_GRAD_KERNEL, S.SPH_VOLUME_STANDARD, S.SPH_VOLUME_GENERALISED
+    for name, fam, n, grad, vol in (("m4", S.SPH_KERNEL_M4, 5, G0, VS),
+                                    ("wendland_c2", S.SPH_KERNEL_WENDLAND_C2, 5, G0, VS),
+                                    ("sinc_5", S.SPH_KERNEL_SINC, 5, G0, VS),
+                                    ("m4_iad", S.SPH_KERNEL_M4, 5, S.SPH_GRAD_IAD, VS),
+                                    ("m4_gve", S.SPH_KERNEL_M4, 5, G0, VG)):
+        prm = S.make_params(dataclasses.replace(ic.params, kernel=fam, sinc_n=n, gradient=grad,
+                                                volume=vol))
+        if vol == VG:
+            S.sph_volume_weights(ctx, st, 0.7)  # weights from the standard density
         for _ in range(warmup):
             S.sph_density(ctx, st, prm)
             S.sph_eos(ctx, st, prm)

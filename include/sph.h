@@ -76,12 +76,16 @@ typedef void *sph_stream; /* a hipStream_t; NULL = the null stream */
 /* Particle state. gx, gy, gz: optional fixed external acceleration (NULL
  * when absent); they are permuted with the rest. rho_ref and p_bg are the
  * per-particle Tait reference density and background pressure (read only by
- * the Tait EOS; may be NULL for the ideal gas). */
+ * the Tait EOS; may be NULL for the ideal gas). xw: the weights X of
+ * generalised volume elements (see SPH_VOLUME_GENERALISED), required only
+ * when sph_params.volume selects them, else may be NULL; permuted with the
+ * rest when present. */
 typedef struct {
     int64_t n;
     double *x, *y, *z, *vx, *vy, *vz, *u, *h, *m, *rho_ref, *p_bg;
     double *gx, *gy, *gz;
     int32_t *id;
+    double *xw;
 } sph_particles;
 
 /* Axis-aligned box. On a periodic axis positions live in [lo, hi) and the
@@ -133,6 +137,22 @@ enum { SPH_KERNEL_M4 = 0, SPH_KERNEL_WENDLAND_C2 = 1, SPH_KERNEL_SINC = 2 };
  *                    use (A_ij - A_ji) / 2 in place of the kernel gradient. */
 enum { SPH_GRAD_KERNEL = 0, SPH_GRAD_IAD = 1 };
 
+/* Volume elements (Table 1: SPHYNX uses generalised ones, the other codes
+ * the standard m/rho):
+ *   SPH_VOLUME_STANDARD     V_i = m_i / rho_i
+ *   SPH_VOLUME_GENERALISED  V_i = X_i / k_i with k_i = sum_j X_j W(r_ij, h_i)
+ *                           (self term included) and weights X = p->xw,
+ *                           normally X_i = (m_i / rho_i)^volume_p from the
+ *                           previous density (sph_volume_weights). Then
+ *                           rho_i = k_i (m_i / X_i), and the pair weight
+ *                           m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi_ij) of the
+ *                           momentum and energy equations becomes
+ *                           (X_j Q_i + X_i Q_j) / m_i + m_j Pi_ij with
+ *                           Q_i = m_i^2 P_i / (rho_i^2 X_i), the general form
+ *                           of Hopkins (2013). X = m is the standard case. IAD
+ *                           keeps V_j = m_j / rho_j (equal to X_j / k_j). */
+enum { SPH_VOLUME_STANDARD = 0, SPH_VOLUME_GENERALISED = 1 };
+
 /* Scalar physics constants (host memory). precision selects the pair
  * arithmetic of sph_density and sph_momentum_energy: SPH_FP64, or
  * SPH_FP32_PAIR (separations formed in FP64 and rounded to FP32, FP32 copies
@@ -142,7 +162,9 @@ enum { SPH_GRAD_KERNEL = 0, SPH_GRAD_IAD = 1 };
  * default of a zeroed struct, is M4); sinc_n is the sinc exponent, read only
  * for SPH_KERNEL_SINC; gradient selects SPH_GRAD_KERNEL (zero) or
  * SPH_GRAD_IAD for sph_momentum_energy (IAD matrices are formed inside that
- * call, in FP64 for both precisions). */
+ * call, in FP64 for both precisions); volume selects the volume elements of
+ * both pair calls and volume_p the exponent used by sph_step and
+ * sph_init_forces to form the weights. */
 typedef struct {
     int32_t precision;
     int32_t eos;
@@ -152,6 +174,8 @@ typedef struct {
     int32_t kernel;
     int32_t sinc_n;
     int32_t gradient;
+    int32_t volume;
+    double volume_p;
 } sph_params;
 
 /* Text for a status code (static storage). */
@@ -197,7 +221,9 @@ sph_status sph_find_neighbors(sph_ctx ctx, const sph_particles *p,
                               const sph_box *box, const sph_nbrs *nb);
 
 /* Algorithm 1, step 3: summation density
- * rho_i = m_i W(0,h_i) + sum_{j in N_i} m_j W(r_ij, h_i). */
+ * rho_i = m_i W(0,h_i) + sum_{j in N_i} m_j W(r_ij, h_i); with generalised
+ * volume elements rho_i = k_i (m_i / X_i), k_i = X_i W(0,h_i) +
+ * sum_{j in N_i} X_j W(r_ij, h_i), X = p->xw (SPH_E_INVALID if NULL). */
 sph_status sph_density(sph_ctx ctx, const sph_particles *p,
                        const sph_box *box, const sph_nbrs *nb,
                        const sph_params *prm, double *rho);
@@ -210,11 +236,20 @@ sph_status sph_eos(sph_ctx ctx, const sph_particles *p, const sph_params *prm,
 
 /* Algorithm 1, step 3: acceleration, du/dt and per-particle max |mu|.
  * Like sph_find_neighbors, it takes h as of the last sph_build_cells (h must
- * not change between the build and the pair calls of a step). */
+ * not change between the build and the pair calls of a step). With
+ * generalised volume elements it reads the weights p->xw (the same the
+ * density used; SPH_E_INVALID if NULL). */
 sph_status sph_momentum_energy(sph_ctx ctx, const sph_particles *p,
                                const sph_box *box, const sph_nbrs *nb,
                                const sph_params *prm, const sph_fields *f,
                                const sph_accel *a);
+
+/* Weights of generalised volume elements (Table 1, SPHYNX) from a density
+ * estimate: p->xw[i] = (p->m[i] / rho[i])^exponent, FP64, in the current
+ * particle order (rho: device, n doubles, e.g. the previous step's density).
+ * SPH_E_INVALID for NULL arrays or a non-finite exponent. */
+sph_status sph_volume_weights(sph_ctx ctx, const sph_particles *p, const double *rho,
+                              double exponent);
 
 /* Algorithm 1, step 4 (self-gravity; Sec. 5.2.5 phase I) by direct
  * summation in FP64, G = 1, Plummer softening eps >= 0:
@@ -249,7 +284,10 @@ sph_status sph_timestep(sph_ctx ctx, const sph_particles *p,
 
 /* Forces at the current state: build cells, neighbours, density, EOS (if
  * set_rho_ref, rho_ref := rho first, so that P = p_bg), momentum and energy,
- * then dt. The t = 0 evaluation that precedes the first step. */
+ * then dt. The t = 0 evaluation that precedes the first step. With
+ * generalised volume elements the density is first taken with standard
+ * elements and the weights p->xw formed from it (sph_volume_weights with
+ * prm->volume_p). */
 sph_status sph_init_forces(sph_ctx ctx, const sph_particles *p,
                            const sph_box *box, double h_max,
                            const sph_nbrs *nb, const sph_params *prm,
@@ -259,7 +297,9 @@ sph_status sph_init_forces(sph_ctx ctx, const sph_particles *p,
 
 /* One whole hydro step: sph_integrate(KICK_DRIFT), sph_build_cells,
  * sph_find_neighbors, sph_density, sph_eos, sph_momentum_energy,
- * sph_integrate(KICK), sph_timestep, in that order on ctx's stream. */
+ * sph_integrate(KICK), sph_timestep, in that order on ctx's stream. With
+ * generalised volume elements the step first forms the weights p->xw from
+ * the previous density f->rho (sph_volume_weights with prm->volume_p). */
 sph_status sph_step(sph_ctx ctx, const sph_particles *p, const sph_box *box,
                     double h_max, const sph_nbrs *nb, const sph_params *prm,
                     const sph_fields *f, const sph_accel *a, double *dt_dev,

@@ -171,6 +171,10 @@ sph_status check_params(sph_ctx ctx, const sph_params *prm)
         return fail(ctx, SPH_E_INVALID, "sinc exponent %d outside [3, 12]", prm->sinc_n);
     if (prm->gradient != SPH_GRAD_KERNEL && prm->gradient != SPH_GRAD_IAD)
         return fail(ctx, SPH_E_INVALID, "unknown gradient %d", prm->gradient);
+    if (prm->volume != SPH_VOLUME_STANDARD && prm->volume != SPH_VOLUME_GENERALISED)
+        return fail(ctx, SPH_E_INVALID, "unknown volume elements %d", prm->volume);
+    if (prm->volume == SPH_VOLUME_GENERALISED && !std::isfinite(prm->volume_p))
+        return fail(ctx, SPH_E_INVALID, "volume_p must be finite");
     return SPH_OK;
 }
 
@@ -392,7 +396,23 @@ sph_status sph_density(sph_ctx ctx, const sph_particles *p, const sph_box *box,
     if (ctx->n_built != p->n || !same_box(ctx->grid, *box))
         return fail(ctx, SPH_E_INVALID, "sph_build_cells was not called for these particles/box");
     if (p->n == 0) return SPH_OK;
-    SPH_HIP(ctx, launch_density(ctx, *p, *nb, prm->precision, kernel_sel(*prm), rho));
+    const bool gve = prm->volume == SPH_VOLUME_GENERALISED;
+    if (gve && !p->xw)
+        return fail(ctx, SPH_E_INVALID, "generalised volume elements need p->xw");
+    SPH_HIP(ctx, launch_density(ctx, *p, *nb, prm->precision, kernel_sel(*prm), gve, rho));
+    return SPH_OK;
+}
+
+sph_status sph_volume_weights(sph_ctx ctx, const sph_particles *p, const double *rho,
+                              double exponent)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, false)) != SPH_OK) return s;
+    if (!std::isfinite(exponent)) return fail(ctx, SPH_E_INVALID, "exponent must be finite");
+    if (p->n == 0) return SPH_OK;
+    if (!rho || !p->xw) return fail(ctx, SPH_E_INVALID, "rho and p->xw are required");
+    SPH_HIP(ctx, launch_volume_weights(ctx, *p, rho, exponent));
     return SPH_OK;
 }
 
@@ -445,6 +465,8 @@ sph_status sph_momentum_energy(sph_ctx ctx, const sph_particles *p, const sph_bo
     if (p->n == 0) return SPH_OK;
     if (!f->rho || !f->c || !f->pr2 || !a->ax || !a->ay || !a->az || !a->dudt || !a->mumax)
         return fail(ctx, SPH_E_INVALID, "rho, c, pr2, ax, ay, az, dudt, mumax are required");
+    if (prm->volume == SPH_VOLUME_GENERALISED && !p->xw)
+        return fail(ctx, SPH_E_INVALID, "generalised volume elements need p->xw");
     SPH_HIP(ctx, launch_momentum(ctx, *p, *nb, *prm, *f, *a));
     return SPH_OK;
 }
@@ -490,6 +512,14 @@ sph_status sph_init_forces(sph_ctx ctx, const sph_particles *p, const sph_box *b
     if ((s = sph_build_cells(ctx, p, box, h_max)) != SPH_OK) return s;
     if ((s = sph_find_neighbors(ctx, p, box, nb)) != SPH_OK) return s;
     if (!f) return fail(ctx, SPH_E_INVALID, "fields is NULL");
+    if ((s = check_params(ctx, prm)) != SPH_OK) return s;
+    if (prm->volume == SPH_VOLUME_GENERALISED) {
+        // no previous density yet: seed the weights from the standard one
+        sph_params std_prm = *prm;
+        std_prm.volume = SPH_VOLUME_STANDARD;
+        if ((s = sph_density(ctx, p, box, nb, &std_prm, f->rho)) != SPH_OK) return s;
+        if ((s = sph_volume_weights(ctx, p, f->rho, prm->volume_p)) != SPH_OK) return s;
+    }
     if ((s = sph_density(ctx, p, box, nb, prm, f->rho)) != SPH_OK) return s;
     if (set_rho_ref && p->n > 0) {
         if (!p->rho_ref) return fail(ctx, SPH_E_INVALID, "set_rho_ref needs rho_ref");
@@ -505,6 +535,11 @@ sph_status sph_step(sph_ctx ctx, const sph_particles *p, const sph_box *box, dou
                     const sph_accel *a, double *dt_dev, double *diag_dev)
 {
     sph_status s;
+    if (!prm) return fail(ctx, SPH_E_INVALID, "params is NULL");
+    if (prm->volume == SPH_VOLUME_GENERALISED) {
+        if (!f) return fail(ctx, SPH_E_INVALID, "fields is NULL");
+        if ((s = sph_volume_weights(ctx, p, f->rho, prm->volume_p)) != SPH_OK) return s;
+    }
     if ((s = sph_integrate(ctx, p, box, SPH_KICK_DRIFT, dt_dev, a)) != SPH_OK) return s;
     if ((s = sph_build_cells(ctx, p, box, h_max)) != SPH_OK) return s;
     if ((s = sph_find_neighbors(ctx, p, box, nb)) != SPH_OK) return s;

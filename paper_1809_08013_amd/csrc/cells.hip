@@ -459,7 +459,7 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
 
     PermFields f{};
     double *fields[kPermFields] = {p.x, p.y, p.z, p.vx, p.vy, p.vz, p.u, p.h, p.m,
-                                   p.rho_ref, p.p_bg, p.gx, p.gy, p.gz};
+                                   p.rho_ref, p.p_bg, p.gx, p.gy, p.gz, p.xw};
     int h_field = -1;
     for (int k = 0; k < kPermFields; ++k) {
         if (!fields[k]) continue;

@@ -773,10 +773,12 @@ sph_status sph_ens_submit(sph_ens e, const sph_run_request *q, uint64_t *ticket)
     const sph_params &prm = q->params;
     if (prm.eos != SPH_EOS_TAIT && prm.eos != SPH_EOS_IDEAL)
         return efail(e, SPH_E_INVALID, "unknown eos %d", prm.eos);
-    if (prm.kernel != SPH_KERNEL_M4 || prm.gradient != SPH_GRAD_KERNEL)
+    if (prm.kernel != SPH_KERNEL_M4 || prm.gradient != SPH_GRAD_KERNEL ||
+        prm.volume != SPH_VOLUME_STANDARD)
         return efail(e, SPH_E_INVALID,
-                     "the engine runs the M4 kernel with kernel derivatives only "
-                     "(kernel %d, gradient %d)", prm.kernel, prm.gradient);
+                     "the engine runs the M4 kernel with kernel derivatives and standard "
+                     "volume elements only (kernel %d, gradient %d, volume %d)", prm.kernel,
+                     prm.gradient, prm.volume);
     if (prm.eos == SPH_EOS_TAIT && !q->set_rho_ref && !q->rho_ref)
         return efail(e, SPH_E_INVALID, "the Tait EOS needs rho_ref or set_rho_ref");
     for (int a = 0; a < 3; ++a) {

@@ -343,6 +343,28 @@ pack_dens_kernel(int64_t n, const int64_t *n_dev, const double *__restrict__ x,
         out[i] = DensRec{x[i], y[i], z[i], m[i]};
 }
 
+// Generalised volume elements: weights X_i = (m_i / rho_i)^e from a density
+// estimate, and the density from the weighted sum k_i (which the density
+// kernel leaves in rho when its records carry X instead of m):
+// rho_i = k_i (m_i / X_i).
+__global__ void __launch_bounds__(256)
+volume_weights_kernel(int64_t n, const double *__restrict__ m, const double *__restrict__ rho,
+                      double e, double *__restrict__ xw)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step)
+        xw[i] = pow(m[i] / rho[i], e);
+}
+
+__global__ void __launch_bounds__(256)
+gve_density_kernel(int64_t n, const double *__restrict__ m, const double *__restrict__ xw,
+                   double *__restrict__ rho)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step)
+        rho[i] = rho[i] * (m[i] / xw[i]);
+}
+
 // ---------------------------------------------------------------------------
 // EOS.
 __global__ void __launch_bounds__(256)
@@ -479,7 +501,8 @@ pack_vol_kernel(int64_t n, const double *__restrict__ x, const double *__restric
 // IAD: the pair terms use Abar_ij = -(W(r, h_i) c_i + W(r, h_j) c_j) r_ij / 2
 // in place of the mean kernel gradient; c_j of the next step is loaded with
 // the records.
-template <bool F32, bool Multi, bool Big, int Per, bool UH, int KF, bool IAD = false>
+template <bool F32, bool Multi, bool Big, int Per, bool UH, int KF, bool IAD = false,
+          bool GVE = false>
 __device__ __forceinline__ void momentum_tile(
     int64_t tile, int64_t n, int64_t ld, const PairRec *__restrict__ rec,
     const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
@@ -503,6 +526,10 @@ __device__ __forceinline__ void momentum_tile(
     const double mevx = mp->vx, mevy = mp->vy, mevz = mp->vz;
     const R hi = (R)mp->h, inv_hi = (R)mp->inv_h, rhoi = (R)mp->rho, ci = (R)mp->c,
             pi = (R)mp->pr2;
+    // generalised volume elements: X_i / m_i and Q_i / m_i of the own record
+    // (pad[0] = X, pad[1] = Q = m^2 P / (rho^2 X))
+    const R xim = GVE ? (R)(mp->pad[0] / mp->m) : R(0);
+    const R qim = GVE ? (R)(mp->pad[1] / mp->m) : R(0);
     const R sg = KF == KF_M4 ? (R)kInvPi : (R)prm.sigma;
     const int sn = prm.sinc_n;
     const R fi = sg * (inv_hi * inv_hi) * (inv_hi * inv_hi);
@@ -527,7 +554,7 @@ __device__ __forceinline__ void momentum_tile(
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, 64));
     const int grp = lane & ~7, s = lane & 7;
-    const bool loader = s < 6;
+    const bool loader = s < (GVE ? 7 : 6);
     const char *src_base = reinterpret_cast<const char *>(rec);
     const uint32_t chunk = 16u * (uint32_t)(loader ? s : 0);
     const char *own = buf + lane * kMomStride;
@@ -573,6 +600,8 @@ __device__ __forceinline__ void momentum_tile(
         const double2 q3 = *reinterpret_cast<const double2 *>(own + 48);  // h inv_h
         const double2 q4 = *reinterpret_cast<const double2 *>(own + 64);  // m rho
         const double2 q5 = *reinterpret_cast<const double2 *>(own + 80);  // c pr2
+        double2 q6 = make_double2(0.0, 0.0);                               // X Q
+        if constexpr (GVE) q6 = *reinterpret_cast<const double2 *>(own + 96);
         if (k < cnt) {
             const R dx = (R)img<Per>(mex - q0.x, im, 0);
             const R dy = (R)img<Per>(mey - q0.y, im, 1);
@@ -620,14 +649,21 @@ __device__ __forceinline__ void momentum_tile(
             const R inv = fast_rcp(den * rhobar);
             const R mu = vdotr < R(0) ? hbar * vdotr * (rhobar * inv) : R(0);
             const R Pi = mu * (beta * mu - alpha * cbar) * (den * inv);
+            // pair weight: m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi), or with
+            // generalised volume elements X_j Q_i/m_i + Q_j X_i/m_i + m_j Pi
+            R wgt;
+            if constexpr (GVE)
+                wgt = fma_r((R)q6.x, qim, fma_r((R)q6.y, xim, (R)q4.x * Pi));
+            else
+                wgt = (R)q4.x * (pi + (R)q5.y + Pi);
             if constexpr (IAD) {
-                const R mGs = (R)q4.x * (pi + (R)q5.y + Pi);
+                const R mGs = wgt;
                 sx = fma_r(-mGs, gx, sx);
                 sy = fma_r(-mGs, gy, sy);
                 sz = fma_r(-mGs, gz, sz);
                 su = fma_r(mGs, fma_r(wz, gz, fma_r(wy, gy, wx * gx)), su);
             } else {
-                const R mG = (R)q4.x * (pi + (R)q5.y + Pi) * F;
+                const R mG = wgt * F;
                 sx = fma_r(-mG, dx, sx);
                 sy = fma_r(-mG, dy, sy);
                 sz = fma_r(-mG, dz, sz);
@@ -645,7 +681,7 @@ __device__ __forceinline__ void momentum_tile(
     }
 }
 
-template <bool F32, bool Multi, bool Big, int Per, int KF, bool IAD = false>
+template <bool F32, bool Multi, bool Big, int Per, int KF, bool IAD = false, bool GVE = false>
 __global__ void __launch_bounds__(kThreads)
 momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
                 const int32_t *__restrict__ count, const int32_t *__restrict__ idx, int max_nb,
@@ -661,10 +697,10 @@ momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
         for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
             momentum_tile<F32, true, Big, -1, false, KF>(t, nn, ld, rec, count, idx, max_nb, g,
                                                          prm, ax, ay, az, dudt, mumax, b, buf);
-    } else if constexpr (IAD) {
-        momentum_tile<F32, false, Big, Per, false, KF, true>(xcd_block(), n, ld, rec, count,
-                                                             idx, max_nb, g, prm, ax, ay, az,
-                                                             dudt, mumax, b, buf);
+    } else if constexpr (IAD || GVE) {
+        momentum_tile<F32, false, Big, Per, false, KF, IAD, GVE>(xcd_block(), n, ld, rec,
+                                                                 count, idx, max_nb, g, prm, ax,
+                                                                 ay, az, dudt, mumax, b, buf);
     } else if (hflag[0] == 0u) {
         // uniform h (flag of the last cell build)
         momentum_tile<F32, false, Big, Per, true, KF>(xcd_block(), n, ld, rec, count, idx,
@@ -677,7 +713,8 @@ momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
     }
 }
 
-// Pair records {x, y, z, vx, vy, vz, h, 1/h, m, rho, c, P/rho^2}.
+// Pair records {x, y, z, vx, vy, vz, h, 1/h, m, rho, c, P/rho^2}, and with
+// generalised volume elements (xw not null) {X, Q = m^2 (P/rho^2) / X}.
 __global__ void __launch_bounds__(256)
 pack_pair_kernel(int64_t n, const int64_t *n_dev, const double *__restrict__ x,
                  const double *__restrict__ y, const double *__restrict__ z,
@@ -685,7 +722,7 @@ pack_pair_kernel(int64_t n, const int64_t *n_dev, const double *__restrict__ x,
                  const double *__restrict__ vz, const double *__restrict__ h,
                  const double *__restrict__ m, const double *__restrict__ rho,
                  const double *__restrict__ c, const double *__restrict__ pr2,
-                 PairRec *__restrict__ out)
+                 const double *__restrict__ xw, PairRec *__restrict__ out)
 {
     if (n_dev) n = *n_dev;
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
@@ -697,6 +734,10 @@ pack_pair_kernel(int64_t n, const int64_t *n_dev, const double *__restrict__ x,
         r.h = hi; r.inv_h = 1.0 / hi; r.m = m[i];
         r.rho = rho[i]; r.c = c[i]; r.pr2 = pr2[i];
         r.pad[0] = r.pad[1] = r.pad[2] = r.pad[3] = 0.0;
+        if (xw) {
+            r.pad[0] = xw[i];
+            r.pad[1] = r.m * r.m * r.pr2 / xw[i];
+        }
         out[i] = r;
     }
 }
@@ -773,7 +814,7 @@ void momentum_launch(hipStream_t st, unsigned blocks, int precision, bool big, i
                      int64_t ld, const PairRec *rec, const int32_t *count, const int32_t *idx,
                      int max_nb, const Grid &g, const MomParams &mp, double *ax, double *ay,
                      double *az, double *dudt, double *mumax, const BatchDev &b,
-                     const uint32_t *hflag, int family, bool iad)
+                     const uint32_t *hflag, int family, bool iad, bool gve)
 {
 #define SPH_MOM_P(F, B, P, K)                                                              \
     momentum_kernel<F, Multi, B, P, K><<<blocks, kThreads, 0, st>>>(                       \
@@ -781,10 +822,21 @@ void momentum_launch(hipStream_t st, unsigned blocks, int precision, bool big, i
 #define SPH_MOM_IAD(F, B, K)                                                               \
     momentum_kernel<F, false, B, -1, K, true><<<blocks, kThreads, 0, st>>>(                \
         n, ld, rec, count, idx, max_nb, g, mp, ax, ay, az, dudt, mumax, b, hflag)
+#define SPH_MOM_GVE(F, B, K, I)                                                            \
+    momentum_kernel<F, false, B, -1, K, I, true><<<blocks, kThreads, 0, st>>>(             \
+        n, ld, rec, count, idx, max_nb, g, mp, ax, ay, az, dudt, mumax, b, hflag)
+#define SPH_MOM_GVE_K(F, B, I)                                                             \
+    do {                                                                                   \
+        if (family == SPH_KERNEL_WENDLAND_C2) SPH_MOM_GVE(F, B, KF_WENDLAND, I);            \
+        else if (family == SPH_KERNEL_SINC) SPH_MOM_GVE(F, B, KF_SINC, I);                 \
+        else SPH_MOM_GVE(F, B, KF_M4, I);                                                  \
+    } while (0)
 #define SPH_MOM(F, B)                                                                      \
     do {                                                                                   \
         const int pm = Multi ? -1 : per_mask(g);                                           \
         if constexpr (Multi) SPH_MOM_P(F, B, -1, KF_M4);                                   \
+        else if (gve && iad) SPH_MOM_GVE_K(F, B, true);                                    \
+        else if (gve) SPH_MOM_GVE_K(F, B, false);                                          \
         else if (iad && family == SPH_KERNEL_WENDLAND_C2) SPH_MOM_IAD(F, B, KF_WENDLAND);  \
         else if (iad && family == SPH_KERNEL_SINC) SPH_MOM_IAD(F, B, KF_SINC);             \
         else if (iad) SPH_MOM_IAD(F, B, KF_M4);                                            \
@@ -801,6 +853,8 @@ void momentum_launch(hipStream_t st, unsigned blocks, int precision, bool big, i
         if (big) SPH_MOM(false, true); else SPH_MOM(false, false);
     }
 #undef SPH_MOM
+#undef SPH_MOM_GVE_K
+#undef SPH_MOM_GVE
 #undef SPH_MOM_IAD
 #undef SPH_MOM_P
 }
@@ -808,14 +862,26 @@ void momentum_launch(hipStream_t st, unsigned blocks, int precision, bool big, i
 }  // namespace
 
 hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
-                          int precision, const KernelSel &ks, double *rho)
+                          int precision, const KernelSel &ks, bool gve, double *rho)
 {
     const unsigned nblk = blocks_for(p.n, kThreads);
-    pack_dens_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, nullptr, p.x, p.y,
-                                                                    p.z, p.m, ctx->drec);
+    // generalised volume elements: the records carry X in place of m, the
+    // kernel leaves k_i in rho, which is then scaled by m_i / X_i
+    pack_dens_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
+        p.n, nullptr, p.x, p.y, p.z, gve ? p.xw : p.m, ctx->drec);
     density_launch<false>(ctx->stream, nblk, precision, big_records(p.n, sizeof(DensRec)), p.n,
                           p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho,
                           BatchDev{}, ks);
+    if (gve)
+        gve_density_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, p.m, p.xw, rho);
+    return hipGetLastError();
+}
+
+hipError_t launch_volume_weights(sph_ctx ctx, const sph_particles &p, const double *rho,
+                                 double exponent)
+{
+    volume_weights_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, p.m, rho,
+                                                                         exponent, p.xw);
     return hipGetLastError();
 }
 
@@ -847,12 +913,14 @@ hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &
         else SPH_IAD(KF_M4);
 #undef SPH_IAD
     }
+    const bool gve = prm.volume == SPH_VOLUME_GENERALISED;
     pack_pair_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
-        p.n, nullptr, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2, ctx->prec);
+        p.n, nullptr, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2,
+        gve ? p.xw : nullptr, ctx->prec);
     momentum_launch<false>(ctx->stream, nblk, prm.precision, big_records(p.n, sizeof(PairRec)),
                            p.n, p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp,
                            a.ax, a.ay, a.az, a.dudt, a.mumax, BatchDev{}, ctx->hflag_dev,
-                           ks.family, iad);
+                           ks.family, iad, gve);
     return hipGetLastError();
 }
 
@@ -897,10 +965,10 @@ hipError_t launch_momentum_batch(sph_ctx ctx, const BatchDev &b, int precision,
     pack_pair_kernel<<<g1, 256, 0, ctx->stream>>>(0, n_out, F + 0 * cap, F + 1 * cap,
                                                   F + 2 * cap, F + 3 * cap, F + 4 * cap,
                                                   F + 5 * cap, F + 7 * cap, F + 8 * cap, rho, c,
-                                                  pr2, ctx->prec);
+                                                  pr2, nullptr, ctx->prec);
     momentum_launch<true>(ctx->stream, g2, precision, big_records(cap, sizeof(PairRec)), 0, cap,
                           ctx->prec, count, idx, max_nb, Grid{}, MomParams{}, ax, ay, az, dudt,
-                          mumax, b, nullptr, SPH_KERNEL_M4, false);
+                          mumax, b, nullptr, SPH_KERNEL_M4, false, false);
     return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ constexpr int kScanChunk = kScanThreads * kScanItems;  // elements per block
 constexpr int kRedThreads = 256;
 constexpr int kRedMaxBlocks = 2048;
 constexpr int kRedFields = 9;   // dt candidate min + 8 totals
-constexpr int kPermFields = 14; // x y z vx vy vz u h m rho_ref p_bg gx gy gz
+constexpr int kPermFields = 15; // x y z vx vy vz u h m rho_ref p_bg gx gy gz xw
 
 // Uniform cell grid of one build (host values, passed to kernels by value).
 struct Grid {
@@ -233,8 +233,11 @@ struct KernelSel {
 };
 KernelSel kernel_sel(const sph_params &prm);
 
+// gve: generalised volume elements with the weights p.xw.
 hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
-                          int precision, const KernelSel &ks, double *rho);
+                          int precision, const KernelSel &ks, bool gve, double *rho);
+hipError_t launch_volume_weights(sph_ctx ctx, const sph_particles &p, const double *rho,
+                                 double exponent);
 hipError_t launch_gravity_direct(sph_ctx ctx, const sph_particles &p, double eps, double *gx,
                                  double *gy, double *gz);
 hipError_t launch_eos(sph_ctx ctx, const sph_particles &p, const sph_params &prm,

@@ -31,6 +31,7 @@ SPH_EOS_TAIT, SPH_EOS_IDEAL = 0, 1
 SPH_KICK_DRIFT, SPH_KICK = 0, 1
 SPH_KERNEL_M4, SPH_KERNEL_WENDLAND_C2, SPH_KERNEL_SINC = 0, 1, 2
 SPH_GRAD_KERNEL, SPH_GRAD_IAD = 0, 1
+SPH_VOLUME_STANDARD, SPH_VOLUME_GENERALISED = 0, 1
 
 _VP = C.c_void_p
 
@@ -44,7 +45,7 @@ class SphError(RuntimeError):
 class Particles(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(k, _VP) for k in (
         "x", "y", "z", "vx", "vy", "vz", "u", "h", "m", "rho_ref", "p_bg",
-        "gx", "gy", "gz", "id")]
+        "gx", "gy", "gz", "id", "xw")]
 
 
 class Box(C.Structure):
@@ -68,7 +69,8 @@ class Params(C.Structure):
     _fields_ = [("precision", C.c_int32), ("eos", C.c_int32)] + [
         (k, C.c_double) for k in ("rho0", "c0", "gamma_tait", "gamma_gas", "alpha",
                                   "beta", "eta2", "c_cfl", "c_force")] + [
-        ("kernel", C.c_int32), ("sinc_n", C.c_int32), ("gradient", C.c_int32)]
+        ("kernel", C.c_int32), ("sinc_n", C.c_int32), ("gradient", C.c_int32),
+        ("volume", C.c_int32), ("volume_p", C.c_double)]
 
 
 class EnsConfig(C.Structure):
@@ -132,6 +134,7 @@ def load():
             "sph_density": (C.c_int32, [_VP, P, B, N, M, _VP]),
             "sph_eos": (C.c_int32, [_VP, P, M, F]),
             "sph_gravity_direct": (C.c_int32, [_VP, P, C.c_double, _VP, _VP, _VP]),
+            "sph_volume_weights": (C.c_int32, [_VP, P, _VP, C.c_double]),
             "sph_momentum_energy": (C.c_int32, [_VP, P, B, N, M, F, A]),
             "sph_integrate": (C.c_int32, [_VP, P, B, C.c_int32, _VP, A]),
             "sph_timestep": (C.c_int32, [_VP, P, M, F, A, _VP, _VP]),
@@ -207,7 +210,9 @@ def make_params(p, precision: int = SPH_FP64) -> Params:
                   float(p.gamma_tait), float(p.gamma_gas), float(p.alpha),
                   float(p.beta), float(p.eta2), float(p.c_cfl), float(p.c_force),
                   int(getattr(p, "kernel", SPH_KERNEL_M4)), int(getattr(p, "sinc_n", 5)),
-                  int(getattr(p, "gradient", SPH_GRAD_KERNEL)))
+                  int(getattr(p, "gradient", SPH_GRAD_KERNEL)),
+                  int(getattr(p, "volume", SPH_VOLUME_STANDARD)),
+                  float(getattr(p, "volume_p", 0.7)))
 
 
 def make_box(lo, hi, periodic) -> Box:
@@ -241,6 +246,9 @@ class SphState:
                 src = arrs[k]
             self.t[k] = torch.as_tensor(np.ascontiguousarray(src, dtype=np.float64)).to(**f64)
         self.t["id"] = torch.as_tensor(np.ascontiguousarray(ic.id, dtype=np.int32)).to(dev)
+        if getattr(ic.params, "volume", SPH_VOLUME_STANDARD) == SPH_VOLUME_GENERALISED:
+            # weights of generalised volume elements, permuted with the state
+            self.t["xw"] = torch.as_tensor(np.ascontiguousarray(ic.m, dtype=np.float64)).to(**f64)
         if g is not None:
             for k, a in zip(("gx", "gy", "gz"), g):
                 self.t[k] = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(**f64)
@@ -259,7 +267,7 @@ class SphState:
         t = self.t
         self.particles = Particles(self.n, *[_ptr(t.get(k)) for k in (
             "x", "y", "z", "vx", "vy", "vz", "u", "h", "m", "rho_ref", "p_bg",
-            "gx", "gy", "gz", "id")])
+            "gx", "gy", "gz", "id", "xw")])
         self.nbrs = Nbrs(self.max_nb, _ptr(t["count"]), _ptr(t["idx"]))
         self.fields = Fields(*[_ptr(t[k]) for k in ("rho", "p", "c", "pr2")])
         self.accel = Accel(*[_ptr(t[k]) for k in ("ax", "ay", "az", "dudt", "mumax")])
@@ -323,6 +331,17 @@ def sph_gravity_direct(ctx: Context, st: SphState, eps: float = 0.01):
     ctx.raise_on(ctx.lib.sph_gravity_direct(ctx.h, C.byref(st.particles), float(eps),
                                             _ptr(st.t["gx"]), _ptr(st.t["gy"]),
                                             _ptr(st.t["gz"])))
+
+
+def sph_volume_weights(ctx: Context, st: SphState, exponent: float, rho=None):
+    """st.t["xw"] = (m / rho)^exponent, rho defaulting to the state's density."""
+    import torch
+    if "xw" not in st.t:
+        st.t["xw"] = torch.zeros(max(st.n, 1), dtype=torch.float64, device=st.device)
+        st._refresh()
+    r = st.t["rho"] if rho is None else rho
+    ctx.raise_on(ctx.lib.sph_volume_weights(ctx.h, C.byref(st.particles), _ptr(r),
+                                            float(exponent)))
 
 
 def sph_eos(ctx: Context, st: SphState, prm: Params):

@@ -24,7 +24,7 @@ def oracle_forces(ic, rho_ref=None, g=None):
 
 
 def gpu_forces(ic, rho_ref, precision=S.SPH_FP64, max_nb=128, rho_in=None, g=None,
-               export=True, ctx=None):
+               export=True, ctx=None, xw=None):
     """HIP per-call results on the same IC and rho_ref, mapped to original ids.
 
     Each call is checked on identical inputs: if rho_in (original order) is
@@ -32,11 +32,16 @@ def gpu_forces(ic, rho_ref, precision=S.SPH_FP64, max_nb=128, rho_in=None, g=Non
     momentum kernel see the oracle's density exactly (the stiff Tait EOS
     would otherwise amplify a last-bit density difference ~2500 times near
     the free surface). out["rho"] is always the GPU's own sph_density.
+    xw (original order): the weights of generalised volume elements, given to
+    both pair calls.
     """
     import torch
     if ctx is None:
         ctx = S.Context(max(ic.n, 1), max_nb)
     st = S.SphState(ic, max_nb, rho_ref=rho_ref, g=g)
+    if xw is not None:
+        st.t["xw"] = torch.as_tensor(np.ascontiguousarray(xw, dtype=np.float64)).to(st.device)
+        st._refresh()
     prm = S.make_params(ic.params, precision)
     S.sph_build_cells(ctx, st)
     S.sph_find_neighbors(ctx, st)

@@ -52,7 +52,7 @@ def test_status_strings_and_null_checks():
     assert b"max_nb" in L.sph_last_error(None)
     for fn in ("sph_ctx_check", "sph_build_cells", "sph_find_neighbors", "sph_density",
                "sph_eos", "sph_momentum_energy", "sph_integrate", "sph_timestep",
-               "sph_gravity_direct"):
+               "sph_gravity_direct", "sph_volume_weights"):
         f = getattr(L, fn)
         nargs = len(f.argtypes)
         args = [None] * nargs
@@ -62,6 +62,8 @@ def test_status_strings_and_null_checks():
             args[3] = 0
         if fn == "sph_gravity_direct":
             args[2] = 0.01
+        if fn == "sph_volume_weights":
+            args[3] = 0.7
         assert f(*args) == S.SPH_E_INVALID, fn
 
 
@@ -91,8 +93,8 @@ def test_ensemble_host_checks():
 
 
 def test_ensemble_structs_match_header():
-    """ctypes mirrors of the ensemble structs and of sph_params have the C
-    sizes and offsets."""
+    """ctypes mirrors of the ensemble structs, sph_params and sph_particles
+    have the C sizes and offsets."""
     import subprocess
     import tempfile
     src = r'''
@@ -100,11 +102,13 @@ def test_ensemble_structs_match_header():
 #include <stdio.h>
 #include "sph.h"
 int main(void) {
-    printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(sph_ens_config),
-           sizeof(sph_run_request), sizeof(sph_run_result), sizeof(sph_ens_counters),
-           offsetof(sph_run_request, rho_ref), offsetof(sph_run_result, status),
-           offsetof(sph_ens_counters, busy_seconds), sizeof(sph_params),
-           offsetof(sph_params, kernel), offsetof(sph_params, sinc_n));
+    printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n",
+           sizeof(sph_ens_config), sizeof(sph_run_request), sizeof(sph_run_result),
+           sizeof(sph_ens_counters), offsetof(sph_run_request, rho_ref),
+           offsetof(sph_run_result, status), offsetof(sph_ens_counters, busy_seconds),
+           sizeof(sph_params), offsetof(sph_params, kernel), offsetof(sph_params, sinc_n),
+           offsetof(sph_params, volume), offsetof(sph_params, volume_p),
+           sizeof(sph_particles), offsetof(sph_particles, xw));
     return 0;
 }
 '''
@@ -117,7 +121,8 @@ int main(void) {
     want = [C.sizeof(S.EnsConfig), C.sizeof(S.RunRequest), C.sizeof(S.RunResult),
             C.sizeof(S.EnsCounters), S.RunRequest.rho_ref.offset, S.RunResult.status.offset,
             S.EnsCounters.busy_seconds.offset, C.sizeof(S.Params), S.Params.kernel.offset,
-            S.Params.sinc_n.offset]
+            S.Params.sinc_n.offset, S.Params.volume.offset, S.Params.volume_p.offset,
+            C.sizeof(S.Particles), S.Particles.xw.offset]
     assert got == want
 
 

@@ -164,6 +164,11 @@ def test_poll_and_rejections():
         with pytest.raises(S.SphError) as e:
             ens.submit(iad, 1)  # and kernel derivatives only
         assert e.value.status == S.SPH_E_INVALID
+        gve = _ic(10, 5.0, 1)
+        gve.params = dataclasses.replace(gve.params, volume=S.SPH_VOLUME_GENERALISED)
+        with pytest.raises(S.SphError) as e:
+            ens.submit(gve, 1)  # and standard volume elements only
+        assert e.value.status == S.SPH_E_INVALID
         bad = _ic(10, 5.0, 1)
         bad.id = bad.id.copy()
         bad.id[0] = bad.id[1]

@@ -377,3 +377,101 @@ def test_iad_gradients(family, name):
     e32 = field_errors(ref, got32)
     print(name, "IAD fp32-pair", e32, flush=True)
     assert e32["a"] <= FP32_TOL and e32["du"] <= FP32_TOL
+
+
+def _gve_case(name):
+    """Generalised volume elements with X = (m / rho)^0.7: the 20^3 patch and
+    a periodic-z cloud with masses varying by a factor three and h from the
+    oracle's count iteration (resolved, as IAD needs: see _iad_case)."""
+    import dataclasses
+    if name == "square_patch_c0":
+        ic = I.square_patch(20)
+    else:
+        ic = I.random_cloud(4000, seed=17, h_min=0.03, h_max=0.07, velocity=2.0,
+                            periodic=(0, 0, 1))
+        ic.m = ic.m * np.random.default_rng(5).uniform(0.5, 1.5, ic.n)
+        ic.h, _, _ = O.smoothing_length(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi, ic.periodic)
+    ic.params = dataclasses.replace(ic.params, volume=S.SPH_VOLUME_GENERALISED, volume_p=0.7)
+    return ic
+
+
+@pytest.mark.parametrize("name", ["square_patch_c0", "cloud"])
+def test_gve_volume_weights(name):
+    """sph_volume_weights: X = (m / rho)^p against the oracle on the same rho
+    (each side's own pow, so a few ulp)."""
+    import torch
+    ic = _gve_case(name)
+    off, ids = O.neighbors(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi, ic.periodic)
+    rho = O.density(ic.x, ic.y, ic.z, ic.h, ic.m, ic.lo, ic.hi, ic.periodic, off, ids)
+    X = O.volume_weights(ic.m, rho, 0.7)
+    ctx = S.Context(ic.n, 128)
+    st = S.SphState(ic, 128)
+    S.sph_volume_weights(ctx, st, 0.7, rho=torch.as_tensor(rho).to(st.device))
+    S.sph_ctx_check(ctx)
+    got = st.host(["xw"])["xw"]
+    err = float(np.max(np.abs(got / X - 1)))
+    print(name, "volume weights max rel", err, flush=True)
+    assert err <= 1e-15
+
+
+@pytest.mark.parametrize("gradient", [S.SPH_GRAD_KERNEL, S.SPH_GRAD_IAD])
+@pytest.mark.parametrize("name", ["square_patch_c0", "cloud"])
+def test_gve_forces(name, gradient):
+    """Generalised volume elements (SPHYNX, Table 1): density and
+    momentum/energy against the oracle on the same weights, with kernel
+    derivatives and with IAD, FP64 and FP32-pair."""
+    import dataclasses
+    ic = _gve_case(name)
+    ic.params = dataclasses.replace(ic.params, gradient=gradient)
+    print(f"case {name} GVE gradient {gradient}", flush=True)
+    lo, hi, per = ic.lo, ic.hi, ic.periodic
+    off, ids = O.neighbors(ic.x, ic.y, ic.z, ic.h, lo, hi, per)
+    max_nb = int(np.diff(off).max()) + 8
+    rho0 = O.density(ic.x, ic.y, ic.z, ic.h, ic.m, lo, hi, per, off, ids)
+    X = O.volume_weights(ic.m, rho0, 0.7)
+    rho = O.density(ic.x, ic.y, ic.z, ic.h, ic.m, lo, hi, per, off, ids, X=X)
+    p, c, pr2 = O.eos(ic.params, rho, ic.u, rho, ic.p_bg)
+    O.set_gradient(gradient)
+    try:
+        acc = O.momentum_energy(ic.x, ic.y, ic.z, ic.vx, ic.vy, ic.vz, ic.h, ic.m, rho, c,
+                                pr2, lo, hi, per, off, ids, ic.params, scales=True, X=X)
+    finally:
+        O.set_gradient(O.GRADIENT_KERNEL)
+    dt = O.timestep(ic.h, c, acc["mumax"], acc["ax"], acc["ay"], acc["az"], ic.params)
+    ref = dict(off=off, ids=ids, rho=rho, dt=dt, **acc)
+    got, _, ctx = gpu_forces(ic, rho, S.SPH_FP64, max_nb=max_nb, rho_in=rho, xw=X)
+    assert np.array_equal(got["off"], off) and np.array_equal(got["ids"], ids)
+    e = field_errors(ref, got)
+    print(name, "GVE fp64", e, flush=True)
+    assert e["rho"] <= FP64_TOL and e["a"] <= FP64_TOL and e["du"] <= FP64_TOL
+    assert e["dt"] <= 1e-13
+    got32, _, _ = gpu_forces(ic, rho, S.SPH_FP32_PAIR, max_nb=max_nb, rho_in=rho, xw=X,
+                             export=False, ctx=ctx)
+    e32 = field_errors(ref, got32)
+    print(name, "GVE fp32-pair", e32, flush=True)
+    assert e32["rho"] <= FP32_TOL and e32["a"] <= FP32_TOL and e32["du"] <= FP32_TOL
+
+
+def test_gve_trajectory_square_patch_c0():
+    """Generalised volume elements through sph_init_forces and sph_step (the
+    weights taken from the previous density before each step, from a standard
+    density at t = 0) against the oracle run doing the same: 5 steps."""
+    ic = _gve_case("square_patch_c0")
+    ref = O.OracleRun(ic).init()
+    ctx = S.Context(ic.n, 128)
+    st = S.SphState(ic, 128)
+    prm = S.make_params(ic.params)
+    S.sph_init_forces(ctx, st, prm, set_rho_ref=True)
+    for _ in range(5):
+        S.sph_step(ctx, st, prm)
+        ref.step()
+    S.sph_ctx_check(ctx)
+    got = st.host(["x", "y", "z", "vx", "vy", "vz", "rho", "xw"])
+    err = {k: float(np.max(np.abs(got[k] - ref.s[k]))) for k in ("x", "y", "z", "vx", "vy", "vz")}
+    err["rho"] = float(np.max(np.abs(got["rho"] / ref.rho - 1)))
+    err["xw"] = float(np.max(np.abs(got["xw"] / ref.X - 1)))
+    print("GVE trajectory max errors after 5 steps", err, flush=True)
+    assert max(err[k] for k in ("x", "y", "z")) < 1e-12
+    assert max(err[k] for k in ("vx", "vy", "vz")) < 1e-10
+    assert err["rho"] < 1e-11 and err["xw"] < 1e-11
+    assert abs(st.dt - ref.dt) / ref.dt < 1e-10
