@@ -244,6 +244,34 @@ sph_status sph_momentum_energy(sph_ctx ctx, const sph_particles *p,
                                const sph_params *prm, const sph_fields *f,
                                const sph_accel *a);
 
+/* Algorithm 1, step 4 (self-gravity; Sec. 5.2.5 phase I) by a Morton
+ * octree with multipoles to quadrupole order, the parent codes' method
+ * (SPHYNX uses quadrupoles), G = 1, in FP64:
+ *   - cube lo_a = min x_a, L = largest extent; keys are 30-bit Morton codes of
+ *     floor((x - lo) / L * 1024) (clamped to 1023); particles are sorted by
+ *     (key, id);
+ *   - a node of level l < 10 with more than leaf_size particles is split
+ *     into its non-empty octants; every node carries its mass M, centre of
+ *     mass c and traceless quadrupole Q = sum m (3 d d^T - |d|^2 I);
+ *   - the sorted particles form groups of 64; a node N is accepted for a
+ *     whole group when the distance from c_N to the group's bounding box
+ *     exceeds s_N / theta + |c_N - centre_N| (s_N the node's side), and then
+ *     contributes -M d/r^3 + Q d/r^5 - 5/2 (d.Q d) d/r^7 (d = x_i - c_N,
+ *     unsoftened); otherwise a leaf contributes its particles directly with
+ *     Plummer softening eps, -m_j d/(|d|^2 + eps^2)^{3/2}, and an internal
+ *     node is opened. theta -> 0 gives the direct sum of sph_gravity_direct.
+ * Reads p->x, y, z, m, id (device, n, current order; id must be a
+ * permutation of 0..n-1) and writes gx, gy, gz (device, n doubles each,
+ * caller-owned, same order). The first call on a context allocates the
+ * tree's buffers (about 100 bytes per particle of n_max plus up to 512 MiB
+ * of traversal frontiers), kept until sph_ctx_destroy; SPH_E_NOMEM if that
+ * fails. Synchronises ctx's stream. SPH_E_INVALID for NULL arrays, eps < 0,
+ * theta <= 0 or a non-finite value, leaf_size outside [8, 64];
+ * SPH_E_CAPACITY if the tree needs more than n_max / 2 + 1024 nodes or a
+ * group's breadth-first frontier more than its scratch (outputs undefined). */
+sph_status sph_gravity_tree(sph_ctx ctx, const sph_particles *p, double eps, double theta,
+                            int32_t leaf_size, double *gx, double *gy, double *gz);
+
 /* Weights of generalised volume elements (Table 1, SPHYNX) from a density
  * estimate: p->xw[i] = (p->m[i] / rho[i])^exponent, FP64, in the current
  * particle order (rho: device, n doubles, e.g. the previous step's density).

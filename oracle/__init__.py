@@ -99,6 +99,12 @@ def lib():
             L.orc_gravity_direct_subset.restype = None
             L.orc_gravity_direct_subset.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_double,
                                                     C.c_int64, _I64, _D, _D, _D, _D]
+            L.orc_gravity_tree.restype = C.c_int64
+            L.orc_gravity_tree.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_double, C.c_double,
+                                           C.c_int32, _D, _D, _D, _DN, C.c_void_p]
+            L.orc_gravity_tree_nodes.restype = C.c_int64
+            L.orc_gravity_tree_nodes.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_int32,
+                                                 C.c_int64, _D, _I64]
             L.orc_num_threads.restype = C.c_int32
             L.orc_num_threads.argtypes = []
             L.orc_set_num_threads.restype = None
@@ -316,6 +322,33 @@ def gravity_direct_subset(x, y, z, m, sel, eps=0.01):
     lib().orc_gravity_direct_subset(n, _d(x), _d(y), _d(z), _d(m), float(eps), k, sel,
                                     gx, gy, gz, sg)
     return gx, gy, gz, sg
+
+
+def gravity_tree(x, y, z, m, eps=0.01, theta=0.5, leaf_size=32):
+    """Octree multipole (quadrupole) self-gravity of sph_oracle.c: returns
+    gx, gy, gz, the per-particle sum of term magnitudes, and the statistics
+    dict (nodes, leaves, node_terms, direct_terms, max_frontier)."""
+    n = len(x)
+    gx, gy, gz, sc = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    st = np.zeros(5, dtype=np.int64)
+    lib().orc_gravity_tree(n, _d(x), _d(y), _d(z), _d(m), float(eps), float(theta),
+                           int(leaf_size), gx, gy, gz, sc.ctypes.data, st.ctypes.data)
+    stats = dict(zip(("nodes", "leaves", "node_terms", "direct_terms", "max_frontier"),
+                     map(int, st)))
+    return gx, gy, gz, sc, stats
+
+
+def gravity_tree_nodes(x, y, z, m, leaf_size=32):
+    """The oracle's octree: (nodes [k, 16] = M, c, Q, s, delta, level, start,
+    end, nchild; order[k] = particle at sorted position k)."""
+    n = len(x)
+    cap = max(16, 4 * n)
+    out = np.zeros(16 * cap)
+    order = np.zeros(n, dtype=np.int64)
+    nn = lib().orc_gravity_tree_nodes(n, _d(x), _d(y), _d(z), _d(m), int(leaf_size), cap,
+                                      out, order)
+    assert nn <= cap
+    return out[: 16 * nn].reshape(nn, 16), order
 
 
 class OracleRun:

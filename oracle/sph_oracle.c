@@ -947,3 +947,352 @@ void orc_set_num_threads(int32_t t)
     (void)t;
 #endif
 }
+
+/* ------------------------------------------------- tree self-gravity */
+
+/*
+ * Self-gravity by a Morton octree with multipoles to quadrupole order (the
+ * parent codes' approach, Alg. 1 step 4, Sec. 5.2.5 phase I; SPHYNX keeps
+ * quadrupoles). G = 1. The tree, the moments and the acceptance test are
+ * fixed here so that they are reproducible:
+ *
+ *   cube   lo_a = min_i x_a, L = max_a (max_i x_a - lo_a) (1 if zero);
+ *   keys   k_a = min(1023, floor((x_a - lo_a) / L * 1024)), interleaved as
+ *          Morton code k_x | k_y << 1 | k_z << 2 per bit (30 bits);
+ *   order  particles sorted by (key, index);
+ *   nodes  the root holds all particles; a node of level l < 10 with more
+ *          than leaf_size particles gets one child per non-empty octant
+ *          (next three key bits), in octant order; the others are leaves.
+ *          Node side s = L / 2^l, geometric centre lo + (k + 1/2) s;
+ *   moments M = sum m, centre of mass c, traceless quadrupole
+ *          Q_ab = sum m (3 d_a d_b - |d|^2 delta_ab), d = x - c; a leaf sums
+ *          its particles in sorted order, an internal node its children in
+ *          octant order with the parallel-axis shift
+ *          Q += Q_k + M_k (3 e_a e_b - |e|^2 delta_ab), e = c_k - c;
+ *   groups consecutive runs of 64 particles in the sorted order (the last
+ *          one shorter). A node N is accepted for every particle of a group
+ *          G when dist(c_N, box_G) > s_N / theta + |c_N - centre_N|, box_G
+ *          the bounding box of G's particles; otherwise a leaf N is summed
+ *          directly and an internal N is opened (its children are visited
+ *          next). Visiting is breadth-first from the root, children in
+ *          octant order;
+ *   terms  direct: -m_j d / (|d|^2 + eps^2)^{3/2}, d = x_i - x_j, j != i;
+ *          node: -M d / r^3 + Q d / r^5 - 5/2 (d.Q d) d / r^7, d = x_i - c
+ *          (unsoftened), the gradient of the expansion of the potential
+ *          -M/r - d.Q d / (2 r^5).
+ * scale (optional): per particle, the sum of the magnitudes of the terms.
+ * stats (optional): [nodes, leaves, node terms, direct terms, largest frontier].
+ */
+#define ORC_GROUP 64
+typedef struct {
+    int64_t start, end, child0;
+    int32_t level, nchild;
+    uint32_t prefix;
+    double M, c[3], Q[6], blo[3], bhi[3], s, delta;
+} orc_gnode;
+
+static uint32_t spread10(uint32_t v)
+{
+    uint32_t r = 0;
+    for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1u) << (3 * b);
+    return r;
+}
+
+typedef struct { uint32_t key; int64_t idx; } orc_kidx;
+
+static int kidx_cmp(const void *a, const void *b)
+{
+    const orc_kidx *p = (const orc_kidx *)a, *q = (const orc_kidx *)b;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    return p->idx < q->idx ? -1 : (p->idx > q->idx);
+}
+
+/* first position in [lo, hi) of the sorted keys with key >= k */
+static int64_t lower_key(const orc_kidx *s, int64_t lo, int64_t hi, uint32_t k)
+{
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (s[mid].key < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/* The tree of the definition above: sorted particles, nodes (breadth-first,
+ * children contiguous) with their moments. The caller frees both. */
+static orc_gnode *gtree_build(int64_t n, const double **P, const double *m,
+                              int32_t leaf_size, orc_kidx **srt_out, int64_t *nn_out)
+{
+    double lo[3], L = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double mn = P[a][0], mx = P[a][0];
+        for (int64_t i = 1; i < n; ++i) {
+            if (P[a][i] < mn) mn = P[a][i];
+            if (P[a][i] > mx) mx = P[a][i];
+        }
+        lo[a] = mn;
+        if (mx - mn > L) L = mx - mn;
+    }
+    if (!(L > 0.0)) L = 1.0;
+    orc_kidx *srt = (orc_kidx *)malloc(sizeof(orc_kidx) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t k[3];
+        for (int a = 0; a < 3; ++a) {
+            double q = floor((P[a][i] - lo[a]) / L * 1024.0);
+            k[a] = q >= 1023.0 ? 1023u : (uint32_t)q;
+        }
+        srt[i].key = spread10(k[0]) | (spread10(k[1]) << 1) | (spread10(k[2]) << 2);
+        srt[i].idx = i;
+    }
+    qsort(srt, (size_t)n, sizeof(orc_kidx), kidx_cmp);
+
+    /* nodes, breadth-first */
+    int64_t cap = 1024, nn = 1;
+    orc_gnode *T = (orc_gnode *)calloc((size_t)cap, sizeof(orc_gnode));
+    T[0].start = 0; T[0].end = n; T[0].level = 0; T[0].prefix = 0;
+    for (int64_t t = 0; t < nn; ++t) {
+        T[t].child0 = -1; T[t].nchild = 0;
+        if (T[t].level >= 10 || T[t].end - T[t].start <= leaf_size) continue;
+        int shift = 3 * (9 - T[t].level);
+        int64_t first = nn;
+        for (uint32_t o = 0; o < 8; ++o) {
+            uint32_t pre = (T[t].prefix << 3) | o;
+            int64_t a = lower_key(srt, T[t].start, T[t].end, pre << shift);
+            int64_t b = lower_key(srt, T[t].start, T[t].end, (pre + 1) << shift);
+            if (a == b) continue;
+            if (nn == cap) {
+                cap *= 2;
+                T = (orc_gnode *)realloc(T, sizeof(orc_gnode) * (size_t)cap);
+            }
+            memset(&T[nn], 0, sizeof(orc_gnode));
+            T[nn].start = a; T[nn].end = b; T[nn].level = T[t].level + 1; T[nn].prefix = pre;
+            ++nn;
+        }
+        T[t].child0 = first;
+        T[t].nchild = (int32_t)(nn - first);
+    }
+
+    /* moments, children before parents */
+    for (int64_t t = nn - 1; t >= 0; --t) {
+        orc_gnode *N = &T[t];
+        double M = 0.0, sc[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < 6; ++q) N->Q[q] = 0.0;
+        if (N->nchild == 0) {
+            for (int a = 0; a < 3; ++a) { N->blo[a] = INFINITY; N->bhi[a] = -INFINITY; }
+            for (int64_t k = N->start; k < N->end; ++k) {
+                int64_t j = srt[k].idx;
+                M += m[j];
+                for (int a = 0; a < 3; ++a) {
+                    sc[a] += m[j] * P[a][j];
+                    if (P[a][j] < N->blo[a]) N->blo[a] = P[a][j];
+                    if (P[a][j] > N->bhi[a]) N->bhi[a] = P[a][j];
+                }
+            }
+            for (int a = 0; a < 3; ++a) N->c[a] = sc[a] / M;
+            for (int64_t k = N->start; k < N->end; ++k) {
+                int64_t j = srt[k].idx;
+                double d[3] = {P[0][j] - N->c[0], P[1][j] - N->c[1], P[2][j] - N->c[2]};
+                double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                N->Q[0] += m[j] * (3.0 * d[0] * d[0] - d2);
+                N->Q[1] += m[j] * (3.0 * d[0] * d[1]);
+                N->Q[2] += m[j] * (3.0 * d[0] * d[2]);
+                N->Q[3] += m[j] * (3.0 * d[1] * d[1] - d2);
+                N->Q[4] += m[j] * (3.0 * d[1] * d[2]);
+                N->Q[5] += m[j] * (3.0 * d[2] * d[2] - d2);
+            }
+        } else {
+            for (int a = 0; a < 3; ++a) { N->blo[a] = INFINITY; N->bhi[a] = -INFINITY; }
+            for (int64_t k = N->child0; k < N->child0 + N->nchild; ++k) {
+                M += T[k].M;
+                for (int a = 0; a < 3; ++a) {
+                    sc[a] += T[k].M * T[k].c[a];
+                    if (T[k].blo[a] < N->blo[a]) N->blo[a] = T[k].blo[a];
+                    if (T[k].bhi[a] > N->bhi[a]) N->bhi[a] = T[k].bhi[a];
+                }
+            }
+            for (int a = 0; a < 3; ++a) N->c[a] = sc[a] / M;
+            for (int64_t k = N->child0; k < N->child0 + N->nchild; ++k) {
+                double e[3] = {T[k].c[0] - N->c[0], T[k].c[1] - N->c[1], T[k].c[2] - N->c[2]};
+                double e2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+                double Mk = T[k].M;
+                N->Q[0] += T[k].Q[0] + Mk * (3.0 * e[0] * e[0] - e2);
+                N->Q[1] += T[k].Q[1] + Mk * (3.0 * e[0] * e[1]);
+                N->Q[2] += T[k].Q[2] + Mk * (3.0 * e[0] * e[2]);
+                N->Q[3] += T[k].Q[3] + Mk * (3.0 * e[1] * e[1] - e2);
+                N->Q[4] += T[k].Q[4] + Mk * (3.0 * e[1] * e[2]);
+                N->Q[5] += T[k].Q[5] + Mk * (3.0 * e[2] * e[2] - e2);
+            }
+        }
+        N->M = M;
+        N->s = L / (double)(1u << N->level);
+        uint32_t kk[3] = {0, 0, 0};
+        for (int b = 0; b < N->level; ++b)
+            for (int a = 0; a < 3; ++a)
+                kk[a] |= ((N->prefix >> (3 * b + a)) & 1u) << b;
+        double dd = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double centre = lo[a] + ((double)kk[a] + 0.5) * N->s;
+            double e = N->c[a] - centre;
+            dd += e * e;
+        }
+        N->delta = sqrt(dd);
+    }
+    *srt_out = srt;
+    *nn_out = nn;
+    return T;
+}
+
+int64_t orc_gravity_tree(int64_t n, const double *x, const double *y, const double *z,
+                         const double *m, double eps, double theta, int32_t leaf_size,
+                         double *gx, double *gy, double *gz, double *scale, int64_t *stats)
+{
+    if (n <= 0) return 0;
+    const double *P[3] = {x, y, z};
+    orc_kidx *srt;
+    int64_t nn;
+    orc_gnode *T = gtree_build(n, P, m, leaf_size, &srt, &nn);
+
+    /* groups of 64 sorted particles, each walked breadth-first from the root */
+    int64_t n_leaf = 0, n_node_terms = 0, n_direct_terms = 0, max_front = 1;
+    for (int64_t t = 0; t < nn; ++t) n_leaf += T[t].nchild == 0;
+    const int64_t n_group = (n + ORC_GROUP - 1) / ORC_GROUP;
+    const double e2 = eps * eps;
+    #pragma omp parallel for schedule(dynamic, 16) reduction(+ : n_node_terms, n_direct_terms) reduction(max : max_front)
+    for (int64_t q = 0; q < n_group; ++q) {
+        orc_gnode Gs;
+        orc_gnode *G = &Gs;
+        G->start = q * ORC_GROUP;
+        G->end = G->start + ORC_GROUP < n ? G->start + ORC_GROUP : n;
+        for (int a = 0; a < 3; ++a) { G->blo[a] = INFINITY; G->bhi[a] = -INFINITY; }
+        for (int64_t k = G->start; k < G->end; ++k)
+            for (int a = 0; a < 3; ++a) {
+                double v = P[a][srt[k].idx];
+                if (v < G->blo[a]) G->blo[a] = v;
+                if (v > G->bhi[a]) G->bhi[a] = v;
+            }
+        int64_t fcap = 64, fn = 1, ncap = 64, nx;
+        int64_t *front = (int64_t *)malloc(sizeof(int64_t) * (size_t)fcap);
+        int64_t *next = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncap);
+        front[0] = 0;
+        int64_t gn = G->end - G->start;
+        double *ax = (double *)calloc((size_t)gn * 4, sizeof(double));
+        while (fn > 0) {
+            nx = 0;
+            for (int64_t f = 0; f < fn; ++f) {
+                const orc_gnode *N = &T[front[f]];
+                double dd = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    double e = 0.0;
+                    if (N->c[a] < G->blo[a]) e = G->blo[a] - N->c[a];
+                    else if (N->c[a] > G->bhi[a]) e = N->c[a] - G->bhi[a];
+                    dd += e * e;
+                }
+                if (sqrt(dd) > N->s / theta + N->delta) {
+                    for (int64_t k = 0; k < gn; ++k) {
+                        int64_t i = srt[G->start + k].idx;
+                        double d[3] = {x[i] - N->c[0], y[i] - N->c[1], z[i] - N->c[2]};
+                        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                        double rinv = 1.0 / sqrt(r2);
+                        double rinv2 = rinv * rinv;
+                        double rinv3 = rinv * rinv2;
+                        double rinv5 = rinv3 * rinv2;
+                        double rinv7 = rinv5 * rinv2;
+                        double Qd[3] = {N->Q[0] * d[0] + N->Q[1] * d[1] + N->Q[2] * d[2],
+                                        N->Q[1] * d[0] + N->Q[3] * d[1] + N->Q[4] * d[2],
+                                        N->Q[2] * d[0] + N->Q[4] * d[1] + N->Q[5] * d[2]};
+                        double dQd = d[0] * Qd[0] + d[1] * Qd[1] + d[2] * Qd[2];
+                        double t[3];
+                        for (int a = 0; a < 3; ++a) {
+                            t[a] = -N->M * d[a] * rinv3 + Qd[a] * rinv5 - 2.5 * dQd * d[a] * rinv7;
+                            ax[4 * k + a] += t[a];
+                        }
+                        ax[4 * k + 3] += sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+                    }
+                    n_node_terms += gn;
+                } else if (N->nchild == 0) {
+                    for (int64_t k = 0; k < gn; ++k) {
+                        int64_t i = srt[G->start + k].idx;
+                        for (int64_t l = N->start; l < N->end; ++l) {
+                            int64_t j = srt[l].idx;
+                            if (j == i) continue;
+                            double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+                            double d2 = dx * dx + dy * dy + dz * dz + e2;
+                            double inv = 1.0 / (d2 * sqrt(d2));
+                            double t0 = -m[j] * dx * inv, t1 = -m[j] * dy * inv,
+                                   t2 = -m[j] * dz * inv;
+                            ax[4 * k + 0] += t0;
+                            ax[4 * k + 1] += t1;
+                            ax[4 * k + 2] += t2;
+                            ax[4 * k + 3] += sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+                        }
+                    }
+                    n_direct_terms += gn * (N->end - N->start);
+                } else {
+                    for (int64_t k = N->child0; k < N->child0 + N->nchild; ++k) {
+                        if (nx == ncap) {
+                            ncap *= 2;
+                            next = (int64_t *)realloc(next, sizeof(int64_t) * (size_t)ncap);
+                        }
+                        next[nx++] = k;
+                    }
+                }
+            }
+            int64_t *tmp = front; front = next; next = tmp;
+            int64_t tc = fcap; fcap = ncap; ncap = tc;
+            fn = nx;
+            if (fn > max_front) max_front = fn;
+        }
+        for (int64_t k = 0; k < gn; ++k) {
+            int64_t i = srt[G->start + k].idx;
+            gx[i] = ax[4 * k + 0];
+            gy[i] = ax[4 * k + 1];
+            gz[i] = ax[4 * k + 2];
+            if (scale) scale[i] = ax[4 * k + 3];
+        }
+        free(ax);
+        free(front);
+        free(next);
+    }
+    if (stats) {
+        stats[0] = nn;
+        stats[1] = n_leaf;
+        stats[2] = n_node_terms;
+        stats[3] = n_direct_terms;
+        stats[4] = max_front;
+    }
+    free(T);
+    free(srt);
+    return nn;
+}
+
+/* The tree itself, for the tests: out[16 t + q] = M, c (3), Q (6), s,
+ * delta, level, start, end, nchild of node t (start and end are positions in
+ * the sorted order, order[k] the particle at position k). Returns the node
+ * count; nothing is written when it exceeds cap. */
+int64_t orc_gravity_tree_nodes(int64_t n, const double *x, const double *y, const double *z,
+                               const double *m, int32_t leaf_size, int64_t cap, double *out,
+                               int64_t *order)
+{
+    if (n <= 0) return 0;
+    const double *P[3] = {x, y, z};
+    orc_kidx *srt;
+    int64_t nn;
+    orc_gnode *T = gtree_build(n, P, m, leaf_size, &srt, &nn);
+    if (nn <= cap) {
+        for (int64_t t = 0; t < nn; ++t) {
+            double *o = out + 16 * t;
+            o[0] = T[t].M;
+            for (int a = 0; a < 3; ++a) o[1 + a] = T[t].c[a];
+            for (int q = 0; q < 6; ++q) o[4 + q] = T[t].Q[q];
+            o[10] = T[t].s;
+            o[11] = T[t].delta;
+            o[12] = T[t].level;
+            o[13] = (double)T[t].start;
+            o[14] = (double)T[t].end;
+            o[15] = T[t].nchild;
+        }
+        for (int64_t k = 0; k < n; ++k) order[k] = srt[k].idx;
+    }
+    free(T);
+    free(srt);
+    return nn;
+}

@@ -215,6 +215,7 @@ sph_status dev_alloc(sph_ctx ctx, T **p, int64_t count)
 
 void free_ctx(sph_ctx ctx)
 {
+    release_gravity_tree(ctx);
     void *ptrs[] = {ctx->keys[0], ctx->keys[1], ctx->vals[0], ctx->vals[1], ctx->hist,
                     ctx->scan_part, ctx->cell_start, ctx->cell_end, ctx->perm_tmp,
                     ctx->perm_tmp_id, ctx->red_part, ctx->status_dev, ctx->nb_mask, ctx->hflag_dev,
@@ -427,6 +428,30 @@ sph_status sph_gravity_direct(sph_ctx ctx, const sph_particles *p, double eps, d
     if (p->n == 0) return SPH_OK;
     if (!gx || !gy || !gz) return fail(ctx, SPH_E_INVALID, "gx, gy and gz are required");
     SPH_HIP(ctx, launch_gravity_direct(ctx, *p, eps, gx, gy, gz));
+    return SPH_OK;
+}
+
+sph_status sph_gravity_tree(sph_ctx ctx, const sph_particles *p, double eps, double theta,
+                            int32_t leaf_size, double *gx, double *gy, double *gz)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, false)) != SPH_OK) return s;
+    if (!(eps >= 0.0) || !std::isfinite(eps))
+        return fail(ctx, SPH_E_INVALID, "eps must be finite and >= 0");
+    if (!(theta > 0.0) || !std::isfinite(theta))
+        return fail(ctx, SPH_E_INVALID, "theta must be finite and > 0");
+    if (leaf_size < 8 || leaf_size > 64)
+        return fail(ctx, SPH_E_INVALID, "leaf_size %d outside [8, 64]", leaf_size);
+    if (p->n == 0) return SPH_OK;
+    if (!gx || !gy || !gz) return fail(ctx, SPH_E_INVALID, "gx, gy and gz are required");
+    uint32_t flags = 0;
+    const hipError_t e = launch_gravity_tree(ctx, *p, eps, theta, leaf_size, gx, gy, gz, &flags);
+    if (e == hipErrorOutOfMemory || (e != hipSuccess && ctx->gt_n_cap == 0))
+        return fail(ctx, SPH_E_NOMEM, "octree buffers: %s", hipGetErrorString(e));
+    SPH_HIP(ctx, e);
+    if (flags & 1u) return fail(ctx, SPH_E_CAPACITY, "octree node capacity exceeded");
+    if (flags & 2u) return fail(ctx, SPH_E_CAPACITY, "octree frontier capacity exceeded");
     return SPH_OK;
 }
 

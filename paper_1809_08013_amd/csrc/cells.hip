@@ -429,6 +429,25 @@ hipError_t exclusive_scan(sph_ctx ctx, uint32_t *a, int64_t len)
 
 }  // namespace
 
+hipError_t radix_sort_pairs(sph_ctx ctx, uint32_t *k[2], int32_t *v[2], int64_t n,
+                            int key_bits, int *cur)
+{
+    hipStream_t s = ctx->stream;
+    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    hipError_t e;
+    for (int shift = 0; shift < key_bits; shift += kRadixBits) {
+        radix_hist_kernel<<<(unsigned)ntiles, kSortThreads, 0, s>>>(k[*cur], n, nullptr, shift,
+                                                                     ctx->hist, ntiles);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = exclusive_scan(ctx, ctx->hist, ntiles * kRadixBins)) != hipSuccess) return e;
+        radix_scatter_kernel<<<(unsigned)ntiles, kSortThreads, 0, s>>>(
+            k[*cur], v[*cur], n, nullptr, shift, ctx->hist, ntiles, k[*cur ^ 1], v[*cur ^ 1]);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        *cur ^= 1;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g,
                               double h_max)
 {

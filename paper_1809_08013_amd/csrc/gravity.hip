@@ -9,6 +9,34 @@
 // exact zero when eps > 0 (dx = dy = dz = 0) and is dropped by the d2 > 0
 // test when eps = 0. O(n^2) work: the reference the parent codes' tree
 // multipoles approximate, not a fast solver.
+//
+// The same sum approximated by a Morton octree with multipoles to quadrupole
+// order (the parent codes' method; SPHYNX keeps quadrupoles), G = 1:
+//   cube   lo_a = min_i x_a, L = max_a (max_i x_a - lo_a) (1 if zero);
+//   keys   k_a = min(1023, floor((x_a - lo_a) / L * 1024)), 30-bit Morton
+//          code; particles sorted by (key, id) (a stable radix sort of the
+//          particles arranged by id);
+//   nodes  the root holds all particles; a node of level l < 10 with more
+//          than leaf_size particles gets one child per non-empty octant, in
+//          octant order; side s = L / 2^l, centre lo + (k + 1/2) s;
+//   moments M, centre of mass c and traceless quadrupole
+//          Q_ab = sum m (3 d_a d_b - |d|^2 delta_ab), d = x - c; leaves sum
+//          their particles in sorted order, internal nodes their children in
+//          octant order with the parallel-axis shift;
+//   groups runs of 64 sorted particles, one wave each. A node N is accepted
+//          for the whole group G when dist(c_N, box_G) > s_N / theta +
+//          |c_N - centre_N|; otherwise a leaf is summed directly and an
+//          internal node opened; breadth-first from the root, children in
+//          octant order, every accepted node and opened leaf evaluated in
+//          that order;
+//   terms  direct -m_j d / (|d|^2 + eps^2)^{3/2} (j != i); node
+//          -M d / r^3 + Q d / r^5 - 5/2 (d.Q d) d / r^7, d = x_i - c.
+// Tree build, moments and terms use plain FP64 operations in the order of
+// their definition (no fused multiply-add; correctly rounded division and
+// square root).
+#include <algorithm>
+#include <cmath>
+
 #include "sph_internal.h"
 
 namespace sph {
@@ -84,6 +112,388 @@ gravity_direct_kernel(int64_t n, const DensRec *__restrict__ rec, double e2,
     }
 }
 
+
+// ------------------------------------------------------------ octree gravity
+
+constexpr int kGLevels = 10;       // key bits per axis
+constexpr int kGBoxBlocks = 1024;  // bounding-box partial blocks (at most)
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// per block: min x, y, z then max x, y, z (exact, so any order gives the same)
+__global__ void __launch_bounds__(256)
+gbox_partial_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                    const double *__restrict__ z, double *__restrict__ part)
+{
+    __shared__ double red[6][256];
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        v[0] = fmin(v[0], x[i]);
+        v[1] = fmin(v[1], y[i]);
+        v[2] = fmin(v[2], z[i]);
+        v[3] = fmax(v[3], x[i]);
+        v[4] = fmax(v[4], y[i]);
+        v[5] = fmax(v[5], z[i]);
+    }
+    for (int a = 0; a < 6; ++a) red[a][threadIdx.x] = v[a];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int a = 0; a < 6; ++a)
+                red[a][threadIdx.x] = a < 3 ? fmin(red[a][threadIdx.x], red[a][threadIdx.x + w])
+                                            : fmax(red[a][threadIdx.x], red[a][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 6; ++a) part[6 * blockIdx.x + a] = red[a][0];
+}
+
+// box = {lo_x, lo_y, lo_z, L}
+__global__ void __launch_bounds__(64)
+gbox_final_kernel(int nblk, const double *__restrict__ part, double *__restrict__ box)
+{
+    if (threadIdx.x != 0) return;
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < nblk; ++b)
+        for (int a = 0; a < 6; ++a)
+            v[a] = a < 3 ? fmin(v[a], part[6 * b + a]) : fmax(v[a], part[6 * b + a]);
+    double L = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        box[a] = v[a];
+        if (v[3 + a] - v[a] > L) L = v[3 + a] - v[a];
+    }
+    if (!(L > 0.0)) L = 1.0;
+    box[3] = L;
+}
+
+// Keys, arranged by particle id: slot id[i] holds (key_i, i). Every slot is
+// first given its own particle, so that all values stay in [0, n) whatever
+// id holds.
+__global__ void __launch_bounds__(256)
+gkeys_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+             const double *__restrict__ z, const int32_t *__restrict__ id,
+             const double *__restrict__ box, int by_id, uint32_t *__restrict__ keys,
+             int32_t *__restrict__ vals)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double L = box[3];
+    const double P[3] = {x[i], y[i], z[i]};
+    uint32_t k[3];
+    for (int a = 0; a < 3; ++a) {
+        const double q = floor((P[a] - box[a]) / L * 1024.0);
+        k[a] = q >= 1023.0 ? 1023u : (uint32_t)q;
+    }
+    const uint32_t key = spread10(k[0]) | (spread10(k[1]) << 1) | (spread10(k[2]) << 2);
+    int64_t slot = i;
+    if (by_id) {
+        const int32_t d = id[i];
+        if (d < 0 || d >= n) return;
+        slot = d;
+    }
+    keys[slot] = key;
+    vals[slot] = (int32_t)i;
+}
+
+__global__ void __launch_bounds__(256)
+ggather_kernel(int64_t n, const int32_t *__restrict__ order, const double *__restrict__ x,
+               const double *__restrict__ y, const double *__restrict__ z,
+               const double *__restrict__ m, DensRec *__restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int32_t i = order[k];
+    out[k] = DensRec{x[i], y[i], z[i], m[i]};
+}
+
+// lvl[0..11]: first node of each level, lvl[12..23]: node count of each level
+__global__ void __launch_bounds__(64)
+gtree_init_kernel(int64_t n, GNode *__restrict__ nodes, int32_t *__restrict__ lvl,
+                  uint32_t *__restrict__ flags)
+{
+    const int t = threadIdx.x;
+    if (t < 24) lvl[t] = t == 12 ? 1 : 0;
+    if (t == 0) {
+        GNode r{};
+        r.start = 0;
+        r.end = (int32_t)n;
+        r.child0 = -1;
+        r.nchild = 0;
+        r.prefix = 0;
+        r.level = 0;
+        nodes[0] = r;
+        flags[0] = 0;
+    }
+}
+
+__device__ __forceinline__ int32_t lower_key(const uint32_t *__restrict__ keys, int32_t lo,
+                                             int32_t hi, uint32_t k)
+{
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Split the nodes of level l: children get a contiguous block of the next
+// level (one atomic per parent; ids vary from run to run, the tree does not).
+__global__ void __launch_bounds__(256)
+gtree_split_kernel(int l, const uint32_t *__restrict__ keys, GNode *__restrict__ nodes,
+                   int32_t *__restrict__ lvl, int64_t node_cap, int leaf_size,
+                   uint32_t *__restrict__ flags)
+{
+    if (flags[0] & 1u) return;  // an earlier level ran out of nodes
+    const int32_t base = lvl[l], cnt = lvl[12 + l];
+    const int32_t base_next = base + cnt;
+    if (blockIdx.x == 0 && threadIdx.x == 0) lvl[l + 1] = base_next;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += step) {
+        GNode &N = nodes[base + t];
+        N.child0 = -1;
+        N.nchild = 0;
+        if (l >= kGLevels || N.end - N.start <= leaf_size) continue;
+        const int shift = 3 * (kGLevels - 1 - l);
+        int32_t b[9];
+        for (uint32_t o = 0; o <= 8; ++o)
+            b[o] = lower_key(keys, N.start, N.end, ((N.prefix << 3) + o) << shift);
+        int nch = 0;
+        for (int o = 0; o < 8; ++o) nch += b[o + 1] > b[o];
+        const int32_t at = atomicAdd(&lvl[12 + l + 1], nch);
+        if ((int64_t)base_next + at + nch > node_cap) {
+            atomicOr(flags, 1u);
+            continue;
+        }
+        int j = 0;
+        for (uint32_t o = 0; o < 8; ++o) {
+            if (b[o + 1] == b[o]) continue;
+            GNode c{};
+            c.start = b[o];
+            c.end = b[o + 1];
+            c.child0 = -1;
+            c.nchild = 0;
+            c.prefix = (N.prefix << 3) | o;
+            c.level = l + 1;
+            nodes[base_next + at + j] = c;
+            ++j;
+        }
+        N.child0 = base_next + at;
+        N.nchild = nch;
+    }
+}
+
+// Moments of the nodes of level l (children already done).
+__global__ void __launch_bounds__(256)
+gtree_moments_kernel(int l, const DensRec *__restrict__ pos, GNode *__restrict__ nodes,
+                     const int32_t *__restrict__ lvl, const double *__restrict__ box,
+                     double theta, const uint32_t *__restrict__ flags)
+{
+    if (flags[0] & 1u) return;
+    const int32_t base = lvl[l], cnt = lvl[12 + l];
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += step) {
+        GNode &N = nodes[base + t];
+        double M = 0.0, sc[3] = {0.0, 0.0, 0.0}, Q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double c[3];
+        if (N.nchild == 0) {
+            for (int32_t k = N.start; k < N.end; ++k) {
+                const DensRec r = pos[k];
+                M += r.m;
+                sc[0] += r.m * r.x;
+                sc[1] += r.m * r.y;
+                sc[2] += r.m * r.z;
+            }
+            for (int a = 0; a < 3; ++a) c[a] = sc[a] / M;
+            for (int32_t k = N.start; k < N.end; ++k) {
+                const DensRec r = pos[k];
+                const double d0 = r.x - c[0], d1 = r.y - c[1], d2v = r.z - c[2];
+                const double d2 = d0 * d0 + d1 * d1 + d2v * d2v;
+                Q[0] += r.m * (3.0 * d0 * d0 - d2);
+                Q[1] += r.m * (3.0 * d0 * d1);
+                Q[2] += r.m * (3.0 * d0 * d2v);
+                Q[3] += r.m * (3.0 * d1 * d1 - d2);
+                Q[4] += r.m * (3.0 * d1 * d2v);
+                Q[5] += r.m * (3.0 * d2v * d2v - d2);
+            }
+        } else {
+            for (int32_t k = N.child0; k < N.child0 + N.nchild; ++k) {
+                const GNode &C = nodes[k];
+                M += C.M;
+                sc[0] += C.M * C.cx;
+                sc[1] += C.M * C.cy;
+                sc[2] += C.M * C.cz;
+            }
+            for (int a = 0; a < 3; ++a) c[a] = sc[a] / M;
+            for (int32_t k = N.child0; k < N.child0 + N.nchild; ++k) {
+                const GNode &C = nodes[k];
+                const double e0 = C.cx - c[0], e1 = C.cy - c[1], e2v = C.cz - c[2];
+                const double e2 = e0 * e0 + e1 * e1 + e2v * e2v;
+                const double Mk = C.M;
+                Q[0] += C.q[0] + Mk * (3.0 * e0 * e0 - e2);
+                Q[1] += C.q[1] + Mk * (3.0 * e0 * e1);
+                Q[2] += C.q[2] + Mk * (3.0 * e0 * e2v);
+                Q[3] += C.q[3] + Mk * (3.0 * e1 * e1 - e2);
+                Q[4] += C.q[4] + Mk * (3.0 * e1 * e2v);
+                Q[5] += C.q[5] + Mk * (3.0 * e2v * e2v - e2);
+            }
+        }
+        const double s = box[3] / (double)(1u << N.level);
+        uint32_t kk[3] = {0u, 0u, 0u};
+        for (int b = 0; b < N.level; ++b)
+            for (int a = 0; a < 3; ++a) kk[a] |= ((N.prefix >> (3 * b + a)) & 1u) << b;
+        double dd = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double centre = box[a] + ((double)kk[a] + 0.5) * s;
+            const double e = c[a] - centre;
+            dd += e * e;
+        }
+        N.cx = c[0];
+        N.cy = c[1];
+        N.cz = c[2];
+        N.ropen = s / theta + sqrt(dd);
+        N.M = M;
+        for (int q = 0; q < 6; ++q) N.q[q] = Q[q];
+    }
+}
+
+__device__ __forceinline__ void wave_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One wave per group of 64 sorted particles (persistent waves, each with its
+// own two frontiers of fcap nodes in global scratch).
+__global__ void __launch_bounds__(256)
+gravity_tree_kernel(int64_t n, const DensRec *__restrict__ pos, const int32_t *__restrict__ order,
+                    const GNode *__restrict__ nodes, int32_t *__restrict__ front_all,
+                    int64_t fcap, double e2, double *__restrict__ gx, double *__restrict__ gy,
+                    double *__restrict__ gz, uint32_t *__restrict__ flags)
+{
+    if (flags[0] & 1u) return;  // the tree is incomplete
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    int32_t *bufA = front_all + wid * 2 * fcap;
+    int32_t *bufB = bufA + fcap;
+    const int64_t ngroup = (n + 63) / 64;
+    for (int64_t g = wid; g < ngroup; g += nw) {
+        const int64_t k = g * 64 + lane;
+        const bool active = k < n;
+        const DensRec me = pos[active ? k : g * 64];
+        double blo[3] = {me.x, me.y, me.z}, bhi[3] = {me.x, me.y, me.z};
+        for (int o = 32; o > 0; o >>= 1)
+            for (int a = 0; a < 3; ++a) {
+                blo[a] = fmin(blo[a], __shfl_xor(blo[a], o, 64));
+                bhi[a] = fmax(bhi[a], __shfl_xor(bhi[a], o, 64));
+            }
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        int32_t *front = bufA, *next = bufB;
+        int64_t fn = 1;
+        bool failed = false;
+        bool root = true;
+        while (fn > 0 && !failed) {
+            int64_t nx = 0;
+            for (int64_t b0 = 0; b0 < fn && !failed; b0 += 64) {
+                const int64_t t = b0 + lane;
+                const bool valid = t < fn;
+                const int32_t nid = !valid ? 0 : (root ? 0 : front[t]);
+                const GNode &N = nodes[nid];
+                double dd = 0.0;
+                {
+                    const double c[3] = {N.cx, N.cy, N.cz};
+                    for (int a = 0; a < 3; ++a) {
+                        double e = 0.0;
+                        if (c[a] < blo[a]) e = blo[a] - c[a];
+                        else if (c[a] > bhi[a]) e = c[a] - bhi[a];
+                        dd += e * e;
+                    }
+                }
+                const bool acc = valid && sqrt(dd) > N.ropen;
+                const int nch = N.nchild;
+                const bool open_int = valid && !acc && nch > 0;
+                // children of opened internal nodes, in lane (= frontier) order
+                int cnt = open_int ? nch : 0;
+                int incl = cnt;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int v = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += v;
+                }
+                const int total = __shfl(incl, 63, 64);
+                if (nx + total > fcap) {
+                    if (lane == 0) atomicOr(flags, 2u);
+                    failed = true;
+                    break;
+                }
+                if (open_int) {
+                    const int64_t at = nx + incl - cnt;
+                    for (int c = 0; c < cnt; ++c) next[at + c] = N.child0 + c;
+                }
+                nx += total;
+                // evaluate accepted nodes and opened leaves in lane order
+                uint64_t use = __ballot(valid && (acc || nch == 0));
+                const uint64_t accm = __ballot(acc);
+                while (use) {
+                    const int tl = __builtin_ctzll(use);
+                    use &= use - 1;
+                    const int32_t id = __builtin_amdgcn_readlane(nid, tl);
+                    const GNode &U = nodes[id];
+                    if ((accm >> tl) & 1ull) {
+                        const double d[3] = {me.x - U.cx, me.y - U.cy, me.z - U.cz};
+                        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                        const double rinv = 1.0 / sqrt(r2);
+                        const double rinv2 = rinv * rinv;
+                        const double rinv3 = rinv * rinv2;
+                        const double rinv5 = rinv3 * rinv2;
+                        const double rinv7 = rinv5 * rinv2;
+                        const double Qd0 = U.q[0] * d[0] + U.q[1] * d[1] + U.q[2] * d[2];
+                        const double Qd1 = U.q[1] * d[0] + U.q[3] * d[1] + U.q[4] * d[2];
+                        const double Qd2 = U.q[2] * d[0] + U.q[4] * d[1] + U.q[5] * d[2];
+                        const double dQd = d[0] * Qd0 + d[1] * Qd1 + d[2] * Qd2;
+                        ax += -U.M * d[0] * rinv3 + Qd0 * rinv5 - 2.5 * dQd * d[0] * rinv7;
+                        ay += -U.M * d[1] * rinv3 + Qd1 * rinv5 - 2.5 * dQd * d[1] * rinv7;
+                        az += -U.M * d[2] * rinv3 + Qd2 * rinv5 - 2.5 * dQd * d[2] * rinv7;
+                    } else {
+                        const int32_t s0 = U.start, s1 = U.end;
+                        for (int32_t l2 = s0; l2 < s1; ++l2) {
+                            const DensRec o = pos[l2];
+                            if (l2 == k) continue;
+                            const double dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
+                            const double d2 = dx * dx + dy * dy + dz * dz + e2;
+                            const double inv = 1.0 / (d2 * sqrt(d2));
+                            ax += -o.m * dx * inv;
+                            ay += -o.m * dy * inv;
+                            az += -o.m * dz * inv;
+                        }
+                    }
+                }
+            }
+            root = false;
+            wave_fence();
+            int32_t *tmp = front;
+            front = next;
+            next = tmp;
+            fn = nx;
+        }
+        if (active) {
+            const int32_t i = order[k];
+            gx[i] = ax;
+            gy[i] = ay;
+            gz[i] = az;
+        }
+    }
+}
+
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -96,6 +506,136 @@ hipError_t launch_gravity_direct(sph_ctx ctx, const sph_particles &p, double eps
     gravity_direct_kernel<<<blocks_for(p.n, kThreads), kThreads, 0, ctx->stream>>>(
         p.n, ctx->drec, eps * eps, gx, gy, gz);
     return hipGetLastError();
+}
+
+
+namespace {
+
+template <typename T>
+hipError_t gt_alloc(sph_ctx ctx, T **p, int64_t count)
+{
+    const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    ctx->scratch_bytes += (int64_t)bytes;
+    return hipSuccess;
+}
+
+void gt_release(sph_ctx ctx)
+{
+    void *ptrs[] = {ctx->gt_keys[0], ctx->gt_keys[1], ctx->gt_vals[0], ctx->gt_vals[1],
+                    ctx->gt_pos, ctx->gt_nodes, ctx->gt_lvl, ctx->gt_front, ctx->gt_flags,
+                    ctx->gt_box, ctx->gt_part};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    ctx->gt_keys[0] = ctx->gt_keys[1] = nullptr;
+    ctx->gt_vals[0] = ctx->gt_vals[1] = nullptr;
+    ctx->gt_pos = nullptr;
+    ctx->gt_nodes = nullptr;
+    ctx->gt_lvl = nullptr;
+    ctx->gt_front = nullptr;
+    ctx->gt_flags = nullptr;
+    ctx->gt_box = nullptr;
+    ctx->gt_part = nullptr;
+    ctx->gt_n_cap = 0;
+}
+
+hipError_t gt_reserve_all(sph_ctx ctx)
+{
+    const int64_t n = ctx->n_max;
+    ctx->gt_node_cap = n / 2 + 1024;
+    ctx->gt_fcap = std::min<int64_t>(ctx->gt_node_cap, 65536);
+    ctx->gt_waves = 1024;
+    hipError_t e;
+    if ((e = gt_alloc(ctx, &ctx->gt_keys[0], n)) != hipSuccess) return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_keys[1], n)) != hipSuccess) return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_vals[0], n)) != hipSuccess) return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_vals[1], n)) != hipSuccess) return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_pos, n)) != hipSuccess) return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_nodes, ctx->gt_node_cap)) != hipSuccess) return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_lvl, 24)) != hipSuccess) return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_front, (int64_t)ctx->gt_waves * 2 * ctx->gt_fcap)) !=
+        hipSuccess)
+        return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_flags, 1)) != hipSuccess) return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_box, 4)) != hipSuccess) return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_part, 6 * kGBoxBlocks)) != hipSuccess) return e;
+    ctx->gt_n_cap = n;
+    return hipSuccess;
+}
+
+// The buffers of the octree gravity, allocated once per context (all or
+// none).
+hipError_t gt_reserve(sph_ctx ctx)
+{
+    if (ctx->gt_n_cap > 0) return hipSuccess;
+    const hipError_t e = gt_reserve_all(ctx);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        gt_release(ctx);
+    }
+    return e;
+}
+
+}  // namespace
+
+void release_gravity_tree(sph_ctx ctx) { gt_release(ctx); }
+
+hipError_t launch_gravity_tree(sph_ctx ctx, const sph_particles &p, double eps, double theta,
+                               int leaf_size, double *gx, double *gy, double *gz,
+                               uint32_t *flags)
+{
+    hipError_t e;
+    if ((e = gt_reserve(ctx)) != hipSuccess) return e;
+    hipStream_t s = ctx->stream;
+    const int64_t n = p.n;
+    const unsigned nbox = std::min<unsigned>(kGBoxBlocks, blocks_for(n, 256));
+    gbox_partial_kernel<<<nbox, 256, 0, s>>>(n, p.x, p.y, p.z, ctx->gt_part);
+    gbox_final_kernel<<<1, 64, 0, s>>>((int)nbox, ctx->gt_part, ctx->gt_box);
+    // (key, i) at slot i, then at slot id[i]: the sort starts from id order
+    gkeys_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, p.x, p.y, p.z, p.id, ctx->gt_box, 0,
+                                                   ctx->gt_keys[0], ctx->gt_vals[0]);
+    gkeys_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, p.x, p.y, p.z, p.id, ctx->gt_box, 1,
+                                                   ctx->gt_keys[0], ctx->gt_vals[0]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int cur = 0;
+    if ((e = radix_sort_pairs(ctx, ctx->gt_keys, ctx->gt_vals, n, 3 * kGLevels, &cur)) !=
+        hipSuccess)
+        return e;
+    const uint32_t *keys = ctx->gt_keys[cur];
+    const int32_t *order = ctx->gt_vals[cur];
+    ggather_kernel<<<blocks_for(n, 256), 256, 0, s>>>(n, order, p.x, p.y, p.z, p.m,
+                                                     ctx->gt_pos);
+    gtree_init_kernel<<<1, 64, 0, s>>>(n, ctx->gt_nodes, ctx->gt_lvl, ctx->gt_flags);
+    // level l has at most min(8^l, node_cap) nodes
+    auto level_blocks = [&](int l) {
+        int64_t most = ctx->gt_node_cap;
+        if (l < 8) most = std::min<int64_t>(most, (int64_t)1 << (3 * l));
+        return std::max(1u, std::min(4096u, blocks_for(most, 256)));
+    };
+    for (int l = 0; l <= kGLevels; ++l)
+        gtree_split_kernel<<<level_blocks(l), 256, 0, s>>>(l, keys, ctx->gt_nodes, ctx->gt_lvl,
+                                                           ctx->gt_node_cap, leaf_size,
+                                                           ctx->gt_flags);
+    for (int l = kGLevels; l >= 0; --l)
+        gtree_moments_kernel<<<level_blocks(l), 256, 0, s>>>(l, ctx->gt_pos, ctx->gt_nodes,
+                                                             ctx->gt_lvl, ctx->gt_box, theta,
+                                                             ctx->gt_flags);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t ngroup = (n + 63) / 64;
+    const unsigned gblocks =
+        (unsigned)std::min<int64_t>(ctx->gt_waves / 4, (ngroup + 3) / 4);
+    gravity_tree_kernel<<<gblocks, 256, 0, s>>>(n, ctx->gt_pos, order, ctx->gt_nodes,
+                                                ctx->gt_front, ctx->gt_fcap, eps * eps, gx, gy,
+                                                gz, ctx->gt_flags);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(flags, ctx->gt_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+        return e;
+    return hipStreamSynchronize(s);
 }
 
 }  // namespace sph

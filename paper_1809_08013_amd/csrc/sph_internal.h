@@ -141,6 +141,21 @@ struct __attribute__((aligned(128))) PairRec {
 };
 static_assert(sizeof(PairRec) == 128, "PairRec is one cache line");
 
+// Octree gravity node: centre of mass and opening radius s / theta + delta
+// (the acceptance test), mass and traceless quadrupole (xx xy xz yy yz zz),
+// the node's range of sorted positions, its children (contiguous, octant
+// order; nchild = 0 for a leaf), Morton prefix and level.
+struct __attribute__((aligned(128))) GNode {
+    double cx, cy, cz, ropen;
+    double M, q[6];
+    double pad0;
+    int32_t start, end, child0, nchild;
+    uint32_t prefix;
+    int32_t level;
+    int32_t pad1[2];
+};
+static_assert(sizeof(GNode) == 128, "GNode is one cache line");
+
 // Block index remapped so that each XCD runs one contiguous range of blocks.
 // Blocks are dispatched to the 8 XCDs round-robin (block b to XCD b % 8);
 // giving XCD x the x-th contiguous slice keeps a Morton-contiguous region of
@@ -210,6 +225,21 @@ struct sph_ctx_s {
     // reductions
     double *red_part = nullptr;      // kRedFields * kRedMaxBlocks
 
+    // octree gravity: allocated by the first sph_gravity_tree call
+    int64_t gt_n_cap = 0;            // particles the buffers hold
+    int64_t gt_node_cap = 0;
+    int64_t gt_fcap = 0;             // frontier entries per wave
+    int32_t gt_waves = 0;            // resident waves of the force kernel
+    uint32_t *gt_keys[2] = {nullptr, nullptr};
+    int32_t *gt_vals[2] = {nullptr, nullptr};
+    sph::DensRec *gt_pos = nullptr;  // sorted {x, y, z, m}
+    sph::GNode *gt_nodes = nullptr;
+    int32_t *gt_lvl = nullptr;       // per level: first node, node count (2 x 12)
+    int32_t *gt_front = nullptr;     // per wave: two frontiers of gt_fcap nodes
+    uint32_t *gt_flags = nullptr;    // bit 0: node capacity, bit 1: frontier capacity
+    double *gt_box = nullptr;        // lo[3], L
+    double *gt_part = nullptr;       // bounding-box partials
+
     uint32_t *status_dev = nullptr;
     uint32_t *hflag_dev = nullptr;   // 0 after a build iff every particle has the same h
     std::string last_error;
@@ -240,6 +270,19 @@ hipError_t launch_volume_weights(sph_ctx ctx, const sph_particles &p, const doub
                                  double exponent);
 hipError_t launch_gravity_direct(sph_ctx ctx, const sph_particles &p, double eps, double *gx,
                                  double *gy, double *gz);
+// Octree gravity; *flags receives the capacity bits of the call (synchronises).
+// Its buffers are allocated by the first call on a context and released by
+// release_gravity_tree.
+void release_gravity_tree(sph_ctx ctx);
+hipError_t launch_gravity_tree(sph_ctx ctx, const sph_particles &p, double eps, double theta,
+                               int leaf_size, double *gx, double *gy, double *gz,
+                               uint32_t *flags);
+// Stable LSD radix sort of (key, value) pairs in k[cur], v[cur] over the low
+// key_bits bits, ping-ponging with k[cur ^ 1], v[cur ^ 1]; *cur is updated to
+// the buffer holding the result. Uses the context's histogram and scan
+// scratch (n <= n_max).
+hipError_t radix_sort_pairs(sph_ctx ctx, uint32_t *k[2], int32_t *v[2], int64_t n,
+                            int key_bits, int *cur);
 hipError_t launch_eos(sph_ctx ctx, const sph_particles &p, const sph_params &prm,
                       const sph_fields &f);
 hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,

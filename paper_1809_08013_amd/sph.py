@@ -135,6 +135,8 @@ def load():
             "sph_eos": (C.c_int32, [_VP, P, M, F]),
             "sph_gravity_direct": (C.c_int32, [_VP, P, C.c_double, _VP, _VP, _VP]),
             "sph_volume_weights": (C.c_int32, [_VP, P, _VP, C.c_double]),
+            "sph_gravity_tree": (C.c_int32, [_VP, P, C.c_double, C.c_double, C.c_int32, _VP,
+                                             _VP, _VP]),
             "sph_momentum_energy": (C.c_int32, [_VP, P, B, N, M, F, A]),
             "sph_integrate": (C.c_int32, [_VP, P, B, C.c_int32, _VP, A]),
             "sph_timestep": (C.c_int32, [_VP, P, M, F, A, _VP, _VP]),
@@ -331,6 +333,20 @@ def sph_gravity_direct(ctx: Context, st: SphState, eps: float = 0.01):
     ctx.raise_on(ctx.lib.sph_gravity_direct(ctx.h, C.byref(st.particles), float(eps),
                                             _ptr(st.t["gx"]), _ptr(st.t["gy"]),
                                             _ptr(st.t["gz"])))
+
+
+def sph_gravity_tree(ctx: Context, st: SphState, eps: float = 0.01, theta: float = 0.5,
+                     leaf_size: int = 16):
+    """Octree (quadrupole) self-gravity into st.t["gx"/"gy"/"gz"] (current
+    order), created if the state has none, like sph_gravity_direct."""
+    import torch
+    if "gx" not in st.t:
+        for k in ("gx", "gy", "gz"):
+            st.t[k] = torch.zeros(max(st.n, 1), dtype=torch.float64, device=st.device)
+        st._refresh()
+    ctx.raise_on(ctx.lib.sph_gravity_tree(ctx.h, C.byref(st.particles), float(eps),
+                                          float(theta), int(leaf_size), _ptr(st.t["gx"]),
+                                          _ptr(st.t["gy"]), _ptr(st.t["gz"])))
 
 
 def sph_volume_weights(ctx: Context, st: SphState, exponent: float, rho=None):

@@ -52,7 +52,7 @@ def test_status_strings_and_null_checks():
     assert b"max_nb" in L.sph_last_error(None)
     for fn in ("sph_ctx_check", "sph_build_cells", "sph_find_neighbors", "sph_density",
                "sph_eos", "sph_momentum_energy", "sph_integrate", "sph_timestep",
-               "sph_gravity_direct", "sph_volume_weights"):
+               "sph_gravity_direct", "sph_volume_weights", "sph_gravity_tree"):
         f = getattr(L, fn)
         nargs = len(f.argtypes)
         args = [None] * nargs
@@ -64,6 +64,8 @@ def test_status_strings_and_null_checks():
             args[2] = 0.01
         if fn == "sph_volume_weights":
             args[3] = 0.7
+        if fn == "sph_gravity_tree":
+            args[2], args[3], args[4] = 0.01, 0.5, 16
         assert f(*args) == S.SPH_E_INVALID, fn
 
 

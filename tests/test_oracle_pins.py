@@ -683,3 +683,91 @@ def test_gve_conservation(gradient):
         assert (amag <= 1e-13 * acc["sa"]).all()
     finally:
         O.set_gradient(O.GRADIENT_KERNEL)
+
+
+def test_gravity_tree_opens_everything_as_theta_vanishes():
+    """Octree gravity (Alg. 1 step 4; the parent codes' multipoles): with
+    theta -> 0 no node is accepted and every leaf is summed directly, so the
+    result is the direct Plummer sum up to summation order."""
+    ic = I.evrard(3000, seed=9)
+    gx, gy, gz, sc, st = O.gravity_tree(ic.x, ic.y, ic.z, ic.m, 0.01, 1e-9, 16)
+    dx, dy, dz = O.gravity_direct(ic.x, ic.y, ic.z, ic.m, 0.01)
+    assert st["node_terms"] == 0 and st["direct_terms"] == ic.n * ic.n  # self pairs counted
+    err = np.sqrt((gx - dx) ** 2 + (gy - dy) ** 2 + (gz - dz) ** 2)
+    assert (err <= 1e-13 * sc).all()
+
+
+def test_gravity_tree_moments_and_structure():
+    """Every node's mass, centre of mass and traceless quadrupole (built
+    bottom-up with the parallel-axis shift) equal those summed directly over
+    its particles; leaves hold at most leaf_size particles (below the finest
+    level); children partition their parent in octant order."""
+    ic = I.evrard(4000, seed=11)
+    ic.m = ic.m * np.random.default_rng(1).uniform(0.5, 1.5, ic.n)
+    T, order = O.gravity_tree_nodes(ic.x, ic.y, ic.z, ic.m, leaf_size=16)
+    P = np.stack([ic.x, ic.y, ic.z], 1)
+    L = np.max(P.max(0) - P.min(0))
+    assert sorted(order.tolist()) == list(range(ic.n))
+    nch = T[:, 15].astype(int)
+    start, end, lev = T[:, 13].astype(int), T[:, 14].astype(int), T[:, 12].astype(int)
+    assert start[0] == 0 and end[0] == ic.n
+    child = 1
+    for t in range(len(T)):
+        sel = order[start[t]:end[t]]
+        m = ic.m[sel]
+        M = m.sum()
+        c = (m[:, None] * P[sel]).sum(0) / M
+        d = P[sel] - c
+        Q = 3 * np.einsum("k,ka,kb->ab", m, d, d) - np.eye(3) * np.sum(m * np.sum(d * d, 1))
+        assert abs(T[t, 0] - M) <= 1e-14 * M
+        assert np.abs(T[t, 1:4] - c).max() <= 1e-14 * L
+        q = np.array([Q[0, 0], Q[0, 1], Q[0, 2], Q[1, 1], Q[1, 2], Q[2, 2]])
+        assert np.abs(T[t, 4:10] - q).max() <= 1e-12 * M * (L / 2 ** lev[t]) ** 2
+        assert T[t, 10] == L / 2 ** lev[t]
+        if nch[t] == 0:
+            assert end[t] - start[t] <= 16 or lev[t] == 10
+        else:
+            kids = range(child, child + nch[t])
+            child += nch[t]
+            assert start[kids[0]] == start[t] and end[kids[-1]] == end[t]
+            assert all(end[a] == start[a + 1] for a in list(kids)[:-1])
+            assert all(lev[a] == lev[t] + 1 for a in kids)
+
+
+def test_gravity_tree_quadrupole_convergence():
+    """A cluster of 192 particles seen from 64 light probes at distance D:
+    the cluster's node is accepted and its monopole plus quadrupole leave an
+    error falling as (size / D)^3 (octupole order), i.e. about eight times
+    per doubling of D; a monopole-only or a wrong quadrupole would fall four
+    times."""
+    rng = np.random.default_rng(4)
+    errs = []
+    for D in (8.0, 16.0, 32.0):
+        cl = rng.random((192, 3)) if D == 8.0 else cl
+        pr = D + 0.01 * (rng.random((64, 3)) if D == 8.0 else pr0)
+        if D == 8.0:
+            pr0 = (pr - D) / 0.01
+        X = np.concatenate([cl, pr])
+        m = np.concatenate([np.full(192, 1.0 / 192), np.full(64, 1e-12)])
+        gx, gy, gz, _, st = O.gravity_tree(X[:, 0], X[:, 1], X[:, 2], m, 0.0, 0.7, 16)
+        dx, dy, dz = O.gravity_direct(X[:, 0], X[:, 1], X[:, 2], m, 0.0)
+        sl = slice(192, 256)
+        e = np.sqrt((gx - dx)[sl] ** 2 + (gy - dy)[sl] ** 2 + (gz - dz)[sl] ** 2)
+        g = np.sqrt(dx[sl] ** 2 + dy[sl] ** 2 + dz[sl] ** 2)
+        assert st["node_terms"] > 0
+        errs.append(float(np.max(e / g)))
+    assert errs[0] < 1e-3
+    assert errs[0] / errs[1] > 6.5 and errs[1] / errs[2] > 6.5
+
+
+def test_gravity_tree_accuracy_evrard():
+    """theta = 0.5, leaves of 16: relative force errors against the direct
+    sum on the Evrard sphere at the level quadrupole trees reach (median
+    a few 1e-4)."""
+    ic = I.evrard(20000, seed=3)
+    gx, gy, gz, _, st = O.gravity_tree(ic.x, ic.y, ic.z, ic.m, 0.01, 0.5, 16)
+    dx, dy, dz = O.gravity_direct(ic.x, ic.y, ic.z, ic.m, 0.01)
+    e = np.sqrt((gx - dx) ** 2 + (gy - dy) ** 2 + (gz - dz) ** 2) / np.sqrt(
+        dx ** 2 + dy ** 2 + dz ** 2)
+    assert np.median(e) < 5e-4 and np.percentile(e, 99) < 3e-3 and e.max() < 2e-2
+    assert st["node_terms"] + st["direct_terms"] < 0.2 * ic.n * ic.n
