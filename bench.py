@@ -129,7 +129,7 @@ def recorded_traffic(kernel: str, workload: str):
 
 
 def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=None,
-            iterate_h: bool = False) -> dict:
+            iterate_h: bool = False, self_gravity=None) -> dict:
     import numpy as np
     import torch
 
@@ -164,6 +164,14 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
         lambda: S.sph_integrate(ctx, st, S.SPH_KICK),
         lambda: S.sph_timestep(ctx, st, prm),
     ]
+    names = list(CALLS)
+    if self_gravity is not None:
+        # Alg. 1 step 4 in the loop: octree gravity at the drifted positions,
+        # before the closing kick (which adds g)
+        eps, theta, leaf = self_gravity
+        S.sph_gravity_tree(ctx, st, eps, theta, leaf)
+        calls.insert(6, lambda: S.sph_gravity_tree(ctx, st, eps, theta, leaf))
+        names.insert(6, "gravity_tree")
     stream = ctx.stream
 
     def step(evs=None):
@@ -186,9 +194,9 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     S.sph_ctx_check(ctx)
-    per_call = {k: 0.0 for k in CALLS}
+    per_call = {k: 0.0 for k in names}
     for evs in events:
-        for k, name in enumerate(CALLS):
+        for k, name in enumerate(names):
             per_call[name] += evs[k].elapsed_time(evs[k + 1])
     per_call = {k: v / steps for k, v in per_call.items()}  # ms per launch
     pairs = float(st.t["count"][: ic.n].sum().item())
@@ -244,8 +252,12 @@ def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
     gather count is in [95, 105]. The self-gravity of the t = 0 particles is
     summed directly on the GPU (sph_gravity_direct, Plummer eps = 0.01; its
     time is reported) and held fixed as an external acceleration over the
-    timed hydro steps: gravity is outside the timed path.
+    timed hydro steps: gravity is outside the timed path. The octree gravity
+    (sph_gravity_tree, theta = 0.5, leaves of 16) is timed on the same state
+    and checked against the direct sum, and a third run recomputes it inside
+    every step (the Evrard collapse with self-gravity, Alg. 1 step 4).
     """
+    import numpy as np
     import torch
 
     from paper_1809_08013_amd import inputs as I
@@ -264,12 +276,29 @@ def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
     t_grav = time.perf_counter() - t0
     gh = st.host(["gx", "gy", "gz"])
     g = (gh["gx"], gh["gy"], gh["gz"])
+    log("octree self-gravity")
+    S.sph_gravity_tree(ctx, st, 0.01, 0.5, 16)  # first call: buffers, code load
+    reps = 10
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S.sph_gravity_tree(ctx, st, 0.01, 0.5, 16)
+    t_tree = (time.perf_counter() - t0) / reps
+    th = st.host(["gx", "gy", "gz"])
+    gd = np.sqrt(g[0] ** 2 + g[1] ** 2 + g[2] ** 2)
+    et = np.sqrt((th["gx"] - g[0]) ** 2 + (th["gy"] - g[1]) ** 2 + (th["gz"] - g[2]) ** 2) / gd
+    tree = {"ms": t_tree * 1e3, "eps": 0.01, "theta": 0.5, "leaf_size": 16,
+            "rel_err_vs_direct_median": float(np.median(et)),
+            "rel_err_vs_direct_p99": float(np.percentile(et, 99)),
+            "rel_err_vs_direct_max": float(et.max()),
+            "speedup_vs_direct": t_grav / t_tree}
     del ctx, st
     out = {"workload": f"Evrard-like sphere, {n:,} particles, rho ~ 1/r, ideal gas gamma=5/3, "
                        "h iterated on the GPU to 95-105 gather neighbours, direct-sum "
                        "self-gravity of the initial state as a fixed external g",
            "gravity_direct": {"ms": t_grav * 1e3, "eps": 0.01,
-                              "pair_interactions_per_s": float(n) * (n - 1) / t_grav}}
+                              "pair_interactions_per_s": float(n) * (n - 1) / t_grav},
+           "gravity_tree": tree}
     for name, prec in (("fp64", S.SPH_FP64), ("fp32_pair", S.SPH_FP32_PAIR)):
         res = run_gpu(ic, prec, steps, warmup, max_nb=512, g=g, iterate_h=True)
         out[name] = {"value": res["pairs_per_step"] / (res["ms_per_step"] * 1e-3),
@@ -278,6 +307,12 @@ def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
                      "mean_neighbours": res["pairs_per_step"] / n,
                      "max_neighbours": res["max_count"],
                      "h_iteration": res["h_iteration"]}
+    res = run_gpu(ic, S.SPH_FP64, steps, warmup, max_nb=512, g=g, iterate_h=True,
+                  self_gravity=(0.01, 0.5, 16))
+    out["fp64_self_gravity"] = {
+        "note": "hydro step plus octree self-gravity recomputed every step",
+        "ms_per_step": res["ms_per_step"],
+        "per_call_ms": {k: round(v, 4) for k, v in res["per_call_ms"].items()}}
     return out
 
 

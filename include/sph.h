@@ -263,12 +263,12 @@ sph_status sph_momentum_energy(sph_ctx ctx, const sph_particles *p,
  * Reads p->x, y, z, m, id (device, n, current order; id must be a
  * permutation of 0..n-1) and writes gx, gy, gz (device, n doubles each,
  * caller-owned, same order). The first call on a context allocates the
- * tree's buffers (about 100 bytes per particle of n_max plus up to 512 MiB
- * of traversal frontiers), kept until sph_ctx_destroy; SPH_E_NOMEM if that
- * fails. Synchronises ctx's stream. SPH_E_INVALID for NULL arrays, eps < 0,
+ * tree's buffers (about 100 bytes per particle of n_max plus 128 MiB of
+ * traversal stacks), kept until sph_ctx_destroy; SPH_E_NOMEM if that fails.
+ * Synchronises ctx's stream. SPH_E_INVALID for NULL arrays, eps < 0,
  * theta <= 0 or a non-finite value, leaf_size outside [8, 64];
- * SPH_E_CAPACITY if the tree needs more than n_max / 2 + 1024 nodes or a
- * group's breadth-first frontier more than its scratch (outputs undefined). */
+ * SPH_E_CAPACITY if the tree needs more than n_max / 2 + 1024 nodes
+ * (outputs undefined). */
 sph_status sph_gravity_tree(sph_ctx ctx, const sph_particles *p, double eps, double theta,
                             int32_t leaf_size, double *gx, double *gy, double *gz);
 

@@ -101,7 +101,7 @@ def lib():
                                                     C.c_int64, _I64, _D, _D, _D, _D]
             L.orc_gravity_tree.restype = C.c_int64
             L.orc_gravity_tree.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_double, C.c_double,
-                                           C.c_int32, _D, _D, _D, _DN, C.c_void_p]
+                                           C.c_int32, _D, _D, _D, _DN, C.c_void_p, C.c_void_p]
             L.orc_gravity_tree_nodes.restype = C.c_int64
             L.orc_gravity_tree_nodes.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_int32,
                                                  C.c_int64, _D, _I64]
@@ -324,17 +324,23 @@ def gravity_direct_subset(x, y, z, m, sel, eps=0.01):
     return gx, gy, gz, sg
 
 
-def gravity_tree(x, y, z, m, eps=0.01, theta=0.5, leaf_size=32):
+def gravity_tree(x, y, z, m, eps=0.01, theta=0.5, leaf_size=32, group_work=False):
     """Octree multipole (quadrupole) self-gravity of sph_oracle.c: returns
     gx, gy, gz, the per-particle sum of term magnitudes, and the statistics
-    dict (nodes, leaves, node_terms, direct_terms, max_frontier)."""
+    dict (nodes, leaves, node_terms, direct_terms, max_frontier; with
+    group_work also the per-group work array)."""
     n = len(x)
     gx, gy, gz, sc = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
-    st = np.zeros(5, dtype=np.int64)
+    st = np.zeros(6, dtype=np.int64)
+    gw = np.zeros(n, dtype=np.int64) if group_work else None
     lib().orc_gravity_tree(n, _d(x), _d(y), _d(z), _d(m), float(eps), float(theta),
-                           int(leaf_size), gx, gy, gz, sc.ctypes.data, st.ctypes.data)
-    stats = dict(zip(("nodes", "leaves", "node_terms", "direct_terms", "max_frontier"),
-                     map(int, st)))
+                           int(leaf_size), gx, gy, gz, sc.ctypes.data, st.ctypes.data,
+                           None if gw is None else gw.ctypes.data)
+    stats = dict(zip(("nodes", "leaves", "node_terms", "direct_terms", "max_frontier",
+                      "groups"), map(int, st)))
+    if gw is not None:
+        gw = gw[: stats["groups"]]
+        stats["group_work"] = gw
     return gx, gy, gz, sc, stats
 
 

@@ -969,8 +969,13 @@ void orc_set_num_threads(int32_t t)
  *          its particles in sorted order, an internal node its children in
  *          octant order with the parallel-axis shift
  *          Q += Q_k + M_k (3 e_a e_b - |e|^2 delta_ab), e = c_k - c;
- *   groups consecutive runs of 64 particles in the sorted order (the last
- *          one shorter). A node N is accepted for every particle of a group
+ *   groups the root if it holds at most 64 particles; else, for every node
+ *          with more than 64 particles, its children with at most 64 taken
+ *          in octant order and merged while the merged run holds at most 64
+ *          (a child with more than 64 ends a run), and a leaf with more than
+ *          64 (finest level only) cut into runs of 64. Each group is a run of
+ *          the sorted order within one node of more than 64 particles, so
+ *          its box stays compact. A node N is accepted for every particle of a group
  *          G when dist(c_N, box_G) > s_N / theta + |c_N - centre_N|, box_G
  *          the bounding box of G's particles; otherwise a leaf N is summed
  *          directly and an internal N is opened (its children are visited
@@ -981,7 +986,10 @@ void orc_set_num_threads(int32_t t)
  *          (unsoftened), the gradient of the expansion of the potential
  *          -M/r - d.Q d / (2 r^5).
  * scale (optional): per particle, the sum of the magnitudes of the terms.
- * stats (optional): [nodes, leaves, node terms, direct terms, largest frontier].
+ * stats (optional): [nodes, leaves, node terms, direct terms, largest frontier,
+ * groups].
+ * group_work (optional): per group, accepted nodes plus directly summed
+ * particles.
  */
 #define ORC_GROUP 64
 typedef struct {
@@ -1143,7 +1151,8 @@ static orc_gnode *gtree_build(int64_t n, const double **P, const double *m,
 
 int64_t orc_gravity_tree(int64_t n, const double *x, const double *y, const double *z,
                          const double *m, double eps, double theta, int32_t leaf_size,
-                         double *gx, double *gy, double *gz, double *scale, int64_t *stats)
+                         double *gx, double *gy, double *gz, double *scale, int64_t *stats,
+                         int64_t *group_work)
 {
     if (n <= 0) return 0;
     const double *P[3] = {x, y, z};
@@ -1151,17 +1160,49 @@ int64_t orc_gravity_tree(int64_t n, const double *x, const double *y, const doub
     int64_t nn;
     orc_gnode *T = gtree_build(n, P, m, leaf_size, &srt, &nn);
 
-    /* groups of 64 sorted particles, each walked breadth-first from the root */
+    /* groups, each walked breadth-first from the root */
     int64_t n_leaf = 0, n_node_terms = 0, n_direct_terms = 0, max_front = 1;
     for (int64_t t = 0; t < nn; ++t) n_leaf += T[t].nchild == 0;
-    const int64_t n_group = (n + ORC_GROUP - 1) / ORC_GROUP;
+    int64_t n_group = 0;
+    int64_t *gs = (int64_t *)malloc(sizeof(int64_t) * (size_t)(8 * nn + n / ORC_GROUP + 2));
+    int64_t *ge = (int64_t *)malloc(sizeof(int64_t) * (size_t)(8 * nn + n / ORC_GROUP + 2));
+    if (n <= ORC_GROUP) {
+        gs[0] = 0;
+        ge[0] = n;
+        n_group = 1;
+    }
+    for (int64_t t = 0; t < nn; ++t) {
+        if (T[t].end - T[t].start <= ORC_GROUP) continue;
+        if (T[t].nchild == 0) {
+            for (int64_t a = T[t].start; a < T[t].end; a += ORC_GROUP) {
+                gs[n_group] = a;
+                ge[n_group++] = a + ORC_GROUP < T[t].end ? a + ORC_GROUP : T[t].end;
+            }
+            continue;
+        }
+        int64_t cs = -1, ce = -1;
+        for (int64_t k = T[t].child0; k < T[t].child0 + T[t].nchild; ++k) {
+            if (T[k].end - T[k].start > ORC_GROUP) {
+                if (cs >= 0) { gs[n_group] = cs; ge[n_group++] = ce; cs = -1; }
+                continue;
+            }
+            if (cs >= 0 && T[k].end - cs <= ORC_GROUP) {
+                ce = T[k].end;
+                continue;
+            }
+            if (cs >= 0) { gs[n_group] = cs; ge[n_group++] = ce; }
+            cs = T[k].start;
+            ce = T[k].end;
+        }
+        if (cs >= 0) { gs[n_group] = cs; ge[n_group++] = ce; }
+    }
     const double e2 = eps * eps;
     #pragma omp parallel for schedule(dynamic, 16) reduction(+ : n_node_terms, n_direct_terms) reduction(max : max_front)
     for (int64_t q = 0; q < n_group; ++q) {
         orc_gnode Gs;
         orc_gnode *G = &Gs;
-        G->start = q * ORC_GROUP;
-        G->end = G->start + ORC_GROUP < n ? G->start + ORC_GROUP : n;
+        G->start = gs[q];
+        G->end = ge[q];
         for (int a = 0; a < 3; ++a) { G->blo[a] = INFINITY; G->bhi[a] = -INFINITY; }
         for (int64_t k = G->start; k < G->end; ++k)
             for (int a = 0; a < 3; ++a) {
@@ -1169,7 +1210,7 @@ int64_t orc_gravity_tree(int64_t n, const double *x, const double *y, const doub
                 if (v < G->blo[a]) G->blo[a] = v;
                 if (v > G->bhi[a]) G->bhi[a] = v;
             }
-        int64_t fcap = 64, fn = 1, ncap = 64, nx;
+        int64_t fcap = 64, fn = 1, ncap = 64, nx, work = 0;
         int64_t *front = (int64_t *)malloc(sizeof(int64_t) * (size_t)fcap);
         int64_t *next = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncap);
         front[0] = 0;
@@ -1208,6 +1249,7 @@ int64_t orc_gravity_tree(int64_t n, const double *x, const double *y, const doub
                         ax[4 * k + 3] += sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
                     }
                     n_node_terms += gn;
+                    work += 1;
                 } else if (N->nchild == 0) {
                     for (int64_t k = 0; k < gn; ++k) {
                         int64_t i = srt[G->start + k].idx;
@@ -1226,6 +1268,7 @@ int64_t orc_gravity_tree(int64_t n, const double *x, const double *y, const doub
                         }
                     }
                     n_direct_terms += gn * (N->end - N->start);
+                    work += N->end - N->start;
                 } else {
                     for (int64_t k = N->child0; k < N->child0 + N->nchild; ++k) {
                         if (nx == ncap) {
@@ -1248,6 +1291,7 @@ int64_t orc_gravity_tree(int64_t n, const double *x, const double *y, const doub
             gz[i] = ax[4 * k + 2];
             if (scale) scale[i] = ax[4 * k + 3];
         }
+        if (group_work) group_work[q] = work;
         free(ax);
         free(front);
         free(next);
@@ -1259,6 +1303,9 @@ int64_t orc_gravity_tree(int64_t n, const double *x, const double *y, const doub
         stats[3] = n_direct_terms;
         stats[4] = max_front;
     }
+    if (stats) stats[5] = n_group;
+    free(gs);
+    free(ge);
     free(T);
     free(srt);
     return nn;

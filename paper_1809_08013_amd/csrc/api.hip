@@ -451,7 +451,7 @@ sph_status sph_gravity_tree(sph_ctx ctx, const sph_particles *p, double eps, dou
         return fail(ctx, SPH_E_NOMEM, "octree buffers: %s", hipGetErrorString(e));
     SPH_HIP(ctx, e);
     if (flags & 1u) return fail(ctx, SPH_E_CAPACITY, "octree node capacity exceeded");
-    if (flags & 2u) return fail(ctx, SPH_E_CAPACITY, "octree frontier capacity exceeded");
+    if (flags & 2u) return fail(ctx, SPH_E_CAPACITY, "octree traversal stack exceeded");
     return SPH_OK;
 }
 

@@ -23,17 +23,22 @@
 //          Q_ab = sum m (3 d_a d_b - |d|^2 delta_ab), d = x - c; leaves sum
 //          their particles in sorted order, internal nodes their children in
 //          octant order with the parallel-axis shift;
-//   groups runs of 64 sorted particles, one wave each. A node N is accepted
+//   groups the root if it holds at most 64 particles; else, for every node
+//          with more than 64 particles, its children with at most 64 in
+//          octant order, merged while the run holds at most 64 (a larger
+//          child ends a run), and a finest-level leaf with more than 64 cut
+//          into runs of 64; one wave each. A node N is accepted
 //          for the whole group G when dist(c_N, box_G) > s_N / theta +
 //          |c_N - centre_N|; otherwise a leaf is summed directly and an
-//          internal node opened; breadth-first from the root, children in
-//          octant order, every accepted node and opened leaf evaluated in
-//          that order;
+//          internal node opened (the definition walks breadth-first; the
+//          kernel visits the same nodes in stack order);
 //   terms  direct -m_j d / (|d|^2 + eps^2)^{3/2} (j != i); node
 //          -M d / r^3 + Q d / r^5 - 5/2 (d.Q d) d / r^7, d = x_i - c.
-// Tree build, moments and terms use plain FP64 operations in the order of
-// their definition (no fused multiply-add; correctly rounded division and
-// square root).
+// Tree build and moments use plain FP64 operations in the order of their
+// definition (no fused multiply-add; correctly rounded division and square
+// root), so the tree and every acceptance decision are the definition's; the
+// terms take 1/sqrt from the hardware estimate refined by two Newton steps
+// (about one ulp).
 #include <algorithm>
 #include <cmath>
 
@@ -157,15 +162,19 @@ gbox_partial_kernel(int64_t n, const double *__restrict__ x, const double *__res
         for (int a = 0; a < 6; ++a) part[6 * blockIdx.x + a] = red[a][0];
 }
 
-// box = {lo_x, lo_y, lo_z, L}
+// box = {lo_x, lo_y, lo_z, L}; one wave
 __global__ void __launch_bounds__(64)
 gbox_final_kernel(int nblk, const double *__restrict__ part, double *__restrict__ box)
 {
-    if (threadIdx.x != 0) return;
     double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    for (int b = 0; b < nblk; ++b)
+    for (int b = threadIdx.x; b < nblk; b += 64)
         for (int a = 0; a < 6; ++a)
             v[a] = a < 3 ? fmin(v[a], part[6 * b + a]) : fmax(v[a], part[6 * b + a]);
+    for (int o = 32; o > 0; o >>= 1)
+        for (int a = 0; a < 6; ++a)
+            v[a] = a < 3 ? fmin(v[a], __shfl_xor(v[a], o, 64))
+                         : fmax(v[a], __shfl_xor(v[a], o, 64));
+    if (threadIdx.x != 0) return;
     double L = 0.0;
     for (int a = 0; a < 3; ++a) {
         box[a] = v[a];
@@ -221,7 +230,7 @@ gtree_init_kernel(int64_t n, GNode *__restrict__ nodes, int32_t *__restrict__ lv
                   uint32_t *__restrict__ flags)
 {
     const int t = threadIdx.x;
-    if (t < 24) lvl[t] = t == 12 ? 1 : 0;
+    if (t < 25) lvl[t] = t == 12 ? 1 : 0;  // lvl[24]: group count
     if (t == 0) {
         GNode r{};
         r.start = 0;
@@ -372,25 +381,92 @@ __device__ __forceinline__ void wave_fence()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// One wave per group of 64 sorted particles (persistent waves, each with its
-// own two frontiers of fcap nodes in global scratch).
+// The groups of the definition; their order in the list does not matter.
 __global__ void __launch_bounds__(256)
-gravity_tree_kernel(int64_t n, const DensRec *__restrict__ pos, const int32_t *__restrict__ order,
-                    const GNode *__restrict__ nodes, int32_t *__restrict__ front_all,
+gtree_groups_kernel(int64_t n, const GNode *__restrict__ nodes, int32_t *__restrict__ lvl,
+                    int2 *__restrict__ groups, const uint32_t *__restrict__ flags)
+{
+    if (flags[0] & 1u) return;
+    constexpr int G = 64;
+    const int32_t total = lvl[kGLevels + 1];  // first node past the last level
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t0 == 0 && n <= G) groups[atomicAdd(&lvl[24], 1)] = make_int2(0, (int32_t)n);
+    for (int64_t t = t0; t < total; t += step) {
+        const GNode &N = nodes[t];
+        if (N.end - N.start <= G) continue;
+        if (N.nchild == 0) {
+            const int32_t num = (N.end - N.start + G - 1) / G;
+            const int32_t at = atomicAdd(&lvl[24], num);
+            for (int32_t q = 0; q < num; ++q)
+                groups[at + q] = make_int2(N.start + q * G, min(N.start + (q + 1) * G, N.end));
+            continue;
+        }
+        int2 run[8];
+        int nr = 0, cs = -1, ce = -1;
+        for (int32_t k = N.child0; k < N.child0 + N.nchild; ++k) {
+            const int32_t a = nodes[k].start, b = nodes[k].end;
+            if (b - a > G) {
+                if (cs >= 0) run[nr++] = make_int2(cs, ce);
+                cs = -1;
+                continue;
+            }
+            if (cs >= 0 && b - cs <= G) {
+                ce = b;
+                continue;
+            }
+            if (cs >= 0) run[nr++] = make_int2(cs, ce);
+            cs = a;
+            ce = b;
+        }
+        if (cs >= 0) run[nr++] = make_int2(cs, ce);
+        const int32_t at = atomicAdd(&lvl[24], nr);
+        for (int q = 0; q < nr; ++q) groups[at + q] = run[q];
+    }
+}
+
+__device__ __forceinline__ void lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave per group of 64 sorted particles (persistent waves). The nodes
+// still to visit sit on a per-wave stack in global scratch: each round pops
+// up to 64 of them, one per lane, tests them against the group's box,
+// pushes the children of the opened internal nodes and evaluates the
+// accepted nodes and the opened leaves in lane order. A round leaves at most
+// 8 * 64 - 64 new entries per tree level on the stack, so 11 levels fit in
+// fcap >= 5700. The nodes visited are those of the breadth-first walk of the
+// definition (the test does not depend on the order), each term is the
+// definition's, and only the order of the per-particle sums differs.
+// Each lane loads its node whole; the accepted nodes' moments are handed to
+// all lanes through LDS, and an opened leaf's particles are staged in LDS by
+// one coalesced load, so no term waits on a memory round trip of its own.
+__global__ void __launch_bounds__(256)
+gravity_tree_kernel(const DensRec *__restrict__ pos, const int32_t *__restrict__ order,
+                    const GNode *__restrict__ nodes, const int2 *__restrict__ groups,
+                    const int32_t *__restrict__ lvl, int32_t *__restrict__ stack_all,
                     int64_t fcap, double e2, double *__restrict__ gx, double *__restrict__ gy,
                     double *__restrict__ gz, uint32_t *__restrict__ flags)
 {
+    __shared__ double nd_all[4][10][64];  // per wave: c, M, Q of each lane's node
+    __shared__ DensRec lr_all[4][64];     // per wave: a leaf's particles
     if (flags[0] & 1u) return;  // the tree is incomplete
     const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int w = threadIdx.x >> 6;
+    double (*nd)[64] = nd_all[w];
+    DensRec *lr = lr_all[w];
+    const int64_t wid = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
-    int32_t *bufA = front_all + wid * 2 * fcap;
-    int32_t *bufB = bufA + fcap;
-    const int64_t ngroup = (n + 63) / 64;
+    int32_t *stk = stack_all + wid * fcap;
+    const int64_t ngroup = lvl[24];
     for (int64_t g = wid; g < ngroup; g += nw) {
-        const int64_t k = g * 64 + lane;
-        const bool active = k < n;
-        const DensRec me = pos[active ? k : g * 64];
+        const int2 gr = groups[g];
+        const int64_t k = gr.x + lane;
+        const bool active = k < gr.y;
+        const DensRec me = pos[active ? k : gr.x];
         double blo[3] = {me.x, me.y, me.z}, bhi[3] = {me.x, me.y, me.z};
         for (int o = 32; o > 0; o >>= 1)
             for (int a = 0; a < 3; ++a) {
@@ -398,79 +474,94 @@ gravity_tree_kernel(int64_t n, const DensRec *__restrict__ pos, const int32_t *_
                 bhi[a] = fmax(bhi[a], __shfl_xor(bhi[a], o, 64));
             }
         double ax = 0.0, ay = 0.0, az = 0.0;
-        int32_t *front = bufA, *next = bufB;
-        int64_t fn = 1;
-        bool failed = false;
+        int64_t sp = 0;
         bool root = true;
-        while (fn > 0 && !failed) {
-            int64_t nx = 0;
-            for (int64_t b0 = 0; b0 < fn && !failed; b0 += 64) {
-                const int64_t t = b0 + lane;
-                const bool valid = t < fn;
-                const int32_t nid = !valid ? 0 : (root ? 0 : front[t]);
-                const GNode &N = nodes[nid];
-                double dd = 0.0;
-                {
-                    const double c[3] = {N.cx, N.cy, N.cz};
-                    for (int a = 0; a < 3; ++a) {
-                        double e = 0.0;
-                        if (c[a] < blo[a]) e = blo[a] - c[a];
-                        else if (c[a] > bhi[a]) e = c[a] - bhi[a];
-                        dd += e * e;
-                    }
+        while (root || sp > 0) {
+            const int64_t nb = root ? 1 : (sp < 64 ? sp : 64);
+            const bool valid = lane < nb;
+            const int32_t nid = (!valid || root) ? 0 : stk[sp - nb + lane];
+            sp -= root ? 0 : nb;
+            root = false;
+            const GNode N = nodes[nid];
+            double dd = 0.0;
+            {
+                const double c[3] = {N.cx, N.cy, N.cz};
+                for (int a = 0; a < 3; ++a) {
+                    double e = 0.0;
+                    if (c[a] < blo[a]) e = blo[a] - c[a];
+                    else if (c[a] > bhi[a]) e = c[a] - bhi[a];
+                    dd += e * e;
                 }
-                const bool acc = valid && sqrt(dd) > N.ropen;
-                const int nch = N.nchild;
-                const bool open_int = valid && !acc && nch > 0;
-                // children of opened internal nodes, in lane (= frontier) order
-                int cnt = open_int ? nch : 0;
-                int incl = cnt;
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int v = __shfl_up(incl, o, 64);
-                    if (lane >= o) incl += v;
-                }
-                const int total = __shfl(incl, 63, 64);
-                if (nx + total > fcap) {
-                    if (lane == 0) atomicOr(flags, 2u);
-                    failed = true;
-                    break;
-                }
-                if (open_int) {
-                    const int64_t at = nx + incl - cnt;
-                    for (int c = 0; c < cnt; ++c) next[at + c] = N.child0 + c;
-                }
-                nx += total;
-                // evaluate accepted nodes and opened leaves in lane order
-                uint64_t use = __ballot(valid && (acc || nch == 0));
-                const uint64_t accm = __ballot(acc);
-                while (use) {
-                    const int tl = __builtin_ctzll(use);
-                    use &= use - 1;
-                    const int32_t id = __builtin_amdgcn_readlane(nid, tl);
-                    const GNode &U = nodes[id];
-                    if ((accm >> tl) & 1ull) {
-                        const double d[3] = {me.x - U.cx, me.y - U.cy, me.z - U.cz};
-                        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                        const double rinv = 1.0 / sqrt(r2);
-                        const double rinv2 = rinv * rinv;
-                        const double rinv3 = rinv * rinv2;
-                        const double rinv5 = rinv3 * rinv2;
-                        const double rinv7 = rinv5 * rinv2;
-                        const double Qd0 = U.q[0] * d[0] + U.q[1] * d[1] + U.q[2] * d[2];
-                        const double Qd1 = U.q[1] * d[0] + U.q[3] * d[1] + U.q[4] * d[2];
-                        const double Qd2 = U.q[2] * d[0] + U.q[4] * d[1] + U.q[5] * d[2];
-                        const double dQd = d[0] * Qd0 + d[1] * Qd1 + d[2] * Qd2;
-                        ax += -U.M * d[0] * rinv3 + Qd0 * rinv5 - 2.5 * dQd * d[0] * rinv7;
-                        ay += -U.M * d[1] * rinv3 + Qd1 * rinv5 - 2.5 * dQd * d[1] * rinv7;
-                        az += -U.M * d[2] * rinv3 + Qd2 * rinv5 - 2.5 * dQd * d[2] * rinv7;
-                    } else {
-                        const int32_t s0 = U.start, s1 = U.end;
-                        for (int32_t l2 = s0; l2 < s1; ++l2) {
-                            const DensRec o = pos[l2];
-                            if (l2 == k) continue;
+            }
+            const bool acc = valid && sqrt(dd) > N.ropen;
+            const int nch = N.nchild;
+            const bool open_int = valid && !acc && nch > 0;
+            // children of the opened internal nodes onto the stack
+            const int cnt = open_int ? nch : 0;
+            int incl = cnt;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += v;
+            }
+            const int total = __shfl(incl, 63, 64);
+            if (sp + total > fcap) {
+                if (lane == 0) atomicOr(flags, 2u);
+                break;
+            }
+            if (open_int) {
+                const int64_t at = sp + incl - cnt;
+                for (int c = 0; c < cnt; ++c) stk[at + c] = N.child0 + c;
+            }
+            sp += total;
+            // moments of the accepted nodes into LDS
+            lds_sync();
+            if (acc) {
+                nd[0][lane] = N.cx;
+                nd[1][lane] = N.cy;
+                nd[2][lane] = N.cz;
+                nd[3][lane] = N.M;
+                for (int q = 0; q < 6; ++q) nd[4 + q][lane] = N.q[q];
+            }
+            lds_sync();
+            // accepted nodes and opened leaves, in lane order
+            uint64_t use = __ballot(valid && (acc || nch == 0));
+            const uint64_t accm = __ballot(acc);
+            while (use) {
+                const int tl = __builtin_ctzll(use);
+                use &= use - 1;
+                if ((accm >> tl) & 1ull) {
+                    const double d[3] = {me.x - nd[0][tl], me.y - nd[1][tl], me.z - nd[2][tl]};
+                    const double M = nd[3][tl];
+                    const double q0 = nd[4][tl], q1 = nd[5][tl], q2 = nd[6][tl],
+                                 q3 = nd[7][tl], q4 = nd[8][tl], q5 = nd[9][tl];
+                    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                    const double rinv = rsq_newton(r2);  // r2 > 0: the node was accepted
+                    const double rinv2 = rinv * rinv;
+                    const double rinv3 = rinv * rinv2;
+                    const double rinv5 = rinv3 * rinv2;
+                    const double rinv7 = rinv5 * rinv2;
+                    const double Qd0 = q0 * d[0] + q1 * d[1] + q2 * d[2];
+                    const double Qd1 = q1 * d[0] + q3 * d[1] + q4 * d[2];
+                    const double Qd2 = q2 * d[0] + q4 * d[1] + q5 * d[2];
+                    const double dQd = d[0] * Qd0 + d[1] * Qd1 + d[2] * Qd2;
+                    ax += -M * d[0] * rinv3 + Qd0 * rinv5 - 2.5 * dQd * d[0] * rinv7;
+                    ay += -M * d[1] * rinv3 + Qd1 * rinv5 - 2.5 * dQd * d[1] * rinv7;
+                    az += -M * d[2] * rinv3 + Qd2 * rinv5 - 2.5 * dQd * d[2] * rinv7;
+                } else {
+                    // the leaf's particles, staged 64 at a time
+                    const int32_t s0 = __builtin_amdgcn_readlane(N.start, tl);
+                    const int32_t s1 = __builtin_amdgcn_readlane(N.end, tl);
+                    for (int32_t c0 = s0; c0 < s1; c0 += 64) {
+                        const int32_t m = min(64, s1 - c0);
+                        lds_sync();
+                        if (lane < m) lr[lane] = pos[c0 + lane];
+                        lds_sync();
+                        for (int32_t j = 0; j < m; ++j) {
+                            const DensRec o = lr[j];
                             const double dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
                             const double d2 = dx * dx + dy * dy + dz * dz + e2;
-                            const double inv = 1.0 / (d2 * sqrt(d2));
+                            const double rs = rsq_newton(d2);
+                            const double inv = c0 + j == k ? 0.0 : rs * rs * rs;
                             ax += -o.m * dx * inv;
                             ay += -o.m * dy * inv;
                             az += -o.m * dz * inv;
@@ -478,12 +569,8 @@ gravity_tree_kernel(int64_t n, const DensRec *__restrict__ pos, const int32_t *_
                     }
                 }
             }
-            root = false;
+            // the pushed entries are read by other lanes next round
             wave_fence();
-            int32_t *tmp = front;
-            front = next;
-            next = tmp;
-            fn = nx;
         }
         if (active) {
             const int32_t i = order[k];
@@ -528,7 +615,7 @@ void gt_release(sph_ctx ctx)
 {
     void *ptrs[] = {ctx->gt_keys[0], ctx->gt_keys[1], ctx->gt_vals[0], ctx->gt_vals[1],
                     ctx->gt_pos, ctx->gt_nodes, ctx->gt_lvl, ctx->gt_front, ctx->gt_flags,
-                    ctx->gt_box, ctx->gt_part};
+                    ctx->gt_box, ctx->gt_part, ctx->gt_groups};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     ctx->gt_keys[0] = ctx->gt_keys[1] = nullptr;
@@ -540,6 +627,7 @@ void gt_release(sph_ctx ctx)
     ctx->gt_flags = nullptr;
     ctx->gt_box = nullptr;
     ctx->gt_part = nullptr;
+    ctx->gt_groups = nullptr;
     ctx->gt_n_cap = 0;
 }
 
@@ -547,8 +635,8 @@ hipError_t gt_reserve_all(sph_ctx ctx)
 {
     const int64_t n = ctx->n_max;
     ctx->gt_node_cap = n / 2 + 1024;
-    ctx->gt_fcap = std::min<int64_t>(ctx->gt_node_cap, 65536);
-    ctx->gt_waves = 1024;
+    ctx->gt_fcap = 8192;
+    ctx->gt_waves = 4096;
     hipError_t e;
     if ((e = gt_alloc(ctx, &ctx->gt_keys[0], n)) != hipSuccess) return e;
     if ((e = gt_alloc(ctx, &ctx->gt_keys[1], n)) != hipSuccess) return e;
@@ -556,8 +644,9 @@ hipError_t gt_reserve_all(sph_ctx ctx)
     if ((e = gt_alloc(ctx, &ctx->gt_vals[1], n)) != hipSuccess) return e;
     if ((e = gt_alloc(ctx, &ctx->gt_pos, n)) != hipSuccess) return e;
     if ((e = gt_alloc(ctx, &ctx->gt_nodes, ctx->gt_node_cap)) != hipSuccess) return e;
-    if ((e = gt_alloc(ctx, &ctx->gt_lvl, 24)) != hipSuccess) return e;
-    if ((e = gt_alloc(ctx, &ctx->gt_front, (int64_t)ctx->gt_waves * 2 * ctx->gt_fcap)) !=
+    if ((e = gt_alloc(ctx, &ctx->gt_lvl, 25)) != hipSuccess) return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_groups, n + 1)) != hipSuccess) return e;
+    if ((e = gt_alloc(ctx, &ctx->gt_front, (int64_t)ctx->gt_waves * ctx->gt_fcap)) !=
         hipSuccess)
         return e;
     if ((e = gt_alloc(ctx, &ctx->gt_flags, 1)) != hipSuccess) return e;
@@ -624,13 +713,16 @@ hipError_t launch_gravity_tree(sph_ctx ctx, const sph_particles &p, double eps, 
         gtree_moments_kernel<<<level_blocks(l), 256, 0, s>>>(l, ctx->gt_pos, ctx->gt_nodes,
                                                              ctx->gt_lvl, ctx->gt_box, theta,
                                                              ctx->gt_flags);
+    gtree_groups_kernel<<<std::min(4096u, blocks_for(ctx->gt_node_cap, 256)), 256, 0, s>>>(
+        n, ctx->gt_nodes, ctx->gt_lvl, ctx->gt_groups, ctx->gt_flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t ngroup = (n + 63) / 64;
+    // groups hold at least one particle each, so at most n of them
     const unsigned gblocks =
-        (unsigned)std::min<int64_t>(ctx->gt_waves / 4, (ngroup + 3) / 4);
-    gravity_tree_kernel<<<gblocks, 256, 0, s>>>(n, ctx->gt_pos, order, ctx->gt_nodes,
-                                                ctx->gt_front, ctx->gt_fcap, eps * eps, gx, gy,
-                                                gz, ctx->gt_flags);
+        (unsigned)std::min<int64_t>(ctx->gt_waves / 4, (n + 3) / 4);
+    gravity_tree_kernel<<<gblocks, 256, 0, s>>>(ctx->gt_pos, order, ctx->gt_nodes,
+                                                ctx->gt_groups, ctx->gt_lvl, ctx->gt_front,
+                                                ctx->gt_fcap, eps * eps, gx, gy, gz,
+                                                ctx->gt_flags);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(flags, ctx->gt_flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) !=
         hipSuccess)

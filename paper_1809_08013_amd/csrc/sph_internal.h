@@ -228,15 +228,16 @@ struct sph_ctx_s {
     // octree gravity: allocated by the first sph_gravity_tree call
     int64_t gt_n_cap = 0;            // particles the buffers hold
     int64_t gt_node_cap = 0;
-    int64_t gt_fcap = 0;             // frontier entries per wave
+    int64_t gt_fcap = 0;             // stack entries per wave
     int32_t gt_waves = 0;            // resident waves of the force kernel
     uint32_t *gt_keys[2] = {nullptr, nullptr};
     int32_t *gt_vals[2] = {nullptr, nullptr};
     sph::DensRec *gt_pos = nullptr;  // sorted {x, y, z, m}
     sph::GNode *gt_nodes = nullptr;
-    int32_t *gt_lvl = nullptr;       // per level: first node, node count (2 x 12)
-    int32_t *gt_front = nullptr;     // per wave: two frontiers of gt_fcap nodes
-    uint32_t *gt_flags = nullptr;    // bit 0: node capacity, bit 1: frontier capacity
+    int32_t *gt_lvl = nullptr;       // per level: first node, node count (2 x 12); groups
+    int2 *gt_groups = nullptr;       // groups: first and end sorted position
+    int32_t *gt_front = nullptr;     // per wave: a stack of gt_fcap nodes to visit
+    uint32_t *gt_flags = nullptr;    // bit 0: node capacity, bit 1: stack capacity
     double *gt_box = nullptr;        // lo[3], L
     double *gt_part = nullptr;       // bounding-box partials
 

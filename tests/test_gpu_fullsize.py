@@ -133,3 +133,22 @@ def test_evrard_1M_gravity_sampled():
     e = float(np.max(d / sg))
     print("gravity 1M sampled error", e, flush=True)
     assert e <= 1e-12
+
+
+def test_evrard_1M_gravity_tree():
+    """Octree gravity at the bench's size (1M Evrard sphere, theta = 0.5,
+    leaves of 16), every particle against the oracle's octree within 1e-12
+    of its term-magnitude sum."""
+    import oracle as O
+    ic = I.evrard(1_000_000, seed=0)
+    print("case tree evrard_1M", flush=True)
+    gx, gy, gz, sc, st = O.gravity_tree(ic.x, ic.y, ic.z, ic.m, 0.01, 0.5, 16)
+    ctx = S.Context(ic.n, 64)
+    s = S.SphState(ic, 64)
+    S.sph_gravity_tree(ctx, s, 0.01, 0.5, 16)
+    S.sph_ctx_check(ctx)
+    got = s.host(["gx", "gy", "gz"])
+    err = np.sqrt((got["gx"] - gx) ** 2 + (got["gy"] - gy) ** 2 + (got["gz"] - gz) ** 2)
+    rel = float(np.max(err / sc))
+    print("evrard 1M tree max err / scale", rel, st, flush=True)
+    assert rel <= 1e-12
