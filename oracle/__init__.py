@@ -88,6 +88,9 @@ def lib():
             L.orc_timestep.restype = C.c_double
             L.orc_timestep.argtypes = ([C.c_int64] + [_D] * 6 + [_DN] * 3
                                        + [C.c_double] * 4)
+            L.orc_timestep_each.restype = None
+            L.orc_timestep_each.argtypes = ([C.c_int64] + [_D] * 6 + [_DN] * 3
+                                            + [C.c_double] * 4 + [_D])
             L.orc_integrate.restype = None
             L.orc_integrate.argtypes = ([C.c_int64, C.c_int32, C.c_double] + [_D] * 7
                                         + [_D] * 4 + [_DN] * 3 + [_D, _D, _I32])
@@ -284,6 +287,30 @@ def timestep(h, c, mumax, ax, ay, az, params, g=None):
         float(params.c_force)))
 
 
+def timestep_each(h, c, mumax, ax, ay, az, params, g=None):
+    """Per-particle Courant and force limit (the global dt is its minimum)."""
+    n = len(h)
+    gx = gy = gz = None
+    if g is not None:
+        gx, gy, gz = (_d(a) for a in g)
+    dtc = np.zeros(n)
+    lib().orc_timestep_each(n, _d(h), _d(c), _d(mumax), _d(ax), _d(ay), _d(az), _dn(gx),
+                            _dn(gy), _dn(gz), float(params.alpha), float(params.beta),
+                            float(params.c_cfl), float(params.c_force), dtc)
+    return dtc
+
+
+def block_bins(dtc, max_bin):
+    """Individual time steps in power-of-two bins: the largest step
+    D = min(max dtc, min dtc * 2^max_bin) and, per particle, the smallest b in
+    [0, max_bin] with D / 2^b <= dtc."""
+    D = float(min(np.max(dtc), np.min(dtc) * 2.0 ** max_bin))
+    b = np.full(len(dtc), max_bin, dtype=np.int64)
+    for k in range(max_bin, -1, -1):
+        b = np.where(np.ldexp(D, -k) <= dtc, k, b)
+    return D, b
+
+
 def integrate(state: dict, stage: int, dt: float, acc: dict, lo, hi, periodic,
               g=None):
     """In place on state's float64 arrays x..vz, u (stage 0 kick+drift, 1 kick)."""
@@ -410,6 +437,57 @@ class OracleRun:
         self.dt = timestep(self.s["h"], self.c, self.acc["mumax"], self.acc["ax"],
                            self.acc["ay"], self.acc["az"], self.params, self.g)
         return self
+
+    def step_blocks(self, max_bin):
+        """One step with individual time steps in power-of-two bins (the
+        NEXT scaling lever of Sec. 4, Table 2). From the synchronised state:
+        D and the bins from the per-particle criterion (block_bins); B = the
+        deepest bin; 2^B substeps of D / 2^B. In substep s a particle of bin
+        b with (s mod 2^(B-b)) == 0 gets its opening half kick of D / 2^(b+1),
+        every particle drifts D / 2^B, the forces are evaluated (neighbours,
+        density, EOS for all, with the current half-kicked velocities and
+        energies as in the global step) and the particles whose step ends,
+        ((s + 1) mod 2^(B-b)) == 0, take the new acceleration, du/dt and
+        max |mu| and their closing half kick. max_bin = 0 is the global
+        step. Returns (D, bins, substeps)."""
+        lo, hi, per = self.box
+        s, a = self.s, self.acc
+        dtc = timestep_each(s["h"], self.c, a["mumax"], a["ax"], a["ay"], a["az"],
+                            self.params, self.g)
+        D, b = block_bins(dtc, max_bin)
+        B = int(b.max())
+        dti = np.ldexp(D, -b)
+        delta = np.ldexp(D, -B)
+        g = self.g
+        L = np.asarray(hi, dtype=np.float64) - np.asarray(lo, dtype=np.float64)
+
+        def kick(mask):
+            a = self.acc
+            half = 0.5 * dti
+            for k, q in (("vx", "ax"), ("vy", "ay"), ("vz", "az")):
+                t = a[q].copy()
+                if g is not None:
+                    t = t + g[("ax", "ay", "az").index(q)]
+                s[k] = np.where(mask, s[k] + half * t, s[k])
+            s["u"] = np.where(mask, s["u"] + half * a["dudt"], s["u"])
+
+        for sub in range(2 ** B):
+            period = 2 ** (B - b)
+            kick(sub % period == 0)
+            for ax_, k, v in ((0, "x", "vx"), (1, "y", "vy"), (2, "z", "vz")):
+                p = s[k] + delta * s[v]
+                if per[ax_]:
+                    p = np.where(p >= hi[ax_], p - L[ax_], np.where(p < lo[ax_], p + L[ax_], p))
+                s[k] = p
+            old = self.acc
+            self.forces()
+            end = (sub + 1) % period == 0
+            self.acc = {k: np.where(end, self.acc[k], old[k]) for k in old}
+            kick(end)
+        self.t += D
+        self.steps += 1
+        self.dt = D
+        return D, b, 2 ** B
 
     def step(self):
         lo, hi, per = self.box

@@ -794,6 +794,23 @@ double orc_timestep(int64_t n, const double *h, const double *c,
     return dt;
 }
 
+/* The same criterion per particle (individual time steps): dtc[i] is the
+ * smaller of the Courant and force limits of particle i. */
+void orc_timestep_each(int64_t n, const double *h, const double *c, const double *mumax,
+                       const double *ax, const double *ay, const double *az,
+                       const double *gx, const double *gy, const double *gz, double alpha,
+                       double beta, double c_cfl, double c_force, double *dtc)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double d = c_cfl * h[i] / (c[i] + 1.2 * (alpha * c[i] + beta * mumax[i]));
+        double tx = ax[i], ty = ay[i], tz = az[i];
+        if (gx) { tx += gx[i]; ty += gy[i]; tz += gz[i]; }
+        double amag = sqrt(tx * tx + ty * ty + tz * tz);
+        if (amag > 0.0) d = fmin(d, c_force * sqrt(h[i] / amag));
+        dtc[i] = d;
+    }
+}
+
 /* ---------------------------------------------------------- integration */
 
 /*

@@ -771,3 +771,52 @@ def test_gravity_tree_accuracy_evrard():
         dx ** 2 + dy ** 2 + dz ** 2)
     assert np.median(e) < 5e-4 and np.percentile(e, 99) < 3e-3 and e.max() < 2e-2
     assert st["node_terms"] + st["direct_terms"] < 0.2 * ic.n * ic.n
+
+
+def _isolated(seed=0):
+    """27 particles 1.0 apart (no neighbours) with h spread over a factor 40,
+    ideal gas, in a uniform external field: each one's criterion, so its bin,
+    differs."""
+    rng = np.random.default_rng(seed)
+    i, j, k = np.meshgrid(np.arange(3), np.arange(3), np.arange(3), indexing="ij")
+    n = 27
+    P = np.stack([i.ravel(), j.ravel(), k.ravel()], 1).astype(float)
+    V = rng.uniform(-1, 1, (n, 3))
+    h = np.geomspace(0.005, 0.2, n)
+    rng.shuffle(h)
+    ic = I.SphIC(x=P[:, 0].copy(), y=P[:, 1].copy(), z=P[:, 2].copy(), vx=V[:, 0].copy(),
+                 vy=V[:, 1].copy(), vz=V[:, 2].copy(), u=np.full(n, 0.01), h=h,
+                 m=np.full(n, 1.0 / n), p_bg=np.zeros(n), id=np.arange(n, dtype=np.int32),
+                 lo=(-1.0, -1.0, -1.0), hi=(3.0, 3.0, 3.0), periodic=(0, 0, 0),
+                 params=I.SphParams(eos=1))
+    g = (np.zeros(n), np.full(n, 0.3), np.full(n, -1.0))
+    return ic, g
+
+
+def test_blocks_zero_is_the_global_step():
+    """Individual time steps with a single bin (max_bin = 0) are the global
+    kick-drift-kick step, bit for bit."""
+    ic = I.square_patch(12)
+    a = O.OracleRun(ic).init()
+    b = O.OracleRun(ic).init()
+    for _ in range(3):
+        a.step()
+        b.step_blocks(0)
+    for k in a.s:
+        assert np.array_equal(a.s[k], b.s[k]), k
+
+
+def test_blocks_isolated_particles_follow_the_closed_form():
+    """Particles without neighbours in a constant field move as
+    x0 + v0 D + g D^2 / 2 over the step D whatever their bins: each one gets
+    2^b kick-drift-kick steps of D / 2^b at the right substeps."""
+    ic, g = _isolated()
+    r = O.OracleRun(ic, g=g).init()
+    assert r.n_pairs == 0
+    x0 = {k: r.s[k].copy() for k in ("x", "y", "z", "vx", "vy", "vz")}
+    D, b, subs = r.step_blocks(4)
+    assert len(set(b.tolist())) >= 3 and subs == 2 ** int(b.max())
+    for q, (k, v) in enumerate((("x", "vx"), ("y", "vy"), ("z", "vz"))):
+        want = x0[k] + x0[v] * D + 0.5 * g[q] * D * D
+        assert np.allclose(r.s[k], want, rtol=0, atol=1e-14 * (1 + np.abs(want)).max())
+        assert np.allclose(r.s[v], x0[v] + g[q] * D, rtol=0, atol=1e-14)
