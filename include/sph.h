@@ -333,6 +333,32 @@ sph_status sph_step(sph_ctx ctx, const sph_particles *p, const sph_box *box,
                     const sph_fields *f, const sph_accel *a, double *dt_dev,
                     double *diag_dev);
 
+/* One step with individual time steps in power-of-two bins (Table 1 and
+ * Table 2: ChaNGa's multiple time-stepping; the paper's other scaling lever
+ * besides the global dt). Needs the forces at the current, synchronised
+ * state (sph_init_forces or a previous step: f->c, a->ax..a->mumax).
+ *   - each particle's criterion is the global one's (sph_timestep); with
+ *     its minimum and maximum, the step D = min(max, min 2^max_bin) goes to
+ *     dt_dev[0], and particle i gets the smallest bin b in [0, max_bin] with
+ *     D / 2^b <= its criterion (written to bin[i] as a double);
+ *   - with B the deepest bin, 2^B substeps of D / 2^B follow. In substep s
+ *     the particles of bin b with s mod 2^(B-b) == 0 take their opening half
+ *     kick of D / 2^(b+1), every particle drifts, cells, neighbours, density
+ *     and EOS are rebuilt for all (with the current, half-kicked velocities
+ *     and energies, as in sph_step), and the particles whose step closes,
+ *     (s + 1) mod 2^(B-b) == 0, get new a, du/dt and max |mu| and their
+ *     closing half kick;
+ *   - bin, ax, ay, az, dudt and mumax are reordered with the particles by
+ *     every cell sort; with generalised volume elements the weights are
+ *     formed from the previous density at every substep.
+ * max_bin = 0 is sph_step. *substeps (host) receives 2^B; diag_dev (if not
+ * NULL) the totals of the end state. Synchronises once (to read B).
+ * SPH_E_INVALID for max_bin outside [0, 16] or NULL arrays. */
+sph_status sph_step_blocks(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                           double h_max, const sph_nbrs *nb, const sph_params *prm,
+                           const sph_fields *f, const sph_accel *a, int32_t max_bin,
+                           double *bin, double *dt_dev, double *diag_dev, int32_t *substeps);
+
 /* Algorithm 1, step 2 ("find the neighbours and the smoothing length"); the
  * target neighbour count of Sec. 3. Iterates, for it = 0, 1, ..., max_iter:
  * build the cells for the current largest h (this reorders p as

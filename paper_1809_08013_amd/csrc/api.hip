@@ -220,7 +220,7 @@ void free_ctx(sph_ctx ctx)
                     ctx->scan_part, ctx->cell_start, ctx->cell_end, ctx->perm_tmp,
                     ctx->perm_tmp_id, ctx->red_part, ctx->status_dev, ctx->nb_mask, ctx->hflag_dev,
                     ctx->fb_tiles, ctx->fb_count, ctx->it_words, ctx->it_hmax, ctx->cell_s2max,
-                    ctx->iad_c,
+                    ctx->iad_c, ctx->dtc, ctx->blk_words,
                     ctx->srec, ctx->drec, ctx->prec};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -310,6 +310,8 @@ sph_status sph_ctx_create(sph_ctx *out, int64_t n_max, int32_t max_nb, sph_strea
     ALLOC(ctx->perm_tmp, (int64_t)kPermFields * n_max);
     ALLOC(ctx->perm_tmp_id, n_max);
     ALLOC(ctx->red_part, (int64_t)kRedFields * kRedMaxBlocks);
+    ALLOC(ctx->dtc, n_max);
+    ALLOC(ctx->blk_words, 2);
     ALLOC(ctx->status_dev, 1);
     ALLOC(ctx->hflag_dev, 1);
 #undef ALLOC
@@ -350,8 +352,13 @@ sph_status sph_ctx_check(sph_ctx ctx)
     return SPH_OK;
 }
 
-sph_status sph_build_cells(sph_ctx ctx, const sph_particles *p, const sph_box *box,
-                           double h_max)
+}  // extern "C"
+
+namespace {
+
+// sph_build_cells, with up to 6 extra per-particle arrays reordered alongside
+sph_status build_cells(sph_ctx ctx, const sph_particles *p, const sph_box *box, double h_max,
+                       double *const *extra, int n_extra)
 {
     if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
     sph_status s;
@@ -365,8 +372,18 @@ sph_status sph_build_cells(sph_ctx ctx, const sph_particles *p, const sph_box *b
     ctx->grid = make_grid(*box, h_max, ctx->cell_cap, kMaxAxisCells);
     ctx->n_built = p->n;
     if (p->n == 0) return SPH_OK;
-    SPH_HIP(ctx, launch_build_cells(ctx, *p, ctx->grid, h_max));
+    SPH_HIP(ctx, launch_build_cells(ctx, *p, ctx->grid, h_max, extra, n_extra));
     return SPH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sph_status sph_build_cells(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                           double h_max)
+{
+    return build_cells(ctx, p, box, h_max, nullptr, 0);
 }
 
 sph_status sph_find_neighbors(sph_ctx ctx, const sph_particles *p, const sph_box *box,
@@ -574,6 +591,55 @@ sph_status sph_step(sph_ctx ctx, const sph_particles *p, const sph_box *box, dou
     if ((s = sph_momentum_energy(ctx, p, box, nb, prm, f, a)) != SPH_OK) return s;
     if ((s = sph_integrate(ctx, p, box, SPH_KICK, dt_dev, a)) != SPH_OK) return s;
     return sph_timestep(ctx, p, prm, f, a, dt_dev, diag_dev);
+}
+
+sph_status sph_step_blocks(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                           double h_max, const sph_nbrs *nb, const sph_params *prm,
+                           const sph_fields *f, const sph_accel *a, int32_t max_bin,
+                           double *bin, double *dt_dev, double *diag_dev, int32_t *substeps)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    sph_status s;
+    if ((s = check_particles(ctx, p, true)) != SPH_OK) return s;
+    if ((s = check_box(ctx, box)) != SPH_OK) return s;
+    if ((s = check_nbrs(ctx, nb, p->n)) != SPH_OK) return s;
+    if ((s = check_params(ctx, prm)) != SPH_OK) return s;
+    if (max_bin < 0 || max_bin > 16)
+        return fail(ctx, SPH_E_INVALID, "max_bin %d outside [0, 16]", max_bin);
+    if (!f || !a || !dt_dev || !substeps)
+        return fail(ctx, SPH_E_INVALID, "fields, accel, dt_dev and substeps are required");
+    *substeps = 0;
+    if (p->n == 0) return SPH_OK;
+    if (!bin) return fail(ctx, SPH_E_INVALID, "bin is required");
+    if (!f->rho || !f->c || !a->ax || !a->ay || !a->az || !a->dudt || !a->mumax)
+        return fail(ctx, SPH_E_INVALID, "rho, c, ax, ay, az, dudt, mumax are required");
+    if (prm->volume == SPH_VOLUME_GENERALISED && !p->xw)
+        return fail(ctx, SPH_E_INVALID, "generalised volume elements need p->xw");
+    SPH_HIP(ctx, launch_block_bins(ctx, *p, *prm, *f, *a, max_bin, bin, dt_dev));
+    uint32_t words[2] = {0, 0};
+    SPH_HIP(ctx, hipMemcpyAsync(words, ctx->blk_words, sizeof words, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    SPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const int B = (int)words[0];
+    // the bins and the last accelerations travel with the particles through
+    // every cell sort
+    double *extra[6] = {bin, a->ax, a->ay, a->az, a->dudt, a->mumax};
+    for (int sub = 0; sub < (1 << B); ++sub) {
+        if (prm->volume == SPH_VOLUME_GENERALISED)
+            if ((s = sph_volume_weights(ctx, p, f->rho, prm->volume_p)) != SPH_OK) return s;
+        SPH_HIP(ctx, launch_kick_bins(ctx, *p, 0, sub, B, dt_dev, bin, *a));
+        SPH_HIP(ctx, launch_drift(ctx, *p, box_grid(*box), B, dt_dev));
+        if ((s = build_cells(ctx, p, box, h_max, extra, 6)) != SPH_OK) return s;
+        if ((s = sph_find_neighbors(ctx, p, box, nb)) != SPH_OK) return s;
+        if ((s = sph_density(ctx, p, box, nb, prm, f->rho)) != SPH_OK) return s;
+        if ((s = sph_eos(ctx, p, prm, f)) != SPH_OK) return s;
+        SPH_HIP(ctx, launch_momentum(ctx, *p, *nb, *prm, *f, *a, bin, sub, B));
+        SPH_HIP(ctx, launch_kick_bins(ctx, *p, 1, sub, B, dt_dev, bin, *a));
+    }
+    *substeps = 1 << B;
+    // totals of the synchronised end state (the criterion output goes to scratch)
+    SPH_HIP(ctx, launch_timestep(ctx, *p, *prm, *f, *a, ctx->dtc, diag_dev));
+    return SPH_OK;
 }
 
 sph_status sph_smoothing_length(sph_ctx ctx, sph_particles *p, const sph_box *box,

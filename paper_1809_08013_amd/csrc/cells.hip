@@ -449,7 +449,7 @@ hipError_t radix_sort_pairs(sph_ctx ctx, uint32_t *k[2], int32_t *v[2], int64_t 
 }
 
 hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g,
-                              double h_max)
+                              double h_max, double *const *extra, int n_extra)
 {
     const int64_t n = p.n;
     hipStream_t s = ctx->stream;
@@ -479,6 +479,7 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
     PermFields f{};
     double *fields[kPermFields] = {p.x, p.y, p.z, p.vx, p.vy, p.vz, p.u, p.h, p.m,
                                    p.rho_ref, p.p_bg, p.gx, p.gy, p.gz, p.xw};
+    for (int k = 0; k < n_extra && 15 + k < kPermFields; ++k) fields[15 + k] = extra[k];
     int h_field = -1;
     for (int k = 0; k < kPermFields; ++k) {
         if (!fields[k]) continue;

@@ -305,6 +305,148 @@ timestep_final_batch_kernel(BatchDev b, const double *__restrict__ part)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Individual time steps in power-of-two bins. The per-particle criterion is
+// the global one's (same operations), its min and max give the largest step
+// D = min(max, min 2^max_bin), and a particle's bin is the smallest b with
+// D / 2^b <= its criterion (exact: scaling by a power of two).
+__global__ void __launch_bounds__(256)
+block_criterion_kernel(int64_t n, const double *__restrict__ h, const double *__restrict__ c,
+                       const double *__restrict__ mumax, const double *__restrict__ ax,
+                       const double *__restrict__ ay, const double *__restrict__ az,
+                       const double *__restrict__ gx, const double *__restrict__ gy,
+                       const double *__restrict__ gz, double alpha, double beta, double c_cfl,
+                       double c_force, double *__restrict__ dtc, double *__restrict__ part)
+{
+    __shared__ double lo[256], hi[256];
+    double mn = INFINITY, mx = -INFINITY;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double hi_ = h[i], ci = c[i];
+        double d = c_cfl * hi_ / (ci + 1.2 * (alpha * ci + beta * mumax[i]));
+        double tx = ax[i], ty = ay[i], tz = az[i];
+        if (gx) {
+            tx += gx[i];
+            ty += gy[i];
+            tz += gz[i];
+        }
+        const double amag = sqrt(tx * tx + ty * ty + tz * tz);
+        if (amag > 0.0) d = fmin(d, c_force * sqrt(hi_ / amag));
+        dtc[i] = d;
+        mn = fmin(mn, d);
+        mx = fmax(mx, d);
+    }
+    lo[threadIdx.x] = mn;
+    hi[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            lo[threadIdx.x] = fmin(lo[threadIdx.x], lo[threadIdx.x + w]);
+            hi[threadIdx.x] = fmax(hi[threadIdx.x], hi[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = lo[0];
+        part[2 * blockIdx.x + 1] = hi[0];
+    }
+}
+
+// D from the block partials (one wave; min and max are exact in any order)
+__global__ void __launch_bounds__(64)
+block_step_kernel(int nblk, const double *__restrict__ part, int max_bin,
+                  double *__restrict__ dt_dev)
+{
+    double mn = INFINITY, mx = -INFINITY;
+    for (int b = threadIdx.x; b < nblk; b += 64) {
+        mn = fmin(mn, part[2 * b]);
+        mx = fmax(mx, part[2 * b + 1]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    if (threadIdx.x == 0) dt_dev[0] = fmin(mx, ldexp(mn, max_bin));
+}
+
+__global__ void __launch_bounds__(256)
+block_bins_kernel(int64_t n, const double *__restrict__ dtc, int max_bin,
+                  const double *__restrict__ dt_dev, double *__restrict__ bin,
+                  uint32_t *__restrict__ words)
+{
+    const double D = dt_dev[0];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = max_bin;
+    for (int k = max_bin; k >= 0; --k)
+        if (ldexp(D, -k) <= dtc[i]) b = k;
+    bin[i] = (double)b;
+    atomicMax(&words[0], (uint32_t)b);
+}
+
+__global__ void __launch_bounds__(64)
+clear_words2_kernel(uint32_t *__restrict__ w)
+{
+    if (threadIdx.x < 2) w[threadIdx.x] = 0u;
+}
+
+// Half kick of the particles of bin b whose step opens (stage 0: sub mod
+// 2^(B-b) == 0) or closes (stage 1: (sub + 1) mod 2^(B-b) == 0), with their
+// step D / 2^b; the same operations as the global kick.
+__global__ void __launch_bounds__(256)
+kick_bins_kernel(int64_t n, int stage, int sub, int B, const double *__restrict__ dt_dev,
+                 const double *__restrict__ bin, double *__restrict__ vx, double *__restrict__ vy,
+                 double *__restrict__ vz, double *__restrict__ u, const double *__restrict__ ax,
+                 const double *__restrict__ ay, const double *__restrict__ az,
+                 const double *__restrict__ dudt, const double *__restrict__ gx,
+                 const double *__restrict__ gy, const double *__restrict__ gz,
+                 uint32_t *status)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b = (int)bin[i];
+    const int mask = (1 << (B - b)) - 1;
+    if (((stage == 0 ? sub : sub + 1) & mask) != 0) return;
+    const double dt = ldexp(dt_dev[0], -b);
+    const double half = 0.5 * dt;
+    double tx = ax[i], ty = ay[i], tz = az[i];
+    if (gx) {
+        tx += gx[i];
+        ty += gy[i];
+        tz += gz[i];
+    }
+    const double nvx = vx[i] + half * tx;
+    const double nvy = vy[i] + half * ty;
+    const double nvz = vz[i] + half * tz;
+    const double nu = u[i] + half * dudt[i];
+    vx[i] = nvx;
+    vy[i] = nvy;
+    vz[i] = nvz;
+    u[i] = nu;
+    if (stage == 1 && !isfinite(nvx + nvy + nvz + nu)) atomicOr(status, ST_NONFINITE);
+}
+
+__global__ void __launch_bounds__(256)
+drift_kernel(int64_t n, int B, const double *__restrict__ dt_dev, Grid g,
+             double *__restrict__ x, double *__restrict__ y, double *__restrict__ z,
+             const double *__restrict__ vx, const double *__restrict__ vy,
+             const double *__restrict__ vz)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double dt = ldexp(dt_dev[0], -B);
+    double p[3] = {x[i] + dt * vx[i], y[i] + dt * vy[i], z[i] + dt * vz[i]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!g.periodic[a]) continue;
+        if (p[a] >= g.hi[a]) p[a] -= g.len[a];
+        else if (p[a] < g.lo[a]) p[a] += g.len[a];
+    }
+    x[i] = p[0];
+    y[i] = p[1];
+    z[i] = p[2];
+}
+
 __global__ void copy_kernel(int64_t n, double *__restrict__ dst, const double *__restrict__ src)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -339,6 +481,38 @@ hipError_t launch_timestep(sph_ctx ctx, const sph_particles &p, const sph_params
     }
     timestep_final_kernel<<<1, kRedThreads, 0, ctx->stream>>>((int)nb, ctx->red_part, dt_dev,
                                                               diag_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_bins(sph_ctx ctx, const sph_particles &p, const sph_params &prm,
+                             const sph_fields &f, const sph_accel &a, int max_bin, double *bin,
+                             double *dt_dev)
+{
+    const int nblk = (int)std::min<int64_t>(kRedMaxBlocks, (p.n + 255) / 256);
+    clear_words2_kernel<<<1, 64, 0, ctx->stream>>>(ctx->blk_words);
+    block_criterion_kernel<<<(unsigned)nblk, 256, 0, ctx->stream>>>(
+        p.n, p.h, f.c, a.mumax, a.ax, a.ay, a.az, p.gx, p.gy, p.gz, prm.alpha, prm.beta,
+        prm.c_cfl, prm.c_force, ctx->dtc, ctx->red_part);
+    block_step_kernel<<<1, 64, 0, ctx->stream>>>(nblk, ctx->red_part, max_bin, dt_dev);
+    block_bins_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
+        p.n, ctx->dtc, max_bin, dt_dev, bin, ctx->blk_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_bins(sph_ctx ctx, const sph_particles &p, int stage, int sub, int B,
+                            const double *dt_dev, const double *bin, const sph_accel &a)
+{
+    kick_bins_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
+        p.n, stage, sub, B, dt_dev, bin, p.vx, p.vy, p.vz, p.u, a.ax, a.ay, a.az, a.dudt, p.gx,
+        p.gy, p.gz, ctx->status_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_drift(sph_ctx ctx, const sph_particles &p, const Grid &g, int B,
+                        const double *dt_dev)
+{
+    drift_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, B, dt_dev, g, p.x, p.y, p.z,
+                                                                 p.vx, p.vy, p.vz);
     return hipGetLastError();
 }
 

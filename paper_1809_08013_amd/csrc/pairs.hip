@@ -404,6 +404,10 @@ struct MomParams {
     double sigma;  // W(0, h) h^3 of the kernel (KF != KF_M4)
     int sinc_n;
     const double *iad_c;  // IAD matrices (IAD instances), 6 per particle
+    // individual time steps (bin not null): only particles of bin b with
+    // ((sub + 1) mod 2^(B - b)) == 0 are evaluated and written
+    const double *bin;
+    int sub, B;
 };
 
 // IAD matrices (integral approach to derivatives, standard volume elements):
@@ -519,7 +523,15 @@ __device__ __forceinline__ void momentum_tile(
     MomParams prm = prm0;
     if constexpr (Multi) {
         const RunDev &r = b.runs[b.slot[ii]];
-        prm = MomParams{r.alpha, r.beta, r.eta2, 0.0, 0, nullptr};
+        prm = MomParams{r.alpha, r.beta, r.eta2, 0.0, 0, nullptr, nullptr, 0, 0};
+    }
+    // individual time steps: lanes whose particle's step does not close now
+    // write nothing; a wave without any such lane has nothing to do
+    bool closes = true;
+    if (!Multi && prm.bin) {
+        const int b = (int)prm.bin[ii];
+        closes = (((prm.sub + 1) & ((1 << (prm.B - b)) - 1)) == 0);
+        if (__ballot(active && closes) == 0ull) return;
     }
     const PairRec *mp = rec + ii;
     const double mex = mp->x, mey = mp->y, mez = mp->z;
@@ -672,7 +684,7 @@ __device__ __forceinline__ void momentum_tile(
             mum = fmax(mum, fabs(mu));
         }
     }
-    if (active) {
+    if (active && closes) {
         ax[i] = (double)sx;
         ay[i] = (double)sy;
         az[i] = (double)sz;
@@ -895,12 +907,14 @@ hipError_t launch_eos(sph_ctx ctx, const sph_particles &p, const sph_params &prm
 }
 
 hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
-                           const sph_params &prm, const sph_fields &f, const sph_accel &a)
+                           const sph_params &prm, const sph_fields &f, const sph_accel &a,
+                           const double *bin, int sub, int B)
 {
     const unsigned nblk = blocks_for(p.n, kThreads);
     const KernelSel ks = kernel_sel(prm);
     const bool iad = prm.gradient == SPH_GRAD_IAD;
-    const MomParams mp{prm.alpha, prm.beta, prm.eta2, ks.sigma, ks.sinc_n, ctx->iad_c};
+    const MomParams mp{prm.alpha, prm.beta, prm.eta2, ks.sigma, ks.sinc_n, ctx->iad_c, bin, sub,
+                       B};
     if (iad) {
         pack_vol_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, p.x, p.y, p.z, p.m,
                                                                        f.rho, ctx->drec);

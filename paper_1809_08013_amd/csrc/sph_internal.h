@@ -30,7 +30,7 @@ constexpr int kScanChunk = kScanThreads * kScanItems;  // elements per block
 constexpr int kRedThreads = 256;
 constexpr int kRedMaxBlocks = 2048;
 constexpr int kRedFields = 9;   // dt candidate min + 8 totals
-constexpr int kPermFields = 15; // x y z vx vy vz u h m rho_ref p_bg gx gy gz xw
+constexpr int kPermFields = 21; // x y z vx vy vz u h m rho_ref p_bg gx gy gz xw + 6 extra
 
 // Uniform cell grid of one build (host values, passed to kernels by value).
 struct Grid {
@@ -241,6 +241,11 @@ struct sph_ctx_s {
     double *gt_box = nullptr;        // lo[3], L
     double *gt_part = nullptr;       // bounding-box partials
 
+    // individual time steps: per-particle criterion, {min, max} partials,
+    // deepest bin
+    double *dtc = nullptr;
+    uint32_t *blk_words = nullptr;
+
     uint32_t *status_dev = nullptr;
     uint32_t *hflag_dev = nullptr;   // 0 after a build iff every particle has the same h
     std::string last_error;
@@ -251,8 +256,9 @@ namespace sph {
 
 // Launchers (defined in the .hip files); each returns hipSuccess or the
 // launch error.
+// extra: up to 6 more per-particle FP64 arrays reordered with the particles.
 hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g,
-                              double h_max);
+                              double h_max, double *const *extra = nullptr, int n_extra = 0);
 hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p,
                                  const sph_nbrs &nb);
 // The interpolation kernel of a pair call: family (SPH_KERNEL_*), sinc
@@ -286,15 +292,30 @@ hipError_t radix_sort_pairs(sph_ctx ctx, uint32_t *k[2], int32_t *v[2], int64_t 
                             int key_bits, int *cur);
 hipError_t launch_eos(sph_ctx ctx, const sph_particles &p, const sph_params &prm,
                       const sph_fields &f);
+// bin (not null): only the particles whose step closes at substep sub of
+// 2^B get new accelerations (individual time steps).
 hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
                            const sph_params &prm, const sph_fields &f,
-                           const sph_accel &a);
+                           const sph_accel &a, const double *bin = nullptr, int sub = 0,
+                           int B = 0);
 hipError_t launch_integrate(sph_ctx ctx, const sph_particles &p, const Grid &g,
                             int stage, const double *dt_dev, const sph_accel &a);
 hipError_t launch_timestep(sph_ctx ctx, const sph_particles &p,
                            const sph_params &prm, const sph_fields &f,
                            const sph_accel &a, double *dt_dev, double *diag_dev);
 hipError_t launch_copy(sph_ctx ctx, double *dst, const double *src, int64_t n);
+// Individual time steps: per-particle criterion, the largest step D into
+// dt_dev[0], the bins into bin (as doubles) and the deepest bin into
+// ctx->blk_words[0].
+hipError_t launch_block_bins(sph_ctx ctx, const sph_particles &p, const sph_params &prm,
+                             const sph_fields &f, const sph_accel &a, int max_bin, double *bin,
+                             double *dt_dev);
+// Half kicks of the particles whose step opens (stage 0) or closes (stage 1)
+// at substep sub of 2^B, and the drift of every particle by D / 2^B.
+hipError_t launch_kick_bins(sph_ctx ctx, const sph_particles &p, int stage, int sub, int B,
+                            const double *dt_dev, const double *bin, const sph_accel &a);
+hipError_t launch_drift(sph_ctx ctx, const sph_particles &p, const Grid &g, int B,
+                        const double *dt_dev);
 
 Grid make_grid(const sph_box &b, double h_max, int64_t cell_cap, int max_axis);
 

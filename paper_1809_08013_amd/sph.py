@@ -143,6 +143,8 @@ def load():
             "sph_init_forces": (C.c_int32, [_VP, P, B, C.c_double, N, M, F, A, C.c_int32,
                                             _VP, _VP]),
             "sph_step": (C.c_int32, [_VP, P, B, C.c_double, N, M, F, A, _VP, _VP]),
+            "sph_step_blocks": (C.c_int32, [_VP, P, B, C.c_double, N, M, F, A, C.c_int32, _VP,
+                                            _VP, _VP, C.POINTER(C.c_int32)]),
             "sph_export_neighbors": (C.c_int32, [_VP, P, N, _VP, _VP, C.c_int64,
                                                  C.POINTER(C.c_int64)]),
             "sph_smoothing_length": (C.c_int32, [_VP, P, B, C.c_double, C.c_int32, C.c_int32,
@@ -398,6 +400,22 @@ def sph_step(ctx: Context, st: SphState, prm: Params, h_max: float | None = None
         float(h_max if h_max is not None else st.h_max), C.byref(st.nbrs), C.byref(prm),
         C.byref(st.fields), C.byref(st.accel), _ptr(st.t["dt"]),
         _ptr(st.t["diag"]) if diag else None))
+
+
+def sph_step_blocks(ctx: Context, st: SphState, prm: Params, max_bin: int,
+                    h_max: float | None = None, diag: bool = True) -> int:
+    """One step with individual time steps (bins in st.t["bin"], created on
+    first use); st.t["dt"] receives the step D. Returns the substep count."""
+    import torch
+    if "bin" not in st.t:
+        st.t["bin"] = torch.zeros(max(st.n, 1), dtype=torch.float64, device=st.device)
+    subs = C.c_int32(0)
+    ctx.raise_on(ctx.lib.sph_step_blocks(
+        ctx.h, C.byref(st.particles), C.byref(st.box),
+        float(h_max if h_max is not None else st.h_max), C.byref(st.nbrs), C.byref(prm),
+        C.byref(st.fields), C.byref(st.accel), int(max_bin), _ptr(st.t["bin"]),
+        _ptr(st.t["dt"]), _ptr(st.t["diag"]) if diag else None, C.byref(subs)))
+    return int(subs.value)
 
 
 def sph_smoothing_length(ctx: Context, st: SphState, n_target: float = 100.0,

@@ -133,3 +133,5 @@ def test_smoothing_length_host_checks():
     it = C.c_int32(0)
     assert L.sph_smoothing_length(None, None, None, 100.0, 95, 105, 10, None,
                                   C.byref(it)) == S.SPH_E_INVALID
+    assert L.sph_step_blocks(None, None, None, 1.0, None, None, None, None, 2, None, None,
+                             None, C.byref(it)) == S.SPH_E_INVALID

@@ -510,3 +510,66 @@ def test_gravity_tree(name, theta):
     rel = float(np.max(err / sc))
     print(name, theta, "tree max err / scale", rel, st, flush=True)
     assert rel <= 1e-12
+
+
+def test_blocks_zero_is_sph_step():
+    """sph_step_blocks with max_bin = 0 is sph_step, bit for bit, over 3 steps."""
+    ic = I.square_patch(12)
+    prm = S.make_params(ic.params)
+    out = []
+    for blocks in (False, True):
+        ctx = S.Context(ic.n, 128)
+        st = S.SphState(ic, 128)
+        S.sph_init_forces(ctx, st, prm, set_rho_ref=True)
+        for _ in range(3):
+            if blocks:
+                assert S.sph_step_blocks(ctx, st, prm, 0) == 1
+            else:
+                S.sph_step(ctx, st, prm)
+        S.sph_ctx_check(ctx)
+        out.append(st.host(["x", "y", "z", "vx", "vy", "vz", "u", "rho"]))
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
+def _blocks_case(name):
+    if name == "isolated":
+        import importlib
+        pins = importlib.import_module("test_oracle_pins")
+        ic, g = pins._isolated()
+        return ic, g, 4, 16
+    if name == "square_patch_c0":
+        return I.square_patch(20), None, 3, 128
+    ic = I.evrard(20000, seed=3)
+    ic.h, _, _ = O.smoothing_length(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi, ic.periodic)
+    g = O.gravity_direct(ic.x, ic.y, ic.z, ic.m, 0.01)
+    return ic, g, 5, 256
+
+
+@pytest.mark.parametrize("name", ["isolated", "square_patch_c0", "evrard_iter"])
+def test_blocks_against_oracle(name):
+    """Individual time steps (sph_step_blocks) against the oracle's: the step
+    D, every particle's bin and, after two steps, the state."""
+    ic, g, max_bin, max_nb = _blocks_case(name)
+    print(f"case blocks {name} n={ic.n} max_bin={max_bin}", flush=True)
+    ref = O.OracleRun(ic, g=g).init()
+    ctx = S.Context(ic.n, max_nb)
+    st = S.SphState(ic, max_nb, g=g)
+    prm = S.make_params(ic.params)
+    S.sph_init_forces(ctx, st, prm, set_rho_ref=True)
+    for k in range(2):
+        subs = S.sph_step_blocks(ctx, st, prm, max_bin)
+        D, b, rsubs = ref.step_blocks(max_bin)
+        S.sph_ctx_check(ctx)
+        got_bin = st.host(["bin"])["bin"]
+        print(name, "step", k, "D", D, st.dt, "substeps", subs, rsubs, flush=True)
+        assert subs == rsubs and abs(st.dt - D) <= 1e-14 * D
+        assert np.array_equal(got_bin.astype(np.int64), b)
+    got = st.host(["x", "y", "z", "vx", "vy", "vz", "u"])
+    err = {k: float(np.max(np.abs(got[k] - ref.s[k]))) for k in got}
+    scale = {k: float(np.max(np.abs(ref.s[k]))) + 1e-300 for k in got}
+    print(name, "blocks max errors", err, flush=True)
+    for k in ("x", "y", "z"):
+        assert err[k] <= 1e-12 * max(1.0, scale[k])
+    for k in ("vx", "vy", "vz", "u"):
+        assert err[k] <= 1e-10 * max(1.0, scale[k])
