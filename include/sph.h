@@ -343,17 +343,20 @@ sph_status sph_step(sph_ctx ctx, const sph_particles *p, const sph_box *box,
  *     D / 2^b <= its criterion (written to bin[i] as a double);
  *   - with B the deepest bin, 2^B substeps of D / 2^B follow. In substep s
  *     the particles of bin b with s mod 2^(B-b) == 0 take their opening half
- *     kick of D / 2^(b+1), every particle drifts, cells, neighbours, density
- *     and EOS are rebuilt for all (with the current, half-kicked velocities
- *     and energies, as in sph_step), and the particles whose step closes,
- *     (s + 1) mod 2^(B-b) == 0, get new a, du/dt and max |mu| and their
- *     closing half kick;
- *   - bin, ax, ay, az, dudt and mumax are reordered with the particles by
- *     every cell sort; with generalised volume elements the weights are
- *     formed from the previous density at every substep.
+ *     kick of D / 2^(b+1), every particle drifts and the cells are rebuilt;
+ *     the particles whose step closes, (s + 1) mod 2^(B-b) == 0, get new
+ *     neighbour lists, density, EOS values, a, du/dt and max |mu| (with the
+ *     current, half-kicked velocities and energies, as in sph_step) and
+ *     their closing half kick; the others keep the density, pressure and
+ *     sound speed of their last evaluation (no prediction), and tiles
+ *     without a closing particle are skipped by every pair kernel;
+ *   - bin, ax, ay, az, dudt, mumax and f->rho, p, c, pr2 are reordered with
+ *     the particles by every cell sort; with generalised volume elements the
+ *     weights are formed from the current density at every substep.
  * max_bin = 0 is sph_step. *substeps (host) receives 2^B; diag_dev (if not
  * NULL) the totals of the end state. Synchronises once (to read B).
- * SPH_E_INVALID for max_bin outside [0, 16] or NULL arrays. */
+ * SPH_E_INVALID for max_bin outside [0, 16], NULL arrays or IAD gradients
+ * (their matrices would need every neighbour's list). */
 sph_status sph_step_blocks(sph_ctx ctx, const sph_particles *p, const sph_box *box,
                            double h_max, const sph_nbrs *nb, const sph_params *prm,
                            const sph_fields *f, const sph_accel *a, int32_t max_bin,

@@ -440,16 +440,19 @@ class OracleRun:
 
     def step_blocks(self, max_bin):
         """One step with individual time steps in power-of-two bins (the
-        NEXT scaling lever of Sec. 4, Table 2). From the synchronised state:
-        D and the bins from the per-particle criterion (block_bins); B = the
-        deepest bin; 2^B substeps of D / 2^B. In substep s a particle of bin
-        b with (s mod 2^(B-b)) == 0 gets its opening half kick of D / 2^(b+1),
-        every particle drifts D / 2^B, the forces are evaluated (neighbours,
-        density, EOS for all, with the current half-kicked velocities and
-        energies as in the global step) and the particles whose step ends,
-        ((s + 1) mod 2^(B-b)) == 0, take the new acceleration, du/dt and
-        max |mu| and their closing half kick. max_bin = 0 is the global
-        step. Returns (D, bins, substeps)."""
+        scaling lever named next to the global dt in Table 1 and Table 2).
+        From the synchronised state: D and the bins from the per-particle
+        criterion (block_bins); B = the deepest bin; 2^B substeps of D / 2^B.
+        In substep s a particle of bin b with (s mod 2^(B-b)) == 0 gets its
+        opening half kick of D / 2^(b+1), every particle drifts D / 2^B, and
+        the particles whose step ends, ((s + 1) mod 2^(B-b)) == 0, are
+        evaluated: neighbours, density and EOS for them (the others keep the
+        density, pressure and sound speed of their last evaluation), then
+        acceleration, du/dt and max |mu| with the current half-kicked
+        velocities, as in the global step, and their closing half kick.
+        max_bin = 0 is the global step. IAD is not supported here (its
+        matrices would need every neighbour's list). Returns (D, bins,
+        substeps)."""
         lo, hi, per = self.box
         s, a = self.s, self.acc
         dtc = timestep_each(s["h"], self.c, a["mumax"], a["ax"], a["ay"], a["az"],
@@ -471,6 +474,7 @@ class OracleRun:
                 s[k] = np.where(mask, s[k] + half * t, s[k])
             s["u"] = np.where(mask, s["u"] + half * a["dudt"], s["u"])
 
+        prm = self.params
         for sub in range(2 ** B):
             period = 2 ** (B - b)
             kick(sub % period == 0)
@@ -479,10 +483,22 @@ class OracleRun:
                 if per[ax_]:
                     p = np.where(p >= hi[ax_], p - L[ax_], np.where(p < lo[ax_], p + L[ax_], p))
                 s[k] = p
-            old = self.acc
-            self.forces()
             end = (sub + 1) % period == 0
-            self.acc = {k: np.where(end, self.acc[k], old[k]) for k in old}
+            off, ids = neighbors(s["x"], s["y"], s["z"], s["h"], lo, hi, per)
+            self.off, self.ids = off, ids
+            X = None
+            if getattr(prm, "volume", 0) == 1:
+                X = volume_weights(s["m"], self.rho, prm.volume_p)
+            rho = density(s["x"], s["y"], s["z"], s["h"], s["m"], lo, hi, per, off, ids, X=X)
+            self.rho = np.where(end, rho, self.rho)
+            pn, cn, pr2n = eos(prm, self.rho, s["u"], self.rho_ref, s["p_bg"])
+            self.p = np.where(end, pn, self.p)
+            self.c = np.where(end, cn, self.c)
+            self.pr2 = np.where(end, pr2n, self.pr2)
+            acc = momentum_energy(s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"],
+                                  s["h"], s["m"], self.rho, self.c, self.pr2, lo, hi, per,
+                                  off, ids, prm, X=X)
+            self.acc = {k: np.where(end, acc[k], self.acc[k]) for k in self.acc}
             kick(end)
         self.t += D
         self.steps += 1

@@ -615,24 +615,33 @@ sph_status sph_step_blocks(sph_ctx ctx, const sph_particles *p, const sph_box *b
         return fail(ctx, SPH_E_INVALID, "rho, c, ax, ay, az, dudt, mumax are required");
     if (prm->volume == SPH_VOLUME_GENERALISED && !p->xw)
         return fail(ctx, SPH_E_INVALID, "generalised volume elements need p->xw");
+    if (prm->gradient == SPH_GRAD_IAD)
+        return fail(ctx, SPH_E_INVALID, "individual time steps do not support IAD");
+    if (!f->p || !f->pr2) return fail(ctx, SPH_E_INVALID, "p and pr2 are required");
+    if (prm->eos == SPH_EOS_TAIT && (!p->rho_ref || !p->p_bg))
+        return fail(ctx, SPH_E_INVALID, "the Tait EOS needs rho_ref and p_bg");
     SPH_HIP(ctx, launch_block_bins(ctx, *p, *prm, *f, *a, max_bin, bin, dt_dev));
     uint32_t words[2] = {0, 0};
     SPH_HIP(ctx, hipMemcpyAsync(words, ctx->blk_words, sizeof words, hipMemcpyDeviceToHost,
                                 ctx->stream));
     SPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const int B = (int)words[0];
-    // the bins and the last accelerations travel with the particles through
-    // every cell sort
-    double *extra[6] = {bin, a->ax, a->ay, a->az, a->dudt, a->mumax};
+    // the bins, the last accelerations and the last density, pressure and
+    // sound speed travel with the particles through every cell sort
+    double *extra[10] = {bin, a->ax, a->ay, a->az, a->dudt, a->mumax,
+                         f->rho, f->p, f->c, f->pr2};
+    const bool gve = prm->volume == SPH_VOLUME_GENERALISED;
+    const KernelSel ks = kernel_sel(*prm);
     for (int sub = 0; sub < (1 << B); ++sub) {
-        if (prm->volume == SPH_VOLUME_GENERALISED)
-            if ((s = sph_volume_weights(ctx, p, f->rho, prm->volume_p)) != SPH_OK) return s;
+        const StepMask mask{bin, sub, B};
+        if (gve) SPH_HIP(ctx, launch_volume_weights(ctx, *p, f->rho, prm->volume_p));
         SPH_HIP(ctx, launch_kick_bins(ctx, *p, 0, sub, B, dt_dev, bin, *a));
         SPH_HIP(ctx, launch_drift(ctx, *p, box_grid(*box), B, dt_dev));
-        if ((s = build_cells(ctx, p, box, h_max, extra, 6)) != SPH_OK) return s;
-        if ((s = sph_find_neighbors(ctx, p, box, nb)) != SPH_OK) return s;
-        if ((s = sph_density(ctx, p, box, nb, prm, f->rho)) != SPH_OK) return s;
-        if ((s = sph_eos(ctx, p, prm, f)) != SPH_OK) return s;
+        if ((s = build_cells(ctx, p, box, h_max, extra, 10)) != SPH_OK) return s;
+        // lists, density and EOS only where a step closes; the others keep theirs
+        SPH_HIP(ctx, launch_find_neighbors(ctx, *p, *nb, mask));
+        SPH_HIP(ctx, launch_density(ctx, *p, *nb, prm->precision, ks, gve, f->rho, mask));
+        SPH_HIP(ctx, launch_eos(ctx, *p, *prm, *f, mask));
         SPH_HIP(ctx, launch_momentum(ctx, *p, *nb, *prm, *f, *a, bin, sub, B));
         SPH_HIP(ctx, launch_kick_bins(ctx, *p, 1, sub, B, dt_dev, bin, *a));
     }

@@ -256,13 +256,16 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
                                              const int32_t *__restrict__ idx, int max_nb,
                                              const Grid &g, double *__restrict__ rho,
                                              const BatchDev &b, char *buf, double sigma,
-                                             int sinc_n)
+                                             int sinc_n, const StepMask &mask)
 {
     using R = typename std::conditional<F32, float, double>::type;
     const int lane = threadIdx.x & 63;
     const int64_t i = tile * kThreads + threadIdx.x;
     const bool active = i < n;
     const int64_t ii = active ? i : 0;
+    // individual time steps: only particles whose step closes are evaluated
+    const bool closes = Multi || step_closes(mask, ii);
+    if (!Multi && mask.bin && __ballot(active && closes) == 0ull) return;
     const Img im = lane_img<Multi>(g, b, ii);
     const DensRec me = drec[ii];
     const R inv_h = R(1) / (R)h[ii];
@@ -307,7 +310,7 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
         }
     }
     const R sg = KF == KF_M4 ? (R)kInvPi : (R)sigma;
-    if (active) rho[i] = (double)(sum * (sg * inv_h * inv_h * inv_h));
+    if (active && closes) rho[i] = (double)(sum * (sg * inv_h * inv_h * inv_h));
 }
 
 template <bool F32, bool Multi, bool Big, int Per, int KF>
@@ -315,7 +318,7 @@ __global__ void __launch_bounds__(kThreads)
 density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
                const double *__restrict__ h, const int32_t *__restrict__ count,
                const int32_t *__restrict__ idx, int max_nb, Grid g, double *__restrict__ rho,
-               BatchDev b, double sigma, int sinc_n)
+               BatchDev b, double sigma, int sinc_n, StepMask mask)
 {
     __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kDensStride];
     char *buf = lds[threadIdx.x >> 6];
@@ -324,10 +327,10 @@ density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
         const int64_t ntile = (nn + kThreads - 1) / kThreads;
         for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
             density_tile<F32, true, Big, -1, KF>(t, nn, ld, drec, h, count, idx, max_nb, g, rho,
-                                                 b, buf, sigma, sinc_n);
+                                                 b, buf, sigma, sinc_n, mask);
     } else {
         density_tile<F32, false, Big, Per, KF>(xcd_cu_block(), n, ld, drec, h, count, idx,
-                                               max_nb, g, rho, b, buf, sigma, sinc_n);
+                                               max_nb, g, rho, b, buf, sigma, sinc_n, mask);
     }
 }
 
@@ -358,11 +361,11 @@ volume_weights_kernel(int64_t n, const double *__restrict__ m, const double *__r
 
 __global__ void __launch_bounds__(256)
 gve_density_kernel(int64_t n, const double *__restrict__ m, const double *__restrict__ xw,
-                   double *__restrict__ rho)
+                   double *__restrict__ rho, StepMask mask)
 {
     const int64_t step = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step)
-        rho[i] = rho[i] * (m[i] / xw[i]);
+        if (step_closes(mask, i)) rho[i] = rho[i] * (m[i] / xw[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -371,10 +374,11 @@ __global__ void __launch_bounds__(256)
 eos_kernel(int64_t n, int eos, double rho0, double c0, double gamma_tait,
            double gamma_gas, const double *__restrict__ rho, const double *__restrict__ u,
            const double *__restrict__ rho_ref, const double *__restrict__ p_bg,
-           double *__restrict__ p, double *__restrict__ c, double *__restrict__ pr2)
+           double *__restrict__ p, double *__restrict__ c, double *__restrict__ pr2,
+           StepMask mask)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || !step_closes(mask, i)) return;
     const double r = rho[i];
     double P, C;
     if (eos == SPH_EOS_TAIT) {
@@ -796,11 +800,11 @@ template <bool Multi>
 void density_launch(hipStream_t st, unsigned blocks, int precision, bool big, int64_t n,
                     int64_t ld, const DensRec *drec, const double *h, const int32_t *count,
                     const int32_t *idx, int max_nb, const Grid &g, double *rho, const BatchDev &b,
-                    const KernelSel &ks)
+                    const KernelSel &ks, const StepMask &mask = StepMask{})
 {
 #define SPH_DENS_P(F, B, P, K)                                                             \
     density_kernel<F, Multi, B, P, K><<<blocks, kThreads, 0, st>>>(                        \
-        n, ld, drec, h, count, idx, max_nb, g, rho, b, ks.sigma, ks.sinc_n)
+        n, ld, drec, h, count, idx, max_nb, g, rho, b, ks.sigma, ks.sinc_n, mask)
 #define SPH_DENS(F, B)                                                                     \
     do {                                                                                   \
         const int pm = Multi ? -1 : per_mask(g);                                           \
@@ -874,7 +878,8 @@ void momentum_launch(hipStream_t st, unsigned blocks, int precision, bool big, i
 }  // namespace
 
 hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
-                          int precision, const KernelSel &ks, bool gve, double *rho)
+                          int precision, const KernelSel &ks, bool gve, double *rho,
+                          const StepMask &mask)
 {
     const unsigned nblk = blocks_for(p.n, kThreads);
     // generalised volume elements: the records carry X in place of m, the
@@ -883,9 +888,10 @@ hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &n
         p.n, nullptr, p.x, p.y, p.z, gve ? p.xw : p.m, ctx->drec);
     density_launch<false>(ctx->stream, nblk, precision, big_records(p.n, sizeof(DensRec)), p.n,
                           p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho,
-                          BatchDev{}, ks);
+                          BatchDev{}, ks, mask);
     if (gve)
-        gve_density_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, p.m, p.xw, rho);
+        gve_density_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, p.m, p.xw, rho,
+                                                                          mask);
     return hipGetLastError();
 }
 
@@ -898,11 +904,11 @@ hipError_t launch_volume_weights(sph_ctx ctx, const sph_particles &p, const doub
 }
 
 hipError_t launch_eos(sph_ctx ctx, const sph_particles &p, const sph_params &prm,
-                      const sph_fields &f)
+                      const sph_fields &f, const StepMask &mask)
 {
     eos_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
         p.n, prm.eos, prm.rho0, prm.c0, prm.gamma_tait, prm.gamma_gas, f.rho, p.u, p.rho_ref,
-        p.p_bg, f.p, f.c, f.pr2);
+        p.p_bg, f.p, f.c, f.pr2, mask);
     return hipGetLastError();
 }
 

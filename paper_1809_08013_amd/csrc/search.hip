@@ -772,7 +772,7 @@ find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
                       int32_t *__restrict__ count, int32_t *__restrict__ idx,
                       uint32_t *__restrict__ mask_scratch, const uint32_t *__restrict__ hflag,
                       uint32_t *status, BatchDev b, int32_t *__restrict__ fb_tiles,
-                      uint32_t *fb_count)
+                      uint32_t *fb_count, StepMask mask)
 {
     __shared__ SearchLds lds[kWavesPerBlock];
     const int w = threadIdx.x / kWave;
@@ -782,6 +782,12 @@ find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
     // the four waves of a block work on consecutive tiles, independently
     for (int64_t tile = xcd_block() * kWavesPerBlock + w; tile < ntile;
          tile += (int64_t)gridDim.x * kWavesPerBlock) {
+        if (!Multi && mask.bin) {
+            // individual time steps: only tiles holding a particle whose step
+            // closes need lists (the others keep their stale ones, unread)
+            const int64_t i = tile * kWave + (threadIdx.x & (kWave - 1));
+            if (__ballot(i < nn && step_closes(mask, i)) == 0ull) break;
+        }
         search_tile<Multi>(tile, nn, ld, srec, keys, cstart, cend, g, max_nb, count, idx,
                            mask_scratch, hflag, status, b, L, fb_tiles, fb_count);
         wave_sync();
@@ -887,7 +893,8 @@ __global__ void clear_words_kernel(uint32_t *a, int k)
 
 }  // namespace
 
-hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb)
+hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
+                                 const StepMask &mask)
 {
     const int64_t tiles = (p.n + kWave - 1) / kWave;
     const unsigned blocks = (unsigned)((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -895,7 +902,7 @@ hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_
     find_neighbors_kernel<false><<<blocks, kBlock, 0, ctx->stream>>>(
         p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
         nb.max_nb, nb.count, nb.idx, ctx->nb_mask, ctx->hflag_dev, ctx->status_dev, BatchDev{},
-        ctx->fb_tiles, ctx->fb_count);
+        ctx->fb_tiles, ctx->fb_count, mask);
     const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, 2048);
     fallback_kernel<false><<<fblocks, kWave, 0, ctx->stream>>>(
         p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
@@ -915,7 +922,8 @@ hipError_t launch_find_neighbors_batch(sph_ctx ctx, const BatchDev &b, int max_n
     clear_count_kernel<<<1, 1, 0, ctx->stream>>>(ctx->fb_count);
     find_neighbors_kernel<true><<<blocks, kBlock, 0, ctx->stream>>>(
         0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,
-        count, idx, ctx->nb_mask, nullptr, nullptr, b, ctx->fb_tiles, ctx->fb_count);
+        count, idx, ctx->nb_mask, nullptr, nullptr, b, ctx->fb_tiles, ctx->fb_count,
+        StepMask{});
     const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, 2048);
     fallback_kernel<true><<<fblocks, kWave, 0, ctx->stream>>>(
         0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,

@@ -30,7 +30,7 @@ constexpr int kScanChunk = kScanThreads * kScanItems;  // elements per block
 constexpr int kRedThreads = 256;
 constexpr int kRedMaxBlocks = 2048;
 constexpr int kRedFields = 9;   // dt candidate min + 8 totals
-constexpr int kPermFields = 21; // x y z vx vy vz u h m rho_ref p_bg gx gy gz xw + 6 extra
+constexpr int kPermFields = 25; // x y z vx vy vz u h m rho_ref p_bg gx gy gz xw + 10 extra
 
 // Uniform cell grid of one build (host values, passed to kernels by value).
 struct Grid {
@@ -156,6 +156,20 @@ struct __attribute__((aligned(128))) GNode {
 };
 static_assert(sizeof(GNode) == 128, "GNode is one cache line");
 
+// Individual time steps: with bin set, a call works only on the particles
+// of bin b whose step closes at substep sub of 2^B, ((sub + 1) mod 2^(B-b))
+// == 0; the others are left as they are.
+struct StepMask {
+    const double *bin = nullptr;
+    int sub = 0, B = 0;
+};
+__device__ __forceinline__ bool step_closes(const StepMask &m, int64_t i)
+{
+    if (!m.bin) return true;
+    const int b = (int)m.bin[i];
+    return ((m.sub + 1) & ((1 << (m.B - b)) - 1)) == 0;
+}
+
 // Block index remapped so that each XCD runs one contiguous range of blocks.
 // Blocks are dispatched to the 8 XCDs round-robin (block b to XCD b % 8);
 // giving XCD x the x-th contiguous slice keeps a Morton-contiguous region of
@@ -256,11 +270,11 @@ namespace sph {
 
 // Launchers (defined in the .hip files); each returns hipSuccess or the
 // launch error.
-// extra: up to 6 more per-particle FP64 arrays reordered with the particles.
+// extra: up to 10 more per-particle FP64 arrays reordered with the particles.
 hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g,
                               double h_max, double *const *extra = nullptr, int n_extra = 0);
 hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p,
-                                 const sph_nbrs &nb);
+                                 const sph_nbrs &nb, const StepMask &mask = StepMask{});
 // The interpolation kernel of a pair call: family (SPH_KERNEL_*), sinc
 // exponent, and sigma = W(0, h) h^3.
 struct KernelSel {
@@ -272,7 +286,8 @@ KernelSel kernel_sel(const sph_params &prm);
 
 // gve: generalised volume elements with the weights p.xw.
 hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
-                          int precision, const KernelSel &ks, bool gve, double *rho);
+                          int precision, const KernelSel &ks, bool gve, double *rho,
+                          const StepMask &mask = StepMask{});
 hipError_t launch_volume_weights(sph_ctx ctx, const sph_particles &p, const double *rho,
                                  double exponent);
 hipError_t launch_gravity_direct(sph_ctx ctx, const sph_particles &p, double eps, double *gx,
@@ -291,7 +306,7 @@ hipError_t launch_gravity_tree(sph_ctx ctx, const sph_particles &p, double eps, 
 hipError_t radix_sort_pairs(sph_ctx ctx, uint32_t *k[2], int32_t *v[2], int64_t n,
                             int key_bits, int *cur);
 hipError_t launch_eos(sph_ctx ctx, const sph_particles &p, const sph_params &prm,
-                      const sph_fields &f);
+                      const sph_fields &f, const StepMask &mask = StepMask{});
 // bin (not null): only the particles whose step closes at substep sub of
 // 2^B get new accelerations (individual time steps).
 hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &nb,
