@@ -254,8 +254,11 @@ def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
     time is reported) and held fixed as an external acceleration over the
     timed hydro steps: gravity is outside the timed path. The octree gravity
     (sph_gravity_tree, theta = 0.5, leaves of 16) is timed on the same state
-    and checked against the direct sum, and a third run recomputes it inside
-    every step (the Evrard collapse with self-gravity, Alg. 1 step 4).
+    and checked against the direct sum, a third run takes individual time
+    steps (sph_step_blocks, max_bin = 5) with the fixed field and reports the
+    simulated time per second against the global step's, and a fourth
+    recomputes the octree gravity inside every step (the Evrard collapse with
+    self-gravity, Alg. 1 step 4).
     """
     import numpy as np
     import torch
