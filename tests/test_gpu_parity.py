@@ -487,11 +487,19 @@ def _tree_case(name):
         return ic, 0.0
     if name == "two_groups":
         return I.random_cloud(65, seed=12, h_min=0.05, h_max=0.08, periodic=(0, 0, 0)), 0.02
+    if name == "clump":
+        # 300 particles inside one finest-level cell (a leaf of more than 64,
+        # cut into runs of 64) next to a sparse cloud
+        ic = I.random_cloud(700, seed=14, h_min=0.05, h_max=0.08, periodic=(0, 0, 0))
+        rng = np.random.default_rng(15)
+        for a in ("x", "y", "z"):
+            getattr(ic, a)[:300] = 0.5 + 1e-7 * rng.random(300)
+        return ic, 0.01
     return I.random_cloud(7, seed=13, h_min=0.05, h_max=0.08, periodic=(0, 0, 0)), 0.02
 
 
 @pytest.mark.parametrize("theta", [0.5, 0.8])
-@pytest.mark.parametrize("name", ["evrard_20k", "cloud_eps0", "two_groups", "ragged"])
+@pytest.mark.parametrize("name", ["evrard_20k", "cloud_eps0", "two_groups", "ragged", "clump"])
 def test_gravity_tree(name, theta):
     """Octree gravity (sph_gravity_tree) against the oracle's octree with the
     same keys, nodes, moments and acceptance test: every particle within
@@ -540,13 +548,19 @@ def _blocks_case(name):
         return ic, g, 4, 16
     if name == "square_patch_c0":
         return I.square_patch(20), None, 3, 128
+    if name == "square_patch_gve":
+        import dataclasses
+        ic = I.square_patch(20)
+        ic.params = dataclasses.replace(ic.params, volume=S.SPH_VOLUME_GENERALISED)
+        return ic, None, 3, 128
     ic = I.evrard(20000, seed=3)
     ic.h, _, _ = O.smoothing_length(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi, ic.periodic)
     g = O.gravity_direct(ic.x, ic.y, ic.z, ic.m, 0.01)
     return ic, g, 5, 256
 
 
-@pytest.mark.parametrize("name", ["isolated", "square_patch_c0", "evrard_iter"])
+@pytest.mark.parametrize("name", ["isolated", "square_patch_c0", "square_patch_gve",
+                                  "evrard_iter"])
 def test_blocks_against_oracle(name):
     """Individual time steps (sph_step_blocks) against the oracle's: the step
     D, every particle's bin and, after two steps, the state."""
