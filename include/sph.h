@@ -263,7 +263,7 @@ sph_status sph_momentum_energy(sph_ctx ctx, const sph_particles *p,
  * Reads p->x, y, z, m, id (device, n, current order; id must be a
  * permutation of 0..n-1) and writes gx, gy, gz (device, n doubles each,
  * caller-owned, same order). The first call on a context allocates the
- * tree's buffers (about 100 bytes per particle of n_max plus 128 MiB of
+ * tree's buffers (about 100 bytes per particle of n_max plus 160 MiB of
  * traversal stacks), kept until sph_ctx_destroy; SPH_E_NOMEM if that fails.
  * Synchronises ctx's stream. SPH_E_INVALID for NULL arrays, eps < 0,
  * theta <= 0 or a non-finite value, leaf_size outside [8, 64];

@@ -37,8 +37,8 @@
 // Tree build and moments use plain FP64 operations in the order of their
 // definition (no fused multiply-add; correctly rounded division and square
 // root), so the tree and every acceptance decision are the definition's; the
-// terms take 1/sqrt from the hardware estimate refined by two Newton steps
-// (about one ulp).
+// terms use fused multiply-adds and take 1/sqrt from the hardware estimate
+// refined by two Newton steps (about one ulp).
 #include <algorithm>
 #include <cmath>
 
@@ -482,19 +482,20 @@ gravity_tree_kernel(const DensRec *__restrict__ pos, const int32_t *__restrict__
             const int32_t nid = (!valid || root) ? 0 : stk[sp - nb + lane];
             sp -= root ? 0 : nb;
             root = false;
-            const GNode N = nodes[nid];
+            // the node's test fields and links first; its moments only if
+            // accepted
+            const GNode &N = nodes[nid];
+            const double c[3] = {N.cx, N.cy, N.cz};
+            const double ropen = N.ropen;
+            const int32_t nstart = N.start, nend = N.end, child0 = N.child0, nch = N.nchild;
             double dd = 0.0;
-            {
-                const double c[3] = {N.cx, N.cy, N.cz};
-                for (int a = 0; a < 3; ++a) {
-                    double e = 0.0;
-                    if (c[a] < blo[a]) e = blo[a] - c[a];
-                    else if (c[a] > bhi[a]) e = c[a] - bhi[a];
-                    dd += e * e;
-                }
+            for (int a = 0; a < 3; ++a) {
+                double e = 0.0;
+                if (c[a] < blo[a]) e = blo[a] - c[a];
+                else if (c[a] > bhi[a]) e = c[a] - bhi[a];
+                dd += e * e;
             }
-            const bool acc = valid && sqrt(dd) > N.ropen;
-            const int nch = N.nchild;
+            const bool acc = valid && sqrt(dd) > ropen;
             const bool open_int = valid && !acc && nch > 0;
             // children of the opened internal nodes onto the stack
             const int cnt = open_int ? nch : 0;
@@ -510,15 +511,15 @@ gravity_tree_kernel(const DensRec *__restrict__ pos, const int32_t *__restrict__
             }
             if (open_int) {
                 const int64_t at = sp + incl - cnt;
-                for (int c = 0; c < cnt; ++c) stk[at + c] = N.child0 + c;
+                for (int q = 0; q < cnt; ++q) stk[at + q] = child0 + q;
             }
             sp += total;
             // moments of the accepted nodes into LDS
             lds_sync();
             if (acc) {
-                nd[0][lane] = N.cx;
-                nd[1][lane] = N.cy;
-                nd[2][lane] = N.cz;
+                nd[0][lane] = c[0];
+                nd[1][lane] = c[1];
+                nd[2][lane] = c[2];
                 nd[3][lane] = N.M;
                 for (int q = 0; q < 6; ++q) nd[4 + q][lane] = N.q[q];
             }
@@ -530,27 +531,32 @@ gravity_tree_kernel(const DensRec *__restrict__ pos, const int32_t *__restrict__
                 const int tl = __builtin_ctzll(use);
                 use &= use - 1;
                 if ((accm >> tl) & 1ull) {
-                    const double d[3] = {me.x - nd[0][tl], me.y - nd[1][tl], me.z - nd[2][tl]};
+                    // -M d / r^3 + Q d / r^5 - 5/2 (d.Q d) d / r^7, as
+                    // (Q d) / r^5 + (-M / r^3 - 5/2 (d.Q d) / r^7) d with fused
+                    // multiply-adds
+                    const double d0 = me.x - nd[0][tl], d1 = me.y - nd[1][tl],
+                                 d2 = me.z - nd[2][tl];
                     const double M = nd[3][tl];
                     const double q0 = nd[4][tl], q1 = nd[5][tl], q2 = nd[6][tl],
                                  q3 = nd[7][tl], q4 = nd[8][tl], q5 = nd[9][tl];
-                    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                    const double r2 = __builtin_fma(d2, d2, __builtin_fma(d1, d1, d0 * d0));
                     const double rinv = rsq_newton(r2);  // r2 > 0: the node was accepted
                     const double rinv2 = rinv * rinv;
                     const double rinv3 = rinv * rinv2;
                     const double rinv5 = rinv3 * rinv2;
                     const double rinv7 = rinv5 * rinv2;
-                    const double Qd0 = q0 * d[0] + q1 * d[1] + q2 * d[2];
-                    const double Qd1 = q1 * d[0] + q3 * d[1] + q4 * d[2];
-                    const double Qd2 = q2 * d[0] + q4 * d[1] + q5 * d[2];
-                    const double dQd = d[0] * Qd0 + d[1] * Qd1 + d[2] * Qd2;
-                    ax += -M * d[0] * rinv3 + Qd0 * rinv5 - 2.5 * dQd * d[0] * rinv7;
-                    ay += -M * d[1] * rinv3 + Qd1 * rinv5 - 2.5 * dQd * d[1] * rinv7;
-                    az += -M * d[2] * rinv3 + Qd2 * rinv5 - 2.5 * dQd * d[2] * rinv7;
+                    const double Qd0 = __builtin_fma(q2, d2, __builtin_fma(q1, d1, q0 * d0));
+                    const double Qd1 = __builtin_fma(q4, d2, __builtin_fma(q3, d1, q1 * d0));
+                    const double Qd2 = __builtin_fma(q5, d2, __builtin_fma(q4, d1, q2 * d0));
+                    const double dQd = __builtin_fma(d2, Qd2, __builtin_fma(d1, Qd1, d0 * Qd0));
+                    const double rad = __builtin_fma(-2.5 * dQd, rinv7, -M * rinv3);
+                    ax = __builtin_fma(Qd0, rinv5, __builtin_fma(rad, d0, ax));
+                    ay = __builtin_fma(Qd1, rinv5, __builtin_fma(rad, d1, ay));
+                    az = __builtin_fma(Qd2, rinv5, __builtin_fma(rad, d2, az));
                 } else {
                     // the leaf's particles, staged 64 at a time
-                    const int32_t s0 = __builtin_amdgcn_readlane(N.start, tl);
-                    const int32_t s1 = __builtin_amdgcn_readlane(N.end, tl);
+                    const int32_t s0 = __builtin_amdgcn_readlane(nstart, tl);
+                    const int32_t s1 = __builtin_amdgcn_readlane(nend, tl);
                     for (int32_t c0 = s0; c0 < s1; c0 += 64) {
                         const int32_t m = min(64, s1 - c0);
                         lds_sync();
@@ -559,12 +565,13 @@ gravity_tree_kernel(const DensRec *__restrict__ pos, const int32_t *__restrict__
                         for (int32_t j = 0; j < m; ++j) {
                             const DensRec o = lr[j];
                             const double dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
-                            const double d2 = dx * dx + dy * dy + dz * dz + e2;
+                            const double d2 = __builtin_fma(
+                                dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, e2)));
                             const double rs = rsq_newton(d2);
-                            const double inv = c0 + j == k ? 0.0 : rs * rs * rs;
-                            ax += -o.m * dx * inv;
-                            ay += -o.m * dy * inv;
-                            az += -o.m * dz * inv;
+                            const double t = c0 + j == k ? 0.0 : o.m * (rs * rs * rs);
+                            ax = __builtin_fma(-t, dx, ax);
+                            ay = __builtin_fma(-t, dy, ay);
+                            az = __builtin_fma(-t, dz, az);
                         }
                     }
                 }
@@ -636,7 +643,7 @@ hipError_t gt_reserve_all(sph_ctx ctx)
     const int64_t n = ctx->n_max;
     ctx->gt_node_cap = n / 2 + 1024;
     ctx->gt_fcap = 8192;
-    ctx->gt_waves = 4096;
+    ctx->gt_waves = 5120;
     hipError_t e;
     if ((e = gt_alloc(ctx, &ctx->gt_keys[0], n)) != hipSuccess) return e;
     if ((e = gt_alloc(ctx, &ctx->gt_keys[1], n)) != hipSuccess) return e;
