@@ -452,12 +452,14 @@ gravity_tree_kernel(const DensRec *__restrict__ pos, const int32_t *__restrict__
                     double *__restrict__ gz, uint32_t *__restrict__ flags)
 {
     __shared__ double nd_all[4][10][64];  // per wave: c, M, Q of each lane's node
-    __shared__ DensRec lr_all[4][64];     // per wave: a leaf's particles
+    __shared__ DensRec lr_all[4][64];     // per wave: staged leaf particles
+    __shared__ int32_t lk_all[4][3][64];  // per wave: their positions; leaf starts, ends
     if (flags[0] & 1u) return;  // the tree is incomplete
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     double (*nd)[64] = nd_all[w];
     DensRec *lr = lr_all[w];
+    int32_t *lpos = lk_all[w][0], *lstart = lk_all[w][1], *lend = lk_all[w][2];
     const int64_t wid = (int64_t)blockIdx.x * 4 + w;
     const int64_t nw = (int64_t)gridDim.x * 4;
     int32_t *stk = stack_all + wid * fcap;
@@ -524,13 +526,24 @@ gravity_tree_kernel(const DensRec *__restrict__ pos, const int32_t *__restrict__
                 for (int q = 0; q < 6; ++q) nd[4 + q][lane] = N.q[q];
             }
             lds_sync();
-            // accepted nodes and opened leaves, in lane order
-            uint64_t use = __ballot(valid && (acc || nch == 0));
-            const uint64_t accm = __ballot(acc);
+            // the opened leaves' particles, as one run: lane t's leaf covers
+            // [lend[t] - its count, lend[t]) of the run
+            const bool leaf = valid && !acc && nch == 0;
+            const int lcnt = leaf ? nend - nstart : 0;
+            int lincl = lcnt;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(lincl, o, 64);
+                if (lane >= o) lincl += v;
+            }
+            const int ltotal = __shfl(lincl, 63, 64);
+            lstart[lane] = nstart;
+            lend[lane] = lincl;
+            // accepted nodes in lane order
+            uint64_t use = __ballot(acc);
             while (use) {
                 const int tl = __builtin_ctzll(use);
                 use &= use - 1;
-                if ((accm >> tl) & 1ull) {
+                {
                     // -M d / r^3 + Q d / r^5 - 5/2 (d.Q d) d / r^7, as
                     // (Q d) / r^5 + (-M / r^3 - 5/2 (d.Q d) / r^7) d with fused
                     // multiply-adds
@@ -553,27 +566,35 @@ gravity_tree_kernel(const DensRec *__restrict__ pos, const int32_t *__restrict__
                     ax = __builtin_fma(Qd0, rinv5, __builtin_fma(rad, d0, ax));
                     ay = __builtin_fma(Qd1, rinv5, __builtin_fma(rad, d1, ay));
                     az = __builtin_fma(Qd2, rinv5, __builtin_fma(rad, d2, az));
-                } else {
-                    // the leaf's particles, staged 64 at a time
-                    const int32_t s0 = __builtin_amdgcn_readlane(nstart, tl);
-                    const int32_t s1 = __builtin_amdgcn_readlane(nend, tl);
-                    for (int32_t c0 = s0; c0 < s1; c0 += 64) {
-                        const int32_t m = min(64, s1 - c0);
-                        lds_sync();
-                        if (lane < m) lr[lane] = pos[c0 + lane];
-                        lds_sync();
-                        for (int32_t j = 0; j < m; ++j) {
-                            const DensRec o = lr[j];
-                            const double dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
-                            const double d2 = __builtin_fma(
-                                dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, e2)));
-                            const double rs = rsq_newton(d2);
-                            const double t = c0 + j == k ? 0.0 : o.m * (rs * rs * rs);
-                            ax = __builtin_fma(-t, dx, ax);
-                            ay = __builtin_fma(-t, dy, ay);
-                            az = __builtin_fma(-t, dz, az);
-                        }
+                }
+            }
+            // then the leaves' particles, staged 64 at a time by one load each
+            for (int base = 0; base < ltotal; base += 64) {
+                const int m = min(64, ltotal - base);
+                lds_sync();
+                if (lane < m) {
+                    const int r = base + lane;
+                    int lo = 0, hi = 63;  // first lane whose run ends past r
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (lend[mid] > r) hi = mid; else lo = mid + 1;
                     }
+                    const int first = lo == 0 ? 0 : lend[lo - 1];
+                    const int32_t q = lstart[lo] + (r - first);
+                    lpos[lane] = q;
+                    lr[lane] = pos[q];
+                }
+                lds_sync();
+                for (int j = 0; j < m; ++j) {
+                    const DensRec o = lr[j];
+                    const double dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
+                    const double d2 =
+                        __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, e2)));
+                    const double rs = rsq_newton(d2);
+                    const double t = lpos[j] == k ? 0.0 : o.m * (rs * rs * rs);
+                    ax = __builtin_fma(-t, dx, ax);
+                    ay = __builtin_fma(-t, dy, ay);
+                    az = __builtin_fma(-t, dz, az);
                 }
             }
             // the pushed entries are read by other lanes next round
