@@ -152,3 +152,32 @@ def test_evrard_1M_gravity_tree():
     rel = float(np.max(err / sc))
     print("evrard 1M tree max err / scale", rel, st, flush=True)
     assert rel <= 1e-12
+
+
+def test_evrard_1M_individual_time_steps():
+    """One step with individual time steps (max_bin = 4) at the bench's size:
+    the 1M Evrard sphere with h from the count iteration and the oracle's
+    octree field held fixed; D, every bin and the state against the oracle."""
+    import oracle as O
+    ic = I.evrard(1_000_000, seed=0)
+    print("case Evrard 1M individual time steps", flush=True)
+    ic.h, _, _ = O.smoothing_length(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi, ic.periodic)
+    g = O.gravity_tree(ic.x, ic.y, ic.z, ic.m, 0.01, 0.5, 16)[:3]
+    ref = O.OracleRun(ic, g=g).init()
+    max_nb = int(np.diff(ref.off).max()) + 64
+    ctx = S.Context(ic.n, max_nb)
+    st = S.SphState(ic, max_nb, g=g)
+    prm = S.make_params(ic.params)
+    S.sph_init_forces(ctx, st, prm, set_rho_ref=False)
+    subs = S.sph_step_blocks(ctx, st, prm, 4)
+    D, b, rsubs = ref.step_blocks(4)
+    S.sph_ctx_check(ctx)
+    got = st.host(["bin", "x", "y", "z", "vx", "vy", "vz", "u"])
+    print("D", st.dt, D, "substeps", subs, rsubs, flush=True)
+    assert subs == rsubs and abs(st.dt - D) <= 1e-14 * D
+    assert np.array_equal(got["bin"].astype(np.int64), b)
+    err = {k: float(np.max(np.abs(got[k] - ref.s[k]))) for k in ("x", "y", "z", "vx", "vy",
+                                                                   "vz", "u")}
+    print("evrard 1M blocks max errors", err, flush=True)
+    assert max(err[k] for k in ("x", "y", "z")) <= 1e-12
+    assert max(err[k] for k in ("vx", "vy", "vz", "u")) <= 1e-10
