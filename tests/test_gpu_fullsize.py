@@ -156,12 +156,11 @@ def test_evrard_1M_gravity_tree():
 
 def test_evrard_1M_individual_time_steps():
     """One step with individual time steps (max_bin = 4) at the bench's size:
-    the 1M Evrard sphere with h from the count iteration and the oracle's
-    octree field held fixed; D, every bin and the state against the oracle."""
+    the 1M Evrard sphere (analytic h) with the oracle's octree field held
+    fixed; D, every bin and the state against the oracle."""
     import oracle as O
     ic = I.evrard(1_000_000, seed=0)
     print("case Evrard 1M individual time steps", flush=True)
-    ic.h, _, _ = O.smoothing_length(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi, ic.periodic)
     g = O.gravity_tree(ic.x, ic.y, ic.z, ic.m, 0.01, 0.5, 16)[:3]
     ref = O.OracleRun(ic, g=g).init()
     max_nb = int(np.diff(ref.off).max()) + 64
