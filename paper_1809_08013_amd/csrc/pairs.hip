@@ -464,8 +464,16 @@ iad_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ vrec,
     const double hh = h[i];
     double a = 0.0, b = 0.0, c = 0.0, d = 0.0, e = 0.0, f = 0.0;
     const int cnt = min(count[i], max_nb);
+    // the next record and the index after it are in flight while a pair is
+    // summed
+    int32_t jn = cnt > 1 ? idx[ld + i] : (int32_t)i;
+    DensRec on = vrec[cnt > 0 ? idx[i] : (int32_t)i];
     for (int k = 0; k < cnt; ++k) {
-        const DensRec o = vrec[idx[(int64_t)k * ld + i]];
+        const DensRec o = on;
+        if (k + 1 < cnt) {
+            on = vrec[jn];
+            jn = k + 2 < cnt ? idx[(int64_t)(k + 2) * ld + i] : (int32_t)i;
+        }
         const double dx = img<-1>(me.x - o.x, im, 0);
         const double dy = img<-1>(me.y - o.y, im, 1);
         const double dz = img<-1>(me.z - o.z, im, 2);
