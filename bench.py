@@ -255,8 +255,9 @@ def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
     timed hydro steps: gravity is outside the timed path. The octree gravity
     (sph_gravity_tree, theta = 0.5, leaves of 16) is timed on the same state
     and checked against the direct sum, a third run takes individual time
-    steps (sph_step_blocks, max_bin = 5) with the fixed field and reports the
-    simulated time per second against the global step's, and a fourth
+    steps (sph_step_blocks, max_bin = 5) with the fixed field and compares the
+    wall time over the same simulated interval with the global step's, and a
+    fourth
     recomputes the octree gravity inside every step (the Evrard collapse with
     self-gravity, Alg. 1 step 4).
     """
@@ -302,23 +303,15 @@ def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
            "gravity_direct": {"ms": t_grav * 1e3, "eps": 0.01,
                               "pair_interactions_per_s": float(n) * (n - 1) / t_grav},
            "gravity_tree": tree}
-    res_dt = None
     for name, prec in (("fp64", S.SPH_FP64), ("fp32_pair", S.SPH_FP32_PAIR)):
         res = run_gpu(ic, prec, steps, warmup, max_nb=512, g=g, iterate_h=True)
-        if res_dt is None:
-            res_dt = res["dt"]
         out[name] = {"value": res["pairs_per_step"] / (res["ms_per_step"] * 1e-3),
                      "ms_per_step": res["ms_per_step"],
                      "per_call_ms": {k: round(v, 4) for k, v in res["per_call_ms"].items()},
                      "mean_neighbours": res["pairs_per_step"] / n,
                      "max_neighbours": res["max_count"],
                      "h_iteration": res["h_iteration"]}
-    glob = out["fp64"]
-    blk = run_blocks(ic, g, max(2, steps // 5), 5)
-    blk["global_step_simulated_time_per_s"] = res_dt / (glob["ms_per_step"] * 1e-3)
-    blk["speedup_vs_global_step"] = blk["simulated_time_per_s"] / blk[
-        "global_step_simulated_time_per_s"]
-    out["fp64_individual_time_steps"] = blk
+    out["fp64_individual_time_steps"] = run_blocks(ic, g, max(2, steps // 10), 5)
     res = run_gpu(ic, S.SPH_FP64, steps, warmup, max_nb=512, g=g, iterate_h=True,
                   self_gravity=(0.01, 0.5, 16))
     out["fp64_self_gravity"] = {
@@ -329,34 +322,53 @@ def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
 
 
 def run_blocks(ic, g, steps: int, max_bin: int, max_nb: int = 512) -> dict:
-    """Individual time steps (sph_step_blocks) on the same input as the
-    global-step leg: wall time per step of D, substeps, and the simulated
-    time advanced per wall-clock second."""
+    """Individual time steps (sph_step_blocks) against the global step over
+    the same simulated interval, from the same state (h iterated, t = 0
+    forces): `steps` block steps advance T; global steps (sph_step) then run
+    from the same start until they pass T. Reports both wall times."""
     import torch
 
     from paper_1809_08013_amd import sph as S
     log(f"individual time steps n={ic.n} max_bin={max_bin}")
-    ctx = S.Context(ic.n, max_nb)
-    st = S.SphState(ic, max_nb, g=g)
     prm = S.make_params(ic.params)
-    S.sph_smoothing_length(ctx, st)
-    S.sph_init_forces(ctx, st, prm, set_rho_ref=False)
-    S.sph_step_blocks(ctx, st, prm, max_bin)  # warm-up
-    S.sph_ctx_check(ctx)
-    torch.cuda.synchronize()
+
+    def start():
+        ctx = S.Context(ic.n, max_nb)
+        st = S.SphState(ic, max_nb, g=g)
+        S.sph_smoothing_length(ctx, st)
+        S.sph_init_forces(ctx, st, prm, set_rho_ref=False)
+        S.sph_ctx_check(ctx)
+        torch.cuda.synchronize()
+        return ctx, st
+
+    ctx, st = start()
     t_sim, subs = 0.0, []
     t0 = time.perf_counter()
     for _ in range(steps):
         subs.append(S.sph_step_blocks(ctx, st, prm, max_bin))
         t_sim += st.dt
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall_blk = time.perf_counter() - t0
     S.sph_ctx_check(ctx)
     bins = st.host(["bin"])["bin"].astype(int)
-    return {"max_bin": max_bin, "steps": steps, "ms_per_step": wall * 1e3 / steps,
-            "mean_substeps": float(sum(subs)) / steps, "mean_D": t_sim / steps,
-            "simulated_time_per_s": t_sim / wall,
-            "bin_counts": {int(k): int((bins == k).sum()) for k in sorted(set(bins.tolist()))}}
+    del ctx, st
+    ctx, st = start()
+    t_glob, n_glob = 0.0, 0
+    t0 = time.perf_counter()
+    while t_glob < t_sim:
+        dt = st.dt  # the dt the next step takes (synchronises)
+        S.sph_step(ctx, st, prm, diag=False)
+        t_glob += dt
+        n_glob += 1
+    torch.cuda.synchronize()
+    wall_glob = time.perf_counter() - t0
+    S.sph_ctx_check(ctx)
+    return {"max_bin": max_bin, "steps": steps, "simulated_interval": t_sim,
+            "ms_per_step": wall_blk * 1e3 / steps, "mean_substeps": float(sum(subs)) / steps,
+            "wall_s": wall_blk, "global_steps": n_glob, "global_wall_s": wall_glob,
+            "global_simulated_interval": t_glob, "speedup_vs_global_step": wall_glob / wall_blk,
+            "bin_counts_last_step": {int(k): int((bins == k).sum())
+                                     for k in sorted(set(bins.tolist()))}}
 
 
 def drift(r: dict) -> dict:
