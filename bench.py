@@ -11,7 +11,9 @@ untimed. Prints ONE JSON line.
     python bench.py [--gpus 1] [--steps 50] [--warmup 5]
 
 value = pair-interactions/s of the plain FP64 form (directed neighbour pairs
-per step / wall time per step). The FP32-pair form (FP32 pair arithmetic,
+per step / wall time per step of the call-by-call launches). The same step
+captured in a HIP graph (sph_step_capture) is replayed afterwards and its
+step time reported beside it. The FP32-pair form (FP32 pair arithmetic,
 FP64 state, integration and reductions) is timed on the same GPU and
 reported beside it. The CPU baseline is the FP64 oracle on the host cores.
 """
@@ -129,7 +131,11 @@ def recorded_traffic(kernel: str, workload: str):
 
 
 def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=None,
-            iterate_h: bool = False, self_gravity=None) -> dict:
+            iterate_h: bool = False, self_gravity=None, graph: bool = False) -> dict:
+    """Timed leg: `steps` steps call by call, a HIP event between calls (the
+    per-call times); ms_per_step is its wall time. With graph=True a second
+    leg then captures sph_step into a HIP graph and times `steps` replays of
+    it on the same state (graph_ms_per_step)."""
     import numpy as np
     import torch
 
@@ -199,9 +205,23 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
         for k, name in enumerate(names):
             per_call[name] += evs[k].elapsed_time(evs[k + 1])
     per_call = {k: v / steps for k, v in per_call.items()}  # ms per launch
+    eager_ms = (t1 - t0) * 1e3 / steps
+    graph_ms = None
+    if graph and self_gravity is None:
+        S.sph_step_capture(ctx, st, prm)
+        S.sph_step_replay(ctx)  # first replay: graph upload
+        S.sph_ctx_check(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            S.sph_step_replay(ctx)
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) * 1e3 / steps
+        S.sph_ctx_check(ctx)
     pairs = float(st.t["count"][: ic.n].sum().item())
     diag = st.diag
-    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, per_call_ms=per_call,
+    return dict(ms_per_step=eager_ms, graph_ms_per_step=graph_ms,
+                per_call_ms=per_call,
                 candidates=stencil_candidates(ic),
                 pairs_per_step=pairs, dt=st.dt, diag=diag.tolist(), diag0=diag0,
                 max_count=int(st.t["count"][: ic.n].max().item()),
@@ -671,8 +691,9 @@ def main():
         del a, b
     ic = I.square_patch(args.n_side, seed=0)
     n = ic.n
-    r64 = run_gpu(ic, S.SPH_FP64, args.steps, args.warmup)
-    r32 = None if args.no_fp32 else run_gpu(ic, S.SPH_FP32_PAIR, args.steps, args.warmup)
+    r64 = run_gpu(ic, S.SPH_FP64, args.steps, args.warmup, graph=True)
+    r32 = None if args.no_fp32 else run_gpu(ic, S.SPH_FP32_PAIR, args.steps, args.warmup,
+                                            graph=True)
     value = r64["pairs_per_step"] / (r64["ms_per_step"] * 1e-3)
     line = {
         "metric": "SPH pair-interactions/s & step time @1M; p50/p99 ensemble-request latency",
@@ -682,6 +703,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": r64["ms_per_step"],
+        "graph_ms_per_step": r64["graph_ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -705,6 +727,7 @@ def main():
         v32 = r32["pairs_per_step"] / (r32["ms_per_step"] * 1e-3)
         line["fp32_pair"] = {
             "value": v32, "ms_per_step": r32["ms_per_step"],
+            "graph_ms_per_step": r32["graph_ms_per_step"],
             "speedup_vs_fp64": r64["ms_per_step"] / r32["ms_per_step"],
             "per_call_ms": {k: round(v, 4) for k, v in r32["per_call_ms"].items()},
             "roofline": roofline(n, r32, 1),

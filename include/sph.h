@@ -333,6 +333,20 @@ sph_status sph_step(sph_ctx ctx, const sph_particles *p, const sph_box *box,
                     const sph_fields *f, const sph_accel *a, double *dt_dev,
                     double *diag_dev);
 
+/* sph_step captured into a HIP graph kept by the context (replacing any
+ * earlier capture): the same kernels with the same arguments, recorded
+ * without running. sph_step_replay launches the graph on ctx's stream, one
+ * step per call, without the host work of the individual calls. The
+ * captured pointers, n, box, h_max and parameters are fixed: the caller keeps
+ * the arrays allocated and unmoved and captures again after changing any of
+ * them. Errors of the captured calls are returned by sph_step_capture (no
+ * graph is kept); SPH_E_INVALID from sph_step_replay without a capture. */
+sph_status sph_step_capture(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                            double h_max, const sph_nbrs *nb, const sph_params *prm,
+                            const sph_fields *f, const sph_accel *a, double *dt_dev,
+                            double *diag_dev);
+sph_status sph_step_replay(sph_ctx ctx);
+
 /* One step with individual time steps in power-of-two bins (Table 1 and
  * Table 2: ChaNGa's multiple time-stepping; the paper's other scaling lever
  * besides the global dt). Needs the forces at the current, synchronised

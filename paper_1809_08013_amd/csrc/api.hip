@@ -216,6 +216,8 @@ sph_status dev_alloc(sph_ctx ctx, T **p, int64_t count)
 void free_ctx(sph_ctx ctx)
 {
     release_gravity_tree(ctx);
+    if (ctx->step_exec) (void)hipGraphExecDestroy(ctx->step_exec);
+    if (ctx->step_graph) (void)hipGraphDestroy(ctx->step_graph);
     void *ptrs[] = {ctx->keys[0], ctx->keys[1], ctx->vals[0], ctx->vals[1], ctx->hist,
                     ctx->scan_part, ctx->cell_start, ctx->cell_end, ctx->perm_tmp,
                     ctx->perm_tmp_id, ctx->red_part, ctx->status_dev, ctx->nb_mask, ctx->hflag_dev,
@@ -591,6 +593,59 @@ sph_status sph_step(sph_ctx ctx, const sph_particles *p, const sph_box *box, dou
     if ((s = sph_momentum_energy(ctx, p, box, nb, prm, f, a)) != SPH_OK) return s;
     if ((s = sph_integrate(ctx, p, box, SPH_KICK, dt_dev, a)) != SPH_OK) return s;
     return sph_timestep(ctx, p, prm, f, a, dt_dev, diag_dev);
+}
+
+sph_status sph_step_capture(sph_ctx ctx, const sph_particles *p, const sph_box *box,
+                            double h_max, const sph_nbrs *nb, const sph_params *prm,
+                            const sph_fields *f, const sph_accel *a, double *dt_dev,
+                            double *diag_dev)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    if (ctx->step_exec) {
+        (void)hipGraphExecDestroy(ctx->step_exec);
+        ctx->step_exec = nullptr;
+    }
+    if (ctx->step_graph) {
+        (void)hipGraphDestroy(ctx->step_graph);
+        ctx->step_graph = nullptr;
+    }
+    // The caller's stream may be the null stream, which cannot be captured:
+    // record on a private stream (the launches take ctx->stream) and launch
+    // the graph on the caller's stream afterwards.
+    hipStream_t cap = nullptr;
+    SPH_HIP(ctx, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t own = ctx->stream;
+    const hipError_t be = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (be != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return hip_fail(ctx, be, "hipStreamBeginCapture");
+    }
+    ctx->stream = cap;
+    const sph_status s = sph_step(ctx, p, box, h_max, nb, prm, f, a, dt_dev, diag_dev);
+    ctx->stream = own;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (s != SPH_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (s != SPH_OK) return s;
+        return hip_fail(ctx, e, "hipStreamEndCapture");
+    }
+    ctx->step_graph = g;
+    const hipError_t ie = hipGraphInstantiate(&ctx->step_exec, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        ctx->step_exec = nullptr;
+        return hip_fail(ctx, ie, "hipGraphInstantiate");
+    }
+    return SPH_OK;
+}
+
+sph_status sph_step_replay(sph_ctx ctx)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    if (!ctx->step_exec) return fail(ctx, SPH_E_INVALID, "no step was captured");
+    SPH_HIP(ctx, hipGraphLaunch(ctx->step_exec, ctx->stream));
+    return SPH_OK;
 }
 
 sph_status sph_step_blocks(sph_ctx ctx, const sph_particles *p, const sph_box *box,

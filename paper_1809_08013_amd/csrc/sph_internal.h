@@ -260,6 +260,10 @@ struct sph_ctx_s {
     double *dtc = nullptr;
     uint32_t *blk_words = nullptr;
 
+    // one captured sph_step (sph_step_capture / sph_step_replay)
+    hipGraph_t step_graph = nullptr;
+    hipGraphExec_t step_exec = nullptr;
+
     uint32_t *status_dev = nullptr;
     uint32_t *hflag_dev = nullptr;   // 0 after a build iff every particle has the same h
     std::string last_error;

@@ -143,6 +143,8 @@ def load():
             "sph_init_forces": (C.c_int32, [_VP, P, B, C.c_double, N, M, F, A, C.c_int32,
                                             _VP, _VP]),
             "sph_step": (C.c_int32, [_VP, P, B, C.c_double, N, M, F, A, _VP, _VP]),
+            "sph_step_capture": (C.c_int32, [_VP, P, B, C.c_double, N, M, F, A, _VP, _VP]),
+            "sph_step_replay": (C.c_int32, [_VP]),
             "sph_step_blocks": (C.c_int32, [_VP, P, B, C.c_double, N, M, F, A, C.c_int32, _VP,
                                             _VP, _VP, C.POINTER(C.c_int32)]),
             "sph_export_neighbors": (C.c_int32, [_VP, P, N, _VP, _VP, C.c_int64,
@@ -400,6 +402,22 @@ def sph_step(ctx: Context, st: SphState, prm: Params, h_max: float | None = None
         float(h_max if h_max is not None else st.h_max), C.byref(st.nbrs), C.byref(prm),
         C.byref(st.fields), C.byref(st.accel), _ptr(st.t["dt"]),
         _ptr(st.t["diag"]) if diag else None))
+
+
+def sph_step_capture(ctx: Context, st: SphState, prm: Params, h_max: float | None = None,
+                     diag: bool = True):
+    """Record one sph_step on st into the context's HIP graph (kept with
+    ctx; st's tensors must stay allocated); sph_step_replay runs it."""
+    ctx._captured = (st, prm)  # keep the arguments' memory alive
+    ctx.raise_on(ctx.lib.sph_step_capture(
+        ctx.h, C.byref(st.particles), C.byref(st.box),
+        float(h_max if h_max is not None else st.h_max), C.byref(st.nbrs), C.byref(prm),
+        C.byref(st.fields), C.byref(st.accel), _ptr(st.t["dt"]),
+        _ptr(st.t["diag"]) if diag else None))
+
+
+def sph_step_replay(ctx: Context):
+    ctx.raise_on(ctx.lib.sph_step_replay(ctx.h))
 
 
 def sph_step_blocks(ctx: Context, st: SphState, prm: Params, max_bin: int,

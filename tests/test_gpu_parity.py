@@ -587,3 +587,41 @@ def test_blocks_against_oracle(name):
         assert err[k] <= 1e-12 * max(1.0, scale[k])
     for k in ("vx", "vy", "vz", "u"):
         assert err[k] <= 1e-10 * max(1.0, scale[k])
+
+
+@pytest.mark.parametrize("name,precision", [("square_patch_c0", S.SPH_FP64),
+                                            ("cloud_pxyz", S.SPH_FP32_PAIR)])
+def test_step_graph_replay_is_sph_step(name, precision):
+    """sph_step_capture + sph_step_replay against eager sph_step, bit for bit:
+    four replays, each followed by an eager step of a twin run and a
+    synchronisation, every replay compared with the eager state."""
+    make, max_nb = _cases()[name]
+    ic = make()
+    print(f"case graph {name} n={ic.n} precision={precision}", flush=True)
+    prm = S.make_params(ic.params, precision)
+    keys = ["x", "y", "z", "vx", "vy", "vz", "u", "rho", "ax", "ay", "az", "dudt"]
+    runs = []
+    for _ in range(2):
+        ctx = S.Context(ic.n, max_nb)
+        st = S.SphState(ic, max_nb)
+        S.sph_init_forces(ctx, st, prm, set_rho_ref=True)
+        runs.append((ctx, st))
+    (cg, sg), (ce, se) = runs
+    with pytest.raises(S.SphError) as ei:
+        S.sph_step_replay(cg)
+    assert ei.value.status == S.SPH_E_INVALID
+    before = sg.host(keys)
+    S.sph_step_capture(cg, sg, prm)
+    torch.cuda.synchronize()
+    after = sg.host(keys)
+    for k in keys:  # capturing runs nothing
+        assert np.array_equal(before[k], after[k]), k
+    for r in range(4):
+        S.sph_step_replay(cg)
+        S.sph_step(ce, se, prm)
+        S.sph_ctx_check(cg)
+        S.sph_ctx_check(ce)
+        g, e = sg.host(keys), se.host(keys)
+        for k in keys:
+            assert np.array_equal(g[k], e[k]), (r, k)
+        assert sg.dt == se.dt and np.array_equal(sg.diag, se.diag), r
