@@ -764,8 +764,10 @@ fallback_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
 __global__ void clear_count_kernel(uint32_t *c) { *c = 0u; }
 
 
+// At most 96 SGPRs (a few spill to VGPR lanes): 8 waves per SIMD instead of
+// the 7 that the compiler's own choice allows; the stream is latency-bound.
 template <bool Multi>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_num_sgpr(96)))
 find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
                       const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
                       const int32_t *__restrict__ cend, Grid g, int max_nb,
