@@ -279,26 +279,28 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
     const uint32_t chunk = 16u * (uint32_t)s;
     char *dst_own = buf + lane * kDensStride;
     char *dst_a = buf + (lane & ~1) * kDensStride + 16 * s;
-    // Software pipelined: the chunks of step k + 1 are loaded while step k is
-    // computed. Lanes 2g and 2g+1 fetch chunk s of the records of both.
+    // Lanes 2g and 2g+1 fetch chunk s of the records of both.
     auto fetch = [&](int jk, double2 &a, double2 &b) {
         const int jp = __shfl_xor(jk, 1, 64);
         const int j0 = s == 0 ? jk : jp, j1 = s == 0 ? jp : jk;
         a = rec_chunk<Big, (int)sizeof(DensRec)>(src_base, j0, chunk);
         b = rec_chunk<Big, (int)sizeof(DensRec)>(src_base, j1, chunk);
     };
-    double2 c0, c1;
-    int jn = cnt > 1 ? idx[ld + ii] : (int)ii;
-    fetch(cnt > 0 ? idx[ii] : (int)ii, c0, c1);
-    for (int k = 0; k < maxc; ++k) {
-        wave_lds_fence();
-        *reinterpret_cast<double2 *>(dst_a) = c0;
-        *reinterpret_cast<double2 *>(dst_a + kDensStride) = c1;
-        wave_lds_fence();
-        if (k + 1 < maxc) {
-            fetch(jn, c0, c1);
-            jn = k + 2 < cnt ? idx[(int64_t)(k + 2) * ld + ii] : (int)ii;
-        }
+    // Two steps in flight: the records of step k + 2 are requested while
+    // step k is computed, alternating between two register sets (the loop
+    // runs two steps per pass, so no set is copied and every wait counts only
+    // the requests issued before the one it needs). Indices are read two
+    // steps before their records; steps past a lane's count fetch its own
+    // record (in bounds, unused).
+    // Index of step k: the list row min(k, max_nb - 1) is read whatever the
+    // lane's count (rows at or past the count hold stale values); the value
+    // is clamped to a valid record only when it is used, so that the read
+    // itself carries no condition.
+    const int krow = max_nb - 1;
+    auto jat = [&](int k) -> int { return idx[(int64_t)min(k, krow) * ld + ii]; };
+    const uint32_t jmax = (uint32_t)(n - 1);
+    auto jfix = [&](int j) -> int { return (int)min((uint32_t)j, jmax); };
+    auto step = [&](int k) {
         const double2 lo = *reinterpret_cast<const double2 *>(dst_own);
         const double2 hi = *reinterpret_cast<const double2 *>(dst_own + 16);
         if (k < cnt) {
@@ -308,6 +310,34 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
             const R r = fast_sqrt(fma_r(dz, dz, fma_r(dy, dy, dx * dx)));
             sum = fma_r((R)hi.y, shape_w<KF>(r * inv_h, sinc_n), sum);
         }
+    };
+    double2 a0, a1, b0, b1;
+    // (issued in the loop's order: the first set is waited for first)
+    const int j0 = jat(0), j1 = jat(1);
+    fetch(jfix(j0), a0, a1);
+    int ja = jat(2);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(jfix(j1), b0, b1);
+    int jb = jat(3);
+    __builtin_amdgcn_sched_barrier(0);
+    // The requests are unconditional (the last pass fetches records that
+    // are never used), so the loop body is straight-line code and each wait
+    // names an exact count.
+    for (int k = 0; k < maxc; k += 2) {
+        wave_lds_fence();
+        *reinterpret_cast<double2 *>(dst_a) = a0;
+        *reinterpret_cast<double2 *>(dst_a + kDensStride) = a1;
+        wave_lds_fence();
+        fetch(jfix(ja), a0, a1);
+        ja = jat(k + 4);
+        step(k);
+        wave_lds_fence();
+        *reinterpret_cast<double2 *>(dst_a) = b0;
+        *reinterpret_cast<double2 *>(dst_a + kDensStride) = b1;
+        wave_lds_fence();
+        fetch(jfix(jb), b0, b1);
+        jb = jat(k + 5);
+        step(k + 1);
     }
     const R sg = KF == KF_M4 ? (R)kInvPi : (R)sigma;
     if (active && closes) rho[i] = (double)(sum * (sg * inv_h * inv_h * inv_h));
@@ -561,13 +591,6 @@ __device__ __forceinline__ void momentum_tile(
     R sx = 0, sy = 0, sz = 0, su = 0, mum = 0;
     // IAD: the lane's own matrix, and the next neighbour's
     R cix = 0, ciy = 0, ciz = 0, ciyy = 0, ciyz = 0, cizz = 0;
-    double2 e0 = make_double2(0.0, 0.0), e1 = e0, e2 = e0;
-    auto load_c = [&](int jj) {
-        const double2 *cp = reinterpret_cast<const double2 *>(prm.iad_c + 6 * (int64_t)jj);
-        e0 = cp[0];
-        e1 = cp[1];
-        e2 = cp[2];
-    };
     if constexpr (IAD) {
         const double *cp = prm.iad_c + 6 * ii;
         cix = (R)cp[0]; ciy = (R)cp[1]; ciz = (R)cp[2];
@@ -583,41 +606,45 @@ __device__ __forceinline__ void momentum_tile(
     const uint32_t chunk = 16u * (uint32_t)(loader ? s : 0);
     const char *own = buf + lane * kMomStride;
     char *dst = buf + grp * kMomStride + 16 * s;
-    // Software pipelined: the chunks of step k + 1 are loaded into registers
-    // (c0..c7) while step k is computed from LDS.
-#define SPH_FETCH(t, jk)                                                                   \
-    c##t = rec_chunk<Big, (int)sizeof(PairRec)>(src_base, __shfl((jk), grp + (t), 64), chunk)
-#define SPH_FETCH_ALL(jk)                                                                  \
-    SPH_FETCH(0, jk); SPH_FETCH(1, jk); SPH_FETCH(2, jk); SPH_FETCH(3, jk);                \
-    SPH_FETCH(4, jk); SPH_FETCH(5, jk); SPH_FETCH(6, jk); SPH_FETCH(7, jk)
-    double2 c0, c1, c2, c3, c4, c5, c6, c7;
-    int jn = cnt > 1 ? idx[ld + ii] : (int)ii;
-    {
-        const int j0 = cnt > 0 ? idx[ii] : (int)ii;
-        SPH_FETCH_ALL(j0);
-        if constexpr (IAD) load_c(j0);
-    }
-    for (int k = 0; k < maxc; ++k) {
-        const double2 f0 = e0, f1 = e1, f2 = e2;  // IAD: c_j of this step
+    // Two steps in flight: the records of step k + 2 are requested while
+    // step k is computed, alternating between two register sets (the loop
+    // runs two steps per pass, so no set is copied and every wait counts only
+    // the requests issued before the one it needs). Indices are read two
+    // steps before their records: the list row min(k, max_nb - 1) whatever
+    // the lane's count (rows at or past the count hold stale values), the
+    // value clamped to a valid record only when it is used, so that no read
+    // carries a condition. Records fetched for steps past a lane's count are
+    // never used.
+    const int krow = max_nb - 1;
+    auto jat = [&](int k) -> int { return idx[(int64_t)min(k, krow) * ld + ii]; };
+    const uint32_t jmax = (uint32_t)(n - 1);
+    auto jfix = [&](int j) -> int { return (int)min((uint32_t)j, jmax); };
+    struct RecSet {
+        double2 c[8];
+        double2 e[3];  // IAD: c_j of the set's step
+    };
+    auto fetch_set = [&](int jk, RecSet &S) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            S.c[t] = rec_chunk<Big, (int)sizeof(PairRec)>(src_base, __shfl(jk, grp + t, 64),
+                                                        chunk);
+        if constexpr (IAD) {
+            const double2 *cp = reinterpret_cast<const double2 *>(prm.iad_c + 6 * (int64_t)jk);
+            S.e[0] = cp[0];
+            S.e[1] = cp[1];
+            S.e[2] = cp[2];
+        }
+    };
+    auto put_set = [&](const RecSet &S) {
         wave_lds_fence();
         if (loader) {
-            *reinterpret_cast<double2 *>(dst + 0 * kMomStride) = c0;
-            *reinterpret_cast<double2 *>(dst + 1 * kMomStride) = c1;
-            *reinterpret_cast<double2 *>(dst + 2 * kMomStride) = c2;
-            *reinterpret_cast<double2 *>(dst + 3 * kMomStride) = c3;
-            *reinterpret_cast<double2 *>(dst + 4 * kMomStride) = c4;
-            *reinterpret_cast<double2 *>(dst + 5 * kMomStride) = c5;
-            *reinterpret_cast<double2 *>(dst + 6 * kMomStride) = c6;
-            *reinterpret_cast<double2 *>(dst + 7 * kMomStride) = c7;
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                *reinterpret_cast<double2 *>(dst + t * kMomStride) = S.c[t];
         }
         wave_lds_fence();
-        if (k + 1 < maxc) {
-            SPH_FETCH_ALL(jn);
-            if constexpr (IAD) load_c(jn);
-            jn = k + 2 < cnt ? idx[(int64_t)(k + 2) * ld + ii] : (int)ii;
-        }
-#undef SPH_FETCH_ALL
-#undef SPH_FETCH
+    };
+    auto step = [&](int k, const double2 f0, const double2 f1, const double2 f2) {
         const double2 q0 = *reinterpret_cast<const double2 *>(own);       // x y
         const double2 q1 = *reinterpret_cast<const double2 *>(own + 16);  // z vx
         const double2 q2 = *reinterpret_cast<const double2 *>(own + 32);  // vy vz
@@ -695,6 +722,29 @@ __device__ __forceinline__ void momentum_tile(
             }
             mum = fmax(mum, fabs(mu));
         }
+    };
+    RecSet A, B;
+    // (issued in the loop's order: the first set is waited for first)
+    const int j0 = jat(0), j1 = jat(1);
+    fetch_set(jfix(j0), A);
+    int ja = jat(2);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_set(jfix(j1), B);
+    int jb = jat(3);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int k = 0; k < maxc; k += 2) {
+        put_set(A);
+        double2 f0 = A.e[0], f1 = A.e[1], f2 = A.e[2];
+        fetch_set(jfix(ja), A);
+        ja = jat(k + 4);
+        step(k, f0, f1, f2);
+        put_set(B);
+        f0 = B.e[0];
+        f1 = B.e[1];
+        f2 = B.e[2];
+        fetch_set(jfix(jb), B);
+        jb = jat(k + 5);
+        step(k + 1, f0, f1, f2);
     }
     if (active && closes) {
         ax[i] = (double)sx;
