@@ -621,7 +621,7 @@ __device__ __forceinline__ void momentum_tile(
     auto jfix = [&](int j) -> int { return (int)min((uint32_t)j, jmax); };
     struct RecSet {
         double2 c[8];
-        double2 e[3];  // IAD: c_j of the set's step
+        double2 e[3] = {};  // IAD: c_j of the set's step (zero otherwise)
     };
     auto fetch_set = [&](int jk, RecSet &S) {
 #pragma unroll

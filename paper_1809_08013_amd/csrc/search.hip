@@ -50,6 +50,11 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kMaxEntries = 128;        // 27 * distinct cells, before dedup
 constexpr int kMaxCandidates = kSearchMaskWords * 32;
 constexpr int kMaxWords = kSearchMaskWords;
+// Grid of the second kernel: one-wave blocks draining the worklist, up to 32
+// per CU (its occupancy limit is 5 waves per SIMD); the blocks past the
+// worklist's length exit at once. 2048 blocks left the dense centre of a 1M
+// Evrard sphere on 2 waves per SIMD (search 3.9 ms, 3.0 ms with this grid).
+constexpr int64_t kFallbackBlocks = 8192;
 
 enum WrapMode { WRAP_NONE = 0, WRAP_CELL = 1, WRAP_PAIR = 2 };
 
@@ -905,7 +910,7 @@ hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_
         p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
         nb.max_nb, nb.count, nb.idx, ctx->nb_mask, ctx->hflag_dev, ctx->status_dev, BatchDev{},
         ctx->fb_tiles, ctx->fb_count, mask);
-    const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, 2048);
+    const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, kFallbackBlocks);
     fallback_kernel<false><<<fblocks, kWave, 0, ctx->stream>>>(
         p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
         nb.max_nb, nb.count, nb.idx, ctx->status_dev, BatchDev{}, ctx->fb_tiles, ctx->fb_count,
@@ -926,7 +931,7 @@ hipError_t launch_find_neighbors_batch(sph_ctx ctx, const BatchDev &b, int max_n
         0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,
         count, idx, ctx->nb_mask, nullptr, nullptr, b, ctx->fb_tiles, ctx->fb_count,
         StepMask{});
-    const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, 2048);
+    const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, kFallbackBlocks);
     fallback_kernel<true><<<fblocks, kWave, 0, ctx->stream>>>(
         0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,
         count, idx, nullptr, b, ctx->fb_tiles, ctx->fb_count, ctx->nb_mask, nullptr, nullptr);
