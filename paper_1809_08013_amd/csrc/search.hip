@@ -293,16 +293,23 @@ __device__ __forceinline__ int stream_direct(const SearchRec &me, const int (&my
     return cnt;
 }
 
-// z window of a union cell for a dense tile (no periodic image in play):
-// the sub-range of the cell's particles whose z slices can hold a candidate
-// related to a particle of the tile. A particle in a slice outside the window
-// lies more than R + (one slice) beyond the tile's z extent [zlo, zhi], where
-// R^2 = the larger of the tile's and the cell's largest (2h)^2, so its
-// distance to every particle of the tile exceeds both smoothing diameters;
-// the one-slice margin dwarfs the rounding of the window's arithmetic. A
-// cell's keys are ordered by slice, so the window is found by binary search.
-__device__ __forceinline__ int2 z_window(int2 cr, uint32_t p, const Grid &g, double zlo,
-                                         double zhi, double s2t,
+// Window of a union cell for a dense tile (no periodic image in play): the
+// sub-range of the cell's particles that can hold a candidate related to a
+// particle of the tile, R^2 being the larger of the tile's and the cell's
+// largest (2h)^2.
+// - The whole cell is skipped when its x or y range lies more than R + a
+//   millionth of a cell beyond the tile's extent [lo, hi] on that axis: every
+//   candidate is then farther than both smoothing diameters from every
+//   particle of the tile (a particle's cell index comes from the same
+//   arithmetic, whose rounding is some 1e-13 of a cell).
+// - Otherwise only the z slices within R + (one slice) of the tile's z
+//   extent are kept, by the same argument; a cell's keys are ordered by
+//   slice, so the window is found by binary search.
+// The first and last cell of an axis also hold the particles clamped into
+// them from outside the box, so their range is taken as unbounded on the
+// outer side, and their outer slice is always kept.
+__device__ __forceinline__ int2 z_window(int2 cr, uint32_t p, const Grid &g, const double (&tlo)[3],
+                                         const double (&thi)[3], double s2t,
                                          const unsigned long long *__restrict__ s2max,
                                          const uint32_t *__restrict__ keys)
 {
@@ -311,11 +318,23 @@ __device__ __forceinline__ int2 z_window(int2 cr, uint32_t p, const Grid &g, dou
     const int64_t cell = ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
     const double s2c = __longlong_as_double((long long)s2max[cell]);
     const double r = sqrt(fmax(s2t, s2c));
+    const int cxy[2] = {x, y};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const double fl = (tlo[a] - g.lo[a]) * g.inv_s[a], fh = (thi[a] - g.lo[a]) * g.inv_s[a];
+        const double ra = r * g.inv_s[a] + 1e-6;
+        const bool above = cxy[a] > 0 && (double)cxy[a] - fh > ra;
+        const bool below = cxy[a] < g.nc[a] - 1 && fl - (double)(cxy[a] + 1) > ra;
+        if (above || below) return make_int2(cr.x, cr.x);
+    }
+    const double zlo = tlo[2], zhi = thi[2];
     const double ns = (double)(1 << g.zbits);
     const double fl = ((zlo - r) - g.lo[2]) * g.inv_s[2] - (double)z;
     const double fh = ((zhi + r) - g.lo[2]) * g.inv_s[2] - (double)z;
-    const double ql = fmax(floor(fl * ns) - 1.0, 0.0);
-    const double qh = fmin(floor(fh * ns) + 1.0, ns - 1.0);
+    double ql = fmax(floor(fl * ns) - 1.0, 0.0);
+    double qh = fmin(floor(fh * ns) + 1.0, ns - 1.0);
+    if (z == 0) qh = fmax(qh, 0.0);
+    if (z == g.nc[2] - 1) ql = fmin(ql, ns - 1.0);
     if (ql > qh) return make_int2(cr.x, cr.x);
     if (ql == 0.0 && qh == ns - 1.0) return cr;
     const uint32_t base = keys[cr.x] & ~((1u << g.zbits) - 1u);
@@ -677,18 +696,27 @@ fallback_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
             p1 = gx[lane + kWave];
         }
         if (!Multi && mode == WRAP_NONE && g.zbits > 0) {
-            // walk only each cell's z window (single run: the cell table
+            // walk only each cell's window (single run: the cell table
             // carries the cells' largest (2h)^2)
-            double zlo = active ? me.z : INFINITY, zhi = active ? me.z : -INFINITY;
+            const double mc[3] = {me.x, me.y, me.z};
+            double tlo[3], thi[3];
             double s2t = active ? me.s2 : 0.0;
 #pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                tlo[a] = active ? mc[a] : INFINITY;
+                thi[a] = active ? mc[a] : -INFINITY;
+            }
+#pragma unroll
             for (int o = 32; o > 0; o >>= 1) {
-                zlo = fmin(zlo, __shfl_xor(zlo, o, kWave));
-                zhi = fmax(zhi, __shfl_xor(zhi, o, kWave));
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    tlo[a] = fmin(tlo[a], __shfl_xor(tlo[a], o, kWave));
+                    thi[a] = fmax(thi[a], __shfl_xor(thi[a], o, kWave));
+                }
                 s2t = fmax(s2t, __shfl_xor(s2t, o, kWave));
             }
-            if (lane < nu) r0 = z_window(r0, p0, g, zlo, zhi, s2t, s2max, keys);
-            if (lane + kWave < nu) r1 = z_window(r1, p1, g, zlo, zhi, s2t, s2max, keys);
+            if (lane < nu) r0 = z_window(r0, p0, g, tlo, thi, s2t, s2max, keys);
+            if (lane + kWave < nu) r1 = z_window(r1, p1, g, tlo, thi, s2t, s2max, keys);
         }
         int cnt;
 #define SPH_DIRECT(M, U) \

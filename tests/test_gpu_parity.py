@@ -43,7 +43,27 @@ def _cases():
         "cloud_pxyz": (lambda: I.random_cloud(2049, seed=3, h_min=0.04, h_max=0.09,
                                               periodic=(1, 1, 1)), 512),
         "square_patch_c0": (lambda: I.square_patch(20), 128),
+        "clump_across_open_faces": (lambda: _clump_cloud(0.95), 256),
+        "clump_outside_open_box": (lambda: _clump_cloud(1.10), 256),
     }
+
+
+def _clump_cloud(c0):
+    """A dense clump of 4000 particles (h = 0.0077, ~60 neighbours) in the
+    cube [c0, c0 + 0.1] on the open x and z axes of a unit box (partly or
+    wholly outside it, so clamped into the border cells), next to 600 sparse
+    particles with h up to 0.08 in x < 0.6. The cells (side 2 h_max = 0.16)
+    then hold the whole clump in one or two cells: its tiles take the
+    dense-union walk, whose windows must keep the clamped particles."""
+    ic = I.random_cloud(4600, seed=11, h_min=0.07, h_max=0.08)
+    rng = np.random.default_rng(12)
+    nc = 4000
+    ic.x[:nc] = rng.uniform(c0, c0 + 0.1, nc)
+    ic.y[:nc] = rng.uniform(0.45, 0.55, nc)
+    ic.z[:nc] = rng.uniform(c0, c0 + 0.1, nc)
+    ic.h[:nc] = 0.0077
+    ic.x[nc:] *= 0.6
+    return ic
 
 
 @pytest.mark.parametrize("name", list(_cases()))
