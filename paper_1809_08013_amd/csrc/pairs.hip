@@ -798,21 +798,45 @@ pack_pair_kernel(int64_t n, const int64_t *n_dev, const double *__restrict__ x,
                  const double *__restrict__ c, const double *__restrict__ pr2,
                  const double *__restrict__ xw, PairRec *__restrict__ out)
 {
+    // Each wave forms the records of 64 consecutive particles in LDS (one
+    // per lane, stride 17 doubles), then stores them as 16-byte chunks with
+    // consecutive lanes on consecutive chunks, so that every store writes
+    // 1 KB of contiguous memory. Only the chunks the momentum kernel reads
+    // are written: 6 (96 B), or 7 with the volume weights.
+    constexpr int kStride = 17;
+    __shared__ double lds[4][64 * kStride];
     if (n_dev) n = *n_dev;
-    const int64_t step = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
-        const double hi = h[i];
-        PairRec r;
-        r.x = x[i]; r.y = y[i]; r.z = z[i];
-        r.vx = vx[i]; r.vy = vy[i]; r.vz = vz[i];
-        r.h = hi; r.inv_h = 1.0 / hi; r.m = m[i];
-        r.rho = rho[i]; r.c = c[i]; r.pr2 = pr2[i];
-        r.pad[0] = r.pad[1] = r.pad[2] = r.pad[3] = 0.0;
-        if (xw) {
-            r.pad[0] = xw[i];
-            r.pad[1] = r.m * r.m * r.pr2 / xw[i];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double *buf = lds[wave];
+    const int nparts = xw ? 7 : 6;
+    const int64_t wstep = (int64_t)gridDim.x * (blockDim.x >> 6) * 64;
+    for (int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64; base < n;
+         base += wstep) {
+        const int64_t i = base + lane;
+        if (i < n) {
+            const double hi = h[i];
+            double *r = buf + lane * kStride;
+            r[0] = x[i]; r[1] = y[i]; r[2] = z[i];
+            r[3] = vx[i]; r[4] = vy[i]; r[5] = vz[i];
+            r[6] = hi; r[7] = 1.0 / hi; r[8] = m[i];
+            r[9] = rho[i]; r[10] = c[i]; r[11] = pr2[i];
+            if (xw) {
+                r[12] = xw[i];
+                r[13] = r[8] * r[8] * r[11] / xw[i];
+            }
         }
-        out[i] = r;
+        wave_lds_fence();
+        char *dst = reinterpret_cast<char *>(out + base);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int q = t * 64 + lane;
+            const int rec = q >> 3, part = q & 7;
+            if (part < nparts && base + rec < n) {
+                const double *src = buf + rec * kStride + 2 * part;
+                *reinterpret_cast<double2 *>(dst + 16 * q) = make_double2(src[0], src[1]);
+            }
+        }
+        wave_lds_fence();
     }
 }
 
