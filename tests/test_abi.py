@@ -67,6 +67,10 @@ def test_status_strings_and_null_checks():
         if fn == "sph_gravity_tree":
             args[2], args[3], args[4] = 0.01, 0.5, 16
         assert f(*args) == S.SPH_E_INVALID, fn
+    # the captured step: a NULL context is refused before any HIP call
+    assert L.sph_step_capture(None, None, None, 1.0, None, None, None, None, None,
+                              None) == S.SPH_E_INVALID
+    assert L.sph_step_replay(None) == S.SPH_E_INVALID
 
 
 def test_ensemble_host_checks():
