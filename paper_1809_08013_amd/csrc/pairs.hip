@@ -487,35 +487,81 @@ iad_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ vrec,
            const int32_t *__restrict__ idx, int max_nb, Grid g, double sigma, int sinc_n,
            double *__restrict__ c6)
 {
+    // The records are gathered as in the density kernel: lanes 2g and 2g+1
+    // fetch chunk s of the records of both and hand them over through LDS,
+    // with two steps in flight (the same index reads, clamped at their use).
+    __shared__ __attribute__((aligned(16))) char lds[4][64 * kDensStride];
+    char *buf = lds[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const Img im = lane_img<false>(g, BatchDev{}, i);
-    const DensRec me = vrec[i];
-    const double hh = h[i];
+    const bool active = i < n;
+    const int64_t ii = active ? i : 0;
+    const Img im = lane_img<false>(g, BatchDev{}, ii);
+    const DensRec me = vrec[ii];
+    const double hh = h[ii];
     double a = 0.0, b = 0.0, c = 0.0, d = 0.0, e = 0.0, f = 0.0;
-    const int cnt = min(count[i], max_nb);
-    // the next record and the index after it are in flight while a pair is
-    // summed
-    int32_t jn = cnt > 1 ? idx[ld + i] : (int32_t)i;
-    DensRec on = vrec[cnt > 0 ? idx[i] : (int32_t)i];
-    for (int k = 0; k < cnt; ++k) {
-        const DensRec o = on;
-        if (k + 1 < cnt) {
-            on = vrec[jn];
-            jn = k + 2 < cnt ? idx[(int64_t)(k + 2) * ld + i] : (int32_t)i;
+    const int cnt = active ? min(count[ii], max_nb) : 0;
+    int maxc = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, 64));
+    const int s = lane & 1;
+    const char *src_base = reinterpret_cast<const char *>(vrec);
+    const uint32_t chunk = 16u * (uint32_t)s;
+    char *dst_own = buf + lane * kDensStride;
+    char *dst_a = buf + (lane & ~1) * kDensStride + 16 * s;
+    auto fetch = [&](int jk, double2 &x0, double2 &x1) {
+        const int jp = __shfl_xor(jk, 1, 64);
+        const int j0 = s == 0 ? jk : jp, j1 = s == 0 ? jp : jk;
+        x0 = rec_chunk<true, (int)sizeof(DensRec)>(src_base, j0, chunk);
+        x1 = rec_chunk<true, (int)sizeof(DensRec)>(src_base, j1, chunk);
+    };
+    const int krow = max_nb - 1;
+    auto jat = [&](int k) -> int { return idx[(int64_t)min(k, krow) * ld + ii]; };
+    const uint32_t jmax = (uint32_t)(n - 1);
+    auto jfix = [&](int j) -> int { return (int)min((uint32_t)j, jmax); };
+    auto step = [&](int k) {
+        const double2 lo = *reinterpret_cast<const double2 *>(dst_own);       // x y
+        const double2 hi = *reinterpret_cast<const double2 *>(dst_own + 16);  // z V
+        if (k < cnt) {
+            const double dx = img<-1>(me.x - lo.x, im, 0);
+            const double dy = img<-1>(me.y - lo.y, im, 1);
+            const double dz = img<-1>(me.z - hi.x, im, 2);
+            const double r = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
+            const double vw = hi.y * kernel_w_plain<KF>(r, hh, sigma, sinc_n);
+            a += vw * dx * dx;
+            b += vw * dx * dy;
+            c += vw * dx * dz;
+            d += vw * dy * dy;
+            e += vw * dy * dz;
+            f += vw * dz * dz;
         }
-        const double dx = img<-1>(me.x - o.x, im, 0);
-        const double dy = img<-1>(me.y - o.y, im, 1);
-        const double dz = img<-1>(me.z - o.z, im, 2);
-        const double r = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
-        const double vw = o.m * kernel_w_plain<KF>(r, hh, sigma, sinc_n);
-        a += vw * dx * dx;
-        b += vw * dx * dy;
-        c += vw * dx * dz;
-        d += vw * dy * dy;
-        e += vw * dy * dz;
-        f += vw * dz * dz;
+    };
+    double2 a0, a1, b0, b1;
+    // (issued in the loop's order: the first set is waited for first)
+    const int j0 = jat(0), j1 = jat(1);
+    fetch(jfix(j0), a0, a1);
+    int ja = jat(2);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(jfix(j1), b0, b1);
+    int jb = jat(3);
+    __builtin_amdgcn_sched_barrier(0);
+    for (int k = 0; k < maxc; k += 2) {
+        wave_lds_fence();
+        *reinterpret_cast<double2 *>(dst_a) = a0;
+        *reinterpret_cast<double2 *>(dst_a + kDensStride) = a1;
+        wave_lds_fence();
+        fetch(jfix(ja), a0, a1);
+        ja = jat(k + 4);
+        step(k);
+        wave_lds_fence();
+        *reinterpret_cast<double2 *>(dst_a) = b0;
+        *reinterpret_cast<double2 *>(dst_a + kDensStride) = b1;
+        wave_lds_fence();
+        fetch(jfix(jb), b0, b1);
+        jb = jat(k + 5);
+        step(k + 1);
     }
+    if (!active) return;
     const double ca = d * f - e * e, cb = c * e - b * f, cc = b * e - c * d;
     const double det = a * ca + b * cb + c * cc;
     double *o6 = c6 + 6 * i;
