@@ -132,7 +132,10 @@ enum { SPH_KERNEL_M4 = 0, SPH_KERNEL_WENDLAND_C2 = 1, SPH_KERNEL_SINC = 2 };
  *   SPH_GRAD_IAD     the integral approach to derivatives with standard
  *                    volume elements V_j = m_j / rho_j:
  *                    tau_i = sum_j V_j (x_j - x_i)(x_j - x_i)^T W(r_ij, h_i),
- *                    c_i = tau_i^{-1} (zero if singular),
+ *                    c_i = tau_i^{-1} where det tau_i >= 0.01 (tr tau_i/3)^3;
+ *                    below that (neighbours not spanning three dimensions)
+ *                    c_i = (tr tau_i / 3)^{-1} I, and c_i = 0 when
+ *                    tr tau_i = 0 (no neighbour inside 2 h_i),
  *                    A_ij = c_i (x_j - x_i) W(r_ij, h_i), and the pair terms
  *                    use (A_ij - A_ji) / 2 in place of the kernel gradient. */
 enum { SPH_GRAD_KERNEL = 0, SPH_GRAD_IAD = 1 };

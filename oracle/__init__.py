@@ -105,6 +105,9 @@ def lib():
             L.orc_gravity_tree.restype = C.c_int64
             L.orc_gravity_tree.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_double, C.c_double,
                                            C.c_int32, _D, _D, _D, _DN, C.c_void_p, C.c_void_p]
+            L.orc_gravity_tree_groups.restype = C.c_int64
+            L.orc_gravity_tree_groups.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_int32,
+                                                  C.c_int64, _I64, _I64, _I64]
             L.orc_gravity_tree_nodes.restype = C.c_int64
             L.orc_gravity_tree_nodes.argtypes = [C.c_int64, _D, _D, _D, _D, C.c_int32,
                                                  C.c_int64, _D, _I64]
@@ -371,6 +374,19 @@ def gravity_tree(x, y, z, m, eps=0.01, theta=0.5, leaf_size=32, group_work=False
     return gx, gy, gz, sc, stats
 
 
+def gravity_tree_groups(x, y, z, m, leaf_size=16):
+    """The oracle octree's groups: (starts, ends) as runs of the sorted
+    order, and order[k] = the particle at sorted position k."""
+    n = len(x)
+    cap = 8 * n + 16
+    gs, ge = np.zeros(cap, dtype=np.int64), np.zeros(cap, dtype=np.int64)
+    order = np.zeros(max(n, 1), dtype=np.int64)
+    ng = lib().orc_gravity_tree_groups(n, _d(x), _d(y), _d(z), _d(m), int(leaf_size), cap,
+                                       gs, ge, order)
+    assert ng >= 0
+    return gs[:ng].copy(), ge[:ng].copy(), order[:n]
+
+
 def gravity_tree_nodes(x, y, z, m, leaf_size=32):
     """The oracle's octree: (nodes [k, 16] = M, c, Q, s, delta, level, start,
     end, nchild; order[k] = particle at sorted position k)."""
@@ -438,7 +454,7 @@ class OracleRun:
                            self.acc["ay"], self.acc["az"], self.params, self.g)
         return self
 
-    def step_blocks(self, max_bin):
+    def step_blocks(self, max_bin, trace=None):
         """One step with individual time steps in power-of-two bins (the
         scaling lever named next to the global dt in Table 1 and Table 2).
         From the synchronised state: D and the bins from the per-particle
@@ -452,7 +468,10 @@ class OracleRun:
         velocities, as in the global step, and their closing half kick.
         max_bin = 0 is the global step. IAD is not supported here (its
         matrices would need every neighbour's list). Returns (D, bins,
-        substeps)."""
+        substeps). trace (a list, optional) receives per substep a dict of
+        copies: sub, end (the closing mask), x, y, z, rho, p, c, pr2, the
+        accelerations after the substep's evaluation, and the velocities and
+        internal energies it used."""
         lo, hi, per = self.box
         s, a = self.s, self.acc
         dtc = timestep_each(s["h"], self.c, a["mumax"], a["ax"], a["ay"], a["az"],
@@ -499,6 +518,13 @@ class OracleRun:
                                   s["h"], s["m"], self.rho, self.c, self.pr2, lo, hi, per,
                                   off, ids, prm, X=X)
             self.acc = {k: np.where(end, acc[k], self.acc[k]) for k in self.acc}
+            if trace is not None:
+                trace.append(dict(sub=sub, end=end.copy(), x=s["x"].copy(), y=s["y"].copy(),
+                                  z=s["z"].copy(), rho=self.rho.copy(), p=self.p.copy(),
+                                  c=self.c.copy(), pr2=self.pr2.copy(),
+                                  acc={k: v.copy() for k, v in self.acc.items()},
+                                  vel={k: s[k].copy() for k in ("vx", "vy", "vz")},
+                                  u=s["u"].copy()))
             kick(end)
         self.t += D
         self.steps += 1

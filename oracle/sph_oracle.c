@@ -595,7 +595,15 @@ void orc_eos(int64_t n, int32_t eos, double rho0, double c0, double gamma_tait,
  * Integral approach to derivatives (Garcia-Senz, Cabezon & Escartin 2012),
  * with standard volume elements V_j = m_j / rho_j:
  *   tau_i = sum_{j in N_i} V_j (x_j - x_i)(x_j - x_i)^T W(r_ij, h_i),
- *   c_i   = tau_i^{-1}  (zero when tau_i is singular),
+ *   c_i   = tau_i^{-1}  when det tau_i >= k_c (tr tau_i / 3)^3,
+ * with k_c = 1e-2 (a reading: the paper gives no rule for the degenerate
+ * case). For a symmetric positive semi-definite tau the ratio
+ * det / (tr / 3)^3 lies in [0, 1] (the arithmetic-geometric mean inequality
+ * on the eigenvalues), equals 1 for an isotropic neighbourhood and tends to
+ * 0 when the neighbours no longer span three dimensions; there the inverse
+ * is set by rounding alone. Below the threshold c_i takes the isotropic form
+ * (tr tau_i / 3)^{-1} I, which the full inverse also reduces to for an
+ * isotropic tau; c_i = 0 when tr tau_i = 0 (no neighbour inside 2 h_i).
  *   A_ij  = c_i (x_j - x_i) W(r_ij, h_i),
  * so that sum_j V_j (f_j - f_i) A_ij is exact for linear f. A_ij takes the
  * place of grad_i W_ij; the pair forces use the antisymmetric mean
@@ -603,6 +611,7 @@ void orc_eos(int64_t n, int32_t eos, double rho0, double c0, double gamma_tait,
  * c6 holds c_i as xx, xy, xz, yy, yz, zz (6 doubles per particle).
  */
 static int32_t g_gradient = 0;   /* 0 kernel derivatives, 1 IAD */
+#define ORC_IAD_COND 1e-2        /* k_c of the conditioning rule above */
 
 int32_t orc_set_gradient(int32_t mode)
 {
@@ -635,9 +644,14 @@ void orc_iad_matrices(int64_t n, const double *x, const double *y, const double 
         }
         double cof_a = d * f - e * e, cof_b = c * e - bb * f, cof_c = bb * e - c * d;
         double det = a * cof_a + bb * cof_b + c * cof_c;
+        double tr = a + d + f;
         double *o = c6 + 6 * i;
-        if (!(det != 0.0) || !isfinite(det)) {
-            for (int t = 0; t < 6; ++t) o[t] = 0.0;
+        for (int t = 0; t < 6; ++t) o[t] = 0.0;
+        if (!(tr > 0.0) || !isfinite(tr) || !isfinite(det))
+            continue;                       /* no neighbour inside 2 h_i */
+        double tm = tr / 3.0;
+        if (!(det >= ORC_IAD_COND * (tm * tm * tm))) {
+            o[0] = o[3] = o[5] = 3.0 / tr;  /* isotropic form */
             continue;
         }
         o[0] = cof_a / det;
@@ -1166,23 +1180,12 @@ static orc_gnode *gtree_build(int64_t n, const double **P, const double *m,
     return T;
 }
 
-int64_t orc_gravity_tree(int64_t n, const double *x, const double *y, const double *z,
-                         const double *m, double eps, double theta, int32_t leaf_size,
-                         double *gx, double *gy, double *gz, double *scale, int64_t *stats,
-                         int64_t *group_work)
+/* The groups of the definition above, as runs [gs[q], ge[q]) of the sorted
+ * order (room for 8 nn + n / 64 + 2 entries); returns their number. */
+static int64_t gtree_groups(const orc_gnode *T, int64_t nn, int64_t n, int64_t *gs,
+                            int64_t *ge)
 {
-    if (n <= 0) return 0;
-    const double *P[3] = {x, y, z};
-    orc_kidx *srt;
-    int64_t nn;
-    orc_gnode *T = gtree_build(n, P, m, leaf_size, &srt, &nn);
-
-    /* groups, each walked breadth-first from the root */
-    int64_t n_leaf = 0, n_node_terms = 0, n_direct_terms = 0, max_front = 1;
-    for (int64_t t = 0; t < nn; ++t) n_leaf += T[t].nchild == 0;
     int64_t n_group = 0;
-    int64_t *gs = (int64_t *)malloc(sizeof(int64_t) * (size_t)(8 * nn + n / ORC_GROUP + 2));
-    int64_t *ge = (int64_t *)malloc(sizeof(int64_t) * (size_t)(8 * nn + n / ORC_GROUP + 2));
     if (n <= ORC_GROUP) {
         gs[0] = 0;
         ge[0] = n;
@@ -1213,6 +1216,54 @@ int64_t orc_gravity_tree(int64_t n, const double *x, const double *y, const doub
         }
         if (cs >= 0) { gs[n_group] = cs; ge[n_group++] = ce; }
     }
+    return n_group;
+}
+
+/* The groups of the tree of the particles (for the tests): starts and ends
+ * in sorted positions (cap entries each) and order[k] = the particle at
+ * sorted position k. Returns the number of groups, or -1 if cap is short. */
+int64_t orc_gravity_tree_groups(int64_t n, const double *x, const double *y, const double *z,
+                                const double *m, int32_t leaf_size, int64_t cap,
+                                int64_t *gs_out, int64_t *ge_out, int64_t *order)
+{
+    if (n <= 0) return 0;
+    const double *P[3] = {x, y, z};
+    orc_kidx *srt;
+    int64_t nn;
+    orc_gnode *T = gtree_build(n, P, m, leaf_size, &srt, &nn);
+    int64_t room = 8 * nn + n / ORC_GROUP + 2;
+    int64_t *gs = (int64_t *)malloc(sizeof(int64_t) * (size_t)room);
+    int64_t *ge = (int64_t *)malloc(sizeof(int64_t) * (size_t)room);
+    int64_t ng = gtree_groups(T, nn, n, gs, ge);
+    if (ng <= cap) {
+        memcpy(gs_out, gs, sizeof(int64_t) * (size_t)ng);
+        memcpy(ge_out, ge, sizeof(int64_t) * (size_t)ng);
+        for (int64_t k = 0; k < n; ++k) order[k] = srt[k].idx;
+    }
+    free(gs);
+    free(ge);
+    free(T);
+    free(srt);
+    return ng <= cap ? ng : -1;
+}
+
+int64_t orc_gravity_tree(int64_t n, const double *x, const double *y, const double *z,
+                         const double *m, double eps, double theta, int32_t leaf_size,
+                         double *gx, double *gy, double *gz, double *scale, int64_t *stats,
+                         int64_t *group_work)
+{
+    if (n <= 0) return 0;
+    const double *P[3] = {x, y, z};
+    orc_kidx *srt;
+    int64_t nn;
+    orc_gnode *T = gtree_build(n, P, m, leaf_size, &srt, &nn);
+
+    /* groups, each walked breadth-first from the root */
+    int64_t n_leaf = 0, n_node_terms = 0, n_direct_terms = 0, max_front = 1;
+    for (int64_t t = 0; t < nn; ++t) n_leaf += T[t].nchild == 0;
+    int64_t *gs = (int64_t *)malloc(sizeof(int64_t) * (size_t)(8 * nn + n / ORC_GROUP + 2));
+    int64_t *ge = (int64_t *)malloc(sizeof(int64_t) * (size_t)(8 * nn + n / ORC_GROUP + 2));
+    int64_t n_group = gtree_groups(T, nn, n, gs, ge);
     const double e2 = eps * eps;
     #pragma omp parallel for schedule(dynamic, 16) reduction(+ : n_node_terms, n_direct_terms) reduction(max : max_front)
     for (int64_t q = 0; q < n_group; ++q) {

@@ -446,8 +446,15 @@ struct MomParams {
 
 // IAD matrices (integral approach to derivatives, standard volume elements):
 // tau_i = sum_j V_j d d^T W(r, h_i) over the lane's list, d = x_i - x_j
-// (the sign cancels), c_i = tau_i^{-1} as xx xy xz yy yz zz, zero when tau_i
-// is singular. Records {x, y, z, V = m / rho}, one lane per particle, FP64.
+// (the sign cancels), c_i = tau_i^{-1} as xx xy xz yy yz zz. The inverse is
+// taken only where det tau_i >= kIadCond (tr tau_i / 3)^3: for a positive
+// semi-definite tau that ratio lies in [0, 1], is 1 for an isotropic
+// neighbourhood and tends to 0 as the neighbours stop spanning three
+// dimensions, where the inverse would be set by rounding alone. Below it
+// c_i = (tr tau_i / 3)^-1 I (what the inverse is for an isotropic tau), and
+// c_i = 0 without a neighbour inside 2 h_i (tr tau_i = 0).
+// Records {x, y, z, V = m / rho}, one lane per particle, FP64.
+constexpr double kIadCond = 1e-2;
 // Near free surfaces tau_i can be close to singular, and its inverse then
 // magnifies last-bit differences. So the matrix is formed with correctly
 // rounded operations only (sqrt, division, no fused multiply-add), in the
@@ -564,9 +571,16 @@ iad_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ vrec,
     if (!active) return;
     const double ca = d * f - e * e, cb = c * e - b * f, cc = b * e - c * d;
     const double det = a * ca + b * cb + c * cc;
+    const double tr = a + d + f;
     double *o6 = c6 + 6 * i;
-    if (!(det != 0.0) || !isfinite(det)) {
-        for (int t = 0; t < 6; ++t) o6[t] = 0.0;
+    for (int t = 0; t < 6; ++t) o6[t] = 0.0;
+    // no neighbour inside 2 h_i: c_i = 0
+    if (!(tr > 0.0) || !isfinite(tr) || !isfinite(det)) return;
+    // neighbours that do not span three dimensions (det below kIadCond of
+    // (tr / 3)^3): the isotropic form (tr / 3)^-1 I
+    const double tm = tr / 3.0;
+    if (!(det >= kIadCond * (tm * tm * tm))) {
+        o6[0] = o6[3] = o6[5] = 3.0 / tr;
         return;
     }
     o6[0] = ca / det;
@@ -635,12 +649,18 @@ __device__ __forceinline__ void momentum_tile(
     const R fi = sg * (inv_hi * inv_hi) * (inv_hi * inv_hi);
     const R alpha = (R)prm.alpha, beta = (R)prm.beta, eta2 = (R)prm.eta2;
     R sx = 0, sy = 0, sz = 0, su = 0, mum = 0;
-    // IAD: the lane's own matrix, and the next neighbour's
-    R cix = 0, ciy = 0, ciz = 0, ciyy = 0, ciyz = 0, cizz = 0;
+    // IAD: the lane's own matrix, and the next neighbour's. The IAD gradient
+    // Abar_ij is formed in FP64 in both forms and rounded to FP32 like r_ij
+    // itself: c_i scales W(r, h_i) up to an O(1) weight (c_i ~ 1 / sum of
+    // V W r^2), so near the edge of the support, where an FP32 W(r, h) =
+    // (2 - q)^3 / 4 ... loses its relative accuracy to cancellation, an FP32
+    // gradient would be off by far more than the FP32 rounding of its size.
+    double cix = 0, ciy = 0, ciz = 0, ciyy = 0, ciyz = 0, cizz = 0;
+    const double inv_hid = IAD ? mp->inv_h : 0.0;
     if constexpr (IAD) {
         const double *cp = prm.iad_c + 6 * ii;
-        cix = (R)cp[0]; ciy = (R)cp[1]; ciz = (R)cp[2];
-        ciyy = (R)cp[3]; ciyz = (R)cp[4]; cizz = (R)cp[5];
+        cix = cp[0]; ciy = cp[1]; ciz = cp[2];
+        ciyy = cp[3]; ciyz = cp[4]; cizz = cp[5];
     }
     const int cnt = active ? min(count[ii], max_nb) : 0;
     int maxc = cnt;
@@ -700,9 +720,10 @@ __device__ __forceinline__ void momentum_tile(
         double2 q6 = make_double2(0.0, 0.0);                               // X Q
         if constexpr (GVE) q6 = *reinterpret_cast<const double2 *>(own + 96);
         if (k < cnt) {
-            const R dx = (R)img<Per>(mex - q0.x, im, 0);
-            const R dy = (R)img<Per>(mey - q0.y, im, 1);
-            const R dz = (R)img<Per>(mez - q1.x, im, 2);
+            const double dxd = img<Per>(mex - q0.x, im, 0);
+            const double dyd = img<Per>(mey - q0.y, im, 1);
+            const double dzd = img<Per>(mez - q1.x, im, 2);
+            const R dx = (R)dxd, dy = (R)dyd, dz = (R)dzd;
             const R r2 = fma_r(dz, dz, fma_r(dy, dy, dx * dx));
             // 1/r (0 for coincident particles, whose gradient term vanishes)
             const R rinv = r2 > R(0) ? fast_rsq(r2) : R(0);
@@ -710,22 +731,27 @@ __device__ __forceinline__ void momentum_tile(
             R dwbar, hbar;
             R gx = 0, gy = 0, gz = 0;  // IAD: Abar_ij
             if constexpr (IAD) {
-                const R hj = (R)q3.x, inv_hj = (R)q3.y;
-                const R wi = sg * (inv_hi * inv_hi * inv_hi) * shape_w<KF>(r * inv_hi, sn);
-                const R wj = sg * (inv_hj * inv_hj * inv_hj) * shape_w<KF>(r * inv_hj, sn);
-                const R cjx = (R)f0.x, cjy = (R)f0.y, cjz = (R)f1.x, cjyy = (R)f1.y,
-                        cjyz = (R)f2.x, cjzz = (R)f2.y;
-                const R tix = fma_r(ciz, dz, fma_r(ciy, dy, cix * dx));
-                const R tiy = fma_r(ciyz, dz, fma_r(ciyy, dy, ciy * dx));
-                const R tiz = fma_r(cizz, dz, fma_r(ciyz, dy, ciz * dx));
-                const R tjx = fma_r(cjz, dz, fma_r(cjy, dy, cjx * dx));
-                const R tjy = fma_r(cjyz, dz, fma_r(cjyy, dy, cjy * dx));
-                const R tjz = fma_r(cjzz, dz, fma_r(cjyz, dy, cjz * dx));
-                gx = R(-0.5) * fma_r(wj, tjx, wi * tix);
-                gy = R(-0.5) * fma_r(wj, tjy, wi * tiy);
-                gz = R(-0.5) * fma_r(wj, tjz, wi * tiz);
+                const double r2d = fma_r(dzd, dzd, fma_r(dyd, dyd, dxd * dxd));
+                const double rd = r2d * (r2d > 0.0 ? fast_rsq(r2d) : 0.0);
+                const double inv_hjd = q3.y;
+                const double sgd = KF == KF_M4 ? kInvPi : prm.sigma;
+                const double wi =
+                    sgd * (inv_hid * inv_hid * inv_hid) * shape_w<KF>(rd * inv_hid, sn);
+                const double wj =
+                    sgd * (inv_hjd * inv_hjd * inv_hjd) * shape_w<KF>(rd * inv_hjd, sn);
+                const double cjx = f0.x, cjy = f0.y, cjz = f1.x, cjyy = f1.y, cjyz = f2.x,
+                             cjzz = f2.y;
+                const double tix = fma_r(ciz, dzd, fma_r(ciy, dyd, cix * dxd));
+                const double tiy = fma_r(ciyz, dzd, fma_r(ciyy, dyd, ciy * dxd));
+                const double tiz = fma_r(cizz, dzd, fma_r(ciyz, dyd, ciz * dxd));
+                const double tjx = fma_r(cjz, dzd, fma_r(cjy, dyd, cjx * dxd));
+                const double tjy = fma_r(cjyz, dzd, fma_r(cjyy, dyd, cjy * dxd));
+                const double tjz = fma_r(cjzz, dzd, fma_r(cjyz, dyd, cjz * dxd));
+                gx = (R)(-0.5 * fma_r(wj, tjx, wi * tix));
+                gy = (R)(-0.5 * fma_r(wj, tjy, wi * tiy));
+                gz = (R)(-0.5 * fma_r(wj, tjz, wi * tiz));
                 dwbar = R(0);
-                hbar = R(0.5) * (hi + hj);
+                hbar = R(0.5) * (hi + (R)q3.x);
             } else if constexpr (UH) {
                 dwbar = fi * shape_dw<KF>(r * inv_hi, sn);
                 hbar = hi;

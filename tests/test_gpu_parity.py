@@ -354,13 +354,20 @@ def test_gravity_direct(case):
 
 
 def _iad_case(name):
-    """Resolved inputs for IAD: the square patch, and the Evrard sphere and a
-    periodic cloud with h from the oracle's count iteration (about 100
-    gather neighbours each). On raw clouds where a particle's 2h sphere holds
-    a handful of particles tau_i is close to singular and its inverse
-    amplifies rounding: a property of the method on unresolved input."""
+    """Inputs for IAD: the square patch (free surfaces on x and y), the
+    Evrard sphere and a periodic cloud with h from the oracle's count
+    iteration (about 100 gather neighbours each), and raw clouds in open,
+    periodic-z and periodic boxes with h ~ U[0.02, 0.08], where about one
+    particle in seven has fewer than a handful of particles inside its own
+    2 h_i, so its tau_i is close to singular or exactly zero: there the
+    conditioning rule (isotropic form below det / (tr / 3)^3 = 0.01, zero
+    without a neighbour inside 2 h_i) decides c_i on both sides."""
     if name == "square_patch_c0":
         return I.square_patch(20), 128
+    if name.startswith("cloud_raw"):
+        per = {"cloud_raw_open": (0, 0, 0), "cloud_raw_z": (0, 0, 1),
+               "cloud_raw_xyz": (1, 1, 1)}[name]
+        return I.random_cloud(5000, seed=4, h_min=0.02, h_max=0.08, periodic=per), 256
     if name == "evrard_iter":
         ic = I.evrard(20000, seed=3)
     else:
@@ -370,7 +377,8 @@ def _iad_case(name):
 
 
 @pytest.mark.parametrize("family", [S.SPH_KERNEL_M4, S.SPH_KERNEL_WENDLAND_C2, S.SPH_KERNEL_SINC])
-@pytest.mark.parametrize("name", ["square_patch_c0", "evrard_iter", "cloud_iter"])
+@pytest.mark.parametrize("name", ["square_patch_c0", "evrard_iter", "cloud_iter",
+                                  "cloud_raw_open", "cloud_raw_z", "cloud_raw_xyz"])
 def test_iad_gradients(family, name):
     """Integral approach to derivatives (the SPHYNX gradients of Table 1):
     momentum and energy against the oracle with the same gradient and
@@ -401,8 +409,9 @@ def test_iad_gradients(family, name):
 
 def _gve_case(name):
     """Generalised volume elements with X = (m / rho)^0.7: the 20^3 patch and
-    a periodic-z cloud with masses varying by a factor three and h from the
-    oracle's count iteration (resolved, as IAD needs: see _iad_case)."""
+    a periodic-z cloud with masses varying by a factor three, with h from the
+    oracle's count iteration ("cloud") and raw ("cloud_raw", h ~ U[0.03,
+    0.07], where the IAD conditioning rule decides the sparse particles)."""
     import dataclasses
     if name == "square_patch_c0":
         ic = I.square_patch(20)
@@ -410,7 +419,9 @@ def _gve_case(name):
         ic = I.random_cloud(4000, seed=17, h_min=0.03, h_max=0.07, velocity=2.0,
                             periodic=(0, 0, 1))
         ic.m = ic.m * np.random.default_rng(5).uniform(0.5, 1.5, ic.n)
-        ic.h, _, _ = O.smoothing_length(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi, ic.periodic)
+        if name == "cloud":
+            ic.h, _, _ = O.smoothing_length(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi,
+                                            ic.periodic)
     ic.params = dataclasses.replace(ic.params, volume=S.SPH_VOLUME_GENERALISED, volume_p=0.7)
     return ic
 
@@ -435,7 +446,7 @@ def test_gve_volume_weights(name):
 
 
 @pytest.mark.parametrize("gradient", [S.SPH_GRAD_KERNEL, S.SPH_GRAD_IAD])
-@pytest.mark.parametrize("name", ["square_patch_c0", "cloud"])
+@pytest.mark.parametrize("name", ["square_patch_c0", "cloud", "cloud_raw"])
 def test_gve_forces(name, gradient):
     """Generalised volume elements (SPHYNX, Table 1): density and
     momentum/energy against the oracle on the same weights, with kernel

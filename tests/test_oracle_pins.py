@@ -346,6 +346,36 @@ def test_T11_evrard_ic_and_h_iteration():
         assert (d2 < 4 * h[i] ** 2).sum() - 1 == cnt[i]
 
 
+def test_T11_h_update_closed_form():
+    """One and two sweeps of the count-based h update on the 16^3 periodic
+    power-of-two lattice, where every gather count is known exactly:
+    h = 1.5 D gives 92 (|n|^2 < 9 on the integer lattice), below the band
+    [95, 105], so h <- h (1 + (100/92)^(1/3)) / 2 = 1.5211 D; at that h the
+    shell |n|^2 = 9 (30 points) is inside, 122 neighbours, above the band,
+    so the second sweep gives h (1 + (100/122)^(1/3)) / 2. A count inside the
+    band leaves h alone, and an empty sphere doubles h. (A wrong factor that
+    still converges would pass the band test above but not this one.)"""
+    lat = I.lattice_periodic(16, spacing=2.0 ** -4)
+    h0 = lat.h.copy()
+    args = (lat.x, lat.y, lat.z)
+    box = (lat.lo, lat.hi, lat.periodic)
+    h1, c1, sw = O.smoothing_length(*args, h0, *box, n_target=100, max_iter=1)
+    want1 = 1.5 * 2.0 ** -4 * 0.5 * (1.0 + (100.0 / 92.0) ** (1.0 / 3.0))
+    assert sw == 1 and (c1 == 122).all()
+    assert np.all(np.abs(h1 / want1 - 1.0) <= 4.5e-16)
+    h2, c2, sw = O.smoothing_length(*args, h0, *box, n_target=100, max_iter=2)
+    want2 = h1[0] * 0.5 * (1.0 + (100.0 / 122.0) ** (1.0 / 3.0))
+    assert sw == 2 and np.all(np.abs(h2 / want2 - 1.0) <= 4.5e-16)
+    # inside the band: nothing to do
+    h3, c3, sw = O.smoothing_length(*args, h0, *box, n_target=92, lo_count=90,
+                                    hi_count=95, max_iter=5)
+    assert sw == 0 and np.array_equal(h3, h0) and (c3 == 92).all()
+    # empty spheres double (h = 0.3 D: no other node within 0.6 D)
+    h4, c4, sw = O.smoothing_length(*args, np.full(lat.n, 0.3 * 2.0 ** -4), *box,
+                                    n_target=100, max_iter=1)
+    assert sw == 1 and np.array_equal(h4, np.full(lat.n, 0.6 * 2.0 ** -4))
+
+
 # --------------------------------------------------------------- T12 -------
 def test_T12_isolated_particle_timestep():
     p = I.SphParams()
@@ -492,6 +522,7 @@ def test_iad_matrices_invert_tau(iad_gradient):
     L = np.asarray(ic.hi) - np.asarray(ic.lo)
     P = np.stack([ic.x, ic.y, ic.z], 1)
     avec = np.array([0.3, -1.2, 0.7])
+    checked = 0
     for i in range(0, ic.n, 37):
         js = ids[off[i]:off[i + 1]]
         d = P[js] - P[i]
@@ -503,10 +534,78 @@ def test_iad_matrices_invert_tau(iad_gradient):
         tau = tau.sum(0)
         c = np.array([[c6[i, 0], c6[i, 1], c6[i, 2]], [c6[i, 1], c6[i, 3], c6[i, 4]],
                       [c6[i, 2], c6[i, 4], c6[i, 5]]])
+        tr = np.trace(tau)
+        ratio = np.linalg.det(tau) / (tr / 3) ** 3
+        if ratio < 1.1e-2:     # the conditioning rule (tested on its own below)
+            continue
+        checked += 1
         assert np.abs(c @ tau - np.eye(3)).max() < 1e-9
         A = (c @ (d * w[:, None]).T).T          # A_ij = c_i (x_j - x_i) W_ij
         grad = ((v * (d @ avec))[:, None] * A).sum(0)
         assert np.abs(grad - avec).max() < 1e-9
+    assert checked >= 30
+
+
+def _iad_one(P, V, h):
+    """IAD matrix of particle 0 of the points P (rows) with volumes V and
+    smoothing lengths h, through the oracle (open box, particle 0's list is
+    every other point with r < 2 max(h_0, h_j))."""
+    n = len(P)
+    m = V.copy()                  # m / rho = V with rho = 1
+    off, ids = O.neighbors(P[:, 0], P[:, 1], P[:, 2], h, (-5.0,) * 3, (5.0,) * 3, (0, 0, 0))
+    c6 = O.iad_matrices(P[:, 0], P[:, 1], P[:, 2], h, m, np.ones(n), (-5.0,) * 3,
+                        (5.0,) * 3, (0, 0, 0), off, ids)
+    return c6[0], ids[off[0]:off[1]]
+
+
+def test_iad_conditioning_rule(iad_gradient):
+    """The IAD conditioning reading: c_i = tau_i^{-1} only where
+    det tau_i >= 0.01 (tr tau_i / 3)^3, else (tr tau_i / 3)^{-1} I, and zero
+    without a neighbour inside 2 h_i. Pinned on hand-built neighbourhoods
+    whose tau is known in closed form:
+    - six neighbours at +-s on the three axes, all at distance s: tau is
+      2 V W(s) s^2 I, the ratio is 1 and c = I / (2 V W(s) s^2);
+    - four neighbours at +-s on x and y only (a plane): tau has rank 2 (the
+      ratio is exactly 0), so c = 3 / (4 V W(s) s^2) I, not the garbage
+      inverse of a rounded singular matrix;
+    - the same plane with two neighbours at +-t s on z: the ratio is
+      tau_zz / ... in closed form, and the rule switches exactly where it
+      crosses 0.01 (checked on both sides of the switch);
+    - neighbours only outside 2 h_i (in the list through their larger h_j):
+      W(r, h_i) = 0 for all, tr = 0 and c = 0."""
+    h0, s, V = 0.5, 0.6, 0.37
+    w = O.kernel_w(s, h0)
+    ax = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], float)
+    P = np.vstack([[0, 0, 0], s * ax])
+    c6, nb = _iad_one(P, np.full(7, V), np.full(7, h0))
+    assert len(nb) == 6
+    want = 1.0 / (2 * V * w * s * s)
+    assert np.allclose(c6, [want, 0, 0, want, 0, want], rtol=1e-14, atol=0)
+    P = np.vstack([[0, 0, 0], s * ax[:4]])
+    c6, nb = _iad_one(P, np.full(5, V), np.full(5, h0))
+    assert len(nb) == 4
+    want = 3.0 / (4 * V * w * s * s)
+    assert np.allclose(c6, [want, 0, 0, want, 0, want], rtol=1e-14, atol=0)
+    # tau = V diag(2 w s^2, 2 w s^2, 2 w_t (t s)^2): ratio = 27 a a b / (2a + b)^3
+    for t, above in ((0.10, True), (0.01, False)):
+        wt = O.kernel_w(t * s, h0)
+        a_, b_ = 2 * V * w * s * s, 2 * V * wt * (t * s) ** 2
+        ratio = 27 * a_ * a_ * b_ / (2 * a_ + b_) ** 3
+        assert (ratio >= 0.01) == above
+        P = np.vstack([[0, 0, 0], s * ax[:4], [[0, 0, t * s], [0, 0, -t * s]]])
+        c6, nb = _iad_one(P, np.full(7, V), np.full(7, h0))
+        assert len(nb) == 6
+        if above:
+            want = [1 / a_, 0, 0, 1 / a_, 0, 1 / b_]
+        else:
+            iso = 3.0 / (2 * a_ + b_)
+            want = [iso, 0, 0, iso, 0, iso]
+        assert np.allclose(c6, want, rtol=1e-13, atol=0)
+    # neighbours at 1.5 (beyond 2 h_0 = 1.0, inside 2 h_j = 2.0)
+    P = np.vstack([[0, 0, 0], 1.5 * ax])
+    h = np.array([h0] + [1.0] * 6)
+    c6, nb = _iad_one(P, np.full(7, V), h)
+    assert len(nb) == 6 and np.array_equal(c6, np.zeros(6))
 
 
 def test_iad_symmetry_invariants(iad_gradient):
@@ -734,6 +833,58 @@ def test_gravity_tree_moments_and_structure():
             assert all(lev[a] == lev[t] + 1 for a in kids)
 
 
+def test_gravity_tree_groups_hand_built():
+    """The octree's group rule (R19), on particles placed in known octants
+    of the unit cube (anchors at (0,0,0) and (1,1,1) fix the cube), counts
+    per root octant 10, 20, 40, 150, 100, 5, 5, 70: octant 3's 150 share one
+    finest-level cell (a leaf of level 10), octant 4's 100 sit in its
+    sub-octants 0, 1, 2 (30, 30, 40) and octant 7's 70 in sub-octants 0 and
+    7 (35 each). By the rule: the root's children packed in octant order
+    while the run holds <= 64 give {0,1}, {2}, {5,6}; octant 4's children
+    {0,1}, {2}; octant 7's {0}, {7}; the finest leaf is cut into 64, 64,
+    22. Sorted positions follow the octant order."""
+    rng = np.random.default_rng(3)
+    pts, tag = [], []
+
+    def box(corner, side, k, label, lo=0.1, hi=0.9):
+        for _ in range(k):
+            pts.append(np.asarray(corner) + side * rng.uniform(lo, hi, 3))
+            tag.append(label)
+
+    def octc(o, base=(0.0, 0.0, 0.0), side=0.5):
+        return np.asarray(base) + side * np.array([o & 1, (o >> 1) & 1, (o >> 2) & 1])
+
+    pts.append(np.zeros(3)); tag.append(0)
+    box(octc(0), 0.5, 9, 0)
+    box(octc(1), 0.5, 20, 1)
+    box(octc(2), 0.5, 40, 2)
+    box((0.6995, 0.6995, 0.1995), 0.0005, 150, 3, 0.0, 1.0)
+    for sub, k in ((0, 30), (1, 30), (2, 40)):
+        box(octc(sub, octc(4), 0.25), 0.25, k, 40 + sub)
+    box(octc(5), 0.5, 5, 5)
+    box(octc(6), 0.5, 5, 6)
+    box(octc(0, octc(7), 0.25), 0.25, 35, 70)
+    box(octc(7, octc(7), 0.25), 0.25, 34, 77)
+    pts.append(np.ones(3)); tag.append(77)
+    P, tag = np.array(pts), np.array(tag)
+    assert len(P) == 400
+    gs, ge, order = O.gravity_tree_groups(P[:, 0], P[:, 1], P[:, 2], np.ones(400), 16)
+    got = sorted(zip(gs.tolist(), ge.tolist()))
+    want = sorted([(0, 30), (30, 70), (320, 330), (220, 280), (280, 320), (330, 365),
+                   (365, 400), (70, 134), (134, 198), (198, 220)])
+    assert got == want
+    # the sorted order is the octant order
+    st = tag[order]
+    bounds = {0: (0, 10), 1: (10, 30), 2: (30, 70), 3: (70, 220), 40: (220, 250),
+              41: (250, 280), 42: (280, 320), 5: (320, 325), 6: (325, 330), 70: (330, 365),
+              77: (365, 400)}
+    for t, (a, b) in bounds.items():
+        assert (st[a:b] == t).all(), t
+    # a cloud of at most 64 particles is one group
+    gs, ge, _ = O.gravity_tree_groups(P[:64, 0], P[:64, 1], P[:64, 2], np.ones(64), 16)
+    assert gs.tolist() == [0] and ge.tolist() == [64]
+
+
 def test_gravity_tree_quadrupole_convergence():
     """A cluster of 192 particles seen from 64 light probes at distance D:
     the cluster's node is accepted and its monopole plus quadrupole leave an
@@ -820,3 +971,60 @@ def test_blocks_isolated_particles_follow_the_closed_form():
         want = x0[k] + x0[v] * D + 0.5 * g[q] * D * D
         assert np.allclose(r.s[k], want, rtol=0, atol=1e-14 * (1 + np.abs(want)).max())
         assert np.allclose(r.s[v], x0[v] + g[q] * D, rtol=0, atol=1e-14)
+
+
+def _m4_density_numpy(P, h, m):
+    """Summation density by brute force in numpy: rho_i = sum_j m_j W(r_ij,
+    h_i), self term included, M4 with sigma = 1/pi (open box)."""
+    d = np.sqrt(((P[:, None, :] - P[None, :, :]) ** 2).sum(-1))
+    q = d / h[:, None]
+    w = np.where(q < 1, 1 - 1.5 * q ** 2 + 0.75 * q ** 3,
+                 np.where(q < 2, 0.25 * np.clip(2 - q, 0, None) ** 3, 0.0))
+    return (w * m[None, :]).sum(1) / (np.pi * h ** 3)
+
+
+def test_blocks_stale_fields_of_waiting_particles():
+    """Individual time steps (R20): in a substep, the particles whose step
+    does not close keep the density, pressure and sound speed of their last
+    evaluation, bit for bit, while the closing ones get the density of the
+    drifted positions (checked against a brute-force numpy sum) and forces
+    computed with the neighbours' stale fields. A 3,000-particle Evrard
+    sphere in its own field with max_bin = 3 has particles in three bins, so
+    substeps 0 and 2 close only the deepest bin. Re-evaluating everyone
+    would give other forces on the closing particles (checked too)."""
+    ic = I.evrard(3000, seed=2)
+    ic.h, _, _ = O.smoothing_length(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi, ic.periodic)
+    g = O.gravity_direct(ic.x, ic.y, ic.z, ic.m, 0.01)
+    r = O.OracleRun(ic, g=g).init()
+    rho_prev = {"rho": r.rho.copy(), "c": r.c.copy(), "pr2": r.pr2.copy()}
+    tr = []
+    D, b, subs = r.step_blocks(3, trace=tr)
+    assert subs == 4 and len(set(b.tolist())) == 3
+    prm = ic.params
+    changed = 0
+    for t in tr:
+        end = t["end"]
+        wait = ~end
+        if t["sub"] in (0, 2):
+            assert 0 < end.sum() < ic.n
+        for k in ("rho", "c", "pr2"):
+            assert np.array_equal(t[k][wait], rho_prev[k][wait]), (t["sub"], k)
+        P = np.stack([t["x"], t["y"], t["z"]], 1)
+        rho_np = _m4_density_numpy(P, ic.h, ic.m)
+        assert np.allclose(t["rho"][end], rho_np[end], rtol=1e-13, atol=0)
+        off, ids = O.neighbors(t["x"], t["y"], t["z"], ic.h, ic.lo, ic.hi, ic.periodic)
+        args = (t["x"], t["y"], t["z"], t["vel"]["vx"], t["vel"]["vy"], t["vel"]["vz"],
+                ic.h, ic.m)
+        mixed = O.momentum_energy(*args, t["rho"], t["c"], t["pr2"], ic.lo, ic.hi,
+                                  ic.periodic, off, ids, prm)
+        for k in ("ax", "ay", "az", "dudt"):
+            assert np.array_equal(mixed[k][end], t["acc"][k][end]), (t["sub"], k)
+        if wait.any():
+            p_all, c_all, pr2_all = O.eos(prm, rho_np, t["u"], r.rho_ref, ic.p_bg)
+            fresh = O.momentum_energy(*args, rho_np, c_all, pr2_all, ic.lo, ic.hi,
+                                      ic.periodic, off, ids, prm)
+            changed += int(np.sum(np.abs(fresh["ax"][end] - t["acc"]["ax"][end])
+                                  > 1e-9 * np.abs(t["acc"]["ax"][end]).max()))
+        for k in ("rho", "c", "pr2"):
+            rho_prev[k] = t[k].copy()
+    assert changed > 0
