@@ -231,6 +231,33 @@ sph_status sph_density(sph_ctx ctx, const sph_particles *p,
                        const sph_box *box, const sph_nbrs *nb,
                        const sph_params *prm, double *rho);
 
+/* sph_density for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and kernels as sph_density, with no context. It calls
+ * no hipMalloc, hipFree or other allocating routine; its scratch (the packed
+ * neighbour records, 32 B per particle) is a static device array of
+ * SPH_DENSITY_NOALLOC_MAX_N records that every GPU the library runs on holds
+ * until the process ends (32 MiB).
+ *   p, nb: device arrays in the order the lists refer to (as left by
+ *          sph_build_cells and sph_find_neighbors); p->x, y, z, h, m are
+ *          read (and p->xw with generalised volume elements);
+ *   box:   the box of that build (its periodic axes and lengths are used);
+ *   rho:   device output, n doubles, bitwise the values sph_density writes
+ *          for the same inputs;
+ *   stream: a hipStream_t (NULL = the null stream) for the launches; the
+ *          current device must be the stream's.
+ * Asynchronous like the other calls. Errors (host-side only, nothing is
+ * launched): SPH_E_CAPACITY if p->n > SPH_DENSITY_NOALLOC_MAX_N,
+ * SPH_E_INVALID for NULL or malformed arguments, SPH_E_HIP for a launch or
+ * symbol failure; sph_last_error(NULL) gives the detail on the calling
+ * thread. Every call on one device shares that device's array, which keeps
+ * the last call's records: calls that overlap on one device (two streams,
+ * two threads) race and must be ordered by the caller. */
+#define SPH_DENSITY_NOALLOC_MAX_N 1048576
+sph_status sph_density_noalloc(const sph_particles *p, const sph_box *box,
+                               const sph_nbrs *nb, const sph_params *prm,
+                               double *rho, sph_stream stream);
+
 /* Algorithm 1, step 3: EOS. Reads f->rho and p->u (ideal) or p->rho_ref,
  * p->p_bg (Tait); writes f->p, f->c, f->pr2 (and the FP32 copies used by the
  * FP32-pair form). */

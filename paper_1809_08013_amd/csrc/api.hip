@@ -423,6 +423,35 @@ sph_status sph_density(sph_ctx ctx, const sph_particles *p, const sph_box *box,
     return SPH_OK;
 }
 
+sph_status sph_density_noalloc(const sph_particles *p, const sph_box *box, const sph_nbrs *nb,
+                               const sph_params *prm, double *rho, sph_stream stream)
+{
+    if (!p) return fail(nullptr, SPH_E_INVALID, "particles is NULL");
+    if (p->n < 0) return fail(nullptr, SPH_E_INVALID, "n = %lld < 0", (long long)p->n);
+    if (p->n > SPH_DENSITY_NOALLOC_MAX_N)
+        return fail(nullptr, SPH_E_CAPACITY,
+                    "n = %lld exceeds the %d particles of the static scratch",
+                    (long long)p->n, SPH_DENSITY_NOALLOC_MAX_N);
+    sph_status s;
+    if ((s = check_box(nullptr, box)) != SPH_OK) return s;
+    if ((s = check_params(nullptr, prm)) != SPH_OK) return s;
+    if (!nb) return fail(nullptr, SPH_E_INVALID, "nbrs is NULL");
+    if (p->n == 0) return SPH_OK;
+    if (nb->max_nb < 1) return fail(nullptr, SPH_E_INVALID, "max_nb = %d < 1", nb->max_nb);
+    if (!nb->count || !nb->idx) return fail(nullptr, SPH_E_INVALID, "count and idx are required");
+    if (!p->x || !p->y || !p->z || !p->h || !p->m || !rho)
+        return fail(nullptr, SPH_E_INVALID, "x, y, z, h, m and rho are required");
+    const bool gve = prm->volume == SPH_VOLUME_GENERALISED;
+    if (gve && !p->xw)
+        return fail(nullptr, SPH_E_INVALID, "generalised volume elements need p->xw");
+    DensRec *recs = nullptr;
+    SPH_HIP(nullptr, density_noalloc_scratch(&recs));
+    SPH_HIP(nullptr, launch_density_noalloc(static_cast<hipStream_t>(stream), *p, *nb,
+                                            box_grid(*box), prm->precision,
+                                            kernel_sel(*prm), gve, rho, recs));
+    return SPH_OK;
+}
+
 sph_status sph_volume_weights(sph_ctx ctx, const sph_particles *p, const double *rho,
                               double exponent)
 {

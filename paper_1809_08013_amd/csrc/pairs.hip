@@ -20,6 +20,7 @@
 //              rounded to FP32, FP32 copies of h, m, rho, P/rho^2 and c, FP32
 //              sums, outputs widened to FP64.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "sph_internal.h"
@@ -1046,6 +1047,55 @@ hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &n
     if (gve)
         gve_density_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, p.m, p.xw, rho,
                                                                           mask);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The density without allocation (sph_density_noalloc): the neighbour records
+// go to a file-scope device array of SPH_DENSITY_NOALLOC_MAX_N records (32 MiB),
+// which each GPU the library runs on holds until the process ends. In host
+// code the array's name is not a device address: the address is taken once
+// per device, with that device current, by hipGetSymbolAddress and kept; the
+// kernels receive it as their record pointer. Every call on a device shares
+// its array, so calls that overlap on one device race.
+static __device__ __align__(256) DensRec scratch[SPH_DENSITY_NOALLOC_MAX_N];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_scratch_mu;
+DensRec *g_scratch_ptr[kNoAllocDevices] = {};
+}  // namespace
+
+hipError_t density_noalloc_scratch(DensRec **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoAllocDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<DensRec *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_density_noalloc(hipStream_t stream, const sph_particles &p, const sph_nbrs &nb,
+                                  const Grid &g, int precision, const KernelSel &ks, bool gve,
+                                  double *rho, DensRec *recs)
+{
+    // the same kernels as launch_density, with recs (the device address of
+    // the static array) in place of the context's records
+    pack_dens_kernel<<<blocks_for(p.n, 256), 256, 0, stream>>>(p.n, nullptr, p.x, p.y, p.z,
+                                                                gve ? p.xw : p.m, recs);
+    density_launch<false>(stream, blocks_for(p.n, kThreads), precision, false, p.n, p.n, recs,
+                          p.h, nb.count, nb.idx, nb.max_nb, g, rho, BatchDev{}, ks);
+    if (gve)
+        gve_density_kernel<<<blocks_for(p.n, 256), 256, 0, stream>>>(p.n, p.m, p.xw, rho,
+                                                                      StepMask{});
     return hipGetLastError();
 }
 

@@ -294,6 +294,14 @@ hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &n
                           const StepMask &mask = StepMask{});
 hipError_t launch_volume_weights(sph_ctx ctx, const sph_particles &p, const double *rho,
                                  double exponent);
+// The density without allocation: the device address of the static record
+// array on the current device (taken once per device and kept), and the
+// density kernels run on it.
+hipError_t density_noalloc_scratch(DensRec **out);
+hipError_t launch_density_noalloc(hipStream_t stream, const sph_particles &p, const sph_nbrs &nb,
+                                  const Grid &g, int precision, const KernelSel &ks, bool gve,
+                                  double *rho, DensRec *recs);
+
 hipError_t launch_gravity_direct(sph_ctx ctx, const sph_particles &p, double eps, double *gx,
                                  double *gy, double *gz);
 // Octree gravity; *flags receives the capacity bits of the call (synchronises).

@@ -32,6 +32,7 @@ SPH_KICK_DRIFT, SPH_KICK = 0, 1
 SPH_KERNEL_M4, SPH_KERNEL_WENDLAND_C2, SPH_KERNEL_SINC = 0, 1, 2
 SPH_GRAD_KERNEL, SPH_GRAD_IAD = 0, 1
 SPH_VOLUME_STANDARD, SPH_VOLUME_GENERALISED = 0, 1
+SPH_DENSITY_NOALLOC_MAX_N = 1 << 20  # the static scratch of sph_density_noalloc
 
 _VP = C.c_void_p
 
@@ -132,6 +133,7 @@ def load():
             "sph_build_cells": (C.c_int32, [_VP, P, B, C.c_double]),
             "sph_find_neighbors": (C.c_int32, [_VP, P, B, N]),
             "sph_density": (C.c_int32, [_VP, P, B, N, M, _VP]),
+            "sph_density_noalloc": (C.c_int32, [P, B, N, M, _VP, _VP]),
             "sph_eos": (C.c_int32, [_VP, P, M, F]),
             "sph_gravity_direct": (C.c_int32, [_VP, P, C.c_double, _VP, _VP, _VP]),
             "sph_volume_weights": (C.c_int32, [_VP, P, _VP, C.c_double]),
@@ -323,6 +325,20 @@ def sph_find_neighbors(ctx: Context, st: SphState):
 def sph_density(ctx: Context, st: SphState, prm: Params):
     ctx.raise_on(ctx.lib.sph_density(ctx.h, C.byref(st.particles), C.byref(st.box),
                                      C.byref(st.nbrs), C.byref(prm), _ptr(st.t["rho"])))
+
+
+def sph_density_noalloc(st: SphState, prm: Params, rho, stream=None):
+    """The density through the entry point that allocates nothing (no
+    context; static device scratch): rho is a float64 device tensor of at
+    least st.n entries; st must hold lists from sph_find_neighbors."""
+    import torch
+    lib = load()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    s = lib.sph_density_noalloc(C.byref(st.particles), C.byref(st.box), C.byref(st.nbrs),
+                                C.byref(prm), _ptr(rho), _VP(stream.cuda_stream))
+    if s != SPH_OK:
+        raise SphError(s, lib.sph_last_error(None).decode())
 
 
 def sph_gravity_direct(ctx: Context, st: SphState, eps: float = 0.01):

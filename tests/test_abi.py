@@ -139,3 +139,27 @@ def test_smoothing_length_host_checks():
                                   C.byref(it)) == S.SPH_E_INVALID
     assert L.sph_step_blocks(None, None, None, 1.0, None, None, None, None, 2, None, None,
                              None, C.byref(it)) == S.SPH_E_INVALID
+
+
+def test_density_noalloc_host_checks():
+    """The entry point that allocates nothing rejects sizes beyond its static
+    scratch (SPH_E_CAPACITY) and malformed arguments on the host, before any
+    HIP call."""
+    L = _lib()
+    box = S.make_box((0.0,) * 3, (1.0,) * 3, (0, 0, 0))
+    prm = S.Params()
+    nb = S.Nbrs(128, None, None)
+    p = S.Particles(S.SPH_DENSITY_NOALLOC_MAX_N + 1)
+    assert L.sph_density_noalloc(C.byref(p), C.byref(box), C.byref(nb), C.byref(prm), None,
+                                 None) == S.SPH_E_CAPACITY
+    assert b"static scratch" in L.sph_last_error(None)
+    p = S.Particles(10)
+    assert L.sph_density_noalloc(None, C.byref(box), C.byref(nb), C.byref(prm), None,
+                                 None) == S.SPH_E_INVALID
+    assert L.sph_density_noalloc(C.byref(p), C.byref(box), C.byref(nb), C.byref(prm), None,
+                                 None) == S.SPH_E_INVALID
+    assert b"count and idx" in L.sph_last_error(None)
+    p0 = S.Particles(0)
+    assert L.sph_density_noalloc(C.byref(p0), C.byref(box), C.byref(nb), C.byref(prm), None,
+                                 None) == S.SPH_OK
+
