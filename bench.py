@@ -104,30 +104,43 @@ def kernel_model(n: int, pairs: float, candidates: float, precision: int) -> dic
     return {k: (per_particle_bytes[k] * n, flops.get(k, 0.0)) for k in CALLS}
 
 
-KERNEL_OF_CALL = {"find_neighbors": "find_neighbors_kernel", "density": "density_kernel",
-                  "momentum_energy": "momentum_kernel"}
+# the timed kernels (sph_ctx_kernel_time) and the call each belongs to
+TIMED_KERNELS = ("find_neighbors_kernel", "fallback_kernel", "density_kernel", "iad_kernel",
+                 "momentum_kernel")
+CALL_OF_KERNEL = {"find_neighbors_kernel": "find_neighbors", "fallback_kernel": "find_neighbors",
+                  "density_kernel": "density", "iad_kernel": "momentum_energy",
+                  "momentum_kernel": "momentum_energy"}
+# non-packed lane-instructions per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_LANE_INSTS_PER_S = 256 * 4 * 16 * 2.4e9
 
 
-def recorded_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/<kernel>_<workload>_counters.md), or None when there is none or
+def recorded_counters(kernel: str, workload: str) -> dict:
+    """Counter figures per launch of `kernel` from the committed summary
+    (profiles/<kernel>_<workload>_counters.md): HBM bytes (traffic) and
+    SQ_INSTS_VALU (valu_insts, wave-instructions); empty when there is none or
     the kernel source changed since the counters were taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     if not os.path.exists(path):
-        return None
+        return {}
     txt = open(path).read()
-    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     h = re.search(r"source_sha256:\s*([0-9a-f]{64})\s+(\S+)", txt)
-    if not m or not h:
-        return None
+    if not h:
+        return {}
     src = os.path.join(ROOT, h.group(2))
     if not os.path.exists(src):
-        return None
+        return {}
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
-        return None
-    return float(m.group(1))
+        return {}
+    out = {}
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if m:
+        out["traffic"] = float(m.group(1))
+    m = re.search(r"valu_insts_per_launch:\s*([0-9.eE+]+)", txt)
+    if m:
+        out["valu_insts"] = float(m.group(1))
+    return out
 
 
 def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=None,
@@ -193,12 +206,19 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
     S.sph_ctx_check(ctx)
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
               for _ in range(steps)]
+    ctx.timing(True)  # HIP events around the hot kernels, on the library's stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
         step(events[s])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ctx.timing(False)
+    kernel_ms = {}
+    for k in TIMED_KERNELS:
+        ms, launches = ctx.kernel_time(k)
+        if launches:
+            kernel_ms[k] = {"avg_ms": round(ms, 5), "launches": launches}
     S.sph_ctx_check(ctx)
     per_call = {k: 0.0 for k in names}
     for evs in events:
@@ -221,7 +241,7 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
     pairs = float(st.t["count"][: ic.n].sum().item())
     diag = st.diag
     return dict(ms_per_step=eager_ms, graph_ms_per_step=graph_ms,
-                per_call_ms=per_call,
+                per_call_ms=per_call, kernel_ms=kernel_ms,
                 candidates=stencil_candidates(ic),
                 pairs_per_step=pairs, dt=st.dt, diag=diag.tolist(), diag0=diag0,
                 max_count=int(st.t["count"][: ic.n].max().item()),
@@ -229,29 +249,42 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
 
 
 def roofline(n: int, r: dict, precision: int, workload: str | None = None) -> dict:
-    """Roofline of the dominant call's kernel (the call with the longest time
-    per launch): achieved = algorithmic bytes or flops per launch / measured
-    time per launch; bound = whichever of the two takes longer at peak."""
+    """HBM roofline of the dominant kernel: the timed kernel with the longest
+    mean duration per launch (HIP events around its launches on the library's
+    stream, over the timed steps). achieved = its call's algorithmic bytes per
+    launch (kernel_model: compulsory traffic, neighbour data from cache) / that
+    duration, against the 8 TB/s HBM peak. Beside it: the same kernel's share
+    of VALU issue from the committed SQ_INSTS_VALU counter (lane-instructions
+    per launch / duration / the chip's 39.3e12 non-packed lane-instructions
+    per second), and the counter traffic, both null when the kernel source has
+    changed since the counters were taken."""
     model = kernel_model(n, r["pairs_per_step"], r["candidates"], precision)
-    dom = max(CALLS, key=lambda k: r["per_call_ms"][k])
-    b, fl = model[dom]
-    t = r["per_call_ms"][dom] * 1e-3
+    km = r["kernel_ms"]
+    # kernel time per call; the dominant call's largest kernel is reported
+    # alone when it takes >= 95% of the call's kernel time (else the call's
+    # kernels together, e.g. the search's two kernels on the Evrard sphere)
+    per_call = {}
+    for k, v in km.items():
+        per_call.setdefault(CALL_OF_KERNEL[k], []).append(k)
+    call = max(per_call, key=lambda c: sum(km[k]["avg_ms"] for k in per_call[c]))
+    ks = sorted(per_call[call], key=lambda k: -km[k]["avg_ms"])
+    tot = sum(km[k]["avg_ms"] for k in ks)
+    if km[ks[0]]["avg_ms"] >= 0.95 * tot:
+        ks = ks[:1]
+    kern = "+".join(ks)
+    b, fl = model[call]
+    t = sum(km[k]["avg_ms"] for k in ks) * 1e-3
     gbs = b / t / 1e9
-    tfl = fl / t / 1e12
-    peak_fl = FP64_VECTOR_PEAK_TFLOPS if precision == 0 else FP32_VECTOR_PEAK_TFLOPS
-    alu_bound = fl / (peak_fl * 1e12) > b / (HBM_PEAK_GBS * 1e9)
-    kern = KERNEL_OF_CALL.get(dom, dom)
-    traffic = recorded_traffic(kern, workload) if (workload and precision == 0) else None
-    out = dict(kernel=kern, call=dom, ms_per_launch=round(r["per_call_ms"][dom], 4),
-               algorithmic_bytes=b, algorithmic_flops=fl,
-               hbm_gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
-               alu_tflops=round(tfl, 3), alu_frac=round(tfl / peak_fl, 4), traffic=traffic)
-    if alu_bound:
-        out.update(bound="alu", achieved=round(tfl, 3), peak=peak_fl, unit="TFLOP/s",
-                   frac=round(tfl / peak_fl, 4))
-    else:
-        out.update(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                   frac=round(gbs / HBM_PEAK_GBS, 4))
+    rec = (recorded_counters(kern, workload)
+           if (workload and precision == 0 and len(ks) == 1) else {})
+    valu = rec.get("valu_insts")
+    out = dict(kernel=kern, call=call, bound="hbm", achieved=round(gbs, 1),
+               peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+               traffic=rec.get("traffic"), ms_per_launch=round(t * 1e3, 5),
+               launches=km[ks[0]]["launches"], algorithmic_bytes=b,
+               valu_issue_frac=(round(valu * 64 / t / VALU_LANE_INSTS_PER_S, 4)
+                                if valu else None),
+               call_ms_per_launch=round(r["per_call_ms"][call], 5))
     return out
 
 
@@ -310,11 +343,13 @@ def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
     t_tree = (time.perf_counter() - t0) / reps
     th = st.host(["gx", "gy", "gz"])
     gd = np.sqrt(g[0] ** 2 + g[1] ** 2 + g[2] ** 2)
-    et = np.sqrt((th["gx"] - g[0]) ** 2 + (th["gy"] - g[1]) ** 2 + (th["gz"] - g[2]) ** 2) / gd
+    # |g| -> 0 at the centre, so errors are given in units of the mean |g|
+    et = np.sqrt((th["gx"] - g[0]) ** 2 + (th["gy"] - g[1]) ** 2
+                 + (th["gz"] - g[2]) ** 2) / float(np.mean(gd))
     tree = {"ms": t_tree * 1e3, "eps": 0.01, "theta": 0.5, "leaf_size": 16,
-            "rel_err_vs_direct_median": float(np.median(et)),
-            "rel_err_vs_direct_p99": float(np.percentile(et, 99)),
-            "rel_err_vs_direct_max": float(et.max()),
+            "err_vs_direct_in_mean_g_median": float(np.median(et)),
+            "err_vs_direct_in_mean_g_p99": float(np.percentile(et, 99)),
+            "err_vs_direct_in_mean_g_max": float(et.max()),
             "speedup_vs_direct": t_grav / t_tree}
     del ctx, st
     out = {"workload": f"Evrard-like sphere, {n:,} particles, rho ~ 1/r, ideal gas gamma=5/3, "
@@ -328,6 +363,9 @@ def run_evrard(steps: int, warmup: int, n: int = 1_000_000) -> dict:
         out[name] = {"value": res["pairs_per_step"] / (res["ms_per_step"] * 1e-3),
                      "ms_per_step": res["ms_per_step"],
                      "per_call_ms": {k: round(v, 4) for k, v in res["per_call_ms"].items()},
+                     "kernel_ms": res["kernel_ms"],
+                     "roofline": roofline(n, res, prec),
+                     "step_hbm": step_hbm(n, res, prec),
                      "mean_neighbours": res["pairs_per_step"] / n,
                      "max_neighbours": res["max_count"],
                      "h_iteration": res["h_iteration"]}
@@ -409,16 +447,23 @@ def run_large(n_side: int, steps: int, warmup: int) -> dict:
     n = ic.n
     out = {"workload": f"rotating square patch, {n_side}^3 = {n:,} particles, same physics "
                        "as the 1M case", "steps": steps, "warmup": warmup}
+    finals = {}
     for name, prec in (("fp32_pair", S.SPH_FP32_PAIR), ("fp64", S.SPH_FP64)):
         res = run_gpu(ic, prec, steps, warmup)
+        finals[name] = res["diag"]
         out[name] = {"value": res["pairs_per_step"] / (res["ms_per_step"] * 1e-3),
                      "ms_per_step": res["ms_per_step"],
                      "per_call_ms": {k: round(v, 4) for k, v in res["per_call_ms"].items()},
+                     "kernel_ms": res["kernel_ms"],
                      "roofline": roofline(n, res, prec),
                      "step_hbm": step_hbm(n, res, prec),
                      "drift": drift(res),
                      "mean_neighbours": res["pairs_per_step"] / n,
                      "scratch_bytes": res["scratch_bytes"]}
+    # after the same steps from the same state: FP32-pair totals against FP64
+    d32, d64 = finals["fp32_pair"], finals["fp64"]
+    out["fp32_vs_fp64"] = {"energy_rel": abs(d32[7] - d64[7]) / abs(d64[7]),
+                           "lz_rel": abs(d32[6] - d64[6]) / abs(d64[6])}
     return out
 
 
@@ -581,30 +626,14 @@ def run_kernels(ic, steps: int, warmup: int) -> dict:
     return out
 
 
-def run_trajectory(n_side: int, steps: int) -> dict:
-    """Per-field error of the GPU runs (FP64 and FP32-pair) against the FP64
-    oracle after `steps` KDK steps from the same state (each path with its own
-    rho_ref = rho(t = 0)). Fields: positions, velocities, u, rho; max and RMS
-    absolute errors, scaled by the field's RMS; totals drift from the FP64
-    on-device reductions."""
-    import numpy as np
-
-    import oracle as O
-    from paper_1809_08013_amd import inputs as I
+def gpu_trajectories(ic, steps: int) -> dict:
+    """The GPU half of the trajectory comparison: FP64 and FP32-pair runs of
+    `steps` KDK steps from the t = 0 state (rho_ref = rho(t = 0)); returns
+    each form's final fields (original order), dt and on-device totals."""
     from paper_1809_08013_amd import sph as S
-    ic = I.square_patch(n_side, seed=0)
-    log(f"trajectory: oracle {steps} steps, n={ic.n}")
-    t0 = time.perf_counter()
-    ref = O.OracleRun(ic).init()
-    for _ in range(steps):
-        ref.step()
-    t_cpu = time.perf_counter() - t0
-    refs = dict(ref.s)
-    refs["rho"] = ref.rho
-    out = {"workload": f"rotating square patch {n_side}^3, {steps} steps", "steps": steps,
-           "oracle_seconds": t_cpu}
+    out = {}
     for name, prec in (("fp64", S.SPH_FP64), ("fp32_pair", S.SPH_FP32_PAIR)):
-        log(f"trajectory: GPU {name}")
+        log(f"trajectory: GPU {name}, {steps} steps")
         ctx = S.Context(ic.n, 128)
         st = S.SphState(ic, 128)
         prm = S.make_params(ic.params, prec)
@@ -613,36 +642,81 @@ def run_trajectory(n_side: int, steps: int) -> dict:
         for _ in range(steps):
             S.sph_step(ctx, st, prm)
         S.sph_ctx_check(ctx)
-        got = st.host(["x", "y", "z", "vx", "vy", "vz", "u", "rho"])
-        d1 = st.diag
-        err = {}
-        for k in ("x", "y", "z", "vx", "vy", "vz", "u", "rho"):
-            d = got[k] - refs[k]
-            scale = float(np.sqrt(np.mean(refs[k] ** 2))) or 1.0
-            err[k] = {"max_abs": float(np.max(np.abs(d))), "rms_abs": float(np.sqrt(np.mean(d * d))),
-                      "max_rel_to_rms": float(np.max(np.abs(d))) / scale}
-        out[name] = {"errors": err, "dt_rel": abs(st.dt - ref.dt) / ref.dt,
-                     "energy_drift": abs(d1[7] - d0[7]) / abs(d0[7]),
-                     "lz_drift": abs(d1[6] - d0[6]) / abs(d0[6]),
-                     "px_drift_abs": abs(d1[1] - d0[1]), "py_drift_abs": abs(d1[2] - d0[2])}
+        out[name] = {"fields": st.host(["x", "y", "z", "vx", "vy", "vz", "u", "rho"]),
+                     "dt": st.dt, "diag0": d0, "diag": st.diag.copy()}
         del ctx, st
     return out
 
 
-def cpu_baseline(ic, steps: int) -> dict:
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(ic, traj_steps: int, gpu_traj: dict | None) -> tuple:
+    """The CPU baseline leg, the only part of this script that runs the
+    oracle: the FP64 oracle (OpenMP over particles, all host threads) takes
+    `traj_steps` full KDK steps of the 1M input after an untimed t = 0 force
+    evaluation; their rate is cpu_baseline.value. One more step on one thread
+    gives the one-core rate. The oracle's final state is the reference for the
+    per-field errors of the GPU trajectories (positions, velocities, u, rho:
+    max and RMS absolute error, max relative to the field's RMS) and of dt;
+    totals drift comes from the FP64 on-device reductions."""
+    import numpy as np
+
     import oracle as O
-    log(f"CPU oracle baseline, {steps} steps")
+    threads = O.num_threads()
+    log(f"CPU oracle: {traj_steps} steps on {threads} threads")
     run = O.OracleRun(ic).init()
     t0 = time.perf_counter()
     pairs = 0
-    for _ in range(steps):
+    for _ in range(traj_steps):
         run.step()
         pairs += run.n_pairs
     t = time.perf_counter() - t0
-    return dict(value=pairs / t, unit="pair-interactions/s", cores=O.num_threads(),
-                kind="oracle", ms_per_step=t * 1e3 / steps,
-                sample=f"{steps} full KDK steps of the same 1,000,000-particle input "
-                       f"(after an untimed t=0 force evaluation), FP64 oracle, OpenMP")
+    base = dict(value=pairs / t, unit="pair-interactions/s", cores=threads,
+                kind="oracle", ms_per_step=t * 1e3 / traj_steps, cpu_model=cpu_model(),
+                sample=f"{traj_steps} full KDK steps of the same 1,000,000-particle input "
+                       "(after an untimed t=0 force evaluation), FP64 oracle, OpenMP over "
+                       "particles; one_core: one more step on one thread")
+    # copies: the oracle integrates its state arrays in place
+    refs = {k: v.copy() for k, v in run.s.items()}
+    refs["rho"] = run.rho.copy()
+    ref_dt = run.dt
+    log("CPU oracle: one step on one thread")
+    O.num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        run.step()
+        t1 = time.perf_counter() - t0
+    finally:
+        O.num_threads(threads)
+    base["one_core"] = {"value": run.n_pairs / t1, "ms_per_step": t1 * 1e3, "cores": 1}
+    traj = None
+    if gpu_traj is not None:
+        traj = {"workload": f"rotating square patch, {ic.n:,} particles, {traj_steps} steps "
+                            "from the t = 0 state, GPU against the FP64 oracle",
+                "steps": traj_steps}
+        for name, g in gpu_traj.items():
+            err = {}
+            for k in ("x", "y", "z", "vx", "vy", "vz", "u", "rho"):
+                d = g["fields"][k] - refs[k]
+                scale = float(np.sqrt(np.mean(refs[k] ** 2))) or 1.0
+                err[k] = {"max_abs": float(np.max(np.abs(d))),
+                          "rms_abs": float(np.sqrt(np.mean(d * d))),
+                          "max_rel_to_rms": float(np.max(np.abs(d))) / scale}
+            d0, d1 = g["diag0"], g["diag"]
+            traj[name] = {"errors": err, "dt_rel": abs(g["dt"] - ref_dt) / ref_dt,
+                          "energy_drift": abs(d1[7] - d0[7]) / abs(d0[7]),
+                          "lz_drift": abs(d1[6] - d0[6]) / abs(d0[6]),
+                          "px_drift_abs": abs(d1[1] - d0[1]),
+                          "py_drift_abs": abs(d1[2] - d0[2])}
+    return base, traj
 
 
 def main():
@@ -651,24 +725,25 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n-side", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle leg (and with it the trajectory errors)")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--evrard", action="store_true",
-                    help="also time the 1,000,000-particle Evrard-like hydro step")
+    ap.add_argument("--no-evrard", action="store_true",
+                    help="skip the 1,000,000-particle Evrard-like sphere leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a known-size "
                          "reference for hardware byte counters)")
-    ap.add_argument("--trajectory", type=int, default=0, metavar="STEPS",
-                    help="also compare FP64 and FP32-pair GPU runs with the oracle after "
-                         "STEPS steps on the same patch")
+    ap.add_argument("--trajectory", type=int, default=50, metavar="STEPS",
+                    help="FP64 and FP32-pair GPU runs of STEPS steps compared with the "
+                         "oracle's (the CPU leg runs the oracle for as many steps; 0: the "
+                         "CPU leg times 3 steps and no trajectory is compared)")
     ap.add_argument("--serve-runs", type=int, default=512,
                     help="ensemble serving requests (0 skips the serving leg)")
     ap.add_argument("--no-kernels", action="store_true",
                     help="skip the timing of the Wendland C2 and sinc kernels")
-    ap.add_argument("--large", type=int, default=0, metavar="N_SIDE",
-                    help="also time a large square patch of N_SIDE^3 particles "
-                         "(400 gives 64,000,000), 20 steps after 2 warm-up steps")
+    ap.add_argument("--large", type=int, default=400, metavar="N_SIDE",
+                    help="the large square patch of N_SIDE^3 particles (400 gives "
+                         "64,000,000), 20 steps after 2 warm-up steps; 0 skips it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -719,6 +794,7 @@ def main():
             "max_neighbours": r64["max_count"],
         },
         "per_call_ms": {k: round(v, 4) for k, v in r64["per_call_ms"].items()},
+        "kernel_ms": r64["kernel_ms"],
         "roofline": roofline(n, r64, 0, f"square_patch_{args.n_side}"),
         "step_hbm": step_hbm(n, r64, 0),
         "drift": drift(r64),
@@ -730,21 +806,26 @@ def main():
             "graph_ms_per_step": r32["graph_ms_per_step"],
             "speedup_vs_fp64": r64["ms_per_step"] / r32["ms_per_step"],
             "per_call_ms": {k: round(v, 4) for k, v in r32["per_call_ms"].items()},
+            "kernel_ms": r32["kernel_ms"],
             "roofline": roofline(n, r32, 1),
             "step_hbm": step_hbm(n, r32, 1),
         }
     if not args.no_kernels:
         line["kernels"] = run_kernels(ic, min(args.steps, 20), 2)
-    if args.trajectory > 0:
-        line["trajectory"] = run_trajectory(args.n_side, args.trajectory)
+    traj = None
+    if args.trajectory > 0 and not args.no_cpu_baseline:
+        traj = gpu_trajectories(ic, args.trajectory)
     if args.serve_runs > 0:
         line["serving"] = run_serving(args.serve_runs)
-    if args.evrard:
+    if not args.no_evrard:
         line["evrard"] = run_evrard(args.steps, args.warmup)
     if args.large:
         line["large"] = run_large(args.large, 20, 2)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(ic, args.cpu_steps)
+        base, terr = cpu_leg(ic, args.trajectory if args.trajectory > 0 else 3, traj)
+        line["cpu_baseline"] = base
+        if terr is not None:
+            line["trajectory"] = terr
     print(json.dumps(line), flush=True)
 
 

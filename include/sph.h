@@ -34,8 +34,10 @@
  *     are structure-of-arrays, FP64 (int32 for id, count and idx), one entry
  *     per particle.
  *   - The library owns only the opaque context and its scratch (sort buffers,
- *     cell table, reduction partials, FP32 copies, status word), allocated
- *     once by sph_ctx_create for n_max particles. Step calls never allocate.
+ *     cell table, packed neighbour records with the FP32-pair form's FP32
+ *     copies, reduction partials, status word), allocated once by
+ *     sph_ctx_create for n_max particles. Step calls never allocate (the
+ *     octree gravity's buffers come with its first call).
  *   - Calls are asynchronous and ordered on the context's stream (borrowed,
  *     never destroyed by the library). Host-side argument errors return at
  *     once. Device-side conditions (neighbour overflow, h above the h_max the
@@ -158,8 +160,12 @@ enum { SPH_VOLUME_STANDARD = 0, SPH_VOLUME_GENERALISED = 1 };
 
 /* Scalar physics constants (host memory). precision selects the pair
  * arithmetic of sph_density and sph_momentum_energy: SPH_FP64, or
- * SPH_FP32_PAIR (separations formed in FP64 and rounded to FP32, FP32 copies
- * of h, m, rho, P/rho^2 and c, FP32 accumulation, results widened to FP64;
+ * SPH_FP32_PAIR (separations and velocity differences formed in FP64 and
+ * rounded to FP32; sph_momentum_energy packs FP32 copies of h, 1/h, m, rho,
+ * c and P/rho^2 next to the FP64 position and velocity into its neighbour
+ * records (80 B of a 128-byte line; with IAD the records stay FP64 and the
+ * IAD gradient is formed in FP64); FP32 pair arithmetic and accumulation,
+ * results widened to FP64;
  * the neighbour relation, the state, the integration and all reductions stay
  * FP64). kernel selects W and its gradient in both pair calls (zero, the
  * default of a zeroed struct, is M4); sinc_n is the sinc exponent, read only
@@ -205,6 +211,19 @@ sph_status sph_ctx_check(sph_ctx ctx);
 
 /* Bytes of device scratch held by ctx (host value). */
 int64_t sph_ctx_scratch_bytes(sph_ctx ctx);
+
+/* Live kernel timing, for measurement. With enable != 0 (which also clears
+ * the sums) every later launch, by this context, of the kernels
+ * find_neighbors_kernel, fallback_kernel, density_kernel, iad_kernel and
+ * momentum_kernel is bracketed by two HIP events on the context's stream (not
+ * inside sph_step_capture); enable = 0 stops. sph_ctx_kernel_time waits for
+ * the recorded launches and returns the named kernel's mean duration in ms
+ * and its launch count since timing was enabled (SPH_E_INVALID for another
+ * name). The events are created on the host (hipEventCreate), never
+ * device memory. */
+sph_status sph_ctx_timing(sph_ctx ctx, int32_t enable);
+sph_status sph_ctx_kernel_time(sph_ctx ctx, const char *kernel, double *avg_ms,
+                               int64_t *launches);
 
 /* Algorithm 1, step 1. Assign every particle to a cell of side
  * >= 2 h_max (1 + 1e-9), sort the particles by the cell's Morton key and,
@@ -259,8 +278,8 @@ sph_status sph_density_noalloc(const sph_particles *p, const sph_box *box,
                                double *rho, sph_stream stream);
 
 /* Algorithm 1, step 3: EOS. Reads f->rho and p->u (ideal) or p->rho_ref,
- * p->p_bg (Tait); writes f->p, f->c, f->pr2 (and the FP32 copies used by the
- * FP32-pair form). */
+ * p->p_bg (Tait); writes f->p, f->c, f->pr2 (FP64; the FP32-pair form's
+ * FP32 copies are made by sph_momentum_energy when it packs its records). */
 sph_status sph_eos(sph_ctx ctx, const sph_particles *p, const sph_params *prm,
                    const sph_fields *f);
 

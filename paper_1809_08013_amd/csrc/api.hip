@@ -88,7 +88,82 @@ Grid make_grid(const sph_box &b, double h_max, int64_t cell_cap, int max_axis)
 
 }  // namespace sph
 
+namespace sph {
+
+const char *const kTimedKernelNames[TK_COUNT] = {"find_neighbors_kernel", "fallback_kernel",
+                                                 "density_kernel", "iad_kernel",
+                                                 "momentum_kernel"};
+
+int ktime_begin(sph_ctx ctx, int id)
+{
+    KTimer &t = ctx->timer;
+    if (!t.on || ctx->capturing) return -1;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (t.pool.size() >= 2) {
+        a = t.pool.back();
+        t.pool.pop_back();
+        b = t.pool.back();
+        t.pool.pop_back();
+    } else if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        (void)hipGetLastError();
+        if (a) (void)hipEventDestroy(a);
+        return -1;
+    }
+    if (hipEventRecord(a, ctx->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        t.pool.push_back(a);
+        t.pool.push_back(b);
+        return -1;
+    }
+    t.pending.push_back(KTimer::Pending{id, a, b});
+    return (int)t.pending.size() - 1;
+}
+
+void ktime_end(sph_ctx ctx, int slot)
+{
+    if (slot < 0) return;
+    KTimer &t = ctx->timer;
+    if (hipEventRecord(t.pending[(size_t)slot].b, ctx->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        t.pending[(size_t)slot].id = -1;  // dropped when read
+    }
+}
+
+}  // namespace sph
+
 namespace {
+
+// Sum the durations of the pending timed launches (synchronises on each
+// closing event) and recycle their events.
+void ktime_collect(sph_ctx ctx)
+{
+    KTimer &t = ctx->timer;
+    for (const KTimer::Pending &q : t.pending) {
+        float ms = 0.0f;
+        if (q.id >= 0 && hipEventSynchronize(q.b) == hipSuccess &&
+            hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+            t.sum_ms[q.id] += ms;
+            t.launches[q.id] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        t.pool.push_back(q.a);
+        t.pool.push_back(q.b);
+    }
+    t.pending.clear();
+}
+
+void ktime_release(sph_ctx ctx)
+{
+    KTimer &t = ctx->timer;
+    for (const KTimer::Pending &q : t.pending) {
+        t.pool.push_back(q.a);
+        t.pool.push_back(q.b);
+    }
+    t.pending.clear();
+    for (hipEvent_t e : t.pool) (void)hipEventDestroy(e);
+    t.pool.clear();
+}
 
 thread_local std::string g_no_ctx_error;
 
@@ -215,6 +290,7 @@ sph_status dev_alloc(sph_ctx ctx, T **p, int64_t count)
 
 void free_ctx(sph_ctx ctx)
 {
+    ktime_release(ctx);
     release_gravity_tree(ctx);
     if (ctx->step_exec) (void)hipGraphExecDestroy(ctx->step_exec);
     if (ctx->step_graph) (void)hipGraphDestroy(ctx->step_graph);
@@ -340,6 +416,37 @@ sph_status sph_ctx_destroy(sph_ctx ctx)
 }
 
 int64_t sph_ctx_scratch_bytes(sph_ctx ctx) { return ctx ? ctx->scratch_bytes : 0; }
+
+sph_status sph_ctx_timing(sph_ctx ctx, int32_t enable)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    if (enable) {
+        SPH_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        ktime_collect(ctx);
+        for (int k = 0; k < TK_COUNT; ++k) {
+            ctx->timer.sum_ms[k] = 0.0;
+            ctx->timer.launches[k] = 0;
+        }
+    }
+    ctx->timer.on = enable != 0;
+    return SPH_OK;
+}
+
+sph_status sph_ctx_kernel_time(sph_ctx ctx, const char *kernel, double *avg_ms,
+                               int64_t *launches)
+{
+    if (!ctx) return fail(nullptr, SPH_E_INVALID, "ctx is NULL");
+    if (!kernel || !avg_ms || !launches)
+        return fail(ctx, SPH_E_INVALID, "kernel, avg_ms and launches are required");
+    int id = -1;
+    for (int k = 0; k < TK_COUNT; ++k)
+        if (std::strcmp(kernel, kTimedKernelNames[k]) == 0) id = k;
+    if (id < 0) return fail(ctx, SPH_E_INVALID, "kernel %s is not timed", kernel);
+    ktime_collect(ctx);
+    *launches = ctx->timer.launches[id];
+    *avg_ms = *launches ? ctx->timer.sum_ms[id] / (double)*launches : 0.0;
+    return SPH_OK;
+}
 
 sph_status sph_ctx_check(sph_ctx ctx)
 {
@@ -650,7 +757,9 @@ sph_status sph_step_capture(sph_ctx ctx, const sph_particles *p, const sph_box *
         return hip_fail(ctx, be, "hipStreamBeginCapture");
     }
     ctx->stream = cap;
+    ctx->capturing = true;
     const sph_status s = sph_step(ctx, p, box, h_max, nb, prm, f, a, dt_dev, diag_dev);
+    ctx->capturing = false;
     ctx->stream = own;
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cap, &g);

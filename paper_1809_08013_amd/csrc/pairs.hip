@@ -636,15 +636,30 @@ __device__ __forceinline__ void momentum_tile(
         closes = (((prm.sub + 1) & ((1 << (prm.B - b)) - 1)) == 0);
         if (__ballot(active && closes) == 0ull) return;
     }
+    // the FP32-pair form with kernel derivatives reads PairRec32 records
+    // (FP32 copies of the fields after the position and velocity)
+    constexpr bool R32 = F32 && !IAD;
+    constexpr int kRecBytes = R32 ? (int)sizeof(PairRec32) : (int)sizeof(PairRec);
     const PairRec *mp = rec + ii;
-    const double mex = mp->x, mey = mp->y, mez = mp->z;
-    const double mevx = mp->vx, mevy = mp->vy, mevz = mp->vz;
-    const R hi = (R)mp->h, inv_hi = (R)mp->inv_h, rhoi = (R)mp->rho, ci = (R)mp->c,
-            pi = (R)mp->pr2;
+    const PairRec32 *mp32 = reinterpret_cast<const PairRec32 *>(rec) + ii;
+    double mex, mey, mez, mevx, mevy, mevz;
+    R hi, inv_hi, rhoi, ci, pi, xim, qim;
     // generalised volume elements: X_i / m_i and Q_i / m_i of the own record
-    // (pad[0] = X, pad[1] = Q = m^2 P / (rho^2 X))
-    const R xim = GVE ? (R)(mp->pad[0] / mp->m) : R(0);
-    const R qim = GVE ? (R)(mp->pad[1] / mp->m) : R(0);
+    // (X and Q = m^2 P / (rho^2 X))
+    if constexpr (R32) {
+        mex = mp32->x; mey = mp32->y; mez = mp32->z;
+        mevx = mp32->vx; mevy = mp32->vy; mevz = mp32->vz;
+        hi = mp32->h; inv_hi = mp32->inv_h; rhoi = mp32->rho; ci = mp32->c; pi = mp32->pr2;
+        xim = GVE ? mp32->X / mp32->m : R(0);
+        qim = GVE ? mp32->Q / mp32->m : R(0);
+    } else {
+        mex = mp->x; mey = mp->y; mez = mp->z;
+        mevx = mp->vx; mevy = mp->vy; mevz = mp->vz;
+        hi = (R)mp->h; inv_hi = (R)mp->inv_h; rhoi = (R)mp->rho; ci = (R)mp->c;
+        pi = (R)mp->pr2;
+        xim = GVE ? (R)(mp->pad[0] / mp->m) : R(0);
+        qim = GVE ? (R)(mp->pad[1] / mp->m) : R(0);
+    }
     const R sg = KF == KF_M4 ? (R)kInvPi : (R)prm.sigma;
     const int sn = prm.sinc_n;
     const R fi = sg * (inv_hi * inv_hi) * (inv_hi * inv_hi);
@@ -657,7 +672,7 @@ __device__ __forceinline__ void momentum_tile(
     // (2 - q)^3 / 4 ... loses its relative accuracy to cancellation, an FP32
     // gradient would be off by far more than the FP32 rounding of its size.
     double cix = 0, ciy = 0, ciz = 0, ciyy = 0, ciyz = 0, cizz = 0;
-    const double inv_hid = IAD ? mp->inv_h : 0.0;
+    const double inv_hid = IAD ? mp->inv_h : 0.0;  // (IAD: PairRec records)
     if constexpr (IAD) {
         const double *cp = prm.iad_c + 6 * ii;
         cix = cp[0]; ciy = cp[1]; ciz = cp[2];
@@ -668,7 +683,7 @@ __device__ __forceinline__ void momentum_tile(
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, 64));
     const int grp = lane & ~7, s = lane & 7;
-    const bool loader = s < (GVE ? 7 : 6);
+    const bool loader = s < (R32 ? 5 : (GVE ? 7 : 6));
     const char *src_base = reinterpret_cast<const char *>(rec);
     const uint32_t chunk = 16u * (uint32_t)(loader ? s : 0);
     const char *own = buf + lane * kMomStride;
@@ -693,8 +708,7 @@ __device__ __forceinline__ void momentum_tile(
     auto fetch_set = [&](int jk, RecSet &S) {
 #pragma unroll
         for (int t = 0; t < 8; ++t)
-            S.c[t] = rec_chunk<Big, (int)sizeof(PairRec)>(src_base, __shfl(jk, grp + t, 64),
-                                                        chunk);
+            S.c[t] = rec_chunk<Big, kRecBytes>(src_base, __shfl(jk, grp + t, 64), chunk);
         if constexpr (IAD) {
             const double2 *cp = reinterpret_cast<const double2 *>(prm.iad_c + 6 * (int64_t)jk);
             S.e[0] = cp[0];
@@ -715,11 +729,27 @@ __device__ __forceinline__ void momentum_tile(
         const double2 q0 = *reinterpret_cast<const double2 *>(own);       // x y
         const double2 q1 = *reinterpret_cast<const double2 *>(own + 16);  // z vx
         const double2 q2 = *reinterpret_cast<const double2 *>(own + 32);  // vy vz
-        const double2 q3 = *reinterpret_cast<const double2 *>(own + 48);  // h inv_h
-        const double2 q4 = *reinterpret_cast<const double2 *>(own + 64);  // m rho
-        const double2 q5 = *reinterpret_cast<const double2 *>(own + 80);  // c pr2
-        double2 q6 = make_double2(0.0, 0.0);                               // X Q
-        if constexpr (GVE) q6 = *reinterpret_cast<const double2 *>(own + 96);
+        // neighbour fields: h, 1/h, m, rho, c, P/rho^2, X, Q
+        R hj_, inv_hj_, mj_, rhoj_, cj_, prj_, Xj_ = R(0), Qj_ = R(0);
+        double inv_hjd = 0.0;  // (IAD)
+        if constexpr (R32) {
+            const float4 a = *reinterpret_cast<const float4 *>(own + 48);  // h 1/h m rho
+            const float4 b = *reinterpret_cast<const float4 *>(own + 64);  // c pr2 X Q
+            hj_ = a.x; inv_hj_ = a.y; mj_ = a.z; rhoj_ = a.w;
+            cj_ = b.x; prj_ = b.y;
+            if constexpr (GVE) { Xj_ = b.z; Qj_ = b.w; }
+        } else {
+            const double2 q3 = *reinterpret_cast<const double2 *>(own + 48);  // h inv_h
+            const double2 q4 = *reinterpret_cast<const double2 *>(own + 64);  // m rho
+            const double2 q5 = *reinterpret_cast<const double2 *>(own + 80);  // c pr2
+            hj_ = (R)q3.x; inv_hj_ = (R)q3.y; mj_ = (R)q4.x; rhoj_ = (R)q4.y;
+            cj_ = (R)q5.x; prj_ = (R)q5.y;
+            inv_hjd = q3.y;
+            if constexpr (GVE) {
+                const double2 q6 = *reinterpret_cast<const double2 *>(own + 96);  // X Q
+                Xj_ = (R)q6.x; Qj_ = (R)q6.y;
+            }
+        }
         if (k < cnt) {
             const double dxd = img<Per>(mex - q0.x, im, 0);
             const double dyd = img<Per>(mey - q0.y, im, 1);
@@ -734,7 +764,6 @@ __device__ __forceinline__ void momentum_tile(
             if constexpr (IAD) {
                 const double r2d = fma_r(dzd, dzd, fma_r(dyd, dyd, dxd * dxd));
                 const double rd = r2d * (r2d > 0.0 ? fast_rsq(r2d) : 0.0);
-                const double inv_hjd = q3.y;
                 const double sgd = KF == KF_M4 ? kInvPi : prm.sigma;
                 const double wi =
                     sgd * (inv_hid * inv_hid * inv_hid) * shape_w<KF>(rd * inv_hid, sn);
@@ -752,12 +781,12 @@ __device__ __forceinline__ void momentum_tile(
                 gy = (R)(-0.5 * fma_r(wj, tjy, wi * tiy));
                 gz = (R)(-0.5 * fma_r(wj, tjz, wi * tiz));
                 dwbar = R(0);
-                hbar = R(0.5) * (hi + (R)q3.x);
+                hbar = R(0.5) * (hi + hj_);
             } else if constexpr (UH) {
                 dwbar = fi * shape_dw<KF>(r * inv_hi, sn);
                 hbar = hi;
             } else {
-                const R hj = (R)q3.x, inv_hj = (R)q3.y;
+                const R hj = hj_, inv_hj = inv_hj_;
                 const R fj = sg * (inv_hj * inv_hj) * (inv_hj * inv_hj);
                 dwbar = R(0.5) * (fi * shape_dw<KF>(r * inv_hi, sn) +
                                   fj * shape_dw<KF>(r * inv_hj, sn));
@@ -766,8 +795,8 @@ __device__ __forceinline__ void momentum_tile(
             const R F = dwbar * rinv;
             const R wx = (R)(mevx - q1.y), wy = (R)(mevy - q2.x), wz = (R)(mevz - q2.y);
             const R vdotr = fma_r(wz, dz, fma_r(wy, dy, wx * dx));
-            const R cbar = R(0.5) * (ci + (R)q5.x);
-            const R rhobar = R(0.5) * (rhoi + (R)q4.y);
+            const R cbar = R(0.5) * (ci + cj_);
+            const R rhobar = R(0.5) * (rhoi + rhoj_);
             // one reciprocal for both denominators: inv = 1 / (den rhobar)
             const R den = fma_r(eta2 * hbar, hbar, r2);
             const R inv = fast_rcp(den * rhobar);
@@ -777,9 +806,9 @@ __device__ __forceinline__ void momentum_tile(
             // generalised volume elements X_j Q_i/m_i + Q_j X_i/m_i + m_j Pi
             R wgt;
             if constexpr (GVE)
-                wgt = fma_r((R)q6.x, qim, fma_r((R)q6.y, xim, (R)q4.x * Pi));
+                wgt = fma_r(Xj_, qim, fma_r(Qj_, xim, mj_ * Pi));
             else
-                wgt = (R)q4.x * (pi + (R)q5.y + Pi);
+                wgt = mj_ * (pi + prj_ + Pi);
             if constexpr (IAD) {
                 const R mGs = wgt;
                 sx = fma_r(-mGs, gx, sx);
@@ -862,6 +891,10 @@ momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
 
 // Pair records {x, y, z, vx, vy, vz, h, 1/h, m, rho, c, P/rho^2}, and with
 // generalised volume elements (xw not null) {X, Q = m^2 (P/rho^2) / X}.
+// R32 (the FP32-pair form, kernel derivatives): PairRec32 records, the
+// fields after the position and velocity rounded to FP32 (1/h from the FP64
+// h, Q from the FP64 fields).
+template <bool R32>
 __global__ void __launch_bounds__(256)
 pack_pair_kernel(int64_t n, const int64_t *n_dev, const double *__restrict__ x,
                  const double *__restrict__ y, const double *__restrict__ z,
@@ -869,19 +902,22 @@ pack_pair_kernel(int64_t n, const int64_t *n_dev, const double *__restrict__ x,
                  const double *__restrict__ vz, const double *__restrict__ h,
                  const double *__restrict__ m, const double *__restrict__ rho,
                  const double *__restrict__ c, const double *__restrict__ pr2,
-                 const double *__restrict__ xw, PairRec *__restrict__ out)
+                 const double *__restrict__ xw, void *__restrict__ out)
 {
     // Each wave forms the records of 64 consecutive particles in LDS (one
     // per lane, stride 17 doubles), then stores them as 16-byte chunks with
     // consecutive lanes on consecutive chunks, so that every store writes
     // 1 KB of contiguous memory. Only the chunks the momentum kernel reads
-    // are written: 6 (96 B), or 7 with the volume weights.
+    // are written: 6 (96 B), or 7 with the volume weights; 5 (80 B) for
+    // PairRec32.
     constexpr int kStride = 17;
+    constexpr int kRecBytes = R32 ? (int)sizeof(PairRec32) : (int)sizeof(PairRec);
+    constexpr int kParts = kRecBytes / 16;  // chunks per record in memory
     __shared__ double lds[4][64 * kStride];
     if (n_dev) n = *n_dev;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *buf = lds[wave];
-    const int nparts = xw ? 7 : 6;
+    const int nparts = R32 ? 5 : (xw ? 7 : 6);
     const int64_t wstep = (int64_t)gridDim.x * (blockDim.x >> 6) * 64;
     for (int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * 64; base < n;
          base += wstep) {
@@ -891,24 +927,35 @@ pack_pair_kernel(int64_t n, const int64_t *n_dev, const double *__restrict__ x,
             double *r = buf + lane * kStride;
             r[0] = x[i]; r[1] = y[i]; r[2] = z[i];
             r[3] = vx[i]; r[4] = vy[i]; r[5] = vz[i];
-            r[6] = hi; r[7] = 1.0 / hi; r[8] = m[i];
-            r[9] = rho[i]; r[10] = c[i]; r[11] = pr2[i];
-            if (xw) {
-                r[12] = xw[i];
-                r[13] = r[8] * r[8] * r[11] / xw[i];
+            const double q = xw ? m[i] * m[i] * pr2[i] / xw[i] : 0.0;
+            if constexpr (R32) {
+                float *f = reinterpret_cast<float *>(r + 6);
+                f[0] = (float)hi; f[1] = (float)(1.0 / hi); f[2] = (float)m[i];
+                f[3] = (float)rho[i]; f[4] = (float)c[i]; f[5] = (float)pr2[i];
+                f[6] = xw ? (float)xw[i] : 0.0f;
+                f[7] = (float)q;
+            } else {
+                r[6] = hi; r[7] = 1.0 / hi; r[8] = m[i];
+                r[9] = rho[i]; r[10] = c[i]; r[11] = pr2[i];
+                if (xw) {
+                    r[12] = xw[i];
+                    r[13] = q;
+                }
             }
         }
         wave_lds_fence();
-        char *dst = reinterpret_cast<char *>(out + base);
+        char *dst = reinterpret_cast<char *>(out) + base * kRecBytes;
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int q = t * 64 + lane;
             const int rec = q >> 3, part = q & 7;
             if (part < nparts && base + rec < n) {
                 const double *src = buf + rec * kStride + 2 * part;
-                *reinterpret_cast<double2 *>(dst + 16 * q) = make_double2(src[0], src[1]);
+                *reinterpret_cast<double2 *>(dst + (int64_t)rec * kRecBytes + 16 * part) =
+                    make_double2(src[0], src[1]);
             }
         }
+        (void)kParts;
         wave_lds_fence();
     }
 }
@@ -1041,9 +1088,11 @@ hipError_t launch_density(sph_ctx ctx, const sph_particles &p, const sph_nbrs &n
     // kernel leaves k_i in rho, which is then scaled by m_i / X_i
     pack_dens_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
         p.n, nullptr, p.x, p.y, p.z, gve ? p.xw : p.m, ctx->drec);
+    const int tk = ktime_begin(ctx, TK_DENSITY);
     density_launch<false>(ctx->stream, nblk, precision, big_records(p.n, sizeof(DensRec)), p.n,
                           p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, rho,
                           BatchDev{}, ks, mask);
+    ktime_end(ctx, tk);
     if (gve)
         gve_density_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(p.n, p.m, p.xw, rho,
                                                                           mask);
@@ -1132,19 +1181,30 @@ hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &
     iad_kernel<K><<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(                          \
         p.n, p.n, ctx->drec, p.h, nb.count, nb.idx, nb.max_nb, ctx->grid, ks.sigma,        \
         ks.sinc_n, ctx->iad_c)
+        const int tk = ktime_begin(ctx, TK_IAD);
         if (ks.family == SPH_KERNEL_WENDLAND_C2) SPH_IAD(KF_WENDLAND);
         else if (ks.family == SPH_KERNEL_SINC) SPH_IAD(KF_SINC);
         else SPH_IAD(KF_M4);
+        ktime_end(ctx, tk);
 #undef SPH_IAD
     }
     const bool gve = prm.volume == SPH_VOLUME_GENERALISED;
-    pack_pair_kernel<<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
-        p.n, nullptr, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2,
-        gve ? p.xw : nullptr, ctx->prec);
-    momentum_launch<false>(ctx->stream, nblk, prm.precision, big_records(p.n, sizeof(PairRec)),
+    const bool r32 = prm.precision == SPH_FP32_PAIR && !iad;  // PairRec32 records
+    if (r32)
+        pack_pair_kernel<true><<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
+            p.n, nullptr, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2,
+            gve ? p.xw : nullptr, ctx->prec);
+    else
+        pack_pair_kernel<false><<<blocks_for(p.n, 256), 256, 0, ctx->stream>>>(
+            p.n, nullptr, p.x, p.y, p.z, p.vx, p.vy, p.vz, p.h, p.m, f.rho, f.c, f.pr2,
+            gve ? p.xw : nullptr, ctx->prec);
+    const int tk = ktime_begin(ctx, TK_MOMENTUM);
+    momentum_launch<false>(ctx->stream, nblk, prm.precision,
+                           big_records(p.n, r32 ? sizeof(PairRec32) : sizeof(PairRec)),
                            p.n, p.n, ctx->prec, nb.count, nb.idx, nb.max_nb, ctx->grid, mp,
                            a.ax, a.ay, a.az, a.dudt, a.mumax, BatchDev{}, ctx->hflag_dev,
                            ks.family, iad, gve);
+    ktime_end(ctx, tk);
     return hipGetLastError();
 }
 
@@ -1186,11 +1246,17 @@ hipError_t launch_momentum_batch(sph_ctx ctx, const BatchDev &b, int precision,
     const int64_t *n_out = &b.hdr->n_out;
     const unsigned g1 = std::min<unsigned>(blocks_for(cap, 256), 4096u);
     const unsigned g2 = std::min<unsigned>(blocks_for(cap, kThreads), 4096u);
-    pack_pair_kernel<<<g1, 256, 0, ctx->stream>>>(0, n_out, F + 0 * cap, F + 1 * cap,
-                                                  F + 2 * cap, F + 3 * cap, F + 4 * cap,
-                                                  F + 5 * cap, F + 7 * cap, F + 8 * cap, rho, c,
-                                                  pr2, nullptr, ctx->prec);
-    momentum_launch<true>(ctx->stream, g2, precision, big_records(cap, sizeof(PairRec)), 0, cap,
+    const bool r32 = precision == SPH_FP32_PAIR;  // PairRec32 records
+    if (r32)
+        pack_pair_kernel<true><<<g1, 256, 0, ctx->stream>>>(
+            0, n_out, F + 0 * cap, F + 1 * cap, F + 2 * cap, F + 3 * cap, F + 4 * cap,
+            F + 5 * cap, F + 7 * cap, F + 8 * cap, rho, c, pr2, nullptr, ctx->prec);
+    else
+        pack_pair_kernel<false><<<g1, 256, 0, ctx->stream>>>(
+            0, n_out, F + 0 * cap, F + 1 * cap, F + 2 * cap, F + 3 * cap, F + 4 * cap,
+            F + 5 * cap, F + 7 * cap, F + 8 * cap, rho, c, pr2, nullptr, ctx->prec);
+    momentum_launch<true>(ctx->stream, g2, precision,
+                          big_records(cap, r32 ? sizeof(PairRec32) : sizeof(PairRec)), 0, cap,
                           ctx->prec, count, idx, max_nb, Grid{}, MomParams{}, ax, ay, az, dudt,
                           mumax, b, nullptr, SPH_KERNEL_M4, false, false);
     return hipGetLastError();

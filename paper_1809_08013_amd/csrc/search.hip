@@ -934,16 +934,20 @@ hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_
     const int64_t tiles = (p.n + kWave - 1) / kWave;
     const unsigned blocks = (unsigned)((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
     clear_count_kernel<<<1, 1, 0, ctx->stream>>>(ctx->fb_count);
+    int tk = ktime_begin(ctx, TK_FIND_NEIGHBORS);
     find_neighbors_kernel<false><<<blocks, kBlock, 0, ctx->stream>>>(
         p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
         nb.max_nb, nb.count, nb.idx, ctx->nb_mask, ctx->hflag_dev, ctx->status_dev, BatchDev{},
         ctx->fb_tiles, ctx->fb_count, mask);
+    ktime_end(ctx, tk);
     const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, kFallbackBlocks);
+    tk = ktime_begin(ctx, TK_FALLBACK);
     fallback_kernel<false><<<fblocks, kWave, 0, ctx->stream>>>(
         p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
         nb.max_nb, nb.count, nb.idx, ctx->status_dev, BatchDev{}, ctx->fb_tiles, ctx->fb_count,
         ctx->nb_mask, ctx->hflag_dev,
         reinterpret_cast<const unsigned long long *>(ctx->cell_s2max));
+    ktime_end(ctx, tk);
     return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "sph.h"
 
@@ -140,6 +141,19 @@ struct __attribute__((aligned(128))) PairRec {
     double pad[4];
 };
 static_assert(sizeof(PairRec) == 128, "PairRec is one cache line");
+// The FP32-pair form's momentum records: position and velocity in FP64 (the
+// separations and velocity differences are formed in FP64, then rounded),
+// h, 1/h, m, rho, c, P/rho^2 and the volume weights X, Q as FP32 copies:
+// 48 + 32 = 80 B, five 16-byte chunks (with kernel derivatives; the IAD
+// instances keep PairRec, their gradient being formed in FP64). Padded to
+// one 128-byte line like PairRec: an 80-byte stride makes most records span
+// two lines, and the gather then touches 1.6 lines per record instead of one
+// (measured slower on the 1M patch: 0.83 against 0.73 ms).
+struct __attribute__((aligned(128))) PairRec32 {
+    double x, y, z, vx, vy, vz;
+    float h, inv_h, m, rho, c, pr2, X, Q;
+};
+static_assert(sizeof(PairRec32) == 128, "PairRec32 is one cache line");
 
 // Octree gravity node: centre of mass and opening radius s / theta + delta
 // (the acceptance test), mass and traceless quadrupole (xx xy xz yy yz zz),
@@ -197,6 +211,36 @@ __device__ __forceinline__ int64_t xcd_cu_block()
     return base + (int64_t)(c * qc + (c < rc ? c : rc)) + round;
 }
 
+}  // namespace sph
+
+namespace sph {
+// Live kernel timing (sph_ctx_timing): while on, the launches of the timed
+// kernels are bracketed by two HIP events on the context's stream; the
+// durations are summed when sph_ctx_kernel_time reads them.
+enum TimedKernel {
+    TK_FIND_NEIGHBORS = 0,  // find_neighbors_kernel
+    TK_FALLBACK,            // fallback_kernel
+    TK_DENSITY,             // density_kernel
+    TK_IAD,                 // iad_kernel
+    TK_MOMENTUM,            // momentum_kernel
+    TK_COUNT
+};
+extern const char *const kTimedKernelNames[TK_COUNT];
+struct KTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;  // free events
+    struct Pending {
+        int id;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    double sum_ms[TK_COUNT] = {};
+    int64_t launches[TK_COUNT] = {};
+};
+// Start/stop one timed launch (no-ops while timing is off or while a step is
+// being captured). ktime_begin returns the pending slot or -1.
+int ktime_begin(sph_ctx ctx, int id);
+void ktime_end(sph_ctx ctx, int slot);
 }  // namespace sph
 
 struct sph_ctx_s {
@@ -263,6 +307,9 @@ struct sph_ctx_s {
     // one captured sph_step (sph_step_capture / sph_step_replay)
     hipGraph_t step_graph = nullptr;
     hipGraphExec_t step_exec = nullptr;
+
+    sph::KTimer timer;
+    bool capturing = false;          // inside sph_step_capture
 
     uint32_t *status_dev = nullptr;
     uint32_t *hflag_dev = nullptr;   // 0 after a build iff every particle has the same h

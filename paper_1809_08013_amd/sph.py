@@ -130,6 +130,9 @@ def load():
             "sph_ctx_destroy": (C.c_int32, [_VP]),
             "sph_ctx_check": (C.c_int32, [_VP]),
             "sph_ctx_scratch_bytes": (C.c_int64, [_VP]),
+            "sph_ctx_timing": (C.c_int32, [_VP, C.c_int32]),
+            "sph_ctx_kernel_time": (C.c_int32, [_VP, C.c_char_p, C.POINTER(C.c_double),
+                                                C.POINTER(C.c_int64)]),
             "sph_build_cells": (C.c_int32, [_VP, P, B, C.c_double]),
             "sph_find_neighbors": (C.c_int32, [_VP, P, B, N]),
             "sph_density": (C.c_int32, [_VP, P, B, N, M, _VP]),
@@ -210,6 +213,18 @@ class Context:
     @property
     def scratch_bytes(self) -> int:
         return int(self.lib.sph_ctx_scratch_bytes(self.h))
+
+    def timing(self, enable: bool):
+        """sph_ctx_timing: HIP events around the timed kernels' launches."""
+        self.raise_on(self.lib.sph_ctx_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self, kernel: str):
+        """sph_ctx_kernel_time: (mean ms per launch, launches) of a timed
+        kernel since timing was enabled."""
+        ms, k = C.c_double(), C.c_int64()
+        self.raise_on(self.lib.sph_ctx_kernel_time(self.h, kernel.encode(), C.byref(ms),
+                                                   C.byref(k)))
+        return float(ms.value), int(k.value)
 
 
 def make_params(p, precision: int = SPH_FP64) -> Params:
