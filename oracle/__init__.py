@@ -66,6 +66,16 @@ def lib():
             L.orc_smoothing_length.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _I32,
                                                C.c_double, C.c_int32, C.c_int32,
                                                C.c_int32, _I32]
+            L.orc_neighbors_subset.restype = C.c_int64
+            L.orc_neighbors_subset.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _I32,
+                                               C.c_int64, _I64, C.c_int64, _I64, _I32]
+            L.orc_density_subset.restype = None
+            L.orc_density_subset.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _D, _I32,
+                                             C.c_int64, _I64, _I64, _I32, _D]
+            L.orc_momentum_energy_subset.restype = C.c_int32
+            L.orc_momentum_energy_subset.argtypes = (
+                [C.c_int64] + [_D] * 11 + [_D, _D, _I32, C.c_int64, _I64, _I64, _I32]
+                + [C.c_double] * 3 + [_D] * 4 + [_DN, _DN, _DN])
             L.orc_density.restype = None
             L.orc_density.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, _D, _I32,
                                       _I64, _I32, _D]
@@ -206,6 +216,57 @@ def neighbors(x, y, z, h, lo, hi, periodic):
 def neighbors_brute(x, y, z, h, lo, hi, periodic):
     """Neighbour sets (CSR, each set ascending) by the O(N^2) definition."""
     return _neighbors(lib().orc_neighbors_brute, x, y, z, h, lo, hi, periodic)
+
+
+def neighbors_subset(x, y, z, h, lo, hi, periodic, sel):
+    """Neighbour sets of the particles sel only (CSR by position in sel, each
+    set ascending), by the same grid over all particles."""
+    x, y, z, h = _d(x), _d(y), _d(z), _d(h)
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    k = len(sel)
+    blo, bhi, bper = _box(lo, hi, periodic)
+    off = np.zeros(k + 1, dtype=np.int64)
+    cap = max(1, 160 * k)
+    ids = np.zeros(cap, dtype=np.int32)
+    tot = lib().orc_neighbors_subset(len(x), x, y, z, h, blo, bhi, bper, k, sel, cap, off, ids)
+    if tot < 0:
+        raise RuntimeError("oracle neighbour set too large")
+    if tot > cap:
+        ids = np.zeros(int(tot), dtype=np.int32)
+        tot = lib().orc_neighbors_subset(len(x), x, y, z, h, blo, bhi, bper, k, sel, int(tot),
+                                         off, ids)
+    return off, ids[:tot].copy()
+
+
+def density_subset(x, y, z, h, m, lo, hi, periodic, sel, off, ids):
+    """Summation density of the particles sel (sets from neighbors_subset)."""
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    rho = np.zeros(len(sel))
+    blo, bhi, bper = _box(lo, hi, periodic)
+    lib().orc_density_subset(len(x), _d(x), _d(y), _d(z), _d(h), _d(m), blo, bhi, bper,
+                             len(sel), sel, np.ascontiguousarray(off, dtype=np.int64),
+                             np.ascontiguousarray(ids, dtype=np.int32), rho)
+    return rho
+
+
+def momentum_energy_subset(x, y, z, vx, vy, vz, h, m, rho, c, pr2, lo, hi, periodic, sel,
+                           off, ids, params):
+    """Momentum and energy (kernel derivatives, standard volume elements) of
+    the particles sel, with the fields of all particles given; dict ax, ay,
+    az, dudt, mumax, sa, su indexed like sel."""
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    k = len(sel)
+    out = {key: np.zeros(k) for key in ("ax", "ay", "az", "dudt", "mumax", "sa", "su")}
+    blo, bhi, bper = _box(lo, hi, periodic)
+    r = lib().orc_momentum_energy_subset(
+        len(x), _d(x), _d(y), _d(z), _d(vx), _d(vy), _d(vz), _d(h), _d(m), _d(rho), _d(c),
+        _d(pr2), blo, bhi, bper, k, sel, np.ascontiguousarray(off, dtype=np.int64),
+        np.ascontiguousarray(ids, dtype=np.int32), float(params.alpha), float(params.beta),
+        float(params.eta2), out["ax"], out["ay"], out["az"], out["dudt"],
+        out["mumax"].ctypes.data, out["sa"].ctypes.data, out["su"].ctypes.data)
+    if r != 0:
+        raise RuntimeError("the subset evaluation takes kernel derivatives only")
+    return out
 
 
 def smoothing_length(x, y, z, h, lo, hi, periodic, n_target=100.0,

@@ -458,6 +458,58 @@ int64_t orc_neighbors_grid(int64_t n, const double *x, const double *y,
 }
 
 /*
+ * Neighbour sets of the particles sel[0..k) only, by the same grid over all
+ * n particles: offsets[q] .. offsets[q + 1] in ids holds particle sel[q]'s
+ * set, ascending. Returns the total (ids written only if it fits cap), or -1
+ * if one set exceeds 2^22 entries.
+ */
+int64_t orc_neighbors_subset(int64_t n, const double *x, const double *y,
+                             const double *z, const double *h,
+                             const double *lo, const double *hi,
+                             const int32_t *per, int64_t k, const int64_t *sel,
+                             int64_t cap, int64_t *offsets, int32_t *ids)
+{
+    orc_box b = make_box(lo, hi, per);
+    orc_grid g;
+    offsets[0] = 0;
+    if (n == 0 || k == 0) {
+        for (int64_t q = 0; q < k; ++q) offsets[q + 1] = 0;
+        return 0;
+    }
+    grid_build(&g, n, x, y, z, &b, 2.0 * max_of(h, n));
+    int64_t *cnt = (int64_t *)calloc((size_t)k, sizeof(int64_t));
+    int64_t bufcap = n < ((int64_t)1 << 22) ? n : ((int64_t)1 << 22);
+    #pragma omp parallel
+    {
+        int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)bufcap);
+        #pragma omp for schedule(dynamic, 16)
+        for (int64_t q = 0; q < k; ++q)
+            cnt[q] = grid_query(&g, sel[q], x, y, z, h, &b, is_neighbor, buf, 0);
+        free(buf);
+    }
+    for (int64_t q = 0; q < k; ++q) {
+        if (cnt[q] > bufcap) { free(cnt); grid_free(&g); return -1; }
+        offsets[q + 1] = offsets[q] + cnt[q];
+    }
+    int64_t total = offsets[k];
+    free(cnt);
+    if (total <= cap) {
+        #pragma omp parallel
+        {
+            int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)bufcap);
+            #pragma omp for schedule(dynamic, 16)
+            for (int64_t q = 0; q < k; ++q) {
+                int64_t c = grid_query(&g, sel[q], x, y, z, h, &b, is_neighbor, buf, bufcap);
+                memcpy(ids + offsets[q], buf, sizeof(int32_t) * (size_t)c);
+            }
+            free(buf);
+        }
+    }
+    grid_free(&g);
+    return total;
+}
+
+/*
  * Smoothing-length iteration toward a target neighbour count (Algorithm 1
  * step 2 and its footnote: the code aims at a given number of neighbours and
  * h follows from it). Gather count N_i = |{j != i : r^2 < 4 h_i^2}|; every
@@ -499,7 +551,23 @@ int32_t orc_smoothing_length(int64_t n, const double *x, const double *y,
 
 /* ------------------------------------------------------------- density */
 
-/* rho_i = m_i W(0, h_i) + sum_{j in N_i} m_j W(r_ij, h_i). */
+/* rho_i = m_i W(0, h_i) + sum_{j in N_i} m_j W(r_ij, h_i), over the set
+ * nb[0..len) of particle i (ascending). */
+static double density_of(int64_t i, const double *x, const double *y, const double *z,
+                         const double *h, const double *m, const orc_box *b,
+                         const int32_t *nb, int64_t len)
+{
+    double s = m[i] * orc_kernel_w(0.0, h[i]);
+    for (int64_t k = 0; k < len; ++k) {
+        int64_t j = nb[k];
+        double dx, dy, dz;
+        separation(x, y, z, i, j, b, &dx, &dy, &dz);
+        double r = sqrt(dist2(dx, dy, dz));
+        s += m[j] * orc_kernel_w(r, h[i]);
+    }
+    return s;
+}
+
 void orc_density(int64_t n, const double *x, const double *y, const double *z,
                  const double *h, const double *m,
                  const double *lo, const double *hi, const int32_t *per,
@@ -507,17 +575,24 @@ void orc_density(int64_t n, const double *x, const double *y, const double *z,
 {
     orc_box b = make_box(lo, hi, per);
     #pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t i = 0; i < n; ++i) {
-        double s = m[i] * orc_kernel_w(0.0, h[i]);
-        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
-            int64_t j = ids[k];
-            double dx, dy, dz;
-            separation(x, y, z, i, j, &b, &dx, &dy, &dz);
-            double r = sqrt(dist2(dx, dy, dz));
-            s += m[j] * orc_kernel_w(r, h[i]);
-        }
-        rho[i] = s;
-    }
+    for (int64_t i = 0; i < n; ++i)
+        rho[i] = density_of(i, x, y, z, h, m, &b, ids + offsets[i], offsets[i + 1] - offsets[i]);
+}
+
+/* The same for the particles sel[0..k) only (their sets in CSR by q, as
+ * orc_neighbors_subset gives them); rho[q] is particle sel[q]'s. */
+void orc_density_subset(int64_t n, const double *x, const double *y, const double *z,
+                        const double *h, const double *m,
+                        const double *lo, const double *hi, const int32_t *per,
+                        int64_t k, const int64_t *sel, const int64_t *offsets,
+                        const int32_t *ids, double *rho)
+{
+    (void)n;
+    orc_box b = make_box(lo, hi, per);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t q = 0; q < k; ++q)
+        rho[q] = density_of(sel[q], x, y, z, h, m, &b, ids + offsets[q],
+                            offsets[q + 1] - offsets[q]);
 }
 
 /* ------------------------------------------ generalised volume elements */
@@ -682,6 +757,68 @@ void orc_iad_matrices(int64_t n, const double *x, const double *y, const double 
  * k = rho X / m; F_ij m_i is symmetric in i and j, so momentum and energy
  * stay conserved. IAD keeps V_j = m_j / rho_j, which equals X_j / k_j.
  */
+/* The pair sums of particle i over its set nb[0..len) (ascending), into
+ * out = {a_x, a_y, a_z, du/dt, max |mu|, S^a, S^u}; c6 (IAD matrices) and X
+ * (weights) may be NULL. */
+static void momentum_of(int64_t i, const int32_t *nb, int64_t len, const double *x,
+                        const double *y, const double *z, const double *vx,
+                        const double *vy, const double *vz, const double *h,
+                        const double *m, const double *X, const double *rho,
+                        const double *c, const double *pr2, const orc_box *b,
+                        const double *c6, double alpha, double beta, double eta2,
+                        double out[7])
+{
+    double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, mum = 0.0;
+    double sai = 0.0, sui = 0.0;
+    for (int64_t k = 0; k < len; ++k) {
+        int64_t j = nb[k];
+        double dx, dy, dz;
+        separation(x, y, z, i, j, b, &dx, &dy, &dz);
+        double r2 = dist2(dx, dy, dz);
+        double r = sqrt(r2);
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        if (c6) {
+            const double *ci = c6 + 6 * i, *cj = c6 + 6 * j;
+            double wi = orc_kernel_w(r, h[i]), wj = orc_kernel_w(r, h[j]);
+            gx = -0.5 * (wi * (ci[0] * dx + ci[1] * dy + ci[2] * dz) +
+                         wj * (cj[0] * dx + cj[1] * dy + cj[2] * dz));
+            gy = -0.5 * (wi * (ci[1] * dx + ci[3] * dy + ci[4] * dz) +
+                         wj * (cj[1] * dx + cj[3] * dy + cj[4] * dz));
+            gz = -0.5 * (wi * (ci[2] * dx + ci[4] * dy + ci[5] * dz) +
+                         wj * (cj[2] * dx + cj[4] * dy + cj[5] * dz));
+        } else if (r > 0.0) {
+            double dwbar = 0.5 * (orc_kernel_dwdr(r, h[i]) + orc_kernel_dwdr(r, h[j]));
+            gx = dwbar * dx / r;
+            gy = dwbar * dy / r;
+            gz = dwbar * dz / r;
+        }
+        double wx = vx[i] - vx[j], wy = vy[i] - vy[j], wz = vz[i] - vz[j];
+        double vdotr = wx * dx + wy * dy + wz * dz;
+        double hbar = 0.5 * (h[i] + h[j]);
+        double cbar = 0.5 * (c[i] + c[j]);
+        double rhobar = 0.5 * (rho[i] + rho[j]);
+        double mu = 0.0;
+        if (vdotr < 0.0) mu = hbar * vdotr / (r2 + eta2 * hbar * hbar);
+        double Pi = (-alpha * cbar * mu + beta * mu * mu) / rhobar;
+        double G = pr2[i] + pr2[j] + Pi;
+        double F = m[j] * G;
+        if (X) {
+            double Qi = m[i] * m[i] * pr2[i] / X[i], Qj = m[j] * m[j] * pr2[j] / X[j];
+            F = (X[j] * Qi + X[i] * Qj) / m[i] + m[j] * Pi;
+        }
+        axi -= F * gx;
+        ayi -= F * gy;
+        azi -= F * gz;
+        dui += 0.5 * F * (wx * gx + wy * gy + wz * gz);
+        if (fabs(mu) > mum) mum = fabs(mu);
+        double gn = sqrt(gx * gx + gy * gy + gz * gz);
+        sai += fabs(F) * gn;
+        sui += 0.5 * fabs(F) * sqrt(wx * wx + wy * wy + wz * wz) * gn;
+    }
+    out[0] = axi; out[1] = ayi; out[2] = azi; out[3] = dui;
+    out[4] = mum; out[5] = sai; out[6] = sui;
+}
+
 static void momentum_energy_impl(int64_t n, const double *x, const double *y,
                                  const double *z, const double *vx, const double *vy,
                                  const double *vz, const double *h, const double *m,
@@ -700,59 +837,46 @@ static void momentum_energy_impl(int64_t n, const double *x, const double *y,
     }
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
-        double axi = 0.0, ayi = 0.0, azi = 0.0, dui = 0.0, mum = 0.0;
-        double sai = 0.0, sui = 0.0;
-        for (int64_t k = offsets[i]; k < offsets[i + 1]; ++k) {
-            int64_t j = ids[k];
-            double dx, dy, dz;
-            separation(x, y, z, i, j, &b, &dx, &dy, &dz);
-            double r2 = dist2(dx, dy, dz);
-            double r = sqrt(r2);
-            double gx = 0.0, gy = 0.0, gz = 0.0;
-            if (c6) {
-                const double *ci = c6 + 6 * i, *cj = c6 + 6 * j;
-                double wi = orc_kernel_w(r, h[i]), wj = orc_kernel_w(r, h[j]);
-                gx = -0.5 * (wi * (ci[0] * dx + ci[1] * dy + ci[2] * dz) +
-                             wj * (cj[0] * dx + cj[1] * dy + cj[2] * dz));
-                gy = -0.5 * (wi * (ci[1] * dx + ci[3] * dy + ci[4] * dz) +
-                             wj * (cj[1] * dx + cj[3] * dy + cj[4] * dz));
-                gz = -0.5 * (wi * (ci[2] * dx + ci[4] * dy + ci[5] * dz) +
-                             wj * (cj[2] * dx + cj[4] * dy + cj[5] * dz));
-            } else if (r > 0.0) {
-                double dwbar = 0.5 * (orc_kernel_dwdr(r, h[i]) + orc_kernel_dwdr(r, h[j]));
-                gx = dwbar * dx / r;
-                gy = dwbar * dy / r;
-                gz = dwbar * dz / r;
-            }
-            double wx = vx[i] - vx[j], wy = vy[i] - vy[j], wz = vz[i] - vz[j];
-            double vdotr = wx * dx + wy * dy + wz * dz;
-            double hbar = 0.5 * (h[i] + h[j]);
-            double cbar = 0.5 * (c[i] + c[j]);
-            double rhobar = 0.5 * (rho[i] + rho[j]);
-            double mu = 0.0;
-            if (vdotr < 0.0) mu = hbar * vdotr / (r2 + eta2 * hbar * hbar);
-            double Pi = (-alpha * cbar * mu + beta * mu * mu) / rhobar;
-            double G = pr2[i] + pr2[j] + Pi;
-            double F = m[j] * G;
-            if (X) {
-                double Qi = m[i] * m[i] * pr2[i] / X[i], Qj = m[j] * m[j] * pr2[j] / X[j];
-                F = (X[j] * Qi + X[i] * Qj) / m[i] + m[j] * Pi;
-            }
-            axi -= F * gx;
-            ayi -= F * gy;
-            azi -= F * gz;
-            dui += 0.5 * F * (wx * gx + wy * gy + wz * gz);
-            if (fabs(mu) > mum) mum = fabs(mu);
-            double gn = sqrt(gx * gx + gy * gy + gz * gz);
-            sai += fabs(F) * gn;
-            sui += 0.5 * fabs(F) * sqrt(wx * wx + wy * wy + wz * wz) * gn;
-        }
-        ax[i] = axi; ay[i] = ayi; az[i] = azi; dudt[i] = dui;
-        if (mumax) mumax[i] = mum;
-        if (sa) sa[i] = sai;
-        if (su) su[i] = sui;
+        double o[7];
+        momentum_of(i, ids + offsets[i], offsets[i + 1] - offsets[i], x, y, z, vx, vy, vz,
+                    h, m, X, rho, c, pr2, &b, c6, alpha, beta, eta2, o);
+        ax[i] = o[0]; ay[i] = o[1]; az[i] = o[2]; dudt[i] = o[3];
+        if (mumax) mumax[i] = o[4];
+        if (sa) sa[i] = o[5];
+        if (su) su[i] = o[6];
     }
     free(c6);
+}
+
+/* Momentum and energy (kernel derivatives, standard volume elements) for
+ * the particles sel[0..k) only, with their sets in CSR by q (as
+ * orc_neighbors_subset gives them); every other array covers all n
+ * particles. Outputs are indexed by q; mumax, sa, su may be NULL. Returns -1
+ * (and computes nothing) when IAD gradients are selected. */
+int32_t orc_momentum_energy_subset(int64_t n, const double *x, const double *y,
+                                   const double *z, const double *vx, const double *vy,
+                                   const double *vz, const double *h, const double *m,
+                                   const double *rho, const double *c, const double *pr2,
+                                   const double *lo, const double *hi, const int32_t *per,
+                                   int64_t k, const int64_t *sel, const int64_t *offsets,
+                                   const int32_t *ids, double alpha, double beta,
+                                   double eta2, double *ax, double *ay, double *az,
+                                   double *dudt, double *mumax, double *sa, double *su)
+{
+    (void)n;
+    if (g_gradient != 0) return -1;
+    orc_box b = make_box(lo, hi, per);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t q = 0; q < k; ++q) {
+        double o[7];
+        momentum_of(sel[q], ids + offsets[q], offsets[q + 1] - offsets[q], x, y, z, vx, vy,
+                    vz, h, m, NULL, rho, c, pr2, &b, NULL, alpha, beta, eta2, o);
+        ax[q] = o[0]; ay[q] = o[1]; az[q] = o[2]; dudt[q] = o[3];
+        if (mumax) mumax[q] = o[4];
+        if (sa) sa[q] = o[5];
+        if (su) su[q] = o[6];
+    }
+    return 0;
 }
 
 void orc_momentum_energy(int64_t n, const double *x, const double *y,

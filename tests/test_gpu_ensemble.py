@@ -108,6 +108,50 @@ def test_mixed_batch_matches_alone():
         ens.close()
 
 
+@pytest.mark.parametrize("precision", [S.SPH_FP64, S.SPH_FP32_PAIR])
+def test_mixed_batch_against_oracle(precision):
+    """The mixed batch (budget admits about half the runs at a time) against
+    each run's FP64 oracle run (t = 0 evaluation with rho_ref = rho(t = 0),
+    then the same number of KDK steps), per run. FP64: x within 1e-12, v and
+    u within 1e-10, rho within 1e-11 relative, dt within 1e-10 relative.
+    FP32-pair (pair arithmetic in FP32, state and integration FP64, at most
+    12 steps): a trajectory diverges from the FP64 one by the FP32 rounding
+    of the forces, amplified by the steps, so these errors are reported (per
+    run, printed) and only bounded loosely: x within 1e-6, v and u within
+    1e-4 of the run's largest |v|, rho within 1e-5 relative, dt within 1e-5
+    (measured: x 2e-8, v 6e-6 of |v|max, rho 5e-7)."""
+    import oracle as O
+    ens = S.Ensemble(32 * MB, max_slots=4, max_n_per_run=8000, precision=precision)
+    try:
+        tickets = []
+        for r in RUNS:
+            ic = _ic(*r[:3])
+            tickets.append((r, ic, ens.submit(ic, r[3])))
+        for r, ic, t in tickets:
+            got = ens.wait(t, ic.n)
+            assert got["status"] == S.SPH_OK and got["steps_done"] == r[3]
+            ref = O.OracleRun(ic).init()
+            for _ in range(r[3]):
+                ref.step()
+            err = {k: float(np.max(np.abs(got[k] - ref.s[k])))
+                   for k in ("x", "y", "z", "vx", "vy", "vz", "u")}
+            err["rho"] = float(np.max(np.abs(got["rho"] / ref.rho - 1)))
+            err["dt"] = abs(got["dt"] - ref.dt) / ref.dt
+            vmax = float(np.max(np.sqrt(ref.s["vx"] ** 2 + ref.s["vy"] ** 2 + ref.s["vz"] ** 2)))
+            print(f"run {r} precision {precision}: " +
+                  " ".join(f"{k} {v:.2e}" for k, v in err.items()), flush=True)
+            xe = max(err[k] for k in ("x", "y", "z"))
+            ve = max(err[k] for k in ("vx", "vy", "vz", "u"))
+            if precision == S.SPH_FP64:
+                assert xe <= 1e-12 and ve <= 1e-10 and err["rho"] <= 1e-11, r
+                assert err["dt"] <= 1e-10, r
+            else:
+                assert xe <= 1e-6 and ve <= 1e-4 * vmax and err["rho"] <= 1e-5, r
+                assert err["dt"] <= 1e-5, r
+    finally:
+        ens.close()
+
+
 def test_arrivals_while_running():
     """Runs arriving while others are on the GPU join the batch (continuous
     batching) and still reproduce their alone results bitwise; a freed slot

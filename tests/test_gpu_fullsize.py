@@ -6,10 +6,13 @@ times (the single-run calls, one context sized for the run).
   the FP64 and FP32-pair tolerances.
 * Evrard-like sphere, 1,000,000 particles (analytic h, dense centre): the
   same, covering the dense-cell and per-lane search paths at full size.
-* Rotating square patch 400^3 (64,000,000 particles): too large for the
-  oracle, so properties that hold at any size: linear momentum of the
-  pairwise forces to round-off, neighbour counts within the lattice bounds,
-  and L_z and total energy after steps.
+* Rotating square patch 400^3 (64,000,000 particles): a random sample of
+  10^4 particles per call against the oracle's subset evaluator (neighbour
+  sets bit-exact; rho, a, du/dt in FP64 and FP32-pair, on identical input
+  snapshots), which runs the 64-bit record offsets of the pair kernels (the
+  records exceed 4 GiB); and properties that hold at any size: linear
+  momentum of the pairwise forces to round-off, neighbour counts within the
+  lattice bounds, and L_z and total energy after steps.
 """
 import numpy as np
 import pytest
@@ -65,6 +68,24 @@ def test_evrard_1M_every_particle():
     _check(ic, ref, max_nb, "evrard 1M")
 
 
+def test_evrard_1M_gpu_iterated_h():
+    """The Evrard sphere in the state the bench times: h from the GPU's own
+    count iteration (sph_smoothing_length), whose largest h sets coarser
+    cells than the analytic guess, so the dense centre takes the dense-union
+    walk with more candidates. Every particle's set bit-exact, fields within
+    the FP64 and FP32-pair tolerances."""
+    ic = I.evrard(1_000_000, seed=0)
+    print("case Evrard 1M, GPU-iterated h", flush=True)
+    ctx = S.Context(ic.n, 64)
+    st = S.SphState(ic, 64)
+    S.sph_smoothing_length(ctx, st)
+    ic.h = st.host(["h"])["h"]
+    del ctx, st
+    ref = oracle_forces(ic, rho_ref=np.ones(ic.n))
+    max_nb = int(np.diff(ref["off"]).max()) + 8
+    _check(ic, ref, max_nb, "evrard 1M iterated h")
+
+
 def test_evrard_1M_smoothing_length_bitwise():
     """The GPU h iteration at full size equals the oracle's bit for bit."""
     import oracle as O
@@ -82,7 +103,34 @@ def test_evrard_1M_smoothing_length_bitwise():
     assert np.array_equal(got["h"], h_ref)
 
 
-def test_square_patch_64M_invariants():
+def _sampled_parity(ctx, st, ic, prm, precision, sel, ref, label):
+    """One density and one EOS + momentum call of the given precision on the
+    state's current lists, checked on the sampled particles against the
+    oracle's subset results ref (computed on the same FP64 snapshot). The
+    momentum call gets the FP64 density the oracle used."""
+    import torch as T
+    n = ic.n
+    p = S.make_params(ic.params, precision)
+    S.sph_density(ctx, st, p)
+    S.sph_ctx_check(ctx)
+    rho = st.t["rho"][:n][T.as_tensor(sel, device=st.device)].cpu().numpy()
+    er = float(np.max(np.abs(rho - ref["rho"]) / ref["rho"]))
+    st.t["rho"][:n].copy_(T.as_tensor(ref["rho_all"], device=st.device))
+    S.sph_eos(ctx, st, p)
+    S.sph_momentum_energy(ctx, st, p)
+    S.sph_ctx_check(ctx)
+    sl = T.as_tensor(sel, device=st.device)
+    g = {k: st.t[k][:n][sl].cpu().numpy() for k in ("ax", "ay", "az", "dudt")}
+    da = np.sqrt((g["ax"] - ref["ax"]) ** 2 + (g["ay"] - ref["ay"]) ** 2
+                 + (g["az"] - ref["az"]) ** 2)
+    ea = float(np.max(da / np.where(ref["sa"] > 0, ref["sa"], 1.0)))
+    eu = float(np.max(np.abs(g["dudt"] - ref["dudt"]) / np.where(ref["su"] > 0, ref["su"], 1.0)))
+    print(label, "sampled errors rho", er, "a", ea, "du", eu, flush=True)
+    return er, ea, eu
+
+
+def test_square_patch_64M_sampled_and_invariants():
+    import oracle as O
     ic = I.square_patch(400, seed=0)
     n = ic.n
     print("case square patch 400^3", flush=True)
@@ -92,6 +140,35 @@ def test_square_patch_64M_invariants():
     S.sph_init_forces(ctx, st, prm, set_rho_ref=True)
     S.sph_ctx_check(ctx)
     t = st.t
+    # sampled parity per call, on the state after the t = 0 evaluation (the
+    # lists, density, pressure and sound speed of this state; GPU order)
+    keys = ("x", "y", "z", "vx", "vy", "vz", "h", "m", "rho", "c", "pr2", "count")
+    H = {k: t[k][:n].cpu().numpy() for k in keys}
+    sel = np.sort(np.random.default_rng(7).choice(n, 10_000, replace=False))
+    box = (ic.lo, ic.hi, ic.periodic)
+    so, si = O.neighbors_subset(H["x"], H["y"], H["z"], H["h"], *box, sel)
+    rows = t["idx"][: 128 * n].view(128, n)[:, torch.as_tensor(sel, device=st.device)]
+    rows = rows.cpu().numpy()
+    for q in range(len(sel)):
+        c = int(H["count"][sel[q]])
+        assert c == so[q + 1] - so[q], q
+        assert np.array_equal(rows[:c, q], si[so[q]:so[q + 1]]), q
+    ref = {"rho": O.density_subset(H["x"], H["y"], H["z"], H["h"], H["m"], *box, sel, so, si),
+           "rho_all": H["rho"]}
+    ref.update(O.momentum_energy_subset(H["x"], H["y"], H["z"], H["vx"], H["vy"], H["vz"],
+                                        H["h"], H["m"], H["rho"], H["c"], H["pr2"], *box, sel,
+                                        so, si, ic.params))
+    del H
+    er, ea, eu = _sampled_parity(ctx, st, ic, prm, S.SPH_FP64, sel, ref, "64M fp64")
+    assert er <= FP64_TOL and ea <= FP64_TOL and eu <= FP64_TOL
+    er, ea, eu = _sampled_parity(ctx, st, ic, prm, S.SPH_FP32_PAIR, sel, ref, "64M fp32-pair")
+    assert er <= FP32_TOL and ea <= FP32_TOL and eu <= FP32_TOL
+    # back to the FP64 state for the invariants
+    S.sph_density(ctx, st, prm)
+    S.sph_eos(ctx, st, prm)
+    S.sph_momentum_energy(ctx, st, prm)
+    S.sph_timestep(ctx, st, prm)
+    S.sph_ctx_check(ctx)
     cnt = t["count"][:n]
     # interior lattice particles have 92..122 neighbours, none more than 128
     assert int(cnt.max().item()) <= 128 and int(cnt.min().item()) >= 20

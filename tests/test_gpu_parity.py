@@ -253,7 +253,7 @@ def test_evrard_variable_h():
                              rho_in=ref["rho"], export=False)
     e32 = field_errors(ref, got32)
     print("evrard fp32-pair", e32)
-    assert e32["a"] <= FP32_TOL and e32["du"] <= FP32_TOL
+    assert e32["rho"] <= FP32_TOL and e32["a"] <= FP32_TOL and e32["du"] <= FP32_TOL
 
 
 @pytest.mark.parametrize("case", ["evrard_20k", "cloud_periodic"])

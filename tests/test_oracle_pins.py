@@ -1028,3 +1028,37 @@ def test_blocks_stale_fields_of_waiting_particles():
         for k in ("rho", "c", "pr2"):
             rho_prev[k] = t[k].copy()
     assert changed > 0
+
+
+def test_subset_evaluation_equals_full_evaluation():
+    """The subset evaluator (used for sampled parity where the oracle cannot
+    evaluate every particle) returns, for each selected particle, exactly the
+    full evaluation's neighbour set, density and pair sums, and the sets
+    match an independent numpy brute force."""
+    ic = I.random_cloud(4000, seed=31, h_min=0.03, h_max=0.07, periodic=(0, 0, 1),
+                        velocity=1.5)
+    box = (ic.lo, ic.hi, ic.periodic)
+    off, ids = O.neighbors(ic.x, ic.y, ic.z, ic.h, *box)
+    rho = O.density(ic.x, ic.y, ic.z, ic.h, ic.m, *box, off, ids)
+    p, c, pr2 = O.eos(ic.params, rho, ic.u, rho, ic.p_bg)
+    full = O.momentum_energy(ic.x, ic.y, ic.z, ic.vx, ic.vy, ic.vz, ic.h, ic.m, rho, c, pr2,
+                             *box, off, ids, ic.params, scales=True)
+    sel = np.random.default_rng(2).choice(ic.n, 300, replace=False)
+    so, si = O.neighbors_subset(ic.x, ic.y, ic.z, ic.h, *box, sel)
+    P = np.stack([ic.x, ic.y, ic.z], 1)
+    Lz = ic.hi[2] - ic.lo[2]
+    for q, i in enumerate(sel):
+        assert np.array_equal(si[so[q]:so[q + 1]], ids[off[i]:off[i + 1]])
+        d = P - P[i]
+        d[:, 2] -= Lz * np.round(d[:, 2] / Lz)
+        r2 = (d ** 2).sum(1)
+        want = np.nonzero(r2 < (2 * np.maximum(ic.h, ic.h[i])) ** 2)[0]
+        want = want[want != i]
+        assert np.array_equal(np.sort(want), si[so[q]:so[q + 1]])
+    rs = O.density_subset(ic.x, ic.y, ic.z, ic.h, ic.m, *box, sel, so, si)
+    assert np.array_equal(rs, rho[sel])
+    sub = O.momentum_energy_subset(ic.x, ic.y, ic.z, ic.vx, ic.vy, ic.vz, ic.h, ic.m, rho, c,
+                                   pr2, *box, sel, so, si, ic.params)
+    for k in ("ax", "ay", "az", "dudt", "mumax", "sa", "su"):
+        assert np.array_equal(sub[k], full[k][sel]), k
+
