@@ -433,12 +433,18 @@ sph_status sph_step_blocks(sph_ctx ctx, const sph_particles *p, const sph_box *b
  * periodic axes) into count[] (DEVICE, n int32, current order); stop when
  * every N_i is in [lo_count, hi_count] or it == max_iter; otherwise, for the
  * particles outside the band, h_i <- 2 h_i if N_i = 0, else
- * h_i <- (h_i / 2) (1 + (n_target / N_i)^(1/3)), the cube root evaluated
- * on the host per distinct count. *iterations (HOST) receives the last it.
- * On return the cells are built for the final h (sph_find_neighbors may
- * follow directly). Synchronising; may allocate a small table.
- * SPH_E_DOMAIN if a periodic axis becomes shorter than 4 h_max,
- * SPH_E_NONFINITE if h stops being finite and positive. */
+ * h_i <- (h_i / 2) (1 + (n_target / N_i)^(1/3)), the cube root by Newton's
+ * iteration in correctly rounded IEEE operations (seven steps from 3/2 after
+ * scaling into [1, 8) by powers of 8), evaluated on the device, so that any
+ * implementation of the same rule gets the same h. The sweeps run on the
+ * device on the cells built for the starting largest h (a particle may grow
+ * to 2 h_i = two cells); the host steps in only to rebuild when a particle
+ * outgrows that, and once at the end. *iterations (HOST) receives the last
+ * it. On return the cells are built for the final h (sph_find_neighbors may
+ * follow directly) and count[] is in that order. Synchronising (twice when
+ * no particle outgrows the cells); allocates nothing.
+ * SPH_E_DOMAIN if a periodic axis is shorter than 4 h_max at the start or
+ * the end, SPH_E_NONFINITE if h stops being finite and positive. */
 sph_status sph_smoothing_length(sph_ctx ctx, sph_particles *p, const sph_box *box,
                                 double n_target, int32_t lo_count, int32_t hi_count,
                                 int32_t max_iter, int32_t *count, int32_t *iterations);

@@ -510,12 +510,32 @@ int64_t orc_neighbors_subset(int64_t n, const double *x, const double *y,
 }
 
 /*
+ * Cube root of a > 0 for the h update, by a rule both implementations
+ * follow so that their h agree bit for bit (a library cbrt is not correctly
+ * rounded and differs between libraries): Newton's iteration for y^3 = a,
+ * y <- (2 y + a / y^2) / 3, seven steps from y = 3/2 after bringing a into
+ * [1, 8) by exact factors of 8 (the start's relative error, at most 1/2,
+ * squares at every step), then scaled back by the matching power of 2.
+ * Only correctly rounded IEEE operations, no fused multiply-add.
+ */
+static double cbrt_newton(double a)
+{
+    int k = 0;
+    while (a >= 8.0) { a *= 0.125; ++k; }
+    while (a < 1.0) { a *= 8.0; --k; }
+    double y = 1.5;
+    for (int t = 0; t < 7; ++t) y = (2.0 * y + a / (y * y)) / 3.0;
+    return ldexp(y, k);
+}
+
+/*
  * Smoothing-length iteration toward a target neighbour count (Algorithm 1
  * step 2 and its footnote: the code aims at a given number of neighbours and
  * h follows from it). Gather count N_i = |{j != i : r^2 < 4 h_i^2}|; every
  * particle outside [lo_count, hi_count] is updated with
- * h <- h * (1 + (n_target / N_i)^(1/3)) / 2 (h doubles when N_i = 0); at most
- * max_iter sweeps. Returns the number of sweeps done.
+ * h <- h * (1 + (n_target / N_i)^(1/3)) / 2 (h doubles when N_i = 0; the
+ * cube root by cbrt_newton); at most max_iter sweeps. Returns the index of
+ * the last sweep.
  */
 int32_t orc_smoothing_length(int64_t n, const double *x, const double *y,
                              const double *z, double *h,
@@ -541,7 +561,7 @@ int32_t orc_smoothing_length(int64_t n, const double *x, const double *y,
         for (int64_t i = 0; i < n; ++i) {
             if (cnt[i] >= lo_count && cnt[i] <= hi_count) continue;
             if (cnt[i] == 0) h[i] = 2.0 * h[i];
-            else h[i] = h[i] * 0.5 * (1.0 + cbrt(n_target / (double)cnt[i]));
+            else h[i] = h[i] * 0.5 * (1.0 + cbrt_newton(n_target / (double)cnt[i]));
         }
     }
     if (count_out) memcpy(count_out, cnt, sizeof(int32_t) * (size_t)n);

@@ -380,7 +380,7 @@ sph_status sph_ctx_create(sph_ctx *out, int64_t n_max, int32_t max_nb, sph_strea
     ALLOC(ctx->nb_mask, (int64_t)kSearchMaskWords * ((n_max + 63) / 64) * 64);
     ALLOC(ctx->fb_tiles, (n_max + 63) / 64);
     ALLOC(ctx->fb_count, 1);
-    ALLOC(ctx->it_words, 2);
+    ALLOC(ctx->it_words, kItWords);
     ALLOC(ctx->it_hmax, 1);
     ALLOC(ctx->srec, n_max);
     ALLOC(ctx->drec, n_max);
@@ -860,64 +860,58 @@ sph_status sph_smoothing_length(sph_ctx ctx, sph_particles *p, const sph_box *bo
         return fail(ctx, SPH_E_INVALID, "count and iterations are required");
     *iterations = 0;
     if (p->n == 0) return SPH_OK;
-    double *factor = nullptr;
-    int64_t factor_len = 0;
-    auto done = [&](sph_status st) {
-        if (factor) (void)hipFree(factor);
-        return st;
-    };
-    int32_t it = 0;
-    for (it = 0; it <= max_iter; ++it) {
+    // The sweeps run on the device on the cells built for the largest h at
+    // the start (a particle may grow to 2 h = two cells); the host steps in
+    // only when a particle outgrows that reach (rebuild and continue) and
+    // once at the end, to rebuild the cells for the final h.
+    auto largest_h = [&](double *h_max) -> sph_status {
         unsigned long long hbits = 0;
         hipError_t e = launch_max_h(ctx, *p, ctx->it_hmax);
         if (e == hipSuccess)
             e = hipMemcpyAsync(&hbits, ctx->it_hmax, sizeof hbits, hipMemcpyDeviceToHost,
                                ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-        if (e != hipSuccess) return done(hip_fail(ctx, e, "largest h"));
-        double h_max;
-        std::memcpy(&h_max, &hbits, sizeof h_max);
-        if (!(h_max > 0.0) || !std::isfinite(h_max))
-            return done(fail(ctx, SPH_E_NONFINITE, "h is not finite and positive"));
+        if (e != hipSuccess) return hip_fail(ctx, e, "largest h");
+        std::memcpy(h_max, &hbits, sizeof *h_max);
+        if (!(*h_max > 0.0) || !std::isfinite(*h_max))
+            return fail(ctx, SPH_E_NONFINITE, "h is not finite and positive");
         for (int a = 0; a < 3; ++a)
-            if (box->periodic[a] && !(box->hi[a] - box->lo[a] > 4.0 * h_max))
-                return done(fail(ctx, SPH_E_DOMAIN,
-                                 "periodic axis %d is not longer than 4 h_max", a));
+            if (box->periodic[a] && !(box->hi[a] - box->lo[a] > 4.0 * *h_max))
+                return fail(ctx, SPH_E_DOMAIN, "periodic axis %d is not longer than 4 h_max", a);
+        return SPH_OK;
+    };
+    auto build = [&](double h_max) -> hipError_t {
         ctx->grid = make_grid(*box, h_max, ctx->cell_cap, kMaxAxisCells);
         ctx->n_built = p->n;
-        uint32_t words[2] = {0, 0};
-        e = launch_build_cells(ctx, *p, ctx->grid, h_max);
-        if (e == hipSuccess) e = launch_gather_count(ctx, *p, count, lo_count, hi_count,
-                                                     ctx->it_words);
+        return launch_build_cells(ctx, *p, ctx->grid, h_max);
+    };
+    double h_max = 0.0;
+    sph_status st;
+    int32_t sweep = 0;
+    uint32_t words[kItWords] = {};
+    for (;;) {
+        if ((st = largest_h(&h_max)) != SPH_OK) return st;
+        hipError_t e = build(h_max);
+        if (e == hipSuccess)
+            e = launch_h_iteration(ctx, *p, count, lo_count, hi_count, n_target, sweep, max_iter,
+                                   ctx->it_words);
         if (e == hipSuccess)
             e = hipMemcpyAsync(words, ctx->it_words, sizeof words, hipMemcpyDeviceToHost,
                                ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-        if (e != hipSuccess) return done(hip_fail(ctx, e, "gather counts"));
-        if (words[0] == 0 || it == max_iter) break;
-        // factor[k] = 1 + (n_target / k)^(1/3), evaluated here once per count
-        const int64_t need = (int64_t)words[1] + 1;
-        if (need > factor_len) {
-            if (factor) (void)hipFree(factor);
-            factor = nullptr;
-            factor_len = std::max<int64_t>(need, 1024);
-            if (hipMalloc((void **)&factor, sizeof(double) * factor_len) != hipSuccess) {
-                (void)hipGetLastError();
-                factor = nullptr;
-                return done(fail(ctx, SPH_E_NOMEM, "factor table allocation failed"));
-            }
-        }
-        std::vector<double> host((size_t)need);
-        host[0] = 0.0;
-        for (int64_t k = 1; k < need; ++k) host[k] = 1.0 + std::cbrt(n_target / (double)k);
-        e = hipMemcpyAsync(factor, host.data(), sizeof(double) * need, hipMemcpyHostToDevice,
-                           ctx->stream);
-        if (e == hipSuccess) e = launch_update_h(ctx, *p, count, lo_count, hi_count, factor);
-        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-        if (e != hipSuccess) return done(hip_fail(ctx, e, "h update"));
+        if (e != hipSuccess) return hip_fail(ctx, e, "smoothing-length sweeps");
+        sweep = (int32_t)words[3];
+        if (words[2]) break;      // done: the counts of sweep `sweep` are final
+        if (!words[4]) return fail(ctx, SPH_E_HIP, "smoothing-length sweeps did not finish");
     }
-    *iterations = it;
-    return done(SPH_OK);
+    *iterations = sweep;
+    // cells for the final h (this may reorder the particles, and the cells'
+    // largest (2 h)^2 must follow the grown h), then the final counts once
+    // more in that order (the same values)
+    if ((st = largest_h(&h_max)) != SPH_OK) return st;
+    SPH_HIP(ctx, build(h_max));
+    SPH_HIP(ctx, launch_gather_count(ctx, *p, count, lo_count, hi_count, ctx->it_words));
+    return SPH_OK;
 }
 
 sph_status sph_export_neighbors(sph_ctx ctx, const sph_particles *p, const sph_nbrs *nb,

@@ -308,6 +308,11 @@ __device__ __forceinline__ int stream_direct(const SearchRec &me, const int (&my
 // The first and last cell of an axis also hold the particles clamped into
 // them from outside the box, so their range is taken as unbounded on the
 // outer side, and their outer slice is always kept.
+// z_window_r: the same for a given reach r (s2max not read).
+__device__ __forceinline__ int2 z_window_r(int2 cr, uint32_t p, const Grid &g,
+                                           const double (&tlo)[3], const double (&thi)[3],
+                                           double r, const uint32_t *__restrict__ keys);
+
 __device__ __forceinline__ int2 z_window(int2 cr, uint32_t p, const Grid &g, const double (&tlo)[3],
                                          const double (&thi)[3], double s2t,
                                          const unsigned long long *__restrict__ s2max,
@@ -317,7 +322,15 @@ __device__ __forceinline__ int2 z_window(int2 cr, uint32_t p, const Grid &g, con
     const int x = (int)(p & 1023u), y = (int)((p >> 10) & 1023u), z = (int)(p >> 20);
     const int64_t cell = ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
     const double s2c = __longlong_as_double((long long)s2max[cell]);
-    const double r = sqrt(fmax(s2t, s2c));
+    return z_window_r(cr, p, g, tlo, thi, sqrt(fmax(s2t, s2c)), keys);
+}
+
+__device__ __forceinline__ int2 z_window_r(int2 cr, uint32_t p, const Grid &g,
+                                           const double (&tlo)[3], const double (&thi)[3],
+                                           double r, const uint32_t *__restrict__ keys)
+{
+    if (cr.x >= cr.y) return cr;
+    const int x = (int)(p & 1023u), y = (int)((p >> 10) & 1023u), z = (int)(p >> 20);
     const int cxy[2] = {x, y};
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -839,68 +852,163 @@ find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
 // integer count (filled by the host, so that the factor is the same number
 // as in any other implementation that evaluates the same expression).
 
-// Offsets -1, 0, +1 on one axis, without repeating a cell when a periodic
-// axis has fewer than 3 cells.
-__device__ __forceinline__ int axis_offsets(int nc, int periodic, int (&off)[3])
+// Offsets -k..k on one axis, without repeating a cell when a periodic axis
+// has fewer than 2k + 1 cells.
+__device__ __forceinline__ int axis_offsets(int nc, int periodic, int k, int (&off)[5])
 {
-    if (periodic && nc == 1) { off[0] = 0; return 1; }
-    if (periodic && nc == 2) { off[0] = 0; off[1] = 1; return 2; }
-    off[0] = -1; off[1] = 0; off[2] = 1;
-    return 3;
+    if (periodic && nc < 2 * k + 1) {
+        for (int d = 0; d < nc; ++d) off[d] = d;
+        return nc;
+    }
+    for (int d = -k; d <= k; ++d) off[d + k] = d;
+    return 2 * k + 1;
 }
 
+// Words of the on-device iteration (ctx->it_words): [0] particles outside
+// the band, [1] largest count, [2] done (the last sweep's counts are final),
+// [3] sweeps counted, [4] a particle outside the grid's reach (2 h > 2
+// cells): the host rebuilds the cells and continues.
+enum { IT_BAD = 0, IT_MAXC = 1, IT_DONE = 2, IT_SWEEP = 3, IT_REACH = 4, IT_WORDS = 5 };
+
+// Gather counts of one sweep: N_i = #{j != i : r^2 < (2 h_i)^2}. The cells
+// were built for a largest h that the sweeps may outgrow: a particle with
+// 2 h_i up to two cells walks the 5^3 cells around its own, beyond that the
+// sweep raises IT_REACH and counts nothing. Each cell reached without a
+// periodic image is walked only in its window for the own sphere (a point
+// box of reach 2 h_i): cells beyond it in x or y are skipped, in the others
+// only the z slices within reach. Does nothing once IT_DONE or IT_REACH is
+// set.
 __global__ void __launch_bounds__(256)
 gather_count_kernel(int64_t n, const SearchRec *__restrict__ srec,
                     const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
                     const int32_t *__restrict__ cend, Grid g, int32_t *__restrict__ count,
-                    int32_t lo_count, int32_t hi_count, uint32_t *bad, uint32_t *max_count)
+                    int32_t lo_count, int32_t hi_count, uint32_t *words)
 {
+    if (words[IT_DONE] || words[IT_REACH]) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const SearchRec me = srec[i];
-    const uint32_t key = keys[i] >> g.zbits;
-    const int myc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
-    int ox[3], oy[3], oz[3];
-    const int nx = axis_offsets(g.nc[0], g.periodic[0], ox);
-    const int ny = axis_offsets(g.nc[1], g.periodic[1], oy);
-    const int nz = axis_offsets(g.nc[2], g.periodic[2], oz);
-    const double no_shift[3] = {0.0, 0.0, 0.0};
+    bool active = i < n;
+    const SearchRec me = active ? srec[i] : SearchRec{0.0, 0.0, 0.0, 0.0};
+    const double R = sqrt(me.s2);
+    int k[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double reach = R * g.inv_s[a] * (1.0 + 1e-12);
+        k[a] = reach <= 1.0 ? 1 : (reach <= 2.0 ? 2 : 3);
+    }
+    const bool outgrown = active && (k[0] > 2 || k[1] > 2 || k[2] > 2);
+    if (__ballot(outgrown) != 0ull) {
+        if ((threadIdx.x & 63) == 0) atomicOr(&words[IT_REACH], 1u);
+        return;  // (the whole wave: the sweep is discarded)
+    }
     int cnt = 0;
-    for (int c = 0; c < nz; ++c) {
-        bool okz;
-        const int z = wrap_or_clip(myc[2] + oz[c], g.nc[2], g.periodic[2], okz);
-        if (!okz) continue;
-        for (int b = 0; b < ny; ++b) {
-            bool oky;
-            const int y = wrap_or_clip(myc[1] + oy[b], g.nc[1], g.periodic[1], oky);
-            if (!oky) continue;
-            for (int a = 0; a < nx; ++a) {
-                bool okx;
-                const int x = wrap_or_clip(myc[0] + ox[a], g.nc[0], g.periodic[0], okx);
-                if (!okx) continue;
-                const int64_t cell = ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
-                const int e = cend[cell];
-                for (int j = cstart[cell]; j < e; ++j)
-                    if (j != (int)i && related<WRAP_PAIR, true>(me, srec[j], g, no_shift)) ++cnt;
+    if (active) {
+        const uint32_t key = keys[i] >> g.zbits;
+        const int myc[3] = {(int)compact3(key), (int)compact3(key >> 1),
+                            (int)compact3(key >> 2)};
+        int ox[5], oy[5], oz[5];
+        const int nx = axis_offsets(g.nc[0], g.periodic[0], k[0], ox);
+        const int ny = axis_offsets(g.nc[1], g.periodic[1], k[1], oy);
+        const int nz = axis_offsets(g.nc[2], g.periodic[2], k[2], oz);
+        const double no_shift[3] = {0.0, 0.0, 0.0};
+        const double pt[3] = {me.x, me.y, me.z};
+        // a periodic axis with fewer than 2k + 1 cells: every cell, once
+        const bool all_x = g.periodic[0] && g.nc[0] < 2 * k[0] + 1;
+        const bool all_y = g.periodic[1] && g.nc[1] < 2 * k[1] + 1;
+        const bool all_z = g.periodic[2] && g.nc[2] < 2 * k[2] + 1;
+        for (int c = 0; c < nz; ++c) {
+            bool okz = true;
+            const int zr = all_z ? oz[c] : myc[2] + oz[c];
+            const int z = all_z ? zr : wrap_or_clip(zr, g.nc[2], g.periodic[2], okz);
+            if (!okz) continue;
+            for (int b = 0; b < ny; ++b) {
+                bool oky = true;
+                const int yr = all_y ? oy[b] : myc[1] + oy[b];
+                const int y = all_y ? yr : wrap_or_clip(yr, g.nc[1], g.periodic[1], oky);
+                if (!oky) continue;
+                for (int a = 0; a < nx; ++a) {
+                    bool okx = true;
+                    const int xr = all_x ? ox[a] : myc[0] + ox[a];
+                    const int x = all_x ? xr : wrap_or_clip(xr, g.nc[0], g.periodic[0], okx);
+                    if (!okx) continue;
+                    const int64_t cell = ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
+                    int2 w = make_int2(cstart[cell], cend[cell]);
+                    // reached without a periodic image: only the window
+                    const bool direct = !all_x && !all_y && !all_z && x == xr && y == yr &&
+                                        z == zr;
+                    if (direct && g.zbits > 0)
+                        w = z_window_r(w, (uint32_t)x | ((uint32_t)y << 10) |
+                                              ((uint32_t)z << 20),
+                                       g, pt, pt, R, keys);
+                    for (int j = w.x; j < w.y; ++j)
+                        if (j != (int)i && related<WRAP_PAIR, true>(me, srec[j], g, no_shift))
+                            ++cnt;
+                }
             }
         }
+        count[i] = cnt;
     }
-    count[i] = cnt;
-    if (cnt < lo_count || cnt > hi_count) atomicAdd(bad, 1u);
-    atomicMax(max_count, (uint32_t)cnt);
+    // one atomic per wave for each word
+    const uint64_t bad = __ballot(active && (cnt < lo_count || cnt > hi_count));
+    int m = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) {
+        if (bad) atomicAdd(&words[IT_BAD], (uint32_t)__popcll(bad));
+        atomicMax(&words[IT_MAXC], (uint32_t)m);
+    }
 }
 
-// h <- 2 h for an empty sphere, else (h / 2) (1 + (n_target / N)^(1/3)),
-// with the second factor read from the table at N.
+// End of a sweep (one thread): the counts of this sweep are final when every
+// particle is inside the band or this is sweep max_iter; else the h update
+// follows. Clears the band count for the next sweep.
+__global__ void sweep_end_kernel(uint32_t *words, int32_t max_iter)
+{
+    if (words[IT_DONE] || words[IT_REACH]) return;
+    if (words[IT_BAD] == 0 || (int32_t)words[IT_SWEEP] == max_iter) words[IT_DONE] = 1u;
+    else words[IT_SWEEP] += 1u;
+    words[IT_BAD] = 0u;
+}
+
+// Cube root of a > 0 by Newton's iteration for y^3 = a in correctly rounded
+// IEEE operations only, so that every implementation that performs the same
+// operations gets the same number: a is brought into [1, 8) by exact
+// factors of 8, y starts at 3/2 and takes seven steps y <- (2 y + a / y^2) / 3
+// (the relative error 1/2 of the start squares at each step), and the
+// result is scaled back by the matching power of 2.
+__device__ __forceinline__ double cbrt_newton(double a)
+{
+    int k = 0;
+    while (a >= 8.0) {
+        a *= 0.125;
+        ++k;
+    }
+    while (a < 1.0) {
+        a *= 8.0;
+        --k;
+    }
+    double y = 1.5;
+    for (int t = 0; t < 7; ++t) y = (2.0 * y + a / (y * y)) / 3.0;
+    return ldexp(y, k);
+}
+
+// h <- 2 h for an empty sphere, else (h / 2) (1 + (n_target / N)^(1/3)), for
+// the particles outside the band; their search records take the new
+// (2 h)^2. Does nothing once the counts are final.
 __global__ void __launch_bounds__(256)
 update_h_kernel(int64_t n, const int32_t *__restrict__ count, double *__restrict__ h,
-                int32_t lo_count, int32_t hi_count, const double *__restrict__ factor)
+                SearchRec *__restrict__ srec, int32_t lo_count, int32_t hi_count,
+                double n_target, const uint32_t *words)
 {
+    if (words[IT_DONE] || words[IT_REACH]) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int c = count[i];
     if (c >= lo_count && c <= hi_count) return;
-    h[i] = c == 0 ? 2.0 * h[i] : (h[i] * 0.5) * factor[c];
+    const double hn = c == 0 ? 2.0 * h[i]
+                             : (h[i] * 0.5) * (1.0 + cbrt_newton(n_target / (double)c));
+    h[i] = hn;
+    const double s = 2.0 * hn;
+    srec[i].s2 = s * s;
 }
 
 // Largest h, as the ordered bit patterns of positive doubles.
@@ -925,6 +1033,8 @@ __global__ void clear_words_kernel(uint32_t *a, int k)
 {
     if ((int)threadIdx.x < k) a[threadIdx.x] = 0u;
 }
+
+__global__ void set_word_kernel(uint32_t *a, uint32_t v) { *a = v; }
 
 }  // namespace
 
@@ -981,18 +1091,31 @@ hipError_t launch_max_h(sph_ctx ctx, const sph_particles &p, unsigned long long 
 hipError_t launch_gather_count(sph_ctx ctx, const sph_particles &p, int32_t *count,
                                int32_t lo_count, int32_t hi_count, uint32_t *words)
 {
-    clear_words_kernel<<<1, 64, 0, ctx->stream>>>(words, 2);
+    clear_words_kernel<<<1, 64, 0, ctx->stream>>>(words, IT_WORDS);
     gather_count_kernel<<<(unsigned)((p.n + 255) / 256), 256, 0, ctx->stream>>>(
         p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid, count,
-        lo_count, hi_count, words, words + 1);
+        lo_count, hi_count, words);
     return hipGetLastError();
 }
 
-hipError_t launch_update_h(sph_ctx ctx, const sph_particles &p, const int32_t *count,
-                           int32_t lo_count, int32_t hi_count, const double *factor)
+hipError_t launch_h_iteration(sph_ctx ctx, const sph_particles &p, int32_t *count,
+                              int32_t lo_count, int32_t hi_count, double n_target,
+                              int32_t first_sweep, int32_t max_iter, uint32_t *words)
 {
-    update_h_kernel<<<(unsigned)((p.n + 255) / 256), 256, 0, ctx->stream>>>(
-        p.n, count, p.h, lo_count, hi_count, factor);
+    // words: IT_WORDS counters, cleared here; sweeps counted from first_sweep
+    clear_words_kernel<<<1, 64, 0, ctx->stream>>>(words, IT_WORDS);
+    set_word_kernel<<<1, 1, 0, ctx->stream>>>(words + IT_SWEEP, (uint32_t)first_sweep);
+    const unsigned blocks = (unsigned)((p.n + 255) / 256);
+    for (int32_t it = first_sweep; it <= max_iter; ++it) {
+        gather_count_kernel<<<blocks, 256, 0, ctx->stream>>>(
+            p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid, count,
+            lo_count, hi_count, words);
+        sweep_end_kernel<<<1, 1, 0, ctx->stream>>>(words, max_iter);
+        if (it < max_iter)
+            update_h_kernel<<<blocks, 256, 0, ctx->stream>>>(p.n, count, p.h, ctx->srec,
+                                                            lo_count, hi_count, n_target,
+                                                            words);
+    }
     return hipGetLastError();
 }
 

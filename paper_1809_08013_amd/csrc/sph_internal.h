@@ -395,10 +395,18 @@ Grid make_grid(const sph_box &b, double h_max, int64_t cell_cap, int max_axis);
 
 // Smoothing-length iteration.
 hipError_t launch_max_h(sph_ctx ctx, const sph_particles &p, unsigned long long *out);
+// Sweeps first_sweep..max_iter of the count-based h iteration on the cells
+// last built, on the device: counts, the band test and the h update, with no
+// host work between sweeps. words (kItWords): [0] out-of-band count, [1]
+// largest count, [2] done, [3] last sweep, [4] a particle outgrew the cells
+// (the host rebuilds and calls again from sweep [3]).
+constexpr int kItWords = 5;
+// One count sweep on the cells last built (words cleared first).
 hipError_t launch_gather_count(sph_ctx ctx, const sph_particles &p, int32_t *count,
                                int32_t lo_count, int32_t hi_count, uint32_t *words);
-hipError_t launch_update_h(sph_ctx ctx, const sph_particles &p, const int32_t *count,
-                           int32_t lo_count, int32_t hi_count, const double *factor);
+hipError_t launch_h_iteration(sph_ctx ctx, const sph_particles &p, int32_t *count,
+                              int32_t lo_count, int32_t hi_count, double n_target,
+                              int32_t first_sweep, int32_t max_iter, uint32_t *words);
 
 // Ensemble launchers: fixed grids sized for b.cap; counts are read from the
 // step header on the device. F is the block of kEnsFields state rows

@@ -256,14 +256,22 @@ def test_evrard_variable_h():
     assert e32["rho"] <= FP32_TOL and e32["a"] <= FP32_TOL and e32["du"] <= FP32_TOL
 
 
-@pytest.mark.parametrize("case", ["evrard_20k", "cloud_periodic"])
+@pytest.mark.parametrize("case", ["evrard_20k", "cloud_periodic", "cloud_tiny_h",
+                                  "cloud_tiny_h_pz"])
 def test_smoothing_length_iteration_bitwise(case):
     """sph_smoothing_length reproduces the oracle's count-based h iteration
-    bit for bit: same iterations, same final gather counts, same h."""
+    bit for bit: same iterations, same final gather counts, same h. The
+    tiny-h clouds start far below the target (every count 0, h doubling), so
+    h outgrows the cells the device sweeps started on (two cells of reach)
+    and the host rebuilds them mid-iteration."""
     if case == "evrard_20k":
         ic = I.evrard(20000, seed=3)
-    else:
+    elif case == "cloud_periodic":
         ic = I.random_cloud(5000, seed=4, h_min=0.02, h_max=0.08, periodic=(1, 1, 1))
+    elif case == "cloud_tiny_h":
+        ic = I.random_cloud(4000, seed=6, h_min=0.002, h_max=0.004, periodic=(0, 0, 0))
+    else:
+        ic = I.random_cloud(4000, seed=7, h_min=0.002, h_max=0.004, periodic=(0, 0, 1))
     print("case", case, flush=True)
     h_ref, cnt_ref, it_ref = O.smoothing_length(ic.x, ic.y, ic.z, ic.h, ic.lo, ic.hi,
                                                 ic.periodic)
