@@ -498,7 +498,7 @@ void engine_main(sph_ens e)
         Upload *u = e->up[ring];
         BatchHdr &hd = u->hdr;
         std::vector<Run *> finishing;
-        int64_t start = 0, cbase = 0, rbase = 0;
+        int64_t start = 0, cbase = 0, rbase = 0, tbase = 0;
         int nl = 0;
         for (int s = 0; s < S; ++s) {
             RunDev &d = u->runs[s];
@@ -514,14 +514,18 @@ void engine_main(sph_ens e)
             hd.live_slot[nl] = s;
             hd.live_cell_base[nl] = (int32_t)cbase;
             hd.live_red_base[nl] = (int32_t)rbase;
+            hd.live_tile_base[nl] = (int32_t)tbase;
             ++nl;
             start += r->n;
             cbase += r->ncell;
             rbase += (r->n + kRedThreads - 1) / kRedThreads;
+            tbase += (r->n + 63) / 64;
             if (r->launched == r->n_steps) finishing.push_back(r);
         }
         hd.live_cell_base[nl] = (int32_t)cbase;
         hd.live_red_base[nl] = (int32_t)rbase;
+        hd.live_tile_base[nl] = (int32_t)tbase;
+        hd.ntile = tbase;
         hd.n_in = n_in;
         hd.n_out = start;
         hd.ncell = cbase;
@@ -707,7 +711,10 @@ sph_status sph_ens_create(sph_ens *out, const sph_ens_config *cfg)
     };
     if ((err = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking)) != hipSuccess)
         return bail(SPH_E_HIP, "hipStreamCreateWithFlags failed");
-    sph_status s = sph_ctx_create(&e->ctx, cap, cfg->max_nb, e->stream);
+    // the search cuts every run into its own tiles of 64: at most one more
+    // (partial) tile per run than the arena's capacity holds
+    sph_status s = sph_ctx_create(&e->ctx, cap + 64 * (int64_t)kEnsMaxSlots, cfg->max_nb,
+                                  e->stream);
     if (s != SPH_OK) {
         std::string m = std::string("scratch: ") + sph_last_error(nullptr);
         return bail(s, m.c_str());

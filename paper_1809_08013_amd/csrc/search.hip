@@ -31,9 +31,10 @@
 // streams the same union but lets each lane append its accepted candidates
 // directly; when no image is in play it walks, in each cell, only the z
 // slices (the lowest key bits order a cell's particles by z) within reach of
-// the tile's z extent. A wave with too many distinct cells, or whose particles belong to
-// two runs of an ensemble, takes the per-lane path instead: each lane walks
-// its own stencil (sorted by Morton key) and writes its entries directly. Both paths produce the same set in the
+// the tile's z extent. A wave with more distinct cells than its union build
+// holds (4, or 9 in an ensemble), or with a union of many dense cells, takes
+// the per-lane path instead: each lane walks its own stencil (sorted by
+// Morton key) and writes its entries directly. Both paths produce the same set in the
 // same (ascending) order, so the sums over a list do not depend on the path
 // or on where the tile boundaries fall.
 #include <algorithm>
@@ -47,8 +48,15 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
-constexpr int kMaxEntries = 128;        // 27 * distinct cells, before dedup
 constexpr int kMaxCandidates = kSearchMaskWords * 32;
+// Stencil entries (27 per distinct cell, before dedup) a tile's union build
+// holds: 4 distinct cells for one run, 9 for an ensemble, whose small runs
+// have few particles per cell so that 64 consecutive particles often span
+// more than four cells.
+template <bool Multi>
+constexpr int kEntries = Multi ? 256 : 128;
+// Cells of a union handed to the second kernel (held two per lane there).
+constexpr int kDenseCells = 2 * 64;
 constexpr int kMaxWords = kSearchMaskWords;
 // Grid of the second kernel: one-wave blocks draining the worklist, up to 32
 // per CU (its occupancy limit is 5 waves per SIMD); the blocks past the
@@ -127,34 +135,41 @@ __device__ __forceinline__ bool related(const SearchRec &me, const SearchRec &o,
     return (r2 < me.s2) | (r2 < o.s2);
 }
 
-// Per-wave LDS. The position -> cell table is filled after the stream and
-// the self-bit removal, when the union-build arrays are no longer read, and
-// overlays them.
+// Per-wave LDS, overlaid by lifetime: the union cells are formed from the
+// sorted entries (all entries are read before the first cell is written);
+// the position -> cell table is filled after the stream and the self-bit
+// removal, when the cells are no longer read; the first union positions are
+// written once the distinct keys have been read. At 256 entries this is 5 KiB
+// per wave, 20 KiB per block: 8 blocks per CU.
+template <int E>
 struct SearchLds {
+    static_assert(E % (2 * kWave) == 0 && E <= 256, "entries: whole pairs per lane, uint8 cells");
     union {
         struct {
-            uint32_t dkeys[kWave];
-            int2 ent[kMaxEntries];        // stencil entries {first particle, entry index}
-            int2 cells[kMaxEntries];      // union cells {first, end}, ascending
-            uint32_t cxyz[kMaxEntries];   // packed cell coordinates x | y << 10 | z << 20
+            union {
+                int2 ent[E];      // stencil entries {first particle, entry index}
+                int2 cells[E];    // union cells {first, end}, ascending (formed from ent)
+            };
+            uint32_t cxyz[E];     // packed cell coordinates x | y << 10 | z << 20
         };
         uint8_t cellof[kMaxCandidates];   // union position -> union cell
     };
-    int base[kMaxEntries];        // first particle minus first union position
-    int u0[kMaxEntries + 1];      // first union position of each cell
+    union {
+        uint32_t dkeys[kWave];    // keys of the tile's distinct cells
+        int u0[E];                // first union position of each cell
+    };
+    int base[E];                  // first particle minus first union position
 };
-static_assert(kMaxCandidates <= 4 * kWave + 8 * kMaxEntries * 2 + 4 * kMaxEntries,
-              "the cell table overlays the union-build arrays");
 
 // Stream the union (cells[0..nu)) and record, for each candidate u, whether
 // it is related to the lane's particle. Masks are 32-bit words bm[word][lane]
 // (word = u / 32) filled from the top: candidate u sits at bit 31 - u % 32.
 // Within a cell the next four records are loaded while the current four are
 // tested, so the scalar-load latency is overlapped with work.
-template <int Mode, bool UniformH>
+template <int Mode, bool UniformH, int E>
 __device__ __forceinline__ void stream_union(const SearchRec &me, const int (&myc)[3],
                                              const SearchRec *__restrict__ srec,
-                                             const SearchLds &L, int nu, const Grid &g,
+                                             const SearchLds<E> &L, int nu, const Grid &g,
                                              uint32_t *__restrict__ bm, int lane, int &cnt,
                                              uint64_t &occ0, uint32_t &occ1)
 {
@@ -366,24 +381,51 @@ __device__ __forceinline__ int2 z_window_r(int2 cr, uint32_t p, const Grid &g,
     return make_int2(first, a);
 }
 
-// One tile of 64 particles. Multi: the particles belong to runs of an
-// ensemble (slot in the high key bits); a tile whose particles are all of one
-// run uses that run's grid and cell range, a tile spanning two runs takes the
-// per-lane path with each lane's own run.
+// First particle and end of search tile `tile`. One run: tiles of 64 from
+// particle 0, the last one ending at n. An ensemble: each live run is cut
+// into its own tiles from its first particle (the step header's tile bases),
+// so that no tile holds particles of two runs and the run's tiles are the
+// ones it has alone.
+template <bool Multi>
+__device__ __forceinline__ void tile_span(int64_t tile, int64_t n, const BatchDev &b,
+                                          int64_t &t0, int64_t &tend)
+{
+    if constexpr (!Multi) {
+        t0 = tile * kWave;
+        tend = min(t0 + (int64_t)kWave, n);
+    } else {
+        const BatchHdr *hd = b.hdr;
+        int lo = 0, hi = hd->nlive - 1;
+        while (lo < hi) {  // last live run whose first tile is <= tile
+            const int mid = (lo + hi + 1) >> 1;
+            if (hd->live_tile_base[mid] <= tile) lo = mid; else hi = mid - 1;
+        }
+        const RunDev &r = b.runs[hd->live_slot[lo]];
+        t0 = (int64_t)r.start + (tile - hd->live_tile_base[lo]) * (int64_t)kWave;
+        tend = min(t0 + (int64_t)kWave, (int64_t)r.start + r.n);
+    }
+}
+
+// One tile of 64 particles. Multi: the particles belong to one run of an
+// ensemble (slot in the high key bits) and the tile uses that run's grid
+// and cell range; a tile found spanning two runs would take the per-lane
+// path with each lane's own run.
 template <bool Multi>
 __device__ __forceinline__ void search_tile(
     int64_t tile, int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
     const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
     const int32_t *__restrict__ cend, const Grid &g0, int max_nb, int32_t *__restrict__ count,
     int32_t *__restrict__ idx, uint32_t *__restrict__ mask_scratch,
-    const uint32_t *__restrict__ hflag, uint32_t *status0, const BatchDev &b, SearchLds &L,
+    const uint32_t *__restrict__ hflag, uint32_t *status0, const BatchDev &b,
+    SearchLds<kEntries<Multi>> &L,
     int32_t *__restrict__ fb_tiles, uint32_t *fb_count)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t t0 = tile * kWave;
+    int64_t t0, tend;
+    tile_span<Multi>(tile, n, b, t0, tend);
     uint32_t *bm = mask_scratch + tile * (kMaxWords * kWave);
     const int64_t i = t0 + lane;
-    const bool active = i < n;
+    const bool active = i < tend;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
     const uint32_t key = active ? keys[i] : 0xFFFFFFFFu;
@@ -396,7 +438,16 @@ __device__ __forceinline__ void search_tile(
         slot0 = __builtin_amdgcn_readfirstlane(my_slot);
         mixed = __ballot(active && my_slot != slot0) != 0ull;
     }
-    const Grid &g = Multi ? b.runs[slot0].grid : g0;
+    // the run's grid, read once into wave-uniform registers
+    Grid gm;
+    if constexpr (Multi) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(&b.runs[slot0].grid);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&gm);
+#pragma unroll
+        for (int k = 0; k < (int)(sizeof(Grid) / 4); ++k)
+            dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    }
+    const Grid &g = Multi ? gm : g0;
     const int64_t cbase = Multi ? (int64_t)b.runs[slot0].cell_base : 0;
     // cell part of the key (run and Morton code, without the z slice)
     const uint32_t ckey = key >> (Multi ? kSliceBits : g0.zbits);
@@ -427,13 +478,15 @@ __device__ __forceinline__ void search_tile(
         if (g.nc[a] < 5) few_cells = true;
     }
 
+    constexpr int E = kEntries<Multi>;
+    constexpr int kC = E / kWave;  // entries per lane
     const int nent = ndist * kStencil;
-    bool use_union = nent <= kMaxEntries && !mixed;
+    bool use_union = nent <= E && !mixed;
     int nu = 0, total = 0;
     wave_sync();
     if (use_union) {
         // stencil cells of every distinct cell; empty ones become sentinels
-        for (int e = lane; e < kMaxEntries; e += kWave) {
+        for (int e = lane; e < E; e += kWave) {
             int2 v = make_int2(INT_MAX, e);
             if (e < nent) {
                 const uint32_t k = L.dkeys[e / kStencil];
@@ -453,34 +506,46 @@ __device__ __forceinline__ void search_tile(
             L.ent[e] = v;
         }
         wave_sync();
-        // bitonic sort of the 128 entries by first particle, one pair per
-        // lane per step
-        for (int k = 2; k <= kMaxEntries; k <<= 1) {
+        // bitonic sort of the E entries by first particle: the E / 2
+        // compare-exchanges of a step are disjoint, kC / 2 per lane
+        for (int k = 2; k <= E; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
-                const int lo_i = ((lane & ~(j - 1)) << 1) | (lane & (j - 1));
-                const int hi_i = lo_i | j;
-                const int2 ea = L.ent[lo_i], eb = L.ent[hi_i];
-                const bool up = (lo_i & k) == 0;
-                if ((ea.x > eb.x) == up) {
-                    L.ent[lo_i] = eb;
-                    L.ent[hi_i] = ea;
+#pragma unroll
+                for (int q = 0; q < kC / 2; ++q) {
+                    const int p = lane + q * kWave;
+                    const int lo_i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+                    const int hi_i = lo_i | j;
+                    const int2 ea = L.ent[lo_i], eb = L.ent[hi_i];
+                    const bool up = (lo_i & k) == 0;
+                    if ((ea.x > eb.x) == up) {
+                        L.ent[lo_i] = eb;
+                        L.ent[hi_i] = ea;
+                    }
                 }
                 wave_sync();
             }
         }
         // drop sentinels and duplicates (a cell listed by several stencils);
-        // a kept entry's cell is recomputed from its entry index
-        const int2 v0 = L.ent[lane], v1 = L.ent[lane + kWave];
-        const int p0 = lane == 0 ? INT_MIN : L.ent[lane - 1].x;
-        const int p1 = L.ent[lane + kWave - 1].x;
-        const bool k0 = v0.x != INT_MAX && v0.x != p0;
-        const bool k1 = v1.x != INT_MAX && v1.x != p1;
-        const uint64_t m0 = __ballot(k0), m1 = __ballot(k1);
-        const int n0 = __popcll(m0);
-        nu = n0 + __popcll(m1);
-        auto keep = [&](const int2 v, int pos) {
-            const uint32_t k = L.dkeys[v.y / kStencil];
-            const int s = v.y % kStencil;
+        // a kept entry's cell is recomputed from its entry index. Lane holds
+        // entries lane + q * 64.
+        int2 v[kC];
+        bool kp[kC];
+        uint64_t m[kC];
+        int off[kC + 1];
+        off[0] = 0;
+#pragma unroll
+        for (int q = 0; q < kC; ++q) {
+            const int e = lane + q * kWave;
+            v[q] = L.ent[e];
+            const int pv = e == 0 ? INT_MIN : L.ent[e - 1].x;
+            kp[q] = v[q].x != INT_MAX && v[q].x != pv;
+            m[q] = __ballot(kp[q]);
+            off[q + 1] = off[q] + __popcll(m[q]);
+        }
+        nu = off[kC];
+        auto keep = [&](const int2 ve, int pos) {
+            const uint32_t k = L.dkeys[ve.y / kStencil];
+            const int s = ve.y % kStencil;
             bool ok;
             const int x = wrap_or_clip((int)compact3(k) + s % 3 - 1, g.nc[0], g.periodic[0], ok);
             const int y = wrap_or_clip((int)compact3(k >> 1) + (s / 3) % 3 - 1, g.nc[1],
@@ -488,52 +553,51 @@ __device__ __forceinline__ void search_tile(
             const int z = wrap_or_clip((int)compact3(k >> 2) + s / 9 - 1, g.nc[2],
                                        g.periodic[2], ok);
             const int64_t cell = cbase + ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
-            L.cells[pos] = make_int2(v.x, cend[cell]);
+            L.cells[pos] = make_int2(ve.x, cend[cell]);
             L.cxyz[pos] = (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
         };
-        if (k0) keep(v0, __popcll(m0 & lt));
-        if (k1) keep(v1, n0 + __popcll(m1 & lt));
-        wave_sync();
-        // u0[c]: exclusive prefix of the cell lengths; lane holds c = lane and
-        // c = lane + 64
-        const int l0 = lane < nu ? L.cells[lane].y - L.cells[lane].x : 0;
-        const int l1 = lane + kWave < nu ? L.cells[lane + kWave].y - L.cells[lane + kWave].x : 0;
-        int s0 = l0, s1 = l1;
 #pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int t0s = __shfl_up(s0, o, kWave), t1s = __shfl_up(s1, o, kWave);
-            if (lane >= o) {
-                s0 += t0s;
-                s1 += t1s;
+        for (int q = 0; q < kC; ++q)
+            if (kp[q]) keep(v[q], off[q] + __popcll(m[q] & lt));
+        wave_sync();
+        // u0[c]: exclusive prefix of the cell lengths; lane holds cells
+        // c = lane + q * 64
+#pragma unroll
+        for (int q = 0; q < kC; ++q) {
+            const int c = lane + q * kWave;
+            const int l = c < nu ? L.cells[c].y - L.cells[c].x : 0;
+            int sc = l;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int t = __shfl_up(sc, o, kWave);
+                if (lane >= o) sc += t;
             }
+            if (c < nu) {
+                L.u0[c] = total + sc - l;
+                L.base[c] = L.cells[c].x - (total + sc - l);
+            }
+            total += __shfl(sc, kWave - 1, kWave);
         }
-        const int tot0 = __shfl(s0, kWave - 1, kWave);
-        total = tot0 + __shfl(s1, kWave - 1, kWave);
-        if (lane < nu) {
-            L.u0[lane] = s0 - l0;
-            L.base[lane] = L.cells[lane].x - (s0 - l0);
-        }
-        if (lane + kWave < nu) {
-            L.u0[lane + kWave] = tot0 + s1 - l1;
-            L.base[lane + kWave] = L.cells[lane + kWave].x - (tot0 + s1 - l1);
-        }
-        if (lane == 0) L.u0[nu] = total;
         wave_sync();
         if (total > kMaxCandidates) {
-            // Too large for the masks: the second kernel walks the same union,
-            // read from this tile's scratch region (cells, then coordinates,
-            // then the count), with each lane appending directly.
-            int2 *gc = reinterpret_cast<int2 *>(bm);
-            uint32_t *gx = bm + 2 * kMaxEntries;
-            for (int c = lane; c < nu; c += kWave) {
-                gc[c] = L.cells[c];
-                gx[c] = L.cxyz[c];
+            if (nu <= kDenseCells) {
+                // Too large for the masks: the second kernel walks the same
+                // union, read from this tile's scratch region (cells, then
+                // coordinates, then the count), with each lane appending
+                // directly.
+                int2 *gc = reinterpret_cast<int2 *>(bm);
+                uint32_t *gx = bm + 2 * kDenseCells;
+                for (int c = lane; c < nu; c += kWave) {
+                    gc[c] = L.cells[c];
+                    gx[c] = L.cxyz[c];
+                }
+                if (lane == 0) {
+                    bm[3 * kDenseCells] = (uint32_t)nu;
+                    fb_tiles[atomicAdd(fb_count, 1u)] = (int32_t)(0x80000000u | (uint32_t)tile);
+                }
+                return;
             }
-            if (lane == 0) {
-                bm[3 * kMaxEntries] = (uint32_t)nu;
-                fb_tiles[atomicAdd(fb_count, 1u)] = (int32_t)(0x80000000u | (uint32_t)tile);
-            }
-            return;
+            use_union = false;  // many dense cells: the per-lane path
         }
     }
 
@@ -579,7 +643,7 @@ __device__ __forceinline__ void search_tile(
         // union position -> union cell, for the expansion (overlays the
         // union-build arrays, which are not read after this point)
         for (int c = 0; c < nu; ++c) {
-            const int a = L.u0[c], e = L.u0[c + 1];
+            const int a = L.u0[c], e = c + 1 < nu ? L.u0[c + 1] : total;
             for (int uu = a + lane; uu < e; uu += kWave) L.cellof[uu] = (uint8_t)c;
         }
         wave_sync();
@@ -667,8 +731,10 @@ fallback_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
     for (uint32_t q = blockIdx.x; q < nfb; q += gridDim.x) {
     const uint32_t entry = (uint32_t)fb_tiles[q];
     const int64_t tile = (int64_t)(entry & 0x7FFFFFFFu);
-    const int64_t i = tile * kWave + lane;
-    const bool active = i < n;
+    int64_t t0, tend;
+    tile_span<Multi>(tile, n, b, t0, tend);
+    const int64_t i = t0 + lane;
+    const bool active = i < tend;
     const uint32_t key = active ? keys[i] : 0xFFFFFFFFu;
     const SearchRec me = active ? srec[i] : SearchRec{0.0, 0.0, 0.0, 0.0};
     const int my_slot = Multi && active ? (int)(key >> kEnsSlotShift) : 0;
@@ -678,7 +744,7 @@ fallback_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
     if (entry & 0x80000000u) {
         // a union too large for the masks (its particles are of one run)
         const uint32_t *bm = mask_scratch + tile * (kMaxWords * kWave);
-        const int nu = (int)__builtin_amdgcn_readfirstlane(bm[3 * kMaxEntries]);
+        const int nu = (int)__builtin_amdgcn_readfirstlane(bm[3 * kDenseCells]);
         const int slot0 = __builtin_amdgcn_readfirstlane(my_slot);
         const Grid &g = Multi ? b.runs[slot0].grid : g0;
         bool wrap = false, few_cells = false;
@@ -697,7 +763,7 @@ fallback_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
         const bool uniform_h = Multi ? b.runs[slot0].uniform_h != 0 : hflag[0] == 0;
         const int mode = !wrap ? WRAP_NONE : (few_cells ? WRAP_PAIR : WRAP_CELL);
         const int2 *gc = reinterpret_cast<const int2 *>(bm);
-        const uint32_t *gx = bm + 2 * kMaxEntries;
+        const uint32_t *gx = bm + 2 * kDenseCells;
         int2 r0 = make_int2(0, 0), r1 = make_int2(0, 0);
         uint32_t p0 = 0u, p1 = 0u;
         if (lane < nu) {
@@ -822,25 +888,35 @@ find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
                       uint32_t *status, BatchDev b, int32_t *__restrict__ fb_tiles,
                       uint32_t *fb_count, StepMask mask)
 {
-    __shared__ SearchLds lds[kWavesPerBlock];
+    __shared__ SearchLds<kEntries<Multi>> lds[kWavesPerBlock];
     const int w = threadIdx.x / kWave;
-    SearchLds &L = lds[w];
+    SearchLds<kEntries<Multi>> &L = lds[w];
     const int64_t nn = Multi ? b.hdr->n_out : n;
-    const int64_t ntile = (nn + kWave - 1) / kWave;
-    // the four waves of a block work on consecutive tiles, independently
-    for (int64_t tile = xcd_block() * kWavesPerBlock + w; tile < ntile;
-         tile += (int64_t)gridDim.x * kWavesPerBlock) {
-        if (!Multi && mask.bin) {
+    int64_t tile;
+    if constexpr (Multi) {
+        // The grid covers the capacity's tiles, the step uses the first
+        // ntile: its blocks are spread over the eight XCDs (block b runs on
+        // XCD b % 8), each XCD taking a contiguous range, and the rest exit.
+        const int64_t ntile = b.hdr->ntile;
+        const int64_t tb = (ntile + kWavesPerBlock - 1) / kWavesPerBlock;
+        const int64_t per = (tb + 7) / 8;
+        const int64_t pos = blockIdx.x / 8;
+        const int64_t bt = (int64_t)(blockIdx.x % 8) * per + pos;
+        if (pos >= per || bt >= tb) return;
+        tile = bt * kWavesPerBlock + w;
+        if (tile >= ntile) return;
+    } else {
+        tile = xcd_block() * kWavesPerBlock + w;
+        if (tile >= (nn + kWave - 1) / kWave) return;
+        if (mask.bin) {
             // individual time steps: only tiles holding a particle whose step
             // closes need lists (the others keep their stale ones, unread)
             const int64_t i = tile * kWave + (threadIdx.x & (kWave - 1));
-            if (__ballot(i < nn && step_closes(mask, i)) == 0ull) break;
+            if (__ballot(i < nn && step_closes(mask, i)) == 0ull) return;
         }
-        search_tile<Multi>(tile, nn, ld, srec, keys, cstart, cend, g, max_nb, count, idx,
-                           mask_scratch, hflag, status, b, L, fb_tiles, fb_count);
-        wave_sync();
-        if (!Multi) break;
     }
+    search_tile<Multi>(tile, nn, ld, srec, keys, cstart, cend, g, max_nb, count, idx,
+                       mask_scratch, hflag, status, b, L, fb_tiles, fb_count);
 }
 
 
@@ -1064,10 +1140,10 @@ hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_
 hipError_t launch_find_neighbors_batch(sph_ctx ctx, const BatchDev &b, int max_nb,
                                        int32_t *count, int32_t *idx)
 {
-    // the mask scratch holds one region per tile of the capacity
-    const int64_t tiles = (b.cap + kWave - 1) / kWave;
-    const unsigned blocks = (unsigned)std::min<int64_t>(
-        (tiles + kWavesPerBlock - 1) / kWavesPerBlock, 4096);
+    // the mask scratch holds one region per tile: the capacity's, plus at
+    // most one partial tile per run (each run is cut into its own tiles)
+    const int64_t tiles = (b.cap + kWave - 1) / kWave + kEnsMaxSlots;
+    const unsigned blocks = (unsigned)((tiles + kWavesPerBlock - 1) / kWavesPerBlock);
     clear_count_kernel<<<1, 1, 0, ctx->stream>>>(ctx->fb_count);
     find_neighbors_kernel<true><<<blocks, kBlock, 0, ctx->stream>>>(
         0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,

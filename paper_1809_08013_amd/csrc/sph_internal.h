@@ -102,11 +102,15 @@ struct BatchHdr {
     int64_t n_out;   // particles of live runs, after the sort
     int64_t ncell;   // cells of live runs
     int64_t nred;    // reduction blocks of live runs
+    int64_t ntile;   // search tiles of live runs
     int32_t nlive;
     int32_t nnew;
     int32_t live_slot[kEnsMaxSlots];
     int32_t live_cell_base[kEnsMaxSlots + 1];
     int32_t live_red_base[kEnsMaxSlots + 1];
+    // first search tile of each live run: a run's particles are cut into
+    // tiles of 64 from its own first particle, so no tile holds two runs
+    int32_t live_tile_base[kEnsMaxSlots + 1];
     int32_t new_slot[kEnsMaxSlots];
     int32_t new_off[kEnsMaxSlots];
     int32_t new_n[kEnsMaxSlots];
