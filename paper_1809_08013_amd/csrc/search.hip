@@ -113,6 +113,55 @@ __device__ __forceinline__ int wrap_or_clip(int c, int nc, int periodic, bool &o
     return c;
 }
 
+// Squared separation of the relation test, with the image conventions of
+// the mode. sh: the per-cell image shift (WRAP_CELL).
+template <int Mode>
+__device__ __forceinline__ double sep2(const SearchRec &me, const SearchRec &o, const Grid &g,
+                                       const double (&sh)[3])
+{
+    double dx = me.x - o.x, dy = me.y - o.y, dz = me.z - o.z;
+    if (Mode == WRAP_CELL) {
+        dx += sh[0];
+        dy += sh[1];
+        dz += sh[2];
+    } else if (Mode == WRAP_PAIR) {
+        if (g.periodic[0]) dx = min_image_sel(dx, g.len[0], g.half[0]);
+        if (g.periodic[1]) dy = min_image_sel(dy, g.len[1], g.half[1]);
+        if (g.periodic[2]) dz = min_image_sel(dz, g.len[2], g.half[2]);
+    }
+    return __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+}
+
+// acc * 2 + [r2 < s2], s2 wave-uniform: the comparison's lane mask is the
+// carry-in of one add (acc + acc + carry), which shifts the bit in.
+__device__ __forceinline__ uint32_t shift_in(uint32_t acc, double r2, double s2)
+{
+    uint32_t out;
+    asm("v_cmp_gt_f64 vcc, %2, %1\n\t"
+        "v_addc_co_u32 %0, vcc, %3, %3, vcc"
+        : "=v"(out)
+        : "v"(r2), "s"(s2), "v"(acc)
+        : "vcc");
+    return out;
+}
+
+// acc * 2 + [r2 < s2a or r2 < s2b], s2b wave-uniform: the two lane masks are
+// joined on the scalar unit (comparing against the larger of the two would
+// cost two more vector instructions).
+__device__ __forceinline__ uint32_t shift_in2(uint32_t acc, double r2, double s2a, double s2b)
+{
+    uint32_t out;
+    uint64_t t;
+    asm("v_cmp_lt_f64 %1, %2, %3\n\t"
+        "v_cmp_gt_f64 vcc, %4, %2\n\t"
+        "s_or_b64 vcc, vcc, %1\n\t"
+        "v_addc_co_u32 %0, vcc, %5, %5, vcc"
+        : "=v"(out), "=&s"(t)
+        : "v"(r2), "v"(s2a), "s"(s2b), "v"(acc)
+        : "vcc", "scc");
+    return out;
+}
+
 // Relation test: r2 < (2h_i)^2 or r2 < (2h_j)^2, i.e. r2 < (2 max(h_i,h_j))^2.
 // UniformH: every particle has the same h, one compare against the lane's
 // own (2h)^2. sh: the per-cell image shift (WRAP_CELL).
@@ -182,32 +231,17 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const int (&my
         if (w < 64) occ0 |= word ? (1ull << w) : 0ull;
         else occ1 |= word ? (1u << (w - 64)) : 0u;
     };
-    auto bit = [&](const SearchRec &o) -> uint32_t {
-        return related<Mode, UniformH>(me, o, g, sh) ? 1u : 0u;
-    };
     auto step = [&](const SearchRec &o) {
-        acc = (acc << 1) | bit(o);
+        const double r2 = sep2<Mode>(me, o, g, sh);
+        // uniform h: every (2h)^2 is the same number, the candidate's is
+        // taken (a scalar operand, and the whole record is then loaded in
+        // wide scalar loads)
+        acc = UniformH ? shift_in(acc, r2, o.s2) : shift_in2(acc, r2, me.s2, o.s2);
         ++u;
         if ((u & 31) == 0) {
             flush((u >> 5) - 1, acc);
             acc = 0;
         }
-    };
-    auto step4 = [&](const SearchRec &o0, const SearchRec &o1, const SearchRec &o2,
-                     const SearchRec &o3) {
-        const uint32_t b4 = (bit(o0) << 3) | (bit(o1) << 2) | (bit(o2) << 1) | bit(o3);
-        const int room = 32 - (u & 31);
-        const int w = u >> 5;
-        if (room > 4) {
-            acc = (acc << 4) | b4;
-        } else if (room == 4) {
-            flush(w, (acc << 4) | b4);
-            acc = 0;
-        } else {
-            flush(w, (acc << room) | (b4 >> (4 - room)));
-            acc = b4 & ((1u << (4 - room)) - 1u);
-        }
-        u += 4;
     };
     for (int c = 0; c < nu; ++c) {
         const int s = __builtin_amdgcn_readfirstlane(L.cells[c].x);
@@ -228,7 +262,12 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const int (&my
             while (e - j >= 4) {
                 const SearchRec b0 = srec[j], b1 = srec[j + 1], b2 = srec[j + 2],
                                 b3 = srec[j + 3];
-                step4(a0, a1, a2, a3);
+                // issue the loads of b0..b3 before the work on a0..a3
+                __builtin_amdgcn_sched_barrier(0);
+                step(a0);
+                step(a1);
+                step(a2);
+                step(a3);
                 // keep the wait for b0..b3 (scalar loads complete out of order,
                 // so it is a full wait) after the work on a0..a3
                 __builtin_amdgcn_sched_barrier(0);
@@ -238,7 +277,10 @@ __device__ __forceinline__ void stream_union(const SearchRec &me, const int (&my
                 a3 = b3;
                 j += 4;
             }
-            step4(a0, a1, a2, a3);
+            step(a0);
+            step(a1);
+            step(a2);
+            step(a3);
         }
         for (; j < e; ++j) step(srec[j]);
     }
