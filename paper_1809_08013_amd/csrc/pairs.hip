@@ -354,9 +354,11 @@ density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
     __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kDensStride];
     char *buf = lds[threadIdx.x >> 6];
     if constexpr (Multi) {
+        // one tile per block over a capacity-sized grid (a loop over tiles
+        // keeps the loop-invariant values of the tile body live in registers)
         const int64_t nn = b.hdr->n_out;
-        const int64_t ntile = (nn + kThreads - 1) / kThreads;
-        for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
+        const int64_t t = xcd_used_block((nn + kThreads - 1) / kThreads);
+        if (t >= 0)
             density_tile<F32, true, Big, -1, KF>(t, nn, ld, drec, h, count, idx, max_nb, g, rho,
                                                  b, buf, sigma, sinc_n, mask);
     } else {
@@ -869,8 +871,8 @@ momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
     char *buf = lds[threadIdx.x >> 6];
     if constexpr (Multi) {
         const int64_t nn = b.hdr->n_out;
-        const int64_t ntile = (nn + kThreads - 1) / kThreads;
-        for (int64_t t = xcd_block(); t < ntile; t += gridDim.x)
+        const int64_t t = xcd_used_block((nn + kThreads - 1) / kThreads);
+        if (t >= 0)
             momentum_tile<F32, true, Big, -1, false, KF>(t, nn, ld, rec, count, idx, max_nb, g,
                                                          prm, ax, ay, az, dudt, mumax, b, buf);
     } else if constexpr (IAD || GVE) {
@@ -1208,8 +1210,10 @@ hipError_t launch_momentum(sph_ctx ctx, const sph_particles &p, const sph_nbrs &
     return hipGetLastError();
 }
 
-// Ensemble launches: fixed grids sized for the capacity (loops over the
-// header's count), so that the same captured sequence serves every step.
+// Ensemble launches: fixed grids sized for the capacity (the elementwise
+// kernels loop over the header's count, the gathers take one tile per block
+// and leave the blocks past it idle), so that the same captured sequence
+// serves every step.
 hipError_t launch_density_batch(sph_ctx ctx, const BatchDev &b, int precision, const double *F,
                                 const int32_t *count, const int32_t *idx, int max_nb,
                                 double *rho)
@@ -1217,7 +1221,7 @@ hipError_t launch_density_batch(sph_ctx ctx, const BatchDev &b, int precision, c
     const int64_t cap = b.cap;
     const int64_t *n_out = &b.hdr->n_out;
     const unsigned g1 = std::min<unsigned>(blocks_for(cap, 256), 4096u);
-    const unsigned g2 = std::min<unsigned>(blocks_for(cap, kThreads), 4096u);
+    const unsigned g2 = blocks_for(cap, kThreads);
     pack_dens_kernel<<<g1, 256, 0, ctx->stream>>>(0, n_out, F + 0 * cap, F + 1 * cap,
                                                   F + 2 * cap, F + 8 * cap, ctx->drec);
     density_launch<true>(ctx->stream, g2, precision, big_records(cap, sizeof(DensRec)), 0, cap,
@@ -1245,7 +1249,7 @@ hipError_t launch_momentum_batch(sph_ctx ctx, const BatchDev &b, int precision,
     const int64_t cap = b.cap;
     const int64_t *n_out = &b.hdr->n_out;
     const unsigned g1 = std::min<unsigned>(blocks_for(cap, 256), 4096u);
-    const unsigned g2 = std::min<unsigned>(blocks_for(cap, kThreads), 4096u);
+    const unsigned g2 = blocks_for(cap, kThreads);
     const bool r32 = precision == SPH_FP32_PAIR;  // PairRec32 records
     if (r32)
         pack_pair_kernel<true><<<g1, 256, 0, ctx->stream>>>(

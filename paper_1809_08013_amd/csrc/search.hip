@@ -937,14 +937,10 @@ find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
     int64_t tile;
     if constexpr (Multi) {
         // The grid covers the capacity's tiles, the step uses the first
-        // ntile: its blocks are spread over the eight XCDs (block b runs on
-        // XCD b % 8), each XCD taking a contiguous range, and the rest exit.
+        // ntile: their blocks are spread over the eight XCDs, the rest exit.
         const int64_t ntile = b.hdr->ntile;
-        const int64_t tb = (ntile + kWavesPerBlock - 1) / kWavesPerBlock;
-        const int64_t per = (tb + 7) / 8;
-        const int64_t pos = blockIdx.x / 8;
-        const int64_t bt = (int64_t)(blockIdx.x % 8) * per + pos;
-        if (pos >= per || bt >= tb) return;
+        const int64_t bt = xcd_used_block((ntile + kWavesPerBlock - 1) / kWavesPerBlock);
+        if (bt < 0) return;
         tile = bt * kWavesPerBlock + w;
         if (tile >= ntile) return;
     } else {

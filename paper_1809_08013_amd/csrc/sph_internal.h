@@ -200,6 +200,18 @@ __device__ __forceinline__ int64_t xcd_block()
                  : (int64_t)r * (q + 1) + (int64_t)(x - r) * q + pos;
 }
 
+// xcd_block for a grid sized for a capacity of which a step uses only the
+// first `used` blocks (a count read on the device): those blocks, which are
+// dispatched first, are mapped as xcd_block maps a grid of `used` blocks, so
+// the work is spread over all eight XCDs; the others get -1 and exit.
+__device__ __forceinline__ int64_t xcd_used_block(int64_t used)
+{
+    const int64_t b = blockIdx.x;
+    if (b >= used) return -1;
+    const int64_t q = used / 8, r = used % 8, x = b % 8, pos = b / 8;
+    return x < r ? x * (q + 1) + pos : r * (q + 1) + (x - r) * q + pos;
+}
+
 // xcd_block, refined per CU: the blocks an XCD receives are handed out to
 // its 32 CUs in turn, so block pos of the XCD is mapped to the pos / 32-th
 // entry of CU pos % 32's own contiguous range. Blocks resident on one CU then
