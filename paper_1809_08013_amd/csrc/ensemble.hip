@@ -24,6 +24,7 @@
 // the same reduction tree as when it runs alone (and as the single-run calls
 // of this library compute them), so its results are bitwise the same.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -59,6 +60,7 @@ struct PinnedPool {
     std::mutex mu;
     std::multimap<size_t, void *> free_;
     std::vector<void *> all;
+    std::atomic<size_t> held{0};  // bytes allocated
 
     static size_t round_up(size_t b)
     {
@@ -85,6 +87,7 @@ struct PinnedPool {
         }
         std::lock_guard<std::mutex> g(mu);
         all.push_back(p);
+        held += *cls;
         return p;
     }
     void put(void *p, size_t cls)
@@ -124,6 +127,7 @@ struct Run {
     int64_t start = 0;       // first particle in the arena for the current step
     void *blk = nullptr;     // pinned staging: upload, then the results
     size_t blk_cls = 0;
+    bool ahead = false;      // staged by the engine before its admission
     // results (valid once DONE)
     RunState state = QUEUED;
     sph_status status = SPH_OK;
@@ -387,6 +391,43 @@ void engine_main(sph_ens e)
     std::deque<InFlight> inflight;
     uint64_t stepno = 0;
     bool idle = false;
+    // Initial states are staged in pinned memory (a pool block, allocated
+    // the first time a size is needed) ahead of admission, while the GPU
+    // works on the steps in flight: the queue head is staged in chunks of at
+    // most kStageChunk bytes per wait, up to kStageAhead bytes of staged runs
+    // not yet admitted. A run admitted unstaged is staged before its upload.
+    constexpr size_t kStageChunk = (size_t)64 << 20, kStageAhead = (size_t)1 << 30;
+    size_t staged_ahead = 0;
+    auto stage = [&](Run *r) -> bool {
+        r->blk = e->pool.get(block_bytes(r->n), &r->blk_cls);
+        if (!r->blk) return false;
+        std::memcpy(r->blk, r->ic.data(), r->ic.size() * sizeof(double));
+        std::memcpy((char *)r->blk + (size_t)r->n * kEnsFields * 8, r->ic_id.data(),
+                    (size_t)r->n * 4);
+        std::vector<double>().swap(r->ic);
+        std::vector<int32_t>().swap(r->ic_id);
+        return true;
+    };
+    auto stage_ahead = [&]() -> bool {
+        size_t done = 0;
+        while (done < kStageChunk && staged_ahead < kStageAhead) {
+            Run *r = nullptr;
+            {
+                std::lock_guard<std::mutex> g(e->mu);
+                for (Run *q : e->queue)
+                    if (!q->blk) {
+                        r = q;
+                        break;
+                    }
+            }
+            if (!r) break;  // queued runs are removed by this thread only
+            if (!stage(r)) return false;
+            r->ahead = true;
+            done += block_bytes(r->n);
+            staged_ahead += block_bytes(r->n);
+        }
+        return true;
+    };
 
     for (;;) {
         // 1. Retire finished steps. Block on the oldest when two are in
@@ -394,6 +435,11 @@ void engine_main(sph_ens e)
         while (!inflight.empty()) {
             InFlight &f = inflight.front();
             const bool block = inflight.size() >= 2 || idle;
+            if (block && !stage_ahead()) {
+                std::lock_guard<std::mutex> g(e->mu);
+                fail_all_locked(e, SPH_E_NOMEM, "pinned host allocation failed");
+                return;
+            }
             err = block ? hipEventSynchronize(e->ev[f.ring]) : hipEventQuery(e->ev[f.ring]);
             if (err == hipErrorNotReady) {
                 (void)hipGetLastError();
@@ -478,19 +524,17 @@ void engine_main(sph_ens e)
                 continue;
             }
         }
-        // stage the admitted runs' initial state in pinned memory
+        // the admitted runs' initial state in pinned memory
         for (Run *r : admitted) {
-            r->blk = e->pool.get(block_bytes(r->n), &r->blk_cls);
-            if (!r->blk) {
+            if (r->blk) {
+                if (r->ahead) staged_ahead -= block_bytes(r->n);
+                continue;
+            }
+            if (!stage(r)) {
                 std::lock_guard<std::mutex> g(e->mu);
                 fail_all_locked(e, SPH_E_NOMEM, "pinned host allocation failed");
                 return;
             }
-            std::memcpy(r->blk, r->ic.data(), r->ic.size() * sizeof(double));
-            std::memcpy((char *)r->blk + (size_t)r->n * kEnsFields * 8, r->ic_id.data(),
-                        (size_t)r->n * 4);
-            std::vector<double>().swap(r->ic);
-            std::vector<int32_t>().swap(r->ic_id);
         }
 
         // 3. Header and run table, in slot order.
@@ -828,20 +872,35 @@ sph_status sph_ens_submit(sph_ens e, const sph_run_request *q, uint64_t *ticket)
     r->ncell = (int64_t)r->grid.nc[0] * r->grid.nc[1] * r->grid.nc[2];
     if (n > e->cap || r->ncell > e->cell_cap)
         return efail(e, SPH_E_CAPACITY, "the run can never fit the budget");
-    r->ic.resize((size_t)n * kEnsFields);
+    // The initial state goes straight into a pinned block while the pool
+    // holds less than kSubmitPinned bytes (the engine then only uploads it),
+    // else into host vectors that the engine stages before the upload.
     const double *rows[kEnsFields] = {q->x, q->y, q->z, q->vx, q->vy, q->vz, q->u,
                                       q->h, q->m, q->p_bg, q->rho_ref};
-    for (int k = 0; k < kEnsFields; ++k) {
-        if (!rows[k] || (k == kEnsFields - 1 && !r->has_rho_ref)) continue;
-        std::memcpy(r->ic.data() + (size_t)k * n, rows[k], (size_t)n * 8);
+    constexpr size_t kSubmitPinned = (size_t)4 << 30;
+    if (e->pool.held.load() + block_bytes(n) <= kSubmitPinned)
+        r->blk = e->pool.get(block_bytes(n), &r->blk_cls);
+    if (r->blk) {
+        for (int k = 0; k < kEnsFields; ++k) {
+            if (!rows[k] || (k == kEnsFields - 1 && !r->has_rho_ref)) continue;
+            std::memcpy((double *)r->blk + (size_t)k * n, rows[k], (size_t)n * 8);
+        }
+        std::memcpy((char *)r->blk + (size_t)n * kEnsFields * 8, q->id, (size_t)n * 4);
+    } else {
+        r->ic.resize((size_t)n * kEnsFields);
+        for (int k = 0; k < kEnsFields; ++k) {
+            if (!rows[k] || (k == kEnsFields - 1 && !r->has_rho_ref)) continue;
+            std::memcpy(r->ic.data() + (size_t)k * n, rows[k], (size_t)n * 8);
+        }
+        r->ic_id.assign(q->id, q->id + n);
     }
-    r->ic_id.assign(q->id, q->id + n);
     std::lock_guard<std::mutex> g(e->mu);
-    if (e->fatal != SPH_OK) {
-        e->last_error = e->fatal_msg;
-        return e->fatal;
-    }
-    if (e->stop) {
+    if (e->fatal != SPH_OK || e->stop) {
+        e->pool.put(r->blk, r->blk_cls);
+        if (e->fatal != SPH_OK) {
+            e->last_error = e->fatal_msg;
+            return e->fatal;
+        }
         e->last_error = "the engine is shutting down";
         return SPH_E_INVALID;
     }

@@ -195,28 +195,57 @@ __device__ __forceinline__ double4 lds_load4(const char *p)
 // Records: DensRec {x, y, z, m}, 32 B; two lanes fetch one record.
 constexpr int kDensStride = 48;  // LDS bytes per record: 32 + 16 padding
 
-// Minimum-image parameters of the lane's run. Single run: the kernel's grid
-// (wave-uniform). Ensemble: the run of the lane's particle; an axis is
-// treated as periodic for the wave when any lane's run is periodic on it, and
-// a lane whose run is not gets half = +inf, for which the select chain leaves
-// the difference unchanged.
+// Minimum-image parameters of the wave's run. Single run: the kernel's
+// grid. Ensemble: the run of the wave's particles (the waves are cut per
+// run), read once into wave-uniform registers.
 struct Img {
     bool per[3];
     double len[3], half[3];
 };
+
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Run slot of a wave's particles (lane 0's: every lane of a wave belongs to
+// the same run).
+__device__ __forceinline__ int run_slot(const BatchDev &b, int64_t ii)
+{
+    return __builtin_amdgcn_readfirstlane(b.slot[ii]);
+}
+
+// First particle of the calling lane and end of its wave's particles. One
+// run: blocks of kThreads consecutive particles (wave w of block `tile`
+// takes its 64). Ensemble: `tile` is the wave's 64-particle tile of one run.
+template <bool Multi>
+__device__ __forceinline__ void lane_span(int64_t tile, int64_t n, const BatchDev &b,
+                                          int64_t &i, int64_t &end)
+{
+    if constexpr (Multi) {
+        int64_t t0;
+        tile_span<true>(tile, n, b, t0, end);
+        i = t0 + (threadIdx.x & 63);
+    } else {
+        i = tile * kThreads + threadIdx.x;
+        end = n;
+    }
+}
 
 template <bool Multi>
 __device__ __forceinline__ Img lane_img(const Grid &g, const BatchDev &b, int64_t ii)
 {
     Img m;
     if constexpr (Multi) {
-        const Grid &rg = b.runs[b.slot[ii]].grid;
+        const Grid &rg = b.runs[run_slot(b, ii)].grid;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const bool p = rg.periodic[a] != 0;
-            m.per[a] = __ballot(p) != 0ull;
-            m.len[a] = rg.len[a];
-            m.half[a] = p ? rg.half[a] : INFINITY;
+            m.per[a] = __builtin_amdgcn_readfirstlane(rg.periodic[a]) != 0;
+            m.len[a] = uniform_f64(rg.len[a]);
+            m.half[a] = uniform_f64(rg.half[a]);
         }
     } else {
 #pragma unroll
@@ -261,9 +290,10 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
 {
     using R = typename std::conditional<F32, float, double>::type;
     const int lane = threadIdx.x & 63;
-    const int64_t i = tile * kThreads + threadIdx.x;
-    const bool active = i < n;
-    const int64_t ii = active ? i : 0;
+    int64_t i, iend;
+    lane_span<Multi>(tile, n, b, i, iend);
+    const bool active = i < iend;
+    const int64_t ii = active ? i : (Multi ? i - lane : 0);
     // individual time steps: only particles whose step closes are evaluated
     const bool closes = Multi || step_closes(mask, ii);
     if (!Multi && mask.bin && __ballot(active && closes) == 0ull) return;
@@ -344,6 +374,18 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
     if (active && closes) rho[i] = (double)(sum * (sg * inv_h * inv_h * inv_h));
 }
 
+// Ensemble: the calling wave's 64-particle tile (-1: none). The grid covers
+// the capacity's tiles (one per wave); the blocks a step uses are spread
+// over the XCDs.
+__device__ __forceinline__ int64_t ens_wave_tile(const BatchDev &b)
+{
+    const int64_t ntile = b.hdr->ntile;
+    const int64_t bt = xcd_used_block((ntile + kThreads / 64 - 1) / (kThreads / 64));
+    if (bt < 0) return -1;
+    const int64_t t = bt * (kThreads / 64) + (threadIdx.x >> 6);
+    return t < ntile ? t : -1;
+}
+
 template <bool F32, bool Multi, bool Big, int Per, int KF>
 __global__ void __launch_bounds__(kThreads)
 density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
@@ -354,12 +396,12 @@ density_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ drec,
     __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kDensStride];
     char *buf = lds[threadIdx.x >> 6];
     if constexpr (Multi) {
-        // one tile per block over a capacity-sized grid (a loop over tiles
-        // keeps the loop-invariant values of the tile body live in registers)
-        const int64_t nn = b.hdr->n_out;
-        const int64_t t = xcd_used_block((nn + kThreads - 1) / kThreads);
+        // one run-aligned tile per wave over a capacity-sized grid (a loop
+        // over tiles keeps the tile body's loop-invariant values live)
+        const int64_t t = ens_wave_tile(b);
         if (t >= 0)
-            density_tile<F32, true, Big, -1, KF>(t, nn, ld, drec, h, count, idx, max_nb, g, rho,
+            density_tile<F32, true, Big, -1, KF>(t, b.hdr->n_out, ld, drec, h, count, idx,
+                                                 max_nb, g, rho,
                                                  b, buf, sigma, sinc_n, mask);
     } else {
         density_tile<F32, false, Big, Per, KF>(xcd_cu_block(), n, ld, drec, h, count, idx,
@@ -621,14 +663,16 @@ __device__ __forceinline__ void momentum_tile(
 {
     using R = typename std::conditional<F32, float, double>::type;
     const int lane = threadIdx.x & 63;
-    const int64_t i = tile * kThreads + threadIdx.x;
-    const bool active = i < n;
-    const int64_t ii = active ? i : 0;
+    int64_t i, iend;
+    lane_span<Multi>(tile, n, b, i, iend);
+    const bool active = i < iend;
+    const int64_t ii = active ? i : (Multi ? i - lane : 0);
     const Img im = lane_img<Multi>(g, b, ii);
     MomParams prm = prm0;
     if constexpr (Multi) {
-        const RunDev &r = b.runs[b.slot[ii]];
-        prm = MomParams{r.alpha, r.beta, r.eta2, 0.0, 0, nullptr, nullptr, 0, 0};
+        const RunDev &r = b.runs[run_slot(b, ii)];
+        prm = MomParams{uniform_f64(r.alpha), uniform_f64(r.beta), uniform_f64(r.eta2), 0.0, 0,
+                        nullptr, nullptr, 0, 0};
     }
     // individual time steps: lanes whose particle's step does not close now
     // write nothing; a wave without any such lane has nothing to do
@@ -870,10 +914,10 @@ momentum_kernel(int64_t n, int64_t ld, const PairRec *__restrict__ rec,
     __shared__ __attribute__((aligned(16))) char lds[kThreads / 64][64 * kMomStride];
     char *buf = lds[threadIdx.x >> 6];
     if constexpr (Multi) {
-        const int64_t nn = b.hdr->n_out;
-        const int64_t t = xcd_used_block((nn + kThreads - 1) / kThreads);
+        const int64_t t = ens_wave_tile(b);
         if (t >= 0)
-            momentum_tile<F32, true, Big, -1, false, KF>(t, nn, ld, rec, count, idx, max_nb, g,
+            momentum_tile<F32, true, Big, -1, false, KF>(t, b.hdr->n_out, ld, rec, count, idx,
+                                                         max_nb, g,
                                                          prm, ax, ay, az, dudt, mumax, b, buf);
     } else if constexpr (IAD || GVE) {
         momentum_tile<F32, false, Big, Per, false, KF, IAD, GVE>(xcd_block(), n, ld, rec,
@@ -963,6 +1007,13 @@ pack_pair_kernel(int64_t n, const int64_t *n_dev, const double *__restrict__ x,
 }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// Blocks of an ensemble gather: one wave per 64-particle tile, at most one
+// partial tile per run beyond the capacity's.
+inline unsigned ens_pair_blocks(int64_t cap)
+{
+    return blocks_for((cap + 63) / 64 + kEnsMaxSlots, kThreads / 64);
+}
 
 // Ensemble EOS: each particle with its run's constants. At a run's t = 0
 // evaluation with a density reference, rho_ref := rho first (then the Tait
@@ -1221,7 +1272,7 @@ hipError_t launch_density_batch(sph_ctx ctx, const BatchDev &b, int precision, c
     const int64_t cap = b.cap;
     const int64_t *n_out = &b.hdr->n_out;
     const unsigned g1 = std::min<unsigned>(blocks_for(cap, 256), 4096u);
-    const unsigned g2 = blocks_for(cap, kThreads);
+    const unsigned g2 = ens_pair_blocks(cap);
     pack_dens_kernel<<<g1, 256, 0, ctx->stream>>>(0, n_out, F + 0 * cap, F + 1 * cap,
                                                   F + 2 * cap, F + 8 * cap, ctx->drec);
     density_launch<true>(ctx->stream, g2, precision, big_records(cap, sizeof(DensRec)), 0, cap,
@@ -1249,7 +1300,7 @@ hipError_t launch_momentum_batch(sph_ctx ctx, const BatchDev &b, int precision,
     const int64_t cap = b.cap;
     const int64_t *n_out = &b.hdr->n_out;
     const unsigned g1 = std::min<unsigned>(blocks_for(cap, 256), 4096u);
-    const unsigned g2 = blocks_for(cap, kThreads);
+    const unsigned g2 = ens_pair_blocks(cap);
     const bool r32 = precision == SPH_FP32_PAIR;  // PairRec32 records
     if (r32)
         pack_pair_kernel<true><<<g1, 256, 0, ctx->stream>>>(

@@ -423,31 +423,6 @@ __device__ __forceinline__ int2 z_window_r(int2 cr, uint32_t p, const Grid &g,
     return make_int2(first, a);
 }
 
-// First particle and end of search tile `tile`. One run: tiles of 64 from
-// particle 0, the last one ending at n. An ensemble: each live run is cut
-// into its own tiles from its first particle (the step header's tile bases),
-// so that no tile holds particles of two runs and the run's tiles are the
-// ones it has alone.
-template <bool Multi>
-__device__ __forceinline__ void tile_span(int64_t tile, int64_t n, const BatchDev &b,
-                                          int64_t &t0, int64_t &tend)
-{
-    if constexpr (!Multi) {
-        t0 = tile * kWave;
-        tend = min(t0 + (int64_t)kWave, n);
-    } else {
-        const BatchHdr *hd = b.hdr;
-        int lo = 0, hi = hd->nlive - 1;
-        while (lo < hi) {  // last live run whose first tile is <= tile
-            const int mid = (lo + hi + 1) >> 1;
-            if (hd->live_tile_base[mid] <= tile) lo = mid; else hi = mid - 1;
-        }
-        const RunDev &r = b.runs[hd->live_slot[lo]];
-        t0 = (int64_t)r.start + (tile - hd->live_tile_base[lo]) * (int64_t)kWave;
-        tend = min(t0 + (int64_t)kWave, (int64_t)r.start + r.n);
-    }
-}
-
 // One tile of 64 particles. Multi: the particles belong to one run of an
 // ensemble (slot in the high key bits) and the tile uses that run's grid
 // and cell range; a tile found spanning two runs would take the per-lane

@@ -212,6 +212,31 @@ __device__ __forceinline__ int64_t xcd_used_block(int64_t used)
     return x < r ? x * (q + 1) + pos : r * (q + 1) + (x - r) * q + pos;
 }
 
+// First particle and end of 64-particle tile `tile` (one wave's particles
+// in the search and pair kernels). One run: tiles of 64 from particle 0, the
+// last one ending at n. An ensemble: each live run is cut into its own tiles
+// from its first particle (the step header's tile bases), so that no tile
+// holds particles of two runs and a wave's run parameters are uniform.
+template <bool Multi>
+__device__ __forceinline__ void tile_span(int64_t tile, int64_t n, const BatchDev &b,
+                                          int64_t &t0, int64_t &tend)
+{
+    if constexpr (!Multi) {
+        t0 = tile * 64;
+        tend = min(t0 + (int64_t)64, n);
+    } else {
+        const BatchHdr *hd = b.hdr;
+        int lo = 0, hi = hd->nlive - 1;
+        while (lo < hi) {  // last live run whose first tile is <= tile
+            const int mid = (lo + hi + 1) >> 1;
+            if (hd->live_tile_base[mid] <= tile) lo = mid; else hi = mid - 1;
+        }
+        const RunDev &r = b.runs[hd->live_slot[lo]];
+        t0 = (int64_t)r.start + (tile - hd->live_tile_base[lo]) * (int64_t)64;
+        tend = min(t0 + (int64_t)64, (int64_t)r.start + r.n);
+    }
+}
+
 // xcd_block, refined per CU: the blocks an XCD receives are handed out to
 // its 32 CUs in turn, so block pos of the XCD is mapped to the pos / 32-th
 // entry of CU pos % 32's own contiguous range. Blocks resident on one CU then
