@@ -906,11 +906,12 @@ sph_status sph_smoothing_length(sph_ctx ctx, sph_particles *p, const sph_box *bo
     }
     *iterations = sweep;
     // cells for the final h (this may reorder the particles, and the cells'
-    // largest (2 h)^2 must follow the grown h), then the final counts once
-    // more in that order (the same values)
+    // largest (2 h)^2 must follow the grown h); the final counts follow the
+    // particles through the build's permutation (the h they were counted
+    // with is the final one)
     if ((st = largest_h(&h_max)) != SPH_OK) return st;
     SPH_HIP(ctx, build(h_max));
-    SPH_HIP(ctx, launch_gather_count(ctx, *p, count, lo_count, hi_count, ctx->it_words));
+    SPH_HIP(ctx, launch_permute_like_build(ctx, count, p->n));
     return SPH_OK;
 }
 

@@ -510,6 +510,31 @@ hipError_t launch_build_cells(sph_ctx ctx, const sph_particles &p, const Grid &g
     return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(256)
+gather_i32_kernel(int64_t n, const int32_t *__restrict__ perm, const int32_t *__restrict__ src,
+                  int32_t *__restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+
+__global__ void __launch_bounds__(256)
+copy_i32_kernel(int64_t n, const int32_t *__restrict__ src, int32_t *__restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_permute_like_build(sph_ctx ctx, int32_t *a, int64_t n)
+{
+    // the sort's values are the particles' indices before the build, in
+    // sorted order, next to the sorted keys
+    const int32_t *perm = ctx->sorted_keys == ctx->keys[0] ? ctx->vals[0] : ctx->vals[1];
+    gather_i32_kernel<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, perm, a, ctx->perm_tmp_id);
+    copy_i32_kernel<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, ctx->perm_tmp_id, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_admit_batch(sph_ctx ctx, const BatchDev &b)
 {
     admit_kernel<<<256, 256, 0, ctx->stream>>>(b);

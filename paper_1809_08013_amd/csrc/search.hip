@@ -959,6 +959,31 @@ __device__ __forceinline__ int axis_offsets(int nc, int periodic, int k, int (&o
 // cells): the host rebuilds the cells and continues.
 enum { IT_BAD = 0, IT_MAXC = 1, IT_DONE = 2, IT_SWEEP = 3, IT_REACH = 4, IT_WORDS = 5 };
 
+// Gather count of the lane's particle over the particles [w.x, w.y): the
+// records are loaded four at a time, so that a test waits for its load once
+// per four (a record per iteration left each test waiting for its own load;
+// the next four in flight as well cost the kernel half its occupancy).
+template <int Mode>
+__device__ __forceinline__ int count_window(const SearchRec &me, const SearchRec *__restrict__ srec,
+                                            int2 w, int self, const Grid &g,
+                                            const double (&sh)[3])
+{
+    int cnt = 0;
+    auto test = [&](const SearchRec &o, int j) {
+        cnt += (j != self && related<Mode, true>(me, o, g, sh)) ? 1 : 0;
+    };
+    int j = w.x;
+    for (; w.y - j >= 4; j += 4) {
+        const SearchRec a0 = srec[j], a1 = srec[j + 1], a2 = srec[j + 2], a3 = srec[j + 3];
+        test(a0, j);
+        test(a1, j + 1);
+        test(a2, j + 2);
+        test(a3, j + 3);
+    }
+    for (; j < w.y; ++j) test(srec[j], j);
+    return cnt;
+}
+
 // Gather counts of one sweep: N_i = #{j != i : r^2 < (2 h_i)^2}. The cells
 // were built for a largest h that the sweeps may outgrow: a particle with
 // 2 h_i up to two cells walks the 5^3 cells around its own, beyond that the
@@ -966,7 +991,9 @@ enum { IT_BAD = 0, IT_MAXC = 1, IT_DONE = 2, IT_SWEEP = 3, IT_REACH = 4, IT_WORD
 // periodic image is walked only in its window for the own sphere (a point
 // box of reach 2 h_i): cells beyond it in x or y are skipped, in the others
 // only the z slices within reach. Does nothing once IT_DONE or IT_REACH is
-// set.
+// set. Periodic: some axis of the box is periodic (then each pair takes the
+// minimum image; else the separation is used as it is).
+template <bool Periodic>
 __global__ void __launch_bounds__(256)
 gather_count_kernel(int64_t n, const SearchRec *__restrict__ srec,
                     const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
@@ -1028,9 +1055,8 @@ gather_count_kernel(int64_t n, const SearchRec *__restrict__ srec,
                         w = z_window_r(w, (uint32_t)x | ((uint32_t)y << 10) |
                                               ((uint32_t)z << 20),
                                        g, pt, pt, R, keys);
-                    for (int j = w.x; j < w.y; ++j)
-                        if (j != (int)i && related<WRAP_PAIR, true>(me, srec[j], g, no_shift))
-                            ++cnt;
+                    cnt += count_window<Periodic ? WRAP_PAIR : WRAP_NONE>(me, srec, w, (int)i,
+                                                                           g, no_shift);
                 }
             }
         }
@@ -1177,14 +1203,18 @@ hipError_t launch_max_h(sph_ctx ctx, const sph_particles &p, unsigned long long 
     return hipGetLastError();
 }
 
-hipError_t launch_gather_count(sph_ctx ctx, const sph_particles &p, int32_t *count,
-                               int32_t lo_count, int32_t hi_count, uint32_t *words)
+static void launch_gather(sph_ctx ctx, const sph_particles &p, int32_t *count, int32_t lo_count,
+                   int32_t hi_count, uint32_t *words, unsigned blocks)
 {
-    clear_words_kernel<<<1, 64, 0, ctx->stream>>>(words, IT_WORDS);
-    gather_count_kernel<<<(unsigned)((p.n + 255) / 256), 256, 0, ctx->stream>>>(
-        p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid, count,
-        lo_count, hi_count, words);
-    return hipGetLastError();
+    const Grid &g = ctx->grid;
+    if (g.periodic[0] || g.periodic[1] || g.periodic[2])
+        gather_count_kernel<true><<<blocks, 256, 0, ctx->stream>>>(
+            p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, g, count,
+            lo_count, hi_count, words);
+    else
+        gather_count_kernel<false><<<blocks, 256, 0, ctx->stream>>>(
+            p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, g, count,
+            lo_count, hi_count, words);
 }
 
 hipError_t launch_h_iteration(sph_ctx ctx, const sph_particles &p, int32_t *count,
@@ -1196,9 +1226,7 @@ hipError_t launch_h_iteration(sph_ctx ctx, const sph_particles &p, int32_t *coun
     set_word_kernel<<<1, 1, 0, ctx->stream>>>(words + IT_SWEEP, (uint32_t)first_sweep);
     const unsigned blocks = (unsigned)((p.n + 255) / 256);
     for (int32_t it = first_sweep; it <= max_iter; ++it) {
-        gather_count_kernel<<<blocks, 256, 0, ctx->stream>>>(
-            p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid, count,
-            lo_count, hi_count, words);
+        launch_gather(ctx, p, count, lo_count, hi_count, words, blocks);
         sweep_end_kernel<<<1, 1, 0, ctx->stream>>>(words, max_iter);
         if (it < max_iter)
             update_h_kernel<<<blocks, 256, 0, ctx->stream>>>(p.n, count, p.h, ctx->srec,

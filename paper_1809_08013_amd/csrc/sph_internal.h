@@ -442,9 +442,9 @@ hipError_t launch_max_h(sph_ctx ctx, const sph_particles &p, unsigned long long 
 // largest count, [2] done, [3] last sweep, [4] a particle outgrew the cells
 // (the host rebuilds and calls again from sweep [3]).
 constexpr int kItWords = 5;
-// One count sweep on the cells last built (words cleared first).
-hipError_t launch_gather_count(sph_ctx ctx, const sph_particles &p, int32_t *count,
-                               int32_t lo_count, int32_t hi_count, uint32_t *words);
+// Reorders an int32 per-particle array as the last cell build reordered the
+// particles (its sort permutation).
+hipError_t launch_permute_like_build(sph_ctx ctx, int32_t *a, int64_t n);
 hipError_t launch_h_iteration(sph_ctx ctx, const sph_particles &p, int32_t *count,
                               int32_t lo_count, int32_t hi_count, double n_target,
                               int32_t first_sweep, int32_t max_iter, uint32_t *words);
