@@ -32,7 +32,7 @@
 // directly; when no image is in play it walks, in each cell, only the z
 // slices (the lowest key bits order a cell's particles by z) within reach of
 // the tile's z extent. A wave with more distinct cells than its union build
-// holds (4, or 9 in an ensemble), or with a union of many dense cells, takes
+// holds (9), or with a union of many dense cells, takes
 // the per-lane path instead: each lane walks its own stencil (sorted by
 // Morton key) and writes its entries directly. Both paths produce the same set in the
 // same (ascending) order, so the sums over a list do not depend on the path
@@ -50,11 +50,11 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 constexpr int kMaxCandidates = kSearchMaskWords * 32;
 // Stencil entries (27 per distinct cell, before dedup) a tile's union build
-// holds: 4 distinct cells for one run, 9 for an ensemble, whose small runs
-// have few particles per cell so that 64 consecutive particles often span
-// more than four cells.
+// holds: 9 distinct cells (tiles of small runs, and tiles of a rotated
+// lattice after some steps, span more than four). Tiles with at most 4 sort
+// only the first 128 entries.
 template <bool Multi>
-constexpr int kEntries = Multi ? 256 : 128;
+constexpr int kEntries = 256;
 // Cells of a union handed to the second kernel (held two per lane there).
 constexpr int kDenseCells = 2 * 64;
 constexpr int kMaxWords = kSearchMaskWords;
@@ -523,12 +523,15 @@ __device__ __forceinline__ void search_tile(
             L.ent[e] = v;
         }
         wave_sync();
-        // bitonic sort of the E entries by first particle: the E / 2
-        // compare-exchanges of a step are disjoint, kC / 2 per lane
-        for (int k = 2; k <= E; k <<= 1) {
+        // bitonic sort of the first sortN entries by first particle (the
+        // rest are sentinels, already in place): the sortN / 2
+        // compare-exchanges of a step are disjoint, up to kC / 2 per lane
+        const int sortN = nent <= 2 * kWave ? 2 * kWave : E;
+        for (int k = 2; k <= sortN; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
 #pragma unroll
                 for (int q = 0; q < kC / 2; ++q) {
+                    if (2 * kWave * q >= sortN) break;
                     const int p = lane + q * kWave;
                     const int lo_i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
                     const int hi_i = lo_i | j;
