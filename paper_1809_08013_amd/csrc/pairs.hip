@@ -474,8 +474,9 @@ eos_kernel(int64_t n, int eos, double rho0, double c0, double gamma_tait,
 
 // ---------------------------------------------------------------------------
 // Momentum and energy with Monaghan artificial viscosity.
-// Records: PairRec (96 B used of 128); a group of 8 lanes fetches one record
-// (lanes 0..5 of the group one 16-byte chunk each), 8 records per load.
+// Records: PairRec (96 B used of 128), PairRec32 (80 B): the used 16-byte
+// chunks of a step's 64 records are fetched by the wave in sequence, 64 per
+// load instruction, and handed to their owners through LDS.
 constexpr int kMomStride = 112;  // LDS bytes per record: 96 + 16 padding
 
 struct MomParams {
@@ -728,12 +729,19 @@ __device__ __forceinline__ void momentum_tile(
     int maxc = cnt;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, 64));
-    const int grp = lane & ~7, s = lane & 7;
-    const bool loader = s < (R32 ? 5 : (GVE ? 7 : 6));
+    // The 64 records of a step are kChunks x 64 16-byte chunks: load
+    // instruction t gives lane L the chunk (64 t + L) of that sequence, chunk
+    // c of record r with 64 t + L = kChunks r + c, so every lane of every
+    // instruction loads a chunk that is used.
+    constexpr int kChunks = R32 ? 5 : (GVE ? 7 : 6);
+    int rsrc[kChunks];
+#pragma unroll
+    for (int t = 0; t < kChunks; ++t) rsrc[t] = (64 * t + lane) / kChunks;
+    auto chunk_of = [&](int t) -> uint32_t {
+        return 16u * (uint32_t)(64 * t + lane - kChunks * rsrc[t]);
+    };
     const char *src_base = reinterpret_cast<const char *>(rec);
-    const uint32_t chunk = 16u * (uint32_t)(loader ? s : 0);
     const char *own = buf + lane * kMomStride;
-    char *dst = buf + grp * kMomStride + 16 * s;
     // Two steps in flight: the records of step k + 2 are requested while
     // step k is computed, alternating between two register sets (the loop
     // runs two steps per pass, so no set is copied and every wait counts only
@@ -748,13 +756,13 @@ __device__ __forceinline__ void momentum_tile(
     const uint32_t jmax = (uint32_t)(n - 1);
     auto jfix = [&](int j) -> int { return (int)min((uint32_t)j, jmax); };
     struct RecSet {
-        double2 c[8];
+        double2 c[kChunks];
         double2 e[3] = {};  // IAD: c_j of the set's step (zero otherwise)
     };
     auto fetch_set = [&](int jk, RecSet &S) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t)
-            S.c[t] = rec_chunk<Big, kRecBytes>(src_base, __shfl(jk, grp + t, 64), chunk);
+        for (int t = 0; t < kChunks; ++t)
+            S.c[t] = rec_chunk<Big, kRecBytes>(src_base, __shfl(jk, rsrc[t], 64), chunk_of(t));
         if constexpr (IAD) {
             const double2 *cp = reinterpret_cast<const double2 *>(prm.iad_c + 6 * (int64_t)jk);
             S.e[0] = cp[0];
@@ -764,11 +772,9 @@ __device__ __forceinline__ void momentum_tile(
     };
     auto put_set = [&](const RecSet &S) {
         wave_lds_fence();
-        if (loader) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t)
-                *reinterpret_cast<double2 *>(dst + t * kMomStride) = S.c[t];
-        }
+        for (int t = 0; t < kChunks; ++t)
+            *reinterpret_cast<double2 *>(buf + rsrc[t] * kMomStride + chunk_of(t)) = S.c[t];
         wave_lds_fence();
     };
     auto step = [&](int k, const double2 f0, const double2 f1, const double2 f2) {
