@@ -145,10 +145,14 @@ def recorded_counters(kernel: str, workload: str) -> dict:
 
 def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=None,
             iterate_h: bool = False, self_gravity=None, graph: bool = False) -> dict:
-    """Timed leg: `steps` steps call by call, a HIP event between calls (the
-    per-call times); ms_per_step is its wall time. With graph=True a second
-    leg then captures sph_step into a HIP graph and times `steps` replays of
-    it on the same state (graph_ms_per_step)."""
+    """Three legs from the same state (a snapshot taken after the t = 0
+    evaluation, restored before each): `steps` steps call by call with no
+    instrumentation, whose wall time is ms_per_step; the same steps with a
+    HIP event between calls and the library's kernel timer on (per-call and
+    per-kernel times, which the events themselves slow slightly); with
+    graph=True, sph_step captured into a HIP graph after the warm-up and
+    `steps` replays timed (graph_ms_per_step). Each leg runs `warmup` steps
+    first."""
     import numpy as np
     import torch
 
@@ -192,6 +196,13 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
         calls.insert(6, lambda: S.sph_gravity_tree(ctx, st, eps, theta, leaf))
         names.insert(6, "gravity_tree")
     stream = ctx.stream
+    # the state every leg starts from (the lists are rebuilt by every step
+    # before they are read)
+    snap = {k: v.clone() for k, v in st.t.items() if k not in ("idx", "count")}
+
+    def restore():
+        for k, v in snap.items():
+            st.t[k].copy_(v)
 
     def step(evs=None):
         for k, c in enumerate(calls):
@@ -204,6 +215,21 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
     for _ in range(warmup):
         step()
     S.sph_ctx_check(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        step()
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1e3 / steps
+    S.sph_ctx_check(ctx)
+    pairs = float(st.t["count"][: ic.n].sum().item())
+    diag = st.diag
+    dt = st.dt
+    max_count = int(st.t["count"][: ic.n].max().item())
+    restore()
+    for _ in range(warmup):
+        step()
+    S.sph_ctx_check(ctx)
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
               for _ in range(steps)]
     ctx.timing(True)  # HIP events around the hot kernels, on the library's stream
@@ -212,7 +238,6 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
     for s in range(steps):
         step(events[s])
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     ctx.timing(False)
     kernel_ms = {}
     for k in TIMED_KERNELS:
@@ -225,11 +250,13 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
         for k, name in enumerate(names):
             per_call[name] += evs[k].elapsed_time(evs[k + 1])
     per_call = {k: v / steps for k, v in per_call.items()}  # ms per launch
-    eager_ms = (t1 - t0) * 1e3 / steps
     graph_ms = None
     if graph and self_gravity is None:
+        restore()
+        for _ in range(warmup - 1):
+            step()
         S.sph_step_capture(ctx, st, prm)
-        S.sph_step_replay(ctx)  # first replay: graph upload
+        S.sph_step_replay(ctx)  # first replay (graph upload): the last warm-up step
         S.sph_ctx_check(ctx)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -238,14 +265,11 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
         torch.cuda.synchronize()
         graph_ms = (time.perf_counter() - t0) * 1e3 / steps
         S.sph_ctx_check(ctx)
-    pairs = float(st.t["count"][: ic.n].sum().item())
-    diag = st.diag
     return dict(ms_per_step=eager_ms, graph_ms_per_step=graph_ms,
                 per_call_ms=per_call, kernel_ms=kernel_ms,
                 candidates=stencil_candidates(ic),
-                pairs_per_step=pairs, dt=st.dt, diag=diag.tolist(), diag0=diag0,
-                max_count=int(st.t["count"][: ic.n].max().item()),
-                scratch_bytes=ctx.scratch_bytes, h_iteration=h_iter)
+                pairs_per_step=pairs, dt=dt, diag=diag.tolist(), diag0=diag0,
+                max_count=max_count, scratch_bytes=ctx.scratch_bytes, h_iteration=h_iter)
 
 
 def roofline(n: int, r: dict, precision: int, workload: str | None = None) -> dict:
