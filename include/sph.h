@@ -441,7 +441,7 @@ sph_status sph_step_blocks(sph_ctx ctx, const sph_particles *p, const sph_box *b
  * to 2 h_i = two cells); the host steps in only to rebuild when a particle
  * outgrows that, and once at the end. *iterations (HOST) receives the last
  * it. On return the cells are built for the final h (sph_find_neighbors may
- * follow directly) and count[] is in that order. Synchronising (twice when
+ * follow directly) and count[] is in that order. Synchronising (three times when
  * no particle outgrows the cells); allocates nothing.
  * SPH_E_DOMAIN if a periodic axis is shorter than 4 h_max at the start or
  * the end, SPH_E_NONFINITE if h stops being finite and positive. */
@@ -542,6 +542,10 @@ typedef struct {
 sph_status sph_ens_create(sph_ens *out, const sph_ens_config *cfg);
 
 /* Queue a run (non-blocking; copies the arrays). *ticket identifies it.
+ * The copy goes into a block of the engine's pinned host memory while the
+ * engine's pinned pool holds under 4 GiB (the block is reused for the
+ * results and returned to the pool when they are taken), else into host
+ * memory that the engine stages before the run's upload.
  * SPH_E_INVALID for bad arguments, SPH_E_DOMAIN if some h > h_max or a
  * periodic axis is not longer than 4 h_max, SPH_E_CAPACITY if the run could
  * never fit (particles or cells above what the budget holds). */
