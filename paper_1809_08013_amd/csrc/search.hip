@@ -53,7 +53,6 @@ constexpr int kMaxCandidates = kSearchMaskWords * 32;
 // holds: 9 distinct cells (tiles of small runs, and tiles of a rotated
 // lattice after some steps, span more than four). Tiles with at most 4 sort
 // only the first 128 entries.
-template <bool Multi>
 constexpr int kEntries = 256;
 // Cells of a union handed to the second kernel (held two per lane there).
 constexpr int kDenseCells = 2 * 64;
@@ -434,7 +433,7 @@ __device__ __forceinline__ void search_tile(
     const int32_t *__restrict__ cend, const Grid &g0, int max_nb, int32_t *__restrict__ count,
     int32_t *__restrict__ idx, uint32_t *__restrict__ mask_scratch,
     const uint32_t *__restrict__ hflag, uint32_t *status0, const BatchDev &b,
-    SearchLds<kEntries<Multi>> &L,
+    SearchLds<kEntries> &L,
     int32_t *__restrict__ fb_tiles, uint32_t *fb_count)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -495,7 +494,7 @@ __device__ __forceinline__ void search_tile(
         if (g.nc[a] < 5) few_cells = true;
     }
 
-    constexpr int E = kEntries<Multi>;
+    constexpr int E = kEntries;
     constexpr int kC = E / kWave;  // entries per lane
     const int nent = ndist * kStencil;
     bool use_union = nent <= E && !mixed;
@@ -908,9 +907,9 @@ find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
                       uint32_t *status, BatchDev b, int32_t *__restrict__ fb_tiles,
                       uint32_t *fb_count, StepMask mask)
 {
-    __shared__ SearchLds<kEntries<Multi>> lds[kWavesPerBlock];
+    __shared__ SearchLds<kEntries> lds[kWavesPerBlock];
     const int w = threadIdx.x / kWave;
-    SearchLds<kEntries<Multi>> &L = lds[w];
+    SearchLds<kEntries> &L = lds[w];
     const int64_t nn = Multi ? b.hdr->n_out : n;
     int64_t tile;
     if constexpr (Multi) {
