@@ -152,6 +152,28 @@ def test_mixed_batch_against_oracle(precision):
         ens.close()
 
 
+def test_tile_edges_in_one_batch():
+    """Runs smaller than one 64-particle tile, of exactly one tile and just
+    past it (each run is cut into its own tiles, so a run of 65 particles has
+    a tile of one particle), open random clouds with variable h, all resident
+    in one batch with a patch run: every run bitwise its single-run result."""
+    runs = [(I.random_cloud(n, seed=40 + k, h_min=0.05, h_max=0.12, velocity=0.5), 12)
+            for k, n in enumerate((1, 2, 5, 63, 64, 65, 127, 130))]
+    runs.append((_ic(9, 4.0, 9), 12))
+    ens = S.Ensemble(64 * MB, max_slots=16, max_n_per_run=800)
+    try:
+        tickets = [(ic, st, ens.submit(ic, st)) for ic, st in runs]
+        for ic, st, t in tickets:
+            got = ens.wait(t, ic.n)
+            print("run n", ic.n, "status", got["status"], flush=True)
+            assert_same(got, single_api(ic, st, S.SPH_FP64), ("tile edges", ic.n))
+        st = ens.stats()
+        print("stats", st)
+        assert st["peak_runs"] >= 2
+    finally:
+        ens.close()
+
+
 def test_arrivals_while_running():
     """Runs arriving while others are on the GPU join the batch (continuous
     batching) and still reproduce their alone results bitwise; a freed slot
