@@ -939,9 +939,9 @@ find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
 // Smoothing-length iteration (Algorithm 1, step 2, "neighbours and smoothing
 // length"; Sec. 3, target neighbour count): gather counts
 // N_i = #{j != i : r^2 < (2 h_i)^2}, the number of particles outside the
-// accepted band, and the update of h from a table of factors indexed by the
-// integer count (filled by the host, so that the factor is the same number
-// as in any other implementation that evaluates the same expression).
+// accepted band, and the update of h with a cube root computed by a fixed
+// rule of IEEE operations (cbrt_newton), so that any implementation of the
+// same rule gets the same h.
 
 // Offsets -k..k on one axis, without repeating a cell when a periodic axis
 // has fewer than 2k + 1 cells.
