@@ -250,6 +250,10 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
         for k, name in enumerate(names):
             per_call[name] += evs[k].elapsed_time(evs[k + 1])
     per_call = {k: v / steps for k, v in per_call.items()}  # ms per launch
+    # hipEvent time from the first call to the last of each step, median over
+    # the timed steps after the first
+    step_ev = sorted(evs[0].elapsed_time(evs[len(calls)]) for evs in events[1:]) or [0.0]
+    step_median = step_ev[len(step_ev) // 2]
     graph_ms = None
     if graph and self_gravity is None:
         restore()
@@ -266,13 +270,15 @@ def run_gpu(ic, precision: int, steps: int, warmup: int, max_nb: int = 128, g=No
         graph_ms = (time.perf_counter() - t0) * 1e3 / steps
         S.sph_ctx_check(ctx)
     return dict(ms_per_step=eager_ms, graph_ms_per_step=graph_ms,
+                step_ms_median_events=step_median,
                 per_call_ms=per_call, kernel_ms=kernel_ms,
                 candidates=stencil_candidates(ic),
                 pairs_per_step=pairs, dt=dt, diag=diag.tolist(), diag0=diag0,
                 max_count=max_count, scratch_bytes=ctx.scratch_bytes, h_iteration=h_iter)
 
 
-def roofline(n: int, r: dict, precision: int, workload: str | None = None) -> dict:
+def roofline(n: int, r: dict, precision: int, workload: str | None = None,
+             copy_gbs: float | None = None) -> dict:
     """HBM roofline of the dominant kernel: the timed kernel with the longest
     mean duration per launch (HIP events around its launches on the library's
     stream, over the timed steps). achieved = its call's algorithmic bytes per
@@ -309,7 +315,38 @@ def roofline(n: int, r: dict, precision: int, workload: str | None = None) -> di
                valu_issue_frac=(round(valu * 64 / t / VALU_LANE_INSTS_PER_S, 4)
                                 if valu else None),
                call_ms_per_launch=round(r["per_call_ms"][call], 5))
+    if copy_gbs:
+        out["copy_ceiling_gbs"] = round(copy_gbs, 1)
+        out["frac_of_copy"] = round(gbs / copy_gbs, 4)
     return out
+
+
+def copy_ceiling() -> float:
+    """A device-to-device copy of 1 GiB (read + written), best of 5: the HBM
+    rate a plain streaming kernel reaches on this GPU, beside the 8 TB/s
+    specification."""
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 0.0
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2.0 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    return best
+
+
+def pair_rates(r: dict) -> dict:
+    """Directed pairs per second of the density and momentum kernels alone
+    (live kernel times)."""
+    km, p = r["kernel_ms"], r["pairs_per_step"]
+    return {k: p / (km[f"{k}_kernel"]["avg_ms"] * 1e-3)
+            for k in ("density", "momentum") if f"{k}_kernel" in km}
 
 
 def step_hbm(n: int, r: dict, precision: int) -> dict:
@@ -579,7 +616,7 @@ def run_serving(runs: int, steps: int = 50, budget_gib: float = 8.0) -> dict:
     out["saturated"] = sat
     mu = sat["runs_per_s"]
     out["poisson"] = []
-    for f in (0.5, 0.8):
+    for f in (0.5, 0.8, 1.0):
         log(f"serving: Poisson arrivals at {f} x saturated rate")
         r = serve(ics, gaps, steps, budget, 511, f * mu)
         r["load_fraction"] = f
@@ -682,6 +719,29 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def cpu_other_configs(threads: int) -> dict:
+    """The oracle (all host threads) on the parity-sized patch (20^3, 10 KDK
+    steps) and one step of the 1M Evrard sphere (its analytic h, no external
+    field: the step's cost, not its physics), each after an untimed t = 0
+    force evaluation."""
+    import oracle as O
+    from paper_1809_08013_amd import inputs as I
+    out = {}
+    for name, ic, steps in (("square_patch_20", I.square_patch(20, seed=0), 10),
+                            ("evrard_1M", I.evrard(1_000_000, seed=0), 1)):
+        log(f"CPU oracle: {name}, {steps} steps on {threads} threads")
+        run = O.OracleRun(ic).init()
+        t0 = time.perf_counter()
+        pairs = 0
+        for _ in range(steps):
+            run.step()
+            pairs += run.n_pairs
+        t = time.perf_counter() - t0
+        out[name] = {"value": pairs / t, "unit": "pair-interactions/s",
+                     "ms_per_step": t * 1e3 / steps, "steps": steps, "cores": threads}
+    return out
+
+
 def cpu_leg(ic, traj_steps: int, gpu_traj: dict | None) -> tuple:
     """The CPU baseline leg, the only part of this script that runs the
     oracle: the FP64 oracle (OpenMP over particles, all host threads) takes
@@ -721,6 +781,7 @@ def cpu_leg(ic, traj_steps: int, gpu_traj: dict | None) -> tuple:
     finally:
         O.num_threads(threads)
     base["one_core"] = {"value": run.n_pairs / t1, "ms_per_step": t1 * 1e3, "cores": 1}
+    base["other_configs"] = cpu_other_configs(threads)
     traj = None
     if gpu_traj is not None:
         traj = {"workload": f"rotating square patch, {ic.n:,} particles, {traj_steps} steps "
@@ -788,6 +849,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    copy_gbs = copy_ceiling()
     ic = I.square_patch(args.n_side, seed=0)
     n = ic.n
     r64 = run_gpu(ic, S.SPH_FP64, args.steps, args.warmup, graph=True)
@@ -817,9 +879,11 @@ def main():
             "mean_neighbours": r64["pairs_per_step"] / n,
             "max_neighbours": r64["max_count"],
         },
+        "step_ms_median_events": r64["step_ms_median_events"],
         "per_call_ms": {k: round(v, 4) for k, v in r64["per_call_ms"].items()},
         "kernel_ms": r64["kernel_ms"],
-        "roofline": roofline(n, r64, 0, f"square_patch_{args.n_side}"),
+        "pair_rates": pair_rates(r64),
+        "roofline": roofline(n, r64, 0, f"square_patch_{args.n_side}", copy_gbs),
         "step_hbm": step_hbm(n, r64, 0),
         "drift": drift(r64),
     }
@@ -830,8 +894,10 @@ def main():
             "graph_ms_per_step": r32["graph_ms_per_step"],
             "speedup_vs_fp64": r64["ms_per_step"] / r32["ms_per_step"],
             "per_call_ms": {k: round(v, 4) for k, v in r32["per_call_ms"].items()},
+            "step_ms_median_events": r32["step_ms_median_events"],
             "kernel_ms": r32["kernel_ms"],
-            "roofline": roofline(n, r32, 1),
+            "pair_rates": pair_rates(r32),
+            "roofline": roofline(n, r32, 1, None, copy_gbs),
             "step_hbm": step_hbm(n, r32, 1),
         }
     if not args.no_kernels:
