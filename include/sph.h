@@ -491,6 +491,10 @@ typedef struct {
     int32_t max_slots;         /* runs resident at once, 1..511 */
     int64_t hbm_budget_bytes;  /* device memory for the arena and its scratch */
     int64_t max_n_per_run;     /* largest run accepted, >= 1 */
+    int64_t pinned_submit_bytes; /* pinned host memory up to which sph_ens_submit
+                                    copies a run straight into a pinned block
+                                    (0: 4 GiB; < 0: never, the engine stages
+                                    every run itself) */
 } sph_ens_config;
 
 typedef struct {
@@ -543,9 +547,10 @@ sph_status sph_ens_create(sph_ens *out, const sph_ens_config *cfg);
 
 /* Queue a run (non-blocking; copies the arrays). *ticket identifies it.
  * The copy goes into a block of the engine's pinned host memory while the
- * engine's pinned pool holds under 4 GiB (the block is reused for the
- * results and returned to the pool when they are taken), else into host
- * memory that the engine stages before the run's upload.
+ * engine's pinned pool holds under cfg.pinned_submit_bytes (the block is
+ * reused for the results and returned to the pool when they are taken),
+ * else into host memory that the engine stages into a pinned block before
+ * the run's upload (ahead of its admission while it waits for a step).
  * SPH_E_INVALID for bad arguments, SPH_E_DOMAIN if some h > h_max or a
  * periodic axis is not longer than 4 h_max, SPH_E_CAPACITY if the run could
  * never fit (particles or cells above what the budget holds). */

@@ -873,12 +873,13 @@ sph_status sph_ens_submit(sph_ens e, const sph_run_request *q, uint64_t *ticket)
     if (n > e->cap || r->ncell > e->cell_cap)
         return efail(e, SPH_E_CAPACITY, "the run can never fit the budget");
     // The initial state goes straight into a pinned block while the pool
-    // holds less than kSubmitPinned bytes (the engine then only uploads it),
-    // else into host vectors that the engine stages before the upload.
+    // holds less than cfg.pinned_submit_bytes (the engine then only uploads
+    // it), else into host vectors that the engine stages before the upload.
     const double *rows[kEnsFields] = {q->x, q->y, q->z, q->vx, q->vy, q->vz, q->u,
                                       q->h, q->m, q->p_bg, q->rho_ref};
-    constexpr size_t kSubmitPinned = (size_t)4 << 30;
-    if (e->pool.held.load() + block_bytes(n) <= kSubmitPinned)
+    const int64_t lim = e->cfg.pinned_submit_bytes;
+    const size_t submit_pinned = lim == 0 ? (size_t)4 << 30 : (lim < 0 ? 0 : (size_t)lim);
+    if (e->pool.held.load() + block_bytes(n) <= submit_pinned)
         r->blk = e->pool.get(block_bytes(n), &r->blk_cls);
     if (r->blk) {
         for (int k = 0; k < kEnsFields; ++k) {

@@ -77,7 +77,7 @@ class Params(C.Structure):
 class EnsConfig(C.Structure):
     _fields_ = [("device", C.c_int32), ("precision", C.c_int32), ("max_nb", C.c_int32),
                 ("max_slots", C.c_int32), ("hbm_budget_bytes", C.c_int64),
-                ("max_n_per_run", C.c_int64)]
+                ("max_n_per_run", C.c_int64), ("pinned_submit_bytes", C.c_int64)]
 
 
 _REQ_ARRAYS = ("x", "y", "z", "vx", "vy", "vz", "u", "h", "m", "p_bg", "rho_ref", "id")
@@ -503,13 +503,14 @@ class Ensemble:
     host arrays, advanced together on the GPU, and collected by ticket."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 64, max_n_per_run: int = 262144,
-                 precision: int = SPH_FP64, max_nb: int = 128, device: int | None = None):
+                 precision: int = SPH_FP64, max_nb: int = 128, device: int | None = None,
+                 pinned_submit_bytes: int = 0):
         import torch
         self.lib = load()
         if device is None:
             device = torch.cuda.current_device()
         cfg = EnsConfig(int(device), int(precision), int(max_nb), int(max_slots),
-                        int(budget_bytes), int(max_n_per_run))
+                        int(budget_bytes), int(max_n_per_run), int(pinned_submit_bytes))
         h = _VP()
         s = self.lib.sph_ens_create(C.byref(h), C.byref(cfg))
         if s != SPH_OK:

@@ -78,14 +78,17 @@ def test_alone_matches_single_run_calls(precision):
         ens.close()
 
 
-def test_mixed_batch_matches_alone():
+@pytest.mark.parametrize("pinned", [0, -1])
+def test_mixed_batch_matches_alone(pinned):
     """All runs submitted at once into an engine whose budget holds about
     half of them: they are admitted as slots and memory free up, several are
-    resident together, and each result is bitwise the run alone."""
+    resident together, and each result is bitwise the run alone. pinned = -1:
+    no run is copied into pinned memory at submit, so the engine stages every
+    one (ahead of admission while it waits for a step, or at admission)."""
     ref = {}
     for r in RUNS:
         ref[r] = single_api(_ic(*r[:3]), r[3], S.SPH_FP64)
-    ens = S.Ensemble(32 * MB, max_slots=4, max_n_per_run=8000)
+    ens = S.Ensemble(32 * MB, max_slots=4, max_n_per_run=8000, pinned_submit_bytes=pinned)
     try:
         st0 = ens.stats()
         cap = st0["capacity_particles"]
