@@ -3,7 +3,9 @@ times (the single-run calls, one context sized for the run).
 
 * Rotating square patch 100^3 (1,000,000 particles): every particle's
   neighbour set bit-exact, and rho, a, du/dt against the FP64 oracle within
-  the FP64 and FP32-pair tolerances.
+  the FP64 and FP32-pair tolerances; the same for the kernel options the
+  bench times on these lists (Wendland C2, sinc, IAD, generalised volume
+  elements).
 * Evrard-like sphere, 1,000,000 particles (analytic h, dense centre): the
   same, covering the dense-cell and per-lane search paths at full size.
 * Rotating square patch 400^3 (64,000,000 particles): a random sample of
@@ -58,6 +60,56 @@ def test_square_patch_1M_every_particle():
     print("case square patch 100^3", flush=True)
     ref = oracle_forces(ic)
     _check(ic, ref, 128, "patch 1M")
+
+
+@pytest.mark.parametrize("option", ["wendland_c2", "sinc_5", "m4_iad", "m4_gve"])
+def test_square_patch_1M_kernel_options(option):
+    """The kernel options the bench times on the 1M patch lists, every
+    particle against the full FP64 oracle with the same option: Wendland C2,
+    sinc n = 5, IAD gradients, generalised volume elements (X = (m/rho)^0.7
+    from the oracle's standard density)."""
+    import dataclasses
+    import oracle as O
+    ic = I.square_patch(100, seed=0)
+    print(f"case square patch 100^3, {option}", flush=True)
+    lo, hi, per = ic.lo, ic.hi, ic.periodic
+    xw = None
+    if option == "m4_gve":
+        ic.params = dataclasses.replace(ic.params, volume=S.SPH_VOLUME_GENERALISED,
+                                        volume_p=0.7)
+        off, ids = O.neighbors(ic.x, ic.y, ic.z, ic.h, lo, hi, per)
+        rho0 = O.density(ic.x, ic.y, ic.z, ic.h, ic.m, lo, hi, per, off, ids)
+        xw = O.volume_weights(ic.m, rho0, 0.7)
+        rho = O.density(ic.x, ic.y, ic.z, ic.h, ic.m, lo, hi, per, off, ids, X=xw)
+        p, c, pr2 = O.eos(ic.params, rho, ic.u, rho0, ic.p_bg)
+        acc = O.momentum_energy(ic.x, ic.y, ic.z, ic.vx, ic.vy, ic.vz, ic.h, ic.m, rho, c,
+                                pr2, lo, hi, per, off, ids, ic.params, scales=True, X=xw)
+        dt = O.timestep(ic.h, c, acc["mumax"], acc["ax"], acc["ay"], acc["az"], ic.params)
+        ref = dict(off=off, ids=ids, rho=rho, rho_ref=rho0, dt=dt, **acc)
+    else:
+        family = {"wendland_c2": S.SPH_KERNEL_WENDLAND_C2, "sinc_5": S.SPH_KERNEL_SINC,
+                  "m4_iad": S.SPH_KERNEL_M4}[option]
+        grad = S.SPH_GRAD_IAD if option == "m4_iad" else S.SPH_GRAD_KERNEL
+        ic.params = dataclasses.replace(ic.params, kernel=family, sinc_n=5, gradient=grad)
+        O.set_kernel(family, 5)
+        O.set_gradient(O.GRADIENT_IAD if option == "m4_iad" else O.GRADIENT_KERNEL)
+        try:
+            ref = oracle_forces(ic)
+        finally:
+            O.set_kernel(O.KERNEL_M4)
+            O.set_gradient(O.GRADIENT_KERNEL)
+    got, _, ctx = gpu_forces(ic, ref["rho_ref"], S.SPH_FP64, max_nb=128, rho_in=ref["rho"],
+                             xw=xw)
+    assert np.array_equal(got["off"], ref["off"]) and np.array_equal(got["ids"], ref["ids"])
+    e = field_errors(ref, got)
+    print(option, "fp64", e, flush=True)
+    assert e["rho"] <= FP64_TOL and e["a"] <= FP64_TOL and e["du"] <= FP64_TOL
+    assert e["dt"] <= 1e-13
+    got32, _, _ = gpu_forces(ic, ref["rho_ref"], S.SPH_FP32_PAIR, max_nb=128,
+                             rho_in=ref["rho"], xw=xw, export=False, ctx=ctx)
+    e32 = field_errors(ref, got32)
+    print(option, "fp32-pair", e32, flush=True)
+    assert e32["rho"] <= FP32_TOL and e32["a"] <= FP32_TOL and e32["du"] <= FP32_TOL
 
 
 def test_evrard_1M_every_particle():
