@@ -328,7 +328,11 @@ __device__ __forceinline__ void density_tile(int64_t tile, int64_t n, int64_t ld
     // is clamped to a valid record only when it is used, so that the read
     // itself carries no condition.
     const int krow = max_nb - 1;
-    auto jat = [&](int k) -> int { return idx[(int64_t)min(k, krow) * ld + ii]; };
+    // The list is read once per call: non-temporal loads keep its 4 B per
+    // pair from evicting the neighbour records from L2.
+    auto jat = [&](int k) -> int {
+        return __builtin_nontemporal_load(&idx[(int64_t)min(k, krow) * ld + ii]);
+    };
     const uint32_t jmax = (uint32_t)(n - 1);
     auto jfix = [&](int j) -> int { return (int)min((uint32_t)j, jmax); };
     auto step = [&](int k) {
@@ -569,7 +573,9 @@ iad_kernel(int64_t n, int64_t ld, const DensRec *__restrict__ vrec,
         x1 = rec_chunk<true, (int)sizeof(DensRec)>(src_base, j1, chunk);
     };
     const int krow = max_nb - 1;
-    auto jat = [&](int k) -> int { return idx[(int64_t)min(k, krow) * ld + ii]; };
+    auto jat = [&](int k) -> int {
+        return __builtin_nontemporal_load(&idx[(int64_t)min(k, krow) * ld + ii]);
+    };
     const uint32_t jmax = (uint32_t)(n - 1);
     auto jfix = [&](int j) -> int { return (int)min((uint32_t)j, jmax); };
     auto step = [&](int k) {
@@ -752,7 +758,9 @@ __device__ __forceinline__ void momentum_tile(
     // carries a condition. Records fetched for steps past a lane's count are
     // never used.
     const int krow = max_nb - 1;
-    auto jat = [&](int k) -> int { return idx[(int64_t)min(k, krow) * ld + ii]; };
+    auto jat = [&](int k) -> int {
+        return __builtin_nontemporal_load(&idx[(int64_t)min(k, krow) * ld + ii]);
+    };
     const uint32_t jmax = (uint32_t)(n - 1);
     auto jfix = [&](int j) -> int { return (int)min((uint32_t)j, jmax); };
     struct RecSet {

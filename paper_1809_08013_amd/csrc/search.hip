@@ -713,9 +713,15 @@ __device__ __forceinline__ void search_tile(
 #pragma unroll
             for (int r = 0; r < kChunk; ++r)
                 if (k0 + r < mine) val[r] += L.base[L.cellof[val[r]]];
+            // Rows of 64 consecutive entries, whole lines: stored
+            // non-temporally, the list (read back only by the next calls)
+            // does not evict the union's records from L2. The scattered
+            // appends of the per-lane walks stay ordinary stores (partial
+            // lines written non-temporally double their time).
 #pragma unroll
             for (int r = 0; r < kChunk; ++r)
-                if (k0 + r < mine) idx[(int64_t)(k0 + r) * ld + i] = val[r];
+                if (k0 + r < mine)
+                    __builtin_nontemporal_store(val[r], &idx[(int64_t)(k0 + r) * ld + i]);
         }
         if (active) {
             count[i] = cnt;
