@@ -376,12 +376,22 @@ block_bins_kernel(int64_t n, const double *__restrict__ dtc, int max_bin,
 {
     const double D = dt_dev[0];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int b = max_bin;
-    for (int k = max_bin; k >= 0; --k)
-        if (ldexp(D, -k) <= dtc[i]) b = k;
-    bin[i] = (double)b;
-    atomicMax(&words[0], (uint32_t)b);
+    int b = 0;
+    if (i < n) {
+        b = max_bin;
+        for (int k = max_bin; k >= 0; --k)
+            if (ldexp(D, -k) <= dtc[i]) b = k;
+        bin[i] = (double)b;
+    }
+    // deepest bin: one atomic per wave (every lane takes part in the
+    // reduction), and only above the value already there (same-address
+    // atomics serialise in their L2 channel)
+    int m = b;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 &&
+        (uint32_t)m > __hip_atomic_load(&words[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&words[0], (uint32_t)m);
 }
 
 __global__ void __launch_bounds__(64)

@@ -961,8 +961,8 @@ __device__ __forceinline__ int axis_offsets(int nc, int periodic, int k, int (&o
     return 2 * k + 1;
 }
 
-// Words of the on-device iteration (ctx->it_words): [0] particles outside
-// the band, [1] largest count, [2] done (the last sweep's counts are final),
+// Words of the on-device iteration (ctx->it_words): [0] nonzero when a
+// particle is outside the band, [1] unused, [2] done (the last sweep's counts are final),
 // [3] sweeps counted, [4] a particle outside the grid's reach (2 h > 2
 // cells): the host rebuilds the cells and continues.
 enum { IT_BAD = 0, IT_MAXC = 1, IT_DONE = 2, IT_SWEEP = 3, IT_REACH = 4, IT_WORDS = 5 };
@@ -1070,20 +1070,19 @@ gather_count_kernel(int64_t n, const SearchRec *__restrict__ srec,
         }
         count[i] = cnt;
     }
-    // one atomic per wave for each word
+    // Only whether some particle is outside the band matters: a wave with
+    // one sets the flag unless it is already set. (An atomic from every wave
+    // to the one word serialises in its L2 channel: ~10 ns each.) The word
+    // is only ever set within a sweep, so a stale read costs one atomic.
     const uint64_t bad = __ballot(active && (cnt < lo_count || cnt > hi_count));
-    int m = cnt;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) {
-        if (bad) atomicAdd(&words[IT_BAD], (uint32_t)__popcll(bad));
-        atomicMax(&words[IT_MAXC], (uint32_t)m);
-    }
+    if ((threadIdx.x & 63) == 0 && bad &&
+        __hip_atomic_load(&words[IT_BAD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+        atomicOr(&words[IT_BAD], 1u);
 }
 
 // End of a sweep (one thread): the counts of this sweep are final when every
 // particle is inside the band or this is sweep max_iter; else the h update
-// follows. Clears the band count for the next sweep.
+// follows. Clears the band flag for the next sweep.
 __global__ void sweep_end_kernel(uint32_t *words, int32_t max_iter)
 {
     if (words[IT_DONE] || words[IT_REACH]) return;
