@@ -1001,16 +1001,24 @@ __device__ __forceinline__ int count_window(const SearchRec &me, const SearchRec
 // only the z slices within reach. Does nothing once IT_DONE or IT_REACH is
 // set. Periodic: some axis of the box is periodic (then each pair takes the
 // minimum image; else the separation is used as it is).
+// recount_all = 0 (every sweep after the first of a run of sweeps on one
+// cell build): a particle whose previous count was inside the band kept its
+// h, so its count cannot change; a wave holding only such particles keeps
+// their counts and exits (after the first sweeps most waves do).
 template <bool Periodic>
 __global__ void __launch_bounds__(256)
 gather_count_kernel(int64_t n, const SearchRec *__restrict__ srec,
                     const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
                     const int32_t *__restrict__ cend, Grid g, int32_t *__restrict__ count,
-                    int32_t lo_count, int32_t hi_count, uint32_t *words)
+                    int32_t lo_count, int32_t hi_count, uint32_t *words, int recount_all)
 {
     if (words[IT_DONE] || words[IT_REACH]) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool active = i < n;
+    if (!recount_all) {
+        const int prev = active ? count[i] : lo_count;
+        if (__ballot(prev < lo_count || prev > hi_count) == 0ull) return;  // the whole wave
+    }
     const SearchRec me = active ? srec[i] : SearchRec{0.0, 0.0, 0.0, 0.0};
     const double R = sqrt(me.s2);
     int k[3];
@@ -1211,17 +1219,17 @@ hipError_t launch_max_h(sph_ctx ctx, const sph_particles &p, unsigned long long 
 }
 
 static void launch_gather(sph_ctx ctx, const sph_particles &p, int32_t *count, int32_t lo_count,
-                   int32_t hi_count, uint32_t *words, unsigned blocks)
+                   int32_t hi_count, uint32_t *words, unsigned blocks, int recount_all)
 {
     const Grid &g = ctx->grid;
     if (g.periodic[0] || g.periodic[1] || g.periodic[2])
         gather_count_kernel<true><<<blocks, 256, 0, ctx->stream>>>(
             p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, g, count,
-            lo_count, hi_count, words);
+            lo_count, hi_count, words, recount_all);
     else
         gather_count_kernel<false><<<blocks, 256, 0, ctx->stream>>>(
             p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, g, count,
-            lo_count, hi_count, words);
+            lo_count, hi_count, words, recount_all);
 }
 
 hipError_t launch_h_iteration(sph_ctx ctx, const sph_particles &p, int32_t *count,
@@ -1233,7 +1241,10 @@ hipError_t launch_h_iteration(sph_ctx ctx, const sph_particles &p, int32_t *coun
     set_word_kernel<<<1, 1, 0, ctx->stream>>>(words + IT_SWEEP, (uint32_t)first_sweep);
     const unsigned blocks = (unsigned)((p.n + 255) / 256);
     for (int32_t it = first_sweep; it <= max_iter; ++it) {
-        launch_gather(ctx, p, count, lo_count, hi_count, words, blocks);
+        // the first sweep on these cells counts every particle (the counts
+        // in memory may belong to another order); later ones only recount
+        // the waves holding a particle whose h was just updated
+        launch_gather(ctx, p, count, lo_count, hi_count, words, blocks, it == first_sweep);
         sweep_end_kernel<<<1, 1, 0, ctx->stream>>>(words, max_iter);
         if (it < max_iter)
             update_h_kernel<<<blocks, 256, 0, ctx->stream>>>(p.n, count, p.h, ctx->srec,
