@@ -962,10 +962,18 @@ __device__ __forceinline__ int axis_offsets(int nc, int periodic, int k, int (&o
 }
 
 // Words of the on-device iteration (ctx->it_words): [0] nonzero when a
-// particle is outside the band, [1] unused, [2] done (the last sweep's counts are final),
+// particle is outside the band, [1] length of the list of particles that the
+// next sweep counts with lane groups, [2] done (the last sweep's counts are final),
 // [3] sweeps counted, [4] a particle outside the grid's reach (2 h > 2
 // cells): the host rebuilds the cells and continues.
-enum { IT_BAD = 0, IT_MAXC = 1, IT_DONE = 2, IT_SWEEP = 3, IT_REACH = 4, IT_WORDS = 5 };
+enum { IT_BAD = 0, IT_NLIST = 1, IT_DONE = 2, IT_SWEEP = 3, IT_REACH = 4, IT_WORDS = 5 };
+
+// After the first sweep on a cell build, a wave whose particles include
+// fewer than kSweepDense to recount leaves them to the lane-group kernel
+// (its slowest lane would set its time); kSweepGroup lanes share each such
+// particle's cells.
+constexpr int kSweepDense = 16;
+constexpr int kSweepGroup = 16;
 
 // Gather count of the lane's particle over the particles [w.x, w.y): the
 // records are loaded four at a time, so that a test waits for its load once
@@ -1003,8 +1011,9 @@ __device__ __forceinline__ int count_window(const SearchRec &me, const SearchRec
 // minimum image; else the separation is used as it is).
 // recount_all = 0 (every sweep after the first of a run of sweeps on one
 // cell build): a particle whose previous count was inside the band kept its
-// h, so its count cannot change; a wave holding only such particles keeps
-// their counts and exits (after the first sweeps most waves do).
+// h, so its count cannot change; a wave holding fewer than kSweepDense
+// particles to recount keeps its counts and exits (after the first sweeps
+// most waves do), its particles to recount being on the lane-group list.
 template <bool Periodic>
 __global__ void __launch_bounds__(256)
 gather_count_kernel(int64_t n, const SearchRec *__restrict__ srec,
@@ -1017,7 +1026,8 @@ gather_count_kernel(int64_t n, const SearchRec *__restrict__ srec,
     bool active = i < n;
     if (!recount_all) {
         const int prev = active ? count[i] : lo_count;
-        if (__ballot(prev < lo_count || prev > hi_count) == 0ull) return;  // the whole wave
+        const uint64_t redo = __ballot(prev < lo_count || prev > hi_count);
+        if (__popcll(redo) < kSweepDense) return;  // the whole wave
     }
     const SearchRec me = active ? srec[i] : SearchRec{0.0, 0.0, 0.0, 0.0};
     const double R = sqrt(me.s2);
@@ -1097,6 +1107,7 @@ __global__ void sweep_end_kernel(uint32_t *words, int32_t max_iter)
     if (words[IT_BAD] == 0 || (int32_t)words[IT_SWEEP] == max_iter) words[IT_DONE] = 1u;
     else words[IT_SWEEP] += 1u;
     words[IT_BAD] = 0u;
+    words[IT_NLIST] = 0u;
 }
 
 // Cube root of a > 0 by Newton's iteration for y^3 = a in correctly rounded
@@ -1124,21 +1135,116 @@ __device__ __forceinline__ double cbrt_newton(double a)
 // h <- 2 h for an empty sphere, else (h / 2) (1 + (n_target / N)^(1/3)), for
 // the particles outside the band; their search records take the new
 // (2 h)^2. Does nothing once the counts are final.
+// The updated particles of a wave with fewer than kSweepDense of them go on
+// the list of the next sweep's lane-group kernel (list, words[IT_NLIST],
+// cleared by the sweep's end; one atomic per block).
 __global__ void __launch_bounds__(256)
 update_h_kernel(int64_t n, const int32_t *__restrict__ count, double *__restrict__ h,
                 SearchRec *__restrict__ srec, int32_t lo_count, int32_t hi_count,
-                double n_target, const uint32_t *words)
+                double n_target, uint32_t *words, int32_t *__restrict__ list)
 {
     if (words[IT_DONE] || words[IT_REACH]) return;
+    __shared__ uint32_t s_cnt[4];
+    __shared__ uint32_t s_base;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int c = count[i];
-    if (c >= lo_count && c <= hi_count) return;
-    const double hn = c == 0 ? 2.0 * h[i]
-                             : (h[i] * 0.5) * (1.0 + cbrt_newton(n_target / (double)c));
-    h[i] = hn;
-    const double s = 2.0 * hn;
-    srec[i].s2 = s * s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = i < n ? count[i] : lo_count;
+    const bool upd = c < lo_count || c > hi_count;
+    if (upd) {
+        const double hn = c == 0 ? 2.0 * h[i]
+                                 : (h[i] * 0.5) * (1.0 + cbrt_newton(n_target / (double)c));
+        h[i] = hn;
+        const double s = 2.0 * hn;
+        srec[i].s2 = s * s;
+    }
+    const uint64_t m = __ballot(upd);
+    const uint32_t nw = (uint32_t)__popcll(m);
+    const uint32_t listed = nw < (uint32_t)kSweepDense ? nw : 0u;
+    if (lane == 0) s_cnt[wave] = listed;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        s_base = tot ? atomicAdd(&words[IT_NLIST], tot) : 0u;
+    }
+    __syncthreads();
+    if (listed && upd) {
+        uint32_t off = s_base;
+        for (int w = 0; w < wave; ++w) off += s_cnt[w];
+        off += (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        list[off] = (int32_t)i;
+    }
+}
+
+// Gather counts of the listed particles (the lane-group half of a sweep):
+// kSweepGroup lanes per particle, which take its cells in turn and add
+// their counts. Same cells, windows and test as gather_count_kernel.
+template <bool Periodic>
+__global__ void __launch_bounds__(256)
+gather_count_list_kernel(const int32_t *__restrict__ list, const SearchRec *__restrict__ srec,
+                         const uint32_t *__restrict__ keys, const int32_t *__restrict__ cstart,
+                         const int32_t *__restrict__ cend, Grid g, int32_t *__restrict__ count,
+                         int32_t lo_count, int32_t hi_count, uint32_t *words)
+{
+    if (words[IT_DONE] || words[IT_REACH]) return;
+    const int64_t nl = words[IT_NLIST];
+    const int sub = threadIdx.x % kSweepGroup;
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kSweepGroup);
+    for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSweepGroup; e < nl;
+         e += groups) {
+        const int64_t i = list[e];
+        const SearchRec me = srec[i];
+        const double R = sqrt(me.s2);
+        int k[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double reach = R * g.inv_s[a] * (1.0 + 1e-12);
+            k[a] = reach <= 1.0 ? 1 : (reach <= 2.0 ? 2 : 3);
+        }
+        if (k[0] > 2 || k[1] > 2 || k[2] > 2) {
+            if (sub == 0) atomicOr(&words[IT_REACH], 1u);
+            continue;  // (the sweep is discarded)
+        }
+        const uint32_t key = keys[i] >> g.zbits;
+        const int myc[3] = {(int)compact3(key), (int)compact3(key >> 1), (int)compact3(key >> 2)};
+        int ox[5], oy[5], oz[5];
+        const int nx = axis_offsets(g.nc[0], g.periodic[0], k[0], ox);
+        const int ny = axis_offsets(g.nc[1], g.periodic[1], k[1], oy);
+        const int nz = axis_offsets(g.nc[2], g.periodic[2], k[2], oz);
+        const double no_shift[3] = {0.0, 0.0, 0.0};
+        const double pt[3] = {me.x, me.y, me.z};
+        const bool all_x = g.periodic[0] && g.nc[0] < 2 * k[0] + 1;
+        const bool all_y = g.periodic[1] && g.nc[1] < 2 * k[1] + 1;
+        const bool all_z = g.periodic[2] && g.nc[2] < 2 * k[2] + 1;
+        int cnt = 0;
+        for (int f = sub; f < nx * ny * nz; f += kSweepGroup) {
+            const int c = f / (nx * ny), bb = (f / nx) % ny, a = f % nx;
+            bool okx = true, oky = true, okz = true;
+            const int zr = all_z ? oz[c] : myc[2] + oz[c];
+            const int z = all_z ? zr : wrap_or_clip(zr, g.nc[2], g.periodic[2], okz);
+            const int yr = all_y ? oy[bb] : myc[1] + oy[bb];
+            const int y = all_y ? yr : wrap_or_clip(yr, g.nc[1], g.periodic[1], oky);
+            const int xr = all_x ? ox[a] : myc[0] + ox[a];
+            const int x = all_x ? xr : wrap_or_clip(xr, g.nc[0], g.periodic[0], okx);
+            if (!okx || !oky || !okz) continue;
+            const int64_t cell = ((int64_t)z * g.nc[1] + y) * g.nc[0] + x;
+            int2 w = make_int2(cstart[cell], cend[cell]);
+            const bool direct = !all_x && !all_y && !all_z && x == xr && y == yr && z == zr;
+            if (direct && g.zbits > 0)
+                w = z_window_r(w, (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20), g, pt,
+                               pt, R, keys);
+            cnt += count_window<Periodic ? WRAP_PAIR : WRAP_NONE>(me, srec, w, (int)i, g,
+                                                                   no_shift);
+        }
+#pragma unroll
+        for (int o = kSweepGroup / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, kSweepGroup);
+        if (sub == 0) {
+            count[i] = cnt;
+            if ((cnt < lo_count || cnt > hi_count) &&
+                __hip_atomic_load(&words[IT_BAD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                    0u)
+                atomicOr(&words[IT_BAD], 1u);
+        }
+    }
 }
 
 // Largest h, as the ordered bit patterns of positive doubles.
@@ -1156,7 +1262,16 @@ max_h_kernel(int64_t n, const double *__restrict__ h, unsigned long long *out)
         const unsigned long long t = __shfl_xor(m, o, 64);
         m = t > m ? t : m;
     }
-    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+    // one atomic per block, and none when the word already holds as much
+    // (atomics on one word serialise in its L2 channel)
+    __shared__ unsigned long long wmax[4];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 4; ++w) m = wmax[w] > m ? wmax[w] : m;
+        if (m > __hip_atomic_load(out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(out, m);
+    }
 }
 
 __global__ void clear_words_kernel(uint32_t *a, int k)
@@ -1213,7 +1328,7 @@ hipError_t launch_find_neighbors_batch(sph_ctx ctx, const BatchDev &b, int max_n
 hipError_t launch_max_h(sph_ctx ctx, const sph_particles &p, unsigned long long *out)
 {
     clear_words_kernel<<<1, 64, 0, ctx->stream>>>(reinterpret_cast<uint32_t *>(out), 2);
-    const unsigned blocks = (unsigned)std::min<int64_t>((p.n + 255) / 256, 1024);
+    const unsigned blocks = (unsigned)std::min<int64_t>((p.n + 255) / 256, 512);
     max_h_kernel<<<blocks, 256, 0, ctx->stream>>>(p.n, p.h, out);
     return hipGetLastError();
 }
@@ -1222,14 +1337,24 @@ static void launch_gather(sph_ctx ctx, const sph_particles &p, int32_t *count, i
                    int32_t hi_count, uint32_t *words, unsigned blocks, int recount_all)
 {
     const Grid &g = ctx->grid;
-    if (g.periodic[0] || g.periodic[1] || g.periodic[2])
+    // the list kernel's grid: enough lane groups for the lists of the late
+    // sweeps (a few thousand particles), the rest loop
+    const unsigned lblocks = std::min<unsigned>(blocks, 1024u);
+    if (g.periodic[0] || g.periodic[1] || g.periodic[2]) {
         gather_count_kernel<true><<<blocks, 256, 0, ctx->stream>>>(
             p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, g, count,
             lo_count, hi_count, words, recount_all);
-    else
+        gather_count_list_kernel<true><<<lblocks, 256, 0, ctx->stream>>>(
+            ctx->perm_tmp_id, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, g,
+            count, lo_count, hi_count, words);
+    } else {
         gather_count_kernel<false><<<blocks, 256, 0, ctx->stream>>>(
             p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, g, count,
             lo_count, hi_count, words, recount_all);
+        gather_count_list_kernel<false><<<lblocks, 256, 0, ctx->stream>>>(
+            ctx->perm_tmp_id, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, g,
+            count, lo_count, hi_count, words);
+    }
 }
 
 hipError_t launch_h_iteration(sph_ctx ctx, const sph_particles &p, int32_t *count,
@@ -1249,7 +1374,7 @@ hipError_t launch_h_iteration(sph_ctx ctx, const sph_particles &p, int32_t *coun
         if (it < max_iter)
             update_h_kernel<<<blocks, 256, 0, ctx->stream>>>(p.n, count, p.h, ctx->srec,
                                                             lo_count, hi_count, n_target,
-                                                            words);
+                                                            words, ctx->perm_tmp_id);
     }
     return hipGetLastError();
 }

@@ -438,9 +438,10 @@ Grid make_grid(const sph_box &b, double h_max, int64_t cell_cap, int max_axis);
 hipError_t launch_max_h(sph_ctx ctx, const sph_particles &p, unsigned long long *out);
 // Sweeps first_sweep..max_iter of the count-based h iteration on the cells
 // last built, on the device: counts, the band test and the h update, with no
-// host work between sweeps. words (kItWords): [0] out-of-band count, [1]
-// largest count, [2] done, [3] last sweep, [4] a particle outgrew the cells
-// (the host rebuilds and calls again from sweep [3]).
+// host work between sweeps. words (kItWords): [0] nonzero when a particle
+// is outside the band, [1] length of the next sweep's list of particles
+// counted by lane groups, [2] done, [3] last sweep, [4] a particle outgrew
+// the cells (the host rebuilds and calls again from sweep [3]).
 constexpr int kItWords = 5;
 // Reorders an int32 per-particle array as the last cell build reordered the
 // particles (its sort permutation).
