@@ -972,8 +972,8 @@ enum { IT_BAD = 0, IT_NLIST = 1, IT_DONE = 2, IT_SWEEP = 3, IT_REACH = 4, IT_WOR
 // fewer than kSweepDense to recount leaves them to the lane-group kernel
 // (its slowest lane would set its time); kSweepGroup lanes share each such
 // particle's cells.
-constexpr int kSweepDense = 16;
-constexpr int kSweepGroup = 16;
+constexpr int kSweepDense = 32;
+constexpr int kSweepGroup = 32;
 
 // Gather count of the lane's particle over the particles [w.x, w.y): the
 // records are loaded four at a time, so that a test waits for its load once
