@@ -1338,7 +1338,9 @@ static void launch_gather(sph_ctx ctx, const sph_particles &p, int32_t *count, i
 {
     const Grid &g = ctx->grid;
     // the list kernel's grid: enough lane groups for the lists of the late
-    // sweeps (a few thousand particles), the rest loop
+    // sweeps (a few thousand particles), the rest loop. The list lives in
+    // the reorder scratch's id array (n_max entries), which no kernel uses
+    // between two cell builds.
     const unsigned lblocks = std::min<unsigned>(blocks, 1024u);
     if (g.periodic[0] || g.periodic[1] || g.periodic[2]) {
         gather_count_kernel<true><<<blocks, 256, 0, ctx->stream>>>(

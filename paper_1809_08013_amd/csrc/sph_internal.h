@@ -319,7 +319,7 @@ struct sph_ctx_s {
 
     // permutation scratch
     double *perm_tmp = nullptr;      // kPermFields * n_max
-    int32_t *perm_tmp_id = nullptr;  // n_max
+    int32_t *perm_tmp_id = nullptr;  // n_max; also the smoothing-length sweeps' list
 
     // reductions
     double *red_part = nullptr;      // kRedFields * kRedMaxBlocks
