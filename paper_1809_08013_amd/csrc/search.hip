@@ -131,6 +131,15 @@ __device__ __forceinline__ double sep2(const SearchRec &me, const SearchRec &o, 
     return __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
 }
 
+// A double that is the same in every lane, as a wave-uniform value.
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // acc * 2 + [r2 < s2], s2 wave-uniform: the comparison's lane mask is the
 // carry-in of one add (acc + acc + carry), which shifts the bit in.
 __device__ __forceinline__ uint32_t shift_in(uint32_t acc, double r2, double s2)
@@ -434,7 +443,8 @@ __device__ __forceinline__ void search_tile(
     int32_t *__restrict__ idx, uint32_t *__restrict__ mask_scratch,
     const uint32_t *__restrict__ hflag, uint32_t *status0, const BatchDev &b,
     SearchLds<kEntries> &L,
-    int32_t *__restrict__ fb_tiles, uint32_t *fb_count)
+    int32_t *__restrict__ fb_tiles, uint32_t *fb_count,
+    const unsigned long long *__restrict__ s2max)
 {
     const int lane = threadIdx.x & (kWave - 1);
     int64_t t0, tend;
@@ -579,6 +589,44 @@ __device__ __forceinline__ void search_tile(
         for (int q = 0; q < kC; ++q)
             if (kp[q]) keep(v[q], off[q] + __popcll(m[q] & lt));
         wave_sync();
+        if constexpr (!Multi) {
+            if (!wrap && g.zbits > 0) {
+                // Each union cell only in its window for the tile (as for the
+                // dense unions of the second kernel): cells beyond reach in x
+                // or y are emptied, the others keep the z slices within reach
+                // of the tile's z extent. Windows stay inside their cells, so
+                // the cells stay ascending and hold the tile's own particles.
+                double tlo[3], thi[3];
+                double s2t = active ? me.s2 : 0.0;
+                const double mc[3] = {me.x, me.y, me.z};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    tlo[a] = active ? mc[a] : INFINITY;
+                    thi[a] = active ? mc[a] : -INFINITY;
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        tlo[a] = fmin(tlo[a], __shfl_xor(tlo[a], o, kWave));
+                        thi[a] = fmax(thi[a], __shfl_xor(thi[a], o, kWave));
+                    }
+                    s2t = fmax(s2t, __shfl_xor(s2t, o, kWave));
+                }
+                // the reduced values are the same in every lane: keep them in
+                // scalar registers (vector registers bound the occupancy)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    tlo[a] = uniform_f64(tlo[a]);
+                    thi[a] = uniform_f64(thi[a]);
+                }
+                s2t = uniform_f64(s2t);
+#pragma unroll 1
+                for (int c = lane; c < nu; c += kWave)
+                    L.cells[c] = z_window(L.cells[c], L.cxyz[c], g, tlo, thi, s2t, s2max, keys);
+                wave_sync();
+            }
+        }
         // u0[c]: exclusive prefix of the cell lengths; lane holds cells
         // c = lane + q * 64
 #pragma unroll
@@ -911,7 +959,8 @@ find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
                       int32_t *__restrict__ count, int32_t *__restrict__ idx,
                       uint32_t *__restrict__ mask_scratch, const uint32_t *__restrict__ hflag,
                       uint32_t *status, BatchDev b, int32_t *__restrict__ fb_tiles,
-                      uint32_t *fb_count, StepMask mask)
+                      uint32_t *fb_count, StepMask mask,
+                      const unsigned long long *__restrict__ s2max)
 {
     __shared__ SearchLds<kEntries> lds[kWavesPerBlock];
     const int w = threadIdx.x / kWave;
@@ -937,7 +986,7 @@ find_neighbors_kernel(int64_t n, int64_t ld, const SearchRec *__restrict__ srec,
         }
     }
     search_tile<Multi>(tile, nn, ld, srec, keys, cstart, cend, g, max_nb, count, idx,
-                       mask_scratch, hflag, status, b, L, fb_tiles, fb_count);
+                       mask_scratch, hflag, status, b, L, fb_tiles, fb_count, s2max);
 }
 
 
@@ -1293,7 +1342,8 @@ hipError_t launch_find_neighbors(sph_ctx ctx, const sph_particles &p, const sph_
     find_neighbors_kernel<false><<<blocks, kBlock, 0, ctx->stream>>>(
         p.n, p.n, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, ctx->grid,
         nb.max_nb, nb.count, nb.idx, ctx->nb_mask, ctx->hflag_dev, ctx->status_dev, BatchDev{},
-        ctx->fb_tiles, ctx->fb_count, mask);
+        ctx->fb_tiles, ctx->fb_count, mask,
+        reinterpret_cast<const unsigned long long *>(ctx->cell_s2max));
     ktime_end(ctx, tk);
     const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, kFallbackBlocks);
     tk = ktime_begin(ctx, TK_FALLBACK);
@@ -1317,7 +1367,7 @@ hipError_t launch_find_neighbors_batch(sph_ctx ctx, const BatchDev &b, int max_n
     find_neighbors_kernel<true><<<blocks, kBlock, 0, ctx->stream>>>(
         0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,
         count, idx, ctx->nb_mask, nullptr, nullptr, b, ctx->fb_tiles, ctx->fb_count,
-        StepMask{});
+        StepMask{}, nullptr);
     const unsigned fblocks = (unsigned)std::min<int64_t>(tiles, kFallbackBlocks);
     fallback_kernel<true><<<fblocks, kWave, 0, ctx->stream>>>(
         0, b.cap, ctx->srec, ctx->sorted_keys, ctx->cell_start, ctx->cell_end, Grid{}, max_nb,
