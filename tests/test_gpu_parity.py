@@ -256,8 +256,28 @@ def test_evrard_variable_h():
     assert e32["rho"] <= FP32_TOL and e32["a"] <= FP32_TOL and e32["du"] <= FP32_TOL
 
 
+def _cluster_isolated():
+    """A cube of 4,000 particles whose h is near its converged value, and 24
+    isolated particles around it with h far too small: from the second sweep
+    on, the isolated ones are the few particles to recount in their waves
+    (the lane-group counts), and their doubling h outgrows the cells there,
+    several times, before the tenth sweep ends the iteration."""
+    ic = I.random_cloud(4024, seed=8, h_min=0.016, h_max=0.020, periodic=(0, 0, 0))
+    rng = np.random.default_rng(9)
+    P = rng.uniform(0.4, 0.6, size=(4000, 3))
+    iso = []
+    while len(iso) < 24:
+        q = rng.uniform(0.0, 1.0, size=3)
+        if np.max(np.abs(q - 0.5)) > 0.2:
+            iso.append(q)
+    P = np.vstack([P, np.array(iso)])
+    ic.x[:], ic.y[:], ic.z[:] = P[:, 0], P[:, 1], P[:, 2]
+    ic.h[4000:] = 0.004
+    return ic
+
+
 @pytest.mark.parametrize("case", ["evrard_20k", "cloud_periodic", "cloud_tiny_h",
-                                  "cloud_tiny_h_pz"])
+                                  "cloud_tiny_h_pz", "cluster_isolated"])
 def test_smoothing_length_iteration_bitwise(case):
     """sph_smoothing_length reproduces the oracle's count-based h iteration
     bit for bit: same iterations, same final gather counts, same h. The
@@ -270,6 +290,8 @@ def test_smoothing_length_iteration_bitwise(case):
         ic = I.random_cloud(5000, seed=4, h_min=0.02, h_max=0.08, periodic=(1, 1, 1))
     elif case == "cloud_tiny_h":
         ic = I.random_cloud(4000, seed=6, h_min=0.002, h_max=0.004, periodic=(0, 0, 0))
+    elif case == "cluster_isolated":
+        ic = _cluster_isolated()
     else:
         ic = I.random_cloud(4000, seed=7, h_min=0.002, h_max=0.004, periodic=(0, 0, 1))
     print("case", case, flush=True)
